@@ -1,0 +1,147 @@
+"""Benchmark of the Monte-Carlo BEM hot path on one MI355X.
+
+One step = one full Monte-Carlo estimate of the precision-form workload
+(noise-displaced ellipsoid with 20480 triangles, 32 modes with their own
+wavenumbers, 4096 surface queries, 1024 samples): sampling, right-hand
+side, GMRES (tol 1e-6, <= 200 iterations) and surface evaluation, in the
+FP32 form.  Inputs are resident in device memory before the timed region.
+
+Prints one JSON line: algorithmic pair evaluations per second
+(sum over modes of N(N-1) + Q N per step), the dominant kernel's roofline
+from HIP events recorded around its launches, the same workload in the
+plain FP64 GPU form, and the FP64 CPU oracle timed on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is "
+              "described in the design notes but not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2506_06190_amd import nat
+
+    dev = "cuda:0"
+    wl = W.config_precision()
+    ctx = nat.Context(0)
+    mesh = nat.Mesh(ctx, wl.vertices, wl.tris)
+    g = torch.from_numpy(wl.g).to(dev)
+    qt = torch.from_numpy(wl.q_tri).to(dev)
+    qb = torch.from_numpy(wl.q_b).to(dev)
+    p = torch.empty((wl.n_modes, wl.n_queries), dtype=torch.complex128, device=dev)
+    opts = nat.nat_mc_opts_default()
+    opts.precision = nat.NAT_PREC_FP32
+    alg_pairs = wl.pair_evals()
+
+    def step(o=opts):
+        return nat.nat_mcbem_estimate(mesh, g, wl.k, qt, qb, wl.n_samples, wl.seed, o, p_out=p)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    nat.nat_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = None
+    for _ in range(args.steps):
+        _, reps = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = nat.nat_profile_read(ctx)
+    nat.nat_profile_enable(ctx, False)
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = alg_pairs * args.steps / elapsed
+    iters = [r["iters"] for r in reps]
+    executed = wl.n_modes * (wl.n_samples ** 2 + wl.n_queries * wl.n_samples) \
+        + sum(iters) * wl.n_samples ** 2
+    p_fp32 = p.cpu().numpy()
+
+    # dominant kernel: the kernel-sum class with the largest total time
+    sums = {k: v for k, v in prof.items() if k.startswith("sum32")}
+    dom_name = max(sums, key=lambda k: sums[k]["total_ms"])
+    dom = sums[dom_name]
+    achieved = dom["flops"] / dom["launches"] / (dom["avg_ms"] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": f"k_sum32 ({dom_name})", "achieved": round(achieved, 3),
+                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                "avg_launch_ms": round(dom["avg_ms"], 5), "launches": dom["launches"],
+                "kernel_share_of_step": round(sum(v["total_ms"] for v in prof.values())
+                                              and dom["total_ms"] / (elapsed * 1e3), 4)}
+
+    plain = None
+    if not args.no_plain:
+        o64 = nat.nat_mc_opts_default()
+        o64.precision = nat.NAT_PREC_FP64
+        step(o64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step(o64)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        p_fp64 = p.cpu().numpy()
+        err_vs_plain = max(float(np.linalg.norm(p_fp32[m] - p_fp64[m]) / np.linalg.norm(p_fp64[m]))
+                           for m in range(wl.n_modes))
+        plain = {"form": "plain FP64, one thread per target, no tiling", "value": alg_pairs / t_plain,
+                 "ms_per_step": 1e3 * t_plain, "fp32_speedup": t_plain / (elapsed / args.steps),
+                 "fp32_max_rel_l2_vs_plain": err_vs_plain}
+
+    cpu = None
+    err_vs_oracle = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        t0 = time.perf_counter()
+        r = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri, wl.q_b, wl.n_samples, wl.seed,
+                    tol=1e-6)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": alg_pairs / t_cpu, "unit": "pair-evals/s", "cores": O.num_threads(),
+               "kind": "oracle", "sample": f"the full workload ({wl.n_modes} modes), FP64, tol 1e-6",
+               "seconds": round(t_cpu, 3)}
+        r12 = r  # same seed; compare the FP32 result with the oracle's
+        err_vs_oracle = max(float(np.linalg.norm(p_fp32[m] - r12["p"][m]) / np.linalg.norm(r12["p"][m]))
+                            for m in range(wl.n_modes))
+
+    out = {
+        "metric": "MC-BEM kernel pair-evals/s (FP32 vs plain) + p50/p99 solve latency at fixed error",
+        "value": value, "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "triangles": len(wl.tris), "modes": wl.n_modes,
+                   "queries": wl.n_queries, "samples": wl.n_samples, "form": "FP32 compensated",
+                   "gmres_tol": 1e-6},
+        "executed_pair_evals_per_s": executed * args.steps / elapsed,
+        "gmres_iters": iters,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "plain": plain,
+        "max_rel_l2_vs_oracle": err_vs_oracle,
+        "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 5),
+                        "total_ms": round(v["total_ms"], 3)} for k, v in prof.items()},
+    }
+    mesh.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

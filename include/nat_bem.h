@@ -1,0 +1,228 @@
+/*
+ * nat_bem.h -- C ABI of libnat_bem.so, the MI355X (gfx950) Monte-Carlo BEM
+ * and dense Burton-Miller BEM library for the radiation solves of
+ * "NAT: Neural Acoustic Transfer for Interactive Scenes in Real Time"
+ * (arXiv 2506.06190), Section 4.
+ *
+ * Problem (Section 4, eq. BurtonMiller; Section 4.1.1, eqs. BIE and
+ * bem_linear_system): given a closed triangle mesh Gamma, Neumann data
+ * g = dp/dn (outward normal, into the fluid) and a wavenumber k = 2 pi f / c,
+ * find the surface pressure p of the radiating solution of
+ * Laplacian(p) + k^2 p = 0 outside Gamma, with time factor e^{-i w t} and
+ * G(x,y) = e^{ik|x-y|} / (4 pi |x-y|).
+ *
+ * Conventions of every entry point
+ *  - Plain pointers only.  "host" arrays live in host memory and are read
+ *    before the call returns; "device" arrays live in device memory of the
+ *    context's GPU and belong to the caller, who keeps them valid until the
+ *    call returns.
+ *  - Complex numbers are interleaved (re, im) doubles, the layout of
+ *    C99 double complex, std::complex<double> and torch.complex128.
+ *  - Arrays indexed [a][b] are row-major with b fastest.
+ *  - Streams are hipStream_t values passed as void*; NULL is the default
+ *    stream.  Calls that fill a host report block until their device work
+ *    has finished; others are stream-ordered and return at once.
+ *  - Every argument is validated before any device work is issued; an
+ *    invalid argument returns NAT_E_INVALID and touches nothing.  No call
+ *    throws or aborts; a HIP runtime failure returns NAT_E_HIP.
+ *    nat_last_error() returns a text description of the last failure in
+ *    the calling thread.
+ *  - Device memory the library allocates is charged to the context's HBM
+ *    budget; a call that would exceed it returns NAT_E_BUDGET before
+ *    allocating anything.
+ *  - A context and everything made from it are used by one host thread at
+ *    a time.
+ */
+#ifndef NAT_BEM_H
+#define NAT_BEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NAT_OK = 0,
+    NAT_E_INVALID = 1,  /* an argument failed validation; nothing was done         */
+    NAT_E_BUDGET = 2,   /* the HBM budget would be exceeded; nothing was allocated */
+    NAT_E_NOCONV = 3,   /* GMRES stopped at max_iter above tol; best iterate kept  */
+    NAT_E_HIP = 4,      /* a HIP runtime call failed                               */
+    NAT_E_INTERNAL = 5
+} nat_status;
+
+typedef struct nat_ctx nat_ctx;
+typedef struct nat_mesh nat_mesh;
+typedef struct nat_bem_op nat_bem_op;
+
+typedef enum {
+    NAT_PREC_FP64 = 0, /* plain form: FP64 kernel sums, one thread per target            */
+    NAT_PREC_FP32 = 1  /* FP32 kernel sums with compensated accumulation, FP64 Krylov    */
+} nat_precision;
+
+typedef enum {
+    NAT_NEUMANN_PER_VERTEX = 0,  /* g given at vertices, linear on each triangle      */
+    NAT_NEUMANN_PER_TRIANGLE = 1 /* g constant on each triangle (Section 3.4 scenes)   */
+} nat_neumann_layout;
+
+/* Options of the Monte-Carlo estimate.  nat_mc_opts_default() fills the
+ * paper's settings: linear-solver tolerance 1e-6, at most 200 iterations
+ * (Section 6.1), disk radius eps = sqrt(|Gamma| / (pi N)). */
+typedef struct {
+    int32_t precision;      /* nat_precision                                         */
+    int32_t layout;         /* nat_neumann_layout of v_n                             */
+    double eps_scale;       /* eps = eps_scale * sqrt(|Gamma| / (pi N)); > 0         */
+    double gmres_tol;       /* relative residual |r| / |b| to stop at; > 0           */
+    int32_t gmres_max_iter; /* 1 .. 1000                                             */
+    int32_t reserved;       /* must be 0                                             */
+} nat_mc_opts;
+
+/* Per right-hand side report of a solve. */
+typedef struct {
+    int32_t iters;     /* GMRES iterations taken                                    */
+    int32_t converged; /* 1 if rel_resid <= tol                                     */
+    double rel_resid;  /* GMRES estimate of |b - A x| / |b|                         */
+    double eps;        /* disk radius used (Monte-Carlo) or 0                       */
+    double area;       /* |Gamma|                                                   */
+} nat_solve_report;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` whose library-owned device
+ * allocations may total at most `hbm_budget_bytes` (0 = no limit). */
+nat_status nat_ctx_create(int32_t device, size_t hbm_budget_bytes, nat_ctx** out);
+void nat_ctx_destroy(nat_ctx* ctx);
+/* Bytes of device memory currently charged to the context. */
+size_t nat_ctx_bytes_in_use(const nat_ctx* ctx);
+
+/* ---- meshes (a1 of the hot path) ---------------------------------------- */
+
+/* Register a closed triangle mesh.  vertices: host double[n_vertices][3];
+ * tris: host int32[n_tris][3], counter-clockwise seen from outside.  The
+ * mesh must be closed and consistently oriented (every edge shared by
+ * exactly two triangles with opposite directions), with no zero-area
+ * triangle and positive enclosed volume.  Triangle areas, unit normals and
+ * the cumulative area table (sampling density 1/|Gamma|, Section 4.1.1) are
+ * built in FP64 on the host and copied to the device with the geometry. */
+nat_status nat_mesh_create(nat_ctx* ctx, const double* vertices, int32_t n_vertices,
+                           const int32_t* tris, int32_t n_tris, nat_mesh** out);
+void nat_mesh_destroy(nat_mesh* mesh);
+/* Host-only check of the conditions nat_mesh_create imposes (no device
+ * needed).  NAT_OK or NAT_E_INVALID with the reason in nat_last_error(). */
+nat_status nat_mesh_validate(const double* vertices, int32_t n_vertices, const int32_t* tris,
+                             int32_t n_tris);
+/* Host-only: the FP64 geometry nat_mesh_create uploads.  Outputs (host):
+ * area[n_tris] = |e1 x e2| / 2, normal[n_tris][3] = (e1 x e2)/|e1 x e2| with
+ * e1 = v1 - v0, e2 = v2 - v0, and cdf[n_tris] = running sum of the areas in
+ * triangle order, each evaluated as written without fused multiply-adds so
+ * any IEEE double implementation of the same formulas reproduces it bit for
+ * bit.  Validates the mesh first. */
+nat_status nat_mesh_geometry(const double* vertices, int32_t n_vertices, const int32_t* tris,
+                             int32_t n_tris, double* area, double* normal, double* cdf);
+/* Total area |Gamma| and the sizes; any output pointer may be NULL. */
+nat_status nat_mesh_info(const nat_mesh* mesh, double* area, int32_t* n_vertices,
+                         int32_t* n_tris);
+/* One (tri, b1, b2) query record per vertex: the first triangle that uses
+ * the vertex and the vertex's corner in it.  Host outputs tri[n_vertices],
+ * bary[n_vertices][2]. */
+nat_status nat_mesh_vertex_queries(const nat_mesh* mesh, int32_t* tri, double* bary);
+
+/* ---- Monte-Carlo BEM (Section 4.1.1, Section 4.2) ------------------------ */
+
+void nat_mc_opts_default(nat_mc_opts* opts);
+
+/* a2: draw the N area-uniform samples of seed `seed`.  Sample j takes the
+ * three SplitMix64 words at counters 3j, 3j+1, 3j+2 of stream 0, turns them
+ * into u0, u1, u2 in [0,1) (top 53 bits), picks the smallest triangle t with
+ * cumulative area > u0 |Gamma| and the point b1 = sqrt(u1)(1-u2),
+ * b2 = sqrt(u1) u2 of it.  Device outputs tri[N] (int32), bary[N][2]
+ * (double).  Stream-ordered. */
+nat_status nat_mcbem_samples(nat_mesh* mesh, int32_t n_samples, uint64_t seed, int32_t* tri,
+                             double* bary, void* stream);
+
+/* a2-a5: the whole Monte-Carlo estimate of the surface pressure at Q query
+ * points for n_modes independent problems (k_m, g_m) on one mesh sharing one
+ * sample set.  With N samples y_j, w = |Gamma|/N and disk radius eps:
+ *   Stage A  (1/2) p_i - sum_{j: r_ij >= eps} w dG(y_i,y_j)/dn_j p_j
+ *              = - sum_{j: r_ij >= eps} w G(y_i,y_j) g_j - (eps/2) g_i
+ *            solved by GMRES (x0 = 0, unrestarted, tol, max_iter);
+ *   Stage B  p(x_q) = 2 [ sum_{j: |x_q-y_j| >= eps} w (dG/dn_j p_j - G g_j)
+ *                         - (eps/2) g(x_q) ].
+ * v_n:      device complex [n_modes][n_vertices or n_tris] (opts->layout)
+ * k:        host double[n_modes], each > 0
+ * q_tri, q_bary: device int32[Q], double[Q][2]: query points on the mesh,
+ *           x = v0 + b1 (v1 - v0) + b2 (v2 - v0), b1, b2 >= 0, b1 + b2 <= 1
+ * p_out:    device complex [n_modes][Q]
+ * p_samples: device complex [n_modes][N] receiving the Stage-A solution,
+ *           or NULL
+ * report:   host nat_solve_report[n_modes], or NULL
+ * N >= 2, Q >= 0, 1 <= n_modes <= 4096.  Blocks until the result is
+ * written.  Returns NAT_E_NOCONV (results still written) if any mode
+ * stopped above its tolerance. */
+nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes,
+                              const double* k, const int32_t* q_tri, const double* q_bary,
+                              int32_t n_queries, int32_t n_samples, uint64_t seed,
+                              const nat_mc_opts* opts, double* p_out, double* p_samples,
+                              nat_solve_report* report, void* stream);
+
+/* ---- dense collocation Burton-Miller BEM (Section 4, Section 4.1) -------- */
+
+/* a6: assemble A and B of A p = B g for piecewise-constant p and g with
+ * collocation at the triangle centroids x_i:
+ *   A = I/2 - K - beta W,  B = -(S + beta K') - (beta/2) I,
+ *   S_ij = int_{T_j} G(x_i, y), K_ij = int dG/dn_y, K'_ij = int dG/dn_x,
+ *   W_ij = int d2G/(dn_x dn_y) (Hadamard finite part on the diagonal),
+ * beta = i/k when burton_miller != 0, else 0.  Quadrature: 3x3 collapsed
+ * Gauss-Legendre on far panels; 4-way midpoint subdivision (depth <= 5)
+ * while |x_i - centroid| < 2 diam; closed-form radial integrals with a
+ * 16-point angular rule on the self panel.  FP64.  k > 0 required when
+ * burton_miller != 0, k >= 0 otherwise.  Charges 2 n^2 16 bytes.  Blocks
+ * until the matrices are built. */
+nat_status nat_bem_assemble(nat_mesh* mesh, double k, int32_t burton_miller,
+                            nat_bem_op** out, void* stream);
+
+/* a7: solve A p = B g for n_rhs Neumann vectors by GMRES (x0 = 0, restart
+ * = max_iter).  v_n: device complex [n_rhs][n_vertices or n_tris]
+ * (per-vertex data is averaged over each triangle's corners); p_out:
+ * device complex [n_rhs][n_tris] at the centroids; report: host
+ * nat_solve_report[n_rhs] or NULL.  Blocks until done. */
+nat_status nat_bem_solve(nat_bem_op* op, const double* v_n, int32_t n_rhs, int32_t layout,
+                         double tol, int32_t max_iter, double* p_out, nat_solve_report* report,
+                         void* stream);
+
+/* Copy the assembled matrices to caller device buffers A_out, B_out
+ * (complex [n_tris][n_tris] each; either may be NULL).  Stream-ordered. */
+nat_status nat_bem_op_matrices(const nat_bem_op* op, double* A_out, double* B_out, void* stream);
+void nat_bem_op_destroy(nat_bem_op* op);
+
+/* ---- per-kernel timing ---------------------------------------------------- */
+
+/* Timing of one kernel class accumulated while profiling is on: launches,
+ * summed duration between HIP events recorded on the launch stream around
+ * each launch, and the algorithmic flops of those launches (kernel-sum
+ * launches count 24, 37 or 47 flops per target-source pair for the G-only,
+ * dG/dn-only and both-term sums; 8 per element for the complex GEMV). */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+    double flops;
+} nat_kernel_stat;
+
+/* Turn per-kernel timing on or off; either way the totals are reset. */
+nat_status nat_profile_enable(nat_ctx* ctx, int32_t enable);
+/* Copy up to max_out non-empty kernel classes into out (host); returns the
+ * number written.  Waits for the device. */
+int32_t nat_profile_read(nat_ctx* ctx, nat_kernel_stat* out, int32_t max_out);
+
+/* ---- errors -------------------------------------------------------------- */
+const char* nat_status_str(nat_status s);
+/* Copy the calling thread's last error message into buf (NUL-terminated,
+ * truncated to len); returns the full message length. */
+size_t nat_last_error(char* buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NAT_BEM_H */

@@ -25,6 +25,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -32,6 +33,12 @@
 typedef double complex cplx;
 
 #define FOUR_PI (4.0 * M_PI)
+
+/* threads OpenMP will use for the parallel loops */
+int32_t orc_num_threads(void)
+{
+    return (int32_t)omp_get_max_threads();
+}
 
 /* ---------------------------------------------------------------------- */
 /* small vector helpers                                                    */

@@ -44,6 +44,7 @@ def lib():
     if _lib is None:
         build(force=False)
         L = C.CDLL(str(LIB))
+        L.orc_num_threads.restype = C.c_int32
         L.orc_geometry.argtypes = [_d, _i, C.c_int32, _d, _d, _d]
         L.orc_splitmix64.argtypes = [C.c_uint64]
         L.orc_splitmix64.restype = C.c_uint64
@@ -90,6 +91,10 @@ def _c2d(a):
     """complex128 array -> contiguous float64 view of interleaved (re, im)."""
     a = np.ascontiguousarray(a, dtype=np.complex128)
     return a.view(np.float64).reshape(-1)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 # ---------------------------------------------------------------- geometry

@@ -1,0 +1,59 @@
+"""Build libnat_bem.so for gfx950 with hipcc (in-tree, no JIT cache).
+
+Every HIP translation unit is compiled with packed-FP32 instructions turned
+off; the host driver is compiled without floating-point contraction so the
+area table is the plain IEEE result of its formulas."""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+from pathlib import Path
+
+PKG = Path(__file__).resolve().parent
+ROOT = PKG.parent
+SRC = PKG / "csrc"
+OUT = PKG / "libnat_bem.so"
+BUILD = ROOT / "_build"
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-I", str(ROOT / "include"), "-I", str(SRC), "-Wall", "-Wno-unused-function",
+          "-Wno-unused-command-line-argument"]
+PER_FILE = {"nat_api.hip": ["-ffp-contract=off"]}
+SOURCES = ["nat_api.hip", "k_sample.hip", "k_sum64.hip", "k_sum32.hip", "k_gmres.hip", "k_bem.hip"]
+
+
+def _compile(name: str) -> Path:
+    obj = BUILD / (name + ".o")
+    cmd = [HIPCC, *COMMON, *PER_FILE.get(name, []), "-c", str(SRC / name), "-o", str(obj)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {name}:\n{r.stdout}\n{r.stderr}")
+    warn = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l
+                     and "not a recognized feature" not in l)
+    if warn.strip():
+        print(warn, file=sys.stderr)
+    return obj
+
+
+def build(verbose: bool = False) -> Path:
+    BUILD.mkdir(exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+        objs = list(ex.map(_compile, SOURCES))
+    tmp = OUT.with_suffix(".so.tmp")
+    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", str(tmp), *map(str, objs)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, OUT)
+    if verbose:
+        print(f"built {OUT}")
+    return OUT
+
+
+if __name__ == "__main__":
+    build(verbose=True)

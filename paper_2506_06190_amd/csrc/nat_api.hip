@@ -1,0 +1,1102 @@
+// Host side of libnat_bem: the C entry points of nat_bem.h, the device-memory
+// ledger, the mesh registry and the drivers of the Monte-Carlo and dense
+// solves.  This file is compiled without floating-point contraction so the
+// triangle areas and the cumulative area table are the plain IEEE results
+// of the written formulas.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <unordered_map>
+
+#include "nat_internal.h"
+
+namespace {
+thread_local std::string g_last_error;
+constexpr double kInv4Pi = 0.07957747154594767;
+constexpr double kTwoPi = 6.283185307179586;
+}  // namespace
+
+namespace nat {
+
+nat_status fail(nat_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+nat_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(NAT_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+nat_status dev_alloc(nat_ctx* ctx, size_t bytes, void** ptr)
+{
+    *ptr = nullptr;
+    if (bytes == 0)
+        return NAT_OK;
+    if (ctx->budget && ctx->in_use + bytes > ctx->budget)
+        return fail(NAT_E_BUDGET, "HBM budget: need %zu bytes, %zu of %zu in use", bytes,
+                    ctx->in_use, ctx->budget);
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        return hip_fail(e, "hipMalloc");
+    }
+    ctx->in_use += bytes;
+    return NAT_OK;
+}
+
+void dev_free(nat_ctx* ctx, void* ptr, size_t bytes)
+{
+    if (!ptr)
+        return;
+    (void)hipFree(ptr);
+    ctx->in_use -= bytes;
+}
+
+nat_status workspace(nat_ctx* ctx, size_t bytes, void** ptr)
+{
+    if (bytes <= ctx->ws_bytes) {
+        *ptr = ctx->ws;
+        return NAT_OK;
+    }
+    // grow: release the old block first (the device must be idle for it)
+    if (ctx->ws) {
+        NAT_HIP(hipDeviceSynchronize());
+        dev_free(ctx, ctx->ws, ctx->ws_bytes);
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+    }
+    const size_t want = bytes + bytes / 8;
+    nat_status st = dev_alloc(ctx, want, &ctx->ws);
+    if (st != NAT_OK) {
+        st = dev_alloc(ctx, bytes, &ctx->ws);
+        if (st != NAT_OK)
+            return st;
+        ctx->ws_bytes = bytes;
+    } else {
+        ctx->ws_bytes = want;
+    }
+    *ptr = ctx->ws;
+    return NAT_OK;
+}
+
+nat_status pinned(nat_ctx* ctx, size_t bytes, void** ptr)
+{
+    if (bytes > ctx->pinned_bytes) {
+        if (ctx->pinned) {
+            NAT_HIP(hipDeviceSynchronize());
+            (void)hipHostFree(ctx->pinned);
+            ctx->pinned = nullptr;
+            ctx->pinned_bytes = 0;
+        }
+        const size_t want = bytes < 65536 ? 65536 : bytes;
+        NAT_HIP(hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
+        ctx->pinned_bytes = want;
+    }
+    *ptr = ctx->pinned;
+    return NAT_OK;
+}
+
+static hipEvent_t prof_event(nat_ctx* ctx)
+{
+    if (!ctx->prof_pool.empty()) {
+        hipEvent_t e = ctx->prof_pool.back();
+        ctx->prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+ProfScope::ProfScope(nat_ctx* c, int32_t kind, double flops, hipStream_t st)
+    : ctx(c), s(st), on(c && c->prof)
+{
+    if (!on)
+        return;
+    ev.kind = kind;
+    ev.flops = flops;
+    ev.start = prof_event(ctx);
+    ev.stop = prof_event(ctx);
+    if (!ev.start || !ev.stop) {
+        on = false;
+        return;
+    }
+    (void)hipEventRecord(ev.start, s);
+}
+
+ProfScope::~ProfScope()
+{
+    if (!on)
+        return;
+    (void)hipEventRecord(ev.stop, s);
+    ctx->prof_pending.push_back(ev);
+}
+
+void prof_collect(nat_ctx* ctx)
+{
+    if (ctx->prof_pending.empty())
+        return;
+    (void)hipDeviceSynchronize();
+    for (const NatProfEvent& e : ctx->prof_pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, e.start, e.stop) == hipSuccess) {
+            NatProfStat& st = ctx->prof_stat[e.kind];
+            st.launches += 1;
+            st.ms += ms;
+            st.flops += e.flops;
+        }
+        ctx->prof_pool.push_back(e.start);
+        ctx->prof_pool.push_back(e.stop);
+    }
+    ctx->prof_pending.clear();
+}
+
+// Gauss-Legendre nodes and weights on [0,1]: Newton's method on P_n from
+// Tricomi's initial guess, P_n and P_n' by the three-term recurrence.
+void gauss_legendre01(int n, double* x, double* w)
+{
+    const double pi = 3.141592653589793;
+    for (int i = 1; i <= n; ++i) {
+        double t = (4.0 * i - 1.0) / (4.0 * n + 2.0) * pi;
+        double z = std::cos(t) * (1.0 - (n - 1.0) / (8.0 * n * n * n));
+        double dp = 1.0;
+        for (int it = 0; it < 64; ++it) {
+            double pm1 = 1.0, p = z;
+            for (int l = 2; l <= n; ++l) {
+                const double pn = ((2.0 * l - 1.0) * z * p - (l - 1.0) * pm1) / l;
+                pm1 = p;
+                p = pn;
+            }
+            if (n == 1) {
+                pm1 = 1.0;
+                p = z;
+            }
+            dp = n * (pm1 - z * p) / (1.0 - z * z);
+            const double step = p / dp;
+            z -= step;
+            if (std::fabs(step) <= 1e-17)
+                break;
+        }
+        {
+            double pm1 = 1.0, p = z;
+            for (int l = 2; l <= n; ++l) {
+                const double pn = ((2.0 * l - 1.0) * z * p - (l - 1.0) * pm1) / l;
+                pm1 = p;
+                p = pn;
+            }
+            dp = n * (pm1 - z * p) / (1.0 - z * z);
+        }
+        // z decreases with i; store ascending on [0,1]
+        x[n - i] = 0.5 * (1.0 + z);
+        w[n - i] = 1.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+}  // namespace nat
+
+using nat::fail;
+
+namespace {
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+nat_status set_device(const nat_ctx* ctx)
+{
+    NAT_HIP(hipSetDevice(ctx->device));
+    return NAT_OK;
+}
+
+// Validation kernels: flag[0] |= 1 on a bad query record, flag[1] |= 1 on a
+// non-finite value.
+__global__ void k_check_queries(const int32_t* tri, const double* bary, int32_t Q, int32_t nT,
+                                int32_t* flag)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Q)
+        return;
+    const int32_t t = tri[i];
+    const double b1 = bary[2 * i], b2 = bary[2 * i + 1];
+    const bool ok = t >= 0 && t < nT && b1 >= 0.0 && b2 >= 0.0 && b1 + b2 <= 1.0 + 1e-12;
+    if (!ok)
+        atomicOr(flag, 1);
+}
+
+__global__ void k_check_finite(const double* v, int64_t n, int32_t* flag)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    if (!isfinite(v[i]))
+        atomicOr(flag + 1, 1);
+}
+
+// Zero the two flags, run the checks, read them back.
+nat_status device_checks(nat_ctx* ctx, int32_t* dflag, const int32_t* q_tri, const double* q_bary,
+                         int32_t Q, int32_t nT, const double* vals, int64_t n_vals,
+                         hipStream_t s, int32_t* host_flags)
+{
+    NAT_HIP(hipMemsetAsync(dflag, 0, 2 * sizeof(int32_t), s));
+    if (Q > 0) {
+        hipLaunchKernelGGL(k_check_queries, dim3((Q + 255) / 256), dim3(256), 0, s, q_tri, q_bary,
+                           Q, nT, dflag);
+        NAT_HIP(hipGetLastError());
+    }
+    if (n_vals > 0) {
+        hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((n_vals + 255) / 256)), dim3(256), 0, s,
+                           vals, n_vals, dflag);
+        NAT_HIP(hipGetLastError());
+    }
+    void* pin = nullptr;
+    nat_status st = nat::pinned(ctx, 64, &pin);
+    if (st != NAT_OK)
+        return st;
+    NAT_HIP(hipMemcpyAsync(pin, dflag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    NAT_HIP(hipStreamSynchronize(s));
+    std::memcpy(host_flags, pin, 2 * sizeof(int32_t));
+    return NAT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nat_status_str(nat_status s)
+{
+    switch (s) {
+    case NAT_OK:
+        return "NAT_OK";
+    case NAT_E_INVALID:
+        return "NAT_E_INVALID";
+    case NAT_E_BUDGET:
+        return "NAT_E_BUDGET";
+    case NAT_E_NOCONV:
+        return "NAT_E_NOCONV";
+    case NAT_E_HIP:
+        return "NAT_E_HIP";
+    case NAT_E_INTERNAL:
+        return "NAT_E_INTERNAL";
+    }
+    return "NAT_E_UNKNOWN";
+}
+
+size_t nat_last_error(char* buf, size_t len)
+{
+    if (buf && len) {
+        const size_t n = g_last_error.size() < len - 1 ? g_last_error.size() : len - 1;
+        std::memcpy(buf, g_last_error.data(), n);
+        buf[n] = '\0';
+    }
+    return g_last_error.size();
+}
+
+void nat_mc_opts_default(nat_mc_opts* o)
+{
+    if (!o)
+        return;
+    o->precision = NAT_PREC_FP32;
+    o->layout = NAT_NEUMANN_PER_VERTEX;
+    o->eps_scale = 1.0;
+    o->gmres_tol = 1e-6;
+    o->gmres_max_iter = 200;
+    o->reserved = 0;
+}
+
+nat_status nat_ctx_create(int32_t device, size_t hbm_budget_bytes, nat_ctx** out)
+{
+    if (!out)
+        return fail(NAT_E_INVALID, "nat_ctx_create: out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess)
+        return nat::hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count)
+        return fail(NAT_E_INVALID, "nat_ctx_create: device %d of %d", device, count);
+    NAT_HIP(hipSetDevice(device));
+    nat_ctx* c = new (std::nothrow) nat_ctx();
+    if (!c)
+        return fail(NAT_E_INTERNAL, "out of host memory");
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    // quadrature rules of the dense assembly: far 3-point, angular 16-point
+    double rules[2 * 3 + 2 * 16];
+    nat::gauss_legendre01(3, rules, rules + 3);
+    nat::gauss_legendre01(16, rules + 6, rules + 22);
+    void* d = nullptr;
+    nat_status st = nat::dev_alloc(c, sizeof(rules), &d);
+    if (st != NAT_OK) {
+        delete c;
+        return st;
+    }
+    c->d_rules = static_cast<double*>(d);
+    e = hipMemcpy(c->d_rules, rules, sizeof(rules), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        nat::dev_free(c, d, sizeof(rules));
+        delete c;
+        return nat::hip_fail(e, "hipMemcpy rules");
+    }
+    *out = c;
+    return NAT_OK;
+}
+
+void nat_ctx_destroy(nat_ctx* ctx)
+{
+    if (!ctx)
+        return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->ws)
+        nat::dev_free(ctx, ctx->ws, ctx->ws_bytes);
+    if (ctx->d_rules)
+        nat::dev_free(ctx, ctx->d_rules, sizeof(double) * 38);
+    if (ctx->pinned)
+        (void)hipHostFree(ctx->pinned);
+    nat::prof_collect(ctx);
+    for (hipEvent_t e : ctx->prof_pool)
+        (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+size_t nat_ctx_bytes_in_use(const nat_ctx* ctx) { return ctx ? ctx->in_use : 0; }
+
+nat_status nat_profile_enable(nat_ctx* ctx, int32_t enable)
+{
+    if (!ctx)
+        return fail(NAT_E_INVALID, "nat_profile_enable: ctx is NULL");
+    nat_status st = set_device(ctx);
+    if (st != NAT_OK)
+        return st;
+    nat::prof_collect(ctx);
+    for (auto& x : ctx->prof_stat)
+        x = NatProfStat();
+    ctx->prof = enable != 0;
+    return NAT_OK;
+}
+
+int32_t nat_profile_read(nat_ctx* ctx, nat_kernel_stat* out, int32_t max_out)
+{
+    static const char* names[8] = {"sum32_rhs", "sum32_matvec", "sum32_eval", "sum64",
+                                   "gmres_orth", "bem_assemble", "zgemv", "other"};
+    if (!ctx || (max_out > 0 && !out))
+        return 0;
+    if (set_device(ctx) != NAT_OK)
+        return 0;
+    nat::prof_collect(ctx);
+    int32_t n = 0;
+    for (int i = 0; i < 8 && n < max_out; ++i) {
+        const NatProfStat& st = ctx->prof_stat[i];
+        if (st.launches == 0)
+            continue;
+        std::snprintf(out[n].name, sizeof(out[n].name), "%s", names[i]);
+        out[n].launches = st.launches;
+        out[n].total_ms = st.ms;
+        out[n].flops = st.flops;
+        ++n;
+    }
+    return n;
+}
+
+// Closed, consistently oriented, no repeated or out-of-range index.
+static nat_status validate_topology(const double* vertices, int32_t n_vertices, const int32_t* tris,
+                                    int32_t n_tris)
+{
+    if (!vertices || !tris)
+        return fail(NAT_E_INVALID, "mesh: NULL argument");
+    if (n_vertices < 4 || n_tris < 4)
+        return fail(NAT_E_INVALID, "mesh: need >= 4 vertices and triangles");
+    for (int64_t i = 0; i < 3 * (int64_t)n_vertices; ++i)
+        if (!is_finite(vertices[i]))
+            return fail(NAT_E_INVALID, "mesh: non-finite vertex coordinate");
+    // each directed edge once, its reverse once
+    std::unordered_map<uint64_t, int32_t> edges;
+    edges.reserve(3 * (size_t)n_tris * 2);
+    for (int32_t t = 0; t < n_tris; ++t) {
+        const int32_t* f = tris + 3 * t;
+        for (int c = 0; c < 3; ++c) {
+            if (f[c] < 0 || f[c] >= n_vertices)
+                return fail(NAT_E_INVALID, "mesh: triangle %d index out of range", t);
+        }
+        if (f[0] == f[1] || f[1] == f[2] || f[2] == f[0])
+            return fail(NAT_E_INVALID, "mesh: triangle %d repeats a vertex", t);
+        for (int c = 0; c < 3; ++c) {
+            const uint64_t key = ((uint64_t)(uint32_t)f[c] << 32) | (uint32_t)f[(c + 1) % 3];
+            if (++edges[key] > 1)
+                return fail(NAT_E_INVALID,
+                            "mesh: directed edge %d->%d used twice (inconsistent orientation or "
+                            "non-manifold)",
+                            f[c], f[(c + 1) % 3]);
+        }
+    }
+    for (const auto& kv : edges) {
+        const uint64_t rev = (kv.first << 32) | (kv.first >> 32);
+        if (edges.find(rev) == edges.end())
+            return fail(NAT_E_INVALID, "mesh: not closed (boundary edge %u->%u)",
+                        (unsigned)(kv.first >> 32), (unsigned)(kv.first & 0xffffffffu));
+    }
+    return NAT_OK;
+}
+
+// Areas, unit normals and the running area sum in the written operation order
+// (no contraction in this file).  Rejects zero-area triangles and a
+// non-positive enclosed volume.
+static nat_status mesh_geometry(const double* V, int32_t n_tris, const int32_t* tris, double* area,
+                                double* normal, double* cdf)
+{
+    double run = 0.0, vol6 = 0.0;
+    for (int32_t t = 0; t < n_tris; ++t) {
+        const double* v0 = V + 3 * (size_t)tris[3 * t + 0];
+        const double* v1 = V + 3 * (size_t)tris[3 * t + 1];
+        const double* v2 = V + 3 * (size_t)tris[3 * t + 2];
+        const double e1[3] = {v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2]};
+        const double e2[3] = {v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2]};
+        const double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                             e1[0] * e2[1] - e1[1] * e2[0]};
+        const double len = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        if (!(len > 0.0))
+            return fail(NAT_E_INVALID, "mesh: triangle %d has zero area", t);
+        area[t] = 0.5 * len;
+        normal[3 * t + 0] = c[0] / len;
+        normal[3 * t + 1] = c[1] / len;
+        normal[3 * t + 2] = c[2] / len;
+        run = run + area[t];
+        cdf[t] = run;
+        vol6 += v0[0] * (v1[1] * v2[2] - v1[2] * v2[1]) - v0[1] * (v1[0] * v2[2] - v1[2] * v2[0]) +
+                v0[2] * (v1[0] * v2[1] - v1[1] * v2[0]);
+    }
+    if (!(vol6 > 0.0))
+        return fail(NAT_E_INVALID, "mesh: enclosed volume is not positive (inward orientation?)");
+    return NAT_OK;
+}
+
+nat_status nat_mesh_validate(const double* vertices, int32_t n_vertices, const int32_t* tris,
+                             int32_t n_tris)
+{
+    nat_status st = validate_topology(vertices, n_vertices, tris, n_tris);
+    if (st != NAT_OK)
+        return st;
+    std::vector<double> a(n_tris), nn(3 * (size_t)n_tris), c(n_tris);
+    return mesh_geometry(vertices, n_tris, tris, a.data(), nn.data(), c.data());
+}
+
+nat_status nat_mesh_geometry(const double* vertices, int32_t n_vertices, const int32_t* tris,
+                             int32_t n_tris, double* area, double* normal, double* cdf)
+{
+    if (!area || !normal || !cdf)
+        return fail(NAT_E_INVALID, "nat_mesh_geometry: NULL output");
+    nat_status st = validate_topology(vertices, n_vertices, tris, n_tris);
+    if (st != NAT_OK)
+        return st;
+    return mesh_geometry(vertices, n_tris, tris, area, normal, cdf);
+}
+
+nat_status nat_mesh_create(nat_ctx* ctx, const double* vertices, int32_t n_vertices,
+                           const int32_t* tris, int32_t n_tris, nat_mesh** out)
+{
+    if (!out)
+        return fail(NAT_E_INVALID, "nat_mesh_create: out is NULL");
+    *out = nullptr;
+    if (!ctx)
+        return fail(NAT_E_INVALID, "nat_mesh_create: ctx is NULL");
+    {
+        nat_status st = validate_topology(vertices, n_vertices, tris, n_tris);
+        if (st != NAT_OK)
+            return st;
+    }
+    nat_mesh* m = new (std::nothrow) nat_mesh();
+    if (!m)
+        return fail(NAT_E_INTERNAL, "out of host memory");
+    m->ctx = ctx;
+    m->nV = n_vertices;
+    m->nT = n_tris;
+    m->V.assign(vertices, vertices + 3 * (size_t)n_vertices);
+    m->T.assign(tris, tris + 3 * (size_t)n_tris);
+    m->area.resize(n_tris);
+    m->normal.resize(3 * (size_t)n_tris);
+    m->cdf.resize(n_tris);
+    {
+        nat_status gst = mesh_geometry(m->V.data(), n_tris, tris, m->area.data(), m->normal.data(),
+                                       m->cdf.data());
+        if (gst != NAT_OK) {
+            delete m;
+            return gst;
+        }
+    }
+    m->area_total = m->cdf[n_tris - 1];
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d)
+        lo[d] = hi[d] = m->V[d];
+    for (int32_t i = 0; i < n_vertices; ++i)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::fmin(lo[d], m->V[3 * (size_t)i + d]);
+            hi[d] = std::fmax(hi[d], m->V[3 * (size_t)i + d]);
+        }
+    for (int d = 0; d < 3; ++d)
+        m->center[d] = 0.5 * (lo[d] + hi[d]);
+
+    nat_status st = set_device(ctx);
+    if (st != NAT_OK) {
+        delete m;
+        return st;
+    }
+    const size_t bV = sizeof(double) * 3 * (size_t)n_vertices, bT = sizeof(int32_t) * 3 * (size_t)n_tris,
+                 bN = sizeof(double) * 3 * (size_t)n_tris, bC = sizeof(double) * (size_t)n_tris;
+    m->bytes = nat::carve_size<>({bV, bT, bN, bC});
+    void* blk = nullptr;
+    st = nat::dev_alloc(ctx, m->bytes, &blk);
+    if (st != NAT_OK) {
+        delete m;
+        return st;
+    }
+    nat::Carver cv(blk);
+    m->d_V = cv.take<double>(3 * (size_t)n_vertices);
+    m->d_T = cv.take<int32_t>(3 * (size_t)n_tris);
+    m->d_normal = cv.take<double>(3 * (size_t)n_tris);
+    m->d_cdf = cv.take<double>(n_tris);
+    hipError_t e = hipMemcpy(m->d_V, m->V.data(), bV, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(m->d_T, m->T.data(), bT, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(m->d_normal, m->normal.data(), bN, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(m->d_cdf, m->cdf.data(), bC, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        nat::dev_free(ctx, blk, m->bytes);
+        delete m;
+        return nat::hip_fail(e, "hipMemcpy mesh");
+    }
+    *out = m;
+    return NAT_OK;
+}
+
+void nat_mesh_destroy(nat_mesh* m)
+{
+    if (!m)
+        return;
+    (void)hipSetDevice(m->ctx->device);
+    (void)hipDeviceSynchronize();
+    nat::dev_free(m->ctx, m->d_V, m->bytes);
+    delete m;
+}
+
+nat_status nat_mesh_info(const nat_mesh* m, double* area, int32_t* nV, int32_t* nT)
+{
+    if (!m)
+        return fail(NAT_E_INVALID, "nat_mesh_info: mesh is NULL");
+    if (area)
+        *area = m->area_total;
+    if (nV)
+        *nV = m->nV;
+    if (nT)
+        *nT = m->nT;
+    return NAT_OK;
+}
+
+nat_status nat_mesh_vertex_queries(const nat_mesh* m, int32_t* tri, double* bary)
+{
+    if (!m || !tri || !bary)
+        return fail(NAT_E_INVALID, "nat_mesh_vertex_queries: NULL argument");
+    for (int32_t v = 0; v < m->nV; ++v)
+        tri[v] = -1;
+    for (int32_t t = 0; t < m->nT; ++t)
+        for (int c = 0; c < 3; ++c) {
+            const int32_t v = m->T[3 * (size_t)t + c];
+            if (tri[v] < 0) {
+                tri[v] = t;
+                bary[2 * v] = c == 1 ? 1.0 : 0.0;
+                bary[2 * v + 1] = c == 2 ? 1.0 : 0.0;
+            }
+        }
+    for (int32_t v = 0; v < m->nV; ++v)
+        if (tri[v] < 0)
+            return fail(NAT_E_INVALID, "nat_mesh_vertex_queries: vertex %d is in no triangle", v);
+    return NAT_OK;
+}
+
+nat_status nat_mcbem_samples(nat_mesh* m, int32_t N, uint64_t seed, int32_t* tri, double* bary,
+                             void* stream)
+{
+    if (!m || !tri || !bary)
+        return fail(NAT_E_INVALID, "nat_mcbem_samples: NULL argument");
+    if (N < 1)
+        return fail(NAT_E_INVALID, "nat_mcbem_samples: N = %d", N);
+    nat_status st = set_device(m->ctx);
+    if (st != NAT_OK)
+        return st;
+    NAT_HIP(nat::launch_samples(m, N, seed, tri, bary, static_cast<hipStream_t>(stream)));
+    return NAT_OK;
+}
+
+nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes, const double* k,
+                              const int32_t* q_tri, const double* q_bary, int32_t Q, int32_t N,
+                              uint64_t seed, const nat_mc_opts* opts, double* p_out,
+                              double* p_samples, nat_solve_report* report, void* stream)
+{
+    using namespace nat;
+    if (!mesh || !v_n || !k || !opts)
+        return fail(NAT_E_INVALID, "nat_mcbem_estimate: NULL argument");
+    if (n_modes < 1 || n_modes > 4096)
+        return fail(NAT_E_INVALID, "nat_mcbem_estimate: n_modes = %d", n_modes);
+    if (N < 2 || N > (1 << 24))
+        return fail(NAT_E_INVALID, "nat_mcbem_estimate: n_samples = %d", N);
+    if (Q < 0 || Q > (1 << 26) || (Q > 0 && (!q_tri || !q_bary || !p_out)))
+        return fail(NAT_E_INVALID, "nat_mcbem_estimate: bad queries (Q = %d)", Q);
+    if (opts->precision != NAT_PREC_FP64 && opts->precision != NAT_PREC_FP32)
+        return fail(NAT_E_INVALID, "nat_mcbem_estimate: precision %d", opts->precision);
+    if (opts->layout != NAT_NEUMANN_PER_VERTEX && opts->layout != NAT_NEUMANN_PER_TRIANGLE)
+        return fail(NAT_E_INVALID, "nat_mcbem_estimate: layout %d", opts->layout);
+    if (!(opts->eps_scale > 0.0) || !is_finite(opts->eps_scale) || !(opts->gmres_tol > 0.0) ||
+        opts->gmres_max_iter < 1 || opts->gmres_max_iter > 1000 || opts->reserved != 0)
+        return fail(NAT_E_INVALID, "nat_mcbem_estimate: bad solver options");
+    for (int32_t m = 0; m < n_modes; ++m)
+        if (!(k[m] > 0.0) || !is_finite(k[m]))
+            return fail(NAT_E_INVALID, "nat_mcbem_estimate: k[%d] = %g", m, k[m]);
+    nat_ctx* ctx = mesh->ctx;
+    nat_status st = set_device(ctx);
+    if (st != NAT_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool fp32 = opts->precision == NAT_PREC_FP32;
+    const int32_t M = n_modes;
+    const int32_t mmax = opts->gmres_max_iter;
+    const int32_t ng = opts->layout == NAT_NEUMANN_PER_TRIANGLE ? mesh->nT : mesh->nV;
+    const size_t n = N, q = Q;
+
+    // scratch layout
+    SumArgs probe{};
+    probe.n_modes = M;
+    probe.NS = N;
+    probe.NT = N;
+    const size_t partA = fp32 ? sum32_partial_bytes(probe) : 0;
+    probe.NT = Q;
+    const size_t partB = fp32 && Q > 0 ? sum32_partial_bytes(probe) : 0;
+    const size_t part = partA > partB ? partA : partB;
+    const size_t bytes = carve_size<>(
+        {sizeof(int32_t) * 4, sizeof(int32_t) * n, sizeof(double) * 2 * n, sizeof(double) * 3 * n,
+         sizeof(double) * 3 * n, sizeof(float) * 3 * n, sizeof(float) * 3 * n,
+         sizeof(double) * 3 * q, sizeof(float) * 3 * q, sizeof(double2) * M * n,
+         sizeof(double2) * M * q, sizeof(double2) * M * n, sizeof(double2) * M * n,
+         sizeof(float2) * M * n, sizeof(double) * M, sizeof(float) * M, sizeof(float) * M, part,
+         gmres_state_bytes(N, M, mmax)});
+    void* ws = nullptr;
+    st = workspace(ctx, bytes, &ws);
+    if (st != NAT_OK)
+        return st;
+    Carver cv(ws);
+    int32_t* dflag = cv.take<int32_t>(4);
+    int32_t* tri = cv.take<int32_t>(n);
+    double* bary = cv.take<double>(2 * n);
+    PointStreams ps{cv.take<double>(3 * n), cv.take<double>(3 * n), cv.take<float>(3 * n),
+                    cv.take<float>(3 * n)};
+    PointStreams qs{cv.take<double>(3 * q), nullptr, cv.take<float>(3 * q), nullptr};
+    double2* gj = cv.take<double2>(M * n);
+    double2* gq = cv.take<double2>(M * q);
+    double2* b = cv.take<double2>(M * n);
+    double2* xin = cv.take<double2>(M * n);
+    float2* a32 = cv.take<float2>(M * n);
+    double* dk = cv.take<double>(M);
+    float* dk32 = cv.take<float>(M);
+    float* dkap = cv.take<float>(M);
+    void* partial = cv.take<char>(part);
+    GmresState gs{};
+    gs.n = N;
+    gs.n_modes = M;
+    gs.mmax = mmax;
+    gmres_carve(gs, cv);
+
+    // validation of the device inputs
+    int32_t flags[2] = {0, 0};
+    st = device_checks(ctx, dflag, q_tri, q_bary, Q, mesh->nT, v_n, 2 * (int64_t)M * ng, s, flags);
+    if (st != NAT_OK)
+        return st;
+    if (flags[0])
+        return fail(NAT_E_INVALID, "nat_mcbem_estimate: query record out of range");
+    if (flags[1])
+        return fail(NAT_E_INVALID, "nat_mcbem_estimate: non-finite Neumann data");
+
+    // per-mode constants
+    void* pin = nullptr;
+    st = pinned(ctx, sizeof(double) * M * 2 + sizeof(float) * M * 2 + 64, &pin);
+    if (st != NAT_OK)
+        return st;
+    {
+        double* hk = static_cast<double*>(pin);
+        float* hk32 = reinterpret_cast<float*>(hk + M);
+        float* hkap = hk32 + M;
+        for (int32_t m = 0; m < M; ++m) {
+            hk[m] = k[m];
+            hk32[m] = static_cast<float>(k[m]);
+            hkap[m] = static_cast<float>(k[m] / kTwoPi);
+        }
+        NAT_HIP(hipMemcpyAsync(dk, hk, sizeof(double) * M, hipMemcpyHostToDevice, s));
+        NAT_HIP(hipMemcpyAsync(dk32, hk32, sizeof(float) * M, hipMemcpyHostToDevice, s));
+        NAT_HIP(hipMemcpyAsync(dkap, hkap, sizeof(float) * M, hipMemcpyHostToDevice, s));
+    }
+
+    const double area = mesh->area_total;
+    const double w = area / static_cast<double>(N);
+    const double eps = opts->eps_scale * std::sqrt(area / (M_PI * static_cast<double>(N)));
+    const double wscale = w * kInv4Pi;
+
+    // a2: samples, points, Neumann data
+    NAT_HIP(launch_samples(mesh, N, seed, tri, bary, s));
+    NAT_HIP(launch_points(mesh, N, tri, bary, ps, s));
+    NAT_HIP(launch_points(mesh, Q, q_tri, q_bary, qs, s));
+    NAT_HIP(launch_neumann(mesh, opts->layout, reinterpret_cast<const double2*>(v_n), ng, M, N,
+                           tri, bary, gj, s));
+    NAT_HIP(launch_neumann(mesh, opts->layout, reinterpret_cast<const double2*>(v_n), ng, M, Q,
+                           q_tri, q_bary, gq, s));
+
+    SumArgs base{};
+    base.n_modes = M;
+    base.s64 = ps.x64;
+    base.sn64 = ps.n64;
+    base.s32 = ps.x32;
+    base.sn32 = ps.n32;
+    base.k = dk;
+    base.k32 = dk32;
+    base.kappa32 = dkap;
+    base.w = w;
+    base.eps = eps;
+    base.NS = N;
+    base.ld_s32 = N;
+
+    // a3: right-hand side
+    {
+        SumArgs a = base;
+        a.op = OP_RHS;
+        a.NT = N;
+        a.t64 = ps.x64;
+        a.t32 = ps.x32;
+        a.g_src = gj;
+        a.ld_gs = N;
+        a.g_tgt = gj;
+        a.ld_gt = N;
+        a.out = b;
+        a.ld_out = N;
+        if (fp32) {
+            NAT_HIP(launch_weight32(gj, N, M, N, wscale, a32, N, s));
+            a.g_src32 = a32;
+            ProfScope ps_(ctx, PK_SUM32_RHS, 24.0 * n * n * M, s);
+            NAT_HIP(launch_sum32(a, partial, s));
+        } else {
+            ProfScope ps_(ctx, PK_SUM64, 24.0 * n * n * M, s);
+            NAT_HIP(launch_sum64(a, s));
+        }
+    }
+
+    // a4: GMRES on (I/2 - K) p = b
+    gs.tol = opts->gmres_tol;
+    gs.v32_scale = wscale;
+    if (!fp32)
+        gs.v32 = nullptr;
+    NAT_HIP(launch_gmres_init(gs, b, N, s));
+    int32_t* hact = static_cast<int32_t*>(pin);
+    int32_t n_active = M;
+    for (int32_t j = 0; j < mmax; ++j) {
+        SumArgs a = base;
+        a.op = OP_MATVEC;
+        a.NT = N;
+        a.t64 = ps.x64;
+        a.t32 = ps.x32;
+        a.p_src = gs.V + (size_t)j * n;
+        a.ld_ps = (int64_t)(mmax + 1) * N;
+        a.p_src32 = gs.v32;
+        a.active = gs.active;
+        a.out = gs.w;
+        a.ld_out = N;
+        if (fp32) {
+            ProfScope ps_(ctx, PK_SUM32_MATVEC, 37.0 * n * n * n_active, s);
+            NAT_HIP(launch_sum32(a, partial, s));
+        } else {
+            ProfScope ps_(ctx, PK_SUM64, 37.0 * n * n * n_active, s);
+            NAT_HIP(launch_sum64(a, s));
+        }
+        {
+            ProfScope ps_(ctx, PK_GMRES_ORTH, 0.0, s);
+            NAT_HIP(launch_gmres_orth(gs, j, s));
+        }
+        NAT_HIP(hipMemcpyAsync(hact, gs.active, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+        NAT_HIP(hipStreamSynchronize(s));
+        n_active = 0;
+        for (int32_t m = 0; m < M; ++m)
+            n_active += hact[m] != 0;
+        if (!n_active)
+            break;
+    }
+    double2* x = p_samples ? reinterpret_cast<double2*>(p_samples) : xin;
+    NAT_HIP(launch_gmres_solution(gs, x, N, s));
+
+    // a5: surface evaluation
+    if (Q > 0) {
+        SumArgs a = base;
+        a.op = OP_EVAL;
+        a.NT = Q;
+        a.t64 = qs.x64;
+        a.t32 = qs.x32;
+        a.g_src = gj;
+        a.ld_gs = N;
+        a.p_src = x;
+        a.ld_ps = N;
+        a.g_tgt = gq;
+        a.ld_gt = Q;
+        a.out = reinterpret_cast<double2*>(p_out);
+        a.ld_out = Q;
+        if (fp32) {
+            NAT_HIP(launch_weight32(gj, N, M, N, -wscale, a32, N, s));
+            NAT_HIP(launch_weight32(x, N, M, N, wscale, gs.v32, N, s));
+            a.g_src32 = a32;
+            a.p_src32 = gs.v32;
+            ProfScope ps_(ctx, PK_SUM32_EVAL, 47.0 * q * n * M, s);
+            NAT_HIP(launch_sum32(a, partial, s));
+        } else {
+            ProfScope ps_(ctx, PK_SUM64, 47.0 * q * n * M, s);
+            NAT_HIP(launch_sum64(a, s));
+        }
+    }
+    prof_collect(ctx);
+
+    // reports
+    {
+        int32_t* hit = static_cast<int32_t*>(pin);
+        double* hres = reinterpret_cast<double*>(static_cast<char*>(pin) + 8 * ((M * 4 + 7) / 8));
+        st = pinned(ctx, 8 * ((M * 4 + 7) / 8) + sizeof(double) * M + 64, &pin);
+        if (st != NAT_OK)
+            return st;
+        hit = static_cast<int32_t*>(pin);
+        hres = reinterpret_cast<double*>(static_cast<char*>(pin) + 8 * ((M * 4 + 7) / 8));
+        NAT_HIP(hipMemcpyAsync(hit, gs.iters, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+        NAT_HIP(hipMemcpyAsync(hres, gs.resid, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+        NAT_HIP(hipStreamSynchronize(s));
+        bool all_conv = true;
+        for (int32_t m = 0; m < M; ++m) {
+            const bool conv = hres[m] <= opts->gmres_tol;
+            all_conv &= conv;
+            if (report) {
+                report[m].iters = hit[m];
+                report[m].converged = conv ? 1 : 0;
+                report[m].rel_resid = hres[m];
+                report[m].eps = eps;
+                report[m].area = area;
+            }
+        }
+        if (!all_conv)
+            return fail(NAT_E_NOCONV, "nat_mcbem_estimate: GMRES stopped above tolerance");
+    }
+    return NAT_OK;
+}
+
+nat_status nat_bem_assemble(nat_mesh* mesh, double k, int32_t burton_miller, nat_bem_op** out,
+                            void* stream)
+{
+    using namespace nat;
+    if (!out)
+        return fail(NAT_E_INVALID, "nat_bem_assemble: out is NULL");
+    *out = nullptr;
+    if (!mesh)
+        return fail(NAT_E_INVALID, "nat_bem_assemble: mesh is NULL");
+    if (!is_finite(k) || k < 0.0 || (burton_miller && !(k > 0.0)))
+        return fail(NAT_E_INVALID, "nat_bem_assemble: k = %g", k);
+    nat_ctx* ctx = mesh->ctx;
+    nat_status st = set_device(ctx);
+    if (st != NAT_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t n = mesh->nT;
+    nat_bem_op* op = new (std::nothrow) nat_bem_op();
+    if (!op)
+        return fail(NAT_E_INTERNAL, "out of host memory");
+    op->ctx = ctx;
+    op->mesh = mesh;
+    op->k = k;
+    op->burton_miller = burton_miller ? 1 : 0;
+    op->n = n;
+    op->bytes = 2 * sizeof(double2) * (size_t)n * n + 256;
+    void* blk = nullptr;
+    st = dev_alloc(ctx, op->bytes, &blk);
+    if (st != NAT_OK) {
+        delete op;
+        return st;
+    }
+    op->d_A = static_cast<double2*>(blk);
+    op->d_B = op->d_A + (size_t)n * n;
+
+    BemGeom g{n, mesh->d_V, mesh->d_T, ctx->d_rules};
+    const double2 beta = op->burton_miller ? make_double2(0.0, 1.0 / k) : make_double2(0.0, 0.0);
+    int32_t cap = 64 * n;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        void* ws = nullptr;
+        st = workspace(ctx, carve_size<>({sizeof(int32_t) * 4, sizeof(int32_t) * 2 * (size_t)cap}), &ws);
+        if (st != NAT_OK) {
+            nat_bem_op_destroy(op);
+            return st;
+        }
+        Carver cv(ws);
+        int32_t* count = cv.take<int32_t>(4);
+        int32_t* list = cv.take<int32_t>(2 * (size_t)cap);
+        hipError_t e = hipMemsetAsync(count, 0, sizeof(int32_t), s);
+        ProfScope ps_(ctx, PK_BEM_ASSEMBLE, 0.0, s);
+        if (e == hipSuccess)
+            e = launch_bem_far(g, k, beta, op->d_A, op->d_B, list, cap, count, s);
+        int32_t n_near = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&n_near, count, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            nat_bem_op_destroy(op);
+            return hip_fail(e, "dense assembly, far pass");
+        }
+        if (n_near > cap) {
+            cap = n_near;
+            continue;
+        }
+        e = launch_bem_near(g, k, beta, op->d_A, op->d_B, list, n_near, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            nat_bem_op_destroy(op);
+            return hip_fail(e, "dense assembly, near pass");
+        }
+        *out = op;
+        return NAT_OK;
+    }
+    nat_bem_op_destroy(op);
+    return fail(NAT_E_INTERNAL, "nat_bem_assemble: near-pair list did not fit");
+}
+
+nat_status nat_bem_solve(nat_bem_op* op, const double* v_n, int32_t n_rhs, int32_t layout,
+                         double tol, int32_t max_iter, double* p_out, nat_solve_report* report,
+                         void* stream)
+{
+    using namespace nat;
+    if (!op || !v_n || !p_out)
+        return fail(NAT_E_INVALID, "nat_bem_solve: NULL argument");
+    if (n_rhs < 1 || n_rhs > 4096)
+        return fail(NAT_E_INVALID, "nat_bem_solve: n_rhs = %d", n_rhs);
+    if (layout != NAT_NEUMANN_PER_VERTEX && layout != NAT_NEUMANN_PER_TRIANGLE)
+        return fail(NAT_E_INVALID, "nat_bem_solve: layout %d", layout);
+    if (!(tol > 0.0) || max_iter < 1 || max_iter > 2000)
+        return fail(NAT_E_INVALID, "nat_bem_solve: tol %g, max_iter %d", tol, max_iter);
+    nat_ctx* ctx = op->ctx;
+    nat_status st = set_device(ctx);
+    if (st != NAT_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t n = op->n;
+    const int32_t M = n_rhs;
+    const int32_t ng = layout == NAT_NEUMANN_PER_TRIANGLE ? n : op->mesh->nV;
+    const size_t bytes = carve_size<>({sizeof(int32_t) * 4, sizeof(double2) * (size_t)M * n,
+                                       sizeof(double2) * (size_t)M * n,
+                                       gmres_state_bytes(n, M, max_iter)});
+    void* ws = nullptr;
+    st = workspace(ctx, bytes, &ws);
+    if (st != NAT_OK)
+        return st;
+    Carver cv(ws);
+    int32_t* dflag = cv.take<int32_t>(4);
+    double2* gp = cv.take<double2>((size_t)M * n);
+    double2* b = cv.take<double2>((size_t)M * n);
+    GmresState gs{};
+    gs.n = n;
+    gs.n_modes = M;
+    gs.mmax = max_iter;
+    gmres_carve(gs, cv);
+    gs.v32 = nullptr;
+    gs.tol = tol;
+
+    int32_t flags[2] = {0, 0};
+    st = device_checks(ctx, dflag, nullptr, nullptr, 0, 0, v_n, 2 * (int64_t)M * ng, s, flags);
+    if (st != NAT_OK)
+        return st;
+    if (flags[1])
+        return fail(NAT_E_INVALID, "nat_bem_solve: non-finite Neumann data");
+
+    const double2* g = reinterpret_cast<const double2*>(v_n);
+    if (layout == NAT_NEUMANN_PER_VERTEX) {
+        NAT_HIP(launch_panel_data(op->mesh->d_T, n, g, ng, M, gp, n, s));
+    } else {
+        NAT_HIP(hipMemcpyAsync(gp, g, sizeof(double2) * (size_t)M * n, hipMemcpyDeviceToDevice, s));
+    }
+    NAT_HIP(launch_zgemv(op->d_B, n, gp, n, M, b, n, nullptr, s));
+    NAT_HIP(launch_gmres_init(gs, b, n, s));
+    void* pin = nullptr;
+    st = pinned(ctx, sizeof(double) * M + sizeof(int32_t) * M + 64, &pin);
+    if (st != NAT_OK)
+        return st;
+    int32_t* hact = static_cast<int32_t*>(pin);
+    for (int32_t j = 0; j < max_iter; ++j) {
+        {
+            ProfScope ps_(ctx, PK_ZGEMV, 8.0 * n * (double)n * M, s);
+            NAT_HIP(launch_zgemv(op->d_A, n, gs.V + (size_t)j * n, (int64_t)(max_iter + 1) * n, M,
+                                 gs.w, n, gs.active, s));
+        }
+        NAT_HIP(launch_gmres_orth(gs, j, s));
+        NAT_HIP(hipMemcpyAsync(hact, gs.active, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+        NAT_HIP(hipStreamSynchronize(s));
+        bool any = false;
+        for (int32_t m = 0; m < M; ++m)
+            any |= hact[m] != 0;
+        if (!any)
+            break;
+    }
+    NAT_HIP(launch_gmres_solution(gs, reinterpret_cast<double2*>(p_out), n, s));
+    int32_t* hit = static_cast<int32_t*>(pin);
+    double* hres = reinterpret_cast<double*>(static_cast<char*>(pin) + 8 * ((M * 4 + 7) / 8));
+    NAT_HIP(hipMemcpyAsync(hit, gs.iters, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+    NAT_HIP(hipMemcpyAsync(hres, gs.resid, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+    NAT_HIP(hipStreamSynchronize(s));
+    bool all_conv = true;
+    for (int32_t m = 0; m < M; ++m) {
+        const bool conv = hres[m] <= tol;
+        all_conv &= conv;
+        if (report) {
+            report[m].iters = hit[m];
+            report[m].converged = conv ? 1 : 0;
+            report[m].rel_resid = hres[m];
+            report[m].eps = 0.0;
+            report[m].area = op->mesh->area_total;
+        }
+    }
+    if (!all_conv)
+        return fail(NAT_E_NOCONV, "nat_bem_solve: GMRES stopped above tolerance");
+    return NAT_OK;
+}
+
+nat_status nat_bem_op_matrices(const nat_bem_op* op, double* A_out, double* B_out, void* stream)
+{
+    if (!op)
+        return fail(NAT_E_INVALID, "nat_bem_op_matrices: op is NULL");
+    nat_status st = set_device(op->ctx);
+    if (st != NAT_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t bytes = sizeof(double2) * (size_t)op->n * op->n;
+    if (A_out)
+        NAT_HIP(hipMemcpyAsync(A_out, op->d_A, bytes, hipMemcpyDeviceToDevice, s));
+    if (B_out)
+        NAT_HIP(hipMemcpyAsync(B_out, op->d_B, bytes, hipMemcpyDeviceToDevice, s));
+    return NAT_OK;
+}
+
+void nat_bem_op_destroy(nat_bem_op* op)
+{
+    if (!op)
+        return;
+    (void)hipSetDevice(op->ctx->device);
+    (void)hipDeviceSynchronize();
+    nat::dev_free(op->ctx, op->d_A, op->bytes);
+    delete op;
+}
+
+}  // extern "C"

@@ -1,0 +1,311 @@
+"""ctypes binding of libnat_bem.so (declared in include/nat_bem.h).
+
+Argument marshalling only: every function forwards torch tensors' device
+pointers and the current HIP stream to the C entry point of the same name
+and turns non-OK statuses into exceptions.  All computation happens in the
+HIP kernels of the library; there is no fallback path, and loading fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+from typing import Optional, Sequence
+
+import numpy as np
+
+LIB_PATH = Path(__file__).resolve().parent / "libnat_bem.so"
+
+NAT_OK, NAT_E_INVALID, NAT_E_BUDGET, NAT_E_NOCONV, NAT_E_HIP, NAT_E_INTERNAL = range(6)
+NAT_PREC_FP64, NAT_PREC_FP32 = 0, 1
+NAT_NEUMANN_PER_VERTEX, NAT_NEUMANN_PER_TRIANGLE = 0, 1
+
+
+class NatError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_str(status)}: {message}")
+        self.status = status
+
+
+class nat_mc_opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("layout", C.c_int32), ("eps_scale", C.c_double),
+                ("gmres_tol", C.c_double), ("gmres_max_iter", C.c_int32), ("reserved", C.c_int32)]
+
+
+class nat_kernel_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("flops", C.c_double)]
+
+
+class nat_solve_report(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("rel_resid", C.c_double),
+                ("eps", C.c_double), ("area", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_P = C.c_void_p
+_SIGS = {
+    "nat_ctx_create": ([C.c_int32, C.c_size_t, C.POINTER(_P)], C.c_int),
+    "nat_ctx_destroy": ([_P], None),
+    "nat_ctx_bytes_in_use": ([_P], C.c_size_t),
+    "nat_mesh_create": ([_P, _P, C.c_int32, _P, C.c_int32, C.POINTER(_P)], C.c_int),
+    "nat_mesh_destroy": ([_P], None),
+    "nat_mesh_validate": ([_P, C.c_int32, _P, C.c_int32], C.c_int),
+    "nat_mesh_geometry": ([_P, C.c_int32, _P, C.c_int32, _P, _P, _P], C.c_int),
+    "nat_mesh_info": ([_P, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+    "nat_mesh_vertex_queries": ([_P, _P, _P], C.c_int),
+    "nat_mc_opts_default": ([C.POINTER(nat_mc_opts)], None),
+    "nat_mcbem_samples": ([_P, C.c_int32, C.c_uint64, _P, _P, _P], C.c_int),
+    "nat_mcbem_estimate": ([_P, _P, C.c_int32, _P, _P, _P, C.c_int32, C.c_int32, C.c_uint64,
+                            C.POINTER(nat_mc_opts), _P, _P, _P, _P], C.c_int),
+    "nat_bem_assemble": ([_P, C.c_double, C.c_int32, C.POINTER(_P), _P], C.c_int),
+    "nat_bem_solve": ([_P, _P, C.c_int32, C.c_int32, C.c_double, C.c_int32, _P, _P, _P], C.c_int),
+    "nat_bem_op_matrices": ([_P, _P, _P, _P], C.c_int),
+    "nat_bem_op_destroy": ([_P], None),
+    "nat_profile_enable": ([_P, C.c_int32], C.c_int),
+    "nat_profile_read": ([_P, _P, C.c_int32], C.c_int32),
+    "nat_status_str": ([C.c_int], C.c_char_p),
+    "nat_last_error": ([C.c_char_p, C.c_size_t], C.c_size_t),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libnat_bem.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2506_06190_amd/build.py "
+                              "(there is no CPU fallback)")
+        L = C.CDLL(str(LIB_PATH))
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def status_str(s: int) -> str:
+    return lib().nat_status_str(s).decode()
+
+
+def last_error() -> str:
+    buf = C.create_string_buffer(1024)
+    lib().nat_last_error(buf, len(buf))
+    return buf.value.decode()
+
+
+def _check(st: int, allow=()):
+    if st != NAT_OK and st not in allow:
+        raise NatError(st, last_error())
+    return st
+
+
+def _stream(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, dtype=None, shape=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------- host-only helpers
+def nat_mesh_validate(vertices, tris):
+    """Returns (status, message); host only."""
+    v = np.ascontiguousarray(vertices, dtype=np.float64)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    st = lib().nat_mesh_validate(v.ctypes.data_as(_P), len(v), t.ctypes.data_as(_P), len(t))
+    return st, (last_error() if st != NAT_OK else "")
+
+
+def nat_mesh_geometry(vertices, tris):
+    v = np.ascontiguousarray(vertices, dtype=np.float64)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    area = np.empty(len(t))
+    normal = np.empty((len(t), 3))
+    cdf = np.empty(len(t))
+    _check(lib().nat_mesh_geometry(v.ctypes.data_as(_P), len(v), t.ctypes.data_as(_P), len(t),
+                                   area.ctypes.data_as(_P), normal.ctypes.data_as(_P),
+                                   cdf.ctypes.data_as(_P)))
+    return area, normal, cdf
+
+
+# ---------------------------------------------------------------- handles
+class Context:
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = C.c_void_p()
+        _check(lib().nat_ctx_create(device, hbm_budget_bytes, C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def bytes_in_use(self) -> int:
+        return int(lib().nat_ctx_bytes_in_use(self.handle))
+
+    def close(self):
+        if self.handle:
+            lib().nat_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mesh:
+    def __init__(self, ctx: Context, vertices: np.ndarray, tris: np.ndarray):
+        v = np.ascontiguousarray(vertices, dtype=np.float64)
+        t = np.ascontiguousarray(tris, dtype=np.int32)
+        h = C.c_void_p()
+        _check(lib().nat_mesh_create(ctx.handle, v.ctypes.data_as(_P), len(v),
+                                     t.ctypes.data_as(_P), len(t), C.byref(h)))
+        self.ctx = ctx
+        self.handle = h
+        self.n_vertices = len(v)
+        self.n_tris = len(t)
+
+    def info(self):
+        a, nv, nt = C.c_double(), C.c_int32(), C.c_int32()
+        _check(lib().nat_mesh_info(self.handle, C.byref(a), C.byref(nv), C.byref(nt)))
+        return a.value, nv.value, nt.value
+
+    def vertex_queries(self):
+        tri = np.empty(self.n_vertices, dtype=np.int32)
+        bary = np.empty((self.n_vertices, 2), dtype=np.float64)
+        _check(lib().nat_mesh_vertex_queries(self.handle, tri.ctypes.data_as(_P),
+                                             bary.ctypes.data_as(_P)))
+        return tri, bary
+
+    def close(self):
+        if self.handle:
+            lib().nat_mesh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BemOp:
+    def __init__(self, handle, mesh: Mesh, k: float):
+        self.handle = handle
+        self.mesh = mesh
+        self.k = k
+        self.n = mesh.n_tris
+
+    def close(self):
+        if self.handle:
+            lib().nat_bem_op_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ entry points
+def nat_profile_enable(ctx: Context, enable: bool = True):
+    _check(lib().nat_profile_enable(ctx.handle, int(bool(enable))))
+
+
+def nat_profile_read(ctx: Context):
+    """{kernel name: {launches, total_ms, flops, avg_ms}}"""
+    buf = (nat_kernel_stat * 16)()
+    n = lib().nat_profile_read(ctx.handle, C.cast(buf, _P), 16)
+    out = {}
+    for i in range(n):
+        b = buf[i]
+        out[b.name.decode()] = {"launches": b.launches, "total_ms": b.total_ms, "flops": b.flops,
+                                "avg_ms": b.total_ms / max(b.launches, 1)}
+    return out
+
+
+def nat_mc_opts_default() -> nat_mc_opts:
+    o = nat_mc_opts()
+    lib().nat_mc_opts_default(C.byref(o))
+    return o
+
+
+def nat_mcbem_samples(mesh: Mesh, n_samples: int, seed: int, tri, bary, stream=None):
+    import torch
+    _check(lib().nat_mcbem_samples(mesh.handle, n_samples, C.c_uint64(seed),
+                                   _dptr(tri, torch.int32, (n_samples,), "tri"),
+                                   _dptr(bary, torch.float64, (n_samples, 2), "bary"),
+                                   _stream(stream)))
+
+
+def nat_mcbem_estimate(mesh: Mesh, v_n, k: Sequence[float], q_tri, q_bary, n_samples: int,
+                       seed: int, opts: Optional[nat_mc_opts] = None, p_out=None,
+                       p_samples=None, stream=None, allow_noconv: bool = False):
+    """Returns (p_out [n_modes, Q] complex128, list of per-mode report dicts)."""
+    import torch
+    if opts is None:
+        opts = nat_mc_opts_default()
+    k = np.ascontiguousarray(np.atleast_1d(k), dtype=np.float64)
+    M = len(k)
+    ng = mesh.n_tris if opts.layout == NAT_NEUMANN_PER_TRIANGLE else mesh.n_vertices
+    Q = int(q_tri.shape[0])
+    dev = v_n.device
+    if p_out is None:
+        p_out = torch.empty((M, Q), dtype=torch.complex128, device=dev)
+    reps = (nat_solve_report * M)()
+    st = lib().nat_mcbem_estimate(
+        mesh.handle, _dptr(v_n, torch.complex128, (M, ng), "v_n"), M, k.ctypes.data_as(_P),
+        _dptr(q_tri, torch.int32, (Q,), "q_tri"), _dptr(q_bary, torch.float64, (Q, 2), "q_bary"),
+        Q, n_samples, C.c_uint64(seed), C.byref(opts),
+        _dptr(p_out, torch.complex128, (M, Q), "p_out"),
+        _dptr(p_samples, torch.complex128, (M, n_samples), "p_samples") if p_samples is not None else None,
+        C.cast(reps, _P), _stream(stream))
+    _check(st, allow=(NAT_E_NOCONV,) if allow_noconv else ())
+    return p_out, [r.as_dict() for r in reps]
+
+
+def nat_bem_assemble(mesh: Mesh, k: float, burton_miller: bool = True, stream=None) -> BemOp:
+    h = C.c_void_p()
+    _check(lib().nat_bem_assemble(mesh.handle, float(k), int(bool(burton_miller)), C.byref(h),
+                                  _stream(stream)))
+    return BemOp(h, mesh, k)
+
+
+def nat_bem_solve(op: BemOp, v_n, layout: int = NAT_NEUMANN_PER_VERTEX, tol: float = 1e-10,
+                  max_iter: int = 500, p_out=None, stream=None, allow_noconv: bool = False):
+    import torch
+    M = int(v_n.shape[0])
+    ng = op.mesh.n_tris if layout == NAT_NEUMANN_PER_TRIANGLE else op.mesh.n_vertices
+    if p_out is None:
+        p_out = torch.empty((M, op.n), dtype=torch.complex128, device=v_n.device)
+    reps = (nat_solve_report * M)()
+    st = lib().nat_bem_solve(op.handle, _dptr(v_n, torch.complex128, (M, ng), "v_n"), M, layout,
+                             float(tol), int(max_iter), _dptr(p_out, torch.complex128, (M, op.n), "p_out"),
+                             C.cast(reps, _P), _stream(stream))
+    _check(st, allow=(NAT_E_NOCONV,) if allow_noconv else ())
+    return p_out, [r.as_dict() for r in reps]
+
+
+def nat_bem_op_matrices(op: BemOp, stream=None):
+    import torch
+    A = torch.empty((op.n, op.n), dtype=torch.complex128, device=f"cuda:{op.mesh.ctx.device}")
+    B = torch.empty_like(A)
+    _check(lib().nat_bem_op_matrices(op.handle, _dptr(A), _dptr(B), _stream(stream)))
+    return A, B

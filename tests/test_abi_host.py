@@ -1,0 +1,75 @@
+"""Host-side checks of libnat_bem.so that need no GPU: it loads, exports every
+entry point include/nat_bem.h declares, validates meshes, and builds the
+FP64 area table bit for bit like the oracle (the precondition for
+bit-exact sample triangle indices)."""
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle as O
+from paper_2506_06190_amd import nat
+
+HEADER = Path(__file__).resolve().parents[1] / "include" / "nat_bem.h"
+
+
+def declared_functions():
+    text = HEADER.read_text()
+    return re.findall(r"^[A-Za-z_][\w \*]*?\b(nat_\w+)\s*\(", text, re.M)
+
+
+def test_library_exports_every_declared_symbol():
+    L = nat.lib()
+    names = declared_functions()
+    assert len(names) >= 18
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # the binding wraps each of them under the same name
+    assert set(names) <= set(nat._SIGS)
+
+
+def test_status_strings_and_defaults():
+    assert nat.status_str(nat.NAT_OK) == "NAT_OK"
+    assert nat.status_str(nat.NAT_E_BUDGET) == "NAT_E_BUDGET"
+    o = nat.nat_mc_opts_default()
+    assert o.gmres_tol == 1e-6 and o.gmres_max_iter == 200     # Section 6.1 solver settings
+    assert o.eps_scale == 1.0 and o.precision == nat.NAT_PREC_FP32 and o.reserved == 0
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.icosphere(3, 1.0)[:2],
+    lambda: W.noisy_ellipsoid(3, subdiv=3)[:2],
+    lambda: W.cubesphere_ellipsoid(5, 3000)[:2],
+])
+def test_geometry_bitwise_equal_to_oracle(maker):
+    v, f = maker()
+    a1, n1, c1 = nat.nat_mesh_geometry(v, f)
+    a2, n2, c2 = O.geometry(v, f)
+    assert np.array_equal(a1, a2) and np.array_equal(n1, n2) and np.array_equal(c1, c2)
+
+
+def test_mesh_validation_rejects_bad_meshes():
+    v, f, _ = W.icosphere(1, 1.0)
+    assert nat.nat_mesh_validate(v, f)[0] == nat.NAT_OK
+    bad = {
+        "open": (v, f[1:]),
+        "one triangle flipped": (v, np.concatenate([f[:1, [0, 2, 1]], f[1:]])),
+        "inward": (v, f[:, [0, 2, 1]]),
+        "index out of range": (v, np.where(f == 3, len(v), f)),
+        "repeated vertex": (v, np.concatenate([f[:1, [0, 0, 1]], f[1:]])),
+    }
+    for name, (vv, ff) in bad.items():
+        st, msg = nat.nat_mesh_validate(vv, ff)
+        assert st == nat.NAT_E_INVALID, name
+        assert msg, name
+    vn = v.copy()
+    vn[5, 1] = np.nan
+    assert nat.nat_mesh_validate(vn, f)[0] == nat.NAT_E_INVALID
+    # a zero-area triangle: collapse one vertex onto another's position
+    vz = v.copy()
+    t0 = f[0]
+    vz[t0[2]] = vz[t0[1]]
+    st, msg = nat.nat_mesh_validate(vz, f)
+    assert st == nat.NAT_E_INVALID and "zero area" in msg

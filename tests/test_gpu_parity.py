@@ -1,0 +1,257 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on
+the same seeded inputs.
+
+Bars: sample triangle indices bit-exact and barycentrics within 4 ulp; the
+plain FP64 form within 1e-10 relative L2 per mode; the FP32 form within
+1e-3 relative L2 per mode (the per-mode error is printed); the dense
+Burton-Miller matrices within 1e-12 of the largest entry and its solutions
+within 1e-9."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2506_06190_amd import nat  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = nat.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _run_gpu(ctx, wl, prec, tol, layout=0, want_samples=False, max_iter=200):
+    mesh = nat.Mesh(ctx, wl.vertices, wl.tris)
+    g = torch.from_numpy(np.ascontiguousarray(wl.g)).to(DEV)
+    qt = torch.from_numpy(np.ascontiguousarray(wl.q_tri)).to(DEV)
+    qb = torch.from_numpy(np.ascontiguousarray(wl.q_b)).to(DEV)
+    opts = nat.nat_mc_opts_default()
+    opts.precision = prec
+    opts.gmres_tol = tol
+    opts.layout = layout
+    opts.gmres_max_iter = max_iter
+    ps = None
+    if want_samples:
+        ps = torch.empty((wl.n_modes, wl.n_samples), dtype=torch.complex128, device=DEV)
+    p, rep = nat.nat_mcbem_estimate(mesh, g, wl.k, qt, qb, wl.n_samples, wl.seed, opts, p_samples=ps)
+    torch.cuda.synchronize()
+    out = p.cpu().numpy(), rep, (ps.cpu().numpy() if ps is not None else None)
+    mesh.close()
+    return out
+
+
+def _small_ellipsoid(n_modes=11, Q=700, N=600, seed=77):
+    v, f, u = W.noisy_ellipsoid(seed, subdiv=3)
+    g = W.sh_neumann(u, n_modes, seed)
+    k = W.wavenumber(W.log_uniform_freqs(n_modes, seed))
+    qt, qb = W.random_face_queries(len(f), Q, seed)
+    return W.MCWorkload("small_ellipsoid", v, f, g, k, qt, qb, N, seed)
+
+
+def test_samples_bit_exact(ctx):
+    for (v, f), N, seed in [(W.icosphere(3, 1.0)[:2], 256, 20250606),
+                            (W.noisy_ellipsoid(3, subdiv=5)[:2], 4099, 12345),
+                            (W.cubesphere_ellipsoid(9, 40000)[:2], 2048, 2**63 + 17)]:
+        _say(f"samples T={len(f)} N={N} seed={seed}")
+        mesh = nat.Mesh(ctx, v, f)
+        tri = torch.empty(N, dtype=torch.int32, device=DEV)
+        bary = torch.empty((N, 2), dtype=torch.float64, device=DEV)
+        nat.nat_mcbem_samples(mesh, N, seed, tri, bary)
+        torch.cuda.synchronize()
+        t_o, b_o = O.samples(v, f, N, seed)
+        assert np.array_equal(tri.cpu().numpy(), t_o)
+        ulp = np.spacing(np.abs(b_o)) + 1e-300
+        assert (np.abs(bary.cpu().numpy() - b_o) <= 4 * ulp).all()
+        mesh.close()
+
+
+def test_plain_fp64_matches_oracle_pulsating_sphere(ctx):
+    wl = W.config_pulsating_sphere()
+    _say(f"fp64 {wl.name} N={wl.n_samples} Q={wl.n_queries}")
+    p, rep, ps = _run_gpu(ctx, wl, nat.NAT_PREC_FP64, 1e-12, want_samples=True)
+    r = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri, wl.q_b, wl.n_samples, wl.seed,
+                tol=1e-12, want_samples=True)
+    e = _rel(p[0], r["p"][0])
+    _say(f"  rel L2 vs oracle {e:.3e}, iters gpu {rep[0]['iters']} oracle {r['iters'][0]}")
+    assert e <= 1e-10
+    assert _rel(ps[0], r["p_samples"][0]) <= 1e-10
+    assert rep[0]["converged"] == 1 and rep[0]["eps"] > 0
+    assert rep[0]["area"] == pytest.approx(O.geometry(wl.vertices, wl.tris)[2][-1], rel=1e-15)
+
+
+def test_plain_fp64_ragged_multimode(ctx):
+    wl = _small_ellipsoid()
+    _say(f"fp64 ragged modes={wl.n_modes} N={wl.n_samples} Q={wl.n_queries}")
+    p, rep, ps = _run_gpu(ctx, wl, nat.NAT_PREC_FP64, 1e-12, want_samples=True)
+    r = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri, wl.q_b, wl.n_samples, wl.seed,
+                tol=1e-12, want_samples=True)
+    for m in range(wl.n_modes):
+        e = _rel(p[m], r["p"][m])
+        assert e <= 1e-10, (m, e)
+        assert _rel(ps[m], r["p_samples"][m]) <= 1e-10
+
+
+def test_fp32_ragged_multimode(ctx):
+    wl = _small_ellipsoid()
+    _say(f"fp32 ragged modes={wl.n_modes} N={wl.n_samples} Q={wl.n_queries}")
+    p, rep, ps = _run_gpu(ctx, wl, nat.NAT_PREC_FP32, 1e-6, want_samples=True)
+    r = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri, wl.q_b, wl.n_samples, wl.seed,
+                tol=1e-12, want_samples=True)
+    errs = [_rel(p[m], r["p"][m]) for m in range(wl.n_modes)]
+    _say("  fp32 rel L2 per mode: " + " ".join(f"{e:.2e}" for e in errs))
+    assert max(errs) <= 1e-3
+    assert all(rr["converged"] for rr in rep)
+
+
+def test_fp32_full_precision_workload(ctx):
+    """Noise-displaced ellipsoid, 20480 triangles, 32 modes, 4096 queries x 1024
+    samples, the launch configuration the benchmark times."""
+    wl = W.config_precision()
+    _say(f"fp32 {wl.name}")
+    p, rep, _ = _run_gpu(ctx, wl, nat.NAT_PREC_FP32, 1e-6)
+    r = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri, wl.q_b, wl.n_samples, wl.seed, tol=1e-12)
+    errs = np.array([_rel(p[m], r["p"][m]) for m in range(wl.n_modes)])
+    _say("  fp32 rel L2 per mode: " + " ".join(f"{e:.2e}" for e in errs))
+    _say(f"  iterations: {[rr['iters'] for rr in rep]}")
+    assert errs.max() <= 1e-3
+
+
+def test_per_triangle_layout_and_no_queries(ctx):
+    v, f, u = W.icosphere(3, 1.0)
+    rng = np.random.default_rng(5)
+    gt = (rng.standard_normal((2, len(f))) + 1j * rng.standard_normal((2, len(f))))
+    qt, qb = W.random_face_queries(len(f), 130, 9)
+    wl = W.MCWorkload("per_tri", v, f, gt, np.array([2.0, 7.5]), qt, qb, 300, 3)
+    p, rep, ps = _run_gpu(ctx, wl, nat.NAT_PREC_FP64, 1e-12, layout=1, want_samples=True)
+    r = O.mcbem(v, f, gt, wl.k, qt, qb, 300, 3, tol=1e-12, layout=1, want_samples=True)
+    for m in range(2):
+        assert _rel(p[m], r["p"][m]) <= 1e-10
+    # Q = 0: only the sample values are produced
+    wl0 = W.MCWorkload("noq", v, f, gt, wl.k, qt[:0], qb[:0], 300, 3)
+    p0, rep0, ps0 = _run_gpu(ctx, wl0, nat.NAT_PREC_FP64, 1e-12, layout=1, want_samples=True)
+    assert p0.shape == (2, 0)
+    assert _rel(ps0, r["p_samples"]) <= 1e-10
+
+
+def test_minimum_sample_count(ctx):
+    wl = W.config_pulsating_sphere(n_samples=2)
+    p, rep, ps = _run_gpu(ctx, wl, nat.NAT_PREC_FP32, 1e-6, want_samples=True)
+    r = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri, wl.q_b, 2, wl.seed, tol=1e-12,
+                want_samples=True)
+    assert _rel(p[0], r["p"][0]) <= 1e-3
+
+
+def test_deterministic_and_rigid_motion(ctx):
+    wl = _small_ellipsoid(n_modes=3, Q=257, N=513, seed=8)
+    a, _, _ = _run_gpu(ctx, wl, nat.NAT_PREC_FP32, 1e-6)
+    b, _, _ = _run_gpu(ctx, wl, nat.NAT_PREC_FP32, 1e-6)
+    assert np.array_equal(a, b)
+    rot = W.random_rotation(np.random.default_rng(1))
+    moved = W.MCWorkload("moved", wl.vertices @ rot.T + np.array([0.4, -0.3, 0.2]), wl.tris, wl.g,
+                         wl.k, wl.q_tri, wl.q_b, wl.n_samples, wl.seed)
+    c, _, _ = _run_gpu(ctx, moved, nat.NAT_PREC_FP32, 1e-6)
+    for m in range(3):
+        assert _rel(c[m], a[m]) <= 1e-4
+
+
+def test_error_paths(ctx):
+    v, f, u = W.icosphere(2, 1.0)
+    mesh = nat.Mesh(ctx, v, f)
+    g = torch.ones((1, len(v)), dtype=torch.complex128, device=DEV)
+    qt = torch.zeros(4, dtype=torch.int32, device=DEV)
+    qb = torch.zeros((4, 2), dtype=torch.float64, device=DEV)
+    with pytest.raises(nat.NatError) as ei:            # k <= 0
+        nat.nat_mcbem_estimate(mesh, g, [0.0], qt, qb, 64, 1)
+    assert ei.value.status == nat.NAT_E_INVALID
+    bad = qt.clone()
+    bad[2] = len(f)
+    with pytest.raises(nat.NatError) as ei:            # triangle out of range
+        nat.nat_mcbem_estimate(mesh, g, [1.0], bad, qb, 64, 1)
+    assert ei.value.status == nat.NAT_E_INVALID
+    gn = g.clone()
+    gn[0, 3] = float("nan")
+    with pytest.raises(nat.NatError) as ei:            # NaN Neumann data
+        nat.nat_mcbem_estimate(mesh, gn, [1.0], qt, qb, 64, 1)
+    assert ei.value.status == nat.NAT_E_INVALID
+    opts = nat.nat_mc_opts_default()
+    opts.gmres_max_iter = 1
+    opts.precision = nat.NAT_PREC_FP64
+    p, rep = nat.nat_mcbem_estimate(mesh, g, [1.0], qt, qb, 64, 1, opts, allow_noconv=True)
+    assert rep[0]["iters"] == 1 and rep[0]["converged"] == 0 and torch.isfinite(p).all()
+    with pytest.raises(nat.NatError) as ei:
+        nat.nat_mcbem_estimate(mesh, g, [1.0], qt, qb, 64, 1, opts)
+    assert ei.value.status == nat.NAT_E_NOCONV
+    mesh.close()
+    small = nat.Context(0, hbm_budget_bytes=1 << 16)
+    m2 = nat.Mesh(small, v, f)
+    with pytest.raises(nat.NatError) as ei:
+        nat.nat_mcbem_estimate(m2, g, [1.0], qt, qb, 4096, 1)
+    assert ei.value.status == nat.NAT_E_BUDGET
+    m2.close()
+    small.close()
+
+
+# ------------------------------------------------------------- dense BEM
+def _dense_gpu(ctx, v, f, k, gv, bm=True, tol=1e-12):
+    mesh = nat.Mesh(ctx, v, f)
+    op = nat.nat_bem_assemble(mesh, k, bm)
+    A, B = nat.nat_bem_op_matrices(op)
+    g = torch.from_numpy(np.ascontiguousarray(np.atleast_2d(gv))).to(DEV)
+    p, rep = nat.nat_bem_solve(op, g, tol=tol)
+    torch.cuda.synchronize()
+    out = A.cpu().numpy(), B.cpu().numpy(), p.cpu().numpy(), rep
+    op.close()
+    mesh.close()
+    return out
+
+
+@pytest.mark.parametrize("bm", [True, False])
+def test_dense_matrices_match_oracle(ctx, bm):
+    v, f, u = W.noisy_ellipsoid(3, subdiv=2)
+    k = 40.0
+    _say(f"dense assemble n={len(f)} bm={bm}")
+    A, B, p, rep = _dense_gpu(ctx, v, f, k, u[:, 2].astype(complex), bm)
+    Ao, Bo = O.bem_assemble(v, f, k, bm)
+    assert np.abs(A - Ao).max() <= 1e-12 * np.abs(Ao).max()
+    assert np.abs(B - Bo).max() <= 1e-12 * np.abs(Bo).max()
+    po, _, _ = O.bem_solve(Ao, Bo, O.panel_data(f, u[:, 2].astype(complex)), tol=1e-12)
+    assert _rel(p[0], po) <= 1e-9
+
+
+def test_dense_oscillating_sphere_full_size(ctx):
+    """Icosphere of radius 0.1 m, 5120 panels, v_n = cos(theta), k a in {1, 5, 10}."""
+    wl = W.config_oscillating_sphere()
+    a = wl.extra["radius"]
+    u = wl.extra["u"]
+    for k in wl.k:
+        _say(f"dense n={len(wl.tris)} ka={k * a}")
+        A, B, p, rep = _dense_gpu(ctx, wl.vertices, wl.tris, k, u[:, 2].astype(complex))
+        Ao, Bo = O.bem_assemble(wl.vertices, wl.tris, k, True)
+        assert np.abs(A - Ao).max() <= 1e-12 * np.abs(Ao).max()
+        po, it, res = O.bem_solve(Ao, Bo, O.panel_data(wl.tris, u[:, 2].astype(complex)), tol=1e-12)
+        e = _rel(p[0], po)
+        _say(f"  rel L2 vs oracle {e:.2e}, iters {rep[0]['iters']}")
+        assert e <= 1e-9
+        del A, B, Ao, Bo
