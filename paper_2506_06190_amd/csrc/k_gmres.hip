@@ -12,7 +12,6 @@ namespace {
 
 constexpr int kBlock = 1024;
 constexpr int kWaves = kBlock / 64;
-constexpr int kChunk = 8;  // basis vectors per reduction round
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
@@ -86,48 +85,80 @@ k_gmres_init(GmresState g, const double2* __restrict__ b, int64_t ld_b)
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_gmres_orth(GmresState g, int32_t j)
+__device__ __forceinline__ void fold2(float& hi, float& lo, float t)
 {
-    extern __shared__ double2 s_h[];  // [j+1] current pass, then [j+1] total
-    __shared__ double red[kWaves * 2 * kChunk];
-    __shared__ double tot[2 * kChunk];
+    const float s = hi + t;
+    const float bp = s - hi;
+    lo += (hi - (s - bp)) + (t - bp);
+    hi = s;
+}
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// One Arnoldi step for system blockIdx.x.  Dot products are spread over the
+// waves (wave q takes basis vectors q, q + 16, ...) and reduced inside the
+// wave, so a CGS pass costs two barriers.
+__global__ void __launch_bounds__(kBlock)
+k_gmres_orth(GmresState g, int32_t j, const float4* __restrict__ partial, int32_t n_split)
+{
+    extern __shared__ double2 s_h[];  // [j+1] this pass, then [j+1] total
+    __shared__ double red[kWaves];
+    __shared__ double s_norm;
     const int m = blockIdx.x;
     if (!g.active[m])
         return;
     const int n = g.n;
     const int mm1 = g.mmax + 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double2* Vm = g.V + (size_t)m * mm1 * n;
     double2* w = g.w + (size_t)m * n;
     double2* h_pass = s_h;
     double2* h_tot = s_h + (j + 1);
-    for (int i = threadIdx.x; i <= j; i += kBlock)
+
+    if (partial) {
+        // matvec epilogue: w = v_j / 2 - (sum of the FP32 split partials)
+        const double2* vj = Vm + (size_t)j * n;
+        for (int t = tid; t < n; t += kBlock) {
+            float hr = 0.0f, hi = 0.0f, lr = 0.0f, li = 0.0f;
+            for (int32_t sp = 0; sp < n_split; ++sp) {
+                const float4 v = partial[((size_t)sp * g.n_modes + m) * n + t];
+                fold2(hr, lr, v.x);
+                fold2(hi, li, v.y);
+                lr += v.z;
+                li += v.w;
+            }
+            const double ar = static_cast<double>(hr) + static_cast<double>(lr);
+            const double ai = static_cast<double>(hi) + static_cast<double>(li);
+            const double2 x = vj[t];
+            w[t] = make_double2(0.5 * x.x - ar, 0.5 * x.y - ai);
+        }
+    }
+    for (int i = tid; i <= j; i += kBlock)
         h_tot[i] = make_double2(0.0, 0.0);
     __syncthreads();
 
     for (int pass = 0; pass < 2; ++pass) {
-        for (int i0 = 0; i0 <= j; i0 += kChunk) {
-            const int cnt = min(kChunk, j + 1 - i0);
-            double acc[2 * kChunk];
-#pragma unroll
-            for (int c = 0; c < 2 * kChunk; ++c)
-                acc[c] = 0.0;
-            for (int t = threadIdx.x; t < n; t += kBlock) {
-                const double2 wt = w[t];
-#pragma unroll
-                for (int c = 0; c < kChunk; ++c) {
-                    if (c < cnt) {
-                        const double2 d = cmulc(Vm[(size_t)(i0 + c) * n + t], wt);
-                        acc[2 * c] += d.x;
-                        acc[2 * c + 1] += d.y;
-                    }
-                }
+        for (int i = wave; i <= j; i += kWaves) {
+            const double2* vi = Vm + (size_t)i * n;
+            double ar = 0.0, ai = 0.0;
+            for (int t = lane; t < n; t += 64) {
+                const double2 d = cmulc(vi[t], w[t]);
+                ar += d.x;
+                ai += d.y;
             }
-            block_sum<2 * kChunk>(acc, red, tot);
-            if (threadIdx.x < cnt)
-                h_pass[i0 + threadIdx.x] = make_double2(tot[2 * threadIdx.x], tot[2 * threadIdx.x + 1]);
-            __syncthreads();
+            ar = wave_sum(ar);
+            ai = wave_sum(ai);
+            if (lane == 0)
+                h_pass[i] = make_double2(ar, ai);
         }
-        for (int t = threadIdx.x; t < n; t += kBlock) {
+        __syncthreads();
+        for (int t = tid; t < n; t += kBlock) {
             double2 wt = w[t];
             for (int i = 0; i <= j; ++i) {
                 const double2 d = cmul(h_pass[i], Vm[(size_t)i * n + t]);
@@ -136,34 +167,42 @@ __global__ void __launch_bounds__(kBlock) k_gmres_orth(GmresState g, int32_t j)
             }
             w[t] = wt;
         }
-        for (int i = threadIdx.x; i <= j; i += kBlock) {
+        for (int i = tid; i <= j; i += kBlock) {
             h_tot[i].x += h_pass[i].x;
             h_tot[i].y += h_pass[i].y;
         }
         __syncthreads();
     }
 
-    double nacc[1] = {0.0};
-    for (int t = threadIdx.x; t < n; t += kBlock) {
+    double nacc = 0.0;
+    for (int t = tid; t < n; t += kBlock) {
         const double2 wt = w[t];
-        nacc[0] += wt.x * wt.x + wt.y * wt.y;
+        nacc += wt.x * wt.x + wt.y * wt.y;
     }
-    block_sum<1>(nacc, red, tot);
-    const double hn = sqrt(tot[0]);
+    nacc = wave_sum(nacc);
+    if (lane == 0)
+        red[wave] = nacc;
+    __syncthreads();
+    if (tid == 0) {
+        double sacc = 0.0;
+        for (int q = 0; q < kWaves; ++q)
+            sacc += red[q];
+        s_norm = sqrt(sacc);
+    }
+    __syncthreads();
+    const double hn = s_norm;
     const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
     double2* vn = g.V + ((size_t)m * mm1 + j + 1) * n;
-    if (j + 1 <= g.mmax) {
-        for (int t = threadIdx.x; t < n; t += kBlock) {
-            const double2 wt = w[t];
-            const double2 u = make_double2(wt.x * inv, wt.y * inv);
-            vn[t] = u;
-            if (g.v32)
-                g.v32[(size_t)m * n + t] = make_float2(static_cast<float>(g.v32_scale * u.x),
-                                                      static_cast<float>(g.v32_scale * u.y));
-        }
+    for (int t = tid; t < n; t += kBlock) {
+        const double2 wt = w[t];
+        const double2 u = make_double2(wt.x * inv, wt.y * inv);
+        vn[t] = u;
+        if (g.v32)
+            g.v32[(size_t)m * n + t] = make_float2(static_cast<float>(g.v32_scale * u.x),
+                                                  static_cast<float>(g.v32_scale * u.y));
     }
 
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         double2* H = g.H + ((size_t)m * g.mmax + j) * mm1;  // column j
         double* cs = g.cs + (size_t)m * g.mmax;
         double2* sn = g.sn + (size_t)m * g.mmax;
@@ -182,21 +221,21 @@ __global__ void __launch_bounds__(kBlock) k_gmres_orth(GmresState g, int32_t j)
         const double amag = hypot(a.x, a.y);
         const double den = hypot(amag, hn);
         double c;
-        double2 s;
+        double2 sg;
         if (amag == 0.0) {
             c = 0.0;
-            s = make_double2(1.0, 0.0);
+            sg = make_double2(1.0, 0.0);
         } else {
             c = amag / den;
-            s = make_double2(a.x / amag * hn / den, a.y / amag * hn / den);
+            sg = make_double2(a.x / amag * hn / den, a.y / amag * hn / den);
         }
         cs[j] = c;
-        sn[j] = s;
-        H[j] = make_double2(c * a.x + s.x * hn, c * a.y + s.y * hn);
+        sn[j] = sg;
+        H[j] = make_double2(c * a.x + sg.x * hn, c * a.y + sg.y * hn);
         H[j + 1] = make_double2(0.0, 0.0);
         const double2 gj = gv[j];
-        const double2 sg = cmulc(s, gj);
-        gv[j + 1] = make_double2(-sg.x, -sg.y);
+        const double2 cg = cmulc(sg, gj);
+        gv[j + 1] = make_double2(-cg.x, -cg.y);
         gv[j] = make_double2(c * gj.x, c * gj.y);
         const double res = hypot(gv[j + 1].x, gv[j + 1].y) / g.beta[m];
         g.resid[m] = res;
@@ -277,10 +316,12 @@ hipError_t launch_gmres_init(const GmresState& g, const double2* b, int64_t ld_b
     return hipGetLastError();
 }
 
-hipError_t launch_gmres_orth(const GmresState& g, int32_t j, hipStream_t s)
+hipError_t launch_gmres_orth(const GmresState& g, int32_t j, const void* partial, int32_t n_split,
+                             hipStream_t s)
 {
     const size_t lds = sizeof(double2) * 2 * (size_t)(j + 1);
-    hipLaunchKernelGGL(k_gmres_orth, dim3(g.n_modes), dim3(kBlock), lds, s, g, j);
+    hipLaunchKernelGGL(k_gmres_orth, dim3(g.n_modes), dim3(kBlock), lds, s, g, j,
+                       static_cast<const float4*>(partial), n_split);
     return hipGetLastError();
 }
 

@@ -39,6 +39,8 @@ struct Sum32Params {
     const float* kappa;    // [n_modes]
     const float* kk;       // [n_modes]
     const int32_t* active; // [n_modes] or null
+    const int32_t* list;   // modes to process (slot -> mode), or null for 0..n_list-1
+    int32_t n_list;
     float eps2;
     int32_t per_split;     // sources per split, multiple of kTS
     float4* partial;       // [split][mode][NT]: (hi.re, hi.im, lo.re, lo.im)
@@ -64,14 +66,23 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Params p)
     const int32_t tid = threadIdx.x;
     const int32_t i = blockIdx.x * kThreads + tid;
     const int32_t split = blockIdx.y;
-    const int32_t m0 = blockIdx.z * MB;
+    const int32_t s0 = blockIdx.z * MB;  // first slot of this mode group
     const int32_t NT = p.NT, NS = p.NS;
 
-    if (p.active) {
+    // modes of the group; slots past the list repeat the last mode and are not stored
+    int32_t mode[MB];
+    bool live[MB];
+#pragma unroll
+    for (int mm = 0; mm < MB; ++mm) {
+        const int32_t slot = s0 + mm < p.n_list ? s0 + mm : p.n_list - 1;
+        mode[mm] = p.list ? p.list[slot] : slot;
+        live[mm] = (s0 + mm < p.n_list) && (!p.active || p.active[mode[mm]]);
+    }
+    {
         bool any = false;
 #pragma unroll
         for (int mm = 0; mm < MB; ++mm)
-            any |= (m0 + mm < p.n_modes) && p.active[m0 + mm];
+            any |= live[mm];
         if (!any)
             return;
     }
@@ -82,9 +93,8 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Params p)
     float kap[MB], kk[MB];
 #pragma unroll
     for (int mm = 0; mm < MB; ++mm) {
-        const int32_t m = m0 + mm < p.n_modes ? m0 + mm : p.n_modes - 1;
-        kap[mm] = p.kappa[m];
-        kk[mm] = p.kk[m];
+        kap[mm] = p.kappa[mode[mm]];
+        kk[mm] = p.kk[mode[mm]];
     }
 
     float hr[MB], hi_[MB], lr[MB], li[MB];
@@ -112,8 +122,8 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Params p)
             for (int e = tid; e < MB * kTS; e += kThreads) {
                 const int mm = e / kTS, c = e % kTS;
                 float2 v = make_float2(0.0f, 0.0f);
-                if (c < cnt && m0 + mm < p.n_modes)
-                    v = p.a32[(size_t)(m0 + mm) * p.ld_s + j0 + c];
+                if (c < cnt)
+                    v = p.a32[(size_t)mode[mm] * p.ld_s + j0 + c];
                 s_a[mm][c] = v;
             }
         }
@@ -121,8 +131,8 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Params p)
             for (int e = tid; e < MB * kTS; e += kThreads) {
                 const int mm = e / kTS, c = e % kTS;
                 float2 v = make_float2(0.0f, 0.0f);
-                if (c < cnt && m0 + mm < p.n_modes)
-                    v = p.b32[(size_t)(m0 + mm) * p.ld_s + j0 + c];
+                if (c < cnt)
+                    v = p.b32[(size_t)mode[mm] * p.ld_s + j0 + c];
                 s_b[mm][c] = v;
             }
         }
@@ -177,9 +187,8 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Params p)
     if (i < NT) {
 #pragma unroll
         for (int mm = 0; mm < MB; ++mm) {
-            const int32_t m = m0 + mm;
-            if (m < p.n_modes)
-                p.partial[((size_t)split * p.n_modes + m) * NT + i] =
+            if (s0 + mm < p.n_list)
+                p.partial[((size_t)split * p.n_modes + mode[mm]) * NT + i] =
                     make_float4(hr[mm], hi_[mm], lr[mm], li[mm]);
         }
     }
@@ -236,19 +245,19 @@ k_weight32(const double2* __restrict__ src, int64_t ld_src, int32_t n, double sc
         make_float2(static_cast<float>(scale * v.x), static_cast<float>(scale * v.y));
 }
 
-constexpr int kModesPerGroup = 8;
-
 struct SplitPlan {
-    int32_t n_split, per_split, groups, tiles;
+    int32_t n_split, per_split, groups, tiles, mb;
 };
 
-SplitPlan plan(const SumArgs& a)
+// Mode-group width from the number of modes processed; source splits so the
+// grid holds about four workgroups per CU of a 256-CU part.
+SplitPlan plan(int32_t NT, int32_t NS, int32_t n_list)
 {
     SplitPlan s;
-    s.tiles = (a.NT + kThreads - 1) / kThreads;
-    s.groups = (a.n_modes + kModesPerGroup - 1) / kModesPerGroup;
-    const int32_t n_tiles_src = (a.NS + kTS - 1) / kTS;
-    // aim at ~4 workgroups per CU on a 256-CU part
+    s.mb = n_list <= 1 ? 1 : n_list <= 2 ? 2 : n_list <= 4 ? 4 : 8;
+    s.tiles = (NT + kThreads - 1) / kThreads;
+    s.groups = (n_list + s.mb - 1) / s.mb;
+    const int32_t n_tiles_src = (NS + kTS - 1) / kTS;
     const int64_t base = static_cast<int64_t>(s.tiles) * s.groups;
     int64_t want = (1024 + base - 1) / base;
     if (want < 1)
@@ -257,14 +266,22 @@ SplitPlan plan(const SumArgs& a)
         want = n_tiles_src;
     const int32_t tiles_per_split = static_cast<int32_t>((n_tiles_src + want - 1) / want);
     s.per_split = tiles_per_split * kTS;
-    s.n_split = (a.NS + s.per_split - 1) / s.per_split;
+    s.n_split = (NS + s.per_split - 1) / s.per_split;
     if (s.n_split < 1)
         s.n_split = 1;
     return s;
 }
 
+template <int OP, int MB>
+void launch_mb(const Sum32Params& p, const SplitPlan& sp, hipStream_t s)
+{
+    dim3 grid(sp.tiles, sp.n_split, sp.groups);
+    hipLaunchKernelGGL((k_sum32<OP, MB>), grid, dim3(kThreads), 0, s, p);
+}
+
 template <int OP>
-hipError_t launch_op(const SumArgs& a, const SplitPlan& sp, float4* partial, hipStream_t s)
+hipError_t launch_op(const SumArgs& a, const SplitPlan& sp, float4* partial, const int32_t* list,
+                     int32_t n_list, bool reduce, hipStream_t s)
 {
     Sum32Params p;
     p.NT = a.NT;
@@ -279,13 +296,27 @@ hipError_t launch_op(const SumArgs& a, const SplitPlan& sp, float4* partial, hip
     p.kappa = a.kappa32;
     p.kk = a.k32;
     p.active = a.active;
+    p.list = list;
+    p.n_list = n_list;
     p.eps2 = static_cast<float>(a.eps * a.eps);
     p.per_split = sp.per_split;
     p.partial = partial;
-    dim3 grid(sp.tiles, sp.n_split, sp.groups);
-    hipLaunchKernelGGL((k_sum32<OP, kModesPerGroup>), grid, dim3(kThreads), 0, s, p);
+    switch (sp.mb) {
+    case 1:
+        launch_mb<OP, 1>(p, sp, s);
+        break;
+    case 2:
+        launch_mb<OP, 2>(p, sp, s);
+        break;
+    case 4:
+        launch_mb<OP, 4>(p, sp, s);
+        break;
+    default:
+        launch_mb<OP, 8>(p, sp, s);
+        break;
+    }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
+    if (e != hipSuccess || !reduce)
         return e;
     dim3 g2(static_cast<unsigned>((a.NT + 255) / 256), static_cast<unsigned>(a.n_modes));
     hipLaunchKernelGGL(k_reduce32<OP>, g2, dim3(256), 0, s, partial, sp.n_split, a);
@@ -296,23 +327,29 @@ hipError_t launch_op(const SumArgs& a, const SplitPlan& sp, float4* partial, hip
 
 size_t sum32_partial_bytes(const SumArgs& a)
 {
-    const SplitPlan sp = plan(a);
-    return sizeof(float4) * (size_t)sp.n_split * (size_t)a.n_modes * (size_t)a.NT;
+    // the largest split count any plan can choose: one split per source tile
+    const size_t n_split = (size_t)((a.NS + kTS - 1) / kTS);
+    return sizeof(float4) * n_split * (size_t)a.n_modes * (size_t)a.NT;
 }
 
-hipError_t launch_sum32(const SumArgs& a, void* partial, hipStream_t s)
+hipError_t launch_sum32(const SumArgs& a, void* partial, hipStream_t s, const int32_t* list,
+                        int32_t n_list, bool reduce, int32_t* n_split_out)
 {
-    if (a.NT <= 0 || a.n_modes <= 0)
+    if (n_list < 0)
+        n_list = a.n_modes;
+    if (a.NT <= 0 || n_list <= 0)
         return hipSuccess;
-    const SplitPlan sp = plan(a);
+    const SplitPlan sp = plan(a.NT, a.NS, n_list);
+    if (n_split_out)
+        *n_split_out = sp.n_split;
     float4* part = static_cast<float4*>(partial);
     switch (a.op) {
     case OP_RHS:
-        return launch_op<OP_RHS>(a, sp, part, s);
+        return launch_op<OP_RHS>(a, sp, part, list, n_list, reduce, s);
     case OP_MATVEC:
-        return launch_op<OP_MATVEC>(a, sp, part, s);
+        return launch_op<OP_MATVEC>(a, sp, part, list, n_list, reduce, s);
     default:
-        return launch_op<OP_EVAL>(a, sp, part, s);
+        return launch_op<OP_EVAL>(a, sp, part, list, n_list, reduce, s);
     }
 }
 

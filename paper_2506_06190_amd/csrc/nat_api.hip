@@ -17,6 +17,9 @@ namespace {
 thread_local std::string g_last_error;
 constexpr double kInv4Pi = 0.07957747154594767;
 constexpr double kTwoPi = 6.283185307179586;
+// GMRES iterations between host reads of the convergence flags; systems
+// that converge in between stop updating on the device.
+constexpr int32_t kCheckEvery = 4;
 }  // namespace
 
 namespace nat {
@@ -687,7 +690,7 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
          sizeof(double) * 3 * q, sizeof(float) * 3 * q, sizeof(double2) * M * n,
          sizeof(double2) * M * q, sizeof(double2) * M * n, sizeof(double2) * M * n,
          sizeof(float2) * M * n, sizeof(double) * M, sizeof(float) * M, sizeof(float) * M, part,
-         gmres_state_bytes(N, M, mmax)});
+         gmres_state_bytes(N, M, mmax), sizeof(int32_t) * M});
     void* ws = nullptr;
     st = workspace(ctx, bytes, &ws);
     if (st != NAT_OK)
@@ -713,6 +716,7 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
     gs.n_modes = M;
     gs.mmax = mmax;
     gmres_carve(gs, cv);
+    int32_t* dlist = cv.take<int32_t>(M);
 
     // validation of the device inputs
     int32_t flags[2] = {0, 0};
@@ -724,24 +728,26 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
     if (flags[1])
         return fail(NAT_E_INVALID, "nat_mcbem_estimate: non-finite Neumann data");
 
-    // per-mode constants
+    // per-mode constants.  Pinned staging, one region per use so no host
+    // write lands on bytes an enqueued copy has still to read:
+    // [k f64 | k f32 | k/2pi f32 | active flags | active list]
     void* pin = nullptr;
-    st = pinned(ctx, sizeof(double) * M * 2 + sizeof(float) * M * 2 + 64, &pin);
+    st = pinned(ctx, sizeof(double) * M + sizeof(float) * M * 2 + sizeof(int32_t) * M * 2 + 64, &pin);
     if (st != NAT_OK)
         return st;
-    {
-        double* hk = static_cast<double*>(pin);
-        float* hk32 = reinterpret_cast<float*>(hk + M);
-        float* hkap = hk32 + M;
-        for (int32_t m = 0; m < M; ++m) {
-            hk[m] = k[m];
-            hk32[m] = static_cast<float>(k[m]);
-            hkap[m] = static_cast<float>(k[m] / kTwoPi);
-        }
-        NAT_HIP(hipMemcpyAsync(dk, hk, sizeof(double) * M, hipMemcpyHostToDevice, s));
-        NAT_HIP(hipMemcpyAsync(dk32, hk32, sizeof(float) * M, hipMemcpyHostToDevice, s));
-        NAT_HIP(hipMemcpyAsync(dkap, hkap, sizeof(float) * M, hipMemcpyHostToDevice, s));
+    double* hk = static_cast<double*>(pin);
+    float* hk32 = reinterpret_cast<float*>(hk + M);
+    float* hkap = hk32 + M;
+    int32_t* hact = reinterpret_cast<int32_t*>(hkap + M);
+    int32_t* hlist = hact + M;
+    for (int32_t m = 0; m < M; ++m) {
+        hk[m] = k[m];
+        hk32[m] = static_cast<float>(k[m]);
+        hkap[m] = static_cast<float>(k[m] / kTwoPi);
     }
+    NAT_HIP(hipMemcpyAsync(dk, hk, sizeof(double) * M, hipMemcpyHostToDevice, s));
+    NAT_HIP(hipMemcpyAsync(dk32, hk32, sizeof(float) * M, hipMemcpyHostToDevice, s));
+    NAT_HIP(hipMemcpyAsync(dkap, hkap, sizeof(float) * M, hipMemcpyHostToDevice, s));
 
     const double area = mesh->area_total;
     const double w = area / static_cast<double>(N);
@@ -801,8 +807,11 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
     if (!fp32)
         gs.v32 = nullptr;
     NAT_HIP(launch_gmres_init(gs, b, N, s));
-    int32_t* hact = static_cast<int32_t*>(pin);
+    // active-mode list for the FP32 matvec, refreshed at each convergence check
     int32_t n_active = M;
+    for (int32_t m = 0; m < M; ++m)
+        hlist[m] = m;
+    NAT_HIP(hipMemcpyAsync(dlist, hlist, sizeof(int32_t) * M, hipMemcpyHostToDevice, s));
     for (int32_t j = 0; j < mmax; ++j) {
         SumArgs a = base;
         a.op = OP_MATVEC;
@@ -815,24 +824,29 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
         a.active = gs.active;
         a.out = gs.w;
         a.ld_out = N;
+        int32_t n_split = 0;
         if (fp32) {
             ProfScope ps_(ctx, PK_SUM32_MATVEC, 37.0 * n * n * n_active, s);
-            NAT_HIP(launch_sum32(a, partial, s));
+            NAT_HIP(launch_sum32(a, partial, s, dlist, n_active, false, &n_split));
         } else {
             ProfScope ps_(ctx, PK_SUM64, 37.0 * n * n * n_active, s);
             NAT_HIP(launch_sum64(a, s));
         }
         {
             ProfScope ps_(ctx, PK_GMRES_ORTH, 0.0, s);
-            NAT_HIP(launch_gmres_orth(gs, j, s));
+            NAT_HIP(launch_gmres_orth(gs, j, fp32 ? partial : nullptr, n_split, s));
         }
-        NAT_HIP(hipMemcpyAsync(hact, gs.active, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
-        NAT_HIP(hipStreamSynchronize(s));
-        n_active = 0;
-        for (int32_t m = 0; m < M; ++m)
-            n_active += hact[m] != 0;
-        if (!n_active)
-            break;
+        if ((j + 1) % kCheckEvery == 0 || j + 1 == mmax) {
+            NAT_HIP(hipMemcpyAsync(hact, gs.active, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+            NAT_HIP(hipStreamSynchronize(s));
+            n_active = 0;
+            for (int32_t m = 0; m < M; ++m)
+                if (hact[m])
+                    hlist[n_active++] = m;
+            if (!n_active)
+                break;
+            NAT_HIP(hipMemcpyAsync(dlist, hlist, sizeof(int32_t) * n_active, hipMemcpyHostToDevice, s));
+        }
     }
     double2* x = p_samples ? reinterpret_cast<double2*>(p_samples) : xin;
     NAT_HIP(launch_gmres_solution(gs, x, N, s));
@@ -868,13 +882,9 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
 
     // reports
     {
+        // the staging block above is large enough: no reallocation here
         int32_t* hit = static_cast<int32_t*>(pin);
         double* hres = reinterpret_cast<double*>(static_cast<char*>(pin) + 8 * ((M * 4 + 7) / 8));
-        st = pinned(ctx, 8 * ((M * 4 + 7) / 8) + sizeof(double) * M + 64, &pin);
-        if (st != NAT_OK)
-            return st;
-        hit = static_cast<int32_t*>(pin);
-        hres = reinterpret_cast<double*>(static_cast<char*>(pin) + 8 * ((M * 4 + 7) / 8));
         NAT_HIP(hipMemcpyAsync(hit, gs.iters, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
         NAT_HIP(hipMemcpyAsync(hres, gs.resid, sizeof(double) * M, hipMemcpyDeviceToHost, s));
         NAT_HIP(hipStreamSynchronize(s));
@@ -1041,14 +1051,19 @@ nat_status nat_bem_solve(nat_bem_op* op, const double* v_n, int32_t n_rhs, int32
             NAT_HIP(launch_zgemv(op->d_A, n, gs.V + (size_t)j * n, (int64_t)(max_iter + 1) * n, M,
                                  gs.w, n, gs.active, s));
         }
-        NAT_HIP(launch_gmres_orth(gs, j, s));
-        NAT_HIP(hipMemcpyAsync(hact, gs.active, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
-        NAT_HIP(hipStreamSynchronize(s));
-        bool any = false;
-        for (int32_t m = 0; m < M; ++m)
-            any |= hact[m] != 0;
-        if (!any)
-            break;
+        {
+            ProfScope ps_(ctx, PK_GMRES_ORTH, 0.0, s);
+            NAT_HIP(launch_gmres_orth(gs, j, nullptr, 0, s));
+        }
+        if ((j + 1) % kCheckEvery == 0 || j + 1 == max_iter) {
+            NAT_HIP(hipMemcpyAsync(hact, gs.active, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+            NAT_HIP(hipStreamSynchronize(s));
+            bool any = false;
+            for (int32_t m = 0; m < M; ++m)
+                any |= hact[m] != 0;
+            if (!any)
+                break;
+        }
     }
     NAT_HIP(launch_gmres_solution(gs, reinterpret_cast<double2*>(p_out), n, s));
     int32_t* hit = static_cast<int32_t*>(pin);

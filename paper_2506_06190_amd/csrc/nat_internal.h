@@ -178,9 +178,15 @@ struct SumArgs {
     int64_t ld_out;
 };
 hipError_t launch_sum64(const SumArgs& a, hipStream_t s);
-// FP32 tiled sum; partial is scratch of sum32_partial_bytes() bytes
+// FP32 tiled sum; partial is scratch of sum32_partial_bytes() bytes.  Modes
+// processed: list[0..n_list) (all modes when list is null and n_list < 0).
+// With reduce = false the per-split partial sums are left in `partial`
+// ([split][mode][target] float4 hi/lo) for the GMRES step to combine, and
+// the split count is returned in *n_split_out.
 size_t sum32_partial_bytes(const SumArgs& a);
-hipError_t launch_sum32(const SumArgs& a, void* partial, hipStream_t s);
+hipError_t launch_sum32(const SumArgs& a, void* partial, hipStream_t s,
+                        const int32_t* list = nullptr, int32_t n_list = -1, bool reduce = true,
+                        int32_t* n_split_out = nullptr);
 // FP32 weighted copies: dst[m][j] = float2(scale * src[m][j])
 hipError_t launch_weight32(const double2* src, int64_t ld_src, int32_t n_modes, int32_t n,
                            double scale, float2* dst, int64_t ld_dst, hipStream_t s);
@@ -205,7 +211,10 @@ struct GmresState {
 size_t gmres_state_bytes(int32_t n, int32_t n_modes, int32_t mmax);
 void gmres_carve(GmresState& g, Carver& c);
 hipError_t launch_gmres_init(const GmresState& g, const double2* b, int64_t ld_b, hipStream_t s);
-hipError_t launch_gmres_orth(const GmresState& g, int32_t j, hipStream_t s);
+// One Arnoldi step after the matvec of v_j.  With `partial` set, w is first
+// formed from the FP32 kernel-sum partials as w = v_j / 2 - sum_splits.
+hipError_t launch_gmres_orth(const GmresState& g, int32_t j, const void* partial, int32_t n_split,
+                             hipStream_t s);
 hipError_t launch_gmres_solution(const GmresState& g, double2* x, int64_t ld_x, hipStream_t s);
 
 // ---- dense BEM (k_bem.hip) -------------------------------------------------
