@@ -60,6 +60,12 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # the same steps without kernel timing, to show what the timing costs
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_unprofiled = 1e3 * (time.perf_counter() - t0) / args.steps
     nat.nat_profile_enable(ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -130,6 +136,7 @@ def main():
                    "queries": wl.n_queries, "samples": wl.n_samples, "form": "FP32 compensated",
                    "gmres_tol": 1e-6},
         "executed_pair_evals_per_s": executed * args.steps / elapsed,
+        "ms_per_step_without_kernel_timing": ms_unprofiled,
         "gmres_iters": iters,
         "roofline": roofline,
         "cpu_baseline": cpu,

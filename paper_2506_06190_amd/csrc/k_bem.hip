@@ -389,27 +389,28 @@ k_panel_data(const int32_t* __restrict__ T, int32_t nT, const double2* __restric
 
 hipError_t launch_bem_far(const BemGeom& g, double k, double2 beta, double2* A, double2* B,
                           int32_t* near_list, int32_t near_cap, int32_t* near_count,
-                          hipStream_t s)
+                          hipStream_t s, const ProfSlot& ev)
 {
     dim3 grid(static_cast<unsigned>((g.n + 255) / 256), static_cast<unsigned>(g.n));
-    hipLaunchKernelGGL(k_bem_far, grid, dim3(256), 0, s, g, k, beta, A, B, near_list, near_cap,
-                       near_count);
+    launch_k(k_bem_far, grid, dim3(256), 0, s, ev.start, ev.stop, g, k, beta, A, B, near_list,
+             near_cap, near_count);
     return hipGetLastError();
 }
 
 hipError_t launch_bem_near(const BemGeom& g, double k, double2 beta, double2* A, double2* B,
-                           const int32_t* near_list, int32_t n_near, hipStream_t s)
+                           const int32_t* near_list, int32_t n_near, hipStream_t s,
+                           const ProfSlot& ev)
 {
     if (n_near <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_bem_near, dim3((n_near + 127) / 128), dim3(128), 0, s, g, k, beta, A, B,
-                       near_list, n_near);
+    launch_k(k_bem_near, dim3((n_near + 127) / 128), dim3(128), 0, s, ev.start, ev.stop, g, k, beta,
+             A, B, near_list, n_near);
     return hipGetLastError();
 }
 
 hipError_t launch_zgemv(const double2* M, int32_t n, const double2* x, int64_t ld_x,
                         int32_t n_rhs, double2* y, int64_t ld_y, const int32_t* active,
-                        hipStream_t s)
+                        hipStream_t s, const ProfSlot& ev)
 {
     (void)active;
     dim3 grid(static_cast<unsigned>((n + 3) / 4));
@@ -417,18 +418,20 @@ hipError_t launch_zgemv(const double2* M, int32_t n, const double2* x, int64_t l
         const int32_t R = n_rhs - r0 < 4 ? n_rhs - r0 : 4;
         const double2* xr = x + (size_t)r0 * ld_x;
         double2* yr = y + (size_t)r0 * ld_y;
+        hipEvent_t e0 = r0 == 0 ? ev.start : nullptr;
+        hipEvent_t e1 = r0 + 4 >= n_rhs ? ev.stop : nullptr;
         switch (R) {
         case 1:
-            hipLaunchKernelGGL(k_zgemv<1>, grid, dim3(256), 0, s, M, n, xr, ld_x, yr, ld_y);
+            launch_k(k_zgemv<1>, grid, dim3(256), 0, s, e0, e1, M, n, xr, ld_x, yr, ld_y);
             break;
         case 2:
-            hipLaunchKernelGGL(k_zgemv<2>, grid, dim3(256), 0, s, M, n, xr, ld_x, yr, ld_y);
+            launch_k(k_zgemv<2>, grid, dim3(256), 0, s, e0, e1, M, n, xr, ld_x, yr, ld_y);
             break;
         case 3:
-            hipLaunchKernelGGL(k_zgemv<3>, grid, dim3(256), 0, s, M, n, xr, ld_x, yr, ld_y);
+            launch_k(k_zgemv<3>, grid, dim3(256), 0, s, e0, e1, M, n, xr, ld_x, yr, ld_y);
             break;
         default:
-            hipLaunchKernelGGL(k_zgemv<4>, grid, dim3(256), 0, s, M, n, xr, ld_x, yr, ld_y);
+            launch_k(k_zgemv<4>, grid, dim3(256), 0, s, e0, e1, M, n, xr, ld_x, yr, ld_y);
             break;
         }
         hipError_t e = hipGetLastError();

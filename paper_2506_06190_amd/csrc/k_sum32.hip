@@ -39,8 +39,7 @@ struct Sum32Params {
     const float* kappa;    // [n_modes]
     const float* kk;       // [n_modes]
     const int32_t* active; // [n_modes] or null
-    const int32_t* list;   // modes to process (slot -> mode), or null for 0..n_list-1
-    int32_t n_list;
+    ModeList modes;        // slots of the launch
     float eps2;
     int32_t per_split;     // sources per split, multiple of kTS
     float4* partial;       // [split][mode][NT]: (hi.re, hi.im, lo.re, lo.im)
@@ -74,9 +73,9 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Params p)
     bool live[MB];
 #pragma unroll
     for (int mm = 0; mm < MB; ++mm) {
-        const int32_t slot = s0 + mm < p.n_list ? s0 + mm : p.n_list - 1;
-        mode[mm] = p.list ? p.list[slot] : slot;
-        live[mm] = (s0 + mm < p.n_list) && (!p.active || p.active[mode[mm]]);
+        const int32_t slot = s0 + mm < p.modes.n ? s0 + mm : p.modes.n - 1;
+        mode[mm] = mode_at(p.modes, slot);
+        live[mm] = (s0 + mm < p.modes.n) && (!p.active || p.active[mode[mm]]);
     }
     {
         bool any = false;
@@ -187,7 +186,7 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Params p)
     if (i < NT) {
 #pragma unroll
         for (int mm = 0; mm < MB; ++mm) {
-            if (s0 + mm < p.n_list)
+            if (s0 + mm < p.modes.n)
                 p.partial[((size_t)split * p.n_modes + mode[mm]) * NT + i] =
                     make_float4(hr[mm], hi_[mm], lr[mm], li[mm]);
         }
@@ -273,15 +272,16 @@ SplitPlan plan(int32_t NT, int32_t NS, int32_t n_list)
 }
 
 template <int OP, int MB>
-void launch_mb(const Sum32Params& p, const SplitPlan& sp, hipStream_t s)
+void launch_mb(const Sum32Params& p, const SplitPlan& sp, hipStream_t s, hipEvent_t e0,
+               hipEvent_t e1)
 {
     dim3 grid(sp.tiles, sp.n_split, sp.groups);
-    hipLaunchKernelGGL((k_sum32<OP, MB>), grid, dim3(kThreads), 0, s, p);
+    launch_k(k_sum32<OP, MB>, grid, dim3(kThreads), 0, s, e0, e1, p);
 }
 
 template <int OP>
-hipError_t launch_op(const SumArgs& a, const SplitPlan& sp, float4* partial, const int32_t* list,
-                     int32_t n_list, bool reduce, hipStream_t s)
+hipError_t launch_op(const SumArgs& a, const SplitPlan& sp, float4* partial, const ModeList& modes,
+                     bool reduce, hipStream_t s, const ProfSlot& ev)
 {
     Sum32Params p;
     p.NT = a.NT;
@@ -296,30 +296,31 @@ hipError_t launch_op(const SumArgs& a, const SplitPlan& sp, float4* partial, con
     p.kappa = a.kappa32;
     p.kk = a.k32;
     p.active = a.active;
-    p.list = list;
-    p.n_list = n_list;
+    p.modes = modes;
     p.eps2 = static_cast<float>(a.eps * a.eps);
     p.per_split = sp.per_split;
     p.partial = partial;
+    // with a reduction the stop event rides on the reduction kernel
+    hipEvent_t stop1 = reduce ? nullptr : ev.stop;
     switch (sp.mb) {
     case 1:
-        launch_mb<OP, 1>(p, sp, s);
+        launch_mb<OP, 1>(p, sp, s, ev.start, stop1);
         break;
     case 2:
-        launch_mb<OP, 2>(p, sp, s);
+        launch_mb<OP, 2>(p, sp, s, ev.start, stop1);
         break;
     case 4:
-        launch_mb<OP, 4>(p, sp, s);
+        launch_mb<OP, 4>(p, sp, s, ev.start, stop1);
         break;
     default:
-        launch_mb<OP, 8>(p, sp, s);
+        launch_mb<OP, 8>(p, sp, s, ev.start, stop1);
         break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !reduce)
         return e;
     dim3 g2(static_cast<unsigned>((a.NT + 255) / 256), static_cast<unsigned>(a.n_modes));
-    hipLaunchKernelGGL(k_reduce32<OP>, g2, dim3(256), 0, s, partial, sp.n_split, a);
+    launch_k(k_reduce32<OP>, g2, dim3(256), 0, s, nullptr, ev.stop, partial, sp.n_split, a);
     return hipGetLastError();
 }
 
@@ -332,24 +333,24 @@ size_t sum32_partial_bytes(const SumArgs& a)
     return sizeof(float4) * n_split * (size_t)a.n_modes * (size_t)a.NT;
 }
 
-hipError_t launch_sum32(const SumArgs& a, void* partial, hipStream_t s, const int32_t* list,
-                        int32_t n_list, bool reduce, int32_t* n_split_out)
+hipError_t launch_sum32(const SumArgs& a, void* partial, hipStream_t s, const ModeList& modes,
+                        bool reduce, int32_t* n_split_out, const ProfSlot& ev)
 {
-    if (n_list < 0)
-        n_list = a.n_modes;
-    if (a.NT <= 0 || n_list <= 0)
+    if (n_split_out)
+        *n_split_out = 0;
+    if (a.NT <= 0 || modes.n <= 0)
         return hipSuccess;
-    const SplitPlan sp = plan(a.NT, a.NS, n_list);
+    const SplitPlan sp = plan(a.NT, a.NS, modes.n);
     if (n_split_out)
         *n_split_out = sp.n_split;
     float4* part = static_cast<float4*>(partial);
     switch (a.op) {
     case OP_RHS:
-        return launch_op<OP_RHS>(a, sp, part, list, n_list, reduce, s);
+        return launch_op<OP_RHS>(a, sp, part, modes, reduce, s, ev);
     case OP_MATVEC:
-        return launch_op<OP_MATVEC>(a, sp, part, list, n_list, reduce, s);
+        return launch_op<OP_MATVEC>(a, sp, part, modes, reduce, s, ev);
     default:
-        return launch_op<OP_EVAL>(a, sp, part, list, n_list, reduce, s);
+        return launch_op<OP_EVAL>(a, sp, part, modes, reduce, s, ev);
     }
 }
 

@@ -87,20 +87,20 @@ __global__ void __launch_bounds__(256) k_sum64(SumArgs a)
 
 }  // namespace
 
-hipError_t launch_sum64(const SumArgs& a, hipStream_t s)
+hipError_t launch_sum64(const SumArgs& a, hipStream_t s, const ProfSlot& ev)
 {
     if (a.NT <= 0 || a.n_modes <= 0)
         return hipSuccess;
     dim3 grid(static_cast<unsigned>((a.NT + 255) / 256), static_cast<unsigned>(a.n_modes));
     switch (a.op) {
     case OP_RHS:
-        hipLaunchKernelGGL(k_sum64<OP_RHS>, grid, dim3(256), 0, s, a);
+        launch_k(k_sum64<OP_RHS>, grid, dim3(256), 0, s, ev.start, ev.stop, a);
         break;
     case OP_MATVEC:
-        hipLaunchKernelGGL(k_sum64<OP_MATVEC>, grid, dim3(256), 0, s, a);
+        launch_k(k_sum64<OP_MATVEC>, grid, dim3(256), 0, s, ev.start, ev.stop, a);
         break;
     default:
-        hipLaunchKernelGGL(k_sum64<OP_EVAL>, grid, dim3(256), 0, s, a);
+        launch_k(k_sum64<OP_EVAL>, grid, dim3(256), 0, s, ev.start, ev.stop, a);
         break;
     }
     return hipGetLastError();

@@ -17,9 +17,7 @@ namespace {
 thread_local std::string g_last_error;
 constexpr double kInv4Pi = 0.07957747154594767;
 constexpr double kTwoPi = 6.283185307179586;
-// GMRES iterations between host reads of the convergence flags; systems
-// that converge in between stop updating on the device.
-constexpr int32_t kCheckEvery = 4;
+
 }  // namespace
 
 namespace nat {
@@ -122,28 +120,22 @@ static hipEvent_t prof_event(nat_ctx* ctx)
     return e;
 }
 
-ProfScope::ProfScope(nat_ctx* c, int32_t kind, double flops, hipStream_t st)
-    : ctx(c), s(st), on(c && c->prof)
+ProfSlot prof_slot(nat_ctx* ctx, int32_t kind, double flops)
 {
-    if (!on)
-        return;
+    ProfSlot slot;
+    if (!ctx || !ctx->prof)
+        return slot;
+    NatProfEvent ev;
     ev.kind = kind;
     ev.flops = flops;
     ev.start = prof_event(ctx);
     ev.stop = prof_event(ctx);
-    if (!ev.start || !ev.stop) {
-        on = false;
-        return;
-    }
-    (void)hipEventRecord(ev.start, s);
-}
-
-ProfScope::~ProfScope()
-{
-    if (!on)
-        return;
-    (void)hipEventRecord(ev.stop, s);
+    if (!ev.start || !ev.stop)
+        return slot;
     ctx->prof_pending.push_back(ev);
+    slot.start = ev.start;
+    slot.stop = ev.stop;
+    return slot;
 }
 
 void prof_collect(nat_ctx* ctx)
@@ -163,6 +155,36 @@ void prof_collect(nat_ctx* ctx)
         ctx->prof_pool.push_back(e.stop);
     }
     ctx->prof_pending.clear();
+}
+
+// Pinned host words the kernels write directly: word 0 is the progress
+// counter, words 16.. the per-system flags.  Returns host and device views.
+nat_status mapped_words(nat_ctx* ctx, size_t n, int32_t** host, int32_t** dev)
+{
+    if (n > ctx->mapped_ints) {
+        if (ctx->mapped) {
+            NAT_HIP(hipDeviceSynchronize());
+            (void)hipHostFree(ctx->mapped);
+            ctx->mapped = nullptr;
+            ctx->mapped_dev = nullptr;
+            ctx->mapped_ints = 0;
+        }
+        const size_t want = n < 4096 ? 4096 : n;
+        void* p = nullptr;
+        NAT_HIP(hipHostMalloc(&p, want * sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent));
+        void* d = nullptr;
+        hipError_t e = hipHostGetDevicePointer(&d, p, 0);
+        if (e != hipSuccess) {
+            (void)hipHostFree(p);
+            return hip_fail(e, "hipHostGetDevicePointer");
+        }
+        ctx->mapped = static_cast<int32_t*>(p);
+        ctx->mapped_dev = static_cast<int32_t*>(d);
+        ctx->mapped_ints = want;
+    }
+    *host = ctx->mapped;
+    *dev = ctx->mapped_dev;
+    return NAT_OK;
 }
 
 // Gauss-Legendre nodes and weights on [0,1]: Newton's method on P_n from
@@ -270,6 +292,75 @@ nat_status device_checks(nat_ctx* ctx, int32_t* dflag, const int32_t* q_tri, con
     return NAT_OK;
 }
 
+// GMRES iterations shared by the Monte-Carlo and dense solves.
+// matvec(j, modes, &n_split) launches the product with v_j for the systems of
+// `modes` (n_split > 0 when it leaves FP32 split partials for the Arnoldi
+// step).  The Arnoldi kernels write each system's convergence flag and the
+// loop's progress into mapped host memory, so the host never waits on a copy:
+// it stays at most kLag iterations ahead of the device, rebuilds the list of
+// running systems from the flags it sees, and stops once none is running.
+// Systems that stop between refreshes are skipped on the device.
+constexpr int32_t kLag = 4;
+
+inline void cpu_relax() { __builtin_ia32_pause(); }
+
+template <class Matvec>
+nat_status gmres_run(nat_ctx* ctx, nat::GmresState& gs, const double2* b, int64_t ld_b,
+                     const void* partial, hipStream_t s, Matvec&& matvec)
+{
+    using namespace nat;
+    const int32_t M = gs.n_modes;
+    int32_t* hwords = nullptr;
+    int32_t* dwords = nullptr;
+    nat_status st = mapped_words(ctx, 16 + (size_t)M, &hwords, &dwords);
+    if (st != NAT_OK)
+        return st;
+    volatile int32_t* hprog = hwords;
+    volatile int32_t* hflag = hwords + 16;
+    // every earlier write of the device to these words has landed: the
+    // previous solve ended with a stream synchronisation
+    *hprog = 0;
+    for (int32_t m = 0; m < M; ++m)
+        hflag[m] = 1;
+    gs.host_progress = dwords;
+    gs.host_active = dwords + 16;
+    NAT_HIP(launch_gmres_init(gs, b, ld_b, s));
+    ModeList modes = all_modes(M);
+    for (int32_t j = 0; j < gs.mmax; ++j) {
+        if (j >= kLag) {
+            // wait until iteration j - kLag has finished on the device
+            const int32_t target = j - kLag + 1;
+            int64_t spins = 0;
+            while (*hprog < target) {
+                if (++spins > (int64_t(1) << 24)) {
+                    NAT_HIP(hipStreamSynchronize(s));
+                    break;
+                }
+                cpu_relax();
+            }
+            int32_t n_run = 0;
+            for (int32_t m = 0; m < M; ++m)
+                n_run += hflag[m] != 0;
+            if (n_run == 0)
+                break;
+            if (n_run <= kInlineModes) {
+                modes.identity = 0;
+                modes.n = 0;
+                for (int32_t m = 0; m < M; ++m)
+                    if (hflag[m])
+                        modes.m[modes.n++] = m;
+            } else {
+                modes = all_modes(M);
+            }
+        }
+        int32_t n_split = 0;
+        NAT_HIP(matvec(j, modes, &n_split));
+        NAT_HIP(launch_gmres_orth(gs, j, n_split > 0 ? partial : nullptr, n_split, modes, s,
+                                  prof_slot(ctx, PK_GMRES_ORTH, 0.0)));
+    }
+    return NAT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -365,6 +456,8 @@ void nat_ctx_destroy(nat_ctx* ctx)
         nat::dev_free(ctx, ctx->d_rules, sizeof(double) * 38);
     if (ctx->pinned)
         (void)hipHostFree(ctx->pinned);
+    if (ctx->mapped)
+        (void)hipHostFree(ctx->mapped);
     nat::prof_collect(ctx);
     for (hipEvent_t e : ctx->prof_pool)
         (void)hipEventDestroy(e);
@@ -690,7 +783,7 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
          sizeof(double) * 3 * q, sizeof(float) * 3 * q, sizeof(double2) * M * n,
          sizeof(double2) * M * q, sizeof(double2) * M * n, sizeof(double2) * M * n,
          sizeof(float2) * M * n, sizeof(double) * M, sizeof(float) * M, sizeof(float) * M, part,
-         gmres_state_bytes(N, M, mmax), sizeof(int32_t) * M});
+         gmres_state_bytes(N, M, mmax)});
     void* ws = nullptr;
     st = workspace(ctx, bytes, &ws);
     if (st != NAT_OK)
@@ -716,7 +809,6 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
     gs.n_modes = M;
     gs.mmax = mmax;
     gmres_carve(gs, cv);
-    int32_t* dlist = cv.take<int32_t>(M);
 
     // validation of the device inputs
     int32_t flags[2] = {0, 0};
@@ -728,18 +820,14 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
     if (flags[1])
         return fail(NAT_E_INVALID, "nat_mcbem_estimate: non-finite Neumann data");
 
-    // per-mode constants.  Pinned staging, one region per use so no host
-    // write lands on bytes an enqueued copy has still to read:
-    // [k f64 | k f32 | k/2pi f32 | active flags | active list]
+    // per-mode constants through pinned staging: [k f64 | k f32 | k/2pi f32]
     void* pin = nullptr;
-    st = pinned(ctx, sizeof(double) * M + sizeof(float) * M * 2 + sizeof(int32_t) * M * 2 + 64, &pin);
+    st = pinned(ctx, sizeof(double) * M + sizeof(float) * M * 2 + 64, &pin);
     if (st != NAT_OK)
         return st;
     double* hk = static_cast<double*>(pin);
     float* hk32 = reinterpret_cast<float*>(hk + M);
     float* hkap = hk32 + M;
-    int32_t* hact = reinterpret_cast<int32_t*>(hkap + M);
-    int32_t* hlist = hact + M;
     for (int32_t m = 0; m < M; ++m) {
         hk[m] = k[m];
         hk32[m] = static_cast<float>(k[m]);
@@ -793,11 +881,10 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
         if (fp32) {
             NAT_HIP(launch_weight32(gj, N, M, N, wscale, a32, N, s));
             a.g_src32 = a32;
-            ProfScope ps_(ctx, PK_SUM32_RHS, 24.0 * n * n * M, s);
-            NAT_HIP(launch_sum32(a, partial, s));
+            NAT_HIP(launch_sum32(a, partial, s, all_modes(M), true, nullptr,
+                                 prof_slot(ctx, PK_SUM32_RHS, 24.0 * n * n * M)));
         } else {
-            ProfScope ps_(ctx, PK_SUM64, 24.0 * n * n * M, s);
-            NAT_HIP(launch_sum64(a, s));
+            NAT_HIP(launch_sum64(a, s, prof_slot(ctx, PK_SUM64, 24.0 * n * n * M)));
         }
     }
 
@@ -806,48 +893,27 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
     gs.v32_scale = wscale;
     if (!fp32)
         gs.v32 = nullptr;
-    NAT_HIP(launch_gmres_init(gs, b, N, s));
-    // active-mode list for the FP32 matvec, refreshed at each convergence check
-    int32_t n_active = M;
-    for (int32_t m = 0; m < M; ++m)
-        hlist[m] = m;
-    NAT_HIP(hipMemcpyAsync(dlist, hlist, sizeof(int32_t) * M, hipMemcpyHostToDevice, s));
-    for (int32_t j = 0; j < mmax; ++j) {
-        SumArgs a = base;
-        a.op = OP_MATVEC;
-        a.NT = N;
-        a.t64 = ps.x64;
-        a.t32 = ps.x32;
-        a.p_src = gs.V + (size_t)j * n;
-        a.ld_ps = (int64_t)(mmax + 1) * N;
-        a.p_src32 = gs.v32;
-        a.active = gs.active;
-        a.out = gs.w;
-        a.ld_out = N;
-        int32_t n_split = 0;
-        if (fp32) {
-            ProfScope ps_(ctx, PK_SUM32_MATVEC, 37.0 * n * n * n_active, s);
-            NAT_HIP(launch_sum32(a, partial, s, dlist, n_active, false, &n_split));
-        } else {
-            ProfScope ps_(ctx, PK_SUM64, 37.0 * n * n * n_active, s);
-            NAT_HIP(launch_sum64(a, s));
-        }
-        {
-            ProfScope ps_(ctx, PK_GMRES_ORTH, 0.0, s);
-            NAT_HIP(launch_gmres_orth(gs, j, fp32 ? partial : nullptr, n_split, s));
-        }
-        if ((j + 1) % kCheckEvery == 0 || j + 1 == mmax) {
-            NAT_HIP(hipMemcpyAsync(hact, gs.active, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
-            NAT_HIP(hipStreamSynchronize(s));
-            n_active = 0;
-            for (int32_t m = 0; m < M; ++m)
-                if (hact[m])
-                    hlist[n_active++] = m;
-            if (!n_active)
-                break;
-            NAT_HIP(hipMemcpyAsync(dlist, hlist, sizeof(int32_t) * n_active, hipMemcpyHostToDevice, s));
-        }
-    }
+    st = gmres_run(ctx, gs, b, N, partial, s,
+                   [&](int32_t j, const ModeList& modes, int32_t* n_split) -> hipError_t {
+                       SumArgs a = base;
+                       a.op = OP_MATVEC;
+                       a.NT = N;
+                       a.t64 = ps.x64;
+                       a.t32 = ps.x32;
+                       a.p_src = gs.V + (size_t)j * n;
+                       a.ld_ps = (int64_t)(mmax + 1) * N;
+                       a.p_src32 = gs.v32;
+                       a.active = gs.active;
+                       a.out = gs.w;
+                       a.ld_out = N;
+                       if (fp32)
+                           return launch_sum32(a, partial, s, modes, false, n_split,
+                                               prof_slot(ctx, PK_SUM32_MATVEC, 37.0 * n * n * modes.n));
+                       *n_split = 0;
+                       return launch_sum64(a, s, prof_slot(ctx, PK_SUM64, 37.0 * n * n * M));
+                   });
+    if (st != NAT_OK)
+        return st;
     double2* x = p_samples ? reinterpret_cast<double2*>(p_samples) : xin;
     NAT_HIP(launch_gmres_solution(gs, x, N, s));
 
@@ -871,11 +937,10 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
             NAT_HIP(launch_weight32(x, N, M, N, wscale, gs.v32, N, s));
             a.g_src32 = a32;
             a.p_src32 = gs.v32;
-            ProfScope ps_(ctx, PK_SUM32_EVAL, 47.0 * q * n * M, s);
-            NAT_HIP(launch_sum32(a, partial, s));
+            NAT_HIP(launch_sum32(a, partial, s, all_modes(M), true, nullptr,
+                                 prof_slot(ctx, PK_SUM32_EVAL, 47.0 * q * n * M)));
         } else {
-            ProfScope ps_(ctx, PK_SUM64, 47.0 * q * n * M, s);
-            NAT_HIP(launch_sum64(a, s));
+            NAT_HIP(launch_sum64(a, s, prof_slot(ctx, PK_SUM64, 47.0 * q * n * M)));
         }
     }
     prof_collect(ctx);
@@ -955,9 +1020,9 @@ nat_status nat_bem_assemble(nat_mesh* mesh, double k, int32_t burton_miller, nat
         int32_t* count = cv.take<int32_t>(4);
         int32_t* list = cv.take<int32_t>(2 * (size_t)cap);
         hipError_t e = hipMemsetAsync(count, 0, sizeof(int32_t), s);
-        ProfScope ps_(ctx, PK_BEM_ASSEMBLE, 0.0, s);
         if (e == hipSuccess)
-            e = launch_bem_far(g, k, beta, op->d_A, op->d_B, list, cap, count, s);
+            e = launch_bem_far(g, k, beta, op->d_A, op->d_B, list, cap, count, s,
+                               prof_slot(ctx, PK_BEM_ASSEMBLE, 0.0));
         int32_t n_near = 0;
         if (e == hipSuccess)
             e = hipMemcpyAsync(&n_near, count, sizeof(int32_t), hipMemcpyDeviceToHost, s);
@@ -971,7 +1036,8 @@ nat_status nat_bem_assemble(nat_mesh* mesh, double k, int32_t burton_miller, nat
             cap = n_near;
             continue;
         }
-        e = launch_bem_near(g, k, beta, op->d_A, op->d_B, list, n_near, s);
+        e = launch_bem_near(g, k, beta, op->d_A, op->d_B, list, n_near, s,
+                            prof_slot(ctx, PK_BEM_ASSEMBLE, 0.0));
         if (e == hipSuccess)
             e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
@@ -1039,32 +1105,19 @@ nat_status nat_bem_solve(nat_bem_op* op, const double* v_n, int32_t n_rhs, int32
         NAT_HIP(hipMemcpyAsync(gp, g, sizeof(double2) * (size_t)M * n, hipMemcpyDeviceToDevice, s));
     }
     NAT_HIP(launch_zgemv(op->d_B, n, gp, n, M, b, n, nullptr, s));
-    NAT_HIP(launch_gmres_init(gs, b, n, s));
-    void* pin = nullptr;
-    st = pinned(ctx, sizeof(double) * M + sizeof(int32_t) * M + 64, &pin);
+    st = gmres_run(ctx, gs, b, n, nullptr, s,
+                   [&](int32_t j, const ModeList&, int32_t* n_split) -> hipError_t {
+                       *n_split = 0;
+                       return launch_zgemv(op->d_A, n, gs.V + (size_t)j * n,
+                                           (int64_t)(max_iter + 1) * n, M, gs.w, n, gs.active, s,
+                                           prof_slot(ctx, PK_ZGEMV, 8.0 * n * (double)n * M));
+                   });
     if (st != NAT_OK)
         return st;
-    int32_t* hact = static_cast<int32_t*>(pin);
-    for (int32_t j = 0; j < max_iter; ++j) {
-        {
-            ProfScope ps_(ctx, PK_ZGEMV, 8.0 * n * (double)n * M, s);
-            NAT_HIP(launch_zgemv(op->d_A, n, gs.V + (size_t)j * n, (int64_t)(max_iter + 1) * n, M,
-                                 gs.w, n, gs.active, s));
-        }
-        {
-            ProfScope ps_(ctx, PK_GMRES_ORTH, 0.0, s);
-            NAT_HIP(launch_gmres_orth(gs, j, nullptr, 0, s));
-        }
-        if ((j + 1) % kCheckEvery == 0 || j + 1 == max_iter) {
-            NAT_HIP(hipMemcpyAsync(hact, gs.active, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
-            NAT_HIP(hipStreamSynchronize(s));
-            bool any = false;
-            for (int32_t m = 0; m < M; ++m)
-                any |= hact[m] != 0;
-            if (!any)
-                break;
-        }
-    }
+    void* pin = nullptr;
+    st = pinned(ctx, sizeof(double) * M + sizeof(int32_t) * M * 2 + 64, &pin);
+    if (st != NAT_OK)
+        return st;
     NAT_HIP(launch_gmres_solution(gs, reinterpret_cast<double2*>(p_out), n, s));
     int32_t* hit = static_cast<int32_t*>(pin);
     double* hres = reinterpret_cast<double*>(static_cast<char*>(pin) + 8 * ((M * 4 + 7) / 8));

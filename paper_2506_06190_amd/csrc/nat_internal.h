@@ -2,6 +2,7 @@
 // the device-memory ledger, and the launchers of the HIP kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -39,6 +40,11 @@ struct nat_ctx {
     // pinned host staging for small device-to-host reads
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
+    // pinned host memory the kernels write directly (convergence flags and
+    // progress of the GMRES loop), read by the host without a copy
+    int32_t* mapped = nullptr;
+    int32_t* mapped_dev = nullptr;
+    size_t mapped_ints = 0;
     // Gauss-Legendre rules on [0,1] for the dense assembly (device copies)
     double* d_rules = nullptr;
 };
@@ -89,6 +95,7 @@ void dev_free(nat_ctx* ctx, void* ptr, size_t bytes);
 // grow-only scratch; contents undefined on return
 nat_status workspace(nat_ctx* ctx, size_t bytes, void** ptr);
 nat_status pinned(nat_ctx* ctx, size_t bytes, void** ptr);
+nat_status mapped_words(nat_ctx* ctx, size_t n, int32_t** host, int32_t** dev);
 
 // Carves aligned sub-buffers out of one allocation.
 struct Carver {
@@ -115,17 +122,45 @@ enum ProfKind {
     PK_SUM32_RHS = 0, PK_SUM32_MATVEC = 1, PK_SUM32_EVAL = 2,
     PK_SUM64 = 3, PK_GMRES_ORTH = 4, PK_BEM_ASSEMBLE = 5, PK_ZGEMV = 6, PK_OTHER = 7
 };
-// Records a start event now and a stop event at destruction when profiling is on.
-struct ProfScope {
-    nat_ctx* ctx;
-    hipStream_t s;
-    NatProfEvent ev;
-    bool on;
-    ProfScope(nat_ctx* c, int32_t kind, double flops, hipStream_t st);
-    ~ProfScope();
+// Start/stop events of one timed launch (null when profiling is off).  The
+// events ride on the dispatch packets of the first and last kernel of the
+// launch (hipExtLaunchKernelGGL), so timing adds no packets to the stream.
+struct ProfSlot {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
 };
+ProfSlot prof_slot(nat_ctx* ctx, int32_t kind, double flops);
 // Resolve finished events into the per-kind totals (synchronises the device).
 void prof_collect(nat_ctx* ctx);
+
+template <class K, class... A>
+inline void launch_k(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, hipEvent_t e0,
+                     hipEvent_t e1, A... args)
+{
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(kernel, grid, block, static_cast<uint32_t>(lds), s, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
+
+// Modes a launch works on: slot s is mode s (identity) or the inline list.
+constexpr int kInlineModes = 64;
+struct ModeList {
+    int32_t n = 0;
+    int32_t identity = 1;
+    int32_t m[kInlineModes];
+};
+__host__ __device__ inline int32_t mode_at(const ModeList& L, int32_t slot)
+{
+    return L.identity ? slot : L.m[slot];
+}
+inline ModeList all_modes(int32_t n)
+{
+    ModeList L;
+    L.n = n;
+    L.identity = 1;
+    return L;
+}
 
 // ---- sampling and surface data (k_sample.hip) ------------------------------
 struct PointStreams {   // SoA surface points
@@ -177,16 +212,14 @@ struct SumArgs {
     double2* out;                // [mode * ld_out + i]
     int64_t ld_out;
 };
-hipError_t launch_sum64(const SumArgs& a, hipStream_t s);
-// FP32 tiled sum; partial is scratch of sum32_partial_bytes() bytes.  Modes
-// processed: list[0..n_list) (all modes when list is null and n_list < 0).
-// With reduce = false the per-split partial sums are left in `partial`
-// ([split][mode][target] float4 hi/lo) for the GMRES step to combine, and
-// the split count is returned in *n_split_out.
+hipError_t launch_sum64(const SumArgs& a, hipStream_t s, const ProfSlot& ev = ProfSlot());
+// FP32 tiled sum over the modes of `modes`; partial is scratch of
+// sum32_partial_bytes() bytes.  With reduce = false the per-split partial
+// sums are left in `partial` ([split][mode][target] float4 hi/lo) for the
+// GMRES step to combine, and the split count is returned in *n_split_out.
 size_t sum32_partial_bytes(const SumArgs& a);
-hipError_t launch_sum32(const SumArgs& a, void* partial, hipStream_t s,
-                        const int32_t* list = nullptr, int32_t n_list = -1, bool reduce = true,
-                        int32_t* n_split_out = nullptr);
+hipError_t launch_sum32(const SumArgs& a, void* partial, hipStream_t s, const ModeList& modes,
+                        bool reduce, int32_t* n_split_out, const ProfSlot& ev = ProfSlot());
 // FP32 weighted copies: dst[m][j] = float2(scale * src[m][j])
 hipError_t launch_weight32(const double2* src, int64_t ld_src, int32_t n_modes, int32_t n,
                            double scale, float2* dst, int64_t ld_dst, hipStream_t s);
@@ -207,14 +240,22 @@ struct GmresState {
     float2* v32;     // [mode][n] FP32 copy of v_j scaled by v32_scale (or null)
     double v32_scale;
     double tol;
+    int32_t nch;        // row chunks of the Arnoldi kernels
+    double2* dp1;       // [mode][chunk][mmax+1] partial dots, first CGS pass
+    double2* dp2;       // [mode][chunk][mmax+1] partial dots, second CGS pass
+    double* normpart;   // [mode][chunk]
+    double2* htot;      // [mode][mmax+1] Hessenberg column being built
+    int32_t* host_active;   // mapped host copy of `active` (or null)
+    int32_t* host_progress; // mapped host word: last finished iteration (or null)
 };
 size_t gmres_state_bytes(int32_t n, int32_t n_modes, int32_t mmax);
 void gmres_carve(GmresState& g, Carver& c);
 hipError_t launch_gmres_init(const GmresState& g, const double2* b, int64_t ld_b, hipStream_t s);
-// One Arnoldi step after the matvec of v_j.  With `partial` set, w is first
+// One Arnoldi step after the matvec of v_j for the systems of `modes`
+// (systems already stopped are skipped).  With `partial` set, w is first
 // formed from the FP32 kernel-sum partials as w = v_j / 2 - sum_splits.
 hipError_t launch_gmres_orth(const GmresState& g, int32_t j, const void* partial, int32_t n_split,
-                             hipStream_t s);
+                             const ModeList& modes, hipStream_t s, const ProfSlot& ev = ProfSlot());
 hipError_t launch_gmres_solution(const GmresState& g, double2* x, int64_t ld_x, hipStream_t s);
 
 // ---- dense BEM (k_bem.hip) -------------------------------------------------
@@ -226,13 +267,14 @@ struct BemGeom {
 };
 hipError_t launch_bem_far(const BemGeom& g, double k, double2 beta, double2* A, double2* B,
                           int32_t* near_list, int32_t near_cap, int32_t* near_count,
-                          hipStream_t s);
+                          hipStream_t s, const ProfSlot& ev = ProfSlot());
 hipError_t launch_bem_near(const BemGeom& g, double k, double2 beta, double2* A, double2* B,
-                           const int32_t* near_list, int32_t n_near, hipStream_t s);
+                           const int32_t* near_list, int32_t n_near, hipStream_t s,
+                           const ProfSlot& ev = ProfSlot());
 // y[r][i] = sum_j M[i][j] x[r][j] for the rows of n x n M, r < n_rhs
 hipError_t launch_zgemv(const double2* M, int32_t n, const double2* x, int64_t ld_x,
                         int32_t n_rhs, double2* y, int64_t ld_y, const int32_t* active,
-                        hipStream_t s);
+                        hipStream_t s, const ProfSlot& ev = ProfSlot());
 hipError_t launch_panel_data(const int32_t* T, int32_t nT, const double2* gv, int64_t ld_in,
                              int32_t n_rhs, double2* gp, int64_t ld_out, hipStream_t s);
 
