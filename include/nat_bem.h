@@ -75,8 +75,12 @@ typedef struct {
     double eps_scale;       /* eps = eps_scale * sqrt(|Gamma| / (pi N)); > 0         */
     double gmres_tol;       /* relative residual |r| / |b| to stop at; > 0           */
     int32_t gmres_max_iter; /* 1 .. 1000                                             */
-    int32_t reserved;       /* must be 0                                             */
+    int32_t flags;          /* 0 or NAT_MC_NO_GRAPH                                  */
 } nat_mc_opts;
+
+/* nat_mc_opts.flags: launch every GMRES kernel directly instead of replaying
+ * captured runs of iterations (results are identical). */
+#define NAT_MC_NO_GRAPH 1
 
 /* Per right-hand side report of a solve. */
 typedef struct {
@@ -165,6 +169,35 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
                               int32_t n_queries, int32_t n_samples, uint64_t seed,
                               const nat_mc_opts* opts, double* p_out, double* p_samples,
                               nat_solve_report* report, void* stream);
+
+/* One problem of a batch: the arguments of nat_mcbem_estimate. */
+typedef struct {
+    nat_mesh* mesh;
+    const double* v_n;       /* device complex [n_modes][n_vertices or n_tris]      */
+    int32_t n_modes;
+    int32_t n_queries;
+    const double* k;         /* host double[n_modes]                                */
+    const int32_t* q_tri;    /* device int32[n_queries]                              */
+    const double* q_bary;    /* device double[n_queries][2]                          */
+    int32_t n_samples;
+    int32_t reserved;        /* ignored                                             */
+    uint64_t seed;
+    double* p_out;           /* device complex [n_modes][n_queries]                  */
+    double* p_samples;       /* device complex [n_modes][n_samples] or NULL          */
+} nat_mc_job;
+
+/* Many Monte-Carlo estimates of uneven size at once (meshes of one context,
+ * each job with its own samples, modes, wavenumbers and queries): every
+ * stage runs as one launch over all (job, mode) systems, GMRES iterates them
+ * in lockstep with converged systems dropped from the work lists, and runs
+ * of iterations are replayed from a captured graph.  Each job's results are
+ * bit-for-bit those of nat_mcbem_estimate on the same job with the same
+ * options: the tiling of a job depends only on its own sizes.  reports:
+ * host nat_solve_report[sum of n_modes] in job order, or NULL.  Blocks until
+ * done; NAT_E_NOCONV if any system stopped above its tolerance. */
+nat_status nat_mcbem_estimate_batch(nat_ctx* ctx, const nat_mc_job* jobs, int32_t n_jobs,
+                                    const nat_mc_opts* opts, nat_solve_report* reports,
+                                    void* stream);
 
 /* ---- dense collocation Burton-Miller BEM (Section 4, Section 4.1) -------- */
 

@@ -15,8 +15,6 @@
 
 namespace {
 thread_local std::string g_last_error;
-constexpr double kInv4Pi = 0.07957747154594767;
-constexpr double kTwoPi = 6.283185307179586;
 
 }  // namespace
 
@@ -232,7 +230,7 @@ void gauss_legendre01(int n, double* x, double* w)
 
 using nat::fail;
 
-namespace {
+namespace nat {
 
 bool is_finite(double v) { return std::isfinite(v); }
 
@@ -269,9 +267,10 @@ __global__ void k_check_finite(const double* v, int64_t n, int32_t* flag)
 // Zero the two flags, run the checks, read them back.
 nat_status device_checks(nat_ctx* ctx, int32_t* dflag, const int32_t* q_tri, const double* q_bary,
                          int32_t Q, int32_t nT, const double* vals, int64_t n_vals,
-                         hipStream_t s, int32_t* host_flags)
+                         hipStream_t s, int32_t* host_flags, bool zero_and_read)
 {
-    NAT_HIP(hipMemsetAsync(dflag, 0, 2 * sizeof(int32_t), s));
+    if (zero_and_read)
+        NAT_HIP(hipMemsetAsync(dflag, 0, 2 * sizeof(int32_t), s));
     if (Q > 0) {
         hipLaunchKernelGGL(k_check_queries, dim3((Q + 255) / 256), dim3(256), 0, s, q_tri, q_bary,
                            Q, nT, dflag);
@@ -282,6 +281,8 @@ nat_status device_checks(nat_ctx* ctx, int32_t* dflag, const int32_t* q_tri, con
                            vals, n_vals, dflag);
         NAT_HIP(hipGetLastError());
     }
+    if (!zero_and_read)
+        return NAT_OK;
     void* pin = nullptr;
     nat_status st = nat::pinned(ctx, 64, &pin);
     if (st != NAT_OK)
@@ -292,76 +293,10 @@ nat_status device_checks(nat_ctx* ctx, int32_t* dflag, const int32_t* q_tri, con
     return NAT_OK;
 }
 
-// GMRES iterations shared by the Monte-Carlo and dense solves.
-// matvec(j, modes, &n_split) launches the product with v_j for the systems of
-// `modes` (n_split > 0 when it leaves FP32 split partials for the Arnoldi
-// step).  The Arnoldi kernels write each system's convergence flag and the
-// loop's progress into mapped host memory, so the host never waits on a copy:
-// it stays at most kLag iterations ahead of the device, rebuilds the list of
-// running systems from the flags it sees, and stops once none is running.
-// Systems that stop between refreshes are skipped on the device.
-constexpr int32_t kLag = 4;
+}  // namespace nat
 
-inline void cpu_relax() { __builtin_ia32_pause(); }
-
-template <class Matvec>
-nat_status gmres_run(nat_ctx* ctx, nat::GmresState& gs, const double2* b, int64_t ld_b,
-                     const void* partial, hipStream_t s, Matvec&& matvec)
-{
-    using namespace nat;
-    const int32_t M = gs.n_modes;
-    int32_t* hwords = nullptr;
-    int32_t* dwords = nullptr;
-    nat_status st = mapped_words(ctx, 16 + (size_t)M, &hwords, &dwords);
-    if (st != NAT_OK)
-        return st;
-    volatile int32_t* hprog = hwords;
-    volatile int32_t* hflag = hwords + 16;
-    // every earlier write of the device to these words has landed: the
-    // previous solve ended with a stream synchronisation
-    *hprog = 0;
-    for (int32_t m = 0; m < M; ++m)
-        hflag[m] = 1;
-    gs.host_progress = dwords;
-    gs.host_active = dwords + 16;
-    NAT_HIP(launch_gmres_init(gs, b, ld_b, s));
-    ModeList modes = all_modes(M);
-    for (int32_t j = 0; j < gs.mmax; ++j) {
-        if (j >= kLag) {
-            // wait until iteration j - kLag has finished on the device
-            const int32_t target = j - kLag + 1;
-            int64_t spins = 0;
-            while (*hprog < target) {
-                if (++spins > (int64_t(1) << 24)) {
-                    NAT_HIP(hipStreamSynchronize(s));
-                    break;
-                }
-                cpu_relax();
-            }
-            int32_t n_run = 0;
-            for (int32_t m = 0; m < M; ++m)
-                n_run += hflag[m] != 0;
-            if (n_run == 0)
-                break;
-            if (n_run <= kInlineModes) {
-                modes.identity = 0;
-                modes.n = 0;
-                for (int32_t m = 0; m < M; ++m)
-                    if (hflag[m])
-                        modes.m[modes.n++] = m;
-            } else {
-                modes = all_modes(M);
-            }
-        }
-        int32_t n_split = 0;
-        NAT_HIP(matvec(j, modes, &n_split));
-        NAT_HIP(launch_gmres_orth(gs, j, n_split > 0 ? partial : nullptr, n_split, modes, s,
-                                  prof_slot(ctx, PK_GMRES_ORTH, 0.0)));
-    }
-    return NAT_OK;
-}
-
-}  // namespace
+using nat::is_finite;
+using nat::set_device;
 
 extern "C" {
 
@@ -403,7 +338,7 @@ void nat_mc_opts_default(nat_mc_opts* o)
     o->eps_scale = 1.0;
     o->gmres_tol = 1e-6;
     o->gmres_max_iter = 200;
-    o->reserved = 0;
+    o->flags = 0;
 }
 
 nat_status nat_ctx_create(int32_t device, size_t hbm_budget_bytes, nat_ctx** out)
@@ -458,6 +393,10 @@ void nat_ctx_destroy(nat_ctx* ctx)
         (void)hipHostFree(ctx->pinned);
     if (ctx->mapped)
         (void)hipHostFree(ctx->mapped);
+    if (ctx->graph_exec)
+        (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->capture_stream)
+        (void)hipStreamDestroy(ctx->capture_stream);
     nat::prof_collect(ctx);
     for (hipEvent_t e : ctx->prof_pool)
         (void)hipEventDestroy(e);
@@ -733,244 +672,6 @@ nat_status nat_mcbem_samples(nat_mesh* m, int32_t N, uint64_t seed, int32_t* tri
     return NAT_OK;
 }
 
-nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes, const double* k,
-                              const int32_t* q_tri, const double* q_bary, int32_t Q, int32_t N,
-                              uint64_t seed, const nat_mc_opts* opts, double* p_out,
-                              double* p_samples, nat_solve_report* report, void* stream)
-{
-    using namespace nat;
-    if (!mesh || !v_n || !k || !opts)
-        return fail(NAT_E_INVALID, "nat_mcbem_estimate: NULL argument");
-    if (n_modes < 1 || n_modes > 4096)
-        return fail(NAT_E_INVALID, "nat_mcbem_estimate: n_modes = %d", n_modes);
-    if (N < 2 || N > (1 << 24))
-        return fail(NAT_E_INVALID, "nat_mcbem_estimate: n_samples = %d", N);
-    if (Q < 0 || Q > (1 << 26) || (Q > 0 && (!q_tri || !q_bary || !p_out)))
-        return fail(NAT_E_INVALID, "nat_mcbem_estimate: bad queries (Q = %d)", Q);
-    if (opts->precision != NAT_PREC_FP64 && opts->precision != NAT_PREC_FP32)
-        return fail(NAT_E_INVALID, "nat_mcbem_estimate: precision %d", opts->precision);
-    if (opts->layout != NAT_NEUMANN_PER_VERTEX && opts->layout != NAT_NEUMANN_PER_TRIANGLE)
-        return fail(NAT_E_INVALID, "nat_mcbem_estimate: layout %d", opts->layout);
-    if (!(opts->eps_scale > 0.0) || !is_finite(opts->eps_scale) || !(opts->gmres_tol > 0.0) ||
-        opts->gmres_max_iter < 1 || opts->gmres_max_iter > 1000 || opts->reserved != 0)
-        return fail(NAT_E_INVALID, "nat_mcbem_estimate: bad solver options");
-    for (int32_t m = 0; m < n_modes; ++m)
-        if (!(k[m] > 0.0) || !is_finite(k[m]))
-            return fail(NAT_E_INVALID, "nat_mcbem_estimate: k[%d] = %g", m, k[m]);
-    nat_ctx* ctx = mesh->ctx;
-    nat_status st = set_device(ctx);
-    if (st != NAT_OK)
-        return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const bool fp32 = opts->precision == NAT_PREC_FP32;
-    const int32_t M = n_modes;
-    const int32_t mmax = opts->gmres_max_iter;
-    const int32_t ng = opts->layout == NAT_NEUMANN_PER_TRIANGLE ? mesh->nT : mesh->nV;
-    const size_t n = N, q = Q;
-
-    // scratch layout
-    SumArgs probe{};
-    probe.n_modes = M;
-    probe.NS = N;
-    probe.NT = N;
-    const size_t partA = fp32 ? sum32_partial_bytes(probe) : 0;
-    probe.NT = Q;
-    const size_t partB = fp32 && Q > 0 ? sum32_partial_bytes(probe) : 0;
-    const size_t part = partA > partB ? partA : partB;
-    const size_t bytes = carve_size<>(
-        {sizeof(int32_t) * 4, sizeof(int32_t) * n, sizeof(double) * 2 * n, sizeof(double) * 3 * n,
-         sizeof(double) * 3 * n, sizeof(float) * 3 * n, sizeof(float) * 3 * n,
-         sizeof(double) * 3 * q, sizeof(float) * 3 * q, sizeof(double2) * M * n,
-         sizeof(double2) * M * q, sizeof(double2) * M * n, sizeof(double2) * M * n,
-         sizeof(float2) * M * n, sizeof(double) * M, sizeof(float) * M, sizeof(float) * M, part,
-         gmres_state_bytes(N, M, mmax)});
-    void* ws = nullptr;
-    st = workspace(ctx, bytes, &ws);
-    if (st != NAT_OK)
-        return st;
-    Carver cv(ws);
-    int32_t* dflag = cv.take<int32_t>(4);
-    int32_t* tri = cv.take<int32_t>(n);
-    double* bary = cv.take<double>(2 * n);
-    PointStreams ps{cv.take<double>(3 * n), cv.take<double>(3 * n), cv.take<float>(3 * n),
-                    cv.take<float>(3 * n)};
-    PointStreams qs{cv.take<double>(3 * q), nullptr, cv.take<float>(3 * q), nullptr};
-    double2* gj = cv.take<double2>(M * n);
-    double2* gq = cv.take<double2>(M * q);
-    double2* b = cv.take<double2>(M * n);
-    double2* xin = cv.take<double2>(M * n);
-    float2* a32 = cv.take<float2>(M * n);
-    double* dk = cv.take<double>(M);
-    float* dk32 = cv.take<float>(M);
-    float* dkap = cv.take<float>(M);
-    void* partial = cv.take<char>(part);
-    GmresState gs{};
-    gs.n = N;
-    gs.n_modes = M;
-    gs.mmax = mmax;
-    gmres_carve(gs, cv);
-
-    // validation of the device inputs
-    int32_t flags[2] = {0, 0};
-    st = device_checks(ctx, dflag, q_tri, q_bary, Q, mesh->nT, v_n, 2 * (int64_t)M * ng, s, flags);
-    if (st != NAT_OK)
-        return st;
-    if (flags[0])
-        return fail(NAT_E_INVALID, "nat_mcbem_estimate: query record out of range");
-    if (flags[1])
-        return fail(NAT_E_INVALID, "nat_mcbem_estimate: non-finite Neumann data");
-
-    // per-mode constants through pinned staging: [k f64 | k f32 | k/2pi f32]
-    void* pin = nullptr;
-    st = pinned(ctx, sizeof(double) * M + sizeof(float) * M * 2 + 64, &pin);
-    if (st != NAT_OK)
-        return st;
-    double* hk = static_cast<double*>(pin);
-    float* hk32 = reinterpret_cast<float*>(hk + M);
-    float* hkap = hk32 + M;
-    for (int32_t m = 0; m < M; ++m) {
-        hk[m] = k[m];
-        hk32[m] = static_cast<float>(k[m]);
-        hkap[m] = static_cast<float>(k[m] / kTwoPi);
-    }
-    NAT_HIP(hipMemcpyAsync(dk, hk, sizeof(double) * M, hipMemcpyHostToDevice, s));
-    NAT_HIP(hipMemcpyAsync(dk32, hk32, sizeof(float) * M, hipMemcpyHostToDevice, s));
-    NAT_HIP(hipMemcpyAsync(dkap, hkap, sizeof(float) * M, hipMemcpyHostToDevice, s));
-
-    const double area = mesh->area_total;
-    const double w = area / static_cast<double>(N);
-    const double eps = opts->eps_scale * std::sqrt(area / (M_PI * static_cast<double>(N)));
-    const double wscale = w * kInv4Pi;
-
-    // a2: samples, points, Neumann data
-    NAT_HIP(launch_samples(mesh, N, seed, tri, bary, s));
-    NAT_HIP(launch_points(mesh, N, tri, bary, ps, s));
-    NAT_HIP(launch_points(mesh, Q, q_tri, q_bary, qs, s));
-    NAT_HIP(launch_neumann(mesh, opts->layout, reinterpret_cast<const double2*>(v_n), ng, M, N,
-                           tri, bary, gj, s));
-    NAT_HIP(launch_neumann(mesh, opts->layout, reinterpret_cast<const double2*>(v_n), ng, M, Q,
-                           q_tri, q_bary, gq, s));
-
-    SumArgs base{};
-    base.n_modes = M;
-    base.s64 = ps.x64;
-    base.sn64 = ps.n64;
-    base.s32 = ps.x32;
-    base.sn32 = ps.n32;
-    base.k = dk;
-    base.k32 = dk32;
-    base.kappa32 = dkap;
-    base.w = w;
-    base.eps = eps;
-    base.NS = N;
-    base.ld_s32 = N;
-
-    // a3: right-hand side
-    {
-        SumArgs a = base;
-        a.op = OP_RHS;
-        a.NT = N;
-        a.t64 = ps.x64;
-        a.t32 = ps.x32;
-        a.g_src = gj;
-        a.ld_gs = N;
-        a.g_tgt = gj;
-        a.ld_gt = N;
-        a.out = b;
-        a.ld_out = N;
-        if (fp32) {
-            NAT_HIP(launch_weight32(gj, N, M, N, wscale, a32, N, s));
-            a.g_src32 = a32;
-            NAT_HIP(launch_sum32(a, partial, s, all_modes(M), true, nullptr,
-                                 prof_slot(ctx, PK_SUM32_RHS, 24.0 * n * n * M)));
-        } else {
-            NAT_HIP(launch_sum64(a, s, prof_slot(ctx, PK_SUM64, 24.0 * n * n * M)));
-        }
-    }
-
-    // a4: GMRES on (I/2 - K) p = b
-    gs.tol = opts->gmres_tol;
-    gs.v32_scale = wscale;
-    if (!fp32)
-        gs.v32 = nullptr;
-    st = gmres_run(ctx, gs, b, N, partial, s,
-                   [&](int32_t j, const ModeList& modes, int32_t* n_split) -> hipError_t {
-                       SumArgs a = base;
-                       a.op = OP_MATVEC;
-                       a.NT = N;
-                       a.t64 = ps.x64;
-                       a.t32 = ps.x32;
-                       a.p_src = gs.V + (size_t)j * n;
-                       a.ld_ps = (int64_t)(mmax + 1) * N;
-                       a.p_src32 = gs.v32;
-                       a.active = gs.active;
-                       a.out = gs.w;
-                       a.ld_out = N;
-                       if (fp32)
-                           return launch_sum32(a, partial, s, modes, false, n_split,
-                                               prof_slot(ctx, PK_SUM32_MATVEC, 37.0 * n * n * modes.n));
-                       *n_split = 0;
-                       return launch_sum64(a, s, prof_slot(ctx, PK_SUM64, 37.0 * n * n * M));
-                   });
-    if (st != NAT_OK)
-        return st;
-    double2* x = p_samples ? reinterpret_cast<double2*>(p_samples) : xin;
-    NAT_HIP(launch_gmres_solution(gs, x, N, s));
-
-    // a5: surface evaluation
-    if (Q > 0) {
-        SumArgs a = base;
-        a.op = OP_EVAL;
-        a.NT = Q;
-        a.t64 = qs.x64;
-        a.t32 = qs.x32;
-        a.g_src = gj;
-        a.ld_gs = N;
-        a.p_src = x;
-        a.ld_ps = N;
-        a.g_tgt = gq;
-        a.ld_gt = Q;
-        a.out = reinterpret_cast<double2*>(p_out);
-        a.ld_out = Q;
-        if (fp32) {
-            NAT_HIP(launch_weight32(gj, N, M, N, -wscale, a32, N, s));
-            NAT_HIP(launch_weight32(x, N, M, N, wscale, gs.v32, N, s));
-            a.g_src32 = a32;
-            a.p_src32 = gs.v32;
-            NAT_HIP(launch_sum32(a, partial, s, all_modes(M), true, nullptr,
-                                 prof_slot(ctx, PK_SUM32_EVAL, 47.0 * q * n * M)));
-        } else {
-            NAT_HIP(launch_sum64(a, s, prof_slot(ctx, PK_SUM64, 47.0 * q * n * M)));
-        }
-    }
-    prof_collect(ctx);
-
-    // reports
-    {
-        // the staging block above is large enough: no reallocation here
-        int32_t* hit = static_cast<int32_t*>(pin);
-        double* hres = reinterpret_cast<double*>(static_cast<char*>(pin) + 8 * ((M * 4 + 7) / 8));
-        NAT_HIP(hipMemcpyAsync(hit, gs.iters, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
-        NAT_HIP(hipMemcpyAsync(hres, gs.resid, sizeof(double) * M, hipMemcpyDeviceToHost, s));
-        NAT_HIP(hipStreamSynchronize(s));
-        bool all_conv = true;
-        for (int32_t m = 0; m < M; ++m) {
-            const bool conv = hres[m] <= opts->gmres_tol;
-            all_conv &= conv;
-            if (report) {
-                report[m].iters = hit[m];
-                report[m].converged = conv ? 1 : 0;
-                report[m].rel_resid = hres[m];
-                report[m].eps = eps;
-                report[m].area = area;
-            }
-        }
-        if (!all_conv)
-            return fail(NAT_E_NOCONV, "nat_mcbem_estimate: GMRES stopped above tolerance");
-    }
-    return NAT_OK;
-}
-
 nat_status nat_bem_assemble(nat_mesh* mesh, double k, int32_t burton_miller, nat_bem_op** out,
                             void* stream)
 {
@@ -1072,57 +773,110 @@ nat_status nat_bem_solve(nat_bem_op* op, const double* v_n, int32_t n_rhs, int32
     const int32_t n = op->n;
     const int32_t M = n_rhs;
     const int32_t ng = layout == NAT_NEUMANN_PER_TRIANGLE ? n : op->mesh->nV;
-    const size_t bytes = carve_size<>({sizeof(int32_t) * 4, sizeof(double2) * (size_t)M * n,
-                                       sizeof(double2) * (size_t)M * n,
-                                       gmres_state_bytes(n, M, max_iter)});
+    const size_t mm1 = (size_t)max_iter + 1;
+    const int32_t nch = gmres_chunks(n);
+
+    // right-hand sides as systems of one instance with equal sizes
+    BatchTables T;
+    T.inst.resize(1);
+    T.inst[0].n = n;
+    T.inst[0].n_modes = M;
+    T.sys.resize(M);
+    for (int32_t r = 0; r < M; ++r) {
+        SysDev& Y = T.sys[r];
+        Y = SysDev{};
+        Y.inst = 0;
+        Y.n = n;
+        Y.nch = nch;
+        Y.off_n = (int64_t)r * n;
+        Y.off_v = (int64_t)r * mm1 * n;
+        Y.off_ch = (int64_t)r * nch;
+        Y.out_n = reinterpret_cast<double2*>(p_out) + (size_t)r * n;
+    }
+    T.max_items = (int64_t)M * nch;
+    const size_t bytes = carve_size<>(
+        {sizeof(int32_t) * 8, sizeof(double2) * (size_t)M * n, sizeof(double2) * (size_t)M * n,
+         sizeof(double2) * (size_t)M * n, sizeof(double2) * (size_t)M * mm1 * n,
+         sizeof(double2) * (size_t)M * max_iter * mm1, sizeof(double) * (size_t)M * max_iter,
+         sizeof(double2) * (size_t)M * max_iter, sizeof(double2) * (size_t)M * mm1,
+         sizeof(double2) * (size_t)M * mm1, sizeof(double) * M, sizeof(double) * M,
+         sizeof(int32_t) * M, sizeof(int32_t) * M, sizeof(double2) * (size_t)M * nch * mm1,
+         sizeof(double2) * (size_t)M * nch * mm1, sizeof(double) * (size_t)M * nch,
+         sizeof(SysDev) * M, sizeof(int2) * (size_t)M * nch});
     void* ws = nullptr;
     st = workspace(ctx, bytes, &ws);
     if (st != NAT_OK)
         return st;
     Carver cv(ws);
-    int32_t* dflag = cv.take<int32_t>(4);
+    int32_t* dcnt = cv.take<int32_t>(8);
     double2* gp = cv.take<double2>((size_t)M * n);
     double2* b = cv.take<double2>((size_t)M * n);
-    GmresState gs{};
-    gs.n = n;
-    gs.n_modes = M;
-    gs.mmax = max_iter;
-    gmres_carve(gs, cv);
-    gs.v32 = nullptr;
-    gs.tol = tol;
+    GmresBatch g{};
+    g.n_sys = M;
+    g.mmax = max_iter;
+    g.tol = tol;
+    g.w = cv.take<double2>((size_t)M * n);
+    g.V = cv.take<double2>((size_t)M * mm1 * n);
+    g.H = cv.take<double2>((size_t)M * max_iter * mm1);
+    g.cs = cv.take<double>((size_t)M * max_iter);
+    g.sn = cv.take<double2>((size_t)M * max_iter);
+    g.gv = cv.take<double2>((size_t)M * mm1);
+    g.htot = cv.take<double2>((size_t)M * mm1);
+    g.beta = cv.take<double>(M);
+    g.resid = cv.take<double>(M);
+    g.iters = cv.take<int32_t>(M);
+    g.active = cv.take<int32_t>(M);
+    g.dp1 = cv.take<double2>((size_t)M * nch * mm1);
+    g.dp2 = cv.take<double2>((size_t)M * nch * mm1);
+    g.normpart = cv.take<double>((size_t)M * nch);
+    T.d_sys = cv.take<SysDev>(M);
+    T.d_items = cv.take<int2>((size_t)M * nch);
+    T.d_nitems = dcnt + 2;
+    T.d_iter = dcnt + 4;
+    g.sys = T.d_sys;
+    g.v32 = nullptr;
+    g.partial = nullptr;
 
     int32_t flags[2] = {0, 0};
-    st = device_checks(ctx, dflag, nullptr, nullptr, 0, 0, v_n, 2 * (int64_t)M * ng, s, flags);
+    st = device_checks(ctx, dcnt, nullptr, nullptr, 0, 0, v_n, 2 * (int64_t)M * ng, s, flags, true);
     if (st != NAT_OK)
         return st;
     if (flags[1])
         return fail(NAT_E_INVALID, "nat_bem_solve: non-finite Neumann data");
+    {
+        void* pin = nullptr;
+        st = pinned(ctx, sizeof(SysDev) * M + 64, &pin);
+        if (st != NAT_OK)
+            return st;
+        std::memcpy(pin, T.sys.data(), sizeof(SysDev) * M);
+        NAT_HIP(hipMemcpyAsync(T.d_sys, pin, sizeof(SysDev) * M, hipMemcpyHostToDevice, s));
+        NAT_HIP(hipStreamSynchronize(s));
+    }
 
-    const double2* g = reinterpret_cast<const double2*>(v_n);
+    const double2* gin = reinterpret_cast<const double2*>(v_n);
     if (layout == NAT_NEUMANN_PER_VERTEX) {
-        NAT_HIP(launch_panel_data(op->mesh->d_T, n, g, ng, M, gp, n, s));
+        NAT_HIP(launch_panel_data(op->mesh->d_T, n, gin, ng, M, gp, n, s));
     } else {
-        NAT_HIP(hipMemcpyAsync(gp, g, sizeof(double2) * (size_t)M * n, hipMemcpyDeviceToDevice, s));
+        NAT_HIP(hipMemcpyAsync(gp, gin, sizeof(double2) * (size_t)M * n, hipMemcpyDeviceToDevice, s));
     }
     NAT_HIP(launch_zgemv(op->d_B, n, gp, n, M, b, n, nullptr, s));
-    st = gmres_run(ctx, gs, b, n, nullptr, s,
-                   [&](int32_t j, const ModeList&, int32_t* n_split) -> hipError_t {
-                       *n_split = 0;
-                       return launch_zgemv(op->d_A, n, gs.V + (size_t)j * n,
-                                           (int64_t)(max_iter + 1) * n, M, gs.w, n, gs.active, s,
-                                           prof_slot(ctx, PK_ZGEMV, 8.0 * n * (double)n * M));
-                   });
+    std::function<hipError_t(int32_t)> mv = [&](int32_t j) -> hipError_t {
+        return launch_zgemv(op->d_A, n, g.V + (size_t)j * n, (int64_t)mm1 * n, M, g.w, n, g.active, s,
+                            prof_slot(ctx, PK_ZGEMV, 8.0 * n * (double)n * M));
+    };
+    st = gmres_drive(ctx, g, T, b, nullptr, mv, false, s);
     if (st != NAT_OK)
         return st;
+    NAT_HIP(launch_gmres_solution(g, s));
+    prof_collect(ctx);
     void* pin = nullptr;
-    st = pinned(ctx, sizeof(double) * M + sizeof(int32_t) * M * 2 + 64, &pin);
+    st = pinned(ctx, (sizeof(double) + sizeof(int32_t)) * M + 64, &pin);
     if (st != NAT_OK)
         return st;
-    NAT_HIP(launch_gmres_solution(gs, reinterpret_cast<double2*>(p_out), n, s));
-    int32_t* hit = static_cast<int32_t*>(pin);
-    double* hres = reinterpret_cast<double*>(static_cast<char*>(pin) + 8 * ((M * 4 + 7) / 8));
-    NAT_HIP(hipMemcpyAsync(hit, gs.iters, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
-    NAT_HIP(hipMemcpyAsync(hres, gs.resid, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+    double* hres = static_cast<double*>(pin);
+    int32_t* hit = reinterpret_cast<int32_t*>(hres + M);
+    NAT_HIP(hipMemcpyAsync(hres, g.resid, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+    NAT_HIP(hipMemcpyAsync(hit, g.iters, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
     NAT_HIP(hipStreamSynchronize(s));
     bool all_conv = true;
     for (int32_t m = 0; m < M; ++m) {

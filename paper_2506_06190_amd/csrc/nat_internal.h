@@ -7,6 +7,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -47,6 +48,10 @@ struct nat_ctx {
     size_t mapped_ints = 0;
     // Gauss-Legendre rules on [0,1] for the dense assembly (device copies)
     double* d_rules = nullptr;
+    // capture stream and the last captured run of GMRES iterations
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<unsigned char> graph_key;
 };
 
 struct nat_mesh {
@@ -96,6 +101,13 @@ void dev_free(nat_ctx* ctx, void* ptr, size_t bytes);
 nat_status workspace(nat_ctx* ctx, size_t bytes, void** ptr);
 nat_status pinned(nat_ctx* ctx, size_t bytes, void** ptr);
 nat_status mapped_words(nat_ctx* ctx, size_t n, int32_t** host, int32_t** dev);
+nat_status set_device(const nat_ctx* ctx);
+bool is_finite(double v);
+// Zero the two flags (when zero_and_read), check query records (flag 0) and
+// values for non-finite entries (flag 1), and read the flags back.
+nat_status device_checks(nat_ctx* ctx, int32_t* dflag, const int32_t* q_tri, const double* q_bary,
+                         int32_t Q, int32_t nT, const double* vals, int64_t n_vals, hipStream_t s,
+                         int32_t* host_flags, bool zero_and_read);
 
 // Carves aligned sub-buffers out of one allocation.
 struct Carver {
@@ -141,25 +153,6 @@ inline void launch_k(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s,
         hipExtLaunchKernelGGL(kernel, grid, block, static_cast<uint32_t>(lds), s, e0, e1, 0, args...);
     else
         hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
-}
-
-// Modes a launch works on: slot s is mode s (identity) or the inline list.
-constexpr int kInlineModes = 64;
-struct ModeList {
-    int32_t n = 0;
-    int32_t identity = 1;
-    int32_t m[kInlineModes];
-};
-__host__ __device__ inline int32_t mode_at(const ModeList& L, int32_t slot)
-{
-    return L.identity ? slot : L.m[slot];
-}
-inline ModeList all_modes(int32_t n)
-{
-    ModeList L;
-    L.n = n;
-    L.identity = 1;
-    return L;
 }
 
 // ---- sampling and surface data (k_sample.hip) ------------------------------
@@ -213,50 +206,130 @@ struct SumArgs {
     int64_t ld_out;
 };
 hipError_t launch_sum64(const SumArgs& a, hipStream_t s, const ProfSlot& ev = ProfSlot());
-// FP32 tiled sum over the modes of `modes`; partial is scratch of
-// sum32_partial_bytes() bytes.  With reduce = false the per-split partial
-// sums are left in `partial` ([split][mode][target] float4 hi/lo) for the
-// GMRES step to combine, and the split count is returned in *n_split_out.
-size_t sum32_partial_bytes(const SumArgs& a);
-hipError_t launch_sum32(const SumArgs& a, void* partial, hipStream_t s, const ModeList& modes,
-                        bool reduce, int32_t* n_split_out, const ProfSlot& ev = ProfSlot());
-// FP32 weighted copies: dst[m][j] = float2(scale * src[m][j])
-hipError_t launch_weight32(const double2* src, int64_t ld_src, int32_t n_modes, int32_t n,
-                           double scale, float2* dst, int64_t ld_dst, hipStream_t s);
+
+// ---- batches of Monte-Carlo problems ---------------------------------------
+// An instance is one mesh with one sample set; a system is one (instance,
+// mode) pair.  Per-system arrays of different lengths are packed back to
+// back; the offsets below locate a system's slice.
+struct InstDev {
+    int32_t n, q, n_modes, sys0;       // samples, queries, modes, first system
+    int32_t nsplit_a, per_split_a;     // source splits of the sums over the samples
+    int32_t nsplit_b, per_split_b;     // ... over the queries
+    float eps2;
+    int32_t pad;
+    double eps, w;
+    const float* s32;                  // [3][n] sample positions, relative to the mesh centre
+    const float* sn32;                 // [3][n] sample normals
+    const float* q32;                  // [3][q] query positions
+};
+
+struct SysDev {
+    int32_t inst, n, q, nch;           // instance, unknowns, queries, Arnoldi row chunks
+    int32_t nsplit_a, nsplit_b;
+    int64_t off_n;                     // [n]-long per-system arrays
+    int64_t off_q;                     // [q]-long per-system arrays
+    int64_t off_v;                     // Krylov basis: (mmax+1) n
+    int64_t off_ch;                    // Arnoldi chunk arrays: nch
+    int64_t off_pa;                    // split partials over the samples: nsplit_a n
+    int64_t off_pb;                    // split partials over the queries: nsplit_b q
+    double k, wscale, eps;             // wavenumber, w/(4 pi), disk radius
+    float k32, kappa32;                // k and k/(2 pi) in FP32
+    double2* out_q;                    // result at the queries (caller row) or null
+    double2* out_n;                    // Stage-A solution (caller row or scratch)
+};
+
+// Up to 8 systems of one instance processed together, and the work items
+// they expand to: tiles of 256 targets x source splits.
+struct GroupDev {
+    int32_t inst, nm, tiles, nsplit;
+    int64_t item0;
+    int32_t sys[8];
+};
+
+struct Sum32Batch {
+    const InstDev* inst;
+    const SysDev* sys;
+    const GroupDev* groups;
+    const int32_t* n_groups;           // device counts, so a captured launch stays valid
+    const int64_t* n_items;
+    const float2* a32;                 // FP32 weighted sources per system: w/(4 pi) g
+    const float2* b32;                 //                                  w/(4 pi) p
+    const int32_t* active;             // per system, or null
+    float4* partial;                   // split partials (hi.re, hi.im, lo.re, lo.im)
+};
+
+// source splits of a sum with n_targets targets over n_sources sources; a
+// function of the instance's own sizes only
+void split_rule(int32_t n_targets, int32_t n_sources, int32_t* nsplit, int32_t* per_split);
+int32_t target_tiles(int32_t n_targets);
+hipError_t launch_sum32_batch(int32_t op, const Sum32Batch& p, int32_t grid, hipStream_t s,
+                              const ProfSlot& ev = ProfSlot());
+// RHS: out_n[off_n + i] = b_i; EVAL: sys.out_q[i] = p(x_i)
+hipError_t launch_reduce32_batch(int32_t op, const Sum32Batch& p, int32_t n_sys, int32_t max_targets,
+                                 const double2* g_tgt, double2* out_n, hipStream_t s,
+                                 const ProfSlot& ev = ProfSlot());
+hipError_t launch_weight32_batch(const SysDev* sys, int32_t n_sys, int32_t max_n,
+                                 const double2* src, double sign, float2* dst, hipStream_t s);
 
 // ---- batched GMRES (k_gmres.hip) ------------------------------------------
-struct GmresState {
-    int32_t n, n_modes, mmax;
-    double2* V;      // [mode][mmax+1][n]
-    double2* H;      // [mode][mmax][mmax+1]  column j, row i at H[(mode*mmax + j)*(mmax+1) + i]
-    double* cs;      // [mode][mmax]
-    double2* sn;     // [mode][mmax]
-    double2* gv;     // [mode][mmax+1]
-    double* beta;    // [mode]
-    double* resid;   // [mode]
-    int32_t* iters;  // [mode]
-    int32_t* active; // [mode]
-    double2* w;      // [mode][n] matvec output
-    float2* v32;     // [mode][n] FP32 copy of v_j scaled by v32_scale (or null)
-    double v32_scale;
+struct GmresBatch {
+    int32_t n_sys, mmax;
+    const SysDev* sys;
+    double2* V;          // [off_v + i n + t]
+    double2* H;          // [sys][mmax][mmax+1]: column j of system s at ((s mmax + j)(mmax+1))
+    double* cs;          // [sys][mmax]
+    double2* sn;         // [sys][mmax]
+    double2* gv;         // [sys][mmax+1]
+    double2* htot;       // [sys][mmax+1] Hessenberg column being built
+    double* beta;        // [sys]
+    double* resid;       // [sys]
+    int32_t* iters;      // [sys]
+    int32_t* active;     // [sys]
+    double2* w;          // [off_n + t] matvec output
+    float2* v32;         // [off_n + t] FP32 copy of the newest basis vector times w/(4 pi), or null
+    double2* dp1;        // [(off_ch + chunk)(mmax+1) + i] partial dots, first CGS pass
+    double2* dp2;        // second pass
+    double* normpart;    // [off_ch + chunk]
+    const float4* partial;     // FP32 matvec split partials, or null (w written by the matvec)
+    const int2* items;         // (system, chunk) work list of the Arnoldi kernels
+    const int32_t* n_items;    // device count
+    int32_t* iter;             // device iteration counter j
+    int32_t* host_active;      // mapped host copy of `active`, or null
+    int32_t* host_progress;    // mapped host word: iterations finished, or null
     double tol;
-    int32_t nch;        // row chunks of the Arnoldi kernels
-    double2* dp1;       // [mode][chunk][mmax+1] partial dots, first CGS pass
-    double2* dp2;       // [mode][chunk][mmax+1] partial dots, second CGS pass
-    double* normpart;   // [mode][chunk]
-    double2* htot;      // [mode][mmax+1] Hessenberg column being built
-    int32_t* host_active;   // mapped host copy of `active` (or null)
-    int32_t* host_progress; // mapped host word: last finished iteration (or null)
 };
-size_t gmres_state_bytes(int32_t n, int32_t n_modes, int32_t mmax);
-void gmres_carve(GmresState& g, Carver& c);
-hipError_t launch_gmres_init(const GmresState& g, const double2* b, int64_t ld_b, hipStream_t s);
-// One Arnoldi step after the matvec of v_j for the systems of `modes`
-// (systems already stopped are skipped).  With `partial` set, w is first
-// formed from the FP32 kernel-sum partials as w = v_j / 2 - sum_splits.
-hipError_t launch_gmres_orth(const GmresState& g, int32_t j, const void* partial, int32_t n_split,
-                             const ModeList& modes, hipStream_t s, const ProfSlot& ev = ProfSlot());
-hipError_t launch_gmres_solution(const GmresState& g, double2* x, int64_t ld_x, hipStream_t s);
+int32_t gmres_chunks(int32_t n);
+hipError_t launch_gmres_init(const GmresBatch& g, const double2* b, hipStream_t s);
+// one Arnoldi step (after the matvec of v_j) for the listed items, j read on
+// the device, then j <- j + 1; `grid` workgroups walk the items
+hipError_t launch_gmres_step(const GmresBatch& g, int32_t grid, hipStream_t s,
+                             const ProfSlot& ev = ProfSlot());
+hipError_t launch_gmres_solution(const GmresBatch& g, hipStream_t s);
+
+// Device tables of a batch and the host copies the GMRES driver refreshes.
+struct BatchTables {
+    std::vector<InstDev> inst;       // host copies (device pointers inside)
+    std::vector<SysDev> sys;
+    InstDev* d_inst = nullptr;
+    SysDev* d_sys = nullptr;
+    // matvec groups of the running systems and the Arnoldi items, refreshed
+    GroupDev* d_groups_mv = nullptr;
+    int32_t* d_ngroups_mv = nullptr;
+    int64_t* d_nitems_mv = nullptr;
+    int2* d_items = nullptr;
+    int32_t* d_nitems = nullptr;
+    int32_t* d_iter = nullptr;
+    int64_t max_items = 0;           // sum of chunks
+};
+// Run GMRES on the batch.  With `mv` the FP32 batched kernel sum is the
+// matvec and runs of kLag iterations are captured once into a graph and
+// replayed (unless graphs are off or kernel timing is on); otherwise
+// eager_mv(j) launches the matvec of iteration j.
+nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double2* b,
+                       Sum32Batch* mv, const std::function<hipError_t(int32_t)>& eager_mv,
+                       bool use_graph, hipStream_t s);
+// Tables for systems of equal size n (the dense solve): n_sys systems,
+// Stage-A layout only.
 
 // ---- dense BEM (k_bem.hip) -------------------------------------------------
 struct BemGeom {

@@ -1,0 +1,739 @@
+// Host drivers of the Monte-Carlo estimate for a batch of instances and of
+// the GMRES loop shared by every solve.
+//
+// A batch holds instances (mesh + sample set) and systems (instance, mode).
+// Per-system arrays are packed back to back with the offsets of SysDev.  The
+// steps of Section 4.1.1 run for the whole batch at once: samples and
+// surface data per instance, then one kernel-sum launch per stage for all
+// systems, GMRES for all systems in lockstep, and the surface evaluation.
+#include <cmath>
+#include <cstring>
+
+#include "nat_internal.h"
+
+namespace nat {
+namespace {
+
+constexpr double kInv4Pi = 0.07957747154594767;
+constexpr double kTwoPi = 6.283185307179586;
+// iterations per captured run; also how far the host may run ahead of the
+// device before it waits to refresh the running-system lists
+constexpr int32_t kLag = 4;
+constexpr int32_t kMaxGrid = 1024;
+
+inline void cpu_relax() { __builtin_ia32_pause(); }
+
+struct Staging {
+    GroupDev* groups;
+    int2* items;
+    int32_t* c32;  // [0] Arnoldi items, [1] matvec groups
+    int64_t* c64;  // [0] matvec work items
+};
+
+struct ListStats {
+    int32_t running = 0;
+    int64_t mv_items = 0;
+    double mv_pairs = 0.0;  // target-source pairs of one matvec
+};
+
+// Lists of the running systems (flag != 0) into staging, then stream-ordered
+// copies into the device tables.
+nat_status refresh_lists(const BatchTables& T, const volatile int32_t* flag, bool with_mv,
+                         const Staging& st, hipStream_t s, ListStats* out)
+{
+    ListStats ls;
+    int32_t n_items = 0, n_groups = 0;
+    const int32_t S = static_cast<int32_t>(T.sys.size());
+    for (int32_t q = 0; q < S; ++q) {
+        if (!flag[q])
+            continue;
+        ++ls.running;
+        ls.mv_pairs += (double)T.sys[q].n * (double)T.sys[q].n;
+        for (int32_t c = 0; c < T.sys[q].nch; ++c)
+            st.items[n_items++] = make_int2(q, c);
+    }
+    if (with_mv) {
+        for (const InstDev& I : T.inst) {
+            GroupDev G{};
+            G.nm = 0;
+            for (int32_t m = 0; m < I.n_modes; ++m) {
+                const int32_t q = I.sys0 + m;
+                if (!flag[q])
+                    continue;
+                if (G.nm == 0) {
+                    G.inst = T.sys[q].inst;
+                    G.tiles = target_tiles(I.n);
+                    G.nsplit = I.nsplit_a;
+                    G.item0 = ls.mv_items;
+                }
+                G.sys[G.nm++] = q;
+                if (G.nm == 8) {
+                    st.groups[n_groups++] = G;
+                    ls.mv_items += (int64_t)G.tiles * G.nsplit;
+                    G.nm = 0;
+                }
+            }
+            if (G.nm > 0) {
+                st.groups[n_groups++] = G;
+                ls.mv_items += (int64_t)G.tiles * G.nsplit;
+            }
+        }
+    }
+    st.c32[0] = n_items;
+    st.c32[1] = n_groups;
+    st.c64[0] = ls.mv_items;
+    if (ls.running > 0) {
+        NAT_HIP(hipMemcpyAsync(T.d_items, st.items, sizeof(int2) * n_items, hipMemcpyHostToDevice, s));
+        NAT_HIP(hipMemcpyAsync(T.d_nitems, st.c32, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        if (with_mv) {
+            NAT_HIP(hipMemcpyAsync(T.d_groups_mv, st.groups, sizeof(GroupDev) * n_groups,
+                                   hipMemcpyHostToDevice, s));
+            NAT_HIP(hipMemcpyAsync(T.d_ngroups_mv, st.c32 + 1, sizeof(int32_t), hipMemcpyHostToDevice, s));
+            NAT_HIP(hipMemcpyAsync(T.d_nitems_mv, st.c64, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        }
+    }
+    *out = ls;
+    return NAT_OK;
+}
+
+template <class T>
+void append_bytes(std::vector<unsigned char>& v, const T& x)
+{
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(&x);
+    v.insert(v.end(), p, p + sizeof(T));
+}
+
+// The run of kLag iterations as an executable graph, captured once per
+// distinct set of launch arguments and kept by the context.
+nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch& mv, int32_t grid_g,
+                        int32_t grid_mv, hipGraphExec_t* exec)
+{
+    std::vector<unsigned char> key;
+    append_bytes(key, g);
+    append_bytes(key, mv);
+    append_bytes(key, grid_g);
+    append_bytes(key, grid_mv);
+    if (ctx->graph_exec && key == ctx->graph_key) {
+        *exec = ctx->graph_exec;
+        return NAT_OK;
+    }
+    if (ctx->graph_exec) {
+        (void)hipGraphExecDestroy(ctx->graph_exec);
+        ctx->graph_exec = nullptr;
+        ctx->graph_key.clear();
+    }
+    if (!ctx->capture_stream)
+        NAT_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = ctx->capture_stream;
+    NAT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int32_t r = 0; r < kLag && e == hipSuccess; ++r) {
+        e = launch_sum32_batch(OP_MATVEC, mv, grid_mv, cs);
+        if (e == hipSuccess)
+            e = launch_gmres_step(g, grid_g, cs);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return hip_fail(e != hipSuccess ? e : e2, "graph capture of the GMRES iterations");
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGraphInstantiate");
+    ctx->graph_exec = ex;
+    ctx->graph_key = key;
+    *exec = ex;
+    return NAT_OK;
+}
+
+}  // namespace
+
+nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double2* b,
+                       Sum32Batch* mv, const std::function<hipError_t(int32_t)>& eager_mv,
+                       bool use_graph, hipStream_t s)
+{
+    const int32_t S = g.n_sys;
+    int32_t* hw = nullptr;
+    int32_t* dw = nullptr;
+    nat_status st = mapped_words(ctx, 16 + (size_t)S, &hw, &dw);
+    if (st != NAT_OK)
+        return st;
+    volatile int32_t* hprog = hw;
+    volatile int32_t* hflag = hw + 16;
+    // every earlier device write to these words has landed: the previous
+    // solve of this context ended with a stream synchronisation
+    *hprog = 0;
+    for (int32_t q = 0; q < S; ++q)
+        hflag[q] = 1;
+    g.host_progress = dw;
+    g.host_active = dw + 16;
+    g.items = T.d_items;
+    g.n_items = T.d_nitems;
+    g.iter = T.d_iter;
+    if (mv) {
+        mv->groups = T.d_groups_mv;
+        mv->n_groups = T.d_ngroups_mv;
+        mv->n_items = T.d_nitems_mv;
+        mv->active = g.active;
+    }
+
+    // two pinned staging areas for the lists, used alternately
+    const size_t per = ((sizeof(GroupDev) * (size_t)S + sizeof(int2) * (size_t)T.max_items + 255) & ~size_t(255)) + 256;
+    void* pin = nullptr;
+    st = pinned(ctx, 2 * per, &pin);
+    if (st != NAT_OK)
+        return st;
+    Staging stg[2];
+    for (int k = 0; k < 2; ++k) {
+        char* base = static_cast<char*>(pin) + k * per;
+        stg[k].c32 = reinterpret_cast<int32_t*>(base);
+        stg[k].c64 = reinterpret_cast<int64_t*>(base + 64);
+        stg[k].groups = reinterpret_cast<GroupDev*>(base + 128);
+        stg[k].items = reinterpret_cast<int2*>(base + 128 + sizeof(GroupDev) * (size_t)S);
+    }
+    ListStats ls;
+    st = refresh_lists(T, hflag, mv != nullptr, stg[0], s, &ls);
+    if (st != NAT_OK)
+        return st;
+    NAT_HIP(launch_gmres_init(g, b, s));
+
+    const int32_t grid_g = static_cast<int32_t>(T.max_items < kMaxGrid ? (T.max_items > 0 ? T.max_items : 1) : kMaxGrid);
+    const int32_t grid_mv = static_cast<int32_t>(ls.mv_items < kMaxGrid ? (ls.mv_items > 0 ? ls.mv_items : 1) : kMaxGrid);
+    hipGraphExec_t exec = nullptr;
+    if (use_graph && mv && !ctx->prof) {
+        st = captured_run(ctx, g, *mv, grid_g, grid_mv, &exec);
+        if (st != NAT_OK)
+            exec = nullptr;  // fall back to direct launches
+    }
+    int32_t launched = 0;
+    int buf = 0;
+    while (launched < g.mmax) {
+        if (exec) {
+            NAT_HIP(hipGraphLaunch(exec, s));
+            launched += kLag;
+        } else {
+            for (int32_t r = 0; r < kLag && launched < g.mmax; ++r) {
+                if (mv)
+                    NAT_HIP(launch_sum32_batch(OP_MATVEC, *mv, grid_mv, s,
+                                               prof_slot(ctx, PK_SUM32_MATVEC, 37.0 * ls.mv_pairs)));
+                else
+                    NAT_HIP(eager_mv(launched));
+                NAT_HIP(launch_gmres_step(g, grid_g, s, prof_slot(ctx, PK_GMRES_ORTH, 0.0)));
+                ++launched;
+            }
+        }
+        if (launched >= g.mmax)
+            break;
+        // wait until the device has finished all but the run just queued
+        const int32_t target = launched - kLag;
+        int64_t spins = 0;
+        while (*hprog < target) {
+            if (++spins > (int64_t(1) << 26)) {
+                NAT_HIP(hipStreamSynchronize(s));
+                break;
+            }
+            cpu_relax();
+        }
+        buf ^= 1;
+        st = refresh_lists(T, hflag, mv != nullptr, stg[buf], s, &ls);
+        if (st != NAT_OK)
+            return st;
+        if (ls.running == 0)
+            break;
+    }
+    return NAT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Monte-Carlo estimate of a batch of jobs
+// ---------------------------------------------------------------------------
+struct McJob {
+    nat_mesh* mesh;
+    const double* v_n;
+    int32_t M, Q, N;
+    const double* k;
+    const int32_t* q_tri;
+    const double* q_bary;
+    uint64_t seed;
+    double* p_out;
+    double* p_samples;
+};
+
+nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts* opts,
+                  nat_solve_report* report, hipStream_t s)
+{
+    if (!opts)
+        return fail(NAT_E_INVALID, "Monte-Carlo estimate: opts is NULL");
+    if (opts->precision != NAT_PREC_FP64 && opts->precision != NAT_PREC_FP32)
+        return fail(NAT_E_INVALID, "Monte-Carlo estimate: precision %d", opts->precision);
+    if (opts->layout != NAT_NEUMANN_PER_VERTEX && opts->layout != NAT_NEUMANN_PER_TRIANGLE)
+        return fail(NAT_E_INVALID, "Monte-Carlo estimate: layout %d", opts->layout);
+    if (!(opts->eps_scale > 0.0) || !is_finite(opts->eps_scale) || !(opts->gmres_tol > 0.0) ||
+        opts->gmres_max_iter < 1 || opts->gmres_max_iter > 1000 || (opts->flags & ~NAT_MC_NO_GRAPH))
+        return fail(NAT_E_INVALID, "Monte-Carlo estimate: bad solver options");
+    int64_t S64 = 0;
+    for (int32_t i = 0; i < nj; ++i) {
+        const McJob& J = jobs[i];
+        if (!J.mesh || !J.v_n || !J.k)
+            return fail(NAT_E_INVALID, "job %d: NULL argument", i);
+        if (J.mesh->ctx != ctx)
+            return fail(NAT_E_INVALID, "job %d: mesh belongs to another context", i);
+        if (J.M < 1 || J.M > 4096)
+            return fail(NAT_E_INVALID, "job %d: n_modes = %d", i, J.M);
+        if (J.N < 2 || J.N > (1 << 24))
+            return fail(NAT_E_INVALID, "job %d: n_samples = %d", i, J.N);
+        if (J.Q < 0 || J.Q > (1 << 26) || (J.Q > 0 && (!J.q_tri || !J.q_bary || !J.p_out)))
+            return fail(NAT_E_INVALID, "job %d: bad queries (Q = %d)", i, J.Q);
+        for (int32_t m = 0; m < J.M; ++m)
+            if (!(J.k[m] > 0.0) || !is_finite(J.k[m]))
+                return fail(NAT_E_INVALID, "job %d: k[%d] = %g", i, m, J.k[m]);
+        S64 += J.M;
+    }
+    if (nj < 1 || S64 > (1 << 20))
+        return fail(NAT_E_INVALID, "Monte-Carlo estimate: %d jobs with %lld systems", nj, (long long)S64);
+    nat_status st = set_device(ctx);
+    if (st != NAT_OK)
+        return st;
+    const int32_t S = static_cast<int32_t>(S64);
+    const bool fp32 = opts->precision == NAT_PREC_FP32;
+    const int32_t mmax = opts->gmres_max_iter;
+    const size_t mm1 = (size_t)mmax + 1;
+
+    // ---- layout ----------------------------------------------------------
+    BatchTables T;
+    T.inst.resize(nj);
+    T.sys.resize(S);
+    size_t inst_n = 0, inst_q = 0;       // sums of n and q over instances
+    int64_t sum_n = 0, sum_q = 0, sum_v = 0, sum_ch = 0, sum_pa = 0, sum_pb = 0;
+    int32_t max_n = 0, max_q = 0;
+    for (int32_t i = 0, q = 0; i < nj; ++i) {
+        const McJob& J = jobs[i];
+        InstDev& I = T.inst[i];
+        I.n = J.N;
+        I.q = J.Q;
+        I.n_modes = J.M;
+        I.sys0 = q;
+        split_rule(J.N, J.N, &I.nsplit_a, &I.per_split_a);
+        if (J.Q > 0)
+            split_rule(J.Q, J.N, &I.nsplit_b, &I.per_split_b);
+        const double area = J.mesh->area_total;
+        I.w = area / static_cast<double>(J.N);
+        I.eps = opts->eps_scale * std::sqrt(area / (M_PI * static_cast<double>(J.N)));
+        I.eps2 = static_cast<float>(I.eps * I.eps);
+        inst_n += J.N;
+        inst_q += J.Q;
+        max_n = J.N > max_n ? J.N : max_n;
+        max_q = J.Q > max_q ? J.Q : max_q;
+        for (int32_t m = 0; m < J.M; ++m, ++q) {
+            SysDev& Y = T.sys[q];
+            Y.inst = i;
+            Y.n = J.N;
+            Y.q = J.Q;
+            Y.nch = gmres_chunks(J.N);
+            Y.nsplit_a = I.nsplit_a;
+            Y.nsplit_b = J.Q > 0 ? I.nsplit_b : 0;
+            Y.off_n = sum_n;
+            Y.off_q = sum_q;
+            Y.off_v = sum_v;
+            Y.off_ch = sum_ch;
+            Y.off_pa = sum_pa;
+            Y.off_pb = sum_pb;
+            Y.k = J.k[m];
+            Y.k32 = static_cast<float>(J.k[m]);
+            Y.kappa32 = static_cast<float>(J.k[m] / kTwoPi);
+            Y.wscale = I.w * kInv4Pi;
+            Y.eps = I.eps;
+            sum_n += J.N;
+            sum_q += J.Q;
+            sum_v += (int64_t)mm1 * J.N;
+            sum_ch += Y.nch;
+            sum_pa += (int64_t)Y.nsplit_a * J.N;
+            sum_pb += (int64_t)Y.nsplit_b * J.Q;
+        }
+    }
+    T.max_items = sum_ch;
+    const int64_t n_part = sum_pa > sum_pb ? sum_pa : sum_pb;
+    const size_t bytes = carve_size<>(
+        {sizeof(int32_t) * 8, sizeof(int32_t) * inst_n, sizeof(double) * 2 * inst_n,
+         sizeof(double) * 3 * inst_n, sizeof(double) * 3 * inst_n, sizeof(float) * 3 * inst_n,
+         sizeof(float) * 3 * inst_n, sizeof(double) * 3 * inst_q, sizeof(float) * 3 * inst_q,
+         sizeof(double2) * sum_n, sizeof(double2) * sum_q, sizeof(double2) * sum_n,
+         sizeof(double2) * sum_n, sizeof(float2) * sum_n, sizeof(float2) * sum_n,
+         sizeof(double2) * sum_n, sizeof(double2) * sum_v, sizeof(double2) * S * mmax * mm1,
+         sizeof(double) * S * mmax, sizeof(double2) * S * mmax, sizeof(double2) * S * mm1,
+         sizeof(double2) * S * mm1, sizeof(double) * S, sizeof(double) * S, sizeof(int32_t) * S,
+         sizeof(int32_t) * S, sizeof(double2) * sum_ch * mm1, sizeof(double2) * sum_ch * mm1,
+         sizeof(double) * sum_ch, sizeof(float4) * n_part, sizeof(InstDev) * nj,
+         sizeof(SysDev) * S, sizeof(GroupDev) * S, sizeof(GroupDev) * S, sizeof(GroupDev) * S,
+         sizeof(int2) * sum_ch, sizeof(double) * S, sizeof(int64_t) * 8});
+    void* ws = nullptr;
+    st = workspace(ctx, bytes, &ws);
+    if (st != NAT_OK)
+        return st;
+    Carver cv(ws);
+    int32_t* dcnt = cv.take<int32_t>(8);  // flags [0,1], n_items, n_groups_mv, iter, n_groups rhs/eval
+    int32_t* tri_all = cv.take<int32_t>(inst_n);
+    double* bary_all = cv.take<double>(2 * inst_n);
+    double* x64_all = cv.take<double>(3 * inst_n);
+    double* n64_all = cv.take<double>(3 * inst_n);
+    float* x32_all = cv.take<float>(3 * inst_n);
+    float* n32_all = cv.take<float>(3 * inst_n);
+    double* q64_all = cv.take<double>(3 * inst_q);
+    float* q32_all = cv.take<float>(3 * inst_q);
+    double2* gj = cv.take<double2>(sum_n);
+    double2* gq = cv.take<double2>(sum_q);
+    double2* bvec = cv.take<double2>(sum_n);
+    double2* xsol = cv.take<double2>(sum_n);
+    float2* a32 = cv.take<float2>(sum_n);
+    float2* v32 = cv.take<float2>(sum_n);
+    GmresBatch g{};
+    g.n_sys = S;
+    g.mmax = mmax;
+    g.tol = opts->gmres_tol;
+    g.w = cv.take<double2>(sum_n);
+    g.V = cv.take<double2>(sum_v);
+    g.H = cv.take<double2>((size_t)S * mmax * mm1);
+    g.cs = cv.take<double>((size_t)S * mmax);
+    g.sn = cv.take<double2>((size_t)S * mmax);
+    g.gv = cv.take<double2>((size_t)S * mm1);
+    g.htot = cv.take<double2>((size_t)S * mm1);
+    g.beta = cv.take<double>(S);
+    g.resid = cv.take<double>(S);
+    g.iters = cv.take<int32_t>(S);
+    g.active = cv.take<int32_t>(S);
+    g.dp1 = cv.take<double2>((size_t)sum_ch * mm1);
+    g.dp2 = cv.take<double2>((size_t)sum_ch * mm1);
+    g.normpart = cv.take<double>(sum_ch);
+    float4* partial = cv.take<float4>(n_part);
+    T.d_inst = cv.take<InstDev>(nj);
+    T.d_sys = cv.take<SysDev>(S);
+    GroupDev* d_groups_rhs = cv.take<GroupDev>(S);
+    GroupDev* d_groups_eval = cv.take<GroupDev>(S);
+    T.d_groups_mv = cv.take<GroupDev>(S);
+    T.d_items = cv.take<int2>(sum_ch);
+    double* dk = cv.take<double>(S);
+    int64_t* dcnt64 = cv.take<int64_t>(8);  // items: [0] rhs, [1] eval, [2] matvec
+    T.d_nitems = dcnt + 2;
+    T.d_ngroups_mv = dcnt + 3;
+    T.d_iter = dcnt + 4;
+    T.d_nitems_mv = dcnt64 + 2;
+    g.sys = T.d_sys;
+    g.v32 = fp32 ? v32 : nullptr;
+    g.partial = fp32 ? partial : nullptr;
+
+    // per-instance streams and the device pointers of the tables
+    {
+        size_t on = 0, oq = 0;
+        for (int32_t i = 0; i < nj; ++i) {
+            InstDev& I = T.inst[i];
+            I.s32 = x32_all + 3 * on;
+            I.sn32 = n32_all + 3 * on;
+            I.q32 = q32_all + 3 * oq;
+            on += I.n;
+            oq += I.q;
+        }
+        for (int32_t q = 0; q < S; ++q) {
+            SysDev& Y = T.sys[q];
+            const McJob& J = jobs[Y.inst];
+            const int32_t m = q - T.inst[Y.inst].sys0;
+            Y.out_q = J.Q > 0 ? reinterpret_cast<double2*>(J.p_out) + (size_t)m * J.Q : nullptr;
+            Y.out_n = xsol + Y.off_n;
+        }
+    }
+
+    // ---- validation of the device inputs ------------------------------------
+    {
+        NAT_HIP(hipMemsetAsync(dcnt, 0, 2 * sizeof(int32_t), s));
+        for (int32_t i = 0; i < nj; ++i) {
+            const McJob& J = jobs[i];
+            const int32_t ng = opts->layout == NAT_NEUMANN_PER_TRIANGLE ? J.mesh->nT : J.mesh->nV;
+            int32_t unused[2];
+            st = device_checks(ctx, dcnt, J.q_tri, J.q_bary, J.Q, J.mesh->nT, J.v_n,
+                               2 * (int64_t)J.M * ng, s, unused, false);
+            if (st != NAT_OK)
+                return st;
+        }
+        void* pin = nullptr;
+        st = pinned(ctx, 64, &pin);
+        if (st != NAT_OK)
+            return st;
+        NAT_HIP(hipMemcpyAsync(pin, dcnt, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        NAT_HIP(hipStreamSynchronize(s));
+        int32_t flags[2];
+        std::memcpy(flags, pin, sizeof(flags));
+        if (flags[0])
+            return fail(NAT_E_INVALID, "Monte-Carlo estimate: query record out of range");
+        if (flags[1])
+            return fail(NAT_E_INVALID, "Monte-Carlo estimate: non-finite Neumann data");
+    }
+
+    // ---- tables and per-mode constants --------------------------------------
+    // all-systems groups for the right-hand side (targets = samples) and the
+    // evaluation (targets = queries)
+    std::vector<GroupDev> grhs, geval;
+    int64_t items_rhs = 0, items_eval = 0;
+    for (const InstDev& I : T.inst) {
+        for (int32_t m0 = 0; m0 < I.n_modes; m0 += 8) {
+            GroupDev G{};
+            G.inst = T.sys[I.sys0].inst;
+            G.nm = I.n_modes - m0 < 8 ? I.n_modes - m0 : 8;
+            for (int32_t c = 0; c < G.nm; ++c)
+                G.sys[c] = I.sys0 + m0 + c;
+            G.tiles = target_tiles(I.n);
+            G.nsplit = I.nsplit_a;
+            G.item0 = items_rhs;
+            items_rhs += (int64_t)G.tiles * G.nsplit;
+            grhs.push_back(G);
+            if (I.q > 0) {
+                G.tiles = target_tiles(I.q);
+                G.nsplit = I.nsplit_b;
+                G.item0 = items_eval;
+                items_eval += (int64_t)G.tiles * G.nsplit;
+                geval.push_back(G);
+            }
+        }
+    }
+    {
+        const size_t bI = sizeof(InstDev) * nj, bS = sizeof(SysDev) * S;
+        const size_t bG1 = sizeof(GroupDev) * grhs.size(), bG2 = sizeof(GroupDev) * geval.size();
+        void* pin = nullptr;
+        st = pinned(ctx, bI + bS + bG1 + bG2 + sizeof(double) * S + 256, &pin);
+        if (st != NAT_OK)
+            return st;
+        char* p = static_cast<char*>(pin);
+        std::memcpy(p, T.inst.data(), bI);
+        std::memcpy(p + bI, T.sys.data(), bS);
+        std::memcpy(p + bI + bS, grhs.data(), bG1);
+        std::memcpy(p + bI + bS + bG1, geval.data(), bG2);
+        double* hk = reinterpret_cast<double*>(p + bI + bS + bG1 + bG2);
+        for (int32_t q = 0; q < S; ++q)
+            hk[q] = T.sys[q].k;
+        int64_t* hc = reinterpret_cast<int64_t*>(p + bI + bS + bG1 + bG2 + sizeof(double) * S);
+        int32_t* hc32 = reinterpret_cast<int32_t*>(hc + 2);
+        hc[0] = items_rhs;
+        hc[1] = items_eval;
+        hc32[0] = static_cast<int32_t>(grhs.size());
+        hc32[1] = static_cast<int32_t>(geval.size());
+        NAT_HIP(hipMemcpyAsync(T.d_inst, p, bI, hipMemcpyHostToDevice, s));
+        NAT_HIP(hipMemcpyAsync(T.d_sys, p + bI, bS, hipMemcpyHostToDevice, s));
+        NAT_HIP(hipMemcpyAsync(d_groups_rhs, p + bI + bS, bG1, hipMemcpyHostToDevice, s));
+        if (bG2)
+            NAT_HIP(hipMemcpyAsync(d_groups_eval, p + bI + bS + bG1, bG2, hipMemcpyHostToDevice, s));
+        NAT_HIP(hipMemcpyAsync(dk, hk, sizeof(double) * S, hipMemcpyHostToDevice, s));
+        NAT_HIP(hipMemcpyAsync(dcnt64, hc, 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        NAT_HIP(hipMemcpyAsync(dcnt + 5, hc32, 2 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        // the staging above is read by the copies; the GMRES driver reuses
+        // this pinned block, so wait for them
+        NAT_HIP(hipStreamSynchronize(s));
+    }
+
+    // ---- samples, points, Neumann data (Section 4.1.1) -----------------------
+    {
+        size_t on = 0, oq = 0;
+        for (int32_t i = 0; i < nj; ++i) {
+            const McJob& J = jobs[i];
+            const InstDev& I = T.inst[i];
+            const int32_t ng = opts->layout == NAT_NEUMANN_PER_TRIANGLE ? J.mesh->nT : J.mesh->nV;
+            int32_t* tri = tri_all + on;
+            double* bary = bary_all + 2 * on;
+            PointStreams ps{x64_all + 3 * on, n64_all + 3 * on, x32_all + 3 * on, n32_all + 3 * on};
+            PointStreams qs{q64_all + 3 * oq, nullptr, q32_all + 3 * oq, nullptr};
+            const SysDev& Y0 = T.sys[I.sys0];
+            NAT_HIP(launch_samples(J.mesh, J.N, J.seed, tri, bary, s));
+            NAT_HIP(launch_points(J.mesh, J.N, tri, bary, ps, s));
+            NAT_HIP(launch_points(J.mesh, J.Q, J.q_tri, J.q_bary, qs, s));
+            NAT_HIP(launch_neumann(J.mesh, opts->layout, reinterpret_cast<const double2*>(J.v_n), ng,
+                                   J.M, J.N, tri, bary, gj + Y0.off_n, s));
+            NAT_HIP(launch_neumann(J.mesh, opts->layout, reinterpret_cast<const double2*>(J.v_n), ng,
+                                   J.M, J.Q, J.q_tri, J.q_bary, gq + Y0.off_q, s));
+            on += J.N;
+            oq += J.Q;
+        }
+    }
+
+    Sum32Batch sb{};
+    sb.inst = T.d_inst;
+    sb.sys = T.d_sys;
+    sb.partial = partial;
+    // per-instance arguments of the plain FP64 sums
+    auto plain_args = [&](int32_t i, int32_t op) {
+        const InstDev& I = T.inst[i];
+        const SysDev& Y0 = T.sys[I.sys0];
+        size_t on = 0, oq = 0;
+        for (int32_t t = 0; t < i; ++t) {
+            on += T.inst[t].n;
+            oq += T.inst[t].q;
+        }
+        SumArgs a{};
+        a.op = op;
+        a.n_modes = I.n_modes;
+        a.NS = I.n;
+        a.s64 = x64_all + 3 * on;
+        a.sn64 = n64_all + 3 * on;
+        a.k = dk + I.sys0;
+        a.w = I.w;
+        a.eps = I.eps;
+        if (op == OP_EVAL) {
+            a.NT = I.q;
+            a.t64 = q64_all + 3 * oq;
+            a.g_tgt = gq + Y0.off_q;
+            a.ld_gt = I.q;
+            a.out = Y0.out_q;
+            a.ld_out = I.q;
+        } else {
+            a.NT = I.n;
+            a.t64 = a.s64;
+            a.g_tgt = gj + Y0.off_n;
+            a.ld_gt = I.n;
+        }
+        a.g_src = gj + Y0.off_n;
+        a.ld_gs = I.n;
+        return a;
+    };
+
+    // ---- right-hand side (eq. bem_linear_system, Section 4.2 disk term) ------
+    double pairs_rhs = 0.0, pairs_eval = 0.0;
+    for (const SysDev& Y : T.sys) {
+        pairs_rhs += (double)Y.n * Y.n;
+        pairs_eval += (double)Y.q * Y.n;
+    }
+    if (fp32) {
+        NAT_HIP(launch_weight32_batch(T.d_sys, S, max_n, gj, 1.0, a32, s));
+        sb.groups = d_groups_rhs;
+        sb.n_groups = dcnt + 5;
+        sb.n_items = dcnt64 + 0;
+        sb.a32 = a32;
+        const ProfSlot ev = prof_slot(ctx, PK_SUM32_RHS, 24.0 * pairs_rhs);
+        const int32_t grid = static_cast<int32_t>(items_rhs < kMaxGrid * 4 ? items_rhs : kMaxGrid * 4);
+        NAT_HIP(launch_sum32_batch(OP_RHS, sb, grid, s, ProfSlot{ev.start, nullptr}));
+        NAT_HIP(launch_reduce32_batch(OP_RHS, sb, S, max_n, gj, bvec, s, ProfSlot{nullptr, ev.stop}));
+    } else {
+        for (int32_t i = 0; i < nj; ++i) {
+            SumArgs a = plain_args(i, OP_RHS);
+            a.out = bvec + T.sys[T.inst[i].sys0].off_n;
+            a.ld_out = T.inst[i].n;
+            NAT_HIP(launch_sum64(a, s, prof_slot(ctx, PK_SUM64, 24.0 * T.inst[i].n * (double)T.inst[i].n * T.inst[i].n_modes)));
+        }
+    }
+
+    // ---- GMRES on (I/2 - K) p = b ---------------------------------------------
+    std::function<hipError_t(int32_t)> eager = [&](int32_t j) -> hipError_t {
+        for (int32_t i = 0; i < nj; ++i) {
+            const InstDev& I = T.inst[i];
+            const SysDev& Y0 = T.sys[I.sys0];
+            SumArgs a = plain_args(i, OP_MATVEC);
+            a.p_src = g.V + Y0.off_v + (size_t)j * I.n;
+            a.ld_ps = (int64_t)mm1 * I.n;
+            a.active = g.active + I.sys0;
+            a.out = g.w + Y0.off_n;
+            a.ld_out = I.n;
+            hipError_t e = launch_sum64(a, s, prof_slot(ctx, PK_SUM64, 37.0 * I.n * (double)I.n * I.n_modes));
+            if (e != hipSuccess)
+                return e;
+        }
+        return hipSuccess;
+    };
+    sb.b32 = v32;
+    st = gmres_drive(ctx, g, T, bvec, fp32 ? &sb : nullptr, eager,
+                     !(opts->flags & NAT_MC_NO_GRAPH), s);
+    if (st != NAT_OK)
+        return st;
+    NAT_HIP(launch_gmres_solution(g, s));
+
+    // ---- surface evaluation (eq. BIE at the queries, Section 4.2) --------------
+    if (max_q > 0) {
+        if (fp32) {
+            NAT_HIP(launch_weight32_batch(T.d_sys, S, max_n, gj, -1.0, a32, s));
+            NAT_HIP(launch_weight32_batch(T.d_sys, S, max_n, xsol, 1.0, v32, s));
+            Sum32Batch se = sb;
+            se.groups = d_groups_eval;
+            se.n_groups = dcnt + 6;
+            se.n_items = dcnt64 + 1;
+            se.active = nullptr;
+            se.a32 = a32;
+            se.b32 = v32;
+            const ProfSlot ev = prof_slot(ctx, PK_SUM32_EVAL, 47.0 * pairs_eval);
+            const int32_t grid = static_cast<int32_t>(items_eval < kMaxGrid * 4 ? items_eval : kMaxGrid * 4);
+            NAT_HIP(launch_sum32_batch(OP_EVAL, se, grid, s, ProfSlot{ev.start, nullptr}));
+            NAT_HIP(launch_reduce32_batch(OP_EVAL, se, S, max_q, gq, nullptr, s, ProfSlot{nullptr, ev.stop}));
+        } else {
+            for (int32_t i = 0; i < nj; ++i) {
+                if (T.inst[i].q == 0)
+                    continue;
+                SumArgs a = plain_args(i, OP_EVAL);
+                a.p_src = xsol + T.sys[T.inst[i].sys0].off_n;
+                a.ld_ps = T.inst[i].n;
+                NAT_HIP(launch_sum64(a, s, prof_slot(ctx, PK_SUM64, 47.0 * T.inst[i].q * (double)T.inst[i].n * T.inst[i].n_modes)));
+            }
+        }
+    }
+    for (int32_t i = 0; i < nj; ++i) {
+        if (!jobs[i].p_samples)
+            continue;
+        const SysDev& Y0 = T.sys[T.inst[i].sys0];
+        NAT_HIP(hipMemcpyAsync(jobs[i].p_samples, xsol + Y0.off_n,
+                               sizeof(double2) * (size_t)jobs[i].M * jobs[i].N, hipMemcpyDeviceToDevice, s));
+    }
+    prof_collect(ctx);
+
+    // ---- reports ----------------------------------------------------------
+    void* pin = nullptr;
+    st = pinned(ctx, (sizeof(int32_t) + sizeof(double)) * (size_t)S + 64, &pin);
+    if (st != NAT_OK)
+        return st;
+    double* hres = static_cast<double*>(pin);
+    int32_t* hit = reinterpret_cast<int32_t*>(hres + S);
+    NAT_HIP(hipMemcpyAsync(hres, g.resid, sizeof(double) * S, hipMemcpyDeviceToHost, s));
+    NAT_HIP(hipMemcpyAsync(hit, g.iters, sizeof(int32_t) * S, hipMemcpyDeviceToHost, s));
+    NAT_HIP(hipStreamSynchronize(s));
+    bool all_conv = true;
+    for (int32_t q = 0; q < S; ++q) {
+        const bool conv = hres[q] <= opts->gmres_tol;
+        all_conv &= conv;
+        if (report) {
+            report[q].iters = hit[q];
+            report[q].converged = conv ? 1 : 0;
+            report[q].rel_resid = hres[q];
+            report[q].eps = T.sys[q].eps;
+            report[q].area = jobs[T.sys[q].inst].mesh->area_total;
+        }
+    }
+    if (!all_conv)
+        return fail(NAT_E_NOCONV, "Monte-Carlo estimate: GMRES stopped above tolerance");
+    return NAT_OK;
+}
+
+}  // namespace nat
+
+extern "C" {
+
+nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes, const double* k,
+                              const int32_t* q_tri, const double* q_bary, int32_t Q, int32_t N,
+                              uint64_t seed, const nat_mc_opts* opts, double* p_out,
+                              double* p_samples, nat_solve_report* report, void* stream)
+{
+    if (!mesh)
+        return nat::fail(NAT_E_INVALID, "nat_mcbem_estimate: mesh is NULL");
+    nat::McJob J{mesh, v_n, n_modes, Q, N, k, q_tri, q_bary, seed, p_out, p_samples};
+    return nat::run_mc(mesh->ctx, &J, 1, opts, report, static_cast<hipStream_t>(stream));
+}
+
+nat_status nat_mcbem_estimate_batch(nat_ctx* ctx, const nat_mc_job* jobs, int32_t n_jobs,
+                                    const nat_mc_opts* opts, nat_solve_report* reports,
+                                    void* stream)
+{
+    if (!ctx || !jobs || n_jobs < 1)
+        return nat::fail(NAT_E_INVALID, "nat_mcbem_estimate_batch: bad arguments");
+    std::vector<nat::McJob> J(n_jobs);
+    for (int32_t i = 0; i < n_jobs; ++i)
+        J[i] = nat::McJob{jobs[i].mesh, jobs[i].v_n, jobs[i].n_modes, jobs[i].n_queries,
+                          jobs[i].n_samples, jobs[i].k, jobs[i].q_tri, jobs[i].q_bary,
+                          jobs[i].seed, jobs[i].p_out, jobs[i].p_samples};
+    return nat::run_mc(ctx, J.data(), n_jobs, opts, reports, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

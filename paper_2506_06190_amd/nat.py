@@ -27,9 +27,19 @@ class NatError(RuntimeError):
         self.status = status
 
 
+NAT_MC_NO_GRAPH = 1
+
+
 class nat_mc_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("layout", C.c_int32), ("eps_scale", C.c_double),
-                ("gmres_tol", C.c_double), ("gmres_max_iter", C.c_int32), ("reserved", C.c_int32)]
+                ("gmres_tol", C.c_double), ("gmres_max_iter", C.c_int32), ("flags", C.c_int32)]
+
+
+class nat_mc_job(C.Structure):
+    _fields_ = [("mesh", C.c_void_p), ("v_n", C.c_void_p), ("n_modes", C.c_int32),
+                ("n_queries", C.c_int32), ("k", C.c_void_p), ("q_tri", C.c_void_p),
+                ("q_bary", C.c_void_p), ("n_samples", C.c_int32), ("reserved", C.c_int32),
+                ("seed", C.c_uint64), ("p_out", C.c_void_p), ("p_samples", C.c_void_p)]
 
 
 class nat_kernel_stat(C.Structure):
@@ -60,6 +70,7 @@ _SIGS = {
     "nat_mcbem_samples": ([_P, C.c_int32, C.c_uint64, _P, _P, _P], C.c_int),
     "nat_mcbem_estimate": ([_P, _P, C.c_int32, _P, _P, _P, C.c_int32, C.c_int32, C.c_uint64,
                             C.POINTER(nat_mc_opts), _P, _P, _P, _P], C.c_int),
+    "nat_mcbem_estimate_batch": ([_P, _P, C.c_int32, C.POINTER(nat_mc_opts), _P, _P], C.c_int),
     "nat_bem_assemble": ([_P, C.c_double, C.c_int32, C.POINTER(_P), _P], C.c_int),
     "nat_bem_solve": ([_P, _P, C.c_int32, C.c_int32, C.c_double, C.c_int32, _P, _P, _P], C.c_int),
     "nat_bem_op_matrices": ([_P, _P, _P, _P], C.c_int),
@@ -279,6 +290,63 @@ def nat_mcbem_estimate(mesh: Mesh, v_n, k: Sequence[float], q_tri, q_bary, n_sam
         C.cast(reps, _P), _stream(stream))
     _check(st, allow=(NAT_E_NOCONV,) if allow_noconv else ())
     return p_out, [r.as_dict() for r in reps]
+
+
+class McJob:
+    """One problem of nat_mcbem_estimate_batch (device tensors, host k)."""
+
+    def __init__(self, mesh: Mesh, v_n, k, q_tri, q_bary, n_samples: int, seed: int,
+                 p_out=None, p_samples=None, layout: int = NAT_NEUMANN_PER_VERTEX):
+        import torch
+        self.mesh = mesh
+        self.k = np.ascontiguousarray(np.atleast_1d(k), dtype=np.float64)
+        self.n_modes = len(self.k)
+        ng = mesh.n_tris if layout == NAT_NEUMANN_PER_TRIANGLE else mesh.n_vertices
+        self.Q = int(q_tri.shape[0])
+        self.v_n, self.q_tri, self.q_bary = v_n, q_tri, q_bary
+        self.n_samples, self.seed = int(n_samples), int(seed)
+        _dptr(v_n, torch.complex128, (self.n_modes, ng), "v_n")
+        _dptr(q_tri, torch.int32, (self.Q,), "q_tri")
+        _dptr(q_bary, torch.float64, (self.Q, 2), "q_bary")
+        if p_out is None:
+            p_out = torch.empty((self.n_modes, self.Q), dtype=torch.complex128, device=v_n.device)
+        self.p_out = p_out
+        self.p_samples = p_samples
+
+    def record(self) -> nat_mc_job:
+        import torch
+        j = nat_mc_job()
+        j.mesh = self.mesh.handle.value
+        j.v_n = self.v_n.data_ptr()
+        j.n_modes = self.n_modes
+        j.n_queries = self.Q
+        j.k = self.k.ctypes.data
+        j.q_tri = self.q_tri.data_ptr()
+        j.q_bary = self.q_bary.data_ptr()
+        j.n_samples = self.n_samples
+        j.seed = self.seed
+        j.p_out = _dptr(self.p_out, torch.complex128, (self.n_modes, self.Q), "p_out").value
+        j.p_samples = (_dptr(self.p_samples, torch.complex128, (self.n_modes, self.n_samples),
+                             "p_samples").value if self.p_samples is not None else None)
+        return j
+
+
+def nat_mcbem_estimate_batch(ctx: Context, jobs, opts: Optional[nat_mc_opts] = None, stream=None,
+                             allow_noconv: bool = False):
+    """Runs the jobs (list of McJob) in one batch; returns per-job lists of report dicts."""
+    if opts is None:
+        opts = nat_mc_opts_default()
+    recs = (nat_mc_job * len(jobs))(*[j.record() for j in jobs])
+    n_sys = sum(j.n_modes for j in jobs)
+    reps = (nat_solve_report * n_sys)()
+    st = lib().nat_mcbem_estimate_batch(ctx.handle, C.cast(recs, _P), len(jobs), C.byref(opts),
+                                        C.cast(reps, _P), _stream(stream))
+    _check(st, allow=(NAT_E_NOCONV,) if allow_noconv else ())
+    out, q = [], 0
+    for j in jobs:
+        out.append([reps[q + m].as_dict() for m in range(j.n_modes)])
+        q += j.n_modes
+    return out
 
 
 def nat_bem_assemble(mesh: Mesh, k: float, burton_miller: bool = True, stream=None) -> BemOp:

@@ -35,7 +35,7 @@ def test_status_strings_and_defaults():
     assert nat.status_str(nat.NAT_E_BUDGET) == "NAT_E_BUDGET"
     o = nat.nat_mc_opts_default()
     assert o.gmres_tol == 1e-6 and o.gmres_max_iter == 200     # Section 6.1 solver settings
-    assert o.eps_scale == 1.0 and o.precision == nat.NAT_PREC_FP32 and o.reserved == 0
+    assert o.eps_scale == 1.0 and o.precision == nat.NAT_PREC_FP32 and o.flags == 0
 
 
 @pytest.mark.parametrize("maker", [
