@@ -1,15 +1,20 @@
 """Benchmark of the Monte-Carlo BEM hot path on one MI355X.
 
-One step = one full Monte-Carlo estimate of the precision-form workload
-(noise-displaced ellipsoid with 20480 triangles, 32 modes with their own
-wavenumbers, 4096 surface queries, 1024 samples): sampling, right-hand
-side, GMRES (tol 1e-6, <= 200 iterations) and surface evaluation, in the
-FP32 form.  Inputs are resident in device memory before the timed region.
+Headline (default): the batched form.  One step = one Monte-Carlo estimate of
+256 cube-sphere instances at once (2k-40k triangles, 8-64 modes with their
+own wavenumbers, 2k-16k queries, 512-2048 samples): sampling, right-hand
+side, GMRES (tol 1e-6, <= 200 iterations) and surface evaluation for all
+~9.4k (instance, mode) systems, FP32 form, inputs resident in HBM.
+`value` = algorithmic pair evaluations per second, sum over systems of
+N(N-1) + Q N per step.
 
-Prints one JSON line: algorithmic pair evaluations per second
-(sum over modes of N(N-1) + Q N per step), the dominant kernel's roofline
-from HIP events recorded around its launches, the same workload in the
-plain FP64 GPU form, and the FP64 CPU oracle timed on the host.
+Also reported on the same JSON line:
+  roofline      the dominant kernel class, from HIP events attached to its
+                dispatches during a second pass over the same steps;
+  precision     the 20480-triangle, 32-mode precision-form workload in the FP32
+                form and in the plain FP64 form ("FP32 vs plain");
+  cpu_baseline  the FP64 oracle on a bounded sample of the headline workload,
+                timed on the host cores, with the GPU's error on that sample.
 """
 import argparse
 import json
@@ -21,13 +26,163 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+METRIC = "MC-BEM kernel pair-evals/s (FP32 vs plain) + p50/p99 solve latency at fixed error"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_jobs(nat, torch, ctx, wls, dev):
+    meshes, jobs = [], []
+    for wl in wls:
+        mesh = nat.Mesh(ctx, wl.vertices, wl.tris)
+        meshes.append(mesh)
+        jobs.append(nat.McJob(mesh, torch.from_numpy(wl.g).to(dev), wl.k,
+                              torch.from_numpy(wl.q_tri).to(dev), torch.from_numpy(wl.q_b).to(dev),
+                              wl.n_samples, wl.seed))
+    return meshes, jobs
+
+
+def roofline_from(prof, peak=FP32_VECTOR_PEAK_TFLOPS):
+    sums = {k: v for k, v in prof.items() if k.startswith("sum32")}
+    dom_name = max(sums, key=lambda k: sums[k]["total_ms"])
+    dom = sums[dom_name]
+    achieved = dom["flops"] / (dom["total_ms"] * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": f"k_sum32 ({dom_name})", "achieved": round(achieved, 3),
+            "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "avg_launch_ms": round(dom["avg_ms"], 5), "launches": dom["launches"],
+            "flops_per_launch": dom["flops"] / dom["launches"]}
+
+
+def run_batched(nat, torch, ctx, args, dev):
+    import numpy as np
+    import workloads as W
+    t0 = time.perf_counter()
+    wls = W.config_batched()
+    log(f"batched workload generated in {time.perf_counter() - t0:.1f} s")
+    meshes, jobs = make_jobs(nat, torch, ctx, wls, dev)
+    alg = sum(w.pair_evals() for w in wls)
+    opts = nat.nat_mc_opts_default()
+    for _ in range(args.warmup):
+        nat.nat_mcbem_estimate_batch(ctx, jobs, opts, allow_noconv=True)
+    torch.cuda.synchronize()
+    log("batched warm-up done")
+    t0 = time.perf_counter()
+    reps = None
+    for _ in range(args.steps):
+        reps = nat.nat_mcbem_estimate_batch(ctx, jobs, opts, allow_noconv=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"batched timed region: {elapsed:.3f} s for {args.steps} steps")
+    iters = np.array([r["iters"] for rr in reps for r in rr])
+    n_s = np.array([w.n_samples for w in wls for _ in range(w.n_modes)], dtype=np.float64)
+    executed = float(np.sum(n_s * n_s) + sum(w.n_modes * w.n_queries * w.n_samples for w in wls)
+                     + np.sum(iters * n_s * n_s))
+    # roofline pass: the same steps with events on the kernel dispatches
+    nat.nat_profile_enable(ctx, True)
+    for _ in range(args.steps):
+        nat.nat_mcbem_estimate_batch(ctx, jobs, opts, allow_noconv=True)
+    torch.cuda.synchronize()
+    prof = nat.nat_profile_read(ctx)
+    nat.nat_profile_enable(ctx, False)
+    roof = roofline_from(prof)
+    roof["timing_pass"] = "second pass over the same steps, eager dispatch, events on each dispatch"
+    out = {
+        "value": alg * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
+        "config": {"workload": "batched: 256 cube-sphere instances, 2k-40k tri, 8-64 modes, "
+                               "Q 2k-16k, N 512-2048, 200 Hz-8 kHz",
+                   "instances": len(wls), "systems": int(len(iters)),
+                   "triangles_total": int(sum(len(w.tris) for w in wls)),
+                   "algorithmic_pair_evals_per_step": alg, "form": "FP32 compensated, graph-replayed GMRES",
+                   "gmres_tol": 1e-6, "gmres_max_iter": 200},
+        "executed_pair_evals_per_s": executed * args.steps / elapsed,
+        "gmres_iters": {"mean": float(iters.mean()), "p50": float(np.median(iters)),
+                        "max": int(iters.max()), "not_converged": int(sum(not r["converged"]
+                                                                         for rr in reps for r in rr))},
+        "roofline": roof,
+        "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 5),
+                        "total_ms": round(v["total_ms"], 3)} for k, v in prof.items()},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        n_inst, n_modes = 8, 4
+        sample_pairs = 0
+        t_cpu = 0.0
+        errs = []
+        for i in range(n_inst):
+            wl = wls[i]
+            m = min(n_modes, wl.n_modes)
+            t0 = time.perf_counter()
+            r = O.mcbem(wl.vertices, wl.tris, wl.g[:m], wl.k[:m], wl.q_tri, wl.q_b, wl.n_samples,
+                        wl.seed, tol=1e-6)
+            t_cpu += time.perf_counter() - t0
+            sample_pairs += m * (wl.n_samples * (wl.n_samples - 1) + wl.n_queries * wl.n_samples)
+            got = jobs[i].p_out.cpu().numpy()
+            errs += [float(np.linalg.norm(got[q] - r["p"][q]) / np.linalg.norm(r["p"][q]))
+                     for q in range(m)]
+        out["cpu_baseline"] = {"value": sample_pairs / t_cpu, "unit": "pair-evals/s",
+                               "cores": O.num_threads(), "kind": "oracle",
+                               "sample": f"first {n_inst} instances x first {n_modes} modes of the "
+                                         "headline workload, FP64, tol 1e-6",
+                               "seconds": round(t_cpu, 3)}
+        out["max_rel_l2_vs_oracle"] = max(errs)
+    for mesh in meshes:
+        mesh.close()
+    return out
+
+
+def run_precision(nat, torch, ctx, args, dev, with_plain=True):
+    import numpy as np
+    import workloads as W
+    wl = W.config_precision()
+    mesh = nat.Mesh(ctx, wl.vertices, wl.tris)
+    g = torch.from_numpy(wl.g).to(dev)
+    qt = torch.from_numpy(wl.q_tri).to(dev)
+    qb = torch.from_numpy(wl.q_b).to(dev)
+    p = torch.empty((wl.n_modes, wl.n_queries), dtype=torch.complex128, device=dev)
+    alg = wl.pair_evals()
+
+    def step(prec):
+        o = nat.nat_mc_opts_default()
+        o.precision = prec
+        return nat.nat_mcbem_estimate(mesh, g, wl.k, qt, qb, wl.n_samples, wl.seed, o, p_out=p)
+
+    for _ in range(max(1, args.warmup)):
+        step(nat.NAT_PREC_FP32)
+    torch.cuda.synchronize()
+    steps = max(args.steps, 5)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, reps = step(nat.NAT_PREC_FP32)
+    torch.cuda.synchronize()
+    t32 = (time.perf_counter() - t0) / steps
+    p32 = p.cpu().numpy()
+    out = {"workload": wl.name, "fp32": {"value": alg / t32, "ms_per_step": 1e3 * t32},
+           "gmres_iters": [r["iters"] for r in reps]}
+    if with_plain:
+        step(nat.NAT_PREC_FP64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step(nat.NAT_PREC_FP64)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        p64 = p.cpu().numpy()
+        out["plain_fp64"] = {"form": "plain FP64, one thread per target, no tiling",
+                             "value": alg / t64, "ms_per_step": 1e3 * t64}
+        out["fp32_speedup_vs_plain"] = t64 / t32
+        out["fp32_max_rel_l2_vs_plain"] = max(
+            float(np.linalg.norm(p32[m] - p64[m]) / np.linalg.norm(p64[m])) for m in range(wl.n_modes))
+    mesh.close()
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["batched", "precision"], default="batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
@@ -36,116 +191,25 @@ def main():
               "described in the design notes but not part of this build.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-
-    import workloads as W
     from paper_2506_06190_amd import nat
 
     dev = "cuda:0"
-    wl = W.config_precision()
     ctx = nat.Context(0)
-    mesh = nat.Mesh(ctx, wl.vertices, wl.tris)
-    g = torch.from_numpy(wl.g).to(dev)
-    qt = torch.from_numpy(wl.q_tri).to(dev)
-    qb = torch.from_numpy(wl.q_b).to(dev)
-    p = torch.empty((wl.n_modes, wl.n_queries), dtype=torch.complex128, device=dev)
-    opts = nat.nat_mc_opts_default()
-    opts.precision = nat.NAT_PREC_FP32
-    alg_pairs = wl.pair_evals()
-
-    def step(o=opts):
-        return nat.nat_mcbem_estimate(mesh, g, wl.k, qt, qb, wl.n_samples, wl.seed, o, p_out=p)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    # the same steps without kernel timing, to show what the timing costs
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    ms_unprofiled = 1e3 * (time.perf_counter() - t0) / args.steps
-    nat.nat_profile_enable(ctx, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = None
-    for _ in range(args.steps):
-        _, reps = step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = nat.nat_profile_read(ctx)
-    nat.nat_profile_enable(ctx, False)
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = alg_pairs * args.steps / elapsed
-    iters = [r["iters"] for r in reps]
-    executed = wl.n_modes * (wl.n_samples ** 2 + wl.n_queries * wl.n_samples) \
-        + sum(iters) * wl.n_samples ** 2
-    p_fp32 = p.cpu().numpy()
-
-    # dominant kernel: the kernel-sum class with the largest total time
-    sums = {k: v for k, v in prof.items() if k.startswith("sum32")}
-    dom_name = max(sums, key=lambda k: sums[k]["total_ms"])
-    dom = sums[dom_name]
-    achieved = dom["flops"] / dom["launches"] / (dom["avg_ms"] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": f"k_sum32 ({dom_name})", "achieved": round(achieved, 3),
-                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-                "avg_launch_ms": round(dom["avg_ms"], 5), "launches": dom["launches"],
-                "kernel_share_of_step": round(sum(v["total_ms"] for v in prof.values())
-                                              and dom["total_ms"] / (elapsed * 1e3), 4)}
-
-    plain = None
-    if not args.no_plain:
-        o64 = nat.nat_mc_opts_default()
-        o64.precision = nat.NAT_PREC_FP64
-        step(o64)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        step(o64)
-        torch.cuda.synchronize()
-        t_plain = time.perf_counter() - t0
-        p_fp64 = p.cpu().numpy()
-        err_vs_plain = max(float(np.linalg.norm(p_fp32[m] - p_fp64[m]) / np.linalg.norm(p_fp64[m]))
-                           for m in range(wl.n_modes))
-        plain = {"form": "plain FP64, one thread per target, no tiling", "value": alg_pairs / t_plain,
-                 "ms_per_step": 1e3 * t_plain, "fp32_speedup": t_plain / (elapsed / args.steps),
-                 "fp32_max_rel_l2_vs_plain": err_vs_plain}
-
-    cpu = None
-    err_vs_oracle = None
-    if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        t0 = time.perf_counter()
-        r = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri, wl.q_b, wl.n_samples, wl.seed,
-                    tol=1e-6)
-        t_cpu = time.perf_counter() - t0
-        cpu = {"value": alg_pairs / t_cpu, "unit": "pair-evals/s", "cores": O.num_threads(),
-               "kind": "oracle", "sample": f"the full workload ({wl.n_modes} modes), FP64, tol 1e-6",
-               "seconds": round(t_cpu, 3)}
-        r12 = r  # same seed; compare the FP32 result with the oracle's
-        err_vs_oracle = max(float(np.linalg.norm(p_fp32[m] - r12["p"][m]) / np.linalg.norm(r12["p"][m]))
-                            for m in range(wl.n_modes))
-
-    out = {
-        "metric": "MC-BEM kernel pair-evals/s (FP32 vs plain) + p50/p99 solve latency at fixed error",
-        "value": value, "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": wl.name, "triangles": len(wl.tris), "modes": wl.n_modes,
-                   "queries": wl.n_queries, "samples": wl.n_samples, "form": "FP32 compensated",
-                   "gmres_tol": 1e-6},
-        "executed_pair_evals_per_s": executed * args.steps / elapsed,
-        "ms_per_step_without_kernel_timing": ms_unprofiled,
-        "gmres_iters": iters,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "plain": plain,
-        "max_rel_l2_vs_oracle": err_vs_oracle,
-        "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 5),
-                        "total_ms": round(v["total_ms"], 3)} for k, v in prof.items()},
-    }
-    mesh.close()
+    out = {"metric": METRIC, "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic"}
+    if args.workload == "batched":
+        res = run_batched(nat, torch, ctx, args, dev)
+        out.update({k: res.pop(k) for k in ("value", "ms_per_step", "config")})
+        out.update(res)
+        out["precision"] = run_precision(nat, torch, ctx, args, dev, with_plain=not args.no_plain)
+    else:
+        res = run_precision(nat, torch, ctx, args, dev, with_plain=not args.no_plain)
+        out["value"] = res["fp32"]["value"]
+        out["ms_per_step"] = res["fp32"]["ms_per_step"]
+        out["config"] = {"workload": res["workload"], "form": "FP32 compensated"}
+        out["precision"] = res
     ctx.close()
     print(json.dumps(out), flush=True)
 

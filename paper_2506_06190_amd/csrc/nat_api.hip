@@ -41,15 +41,20 @@ nat_status dev_alloc(nat_ctx* ctx, size_t bytes, void** ptr)
     *ptr = nullptr;
     if (bytes == 0)
         return NAT_OK;
-    if (ctx->budget && ctx->in_use + bytes > ctx->budget)
-        return fail(NAT_E_BUDGET, "HBM budget: need %zu bytes, %zu of %zu in use", bytes,
-                    ctx->in_use, ctx->budget);
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->budget && ctx->in_use + bytes > ctx->budget)
+            return fail(NAT_E_BUDGET, "HBM budget: need %zu bytes, %zu of %zu in use", bytes,
+                        ctx->in_use, ctx->budget);
+        ctx->in_use += bytes;
+    }
     hipError_t e = hipMalloc(ptr, bytes);
     if (e != hipSuccess) {
         *ptr = nullptr;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->in_use -= bytes;
         return hip_fail(e, "hipMalloc");
     }
-    ctx->in_use += bytes;
     return NAT_OK;
 }
 
@@ -58,50 +63,91 @@ void dev_free(nat_ctx* ctx, void* ptr, size_t bytes)
     if (!ptr)
         return;
     (void)hipFree(ptr);
+    std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->in_use -= bytes;
+}
+
+namespace {
+thread_local NatScratch* t_scratch = nullptr;
+}
+
+NatScratch& scratch_of(nat_ctx* ctx) { return t_scratch ? *t_scratch : ctx->scratch; }
+
+void bind_scratch(NatScratch* s) { t_scratch = s; }
+
+void release_scratch(nat_ctx* ctx, NatScratch& sc)
+{
+    if (sc.ws)
+        dev_free(ctx, sc.ws, sc.ws_bytes);
+    sc.ws = nullptr;
+    sc.ws_bytes = 0;
+    if (sc.pinned)
+        (void)hipHostFree(sc.pinned);
+    sc.pinned = nullptr;
+    sc.pinned_bytes = 0;
+    if (sc.mapped)
+        (void)hipHostFree(sc.mapped);
+    sc.mapped = nullptr;
+    sc.mapped_dev = nullptr;
+    sc.mapped_ints = 0;
+    if (sc.graph_exec)
+        (void)hipGraphExecDestroy(sc.graph_exec);
+    sc.graph_exec = nullptr;
+    sc.graph_key.clear();
+    if (sc.capture_stream)
+        (void)hipStreamDestroy(sc.capture_stream);
+    sc.capture_stream = nullptr;
 }
 
 nat_status workspace(nat_ctx* ctx, size_t bytes, void** ptr)
 {
-    if (bytes <= ctx->ws_bytes) {
-        *ptr = ctx->ws;
+    NatScratch& sc = scratch_of(ctx);
+    if (sc.ext_ws) {
+        if (bytes > sc.ext_ws_bytes)
+            return fail(NAT_E_BUDGET, "workspace: need %zu bytes, %zu lent", bytes, sc.ext_ws_bytes);
+        *ptr = sc.ext_ws;
+        return NAT_OK;
+    }
+    if (bytes <= sc.ws_bytes) {
+        *ptr = sc.ws;
         return NAT_OK;
     }
     // grow: release the old block first (the device must be idle for it)
-    if (ctx->ws) {
+    if (sc.ws) {
         NAT_HIP(hipDeviceSynchronize());
-        dev_free(ctx, ctx->ws, ctx->ws_bytes);
-        ctx->ws = nullptr;
-        ctx->ws_bytes = 0;
+        dev_free(ctx, sc.ws, sc.ws_bytes);
+        sc.ws = nullptr;
+        sc.ws_bytes = 0;
     }
     const size_t want = bytes + bytes / 8;
-    nat_status st = dev_alloc(ctx, want, &ctx->ws);
+    nat_status st = dev_alloc(ctx, want, &sc.ws);
     if (st != NAT_OK) {
-        st = dev_alloc(ctx, bytes, &ctx->ws);
+        st = dev_alloc(ctx, bytes, &sc.ws);
         if (st != NAT_OK)
             return st;
-        ctx->ws_bytes = bytes;
+        sc.ws_bytes = bytes;
     } else {
-        ctx->ws_bytes = want;
+        sc.ws_bytes = want;
     }
-    *ptr = ctx->ws;
+    *ptr = sc.ws;
     return NAT_OK;
 }
 
 nat_status pinned(nat_ctx* ctx, size_t bytes, void** ptr)
 {
-    if (bytes > ctx->pinned_bytes) {
-        if (ctx->pinned) {
+    NatScratch& sc = scratch_of(ctx);
+    if (bytes > sc.pinned_bytes) {
+        if (sc.pinned) {
             NAT_HIP(hipDeviceSynchronize());
-            (void)hipHostFree(ctx->pinned);
-            ctx->pinned = nullptr;
-            ctx->pinned_bytes = 0;
+            (void)hipHostFree(sc.pinned);
+            sc.pinned = nullptr;
+            sc.pinned_bytes = 0;
         }
         const size_t want = bytes < 65536 ? 65536 : bytes;
-        NAT_HIP(hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
-        ctx->pinned_bytes = want;
+        NAT_HIP(hipHostMalloc(&sc.pinned, want, hipHostMallocDefault));
+        sc.pinned_bytes = want;
     }
-    *ptr = ctx->pinned;
+    *ptr = sc.pinned;
     return NAT_OK;
 }
 
@@ -123,6 +169,7 @@ ProfSlot prof_slot(nat_ctx* ctx, int32_t kind, double flops)
     ProfSlot slot;
     if (!ctx || !ctx->prof)
         return slot;
+    std::lock_guard<std::mutex> lk(ctx->mu);
     NatProfEvent ev;
     ev.kind = kind;
     ev.flops = flops;
@@ -138,6 +185,7 @@ ProfSlot prof_slot(nat_ctx* ctx, int32_t kind, double flops)
 
 void prof_collect(nat_ctx* ctx)
 {
+    std::lock_guard<std::mutex> lk(ctx->mu);
     if (ctx->prof_pending.empty())
         return;
     (void)hipDeviceSynchronize();
@@ -159,13 +207,14 @@ void prof_collect(nat_ctx* ctx)
 // counter, words 16.. the per-system flags.  Returns host and device views.
 nat_status mapped_words(nat_ctx* ctx, size_t n, int32_t** host, int32_t** dev)
 {
-    if (n > ctx->mapped_ints) {
-        if (ctx->mapped) {
+    NatScratch& sc = scratch_of(ctx);
+    if (n > sc.mapped_ints) {
+        if (sc.mapped) {
             NAT_HIP(hipDeviceSynchronize());
-            (void)hipHostFree(ctx->mapped);
-            ctx->mapped = nullptr;
-            ctx->mapped_dev = nullptr;
-            ctx->mapped_ints = 0;
+            (void)hipHostFree(sc.mapped);
+            sc.mapped = nullptr;
+            sc.mapped_dev = nullptr;
+            sc.mapped_ints = 0;
         }
         const size_t want = n < 4096 ? 4096 : n;
         void* p = nullptr;
@@ -176,12 +225,12 @@ nat_status mapped_words(nat_ctx* ctx, size_t n, int32_t** host, int32_t** dev)
             (void)hipHostFree(p);
             return hip_fail(e, "hipHostGetDevicePointer");
         }
-        ctx->mapped = static_cast<int32_t*>(p);
-        ctx->mapped_dev = static_cast<int32_t*>(d);
-        ctx->mapped_ints = want;
+        sc.mapped = static_cast<int32_t*>(p);
+        sc.mapped_dev = static_cast<int32_t*>(d);
+        sc.mapped_ints = want;
     }
-    *host = ctx->mapped;
-    *dev = ctx->mapped_dev;
+    *host = sc.mapped;
+    *dev = sc.mapped_dev;
     return NAT_OK;
 }
 
@@ -385,18 +434,9 @@ void nat_ctx_destroy(nat_ctx* ctx)
         return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    if (ctx->ws)
-        nat::dev_free(ctx, ctx->ws, ctx->ws_bytes);
+    nat::release_scratch(ctx, ctx->scratch);
     if (ctx->d_rules)
         nat::dev_free(ctx, ctx->d_rules, sizeof(double) * 38);
-    if (ctx->pinned)
-        (void)hipHostFree(ctx->pinned);
-    if (ctx->mapped)
-        (void)hipHostFree(ctx->mapped);
-    if (ctx->graph_exec)
-        (void)hipGraphExecDestroy(ctx->graph_exec);
-    if (ctx->capture_stream)
-        (void)hipStreamDestroy(ctx->capture_stream);
     nat::prof_collect(ctx);
     for (hipEvent_t e : ctx->prof_pool)
         (void)hipEventDestroy(e);
@@ -672,6 +712,62 @@ nat_status nat_mcbem_samples(nat_mesh* m, int32_t N, uint64_t seed, int32_t* tri
     return NAT_OK;
 }
 
+}  // extern "C"
+
+namespace nat {
+
+size_t bem_assemble_ws_bytes(int32_t n)
+{
+    return carve_size<>({sizeof(int32_t) * 4, sizeof(int32_t) * 2 * (size_t)64 * n});
+}
+
+nat_status bem_assemble_into(nat_bem_op* op, hipStream_t s)
+{
+    nat_ctx* ctx = op->ctx;
+    nat_mesh* mesh = op->mesh;
+    const int32_t n = op->n;
+    const double k = op->k;
+    BemGeom g{n, mesh->d_V, mesh->d_T, ctx->d_rules};
+    const double2 beta = op->burton_miller ? make_double2(0.0, 1.0 / k) : make_double2(0.0, 0.0);
+    int32_t cap = 64 * n;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        void* ws = nullptr;
+        nat_status st = workspace(ctx, carve_size<>({sizeof(int32_t) * 4, sizeof(int32_t) * 2 * (size_t)cap}), &ws);
+        if (st != NAT_OK)
+            return st;
+        Carver cv(ws);
+        int32_t* count = cv.take<int32_t>(4);
+        int32_t* list = cv.take<int32_t>(2 * (size_t)cap);
+        hipError_t e = hipMemsetAsync(count, 0, sizeof(int32_t), s);
+        if (e == hipSuccess)
+            e = launch_bem_far(g, k, beta, op->d_A, op->d_B, list, cap, count, s,
+                               prof_slot(ctx, PK_BEM_ASSEMBLE, 0.0));
+        int32_t n_near = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&n_near, count, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            return hip_fail(e, "dense assembly, far pass");
+        if (n_near > cap) {
+            cap = n_near;
+            continue;
+        }
+        e = launch_bem_near(g, k, beta, op->d_A, op->d_B, list, n_near, s,
+                            prof_slot(ctx, PK_BEM_ASSEMBLE, 0.0));
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            return hip_fail(e, "dense assembly, near pass");
+        return NAT_OK;
+    }
+    return fail(NAT_E_INTERNAL, "dense assembly: near-pair list did not fit");
+}
+
+}  // namespace nat
+
+extern "C" {
+
 nat_status nat_bem_assemble(nat_mesh* mesh, double k, int32_t burton_miller, nat_bem_op** out,
                             void* stream)
 {
@@ -706,51 +802,35 @@ nat_status nat_bem_assemble(nat_mesh* mesh, double k, int32_t burton_miller, nat
     }
     op->d_A = static_cast<double2*>(blk);
     op->d_B = op->d_A + (size_t)n * n;
-
-    BemGeom g{n, mesh->d_V, mesh->d_T, ctx->d_rules};
-    const double2 beta = op->burton_miller ? make_double2(0.0, 1.0 / k) : make_double2(0.0, 0.0);
-    int32_t cap = 64 * n;
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        void* ws = nullptr;
-        st = workspace(ctx, carve_size<>({sizeof(int32_t) * 4, sizeof(int32_t) * 2 * (size_t)cap}), &ws);
-        if (st != NAT_OK) {
-            nat_bem_op_destroy(op);
-            return st;
-        }
-        Carver cv(ws);
-        int32_t* count = cv.take<int32_t>(4);
-        int32_t* list = cv.take<int32_t>(2 * (size_t)cap);
-        hipError_t e = hipMemsetAsync(count, 0, sizeof(int32_t), s);
-        if (e == hipSuccess)
-            e = launch_bem_far(g, k, beta, op->d_A, op->d_B, list, cap, count, s,
-                               prof_slot(ctx, PK_BEM_ASSEMBLE, 0.0));
-        int32_t n_near = 0;
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(&n_near, count, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(s);
-        if (e != hipSuccess) {
-            nat_bem_op_destroy(op);
-            return hip_fail(e, "dense assembly, far pass");
-        }
-        if (n_near > cap) {
-            cap = n_near;
-            continue;
-        }
-        e = launch_bem_near(g, k, beta, op->d_A, op->d_B, list, n_near, s,
-                            prof_slot(ctx, PK_BEM_ASSEMBLE, 0.0));
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(s);
-        if (e != hipSuccess) {
-            nat_bem_op_destroy(op);
-            return hip_fail(e, "dense assembly, near pass");
-        }
-        *out = op;
-        return NAT_OK;
+    st = bem_assemble_into(op, s);
+    if (st != NAT_OK) {
+        nat_bem_op_destroy(op);
+        return st;
     }
-    nat_bem_op_destroy(op);
-    return fail(NAT_E_INTERNAL, "nat_bem_assemble: near-pair list did not fit");
+    *out = op;
+    return NAT_OK;
 }
+
+}  // extern "C"
+
+namespace nat {
+size_t bem_solve_ws_bytes(int32_t n, int32_t M, int32_t max_iter)
+{
+    const size_t mm1 = (size_t)max_iter + 1;
+    const int32_t nch = gmres_chunks(n);
+    return carve_size<>(
+        {sizeof(int32_t) * 8, sizeof(double2) * (size_t)M * n, sizeof(double2) * (size_t)M * n,
+         sizeof(double2) * (size_t)M * n, sizeof(double2) * (size_t)M * mm1 * n,
+         sizeof(double2) * (size_t)M * max_iter * mm1, sizeof(double) * (size_t)M * max_iter,
+         sizeof(double2) * (size_t)M * max_iter, sizeof(double2) * (size_t)M * mm1,
+         sizeof(double2) * (size_t)M * mm1, sizeof(double) * M, sizeof(double) * M,
+         sizeof(int32_t) * M, sizeof(int32_t) * M, sizeof(double2) * (size_t)M * nch * mm1,
+         sizeof(double2) * (size_t)M * nch * mm1, sizeof(double) * (size_t)M * nch,
+         sizeof(SysDev) * M, sizeof(int2) * (size_t)M * nch});
+}
+}  // namespace nat
+
+extern "C" {
 
 nat_status nat_bem_solve(nat_bem_op* op, const double* v_n, int32_t n_rhs, int32_t layout,
                          double tol, int32_t max_iter, double* p_out, nat_solve_report* report,
@@ -794,15 +874,7 @@ nat_status nat_bem_solve(nat_bem_op* op, const double* v_n, int32_t n_rhs, int32
         Y.out_n = reinterpret_cast<double2*>(p_out) + (size_t)r * n;
     }
     T.max_items = (int64_t)M * nch;
-    const size_t bytes = carve_size<>(
-        {sizeof(int32_t) * 8, sizeof(double2) * (size_t)M * n, sizeof(double2) * (size_t)M * n,
-         sizeof(double2) * (size_t)M * n, sizeof(double2) * (size_t)M * mm1 * n,
-         sizeof(double2) * (size_t)M * max_iter * mm1, sizeof(double) * (size_t)M * max_iter,
-         sizeof(double2) * (size_t)M * max_iter, sizeof(double2) * (size_t)M * mm1,
-         sizeof(double2) * (size_t)M * mm1, sizeof(double) * M, sizeof(double) * M,
-         sizeof(int32_t) * M, sizeof(int32_t) * M, sizeof(double2) * (size_t)M * nch * mm1,
-         sizeof(double2) * (size_t)M * nch * mm1, sizeof(double) * (size_t)M * nch,
-         sizeof(SysDev) * M, sizeof(int2) * (size_t)M * nch});
+    const size_t bytes = bem_solve_ws_bytes(n, M, max_iter);
     void* ws = nullptr;
     st = workspace(ctx, bytes, &ws);
     if (st != NAT_OK)

@@ -8,6 +8,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,8 +27,28 @@ struct NatProfStat {
     double flops = 0.0;
 };
 
+// Scratch state of one solve at a time: device workspace, pinned staging,
+// pinned words the kernels write (convergence flags, loop progress) and the
+// cached graph of GMRES iterations.  A context owns one; each worker of a
+// server owns its own so solves can run concurrently on one context.
+struct NatScratch {
+    void* ws = nullptr;             // grow-only device workspace
+    size_t ws_bytes = 0;
+    void* ext_ws = nullptr;         // workspace lent by the caller instead (server arena)
+    size_t ext_ws_bytes = 0;
+    void* pinned = nullptr;
+    size_t pinned_bytes = 0;
+    int32_t* mapped = nullptr;
+    int32_t* mapped_dev = nullptr;
+    size_t mapped_ints = 0;
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<unsigned char> graph_key;
+};
+
 struct nat_ctx {
     int32_t device = 0;
+    std::mutex mu;       // guards the ledger and the timing lists
     // per-kernel timing (off unless enabled)
     bool prof = false;
     std::vector<NatProfEvent> prof_pending;
@@ -35,23 +56,9 @@ struct nat_ctx {
     NatProfStat prof_stat[8];
     size_t budget = 0;   // 0: unlimited
     size_t in_use = 0;   // bytes charged
-    // grow-only scratch shared by the solves of this context
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
-    // pinned host staging for small device-to-host reads
-    void* pinned = nullptr;
-    size_t pinned_bytes = 0;
-    // pinned host memory the kernels write directly (convergence flags and
-    // progress of the GMRES loop), read by the host without a copy
-    int32_t* mapped = nullptr;
-    int32_t* mapped_dev = nullptr;
-    size_t mapped_ints = 0;
+    NatScratch scratch;
     // Gauss-Legendre rules on [0,1] for the dense assembly (device copies)
     double* d_rules = nullptr;
-    // capture stream and the last captured run of GMRES iterations
-    hipStream_t capture_stream = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    std::vector<unsigned char> graph_key;
 };
 
 struct nat_mesh {
@@ -97,6 +104,11 @@ nat_status hip_fail(hipError_t e, const char* what);
 // ---- device memory charged to a context -----------------------------------
 nat_status dev_alloc(nat_ctx* ctx, size_t bytes, void** ptr);
 void dev_free(nat_ctx* ctx, void* ptr, size_t bytes);
+// The calling thread's scratch: the one bound by bind_scratch, else the
+// context's own.
+NatScratch& scratch_of(nat_ctx* ctx);
+void bind_scratch(NatScratch* s);
+void release_scratch(nat_ctx* ctx, NatScratch& s);
 // grow-only scratch; contents undefined on return
 nat_status workspace(nat_ctx* ctx, size_t bytes, void** ptr);
 nat_status pinned(nat_ctx* ctx, size_t bytes, void** ptr);
@@ -328,8 +340,28 @@ struct BatchTables {
 nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double2* b,
                        Sum32Batch* mv, const std::function<hipError_t(int32_t)>& eager_mv,
                        bool use_graph, hipStream_t s);
-// Tables for systems of equal size n (the dense solve): n_sys systems,
-// Stage-A layout only.
+// One Monte-Carlo job (the arguments of nat_mcbem_estimate).
+struct McJob {
+    nat_mesh* mesh;
+    const double* v_n;
+    int32_t M, Q, N;
+    const double* k;
+    const int32_t* q_tri;
+    const double* q_bary;
+    uint64_t seed;
+    double* p_out;
+    double* p_samples;
+};
+// Run the jobs as one batch; with bytes_only set, only validate the host
+// arguments and report the workspace the batch needs.
+nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts* opts,
+                  nat_solve_report* report, hipStream_t s, size_t* bytes_only);
+// Dense assembly into caller matrices (op->d_A, op->d_B set), near-pair list
+// in the calling thread's workspace.
+nat_status bem_assemble_into(nat_bem_op* op, hipStream_t s);
+// Workspace of nat_bem_assemble and nat_bem_solve for n panels.
+size_t bem_assemble_ws_bytes(int32_t n);
+size_t bem_solve_ws_bytes(int32_t n, int32_t n_rhs, int32_t max_iter);
 
 // ---- dense BEM (k_bem.hip) -------------------------------------------------
 struct BemGeom {

@@ -108,23 +108,24 @@ void append_bytes(std::vector<unsigned char>& v, const T& x)
 nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch& mv, int32_t grid_g,
                         int32_t grid_mv, hipGraphExec_t* exec)
 {
+    NatScratch& sc = scratch_of(ctx);
     std::vector<unsigned char> key;
     append_bytes(key, g);
     append_bytes(key, mv);
     append_bytes(key, grid_g);
     append_bytes(key, grid_mv);
-    if (ctx->graph_exec && key == ctx->graph_key) {
-        *exec = ctx->graph_exec;
+    if (sc.graph_exec && key == sc.graph_key) {
+        *exec = sc.graph_exec;
         return NAT_OK;
     }
-    if (ctx->graph_exec) {
-        (void)hipGraphExecDestroy(ctx->graph_exec);
-        ctx->graph_exec = nullptr;
-        ctx->graph_key.clear();
+    if (sc.graph_exec) {
+        (void)hipGraphExecDestroy(sc.graph_exec);
+        sc.graph_exec = nullptr;
+        sc.graph_key.clear();
     }
-    if (!ctx->capture_stream)
-        NAT_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
-    hipStream_t cs = ctx->capture_stream;
+    if (!sc.capture_stream)
+        NAT_HIP(hipStreamCreateWithFlags(&sc.capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = sc.capture_stream;
     NAT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int32_t r = 0; r < kLag && e == hipSuccess; ++r) {
@@ -144,8 +145,8 @@ nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch& mv,
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess)
         return hip_fail(e, "hipGraphInstantiate");
-    ctx->graph_exec = ex;
-    ctx->graph_key = key;
+    sc.graph_exec = ex;
+    sc.graph_key = key;
     *exec = ex;
     return NAT_OK;
 }
@@ -251,20 +252,8 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
 // ---------------------------------------------------------------------------
 // Monte-Carlo estimate of a batch of jobs
 // ---------------------------------------------------------------------------
-struct McJob {
-    nat_mesh* mesh;
-    const double* v_n;
-    int32_t M, Q, N;
-    const double* k;
-    const int32_t* q_tri;
-    const double* q_bary;
-    uint64_t seed;
-    double* p_out;
-    double* p_samples;
-};
-
 nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts* opts,
-                  nat_solve_report* report, hipStream_t s)
+                  nat_solve_report* report, hipStream_t s, size_t* bytes_only)
 {
     if (!opts)
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: opts is NULL");
@@ -295,9 +284,12 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     }
     if (nj < 1 || S64 > (1 << 20))
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: %d jobs with %lld systems", nj, (long long)S64);
-    nat_status st = set_device(ctx);
-    if (st != NAT_OK)
-        return st;
+    nat_status st = NAT_OK;
+    if (!bytes_only) {
+        st = set_device(ctx);
+        if (st != NAT_OK)
+            return st;
+    }
     const int32_t S = static_cast<int32_t>(S64);
     const bool fp32 = opts->precision == NAT_PREC_FP32;
     const int32_t mmax = opts->gmres_max_iter;
@@ -370,6 +362,10 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
          sizeof(double) * sum_ch, sizeof(float4) * n_part, sizeof(InstDev) * nj,
          sizeof(SysDev) * S, sizeof(GroupDev) * S, sizeof(GroupDev) * S, sizeof(GroupDev) * S,
          sizeof(int2) * sum_ch, sizeof(double) * S, sizeof(int64_t) * 8});
+    if (bytes_only) {
+        *bytes_only = bytes;
+        return NAT_OK;
+    }
     void* ws = nullptr;
     st = workspace(ctx, bytes, &ws);
     if (st != NAT_OK)
@@ -719,7 +715,7 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
     if (!mesh)
         return nat::fail(NAT_E_INVALID, "nat_mcbem_estimate: mesh is NULL");
     nat::McJob J{mesh, v_n, n_modes, Q, N, k, q_tri, q_bary, seed, p_out, p_samples};
-    return nat::run_mc(mesh->ctx, &J, 1, opts, report, static_cast<hipStream_t>(stream));
+    return nat::run_mc(mesh->ctx, &J, 1, opts, report, static_cast<hipStream_t>(stream), nullptr);
 }
 
 nat_status nat_mcbem_estimate_batch(nat_ctx* ctx, const nat_mc_job* jobs, int32_t n_jobs,
@@ -733,7 +729,7 @@ nat_status nat_mcbem_estimate_batch(nat_ctx* ctx, const nat_mc_job* jobs, int32_
         J[i] = nat::McJob{jobs[i].mesh, jobs[i].v_n, jobs[i].n_modes, jobs[i].n_queries,
                           jobs[i].n_samples, jobs[i].k, jobs[i].q_tri, jobs[i].q_bary,
                           jobs[i].seed, jobs[i].p_out, jobs[i].p_samples};
-    return nat::run_mc(ctx, J.data(), n_jobs, opts, reports, static_cast<hipStream_t>(stream));
+    return nat::run_mc(ctx, J.data(), n_jobs, opts, reports, static_cast<hipStream_t>(stream), nullptr);
 }
 
 }  // extern "C"

@@ -22,6 +22,7 @@ both sides draw from the counter generator given by the seed argument.
 """
 from __future__ import annotations
 
+import functools
 import math
 from dataclasses import dataclass, field
 
@@ -91,37 +92,43 @@ def icosphere(subdiv: int, radius: float = 1.0):
     return u * radius, f, u
 
 
-def cubesphere_unit(n: int):
-    """Unit cube-sphere: 12 n^2 triangles, 6 n^2 + 2 vertices."""
-    idx = {}
-    verts = []
-
-    def vid(p):
-        key = tuple(np.round(p * (2 * n)).astype(int))
-        if key not in idx:
-            idx[key] = len(verts)
-            verts.append(p)
-        return idx[key]
-
-    faces = []
+@functools.lru_cache(maxsize=128)
+def _cubesphere_unit_cached(n: int):
+    # grid points of the six faces, then merge duplicates on the cube edges
     g = np.linspace(-1.0, 1.0, n + 1)
+    A, B = np.meshgrid(np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    pts, faces = [], []
+    base = 0
     for axis in range(3):
         for sgn in (-1.0, 1.0):
-            for i in range(n):
-                for j in range(n):
-                    quad = []
-                    for (a, b) in ((i, j), (i + 1, j), (i + 1, j + 1), (i, j + 1)):
-                        p = np.zeros(3)
-                        p[axis] = sgn
-                        p[(axis + 1) % 3] = g[a]
-                        p[(axis + 2) % 3] = g[b]
-                        quad.append(vid(p))
-                    faces.append((quad[0], quad[1], quad[2]))
-                    faces.append((quad[0], quad[2], quad[3]))
-    v = np.asarray(verts, dtype=np.float64)
-    v /= np.linalg.norm(v, axis=1, keepdims=True)
-    f = np.asarray(faces, dtype=np.int32)
+            p = np.zeros((n + 1, n + 1, 3))
+            p[..., axis] = sgn
+            p[..., (axis + 1) % 3] = g[A]
+            p[..., (axis + 2) % 3] = g[B]
+            pts.append(p.reshape(-1, 3))
+            idx = base + (A * (n + 1) + B)
+            q00, q10 = idx[:-1, :-1], idx[1:, :-1]
+            q11, q01 = idx[1:, 1:], idx[:-1, 1:]
+            faces.append(np.stack([q00, q10, q11], -1).reshape(-1, 3))
+            faces.append(np.stack([q00, q11, q01], -1).reshape(-1, 3))
+            base += (n + 1) * (n + 1)
+    pts = np.concatenate(pts)
+    faces = np.concatenate(faces)
+    key = np.round(pts * (2 * n)).astype(np.int64)
+    _, first, inv = np.unique(key, axis=0, return_index=True, return_inverse=True)
+    order = np.argsort(first)                 # keep first-seen vertex order
+    remap = np.empty_like(order)
+    remap[order] = np.arange(len(order))
+    v = pts[first[order]]
+    f = remap[inv.reshape(-1)][faces].astype(np.int32)
+    v = v / np.linalg.norm(v, axis=1, keepdims=True)
     return v, _orient_outward(v, f)
+
+
+def cubesphere_unit(n: int):
+    """Unit cube-sphere: 12 n^2 triangles, 6 n^2 + 2 vertices."""
+    v, f = _cubesphere_unit_cached(int(n))
+    return v.copy(), f.copy()
 
 
 def real_sh_basis(u: np.ndarray, lmax: int) -> np.ndarray:
