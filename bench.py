@@ -14,7 +14,12 @@ Also reported on the same JSON line:
   precision     the 20480-triangle, 32-mode precision-form workload in the FP32
                 form and in the plain FP64 form ("FP32 vs plain");
   cpu_baseline  the FP64 oracle on a bounded sample of the headline workload,
-                timed on the host cores, with the GPU's error on that sample.
+                timed on the host cores, with the GPU's error on that sample;
+  served        the request server on a Poisson stream of Monte-Carlo and
+                dense solves over 64 resident meshes: p50/p99 latency and
+                solves/s, against the plain per-solve form (the same requests
+                one at a time, no batching, no graphs) on the same arrivals,
+                whose results are bitwise those of the served run.
 """
 import argparse
 import json
@@ -132,6 +137,132 @@ def run_batched(nat, torch, ctx, args, dev):
     return out
 
 
+def _percentiles(x):
+    import numpy as np
+    x = np.asarray(x, dtype=np.float64)
+    return {"p50_ms": round(float(np.percentile(x, 50)), 3), "p99_ms": round(float(np.percentile(x, 99)), 3),
+            "mean_ms": round(float(x.mean()), 3), "max_ms": round(float(x.max()), 3)}
+
+
+def run_served(nat, torch, ctx, args, dev):
+    import numpy as np
+    import workloads as W
+    t0 = time.perf_counter()
+    meshes, reqs = W.config_served(n_requests=args.serve_requests)
+    log(f"served workload generated in {time.perf_counter() - t0:.1f} s")
+    R = []
+    for m in meshes:
+        R.append({"mesh": nat.Mesh(ctx, m.vertices, m.tris),
+                  "gv": torch.from_numpy(m.g_vertex).to(dev), "gt": torch.from_numpy(m.g_tri).to(dev),
+                  "qt": torch.from_numpy(m.q_tri).to(dev), "qb": torch.from_numpy(m.q_b).to(dev)})
+    sopts = nat.nat_server_opts_default()
+    sopts.n_slots = args.serve_slots
+    sopts.max_batch = args.serve_max_batch
+    sopts.hbm_budget = args.serve_budget_gib << 30
+
+    def build(rq):
+        r = R[rq.mesh]
+        M = rq.n_modes
+        if rq.kind == "mc":
+            return nat.Request(nat.NAT_REQ_MCBEM, r["mesh"], r["gv"][rq.m0:rq.m0 + M], rq.k,
+                               r["qt"][:rq.n_queries], r["qb"][:rq.n_queries], rq.n_samples, rq.seed)
+        return nat.Request(nat.NAT_REQ_DENSE, r["mesh"], r["gt"][rq.m0:rq.m0 + M], rq.k,
+                           layout=nat.NAT_NEUMANN_PER_TRIANGLE)
+
+    def plain(rq, out):
+        r = R[rq.mesh]
+        M = rq.n_modes
+        if rq.kind == "mc":
+            o = nat.nat_mc_opts_default()
+            o.flags = nat.NAT_MC_NO_GRAPH
+            nat.nat_mcbem_estimate(r["mesh"], r["gv"][rq.m0:rq.m0 + M], rq.k, r["qt"][:rq.n_queries],
+                                   r["qb"][:rq.n_queries], rq.n_samples, rq.seed, o, p_out=out,
+                                   allow_noconv=True)
+            return
+        for m in range(M):
+            op = nat.nat_bem_assemble(r["mesh"], rq.k[m], True)
+            nat.nat_bem_solve(op, r["gt"][rq.m0 + m:rq.m0 + m + 1], layout=nat.NAT_NEUMANN_PER_TRIANGLE,
+                              tol=sopts.dense_tol, max_iter=sopts.dense_max_iter, p_out=out[m:m + 1],
+                              allow_noconv=True)
+            op.close()
+
+    srv = nat.Server(ctx, sopts)
+    # warm-up: the first 16 requests
+    warm = [build(rq) for rq in reqs[:16]]
+    torch.cuda.synchronize()
+    for t in [nat.nat_server_submit(srv, b) for b in warm]:
+        nat.nat_server_wait(srv, t)
+    del warm
+    # capacity: the whole stream submitted at once
+    built = [build(rq) for rq in reqs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = [nat.nat_server_submit(srv, b) for b in built]
+    for t in tickets:
+        nat.nat_server_wait(srv, t)
+    cap_s = time.perf_counter() - t0
+    capacity = len(reqs) / cap_s
+    log(f"served capacity: {len(reqs)} requests in {cap_s:.2f} s")
+    # Poisson arrivals at 70 % of that capacity
+    rate = 0.7 * capacity
+    arrive = np.cumsum([rq.gap for rq in reqs]) / rate
+    built = [build(rq) for rq in reqs]
+    torch.cuda.synchronize()
+    lat, qms, bsz, iters_max = [], [], [], []
+    t0 = time.perf_counter()
+    tickets = []
+    for i, b in enumerate(built):
+        d = arrive[i] - (time.perf_counter() - t0)
+        if d > 0:
+            time.sleep(d)
+        tickets.append(nat.nat_server_submit(srv, b))
+    for t in tickets:
+        st, r, _ = nat.nat_server_wait(srv, t)
+        if st not in (nat.NAT_OK, nat.NAT_E_NOCONV):
+            raise RuntimeError(f"served request failed: {nat.status_str(st)}")
+        lat.append(r["latency_ms"])
+        qms.append(r["queue_ms"])
+        bsz.append(r["batch_size"])
+        iters_max.append(r["max_iters"])
+    span = time.perf_counter() - t0
+    stats = nat.nat_server_stats_read(srv)
+    srv.close()
+    log(f"served Poisson run: {span:.2f} s")
+    # plain per-solve form on the same arrivals
+    outs = [torch.empty_like(b.p_out) for b in built]
+    torch.cuda.synchronize()
+    plat = []
+    t0 = time.perf_counter()
+    for i, rq in enumerate(reqs):
+        d = arrive[i] - (time.perf_counter() - t0)
+        if d > 0:
+            time.sleep(d)
+        plain(rq, outs[i])
+        torch.cuda.synchronize()
+        plat.append(1e3 * (time.perf_counter() - t0 - arrive[i]))
+    pspan = time.perf_counter() - t0
+    log(f"plain per-solve run: {pspan:.2f} s")
+    equal = all(torch.equal(b.p_out, o) for b, o in zip(built, outs))
+    alg = sum(rq.pair_evals() for rq in reqs)
+    for r in R:
+        r["mesh"].close()
+    return {
+        "workload": f"{len(meshes)} resident cube-spheres T {min(len(m.tris) for m in meshes)}-"
+                    f"{max(len(m.tris) for m in meshes)}, {len(reqs)} requests "
+                    f"({sum(rq.kind == 'dense' for rq in reqs)} dense), modes 1-64, Q 1-16k, N 512-2048",
+        "server": {"slots": sopts.n_slots, "max_batch": sopts.max_batch, "budget_gib": args.serve_budget_gib},
+        "capacity_req_per_s": round(capacity, 2), "arrival_rate_req_per_s": round(rate, 2),
+        "latency": _percentiles(lat), "queue": _percentiles(qms),
+        "solves_per_s": round(len(reqs) / span, 2),
+        "mc_pair_evals_per_s_at_capacity": alg / cap_s,
+        "batch_size_mean": round(float(np.mean(bsz)), 2), "gmres_iters_max": int(max(iters_max)),
+        "stats": stats,
+        "plain_per_solve": {"latency": _percentiles(plat), "solves_per_s": round(len(reqs) / pspan, 2),
+                            "form": "one request at a time, direct launches, no batching"},
+        "results_bitwise_equal_to_plain": bool(equal),
+    }
+
+
 def run_precision(nat, torch, ctx, args, dev, with_plain=True):
     import numpy as np
     import workloads as W
@@ -182,7 +313,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["batched", "precision"], default="batched")
+    ap.add_argument("--workload", choices=["batched", "precision", "served"], default="batched")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-max-batch", type=int, default=64)
+    ap.add_argument("--serve-budget-gib", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
@@ -204,6 +340,16 @@ def main():
         out.update({k: res.pop(k) for k in ("value", "ms_per_step", "config")})
         out.update(res)
         out["precision"] = run_precision(nat, torch, ctx, args, dev, with_plain=not args.no_plain)
+        if not args.no_serve:
+            out["served"] = run_served(nat, torch, ctx, args, dev)
+    elif args.workload == "served":
+        res = run_served(nat, torch, ctx, args, dev)
+        out["metric"] = "served solves/s with p50/p99 latency"
+        out["unit"] = "solves/s"
+        out["value"] = res["solves_per_s"]
+        out["ms_per_step"] = None
+        out["config"] = {"workload": res["workload"]}
+        out["served"] = res
     else:
         res = run_precision(nat, torch, ctx, args, dev, with_plain=not args.no_plain)
         out["value"] = res["fp32"]["value"]

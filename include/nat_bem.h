@@ -49,7 +49,9 @@ typedef enum {
     NAT_E_BUDGET = 2,   /* the HBM budget would be exceeded; nothing was allocated */
     NAT_E_NOCONV = 3,   /* GMRES stopped at max_iter above tol; best iterate kept  */
     NAT_E_HIP = 4,      /* a HIP runtime call failed                               */
-    NAT_E_INTERNAL = 5
+    NAT_E_INTERNAL = 5,
+    NAT_E_PENDING = 6,  /* a served request has not finished yet (nat_serve.h)     */
+    NAT_E_CANCELLED = 7 /* a served request was cancelled before it started        */
 } nat_status;
 
 typedef struct nat_ctx nat_ctx;

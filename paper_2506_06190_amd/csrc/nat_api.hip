@@ -364,6 +364,10 @@ const char* nat_status_str(nat_status s)
         return "NAT_E_HIP";
     case NAT_E_INTERNAL:
         return "NAT_E_INTERNAL";
+    case NAT_E_PENDING:
+        return "NAT_E_PENDING";
+    case NAT_E_CANCELLED:
+        return "NAT_E_CANCELLED";
     }
     return "NAT_E_UNKNOWN";
 }

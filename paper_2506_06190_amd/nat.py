@@ -1,4 +1,5 @@
-"""ctypes binding of libnat_bem.so (declared in include/nat_bem.h).
+"""ctypes binding of libnat_bem.so (declared in include/nat_bem.h and
+include/nat_serve.h).
 
 Argument marshalling only: every function forwards torch tensors' device
 pointers and the current HIP stream to the C entry point of the same name
@@ -16,7 +17,9 @@ import numpy as np
 
 LIB_PATH = Path(__file__).resolve().parent / "libnat_bem.so"
 
-NAT_OK, NAT_E_INVALID, NAT_E_BUDGET, NAT_E_NOCONV, NAT_E_HIP, NAT_E_INTERNAL = range(6)
+(NAT_OK, NAT_E_INVALID, NAT_E_BUDGET, NAT_E_NOCONV, NAT_E_HIP, NAT_E_INTERNAL, NAT_E_PENDING,
+ NAT_E_CANCELLED) = range(8)
+NAT_REQ_MCBEM, NAT_REQ_DENSE = 0, 1
 NAT_PREC_FP64, NAT_PREC_FP32 = 0, 1
 NAT_NEUMANN_PER_VERTEX, NAT_NEUMANN_PER_TRIANGLE = 0, 1
 
@@ -55,6 +58,38 @@ class nat_solve_report(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class nat_server_opts(C.Structure):
+    _fields_ = [("n_slots", C.c_int32), ("max_batch", C.c_int32), ("hbm_budget", C.c_size_t),
+                ("mc", nat_mc_opts), ("dense_tol", C.c_double), ("dense_max_iter", C.c_int32),
+                ("dense_burton_miller", C.c_int32)]
+
+
+class nat_request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("layout", C.c_int32), ("mesh", C.c_void_p),
+                ("n_modes", C.c_int32), ("n_queries", C.c_int32), ("k", C.c_void_p),
+                ("v_n", C.c_void_p), ("q_tri", C.c_void_p), ("q_bary", C.c_void_p),
+                ("n_samples", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64),
+                ("p_out", C.c_void_p), ("report", C.c_void_p)]
+
+
+class nat_request_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("batch_size", C.c_int32), ("slot", C.c_int32),
+                ("max_iters", C.c_int32), ("batch_id", C.c_int64), ("queue_ms", C.c_double),
+                ("run_ms", C.c_double), ("latency_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class nat_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("cancelled", C.c_int64),
+                ("batches", C.c_int64), ("max_batch_seen", C.c_int64), ("max_concurrent", C.c_int32),
+                ("reserved", C.c_int32), ("peak_bytes", C.c_size_t), ("budget", C.c_size_t)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 _P = C.c_void_p
 _SIGS = {
     "nat_ctx_create": ([C.c_int32, C.c_size_t, C.POINTER(_P)], C.c_int),
@@ -77,6 +112,13 @@ _SIGS = {
     "nat_bem_op_destroy": ([_P], None),
     "nat_profile_enable": ([_P, C.c_int32], C.c_int),
     "nat_profile_read": ([_P, _P, C.c_int32], C.c_int32),
+    "nat_server_opts_default": ([C.POINTER(nat_server_opts)], None),
+    "nat_server_create": ([_P, C.POINTER(nat_server_opts), C.POINTER(_P)], C.c_int),
+    "nat_server_submit": ([_P, C.POINTER(nat_request), C.POINTER(C.c_uint64)], C.c_int),
+    "nat_server_wait": ([_P, C.c_uint64, C.c_double, C.POINTER(nat_request_result)], C.c_int),
+    "nat_server_cancel": ([_P, C.c_uint64], C.c_int),
+    "nat_server_stats_read": ([_P, C.POINTER(nat_server_stats)], C.c_int),
+    "nat_server_destroy": ([_P], None),
     "nat_status_str": ([C.c_int], C.c_char_p),
     "nat_last_error": ([C.c_char_p, C.c_size_t], C.c_size_t),
 }
@@ -377,3 +419,122 @@ def nat_bem_op_matrices(op: BemOp, stream=None):
     B = torch.empty_like(A)
     _check(lib().nat_bem_op_matrices(op.handle, _dptr(A), _dptr(B), _stream(stream)))
     return A, B
+
+
+# ------------------------------------------------------------- served form
+def nat_server_opts_default() -> nat_server_opts:
+    o = nat_server_opts()
+    lib().nat_server_opts_default(C.byref(o))
+    return o
+
+
+class Request:
+    """One served request: device tensors, host k, and the output tensor.
+
+    kind NAT_REQ_MCBEM: p_out [n_modes, Q] at the query points;
+    kind NAT_REQ_DENSE: p_out [n_modes, n_tris] at the centroids."""
+
+    def __init__(self, kind: int, mesh: Mesh, v_n, k, q_tri=None, q_bary=None, n_samples: int = 0,
+                 seed: int = 0, layout: int = NAT_NEUMANN_PER_VERTEX, p_out=None):
+        import torch
+        self.kind, self.mesh, self.layout = int(kind), mesh, int(layout)
+        self.k = np.ascontiguousarray(np.atleast_1d(k), dtype=np.float64)
+        self.n_modes = len(self.k)
+        ng = mesh.n_tris if layout == NAT_NEUMANN_PER_TRIANGLE else mesh.n_vertices
+        _dptr(v_n, torch.complex128, (self.n_modes, ng), "v_n")
+        self.v_n, self.q_tri, self.q_bary = v_n, q_tri, q_bary
+        self.n_samples, self.seed = int(n_samples), int(seed)
+        if kind == NAT_REQ_MCBEM:
+            self.Q = int(q_tri.shape[0])
+            _dptr(q_tri, torch.int32, (self.Q,), "q_tri")
+            _dptr(q_bary, torch.float64, (self.Q, 2), "q_bary")
+            shape = (self.n_modes, self.Q)
+        else:
+            self.Q = 0
+            shape = (self.n_modes, mesh.n_tris)
+        if p_out is None:
+            p_out = torch.empty(shape, dtype=torch.complex128, device=v_n.device)
+        _dptr(p_out, torch.complex128, shape, "p_out")
+        self.p_out = p_out
+        self.reports = (nat_solve_report * self.n_modes)()
+
+    def record(self) -> nat_request:
+        r = nat_request()
+        r.kind, r.layout, r.mesh = self.kind, self.layout, self.mesh.handle.value
+        r.n_modes, r.n_queries = self.n_modes, self.Q
+        r.k = self.k.ctypes.data
+        r.v_n = self.v_n.data_ptr()
+        if self.kind == NAT_REQ_MCBEM:
+            r.q_tri = self.q_tri.data_ptr()
+            r.q_bary = self.q_bary.data_ptr()
+        r.n_samples, r.seed = self.n_samples, self.seed
+        r.p_out = self.p_out.data_ptr()
+        r.report = C.cast(self.reports, _P).value
+        return r
+
+
+class Server:
+    """Handle of nat_server_create; keeps each submitted Request alive until
+    its result has been collected."""
+
+    def __init__(self, ctx: Context, opts: Optional[nat_server_opts] = None):
+        if opts is None:
+            opts = nat_server_opts_default()
+        h = C.c_void_p()
+        _check(lib().nat_server_create(ctx.handle, C.byref(opts), C.byref(h)))
+        self.ctx, self.handle, self.opts = ctx, h, opts
+        self._live = {}
+
+    def close(self):
+        if self.handle:
+            lib().nat_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nat_server_create(ctx: Context, opts: Optional[nat_server_opts] = None) -> Server:
+    return Server(ctx, opts)
+
+
+def nat_server_submit(srv: Server, req: Request) -> int:
+    """Queue req (device work is stream-ordered on the server's own streams:
+    the caller synchronises its producers first); returns the ticket."""
+    t = C.c_uint64()
+    rec = req.record()
+    _check(lib().nat_server_submit(srv.handle, C.byref(rec), C.byref(t)))
+    srv._live[t.value] = req
+    return t.value
+
+
+def nat_server_wait(srv: Server, ticket: int, timeout_ms: float = -1.0):
+    """(status, result dict, per-mode report dicts); status NAT_E_PENDING
+    (result None) if the request has not ended within timeout_ms."""
+    res = nat_request_result()
+    st = lib().nat_server_wait(srv.handle, C.c_uint64(ticket), float(timeout_ms), C.byref(res))
+    if st == NAT_E_PENDING:
+        return st, None, None
+    req = srv._live.pop(ticket, None)
+    if req is None:
+        _check(st)
+    reps = [r.as_dict() for r in req.reports] if st in (NAT_OK, NAT_E_NOCONV) else None
+    return st, res.as_dict(), reps
+
+
+def nat_server_cancel(srv: Server, ticket: int) -> int:
+    return _check(lib().nat_server_cancel(srv.handle, C.c_uint64(ticket)))
+
+
+def nat_server_stats_read(srv: Server) -> dict:
+    s = nat_server_stats()
+    _check(lib().nat_server_stats_read(srv.handle, C.byref(s)))
+    return s.as_dict()
+
+
+def nat_server_destroy(srv: Server):
+    srv.close()

@@ -330,3 +330,79 @@ def config_batched(seed: int = BASE_SEED + 3, n_instances: int = 256, scale: flo
         qt, qb = random_face_queries(len(f), max(q, 1), seed * 1000 + i)
         out.append(MCWorkload(f"batch{i}", v, f, g, k, qt, qb, max(n, 2), seed * 1000 + i))
     return out
+
+
+@dataclass
+class ServedMesh:
+    vertices: np.ndarray
+    tris: np.ndarray
+    g_vertex: np.ndarray            # (pool_modes, V) complex128, per-vertex Neumann pool
+    g_tri: np.ndarray               # (dense_modes, T) complex128, per-triangle Neumann pool
+    q_tri: np.ndarray               # (pool_queries,) int32
+    q_b: np.ndarray                 # (pool_queries, 2) float64
+
+
+@dataclass
+class ServedRequest:
+    kind: str                       # "mc" or "dense"
+    mesh: int                       # index into the resident meshes
+    m0: int                         # first mode of the mesh's pool
+    k: np.ndarray                   # (n_modes,) wavenumbers
+    n_queries: int                  # Monte-Carlo: first Q queries of the pool
+    n_samples: int
+    seed: int
+    gap: float                      # unit-rate exponential inter-arrival gap
+
+    @property
+    def n_modes(self):
+        return len(self.k)
+
+    def pair_evals(self):
+        if self.kind != "mc":
+            return 0
+        n = self.n_samples
+        return self.n_modes * (n * (n - 1) + self.n_queries * n)
+
+
+def config_served(seed: int = BASE_SEED + 4, n_meshes: int = 64, n_requests: int = 2000,
+                  t_range=(1000, 50000), q_range=(1, 16384), n_range=(512, 2048),
+                  pool_modes: int = 64, dense_fraction: float = 0.1, dense_max_tris: int = 8000,
+                  dense_modes: int = 4):
+    """Resident cube-sphere meshes of T log-uniform in t_range and a request
+    stream over them.  Monte-Carlo requests: modes uniform {1..pool_modes}
+    (a contiguous slice of the mesh's Neumann pool, wavenumbers of their own,
+    log-uniform 200 Hz - 8 kHz), Q log-uniform in q_range (the first Q of the
+    mesh's query pool), N log-uniform in n_range.  Dense requests (a
+    dense_fraction share) go to meshes of at most dense_max_tris triangles
+    with 1..dense_modes modes.  Arrivals are Poisson: `gap` is a unit-rate
+    exponential, scaled by 1/rate by the caller."""
+    rng = np.random.default_rng([seed, 7])
+    meshes = []
+    for i in range(n_meshes):
+        t_target = int(log_uniform_int(rng, *t_range))
+        v, f, u = cubesphere_ellipsoid(seed * 1000 + i, max(t_target, 48))
+        g_v = sh_neumann(u, pool_modes, seed * 1000 + i)
+        c = u[f].mean(axis=1)
+        c /= np.linalg.norm(c, axis=1, keepdims=True)
+        g_t = sh_neumann(c, dense_modes, seed * 1000 + i + 500)
+        qt, qb = random_face_queries(len(f), q_range[1], seed * 1000 + i)
+        meshes.append(ServedMesh(v, f, g_v, g_t, qt, qb))
+    small = [i for i, m in enumerate(meshes) if len(m.tris) <= dense_max_tris]
+    reqs = []
+    for r in range(n_requests):
+        dense = bool(small) and rng.random() < dense_fraction
+        if dense:
+            mi = int(rng.choice(small))
+            M = int(rng.integers(1, dense_modes + 1))
+            m0 = int(rng.integers(0, dense_modes - M + 1))
+            q, n = 0, 0
+        else:
+            mi = int(rng.integers(0, n_meshes))
+            M = int(rng.integers(1, pool_modes + 1))
+            m0 = int(rng.integers(0, pool_modes - M + 1))
+            q = int(log_uniform_int(rng, *q_range))
+            n = int(log_uniform_int(rng, *n_range))
+        k = wavenumber(log_uniform_freqs(M, seed * 100000 + r))
+        reqs.append(ServedRequest("dense" if dense else "mc", mi, m0, k, q, max(n, 2),
+                                  seed * 100000 + r, float(rng.exponential(1.0))))
+    return meshes, reqs
