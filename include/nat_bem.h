@@ -31,7 +31,8 @@
  *    budget; a call that would exceed it returns NAT_E_BUDGET before
  *    allocating anything.
  *  - A context and everything made from it are used by one host thread at
- *    a time.
+ *    a time; a request server (nat_serve.h) runs its own worker threads on
+ *    its context alongside that thread.
  */
 #ifndef NAT_BEM_H
 #define NAT_BEM_H
@@ -102,7 +103,7 @@ void nat_ctx_destroy(nat_ctx* ctx);
 /* Bytes of device memory currently charged to the context. */
 size_t nat_ctx_bytes_in_use(const nat_ctx* ctx);
 
-/* ---- meshes (a1 of the hot path) ---------------------------------------- */
+/* ---- meshes (Section 4.1.1: surface, areas, sampling density) ----------- */
 
 /* Register a closed triangle mesh.  vertices: host double[n_vertices][3];
  * tris: host int32[n_tris][3], counter-clockwise seen from outside.  The
@@ -138,7 +139,7 @@ nat_status nat_mesh_vertex_queries(const nat_mesh* mesh, int32_t* tri, double* b
 
 void nat_mc_opts_default(nat_mc_opts* opts);
 
-/* a2: draw the N area-uniform samples of seed `seed`.  Sample j takes the
+/* Draw the N area-uniform samples of seed `seed`.  Sample j takes the
  * three SplitMix64 words at counters 3j, 3j+1, 3j+2 of stream 0, turns them
  * into u0, u1, u2 in [0,1) (top 53 bits), picks the smallest triangle t with
  * cumulative area > u0 |Gamma| and the point b1 = sqrt(u1)(1-u2),
@@ -147,7 +148,7 @@ void nat_mc_opts_default(nat_mc_opts* opts);
 nat_status nat_mcbem_samples(nat_mesh* mesh, int32_t n_samples, uint64_t seed, int32_t* tri,
                              double* bary, void* stream);
 
-/* a2-a5: the whole Monte-Carlo estimate of the surface pressure at Q query
+/* The whole Monte-Carlo estimate of the surface pressure at Q query
  * points for n_modes independent problems (k_m, g_m) on one mesh sharing one
  * sample set.  With N samples y_j, w = |Gamma|/N and disk radius eps:
  *   Stage A  (1/2) p_i - sum_{j: r_ij >= eps} w dG(y_i,y_j)/dn_j p_j
@@ -203,7 +204,7 @@ nat_status nat_mcbem_estimate_batch(nat_ctx* ctx, const nat_mc_job* jobs, int32_
 
 /* ---- dense collocation Burton-Miller BEM (Section 4, Section 4.1) -------- */
 
-/* a6: assemble A and B of A p = B g for piecewise-constant p and g with
+/* Assemble A and B of A p = B g for piecewise-constant p and g with
  * collocation at the triangle centroids x_i:
  *   A = I/2 - K - beta W,  B = -(S + beta K') - (beta/2) I,
  *   S_ij = int_{T_j} G(x_i, y), K_ij = int dG/dn_y, K'_ij = int dG/dn_x,
@@ -217,7 +218,7 @@ nat_status nat_mcbem_estimate_batch(nat_ctx* ctx, const nat_mc_job* jobs, int32_
 nat_status nat_bem_assemble(nat_mesh* mesh, double k, int32_t burton_miller,
                             nat_bem_op** out, void* stream);
 
-/* a7: solve A p = B g for n_rhs Neumann vectors by GMRES (x0 = 0, restart
+/* Solve A p = B g for n_rhs Neumann vectors by GMRES (x0 = 0, restart
  * = max_iter).  v_n: device complex [n_rhs][n_vertices or n_tris]
  * (per-vertex data is averaged over each triangle's corners); p_out:
  * device complex [n_rhs][n_tris] at the centroids; report: host

@@ -1,5 +1,5 @@
-// Sample generation and surface data (hot-path steps a2 and the point/data
-// streams the kernel sums read).
+// Sample generation and surface data (the sample set of the estimate and
+// the point/data streams the kernel sums read).
 //
 // Samples are area-uniform on the mesh (Section 4.1.1: density 1/|Gamma|).
 // Random words come from SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) used

@@ -57,48 +57,116 @@ __device__ __forceinline__ int32_t find_group(const GroupDev* __restrict__ g, in
     return lo;
 }
 
+__device__ __forceinline__ float uniform_f(float x)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+// The pairs of one LDS tile for the first MB modes of the group (MB is the
+// group width rounded up to a power of two; the padded modes carry zero
+// source data).  Per (pair, mode):
+//   RHS     acc += (1/r) e^{i th} a
+//   MATVEC  acc += q e^{i th} (ikr - 1) b,           q = (d.n) / r^3
+//   EVAL    acc += e^{i th} (a/r + q (ikr - 1) b)
+// with th = 2 pi fract(kappa r) taken by the hardware sine and cosine.
+template <int OP, int MB>
+__device__ __forceinline__ void tile_pairs(const float (&s_pos)[6][kTS],
+                                           const float2 (*s_a)[kMB], const float2 (*s_b)[kMB],
+                                           float tx, float ty,
+                                           float tz, float eps2, const float (&kap)[kMB],
+                                           const float (&kk)[kMB], float (&ar)[kMB], float (&ai)[kMB])
+{
+    constexpr bool kA = (OP == OP_RHS || OP == OP_EVAL);
+    constexpr bool kB = (OP == OP_MATVEC || OP == OP_EVAL);
+    for (int c = 0; c < kTS; ++c) {
+        float2 av[MB], bv[MB];
+#pragma unroll
+        for (int mm = 0; mm < MB; ++mm) {
+            if (kA)
+                av[mm] = s_a[c][mm];
+            if (kB)
+                bv[mm] = s_b[c][mm];
+        }
+        const float dx = s_pos[0][c] - tx;
+        const float dy = s_pos[1][c] - ty;
+        const float dz = s_pos[2][c] - tz;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const float rinv = (r2 >= eps2) ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+        const float r = r2 * rinv;
+        float q = 0.0f;
+        if (kB) {
+            const float dn = fmaf(dz, s_pos[5][c], fmaf(dy, s_pos[4][c], dx * s_pos[3][c]));
+            q = dn * (rinv * rinv) * rinv;
+        }
+#pragma unroll
+        for (int mm = 0; mm < MB; ++mm) {
+            const float ph = __builtin_amdgcn_fractf(r * kap[mm]);
+            const float sn = __builtin_amdgcn_sinf(ph);
+            const float cs = __builtin_amdgcn_cosf(ph);
+            if (OP == OP_RHS) {
+                const float vr = fmaf(cs, av[mm].x, -(sn * av[mm].y));
+                const float vi = fmaf(cs, av[mm].y, sn * av[mm].x);
+                ar[mm] = fmaf(rinv, vr, ar[mm]);
+                ai[mm] = fmaf(rinv, vi, ai[mm]);
+            } else {
+                const float kr = r * kk[mm];
+                const float ur = fmaf(-kr, bv[mm].y, -bv[mm].x);
+                const float ui = fmaf(kr, bv[mm].x, -bv[mm].y);
+                if (OP == OP_MATVEC) {
+                    const float vr = fmaf(cs, ur, -(sn * ui));
+                    const float vi = fmaf(cs, ui, sn * ur);
+                    ar[mm] = fmaf(q, vr, ar[mm]);
+                    ai[mm] = fmaf(q, vi, ai[mm]);
+                } else {
+                    const float zr = fmaf(q, ur, rinv * av[mm].x);
+                    const float zi = fmaf(q, ui, rinv * av[mm].y);
+                    ar[mm] = fmaf(-sn, zi, fmaf(cs, zr, ar[mm]));
+                    ai[mm] = fmaf(sn, zr, fmaf(cs, zi, ai[mm]));
+                }
+            }
+        }
+    }
+}
+
 template <int OP>
 __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
 {
     constexpr bool kA = (OP == OP_RHS || OP == OP_EVAL);
     constexpr bool kB = (OP == OP_MATVEC || OP == OP_EVAL);
     __shared__ float s_pos[6][kTS];
-    __shared__ float2 s_a[kA ? kMB : 1][kTS];
-    __shared__ float2 s_b[kB ? kMB : 1][kTS];
+    __shared__ float2 s_a[kA ? kTS : 1][kMB];
+    __shared__ float2 s_b[kB ? kTS : 1][kMB];
 
     const int32_t tid = threadIdx.x;
     const int64_t n_items = *p.n_items;
     const int32_t n_groups = *p.n_groups;
 
     for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const GroupDev G = p.groups[find_group(p.groups, n_groups, item)];
-        const InstDev I = p.inst[G.inst];
+        const GroupDev& G = p.groups[find_group(p.groups, n_groups, item)];
+        const int32_t nm = __builtin_amdgcn_readfirstlane(G.nm);
+        const int32_t inst = __builtin_amdgcn_readfirstlane(G.inst);
+        const int32_t nsplit = __builtin_amdgcn_readfirstlane(G.nsplit);
         const int64_t local = item - G.item0;
-        const int32_t tile = static_cast<int32_t>(local / G.nsplit);
-        const int32_t split = static_cast<int32_t>(local % G.nsplit);
+        const InstDev& I = p.inst[inst];
+        const int32_t tile = static_cast<int32_t>(local / nsplit);
+        const int32_t split = static_cast<int32_t>(local % nsplit);
         const int32_t NS = I.n;
         const int32_t NT = (OP == OP_EVAL) ? I.q : I.n;
         const float* t32 = (OP == OP_EVAL) ? I.q32 : I.s32;
         const int32_t per_split = (OP == OP_EVAL) ? I.per_split_b : I.per_split_a;
 
         int32_t sys[kMB];
-        bool live[kMB];
         float kap[kMB], kk[kMB];
-        int64_t src_off[kMB];
-#pragma unroll
-        for (int mm = 0; mm < kMB; ++mm) {
-            const int32_t sl = mm < G.nm ? mm : G.nm - 1;
-            sys[mm] = G.sys[sl];
-            const SysDev& S = p.sys[sys[mm]];
-            live[mm] = mm < G.nm && (!p.active || p.active[sys[mm]]);
-            kap[mm] = S.kappa32;
-            kk[mm] = S.k32;
-            src_off[mm] = S.off_n;
-        }
         bool any = false;
 #pragma unroll
-        for (int mm = 0; mm < kMB; ++mm)
-            any |= live[mm];
+        for (int mm = 0; mm < kMB; ++mm) {
+            const int32_t sl = mm < nm ? mm : nm - 1;
+            sys[mm] = __builtin_amdgcn_readfirstlane(G.sys[sl]);
+            const SysDev& S = p.sys[sys[mm]];
+            any |= mm < nm && (!p.active || p.active[sys[mm]]);
+            kap[mm] = uniform_f(S.kappa32);
+            kk[mm] = uniform_f(S.k32);
+        }
         if (!any)
             continue;  // uniform across the workgroup
 
@@ -127,11 +195,12 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
             }
             for (int e = tid; e < kMB * kTS; e += kThreads) {
                 const int mm = e / kTS, c = e % kTS;
-                const bool ok = c < cnt && mm < G.nm;
+                const bool ok = c < cnt && mm < nm;
+                const int64_t o = p.sys[sys[mm]].off_n + j0 + c;
                 if (kA)
-                    s_a[mm][c] = ok ? p.a32[src_off[mm] + j0 + c] : make_float2(0.0f, 0.0f);
+                    s_a[c][mm] = ok ? p.a32[o] : make_float2(0.0f, 0.0f);
                 if (kB)
-                    s_b[mm][c] = ok ? p.b32[src_off[mm] + j0 + c] : make_float2(0.0f, 0.0f);
+                    s_b[c][mm] = ok ? p.b32[o] : make_float2(0.0f, 0.0f);
             }
             __syncthreads();
 
@@ -139,43 +208,14 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
 #pragma unroll
             for (int mm = 0; mm < kMB; ++mm)
                 ar[mm] = ai[mm] = 0.0f;
-
-            for (int c = 0; c < kTS; ++c) {
-                const float dx = s_pos[0][c] - tx;
-                const float dy = s_pos[1][c] - ty;
-                const float dz = s_pos[2][c] - tz;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                const float rinv = (r2 >= eps2) ? __builtin_amdgcn_rsqf(r2) : 0.0f;
-                const float r = r2 * rinv;
-                float q = 0.0f;
-                if (kB) {
-                    const float dn = dx * s_pos[3][c] + dy * s_pos[4][c] + dz * s_pos[5][c];
-                    q = dn * (rinv * rinv * rinv);
-                }
-#pragma unroll
-                for (int mm = 0; mm < kMB; ++mm) {
-                    if (mm >= G.nm)
-                        break;  // uniform: the group's width
-                    const float ph = __builtin_amdgcn_fractf(r * kap[mm]);
-                    const float sn = __builtin_amdgcn_sinf(ph);
-                    const float cs = __builtin_amdgcn_cosf(ph);
-                    float zr = 0.0f, zi = 0.0f;
-                    if (kB) {
-                        const float2 b = s_b[mm][c];
-                        const float kr = r * kk[mm];
-                        const float qbr = q * b.x, qbi = q * b.y;
-                        zr = -(qbr + kr * qbi);
-                        zi = kr * qbr - qbi;
-                    }
-                    if (kA) {
-                        const float2 av = s_a[mm][c];
-                        zr += rinv * av.x;
-                        zi += rinv * av.y;
-                    }
-                    ar[mm] += cs * zr - sn * zi;
-                    ai[mm] += cs * zi + sn * zr;
-                }
-            }
+            if (nm > 4)
+                tile_pairs<OP, 8>(s_pos, s_a, s_b, tx, ty, tz, eps2, kap, kk, ar, ai);
+            else if (nm > 2)
+                tile_pairs<OP, 4>(s_pos, s_a, s_b, tx, ty, tz, eps2, kap, kk, ar, ai);
+            else if (nm > 1)
+                tile_pairs<OP, 2>(s_pos, s_a, s_b, tx, ty, tz, eps2, kap, kk, ar, ai);
+            else
+                tile_pairs<OP, 1>(s_pos, s_a, s_b, tx, ty, tz, eps2, kap, kk, ar, ai);
 #pragma unroll
             for (int mm = 0; mm < kMB; ++mm) {
                 two_sum_fold(hr[mm], lr[mm], ar[mm]);
@@ -186,7 +226,7 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
         if (i < NT) {
 #pragma unroll
             for (int mm = 0; mm < kMB; ++mm) {
-                if (mm < G.nm) {
+                if (mm < nm) {
                     const SysDev& S = p.sys[sys[mm]];
                     const int64_t off = (OP == OP_EVAL) ? S.off_pb : S.off_pa;
                     p.partial[off + (int64_t)split * NT + i] =
