@@ -315,6 +315,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=["batched", "precision", "served"], default="batched")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2506_06190_amd", "tune",
+                                                         "kernel_sum_tiles.json"))
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-max-batch", type=int, default=64)
@@ -332,9 +334,17 @@ def main():
 
     dev = "cuda:0"
     ctx = nat.Context(0)
+    had_cache = os.path.exists(args.tune_cache)
+    os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
+    t0 = time.perf_counter()
+    table = nat.nat_autotune(ctx, args.tune_cache)
+    tune = {"cache": os.path.relpath(args.tune_cache, ROOT), "source": "cache" if had_cache else "sweep",
+            "seconds": round(time.perf_counter() - t0, 2), "items_a": table["items_a"],
+            "items_b": table["items_b"]}
+    log(f"kernel-sum tiling from {tune['source']} in {tune['seconds']} s")
     out = {"metric": METRIC, "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32", "data": "synthetic"}
+           "dtype": "f32", "data": "synthetic", "autotune": tune}
     if args.workload == "batched":
         res = run_batched(nat, torch, ctx, args, dev)
         out.update({k: res.pop(k) for k in ("value", "ms_per_step", "config")})

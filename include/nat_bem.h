@@ -232,6 +232,33 @@ nat_status nat_bem_solve(nat_bem_op* op, const double* v_n, int32_t n_rhs, int32
 nat_status nat_bem_op_matrices(const nat_bem_op* op, double* A_out, double* B_out, void* stream);
 void nat_bem_op_destroy(nat_bem_op* op);
 
+/* ---- tiling autotuner ----------------------------------------------------- */
+
+/* The FP32 kernel sums cut each group of up to 8 modes of an instance into
+ * work items of 256 targets x a share of the sources; the number of source
+ * shares follows from how many items a group should span, looked up per
+ * size bucket b = clamp(floor(log2 n) - 6, 0, 9) of the target count n
+ * (items_a: sums over the N samples, by N; items_b: sums at the Q queries,
+ * by Q).  The defaults are 64 everywhere.  The split of an instance depends
+ * only on its own sizes and the context's table, so results stay bit-for-bit
+ * equal alone and in any batch on one context; two tables may round
+ * differently in FP32. */
+#define NAT_TUNE_FORCE 1  /* sweep even when the cache holds a table for this device */
+
+/* Fill the context's table: read it from the JSON file cache_path when it
+ * holds one for this device (architecture and CU count), otherwise time
+ * every bucket's candidates (16 .. 512 items) on synthetic sums, one mode
+ * group alone and many at once, keep the candidate with the smallest summed
+ * slowdown against each regime's best, and write the table to cache_path
+ * (NULL: no cache).  Runs on `stream`, using the context's workspace;
+ * blocks until done (a few seconds). */
+nat_status nat_autotune(nat_ctx* ctx, const char* cache_path, int32_t flags, void* stream);
+/* Copy the table (host int32[10] each); tuned (may be NULL) is 1 after a
+ * sweep, a cache load or nat_tune_set, else 0. */
+nat_status nat_tune_get(const nat_ctx* ctx, int32_t* items_a, int32_t* items_b, int32_t* tuned);
+/* Set the table (host int32[10] each, every entry 1 .. 2^20). */
+nat_status nat_tune_set(nat_ctx* ctx, const int32_t* items_a, const int32_t* items_b);
+
 /* ---- per-kernel timing ---------------------------------------------------- */
 
 /* Timing of one kernel class accumulated while profiling is on: launches,

@@ -24,7 +24,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-I", str(ROOT / "include"), "-I", str(SRC), "-Wall", "-Wno-unused-function",
           "-Wno-unused-command-line-argument"]
 PER_FILE = {"nat_api.hip": ["-ffp-contract=off"]}
-SOURCES = ["nat_api.hip", "nat_solver.hip", "nat_server.hip", "serve_core.cpp", "k_sample.hip",
+SOURCES = ["nat_api.hip", "nat_solver.hip", "nat_server.hip", "nat_autotune.hip", "serve_core.cpp",
+           "k_sample.hip",
            "k_sum64.hip", "k_sum32.hip", "k_gmres.hip", "k_bem.hip"]
 
 

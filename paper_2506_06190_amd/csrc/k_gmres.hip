@@ -140,12 +140,23 @@ __global__ void __launch_bounds__(kRows) k_orth_dots(GmresBatch g)
             if (g.partial) {
                 // matvec epilogue: w = v_j / 2 - (sum of the FP32 split partials)
                 float hr = 0.0f, hi = 0.0f, lr = 0.0f, li = 0.0f;
-                for (int32_t sp = 0; sp < S.nsplit_a; ++sp) {
-                    const float4 v = g.partial[S.off_pa + (int64_t)sp * n + t];
-                    fold2(hr, lr, v.x);
-                    fold2(hi, li, v.y);
-                    lr += v.z;
-                    li += v.w;
+                const float4* pp = g.partial + S.off_pa + t;
+                for (int32_t sp0 = 0; sp0 < S.nsplit_a; sp0 += 8) {
+                    // issue the group's loads together, fold in split order
+                    float4 v[8];
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        v[c] = sp0 + c < S.nsplit_a ? pp[(int64_t)(sp0 + c) * n]
+                                                    : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        if (sp0 + c < S.nsplit_a) {
+                            fold2(hr, lr, v[c].x);
+                            fold2(hi, li, v[c].y);
+                            lr += v[c].z;
+                            li += v[c].w;
+                        }
+                    }
                 }
                 const double ar = static_cast<double>(hr) + static_cast<double>(lr);
                 const double ai = static_cast<double>(hi) + static_cast<double>(li);
@@ -186,10 +197,18 @@ __global__ void __launch_bounds__(kRows) k_orth_update(GmresBatch g, int32_t pas
         __syncthreads();
         for (int i = threadIdx.x; i <= j; i += kRows) {
             double hr = 0.0, hi = 0.0;
-            for (int c = 0; c < S.nch; ++c) {
-                const double2 v = dp[(size_t)c * mm1 + i];
-                hr += v.x;
-                hi += v.y;
+            for (int c0 = 0; c0 < S.nch; c0 += 8) {
+                double2 v[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    v[c] = c0 + c < S.nch ? dp[(size_t)(c0 + c) * mm1 + i] : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    if (c0 + c < S.nch) {
+                        hr += v[c].x;
+                        hi += v[c].y;
+                    }
+                }
             }
             s_h[i] = make_double2(hr, hi);
             if (chunk == 0) {
@@ -205,24 +224,22 @@ __global__ void __launch_bounds__(kRows) k_orth_update(GmresBatch g, int32_t pas
         double2 wt = make_double2(0.0, 0.0);
         if (t < n) {
             wt = w[t];
+            // groups of 16 basis vectors, the last one predicated, so every
+            // group's loads are in flight together; subtraction in index order
             constexpr int U = 16;
-            int i = 0;
-            for (; i + U <= j + 1; i += U) {
+            for (int i = 0; i <= j; i += U) {
                 double2 v[U];
 #pragma unroll
                 for (int c = 0; c < U; ++c)
-                    v[c] = Vs[(size_t)(i + c) * n + t];
+                    v[c] = i + c <= j ? Vs[(size_t)(i + c) * n + t] : make_double2(0.0, 0.0);
 #pragma unroll
                 for (int c = 0; c < U; ++c) {
-                    const double2 d = cmul(s_h[i + c], v[c]);
-                    wt.x -= d.x;
-                    wt.y -= d.y;
+                    if (i + c <= j) {
+                        const double2 d = cmul(s_h[i + c], v[c]);
+                        wt.x -= d.x;
+                        wt.y -= d.y;
+                    }
                 }
-            }
-            for (; i <= j; ++i) {
-                const double2 d = cmul(s_h[i], Vs[(size_t)i * n + t]);
-                wt.x -= d.x;
-                wt.y -= d.y;
             }
             w[t] = wt;
         }

@@ -254,12 +254,22 @@ k_reduce32(const Sum32Batch p, const double2* __restrict__ g_tgt, double2* __res
     const int32_t nsplit = (OP == OP_EVAL) ? S.nsplit_b : S.nsplit_a;
     const int64_t off = (OP == OP_EVAL) ? S.off_pb : S.off_pa;
     float hr = 0.0f, hi = 0.0f, lr = 0.0f, li = 0.0f;
-    for (int32_t sp = 0; sp < nsplit; ++sp) {
-        const float4 v = p.partial[off + (int64_t)sp * NT + i];
-        two_sum_fold(hr, lr, v.x);
-        two_sum_fold(hi, li, v.y);
-        lr += v.z;
-        li += v.w;
+    const float4* pp = p.partial + off + i;
+    for (int32_t sp0 = 0; sp0 < nsplit; sp0 += 8) {
+        // issue the group's loads together, fold in split order
+        float4 v[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            v[c] = sp0 + c < nsplit ? pp[(int64_t)(sp0 + c) * NT] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            if (sp0 + c < nsplit) {
+                two_sum_fold(hr, lr, v[c].x);
+                two_sum_fold(hi, li, v[c].y);
+                lr += v[c].z;
+                li += v[c].w;
+            }
+        }
     }
     const double accr = static_cast<double>(hr) + static_cast<double>(lr);
     const double acci = static_cast<double>(hi) + static_cast<double>(li);
@@ -288,13 +298,14 @@ k_weight32(const SysDev* __restrict__ sys, const double2* __restrict__ src, doub
 
 }  // namespace
 
-void split_rule(int32_t n_targets, int32_t n_sources, int32_t* nsplit, int32_t* per_split)
+void split_rule(int32_t n_targets, int32_t n_sources, int32_t want_items, int32_t* nsplit,
+                int32_t* per_split)
 {
-    // enough splits that one mode group spans >= 64 work items, never more
-    // than one split per LDS tile of sources
+    // enough splits that one mode group spans >= want_items work items,
+    // never more than one split per LDS tile of sources
     const int32_t tiles = (n_targets + kThreads - 1) / kThreads;
     const int32_t src_tiles = (n_sources + kTS - 1) / kTS;
-    int32_t want = (64 + tiles - 1) / tiles;
+    int32_t want = (want_items + tiles - 1) / tiles;
     if (want < 1)
         want = 1;
     if (want > src_tiles)

@@ -411,6 +411,7 @@ nat_status nat_ctx_create(int32_t device, size_t hbm_budget_bytes, nat_ctx** out
         return fail(NAT_E_INTERNAL, "out of host memory");
     c->device = device;
     c->budget = hbm_budget_bytes;
+    nat::tune_defaults(&c->tune);
     // quadrature rules of the dense assembly: far 3-point, angular 16-point
     double rules[2 * 3 + 2 * 16];
     nat::gauss_legendre01(3, rules, rules + 3);

@@ -46,8 +46,23 @@ struct NatScratch {
     std::vector<unsigned char> graph_key;
 };
 
+namespace nat {
+// Work items wanted per mode group of the FP32 kernel sums, by size bucket
+// (floor(log2 n) clamped to [6, 15]); the source split count of an instance
+// follows from it and the instance's own sizes.
+constexpr int kTuneBuckets = 10;
+struct TuneTable {
+    int32_t items_a[kTuneBuckets];  // sums over the samples, by the sample count N
+    int32_t items_b[kTuneBuckets];  // sums at the queries, by the query count Q
+    int32_t tuned = 0;              // 0: defaults, 1: swept or loaded
+};
+int32_t tune_bucket(int32_t n);
+void tune_defaults(TuneTable* t);
+}  // namespace nat
+
 struct nat_ctx {
     int32_t device = 0;
+    nat::TuneTable tune;
     std::mutex mu;       // guards the ledger and the timing lists
     // per-kernel timing (off unless enabled)
     bool prof = false;
@@ -270,10 +285,15 @@ struct Sum32Batch {
     float4* partial;                   // split partials (hi.re, hi.im, lo.re, lo.im)
 };
 
-// source splits of a sum with n_targets targets over n_sources sources; a
-// function of the instance's own sizes only
-void split_rule(int32_t n_targets, int32_t n_sources, int32_t* nsplit, int32_t* per_split);
+// source splits of a sum with n_targets targets over n_sources sources: a
+// function of the instance's own sizes and the wanted items per mode group
+void split_rule(int32_t n_targets, int32_t n_sources, int32_t want_items, int32_t* nsplit,
+                int32_t* per_split);
 int32_t target_tiles(int32_t n_targets);
+// workgroups of the persistent kernel-sum launches: the GMRES matvec, and
+// the right-hand side and query stages
+constexpr int32_t kGridMatvec = 1024;
+constexpr int32_t kGridStage = 4096;
 hipError_t launch_sum32_batch(int32_t op, const Sum32Batch& p, int32_t grid, hipStream_t s,
                               const ProfSlot& ev = ProfSlot());
 // RHS: out_n[off_n + i] = b_i; EVAL: sys.out_q[i] = p(x_i)

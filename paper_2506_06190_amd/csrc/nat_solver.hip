@@ -19,7 +19,7 @@ constexpr double kTwoPi = 6.283185307179586;
 // iterations per captured run; also how far the host may run ahead of the
 // device before it waits to refresh the running-system lists
 constexpr int32_t kLag = 4;
-constexpr int32_t kMaxGrid = 1024;
+constexpr int32_t kMaxGrid = kGridMatvec;
 
 inline void cpu_relax() { __builtin_ia32_pause(); }
 
@@ -309,9 +309,9 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         I.q = J.Q;
         I.n_modes = J.M;
         I.sys0 = q;
-        split_rule(J.N, J.N, &I.nsplit_a, &I.per_split_a);
+        split_rule(J.N, J.N, ctx->tune.items_a[tune_bucket(J.N)], &I.nsplit_a, &I.per_split_a);
         if (J.Q > 0)
-            split_rule(J.Q, J.N, &I.nsplit_b, &I.per_split_b);
+            split_rule(J.Q, J.N, ctx->tune.items_b[tune_bucket(J.Q)], &I.nsplit_b, &I.per_split_b);
         const double area = J.mesh->area_total;
         I.w = area / static_cast<double>(J.N);
         I.eps = opts->eps_scale * std::sqrt(area / (M_PI * static_cast<double>(J.N)));
@@ -604,7 +604,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         sb.n_items = dcnt64 + 0;
         sb.a32 = a32;
         const ProfSlot ev = prof_slot(ctx, PK_SUM32_RHS, 24.0 * pairs_rhs);
-        const int32_t grid = static_cast<int32_t>(items_rhs < kMaxGrid * 4 ? items_rhs : kMaxGrid * 4);
+        const int32_t grid = static_cast<int32_t>(items_rhs < kGridStage ? items_rhs : kGridStage);
         NAT_HIP(launch_sum32_batch(OP_RHS, sb, grid, s, ProfSlot{ev.start, nullptr}));
         NAT_HIP(launch_reduce32_batch(OP_RHS, sb, S, max_n, gj, bvec, s, ProfSlot{nullptr, ev.stop}));
     } else {
@@ -653,7 +653,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
             se.a32 = a32;
             se.b32 = v32;
             const ProfSlot ev = prof_slot(ctx, PK_SUM32_EVAL, 47.0 * pairs_eval);
-            const int32_t grid = static_cast<int32_t>(items_eval < kMaxGrid * 4 ? items_eval : kMaxGrid * 4);
+            const int32_t grid = static_cast<int32_t>(items_eval < kGridStage ? items_eval : kGridStage);
             NAT_HIP(launch_sum32_batch(OP_EVAL, se, grid, s, ProfSlot{ev.start, nullptr}));
             NAT_HIP(launch_reduce32_batch(OP_EVAL, se, S, max_q, gq, nullptr, s, ProfSlot{nullptr, ev.stop}));
         } else {

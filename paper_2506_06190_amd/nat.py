@@ -31,6 +31,8 @@ class NatError(RuntimeError):
 
 
 NAT_MC_NO_GRAPH = 1
+NAT_TUNE_FORCE = 1
+TUNE_BUCKETS = 10
 
 
 class nat_mc_opts(C.Structure):
@@ -112,6 +114,9 @@ _SIGS = {
     "nat_bem_op_destroy": ([_P], None),
     "nat_profile_enable": ([_P, C.c_int32], C.c_int),
     "nat_profile_read": ([_P, _P, C.c_int32], C.c_int32),
+    "nat_autotune": ([_P, C.c_char_p, C.c_int32, _P], C.c_int),
+    "nat_tune_get": ([_P, _P, _P, C.POINTER(C.c_int32)], C.c_int),
+    "nat_tune_set": ([_P, _P, _P], C.c_int),
     "nat_server_opts_default": ([C.POINTER(nat_server_opts)], None),
     "nat_server_create": ([_P, C.POINTER(nat_server_opts), C.POINTER(_P)], C.c_int),
     "nat_server_submit": ([_P, C.POINTER(nat_request), C.POINTER(C.c_uint64)], C.c_int),
@@ -292,6 +297,30 @@ def nat_profile_read(ctx: Context):
         out[b.name.decode()] = {"launches": b.launches, "total_ms": b.total_ms, "flops": b.flops,
                                 "avg_ms": b.total_ms / max(b.launches, 1)}
     return out
+
+
+def nat_autotune(ctx: Context, cache_path=None, force: bool = False, stream=None):
+    """Fill the context's tiling table (from the cache or by a sweep); returns it."""
+    path = None if cache_path is None else str(cache_path).encode()
+    _check(lib().nat_autotune(ctx.handle, path, NAT_TUNE_FORCE if force else 0, _stream(stream)))
+    return nat_tune_get(ctx)
+
+
+def nat_tune_get(ctx: Context):
+    """{"items_a": [10 ints], "items_b": [10 ints], "tuned": bool}"""
+    a = np.zeros(TUNE_BUCKETS, dtype=np.int32)
+    b = np.zeros(TUNE_BUCKETS, dtype=np.int32)
+    t = C.c_int32()
+    _check(lib().nat_tune_get(ctx.handle, a.ctypes.data_as(_P), b.ctypes.data_as(_P), C.byref(t)))
+    return {"items_a": a.tolist(), "items_b": b.tolist(), "tuned": bool(t.value)}
+
+
+def nat_tune_set(ctx: Context, items_a, items_b):
+    a = np.ascontiguousarray(items_a, dtype=np.int32)
+    b = np.ascontiguousarray(items_b, dtype=np.int32)
+    if a.shape != (TUNE_BUCKETS,) or b.shape != (TUNE_BUCKETS,):
+        raise ValueError(f"tables must have {TUNE_BUCKETS} entries")
+    _check(lib().nat_tune_set(ctx.handle, a.ctypes.data_as(_P), b.ctypes.data_as(_P)))
 
 
 def nat_mc_opts_default() -> nat_mc_opts:

@@ -125,3 +125,31 @@ def test_batch_fp64_plain_matches_oracle(ctx):
             assert np.linalg.norm(got[m] - ref["p"][m]) <= 1e-10 * np.linalg.norm(ref["p"][m])
     for m in meshes:
         m.close()
+
+
+def test_full_batched_workload_sampled(ctx):
+    """The headline workload at full size, in the form the benchmark times
+    (one batch of 256 instances, graph-replayed GMRES): every output finite,
+    and sampled (instance, mode) results against the FP64 oracle."""
+    wls = W.config_batched()
+    meshes = [nat.Mesh(ctx, wl.vertices, wl.tris) for wl in wls]
+    jobs = [nat.McJob(m, torch.from_numpy(wl.g).to(DEV), wl.k, torch.from_numpy(wl.q_tri).to(DEV),
+                      torch.from_numpy(wl.q_b).to(DEV), wl.n_samples, wl.seed)
+            for wl, m in zip(wls, meshes)]
+    _say(f"full batch: {len(jobs)} instances, {sum(j.n_modes for j in jobs)} systems")
+    reps = nat.nat_mcbem_estimate_batch(ctx, jobs, nat.nat_mc_opts_default(), allow_noconv=True)
+    torch.cuda.synchronize()
+    assert all(bool(torch.isfinite(torch.view_as_real(j.p_out)).all()) for j in jobs)
+    for i in (0, 37, 128, 255):
+        wl = wls[i]
+        modes = sorted({0, wl.n_modes - 1})
+        ref = O.mcbem(wl.vertices, wl.tris, wl.g[modes], wl.k[modes], wl.q_tri, wl.q_b,
+                      wl.n_samples, wl.seed, tol=1e-6)
+        got = jobs[i].p_out.cpu().numpy()[modes]
+        for a, m in enumerate(modes):
+            e = float(np.linalg.norm(got[a] - ref["p"][a]) / np.linalg.norm(ref["p"][a]))
+            _say(f"  instance {i} (T={len(wl.tris)}, N={wl.n_samples}, Q={wl.n_queries}) mode {m}: "
+                 f"rel L2 {e:.2e}, iters gpu {reps[i][m]['iters']} oracle {ref['iters'][a]}")
+            assert e <= 1e-3
+    for m in meshes:
+        m.close()
