@@ -93,6 +93,8 @@ def run_batched(nat, torch, ctx, args, dev):
     nat.nat_profile_enable(ctx, False)
     roof = roofline_from(prof)
     roof["timing_pass"] = "second pass over the same steps, eager dispatch, events on each dispatch"
+    roof["traffic"] = traffic_from_profile()
+    roof["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)"
     out = {
         "value": alg * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
         "config": {"workload": "batched: 256 cube-sphere instances, 2k-40k tri, 8-64 modes, "
@@ -263,6 +265,115 @@ def run_served(nat, torch, ctx, args, dev):
     }
 
 
+# ---------------------------------------------------------------- HBM traffic
+# The counter passes are separate runs of this script under rocprofv3:
+#   rocprofv3 --pmc FETCH_SIZE -d D1 -o run -- python3 bench.py --pmc-pass
+#   rocprofv3 --pmc WRITE_SIZE -d D2 -o run -- python3 bench.py --pmc-pass
+#   python3 bench.py --pmc-summarize D1 D2
+# --pmc-pass copies a 1 GiB buffer (the calibration kernel of known traffic)
+# and then runs one headline step with direct launches; --pmc-summarize
+# scales the matvec kernel's per-dispatch counters by the copy's measured /
+# true bytes and writes TRAFFIC_FILE, stamped with a hash of the kernel
+# source so the bench reports the figure only while the kernel is unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sum32_matvec_batched_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2506_06190_amd", "csrc", "k_sum32.hip")
+COPY_BYTES = 1 << 30
+
+
+def kernel_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def run_pmc_pass(nat, torch, ctx, args, dev):
+    import workloads as W
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    wls = W.config_batched()
+    meshes, jobs = make_jobs(nat, torch, ctx, wls, dev)
+    opts = nat.nat_mc_opts_default()
+    opts.flags = nat.NAT_MC_NO_GRAPH
+    nat.nat_mcbem_estimate_batch(ctx, jobs, opts, allow_noconv=True)
+    torch.cuda.synchronize()
+    for m in meshes:
+        m.close()
+    log("pmc pass done")
+
+
+def _counter_rows(d):
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            rows += list(csv.DictReader(f))
+    if not rows:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    return rows
+
+
+def pmc_summarize(d_fetch, d_write):
+    out = {}
+    for name, d in (("FETCH_SIZE", d_fetch), ("WRITE_SIZE", d_write)):
+        per = {}
+        for r in _counter_rows(d):
+            if r.get("Counter_Name") != name:
+                continue
+            key = (r["Kernel_Name"], r.get("Dispatch_Id", r.get("Correlation_Id")))
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"]) * 1024.0  # KiB per dispatch
+        copy = [v for (k, _), v in per.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+        mv = [v for (k, _), v in per.items() if "k_sum32ILi1E" in k]
+        if not copy or not mv:
+            raise SystemExit(f"{name}: copy kernel or matvec kernel not found")
+        big = max(copy)
+        out[name] = {"scale": COPY_BYTES / big, "copy_measured": big, "dispatches": len(mv),
+                     "per_launch_raw": sum(mv) / len(mv)}
+    f, w = out["FETCH_SIZE"], out["WRITE_SIZE"]
+    fetch = f["per_launch_raw"] * f["scale"]
+    write = w["per_launch_raw"] * w["scale"]
+    lines = [
+        "# HBM traffic of k_sum32<OP_MATVEC> (batched headline step, direct launches)",
+        "# commands (run from the repository root, TMPDIR=/tmp):",
+        "#   rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o run -- python3 bench.py --pmc-pass",
+        "#   rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o run -- python3 bench.py --pmc-pass",
+        "#   python3 bench.py --pmc-summarize gpurun_out/pmc_fetch gpurun_out/pmc_write",
+        f"kernel_source_sha256_16: {kernel_hash()}",
+        f"matvec_dispatches: {f['dispatches']}",
+        f"copy_bytes_true: {COPY_BYTES}",
+        f"copy_fetch_measured_bytes: {f['copy_measured']:.0f}",
+        f"copy_write_measured_bytes: {w['copy_measured']:.0f}",
+        f"fetch_scale: {f['scale']:.4f}",
+        f"write_scale: {w['scale']:.4f}",
+        f"fetch_bytes_per_launch_scaled: {fetch:.0f}",
+        f"write_bytes_per_launch_scaled: {write:.0f}",
+        f"traffic_bytes_per_launch: {fetch + write:.0f}",
+    ]
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def traffic_from_profile():
+    """Scaled HBM bytes per matvec launch, or None when absent or stale."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def run_precision(nat, torch, ctx, args, dev, with_plain=True):
     import numpy as np
     import workloads as W
@@ -315,6 +426,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=["batched", "precision", "served"], default="batched")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--pmc-pass", action="store_true")
+    ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2506_06190_amd", "tune",
                                                          "kernel_sum_tiles.json"))
     ap.add_argument("--serve-requests", type=int, default=1000)
@@ -324,6 +437,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
+    if args.pmc_summarize:
+        pmc_summarize(*args.pmc_summarize)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is "
               "described in the design notes but not part of this build.", file=sys.stderr)
@@ -334,6 +450,11 @@ def main():
 
     dev = "cuda:0"
     ctx = nat.Context(0)
+    if args.pmc_pass:
+        nat.nat_autotune(ctx, args.tune_cache)
+        run_pmc_pass(nat, torch, ctx, args, dev)
+        ctx.close()
+        return
     had_cache = os.path.exists(args.tune_cache)
     os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
     t0 = time.perf_counter()

@@ -172,6 +172,10 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
 
         const int32_t i = tile * kThreads + tid;
         const int32_t ic = i < NT ? i : NT - 1;
+        // a wave whose 64 targets all lie past the end of a ragged last tile
+        // only helps stage the LDS tiles
+        const bool wave_live =
+            __builtin_amdgcn_readfirstlane(tile * kThreads + (tid & ~63)) < NT;
         const float tx = t32[ic], ty = t32[NT + ic], tz = t32[2 * NT + ic];
         const float eps2 = I.eps2;
 
@@ -208,7 +212,9 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
 #pragma unroll
             for (int mm = 0; mm < kMB; ++mm)
                 ar[mm] = ai[mm] = 0.0f;
-            if (nm > 4)
+            if (!wave_live)
+                ;
+            else if (nm > 4)
                 tile_pairs<OP, 8>(s_pos, s_a, s_b, tx, ty, tz, eps2, kap, kk, ar, ai);
             else if (nm > 2)
                 tile_pairs<OP, 4>(s_pos, s_a, s_b, tx, ty, tz, eps2, kap, kk, ar, ai);
