@@ -1,7 +1,8 @@
 // Autotuning of the FP32 kernel-sum tiling: how many work items a mode
 // group is cut into (the source split count follows from it), per size
 // bucket of the target count.  The sweep times the batched kernel-sum
-// launch on synthetic sums of each bucket's size in two regimes, one mode
+// launch plus the fold of its split partials (the consumer every stage
+// has) on synthetic sums of each bucket's size in two regimes, one mode
 // group alone (where more splits fill the device) and many groups at once
 // (where extra splits only add partial-sum traffic), and keeps the
 // candidate with the smallest summed slowdown against each regime's best.
@@ -94,10 +95,11 @@ double time_config(Sweep& w, int32_t op, int32_t NT, int32_t NS, int32_t groups,
     }
 
     const size_t partial_n = (size_t)S * nsplit * NT;
+    const size_t vec_n = (size_t)S * std::max(NT, NS);
     const size_t bytes = carve_size<>(
         {sizeof(float) * src.size(), sizeof(float) * tgt.size(), sizeof(float2) * data.size(),
          sizeof(float4) * partial_n, sizeof(InstDev), sizeof(SysDev) * S, sizeof(GroupDev) * groups,
-         sizeof(int64_t) * 2});
+         sizeof(int64_t) * 2, sizeof(double2) * vec_n, sizeof(double2) * vec_n});
     void* ws = nullptr;
     if (workspace(w.ctx, bytes, &ws) != NAT_OK)
         return -1.0;
@@ -110,6 +112,8 @@ double time_config(Sweep& w, int32_t op, int32_t NT, int32_t NS, int32_t groups,
     SysDev* d_sys = cv.take<SysDev>(S);
     GroupDev* d_groups = cv.take<GroupDev>(groups);
     int64_t* d_counts = cv.take<int64_t>(2);
+    double2* d_g = cv.take<double2>(vec_n);
+    double2* d_out = cv.take<double2>(vec_n);
 
     InstDev I{};
     I.n = NS;
@@ -134,6 +138,8 @@ double time_config(Sweep& w, int32_t op, int32_t NT, int32_t NS, int32_t groups,
         Y.nsplit_a = Y.nsplit_b = nsplit;
         Y.off_n = (int64_t)q * NS;
         Y.off_pa = Y.off_pb = (int64_t)q * nsplit * NT;
+        Y.off_q = (int64_t)q * NT;
+        Y.out_q = eval ? d_out + (size_t)q * NT : nullptr;
         Y.k = 20.0 + 15.0 * (q % kModes);
         Y.k32 = static_cast<float>(Y.k);
         Y.kappa32 = static_cast<float>(Y.k / (2.0 * M_PI));
@@ -168,6 +174,8 @@ double time_config(Sweep& w, int32_t op, int32_t NT, int32_t NS, int32_t groups,
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_counts + 1, &ng32, sizeof(int32_t), hipMemcpyHostToDevice, w.s);
     if (e == hipSuccess)
+        e = hipMemsetAsync(d_g, 0, sizeof(double2) * vec_n, w.s);
+    if (e == hipSuccess)
         e = hipStreamSynchronize(w.s);  // the host vectors go out of scope below
     if (e != hipSuccess)
         return -1.0;
@@ -189,6 +197,8 @@ double time_config(Sweep& w, int32_t op, int32_t NT, int32_t NS, int32_t groups,
         e = hipEventRecord(w.e0, w.s);
         if (e == hipSuccess)
             e = launch_sum32_batch(op, p, grid, w.s);
+        if (e == hipSuccess)
+            e = launch_reduce32_batch(eval ? OP_EVAL : OP_RHS, p, S, NT, d_g, d_out, w.s);
         if (e == hipSuccess)
             e = hipEventRecord(w.e1, w.s);
         if (e == hipSuccess)
