@@ -120,7 +120,134 @@ k_neumann(const int32_t* __restrict__ T, int32_t layout, const double2* __restri
 
 inline dim3 grid1(int64_t n) { return dim3(static_cast<unsigned>((n + 255) / 256)); }
 
+// ---- the batch forms: blockIdx.y is the instance ---------------------------
+
+__global__ void __launch_bounds__(256) k_samples_batch(const SurfBatch b)
+{
+    const SurfJob& J = b.jobs[blockIdx.y];
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= J.N)
+        return;
+    const uint64_t c = 3ull * static_cast<uint64_t>(j);
+    const double u0 = unit_draw(J.seed, 0, c);
+    const double u1 = unit_draw(J.seed, 0, c + 1);
+    const double u2 = unit_draw(J.seed, 0, c + 2);
+    const double tau = u0 * J.area;
+    b.tri[J.on + j] = upper_search(J.cdf, J.nT, tau);
+    const double sq = __builtin_sqrt(u1);
+    b.bary[2 * (J.on + j) + 0] = sq * (1.0 - u2);
+    b.bary[2 * (J.on + j) + 1] = sq * u2;
+}
+
+// blockIdx.z = 0: the samples, 1: the queries.
+__global__ void __launch_bounds__(256) k_points_batch(const SurfBatch b)
+{
+    const SurfJob& J = b.jobs[blockIdx.y];
+    const bool q = blockIdx.z == 1;
+    const int32_t n = q ? J.Q : J.N;
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int32_t t = q ? J.q_tri[i] : b.tri[J.on + i];
+    const double* bb = q ? J.q_bary + 2 * i : b.bary + 2 * (J.on + i);
+    const double b1 = bb[0], b2 = bb[1];
+    const double* v0 = J.V + 3 * J.T[3 * t + 0];
+    const double* v1 = J.V + 3 * J.T[3 * t + 1];
+    const double* v2 = J.V + 3 * J.T[3 * t + 2];
+    const double ctr[3] = {J.cx, J.cy, J.cz};
+    double* x64 = q ? b.q64 + 3 * J.oq : b.x64 + 3 * J.on;
+    float* x32 = q ? b.q32 + 3 * J.oq : b.x32 + 3 * J.on;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double x = v0[d] + b1 * (v1[d] - v0[d]) + b2 * (v2[d] - v0[d]);
+        x64[(size_t)d * n + i] = x;
+        x32[(size_t)d * n + i] = static_cast<float>(x - ctr[d]);
+        if (!q) {
+            const double nd = J.nrm[3 * t + d];
+            b.n64[3 * J.on + (size_t)d * n + i] = nd;
+            b.n32[3 * J.on + (size_t)d * n + i] = static_cast<float>(nd);
+        }
+    }
+}
+
+// blockIdx.z = 0: data at the samples, 1: at the queries; all modes.
+__global__ void __launch_bounds__(256) k_neumann_batch(const SurfBatch b)
+{
+    const SurfJob& J = b.jobs[blockIdx.y];
+    const bool q = blockIdx.z == 1;
+    const int32_t n = q ? J.Q : J.N;
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int32_t t = q ? J.q_tri[i] : b.tri[J.on + i];
+    const double* bb = q ? J.q_bary + 2 * i : b.bary + 2 * (J.on + i);
+    double2* out = q ? b.gq + J.og_q : b.gj + J.og_n;
+    if (b.layout == NAT_NEUMANN_PER_TRIANGLE) {
+        for (int32_t m = 0; m < J.M; ++m)
+            out[(size_t)m * n + i] = J.v_n[(size_t)m * J.ng + t];
+        return;
+    }
+    const double b1 = bb[0], b2 = bb[1];
+    const double b0 = 1.0 - b1 - b2;
+    const int32_t c0 = J.T[3 * t], c1 = J.T[3 * t + 1], c2 = J.T[3 * t + 2];
+    for (int32_t m = 0; m < J.M; ++m) {
+        const double2* gm = J.v_n + (size_t)m * J.ng;
+        const double2 g0 = gm[c0], g1 = gm[c1], g2 = gm[c2];
+        double2 r;
+        r.x = b0 * g0.x + b1 * g1.x + b2 * g2.x;
+        r.y = b0 * g0.y + b1 * g1.y + b2 * g2.y;
+        out[(size_t)m * n + i] = r;
+    }
+}
+
+// Query records in range and finite Neumann data, for every instance.
+__global__ void __launch_bounds__(256) k_checks_batch(const SurfBatch b)
+{
+    const SurfJob& J = b.jobs[blockIdx.y];
+    const int64_t n_vals = 2 * (int64_t)J.M * J.ng;
+    const double* vals = reinterpret_cast<const double*>(J.v_n);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_vals || i < J.Q; i += stride) {
+        if (i < J.Q) {
+            const int32_t t = J.q_tri[i];
+            const double b1 = J.q_bary[2 * i], b2 = J.q_bary[2 * i + 1];
+            if (!(t >= 0 && t < J.nT && b1 >= 0.0 && b2 >= 0.0 && b1 + b2 <= 1.0 + 1e-12))
+                atomicOr(b.flags, 1);
+        }
+        if (i < n_vals && !isfinite(vals[i]))
+            atomicOr(b.flags + 1, 1);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_checks_batch(const SurfBatch& b, int64_t max_work, hipStream_t s)
+{
+    if (b.n_jobs <= 0 || max_work <= 0)
+        return hipSuccess;
+    const int64_t blocks = (max_work + 255) / 256;
+    dim3 grid(static_cast<unsigned>(blocks < 256 ? blocks : 256), static_cast<unsigned>(b.n_jobs));
+    hipLaunchKernelGGL(k_checks_batch, grid, dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_surface_batch(const SurfBatch& b, int32_t max_n, int32_t max_q, hipStream_t s)
+{
+    if (b.n_jobs <= 0 || max_n <= 0)
+        return hipSuccess;
+    const int32_t mx = max_n > max_q ? max_n : max_q;
+    const unsigned nj = static_cast<unsigned>(b.n_jobs);
+    hipLaunchKernelGGL(k_samples_batch, dim3((max_n + 255) / 256, nj), dim3(256), 0, s, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_points_batch, dim3((mx + 255) / 256, nj, max_q > 0 ? 2 : 1), dim3(256), 0, s, b);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_neumann_batch, dim3((mx + 255) / 256, nj, max_q > 0 ? 2 : 1), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
 
 hipError_t launch_samples(const nat_mesh* m, int32_t N, uint64_t seed, int32_t* tri,
                           double* bary, hipStream_t s)

@@ -198,6 +198,42 @@ hipError_t launch_neumann(const nat_mesh* m, int32_t layout, const double2* g, i
                           int32_t n_modes, int32_t n, const int32_t* tri, const double* bary,
                           double2* g_out, hipStream_t s);
 
+// The same surface work for every instance of a batch in one launch per
+// step: a device table of instances, the batch arrays they index into.
+struct SurfJob {
+    const double* V;                   // mesh vertices [nV][3]
+    const int32_t* T;                  // mesh triangles [nT][3]
+    const double* nrm;                 // triangle normals [nT][3]
+    const double* cdf;                 // running area sum [nT]
+    const int32_t* q_tri;              // caller's queries
+    const double* q_bary;
+    const double2* v_n;                // caller's Neumann data [M][ng]
+    double area, cx, cy, cz;           // |Gamma| and the mesh centre
+    uint64_t seed;
+    int64_t on, oq;                    // first sample / query of the instance in the batch arrays
+    int64_t og_n, og_q;                // first entry of its systems' per-sample / per-query data
+    int32_t nT, N, Q, M, ng, pad;
+};
+struct SurfBatch {
+    const SurfJob* jobs;
+    int32_t n_jobs, layout;
+    int32_t* tri;                      // [sum N]
+    double* bary;                      // [sum N][2]
+    double* x64;                       // per instance [3][N] at 3 on
+    double* n64;
+    float* x32;
+    float* n32;
+    double* q64;                       // per instance [3][Q] at 3 oq
+    float* q32;
+    double2* gj;                       // per system [N] at og_n + m N
+    double2* gq;                       // per system [Q] at og_q + m Q
+    int32_t* flags;                    // [0] query out of range, [1] non-finite Neumann data
+};
+// Device-side argument checks of every instance (flags are OR-ed, not cleared).
+hipError_t launch_checks_batch(const SurfBatch& b, int64_t max_work, hipStream_t s);
+// Samples, points and Neumann data of every instance.
+hipError_t launch_surface_batch(const SurfBatch& b, int32_t max_n, int32_t max_q, hipStream_t s);
+
 // ---- kernel sums ----------------------------------------------------------
 // Operation of a kernel sum over sources j for target i (w = |Gamma|/N):
 //   RHS    out_i = -sum w G g_j - (eps/2) g_i

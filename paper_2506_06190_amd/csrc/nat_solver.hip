@@ -282,7 +282,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
                 return fail(NAT_E_INVALID, "job %d: k[%d] = %g", i, m, J.k[m]);
         S64 += J.M;
     }
-    if (nj < 1 || S64 > (1 << 20))
+    if (nj < 1 || nj > 65535 || S64 > (1 << 20))
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: %d jobs with %lld systems", nj, (long long)S64);
     nat_status st = NAT_OK;
     if (!bytes_only) {
@@ -361,7 +361,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
          sizeof(int32_t) * S, sizeof(double2) * sum_ch * mm1, sizeof(double2) * sum_ch * mm1,
          sizeof(double) * sum_ch, sizeof(float4) * n_part, sizeof(InstDev) * nj,
          sizeof(SysDev) * S, sizeof(GroupDev) * S, sizeof(GroupDev) * S, sizeof(GroupDev) * S,
-         sizeof(int2) * sum_ch, sizeof(double) * S, sizeof(int64_t) * 8});
+         sizeof(int2) * sum_ch, sizeof(double) * S, sizeof(int64_t) * 8, sizeof(SurfJob) * nj});
     if (bytes_only) {
         *bytes_only = bytes;
         return NAT_OK;
@@ -413,6 +413,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     T.d_items = cv.take<int2>(sum_ch);
     double* dk = cv.take<double>(S);
     int64_t* dcnt64 = cv.take<int64_t>(8);  // items: [0] rhs, [1] eval, [2] matvec
+    SurfJob* d_surf = cv.take<SurfJob>(nj);
     T.d_nitems = dcnt + 2;
     T.d_ngroups_mv = dcnt + 3;
     T.d_iter = dcnt + 4;
@@ -441,29 +442,71 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         }
     }
 
-    // ---- validation of the device inputs ------------------------------------
+    // ---- the instance table of the surface kernels and the device checks -----
+    SurfBatch sbat{};
+    int64_t max_check = 0;
     {
-        NAT_HIP(hipMemsetAsync(dcnt, 0, 2 * sizeof(int32_t), s));
+        std::vector<SurfJob> sj(nj);
+        size_t on = 0, oq = 0;
         for (int32_t i = 0; i < nj; ++i) {
             const McJob& J = jobs[i];
-            const int32_t ng = opts->layout == NAT_NEUMANN_PER_TRIANGLE ? J.mesh->nT : J.mesh->nV;
-            int32_t unused[2];
-            st = device_checks(ctx, dcnt, J.q_tri, J.q_bary, J.Q, J.mesh->nT, J.v_n,
-                               2 * (int64_t)J.M * ng, s, unused, false);
-            if (st != NAT_OK)
-                return st;
+            const nat_mesh* m = J.mesh;
+            SurfJob& X = sj[i];
+            X = SurfJob{};
+            X.V = m->d_V;
+            X.T = m->d_T;
+            X.nrm = m->d_normal;
+            X.cdf = m->d_cdf;
+            X.q_tri = J.q_tri;
+            X.q_bary = J.q_bary;
+            X.v_n = reinterpret_cast<const double2*>(J.v_n);
+            X.area = m->area_total;
+            X.cx = m->center[0];
+            X.cy = m->center[1];
+            X.cz = m->center[2];
+            X.seed = J.seed;
+            X.on = (int64_t)on;
+            X.oq = (int64_t)oq;
+            X.og_n = T.sys[T.inst[i].sys0].off_n;
+            X.og_q = T.sys[T.inst[i].sys0].off_q;
+            X.nT = m->nT;
+            X.N = J.N;
+            X.Q = J.Q;
+            X.M = J.M;
+            X.ng = opts->layout == NAT_NEUMANN_PER_TRIANGLE ? m->nT : m->nV;
+            on += J.N;
+            oq += J.Q;
+            const int64_t w = std::max<int64_t>(J.Q, 2 * (int64_t)J.M * X.ng);
+            max_check = w > max_check ? w : max_check;
         }
         void* pin = nullptr;
-        st = pinned(ctx, 64, &pin);
+        st = pinned(ctx, sizeof(SurfJob) * nj + 64, &pin);
         if (st != NAT_OK)
             return st;
-        NAT_HIP(hipMemcpyAsync(pin, dcnt, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        std::memcpy(pin, sj.data(), sizeof(SurfJob) * nj);
+        NAT_HIP(hipMemcpyAsync(d_surf, pin, sizeof(SurfJob) * nj, hipMemcpyHostToDevice, s));
+        sbat.jobs = d_surf;
+        sbat.n_jobs = nj;
+        sbat.layout = opts->layout;
+        sbat.tri = tri_all;
+        sbat.bary = bary_all;
+        sbat.x64 = x64_all;
+        sbat.n64 = n64_all;
+        sbat.x32 = x32_all;
+        sbat.n32 = n32_all;
+        sbat.q64 = q64_all;
+        sbat.q32 = q32_all;
+        sbat.gj = gj;
+        sbat.gq = gq;
+        sbat.flags = dcnt;
+        NAT_HIP(hipMemsetAsync(dcnt, 0, 2 * sizeof(int32_t), s));
+        NAT_HIP(launch_checks_batch(sbat, max_check, s));
+        int32_t* hflags = reinterpret_cast<int32_t*>(static_cast<char*>(pin) + sizeof(SurfJob) * nj);
+        NAT_HIP(hipMemcpyAsync(hflags, dcnt, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         NAT_HIP(hipStreamSynchronize(s));
-        int32_t flags[2];
-        std::memcpy(flags, pin, sizeof(flags));
-        if (flags[0])
+        if (hflags[0])
             return fail(NAT_E_INVALID, "Monte-Carlo estimate: query record out of range");
-        if (flags[1])
+        if (hflags[1])
             return fail(NAT_E_INVALID, "Monte-Carlo estimate: non-finite Neumann data");
     }
 
@@ -528,28 +571,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     }
 
     // ---- samples, points, Neumann data (Section 4.1.1) -----------------------
-    {
-        size_t on = 0, oq = 0;
-        for (int32_t i = 0; i < nj; ++i) {
-            const McJob& J = jobs[i];
-            const InstDev& I = T.inst[i];
-            const int32_t ng = opts->layout == NAT_NEUMANN_PER_TRIANGLE ? J.mesh->nT : J.mesh->nV;
-            int32_t* tri = tri_all + on;
-            double* bary = bary_all + 2 * on;
-            PointStreams ps{x64_all + 3 * on, n64_all + 3 * on, x32_all + 3 * on, n32_all + 3 * on};
-            PointStreams qs{q64_all + 3 * oq, nullptr, q32_all + 3 * oq, nullptr};
-            const SysDev& Y0 = T.sys[I.sys0];
-            NAT_HIP(launch_samples(J.mesh, J.N, J.seed, tri, bary, s));
-            NAT_HIP(launch_points(J.mesh, J.N, tri, bary, ps, s));
-            NAT_HIP(launch_points(J.mesh, J.Q, J.q_tri, J.q_bary, qs, s));
-            NAT_HIP(launch_neumann(J.mesh, opts->layout, reinterpret_cast<const double2*>(J.v_n), ng,
-                                   J.M, J.N, tri, bary, gj + Y0.off_n, s));
-            NAT_HIP(launch_neumann(J.mesh, opts->layout, reinterpret_cast<const double2*>(J.v_n), ng,
-                                   J.M, J.Q, J.q_tri, J.q_bary, gq + Y0.off_q, s));
-            on += J.N;
-            oq += J.Q;
-        }
-    }
+    NAT_HIP(launch_surface_batch(sbat, max_n, max_q, s));
 
     Sum32Batch sb{};
     sb.inst = T.d_inst;
