@@ -450,6 +450,7 @@ def main():
 
     dev = "cuda:0"
     ctx = nat.Context(0)
+    os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
     if args.pmc_pass:
         nat.nat_autotune(ctx, args.tune_cache)
         run_pmc_pass(nat, torch, ctx, args, dev)
