@@ -25,7 +25,7 @@ namespace {
 
 constexpr int kRows = 256;  // rows per chunk = threads per workgroup
 constexpr int kRowWaves = kRows / 64;
-constexpr int kDotGroup = 8;
+constexpr int kDotGroup = 4;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
@@ -67,8 +67,10 @@ __device__ __forceinline__ double block_sum(double v, double* red)
 }
 
 // Partial dot products of the chunk's rows s_w (LDS) with v_0..v_j.  A wave
-// takes 8 consecutive basis vectors per round: all loads of the round are
-// issued before the 16 interleaved butterfly reductions.
+// takes 4 consecutive basis vectors per round: all loads of the round are
+// issued before the 8 interleaved butterfly reductions.  Small groups keep
+// the register count low enough for 6-7 waves per SIMD, which hides the
+// latency of the many short items of the early iterations.
 __device__ __forceinline__ void chunk_dots(const double2* Vs, int32_t n, int32_t j, int32_t r0,
                                            const double2* s_w, double2* dp_out)
 {
@@ -224,9 +226,9 @@ __global__ void __launch_bounds__(kRows) k_orth_update(GmresBatch g, int32_t pas
         double2 wt = make_double2(0.0, 0.0);
         if (t < n) {
             wt = w[t];
-            // groups of 16 basis vectors, the last one predicated, so every
+            // groups of 8 basis vectors, the last one predicated, so every
             // group's loads are in flight together; subtraction in index order
-            constexpr int U = 16;
+            constexpr int U = 8;
             for (int i = 0; i <= j; i += U) {
                 double2 v[U];
 #pragma unroll

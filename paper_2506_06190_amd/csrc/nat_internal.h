@@ -330,6 +330,8 @@ int32_t target_tiles(int32_t n_targets);
 // the right-hand side and query stages
 constexpr int32_t kGridMatvec = 1024;
 constexpr int32_t kGridStage = 4096;
+// workgroups of the persistent Arnoldi-step kernels (6-7 resident per CU)
+constexpr int32_t kGridArnoldi = 1536;
 hipError_t launch_sum32_batch(int32_t op, const Sum32Batch& p, int32_t grid, hipStream_t s,
                               const ProfSlot& ev = ProfSlot());
 // RHS: out_n[off_n + i] = b_i; EVAL: sys.out_q[i] = p(x_i)

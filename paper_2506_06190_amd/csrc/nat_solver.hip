@@ -202,7 +202,7 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
         return st;
     NAT_HIP(launch_gmres_init(g, b, s));
 
-    const int32_t grid_g = static_cast<int32_t>(T.max_items < kMaxGrid ? (T.max_items > 0 ? T.max_items : 1) : kMaxGrid);
+    const int32_t grid_g = static_cast<int32_t>(T.max_items < kGridArnoldi ? (T.max_items > 0 ? T.max_items : 1) : kGridArnoldi);
     const int32_t grid_mv = static_cast<int32_t>(ls.mv_items < kMaxGrid ? (ls.mv_items > 0 ? ls.mv_items : 1) : kMaxGrid);
     hipGraphExec_t exec = nullptr;
     if (use_graph && mv && !ctx->prof) {
