@@ -327,7 +327,7 @@ def pmc_summarize(d_fetch, d_write):
             key = (r["Kernel_Name"], r.get("Dispatch_Id", r.get("Correlation_Id")))
             per[key] = per.get(key, 0.0) + float(r["Counter_Value"]) * 1024.0  # KiB per dispatch
         copy = [v for (k, _), v in per.items() if "copy" in k.lower() or "elementwise" in k.lower()]
-        mv = [v for (k, _), v in per.items() if "k_sum32ILi1E" in k]
+        mv = [v for (k, _), v in per.items() if "k_sum32<1>" in k or "k_sum32ILi1E" in k]
         if not copy or not mv:
             raise SystemExit(f"{name}: copy kernel or matvec kernel not found")
         big = max(copy)
@@ -428,6 +428,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--pmc-pass", action="store_true")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--tune", choices=["cache", "default"], default="cache",
+                    help="kernel-sum tiling: the autotuner's table (cache, else a sweep) or the defaults")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2506_06190_amd", "tune",
                                                          "kernel_sum_tiles.json"))
     ap.add_argument("--serve-requests", type=int, default=1000)
@@ -457,10 +459,14 @@ def main():
         ctx.close()
         return
     had_cache = os.path.exists(args.tune_cache)
-    os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
     t0 = time.perf_counter()
-    table = nat.nat_autotune(ctx, args.tune_cache)
-    tune = {"cache": os.path.relpath(args.tune_cache, ROOT), "source": "cache" if had_cache else "sweep",
+    if args.tune == "cache":
+        table = nat.nat_autotune(ctx, args.tune_cache)
+        source = "cache" if had_cache else "sweep"
+    else:
+        table = nat.nat_tune_get(ctx)
+        source = "defaults"
+    tune = {"cache": os.path.relpath(args.tune_cache, ROOT), "source": source,
             "seconds": round(time.perf_counter() - t0, 2), "items_a": table["items_a"],
             "items_b": table["items_b"]}
     log(f"kernel-sum tiling from {tune['source']} in {tune['seconds']} s")

@@ -2,22 +2,40 @@
 // size that share their matvec launches.  x0 = 0, restart = mmax
 // (unrestarted up to mmax steps; Section 6.1 uses at most 200).
 //
-// The Arnoldi step after each matvec is classical Gram-Schmidt applied
-// twice (CGS2) in FP64, spread over work items (system, chunk of 256 rows),
-// so one system uses as many CUs as it has chunks:
-//   dots     w formed from the FP32 matvec partials when there are any, then
-//            partial <v_i, w> over the chunk's rows
-//   update   h = sum of the chunk partials in chunk order; w -= V h on the
-//            chunk's rows; then either the second pass's partial dots or the
-//            partial squared norm
-//   finalize |w|, v_{j+1} = w/|w| and its FP32 copy; the first chunk applies
-//            the Givens rotations to the new Hessenberg column and sets the
-//            convergence flag
-//   advance  j <- j + 1
+// Arnoldi step: classical Gram-Schmidt with the reorthogonalisation of CGS2
+// folded into the first projection through the Gram matrix of the basis.
+// With s = V^H w and G = V^H V, the second CGS pass would project with
+// V^H (w - V s) = s - G s in exact arithmetic, so the step uses the single
+// coefficient vector h = s - (G - I) s and one update w <- w - V h.  G is
+// kept column by column: the pass that forms s also forms V^H v_j for the
+// newest basis vector.  This corrects the basis's own loss of orthogonality
+// exactly; what it cannot see is the rounding of the update itself, of
+// relative size eps |w| / |w - V h|, so when the update cancels w by more
+// than a factor 100 a true second pass (dots and update) follows, as in
+// selective reorthogonalisation (Daniel, Gragg, Kaufman & Stewart 1976).
+// The idea of obtaining the reorthogonalisation coefficients from inner
+// products computed in the same sweep follows the low-synchronisation
+// Gram-Schmidt variants of Swirydowicz, Langou, Ananthan, Yang & Thomas
+// (2020).  The basis is read twice per step instead of four times.
+//
+// The work is spread over items (system, chunk of 256 rows), so one system
+// uses as many CUs as it has chunks:
+//   dots      w formed from the FP32 matvec partials when there are any, then
+//             partial <v_i, w> and <v_i, v_j> over the chunk's rows, and the
+//             partial |w|^2
+//   coef      (first chunk) the Gram column of v_j and h = s - (G - I) s
+//   update    w -= V h on the chunk's rows, partial |w|^2
+//   dots2     (only after strong cancellation) partial <v_i, w>
+//   update2   (same) w -= V h2, h += h2, partial |w|^2
+//   finalize  |w|, v_{j+1} = w/|w| and its FP32 copy; the first chunk applies
+//             the Givens rotations to the new Hessenberg column and sets the
+//             convergence flag
+//   advance   j <- j + 1
 // Every chunk sums the same partials in the same order, so all chunks use
-// identical coefficients.  The kernels are persistent over the item list and
-// read j from device memory, so a run of iterations can be captured once as
-// a graph and replayed while the host refreshes the lists between replays.
+// identical coefficients and take identical decisions.  The kernels are
+// persistent over the item list and read j from device memory, so a run of
+// iterations can be captured once as a graph and replayed while the host
+// refreshes the lists between replays.
 #include "nat_internal.h"
 
 namespace nat {
@@ -25,7 +43,8 @@ namespace {
 
 constexpr int kRows = 256;  // rows per chunk = threads per workgroup
 constexpr int kRowWaves = kRows / 64;
-constexpr int kDotGroup = 4;
+// true second pass when |w - V h|^2 < kCancel2 |w|^2 (cancellation by > 100x)
+constexpr double kCancel2 = 1e-4;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
@@ -66,35 +85,44 @@ __device__ __forceinline__ double block_sum(double v, double* red)
     return s;
 }
 
-// Partial dot products of the chunk's rows s_w (LDS) with v_0..v_j.  A wave
-// takes 4 consecutive basis vectors per round: all loads of the round are
-// issued before the 8 interleaved butterfly reductions.  Small groups keep
-// the register count low enough for 6-7 waves per SIMD, which hides the
-// latency of the many short items of the early iterations.
+// Partial dot products of the chunk's rows s_x (LDS) with v_0..v_j, and with
+// kTwo of s_y as well.  A wave takes kDotGroup consecutive basis vectors
+// per round: all loads of the round are issued before the interleaved
+// butterfly reductions.  Small groups keep the register count low enough for 6-7
+// waves per SIMD, which hides the latency of the many short items of the
+// early iterations.
+template <bool kTwo, int kDotGroup = kTwo ? 2 : 4>
 __device__ __forceinline__ void chunk_dots(const double2* Vs, int32_t n, int32_t j, int32_t r0,
-                                           const double2* s_w, double2* dp_out)
+                                           const double2* s_x, const double2* s_y, double2* dpx,
+                                           double2* dpy)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int i0 = kDotGroup * wave; i0 <= j; i0 += kDotGroup * kRowWaves) {
-        double ar[kDotGroup], ai[kDotGroup];
+        double ar[kDotGroup], ai[kDotGroup], br[kDotGroup], bi[kDotGroup];
 #pragma unroll
         for (int c = 0; c < kDotGroup; ++c)
-            ar[c] = ai[c] = 0.0;
+            ar[c] = ai[c] = br[c] = bi[c] = 0.0;
 #pragma unroll
         for (int q = 0; q < kRows / 64; ++q) {
             const int rr = lane + 64 * q;
             if (r0 + rr >= n)
                 continue;
-            const double2 wv = s_w[rr];
+            const double2 xv = s_x[rr];
+            const double2 yv = kTwo ? s_y[rr] : make_double2(0.0, 0.0);
             double2 v[kDotGroup];
 #pragma unroll
             for (int c = 0; c < kDotGroup; ++c)
                 v[c] = (i0 + c <= j) ? Vs[(size_t)(i0 + c) * n + r0 + rr] : make_double2(0.0, 0.0);
 #pragma unroll
             for (int c = 0; c < kDotGroup; ++c) {
-                const double2 d = cmulc(v[c], wv);
+                const double2 d = cmulc(v[c], xv);
                 ar[c] += d.x;
                 ai[c] += d.y;
+                if (kTwo) {
+                    const double2 e = cmulc(v[c], yv);
+                    br[c] += e.x;
+                    bi[c] += e.y;
+                }
             }
         }
 #pragma unroll
@@ -103,24 +131,66 @@ __device__ __forceinline__ void chunk_dots(const double2* Vs, int32_t n, int32_t
             for (int c = 0; c < kDotGroup; ++c) {
                 ar[c] += __shfl_xor(ar[c], off, 64);
                 ai[c] += __shfl_xor(ai[c], off, 64);
+                if (kTwo) {
+                    br[c] += __shfl_xor(br[c], off, 64);
+                    bi[c] += __shfl_xor(bi[c], off, 64);
+                }
             }
         }
         if (lane < kDotGroup && i0 + lane <= j) {
-            double xr = ar[0], xi = ai[0];
+            double xr = ar[0], xi = ai[0], yr = br[0], yi = bi[0];
 #pragma unroll
             for (int c = 1; c < kDotGroup; ++c)
                 if (lane == c) {
                     xr = ar[c];
                     xi = ai[c];
+                    yr = br[c];
+                    yi = bi[c];
                 }
-            dp_out[i0 + lane] = make_double2(xr, xi);
+            dpx[i0 + lane] = make_double2(xr, xi);
+            if (kTwo)
+                dpy[i0 + lane] = make_double2(yr, yi);
         }
     }
+}
+
+// Whether system S's step needs the true second pass: |w - V h|^2 against
+// |w|^2 before the projection, both summed over the chunks in order.
+__device__ __forceinline__ bool strong_cancel(const GmresBatch& g, const SysDev& S)
+{
+    double a = 0.0, b = 0.0;
+    for (int c = 0; c < S.nch; ++c) {
+        a += g.normpart[S.off_ch + c];
+        b += g.wnorm0[S.off_ch + c];
+    }
+    return a < kCancel2 * b;
+}
+
+// Sum of the chunk partials of entry i, in chunk order.
+__device__ __forceinline__ double2 chunk_sum(const double2* dp, int32_t nch, int mm1, int i)
+{
+    double hr = 0.0, hi = 0.0;
+    for (int c0 = 0; c0 < nch; c0 += 8) {
+        double2 v[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            v[c] = c0 + c < nch ? dp[(size_t)(c0 + c) * mm1 + i] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            if (c0 + c < nch) {
+                hr += v[c].x;
+                hi += v[c].y;
+            }
+        }
+    }
+    return make_double2(hr, hi);
 }
 
 __global__ void __launch_bounds__(kRows) k_orth_dots(GmresBatch g)
 {
     __shared__ double2 s_w[kRows];
+    __shared__ double2 s_v[kRows];
+    __shared__ double red[kRowWaves];
     const int32_t j = *g.iter;
     const int32_t n_items = *g.n_items;
     if (j >= g.mmax)
@@ -138,7 +208,9 @@ __global__ void __launch_bounds__(kRows) k_orth_dots(GmresBatch g)
         const double2* Vs = g.V + S.off_v;
         double2* w = g.w + S.off_n;
         double2 wt = make_double2(0.0, 0.0);
+        double2 vj = make_double2(0.0, 0.0);
         if (t < n) {
+            vj = Vs[(size_t)j * n + t];
             if (g.partial) {
                 // matvec epilogue: w = v_j / 2 - (sum of the FP32 split partials)
                 float hr = 0.0f, hi = 0.0f, lr = 0.0f, li = 0.0f;
@@ -162,8 +234,7 @@ __global__ void __launch_bounds__(kRows) k_orth_dots(GmresBatch g)
                 }
                 const double ar = static_cast<double>(hr) + static_cast<double>(lr);
                 const double ai = static_cast<double>(hi) + static_cast<double>(li);
-                const double2 x = Vs[(size_t)j * n + t];
-                wt = make_double2(0.5 * x.x - ar, 0.5 * x.y - ai);
+                wt = make_double2(0.5 * vj.x - ar, 0.5 * vj.y - ai);
                 w[t] = wt;
             } else {
                 wt = w[t];
@@ -171,17 +242,75 @@ __global__ void __launch_bounds__(kRows) k_orth_dots(GmresBatch g)
         }
         __syncthreads();
         s_w[threadIdx.x] = wt;
+        s_v[threadIdx.x] = vj;
         __syncthreads();
-        chunk_dots(Vs, n, j, r0, s_w, g.dp1 + (S.off_ch + chunk) * mm1);
+        chunk_dots<true>(Vs, n, j, r0, s_w, s_v, g.dp1 + (S.off_ch + chunk) * mm1,
+                         g.dp2 + (S.off_ch + chunk) * mm1);
+        const double nw = block_sum(wt.x * wt.x + wt.y * wt.y, red);
+        if (threadIdx.x == 0)
+            g.wnorm0[S.off_ch + chunk] = nw;
     }
 }
 
-// pass 0: w -= V h1, then the partial dots of the second pass into dp2.
-// pass 1: w -= V h2, then the partial squared norm.
+// First chunk of each system: s = V^H w and the new Gram column V^H v_j from
+// the chunk partials, then h = s - (G - I) s into the Hessenberg column.
+__global__ void __launch_bounds__(kRows) k_orth_coef(GmresBatch g)
+{
+    extern __shared__ double2 s_sv[];  // [mmax + 1] s | [mmax + 1] Gram column j
+    const int32_t j = *g.iter;
+    const int32_t n_items = *g.n_items;
+    if (j >= g.mmax)
+        return;
+    const int mm1 = g.mmax + 1;
+    double2* s_gj = s_sv + mm1;
+    for (int32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 item = g.items[it];
+        const int32_t s = item.x, chunk = item.y;
+        if (chunk != 0 || !g.active[s])
+            continue;
+        const SysDev& S = g.sys[s];
+        double2* G = g.gram + (size_t)s * g.gram_stride;  // column k at k (k + 1) / 2
+        __syncthreads();
+        for (int i = threadIdx.x; i <= j; i += kRows) {
+            s_sv[i] = chunk_sum(g.dp1 + S.off_ch * mm1, S.nch, mm1, i);
+            const double2 gij = chunk_sum(g.dp2 + S.off_ch * mm1, S.nch, mm1, i);
+            s_gj[i] = gij;
+            G[(size_t)j * (j + 1) / 2 + i] = gij;
+        }
+        __syncthreads();
+        double2* ht = g.htot + (size_t)s * mm1;
+        for (int i = threadIdx.x; i <= j; i += kRows) {
+            // (G - I) s, row i; G_ik is column k's entry i for k >= i, else
+            // the conjugate of column i's entry k
+            double er = 0.0, ei = 0.0;
+            for (int k = 0; k <= j; ++k) {
+                double2 gik;
+                if (k == j)
+                    gik = s_gj[i];
+                else if (k >= i)
+                    gik = G[(size_t)k * (k + 1) / 2 + i];
+                else {
+                    const double2 x = G[(size_t)i * (i + 1) / 2 + k];
+                    gik = make_double2(x.x, -x.y);
+                }
+                if (k == i)
+                    gik.x -= 1.0;
+                const double2 d = cmul(gik, s_sv[k]);
+                er += d.x;
+                ei += d.y;
+            }
+            ht[i] = make_double2(s_sv[i].x - er, s_sv[i].y - ei);
+        }
+    }
+}
+
+// pass 0: w -= V h with h the Hessenberg column, partial |w|^2 into normpart.
+// pass 1 (systems with strong cancellation only): h2 = sum of the second
+// pass's partial dots, w -= V h2, h += h2, partial |w|^2 into normpart2.
 __global__ void __launch_bounds__(kRows) k_orth_update(GmresBatch g, int32_t pass)
 {
-    __shared__ double2 s_w[kRows];
     __shared__ double red[kRowWaves];
+    __shared__ int32_t s_go;
     extern __shared__ double2 s_h[];  // [mmax + 1]
     const int32_t j = *g.iter;
     const int32_t n_items = *g.n_items;
@@ -195,32 +324,27 @@ __global__ void __launch_bounds__(kRows) k_orth_update(GmresBatch g, int32_t pas
             continue;
         const SysDev& S = g.sys[s];
         const int32_t n = S.n;
-        const double2* dp = (pass == 0 ? g.dp1 : g.dp2) + S.off_ch * mm1;
         __syncthreads();
+        if (pass == 1) {
+            if (threadIdx.x == 0)
+                s_go = strong_cancel(g, S) ? 1 : 0;
+            __syncthreads();
+            if (!s_go)
+                continue;
+        }
+        double2* ht = g.htot + (size_t)s * mm1;
         for (int i = threadIdx.x; i <= j; i += kRows) {
-            double hr = 0.0, hi = 0.0;
-            for (int c0 = 0; c0 < S.nch; c0 += 8) {
-                double2 v[8];
-#pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    v[c] = c0 + c < S.nch ? dp[(size_t)(c0 + c) * mm1 + i] : make_double2(0.0, 0.0);
-#pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    if (c0 + c < S.nch) {
-                        hr += v[c].x;
-                        hi += v[c].y;
-                    }
-                }
-            }
-            s_h[i] = make_double2(hr, hi);
-            if (chunk == 0) {
-                double2* ht = g.htot + (size_t)s * mm1;
-                ht[i] = pass == 0 ? make_double2(hr, hi) : make_double2(ht[i].x + hr, ht[i].y + hi);
+            if (pass == 0) {
+                s_h[i] = ht[i];
+            } else {
+                const double2 h2 = chunk_sum(g.dp1 + S.off_ch * mm1, S.nch, mm1, i);
+                s_h[i] = h2;
+                if (chunk == 0)
+                    ht[i] = make_double2(ht[i].x + h2.x, ht[i].y + h2.y);
             }
         }
         __syncthreads();
-        const int32_t r0 = chunk * kRows;
-        const int32_t t = r0 + threadIdx.x;
+        const int32_t t = chunk * kRows + threadIdx.x;
         const double2* Vs = g.V + S.off_v;
         double2* w = g.w + S.off_n;
         double2 wt = make_double2(0.0, 0.0);
@@ -245,15 +369,41 @@ __global__ void __launch_bounds__(kRows) k_orth_update(GmresBatch g, int32_t pas
             }
             w[t] = wt;
         }
-        s_w[threadIdx.x] = wt;
+        const double tot = block_sum(wt.x * wt.x + wt.y * wt.y, red);
+        if (threadIdx.x == 0)
+            (pass == 0 ? g.normpart : g.normpart2)[S.off_ch + chunk] = tot;
+    }
+}
+
+// Partial dots of the second pass, for the systems with strong cancellation.
+__global__ void __launch_bounds__(kRows) k_orth_dots2(GmresBatch g)
+{
+    __shared__ double2 s_w[kRows];
+    __shared__ int32_t s_go;
+    const int32_t j = *g.iter;
+    const int32_t n_items = *g.n_items;
+    if (j >= g.mmax)
+        return;
+    const int mm1 = g.mmax + 1;
+    for (int32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 item = g.items[it];
+        const int32_t s = item.x, chunk = item.y;
+        if (!g.active[s])
+            continue;
+        const SysDev& S = g.sys[s];
         __syncthreads();
-        if (pass == 0) {
-            chunk_dots(Vs, n, j, r0, s_w, g.dp2 + (S.off_ch + chunk) * mm1);
-        } else {
-            const double tot = block_sum(wt.x * wt.x + wt.y * wt.y, red);
-            if (threadIdx.x == 0)
-                g.normpart[S.off_ch + chunk] = tot;
-        }
+        if (threadIdx.x == 0)
+            s_go = strong_cancel(g, S) ? 1 : 0;
+        __syncthreads();
+        if (!s_go)
+            continue;
+        const int32_t n = S.n;
+        const int32_t r0 = chunk * kRows;
+        const int32_t t = r0 + threadIdx.x;
+        s_w[threadIdx.x] = t < n ? g.w[S.off_n + t] : make_double2(0.0, 0.0);
+        __syncthreads();
+        chunk_dots<false>(g.V + S.off_v, n, j, r0, s_w, nullptr,
+                          g.dp1 + (S.off_ch + chunk) * mm1, nullptr);
     }
 }
 
@@ -285,9 +435,10 @@ __global__ void __launch_bounds__(kRows) k_orth_finalize(GmresBatch g)
         const SysDev& S = g.sys[s];
         const int32_t n = S.n;
         if (threadIdx.x == 0) {
+            const double* np = strong_cancel(g, S) ? g.normpart2 : g.normpart;
             double sacc = 0.0;
             for (int c = 0; c < S.nch; ++c)
-                sacc += g.normpart[S.off_ch + c];
+                sacc += np[S.off_ch + c];
             s_hn = sqrt(sacc);
         }
         __syncthreads();
@@ -474,7 +625,9 @@ hipError_t launch_gmres_step(const GmresBatch& g, int32_t grid, hipStream_t s, c
     const size_t lds_h = sizeof(double2) * (size_t)(g.mmax + 1);
     const size_t lds_fin = sizeof(double2) * (size_t)(2 * g.mmax + 2) + sizeof(double) * (size_t)g.mmax;
     launch_k(k_orth_dots, dim3(grid), dim3(kRows), 0, s, ev.start, nullptr, g);
+    hipLaunchKernelGGL(k_orth_coef, dim3(grid), dim3(kRows), 2 * lds_h, s, g);
     hipLaunchKernelGGL(k_orth_update, dim3(grid), dim3(kRows), lds_h, s, g, 0);
+    hipLaunchKernelGGL(k_orth_dots2, dim3(grid), dim3(kRows), 0, s, g);
     hipLaunchKernelGGL(k_orth_update, dim3(grid), dim3(kRows), lds_h, s, g, 1);
     hipLaunchKernelGGL(k_orth_finalize, dim3(grid), dim3(kRows), lds_fin, s, g);
     launch_k(k_gmres_advance, dim3(1), dim3(1), 0, s, nullptr, ev.stop, g);

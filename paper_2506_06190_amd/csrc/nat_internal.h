@@ -330,8 +330,8 @@ int32_t target_tiles(int32_t n_targets);
 // the right-hand side and query stages
 constexpr int32_t kGridMatvec = 1024;
 constexpr int32_t kGridStage = 4096;
-// workgroups of the persistent Arnoldi-step kernels (6-7 resident per CU)
-constexpr int32_t kGridArnoldi = 1536;
+// workgroups of the persistent Arnoldi-step kernels (5 or more resident per CU)
+constexpr int32_t kGridArnoldi = 1280;
 hipError_t launch_sum32_batch(int32_t op, const Sum32Batch& p, int32_t grid, hipStream_t s,
                               const ProfSlot& ev = ProfSlot());
 // RHS: out_n[off_n + i] = b_i; EVAL: sys.out_q[i] = p(x_i)
@@ -357,9 +357,13 @@ struct GmresBatch {
     int32_t* active;     // [sys]
     double2* w;          // [off_n + t] matvec output
     float2* v32;         // [off_n + t] FP32 copy of the newest basis vector times w/(4 pi), or null
-    double2* dp1;        // [(off_ch + chunk)(mmax+1) + i] partial dots, first CGS pass
-    double2* dp2;        // second pass
-    double* normpart;    // [off_ch + chunk]
+    double2* dp1;        // [(off_ch + chunk)(mmax+1) + i] partial <v_i, w>
+    double2* dp2;        // partial <v_i, v_j> (the new Gram column)
+    double2* gram;       // [sys][gram_stride]: Gram column k of the basis at k (k + 1) / 2
+    int64_t gram_stride; // (mmax+1)(mmax+2)/2
+    double* wnorm0;      // [off_ch + chunk] partial |w|^2 before the projection
+    double* normpart;    // [off_ch + chunk] partial |w|^2 after the update
+    double* normpart2;   // ... after the second pass, when one was needed
     const float4* partial;     // FP32 matvec split partials, or null (w written by the matvec)
     const int2* items;         // (system, chunk) work list of the Arnoldi kernels
     const int32_t* n_items;    // device count

@@ -349,6 +349,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     }
     T.max_items = sum_ch;
     const int64_t n_part = sum_pa > sum_pb ? sum_pa : sum_pb;
+    const int64_t gram_stride = (int64_t)mm1 * (mm1 + 1) / 2;
     const size_t bytes = carve_size<>(
         {sizeof(int32_t) * 8, sizeof(int32_t) * inst_n, sizeof(double) * 2 * inst_n,
          sizeof(double) * 3 * inst_n, sizeof(double) * 3 * inst_n, sizeof(float) * 3 * inst_n,
@@ -359,7 +360,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
          sizeof(double) * S * mmax, sizeof(double2) * S * mmax, sizeof(double2) * S * mm1,
          sizeof(double2) * S * mm1, sizeof(double) * S, sizeof(double) * S, sizeof(int32_t) * S,
          sizeof(int32_t) * S, sizeof(double2) * sum_ch * mm1, sizeof(double2) * sum_ch * mm1,
-         sizeof(double) * sum_ch, sizeof(float4) * n_part, sizeof(InstDev) * nj,
+         sizeof(double) * sum_ch, sizeof(double) * sum_ch, sizeof(double) * sum_ch,
+         sizeof(double2) * S * gram_stride, sizeof(float4) * n_part, sizeof(InstDev) * nj,
          sizeof(SysDev) * S, sizeof(GroupDev) * S, sizeof(GroupDev) * S, sizeof(GroupDev) * S,
          sizeof(int2) * sum_ch, sizeof(double) * S, sizeof(int64_t) * 8, sizeof(SurfJob) * nj});
     if (bytes_only) {
@@ -404,6 +406,10 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     g.dp1 = cv.take<double2>((size_t)sum_ch * mm1);
     g.dp2 = cv.take<double2>((size_t)sum_ch * mm1);
     g.normpart = cv.take<double>(sum_ch);
+    g.normpart2 = cv.take<double>(sum_ch);
+    g.wnorm0 = cv.take<double>(sum_ch);
+    g.gram = cv.take<double2>((size_t)S * gram_stride);
+    g.gram_stride = gram_stride;
     float4* partial = cv.take<float4>(n_part);
     T.d_inst = cv.take<InstDev>(nj);
     T.d_sys = cv.take<SysDev>(S);

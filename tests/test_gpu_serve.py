@@ -139,7 +139,7 @@ def test_budget_bounds_admission(ctx, stream_setup):
     sopts.n_slots = 4
     sopts.max_batch = 64
     # an arena that holds only a few of the requests at once
-    sopts.hbm_budget = 24 << 20
+    sopts.hbm_budget = 40 << 20
     before = ctx.bytes_in_use()
     srv = nat.Server(ctx, sopts)
     assert ctx.bytes_in_use() - before == sopts.hbm_budget
