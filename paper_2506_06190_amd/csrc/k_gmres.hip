@@ -280,24 +280,38 @@ __global__ void __launch_bounds__(kRows) k_orth_coef(GmresBatch g)
         __syncthreads();
         double2* ht = g.htot + (size_t)s * mm1;
         for (int i = threadIdx.x; i <= j; i += kRows) {
-            // (G - I) s, row i; G_ik is column k's entry i for k >= i, else
-            // the conjugate of column i's entry k
+            // (G - I) s, row i, in k order; G_ik is column k's entry i for
+            // k >= i, else the conjugate of column i's entry k.  Groups of 8
+            // entries are loaded together (the last column comes from LDS).
             double er = 0.0, ei = 0.0;
-            for (int k = 0; k <= j; ++k) {
-                double2 gik;
-                if (k == j)
-                    gik = s_gj[i];
-                else if (k >= i)
-                    gik = G[(size_t)k * (k + 1) / 2 + i];
-                else {
-                    const double2 x = G[(size_t)i * (i + 1) / 2 + k];
-                    gik = make_double2(x.x, -x.y);
+            for (int k0 = 0; k0 <= j; k0 += 8) {
+                double2 gk[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int k = k0 + c;
+                    if (k >= j) {
+                        gk[c] = k == j ? s_gj[i] : make_double2(0.0, 0.0);
+                    } else if (i == j) {
+                        gk[c] = make_double2(s_gj[k].x, -s_gj[k].y);
+                    } else if (k >= i) {
+                        gk[c] = G[(size_t)k * (k + 1) / 2 + i];
+                    } else {
+                        const double2 x = G[(size_t)i * (i + 1) / 2 + k];
+                        gk[c] = make_double2(x.x, -x.y);
+                    }
                 }
-                if (k == i)
-                    gik.x -= 1.0;
-                const double2 d = cmul(gik, s_sv[k]);
-                er += d.x;
-                ei += d.y;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int k = k0 + c;
+                    if (k <= j) {
+                        double2 gik = gk[c];
+                        if (k == i)
+                            gik.x -= 1.0;
+                        const double2 d = cmul(gik, s_sv[k]);
+                        er += d.x;
+                        ei += d.y;
+                    }
+                }
             }
             ht[i] = make_double2(s_sv[i].x - er, s_sv[i].y - ei);
         }
