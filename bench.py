@@ -267,8 +267,8 @@ def run_served(nat, torch, ctx, args, dev):
 
 # ---------------------------------------------------------------- HBM traffic
 # The counter passes are separate runs of this script under rocprofv3:
-#   rocprofv3 --pmc FETCH_SIZE -d D1 -o run -- python3 bench.py --pmc-pass
-#   rocprofv3 --pmc WRITE_SIZE -d D2 -o run -- python3 bench.py --pmc-pass
+#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d D1 -o run -- python3 bench.py --pmc-pass
+#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d D2 -o run -- python3 bench.py --pmc-pass
 #   python3 bench.py --pmc-summarize D1 D2
 # --pmc-pass copies a 1 GiB buffer (the calibration kernel of known traffic)
 # and then runs one headline step with direct launches; --pmc-summarize
@@ -339,9 +339,13 @@ def pmc_summarize(d_fetch, d_write):
     lines = [
         "# HBM traffic of k_sum32<OP_MATVEC> (batched headline step, direct launches)",
         "# commands (run from the repository root, TMPDIR=/tmp):",
-        "#   rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o run -- python3 bench.py --pmc-pass",
-        "#   rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o run -- python3 bench.py --pmc-pass",
+        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o run -- \\",
+        "#       python3 bench.py --pmc-pass",
+        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o run -- \\",
+        "#       python3 bench.py --pmc-pass",
         "#   python3 bench.py --pmc-summarize gpurun_out/pmc_fetch gpurun_out/pmc_write",
+        "# The copy kernel (a 1 GiB device-to-device copy, 1 GiB read + 1 GiB written) gives",
+        "# the scale of each counter; per-launch figures are averages over the matvec dispatches.",
         f"kernel_source_sha256_16: {kernel_hash()}",
         f"matvec_dispatches: {f['dispatches']}",
         f"copy_bytes_true: {COPY_BYTES}",
