@@ -269,36 +269,36 @@ __global__ void __launch_bounds__(kRows) k_orth_coef(GmresBatch g)
         if (chunk != 0 || !g.active[s])
             continue;
         const SysDev& S = g.sys[s];
-        double2* G = g.gram + (size_t)s * g.gram_stride;  // column k at k (k + 1) / 2
+        // the full Hermitian G, column-major with leading dimension mmax + 1:
+        // column k is complete up to row j once step j has run
+        double2* G = g.gram + (size_t)s * g.gram_stride;
         __syncthreads();
         for (int i = threadIdx.x; i <= j; i += kRows) {
             s_sv[i] = chunk_sum(g.dp1 + S.off_ch * mm1, S.nch, mm1, i);
             const double2 gij = chunk_sum(g.dp2 + S.off_ch * mm1, S.nch, mm1, i);
             s_gj[i] = gij;
-            G[(size_t)j * (j + 1) / 2 + i] = gij;
+            G[(size_t)j * mm1 + i] = gij;
+            if (i < j)
+                G[(size_t)i * mm1 + j] = make_double2(gij.x, -gij.y);
         }
         __syncthreads();
         double2* ht = g.htot + (size_t)s * mm1;
         for (int i = threadIdx.x; i <= j; i += kRows) {
-            // (G - I) s, row i, in k order; G_ik is column k's entry i for
-            // k >= i, else the conjugate of column i's entry k.  Groups of 8
-            // entries are loaded together (the last column comes from LDS).
+            // (G - I) s, row i, in k order: entry (i, k) is column k's row i
+            // (loads coalesced across the rows), column j from LDS.  Groups
+            // of 8 entries are loaded together.
             double er = 0.0, ei = 0.0;
             for (int k0 = 0; k0 <= j; k0 += 8) {
                 double2 gk[8];
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
                     const int k = k0 + c;
-                    if (k >= j) {
+                    if (k >= j)
                         gk[c] = k == j ? s_gj[i] : make_double2(0.0, 0.0);
-                    } else if (i == j) {
+                    else if (i == j)
                         gk[c] = make_double2(s_gj[k].x, -s_gj[k].y);
-                    } else if (k >= i) {
-                        gk[c] = G[(size_t)k * (k + 1) / 2 + i];
-                    } else {
-                        const double2 x = G[(size_t)i * (i + 1) / 2 + k];
-                        gk[c] = make_double2(x.x, -x.y);
-                    }
+                    else
+                        gk[c] = G[(size_t)k * mm1 + i];
                 }
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {

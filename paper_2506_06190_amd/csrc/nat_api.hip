@@ -832,7 +832,7 @@ size_t bem_solve_ws_bytes(int32_t n, int32_t M, int32_t max_iter)
          sizeof(int32_t) * M, sizeof(int32_t) * M, sizeof(double2) * (size_t)M * nch * mm1,
          sizeof(double2) * (size_t)M * nch * mm1, sizeof(double) * (size_t)M * nch,
          sizeof(double) * (size_t)M * nch, sizeof(double) * (size_t)M * nch,
-         sizeof(double2) * (size_t)M * (mm1 * (mm1 + 1) / 2), sizeof(SysDev) * M,
+         sizeof(double2) * (size_t)M * (mm1 * mm1), sizeof(SysDev) * M,
          sizeof(int2) * (size_t)M * nch});
 }
 }  // namespace nat
@@ -910,7 +910,7 @@ nat_status nat_bem_solve(nat_bem_op* op, const double* v_n, int32_t n_rhs, int32
     g.normpart = cv.take<double>((size_t)M * nch);
     g.normpart2 = cv.take<double>((size_t)M * nch);
     g.wnorm0 = cv.take<double>((size_t)M * nch);
-    g.gram_stride = (int64_t)mm1 * (mm1 + 1) / 2;
+    g.gram_stride = (int64_t)mm1 * mm1;
     g.gram = cv.take<double2>((size_t)M * g.gram_stride);
     T.d_sys = cv.take<SysDev>(M);
     T.d_items = cv.take<int2>((size_t)M * nch);

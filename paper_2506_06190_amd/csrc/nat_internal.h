@@ -359,8 +359,8 @@ struct GmresBatch {
     float2* v32;         // [off_n + t] FP32 copy of the newest basis vector times w/(4 pi), or null
     double2* dp1;        // [(off_ch + chunk)(mmax+1) + i] partial <v_i, w>
     double2* dp2;        // partial <v_i, v_j> (the new Gram column)
-    double2* gram;       // [sys][gram_stride]: Gram column k of the basis at k (k + 1) / 2
-    int64_t gram_stride; // (mmax+1)(mmax+2)/2
+    double2* gram;       // [sys][gram_stride]: Gram matrix of the basis, column-major, ld mmax+1
+    int64_t gram_stride; // (mmax+1)^2
     double* wnorm0;      // [off_ch + chunk] partial |w|^2 before the projection
     double* normpart;    // [off_ch + chunk] partial |w|^2 after the update
     double* normpart2;   // ... after the second pass, when one was needed

@@ -349,7 +349,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     }
     T.max_items = sum_ch;
     const int64_t n_part = sum_pa > sum_pb ? sum_pa : sum_pb;
-    const int64_t gram_stride = (int64_t)mm1 * (mm1 + 1) / 2;
+    const int64_t gram_stride = (int64_t)mm1 * mm1;
     const size_t bytes = carve_size<>(
         {sizeof(int32_t) * 8, sizeof(int32_t) * inst_n, sizeof(double) * 2 * inst_n,
          sizeof(double) * 3 * inst_n, sizeof(double) * 3 * inst_n, sizeof(float) * 3 * inst_n,
