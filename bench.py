@@ -378,6 +378,57 @@ def traffic_from_profile():
     return float(kv["traffic_bytes_per_launch"])
 
 
+def run_dense(nat, torch, ctx, args, dev):
+    """Dense Burton-Miller path on the 5120-triangle sphere at ka = 5: assembly,
+    one solve, and 16 right-hand sides at once (FP64 matrix cores) against the
+    same 16 as four 4-wide solves (GEMV passes)."""
+    import numpy as np
+    import workloads as W
+    wl = W.config_oscillating_sphere(ka=(5.0,))
+    v, f = wl.vertices, wl.tris
+    u = wl.extra["u"]
+    c = u[f].mean(axis=1)
+    c /= np.linalg.norm(c, axis=1, keepdims=True)
+    mesh = nat.Mesh(ctx, v, f)
+    g1 = torch.from_numpy(np.ascontiguousarray(c[None, :, 2].astype(np.complex128))).to(dev)
+    g16 = torch.from_numpy(W.sh_neumann(c, 16, 5)).to(dev)
+    torch.cuda.synchronize()
+    op = nat.nat_bem_assemble(mesh, wl.k[0], True)       # warm-up
+    torch.cuda.synchronize()
+    op.close()
+    t0 = time.perf_counter()
+    op = nat.nat_bem_assemble(mesh, wl.k[0], True)
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    lay = nat.NAT_NEUMANN_PER_TRIANGLE
+    nat.nat_bem_solve(op, g1, layout=lay, tol=1e-10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rep1 = nat.nat_bem_solve(op, g1, layout=lay, tol=1e-10)
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+    nat.nat_bem_solve(op, g16, layout=lay, tol=1e-10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rep16 = nat.nat_bem_solve(op, g16, layout=lay, tol=1e-10)
+    torch.cuda.synchronize()
+    t_mfma = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for r0 in range(0, 16, 4):
+        nat.nat_bem_solve(op, g16[r0:r0 + 4].contiguous(), layout=lay, tol=1e-10)
+    torch.cuda.synchronize()
+    t_gemv = time.perf_counter() - t0
+    n = len(f)
+    op.close()
+    mesh.close()
+    return {"workload": f"icosphere {n} triangles, a = 0.1 m, ka = 5, Burton-Miller, tol 1e-10",
+            "assembly_ms": round(1e3 * t_asm, 2), "assembly_pairs_per_s": n * n / t_asm,
+            "solve_1rhs_ms": round(1e3 * t_one, 2), "iters_1rhs": rep1[0]["iters"],
+            "solve_16rhs_matrix_cores_ms": round(1e3 * t_mfma, 2),
+            "solve_16rhs_as_4x4_gemv_ms": round(1e3 * t_gemv, 2),
+            "iters_16rhs_max": max(r["iters"] for r in rep16)}
+
+
 def run_precision(nat, torch, ctx, args, dev, with_plain=True):
     import numpy as np
     import workloads as W
@@ -482,6 +533,7 @@ def main():
         out.update({k: res.pop(k) for k in ("value", "ms_per_step", "config")})
         out.update(res)
         out["precision"] = run_precision(nat, torch, ctx, args, dev, with_plain=not args.no_plain)
+        out["dense"] = run_dense(nat, torch, ctx, args, dev)
         if not args.no_serve:
             out["served"] = run_served(nat, torch, ctx, args, dev)
     elif args.workload == "served":

@@ -372,6 +372,85 @@ k_zgemv(const double2* __restrict__ M, int32_t n, const double2* __restrict__ x,
     }
 }
 
+// Y_m = M X_m for up to 8 NT right-hand sides at once on the FP64 matrix
+// cores.  The complex product is the real product of M viewed as a real
+// n x 2n matrix (interleaved re, im) with the real 2n x 2R matrix built from
+// the right-hand sides: rows 2k, 2k+1 of column pair (2m, 2m+1) hold
+// [[re x_mk, im x_mk], [-im x_mk, re x_mk]], so M is read once in its
+// stored layout for all of them.  v_mfma_f64_16x16x4f64 tiles: lane l
+// supplies A(row l % 16, k l / 16) and B(k l / 16, col l % 16) and holds
+// D(row 4 r + l / 16, col l % 16) in accumulator r.  One wave per 16 rows
+// and K segment (blockIdx.y); the segments' partial products are added in
+// segment order by k_zgemm_reduce, so the result does not depend on timing.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+template <int NT>
+__global__ void __launch_bounds__(64)
+k_zgemm_mfma(const double2* __restrict__ M, int32_t n, const double2* __restrict__ x, int64_t ld_x,
+             int32_t n_rhs, int32_t seg, double2* __restrict__ part)
+{
+    const int lane = threadIdx.x;
+    const int32_t row0 = blockIdx.x * 16;
+    const int32_t k0 = blockIdx.y * seg, k1 = min(n, k0 + seg);  // complex columns
+    const double* Mreal = reinterpret_cast<const double*>(M);
+    const int32_t ar = row0 + (lane & 15);
+    const bool arow = ar < n;
+    const int kq = lane >> 4;                // k within the step of 4 real columns
+    mfma_d4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+        acc[t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+    for (int32_t kr0 = 2 * k0; kr0 < 2 * k1; kr0 += 4) {
+        const int32_t kr = kr0 + kq;         // real column of M
+        const bool kok = kr < 2 * k1;
+        const double a = (arow && kok) ? Mreal[(size_t)ar * 2 * n + kr] : 0.0;
+        const int32_t kc = kr >> 1;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int c = 16 * t + (lane & 15);
+            const int m = c >> 1;
+            double bv = 0.0;
+            if (kok && m < n_rhs) {
+                const double2 v = x[(size_t)m * ld_x + kc];
+                bv = (kr & 1) == 0 ? ((c & 1) == 0 ? v.x : v.y) : ((c & 1) == 0 ? -v.y : v.x);
+            }
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[t], 0, 0, 0);
+        }
+    }
+    // partial [segment][rhs][row]
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int c = 16 * t + (lane & 15);
+        const int m = c >> 1;
+        if (m >= n_rhs)
+            continue;
+        double* pm = reinterpret_cast<double*>(part + ((size_t)blockIdx.y * n_rhs + m) * n);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int32_t row = row0 + 4 * r + (lane >> 4);
+            if (row < n)
+                pm[2 * (size_t)row + (c & 1)] = acc[t][r];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_zgemm_reduce(const double2* __restrict__ part, int32_t n, int32_t n_rhs, int32_t n_seg,
+               double2* __restrict__ y, int64_t ld_y)
+{
+    const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t m = blockIdx.y;
+    if (row >= n)
+        return;
+    double sr = 0.0, si = 0.0;
+    for (int32_t sg = 0; sg < n_seg; ++sg) {
+        const double2 v = part[((size_t)sg * n_rhs + m) * n + row];
+        sr += v.x;
+        si += v.y;
+    }
+    y[(size_t)m * ld_y + row] = make_double2(sr, si);
+}
+
 __global__ void __launch_bounds__(256)
 k_panel_data(const int32_t* __restrict__ T, int32_t nT, const double2* __restrict__ gv,
              int64_t ld_in, double2* __restrict__ gp, int64_t ld_out)
@@ -408,11 +487,40 @@ hipError_t launch_bem_near(const BemGeom& g, double k, double2 beta, double2* A,
     return hipGetLastError();
 }
 
+int32_t zgemm_segments(int32_t n)
+{
+    const int32_t sg = (n + 255) / 256;
+    return sg < 1 ? 1 : (sg > 16 ? 16 : sg);
+}
+
 hipError_t launch_zgemv(const double2* M, int32_t n, const double2* x, int64_t ld_x,
                         int32_t n_rhs, double2* y, int64_t ld_y, const int32_t* active,
-                        hipStream_t s, const ProfSlot& ev)
+                        hipStream_t s, const ProfSlot& ev, double2* scratch)
 {
     (void)active;
+    if (n_rhs >= kZgemmMinRhs && scratch) {
+        // matrix cores, 16 right-hand sides per pass over M (8 in a last pass of <= 8)
+        const int32_t n_seg = zgemm_segments(n);
+        const int32_t seg = (n + n_seg - 1) / n_seg;
+        for (int32_t r0 = 0; r0 < n_rhs; r0 += 16) {
+            const int32_t R = n_rhs - r0 < 16 ? n_rhs - r0 : 16;
+            hipEvent_t e0 = r0 == 0 ? ev.start : nullptr;
+            hipEvent_t e1 = r0 + 16 >= n_rhs ? ev.stop : nullptr;
+            dim3 grid(static_cast<unsigned>((n + 15) / 16), static_cast<unsigned>(n_seg));
+            if (R > 8)
+                launch_k(k_zgemm_mfma<2>, grid, dim3(64), 0, s, e0, nullptr, M, n,
+                         x + (size_t)r0 * ld_x, ld_x, R, seg, scratch);
+            else
+                launch_k(k_zgemm_mfma<1>, grid, dim3(64), 0, s, e0, nullptr, M, n,
+                         x + (size_t)r0 * ld_x, ld_x, R, seg, scratch);
+            launch_k(k_zgemm_reduce, dim3((n + 255) / 256, R), dim3(256), 0, s, nullptr, e1,
+                     static_cast<const double2*>(scratch), n, R, n_seg, y + (size_t)r0 * ld_y, ld_y);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess)
+                return e;
+        }
+        return hipSuccess;
+    }
     dim3 grid(static_cast<unsigned>((n + 3) / 4));
     for (int32_t r0 = 0; r0 < n_rhs; r0 += 4) {
         const int32_t R = n_rhs - r0 < 4 ? n_rhs - r0 : 4;

@@ -819,6 +819,12 @@ nat_status nat_bem_assemble(nat_mesh* mesh, double k, int32_t burton_miller, nat
 }  // extern "C"
 
 namespace nat {
+// Split-K partial products of the matrix-core path (none below its threshold).
+static size_t zgemm_part_len(int32_t n, int32_t M)
+{
+    return M >= kZgemmMinRhs ? (size_t)zgemm_segments(n) * 16 * (size_t)n : 0;
+}
+
 size_t bem_solve_ws_bytes(int32_t n, int32_t M, int32_t max_iter)
 {
     const size_t mm1 = (size_t)max_iter + 1;
@@ -833,7 +839,7 @@ size_t bem_solve_ws_bytes(int32_t n, int32_t M, int32_t max_iter)
          sizeof(double2) * (size_t)M * nch * mm1, sizeof(double) * (size_t)M * nch,
          sizeof(double) * (size_t)M * nch, sizeof(double) * (size_t)M * nch,
          sizeof(double2) * (size_t)M * (mm1 * mm1), sizeof(SysDev) * M,
-         sizeof(int2) * (size_t)M * nch});
+         sizeof(int2) * (size_t)M * nch, sizeof(double2) * zgemm_part_len(n, M)});
 }
 }  // namespace nat
 
@@ -914,6 +920,7 @@ nat_status nat_bem_solve(nat_bem_op* op, const double* v_n, int32_t n_rhs, int32
     g.gram = cv.take<double2>((size_t)M * g.gram_stride);
     T.d_sys = cv.take<SysDev>(M);
     T.d_items = cv.take<int2>((size_t)M * nch);
+    double2* zpart = M >= kZgemmMinRhs ? cv.take<double2>(zgemm_part_len(n, M)) : nullptr;
     T.d_nitems = dcnt + 2;
     T.d_iter = dcnt + 4;
     g.sys = T.d_sys;
@@ -942,10 +949,10 @@ nat_status nat_bem_solve(nat_bem_op* op, const double* v_n, int32_t n_rhs, int32
     } else {
         NAT_HIP(hipMemcpyAsync(gp, gin, sizeof(double2) * (size_t)M * n, hipMemcpyDeviceToDevice, s));
     }
-    NAT_HIP(launch_zgemv(op->d_B, n, gp, n, M, b, n, nullptr, s));
+    NAT_HIP(launch_zgemv(op->d_B, n, gp, n, M, b, n, nullptr, s, ProfSlot(), zpart));
     std::function<hipError_t(int32_t)> mv = [&](int32_t j) -> hipError_t {
         return launch_zgemv(op->d_A, n, g.V + (size_t)j * n, (int64_t)mm1 * n, M, g.w, n, g.active, s,
-                            prof_slot(ctx, PK_ZGEMV, 8.0 * n * (double)n * M));
+                            prof_slot(ctx, PK_ZGEMV, 8.0 * n * (double)n * M), zpart);
     };
     st = gmres_drive(ctx, g, T, b, nullptr, mv, false, s);
     if (st != NAT_OK)

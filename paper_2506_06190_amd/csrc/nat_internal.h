@@ -439,9 +439,14 @@ hipError_t launch_bem_near(const BemGeom& g, double k, double2 beta, double2* A,
                            const int32_t* near_list, int32_t n_near, hipStream_t s,
                            const ProfSlot& ev = ProfSlot());
 // y[r][i] = sum_j M[i][j] x[r][j] for the rows of n x n M, r < n_rhs
+// From this many right-hand sides on (and with a scratch buffer of
+// zgemm_segments(n) * 16 * n entries), the complex products run on the FP64
+// matrix cores, one pass over M per 16; below, a GEMV pass per 4.
+constexpr int32_t kZgemmMinRhs = 8;
+int32_t zgemm_segments(int32_t n);
 hipError_t launch_zgemv(const double2* M, int32_t n, const double2* x, int64_t ld_x,
                         int32_t n_rhs, double2* y, int64_t ld_y, const int32_t* active,
-                        hipStream_t s, const ProfSlot& ev = ProfSlot());
+                        hipStream_t s, const ProfSlot& ev = ProfSlot(), double2* scratch = nullptr);
 hipError_t launch_panel_data(const int32_t* T, int32_t nT, const double2* gv, int64_t ld_in,
                              int32_t n_rhs, double2* gp, int64_t ld_out, hipStream_t s);
 

@@ -282,3 +282,29 @@ def test_dense_oscillating_sphere_full_size(ctx):
         _say(f"  rel L2 vs oracle {e:.2e}, iters {rep[0]['iters']}")
         assert e <= 1e-9
         del A, B, Ao, Bo
+
+
+@pytest.mark.parametrize("n_rhs", [9, 20])
+def test_dense_multi_rhs_matrix_cores(ctx, n_rhs):
+    """From 8 right-hand sides on, the dense products run on the FP64 matrix
+    cores (16 per pass over the matrix, a GEMV pass for a remainder below 8);
+    the solutions agree with the same right-hand sides solved one at a time
+    (GEMV path) to rounding, and the right-hand sides span several modes."""
+    v, f, u = W.icosphere(3, 0.1)
+    c = u[f].mean(axis=1)
+    c /= np.linalg.norm(c, axis=1, keepdims=True)
+    g = torch.from_numpy(W.sh_neumann(c, n_rhs, 77)).to(DEV)
+    mesh = nat.Mesh(ctx, v, f)
+    op = nat.nat_bem_assemble(mesh, 30.0, True)
+    _say(f"dense multi-rhs: n={len(f)} n_rhs={n_rhs}")
+    p_all, rep_all = nat.nat_bem_solve(op, g, layout=nat.NAT_NEUMANN_PER_TRIANGLE, tol=1e-10)
+    torch.cuda.synchronize()
+    for r in range(n_rhs):
+        p1, rep1 = nat.nat_bem_solve(op, g[r:r + 1].contiguous(), layout=nat.NAT_NEUMANN_PER_TRIANGLE,
+                                     tol=1e-10)
+        torch.cuda.synchronize()
+        a, b = p_all[r].cpu().numpy(), p1[0].cpu().numpy()
+        assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b), r
+        assert abs(rep_all[r]["iters"] - rep1[0]["iters"]) <= 1
+    op.close()
+    mesh.close()
