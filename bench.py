@@ -479,7 +479,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["batched", "precision", "served"], default="batched")
+    ap.add_argument("--workload", choices=["batched", "precision", "served", "dense"], default="batched")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--pmc-pass", action="store_true")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
@@ -544,6 +544,15 @@ def main():
         out["ms_per_step"] = None
         out["config"] = {"workload": res["workload"]}
         out["served"] = res
+    elif args.workload == "dense":
+        res = run_dense(nat, torch, ctx, args, dev)
+        out["metric"] = "dense Burton-Miller solve, 16 right-hand sides"
+        out["unit"] = "solves/s"
+        out["value"] = 16e3 / res["solve_16rhs_matrix_cores_ms"]
+        out["ms_per_step"] = res["solve_16rhs_matrix_cores_ms"]
+        out["dtype"] = "f64"
+        out["config"] = {"workload": res["workload"]}
+        out["dense"] = res
     else:
         res = run_precision(nat, torch, ctx, args, dev, with_plain=not args.no_plain)
         out["value"] = res["fp32"]["value"]

@@ -379,58 +379,145 @@ k_zgemv(const double2* __restrict__ M, int32_t n, const double2* __restrict__ x,
 // [[re x_mk, im x_mk], [-im x_mk, re x_mk]], so M is read once in its
 // stored layout for all of them.  v_mfma_f64_16x16x4f64 tiles: lane l
 // supplies A(row l % 16, k l / 16) and B(k l / 16, col l % 16) and holds
-// D(row 4 r + l / 16, col l % 16) in accumulator r.  One wave per 16 rows
-// and K segment (blockIdx.y); the segments' partial products are added in
-// segment order by k_zgemm_reduce, so the result does not depend on timing.
+// D(row 4 r + l / 16, col l % 16) in accumulator r.  The contraction index of
+// one instruction is any 4 real columns, the same for A and B: here lane
+// group q = l / 16 takes complex columns k + 2q and k + 2q + 1 of an 8-column
+// step (two 16-byte loads per row), and the real and imaginary parts of each
+// feed one instruction apiece.  One wave per 16 RB rows and K segment
+// (blockIdx.y), so every right-hand-side fragment loaded serves RB row
+// tiles; the segments' partial products are added in segment order by
+// k_zgemm_reduce, so the result does not depend on timing.
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 
-template <int NT>
+template <int NT, int RB>
 __global__ void __launch_bounds__(64)
 k_zgemm_mfma(const double2* __restrict__ M, int32_t n, const double2* __restrict__ x, int64_t ld_x,
              int32_t n_rhs, int32_t seg, double2* __restrict__ part)
 {
     const int lane = threadIdx.x;
-    const int32_t row0 = blockIdx.x * 16;
+    const int r16 = lane & 15, q = lane >> 4;
+    const bool odd = (lane & 1) != 0;        // output column 16 t + r16 is an imaginary part
+    const int32_t row0 = blockIdx.x * 16 * RB;
     const int32_t k0 = blockIdx.y * seg, k1 = min(n, k0 + seg);  // complex columns
-    const double* Mreal = reinterpret_cast<const double*>(M);
-    const int32_t ar = row0 + (lane & 15);
-    const bool arow = ar < n;
-    const int kq = lane >> 4;                // k within the step of 4 real columns
-    mfma_d4 acc[NT];
+    // Rows past n and right-hand sides past n_rhs read a valid row instead
+    // (their results are not stored), so the loads of whole steps need no
+    // guards; only the last, partial step of a segment zeroes its operands.
+    const double2* arow[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+        arow[rb] = M + (size_t)min(row0 + 16 * rb + r16, n - 1) * n;
+    const double2* xrow[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
-        acc[t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
-    for (int32_t kr0 = 2 * k0; kr0 < 2 * k1; kr0 += 4) {
-        const int32_t kr = kr0 + kq;         // real column of M
-        const bool kok = kr < 2 * k1;
-        const double a = (arow && kok) ? Mreal[(size_t)ar * 2 * n + kr] : 0.0;
-        const int32_t kc = kr >> 1;
+        xrow[t] = x + (size_t)min((16 * t + r16) >> 1, n_rhs - 1) * ld_x;
+    mfma_d4 acc[RB][NT];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            acc[rb][t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+    // B entries: real row (re M) -> [re x, im x]; imaginary row -> [-im x, re x]
+    auto step = [&](const double2 (&c0)[RB], const double2 (&c1)[RB], const double2 (&y0)[NT],
+                    const double2 (&y1)[NT]) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int c = 16 * t + (lane & 15);
-            const int m = c >> 1;
-            double bv = 0.0;
-            if (kok && m < n_rhs) {
-                const double2 v = x[(size_t)m * ld_x + kc];
-                bv = (kr & 1) == 0 ? ((c & 1) == 0 ? v.x : v.y) : ((c & 1) == 0 ? -v.y : v.x);
-            }
-            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[t], 0, 0, 0);
+            const double b0r = odd ? y0[t].y : y0[t].x, b0i = odd ? y0[t].x : -y0[t].y;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+                acc[rb][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(c0[rb].x, b0r, acc[rb][t], 0, 0, 0);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+                acc[rb][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(c0[rb].y, b0i, acc[rb][t], 0, 0, 0);
         }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const double b1r = odd ? y1[t].y : y1[t].x, b1i = odd ? y1[t].x : -y1[t].y;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+                acc[rb][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(c1[rb].x, b1r, acc[rb][t], 0, 0, 0);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+                acc[rb][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(c1[rb].y, b1i, acc[rb][t], 0, 0, 0);
+        }
+    };
+    // Triples of whole steps, three operand sets in rotation: each step's
+    // operands are loaded two steps ahead of their products.  Refills past
+    // the last triple repeat an address already read (in bounds, unused).
+    const int32_t k24 = k0 + (max(k1 - k0, 0) / 24) * 24;
+    double2 pa0[RB], pa1[RB], px0[NT], px1[NT];   // set A
+    double2 qa0[RB], qa1[RB], qx0[NT], qx1[NT];   // set B
+    double2 ra0[RB], ra1[RB], rx0[NT], rx1[NT];   // set C
+    auto load = [&](int32_t k, double2 (&a0)[RB], double2 (&a1)[RB], double2 (&x0)[NT],
+                    double2 (&x1)[NT]) {
+        const int32_t kc = k + 2 * q;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            a0[rb] = arow[rb][kc];
+            a1[rb] = arow[rb][kc + 1];
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            x0[t] = xrow[t][kc];
+            x1[t] = xrow[t][kc + 1];
+        }
+    };
+    if (k0 < k24) {
+        load(k0, pa0, pa1, px0, px1);
+        load(k0 + 8, qa0, qa1, qx0, qx1);
+    }
+    for (int32_t k = k0; k < k24; k += 24) {
+        // the scheduling barriers keep each refill ahead of the products
+        // that follow it
+        const bool more = k + 24 < k24;
+        load(k + 16, ra0, ra1, rx0, rx1);
+        __builtin_amdgcn_sched_barrier(0);
+        step(pa0, pa1, px0, px1);
+        __builtin_amdgcn_sched_barrier(0);
+        load(more ? k + 24 : k, pa0, pa1, px0, px1);
+        __builtin_amdgcn_sched_barrier(0);
+        step(qa0, qa1, qx0, qx1);
+        __builtin_amdgcn_sched_barrier(0);
+        load(more ? k + 32 : k, qa0, qa1, qx0, qx1);
+        __builtin_amdgcn_sched_barrier(0);
+        step(ra0, ra1, rx0, rx1);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // at most two whole steps and a partial one, guarded
+    const double2 z2 = make_double2(0.0, 0.0);
+    for (int32_t k = k24; k < k1; k += 8) {
+        const int32_t kc = k + 2 * q;
+        const bool ok0 = kc < k1, ok1 = kc + 1 < k1;
+        const int32_t i0 = ok0 ? kc : k1 - 1, i1 = ok1 ? kc + 1 : k1 - 1;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            const double2 u0 = arow[rb][i0], u1 = arow[rb][i1];
+            pa0[rb] = ok0 ? u0 : z2;
+            pa1[rb] = ok1 ? u1 : z2;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const double2 u0 = xrow[t][i0], u1 = xrow[t][i1];
+            px0[t] = ok0 ? u0 : z2;
+            px1[t] = ok1 ? u1 : z2;
+        }
+        step(pa0, pa1, px0, px1);
     }
     // partial [segment][rhs][row]
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        const int c = 16 * t + (lane & 15);
+        const int c = 16 * t + r16;
         const int m = c >> 1;
         if (m >= n_rhs)
             continue;
         double* pm = reinterpret_cast<double*>(part + ((size_t)blockIdx.y * n_rhs + m) * n);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int32_t row = row0 + 4 * r + (lane >> 4);
-            if (row < n)
-                pm[2 * (size_t)row + (c & 1)] = acc[t][r];
-        }
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int32_t row = row0 + 16 * rb + 4 * r + q;
+                if (row < n)
+                    pm[2 * (size_t)row + (c & 1)] = acc[rb][t][r];
+            }
     }
 }
 
@@ -487,10 +574,29 @@ hipError_t launch_bem_near(const BemGeom& g, double k, double2 beta, double2* A,
     return hipGetLastError();
 }
 
-int32_t zgemm_segments(int32_t n)
+// Rows per wave of the matrix-core product, and its K split: about 2048
+// waves in all (eight per SIMD), at most 32 segments, each a multiple of 8
+// complex columns.
+constexpr int32_t kZgemmRows = 64;
+
+int32_t zgemm_segments(int32_t n, int32_t* seg_out)
 {
-    const int32_t sg = (n + 255) / 256;
-    return sg < 1 ? 1 : (sg > 16 ? 16 : sg);
+    if (n < 1) {
+        if (seg_out)
+            *seg_out = 8;
+        return 1;
+    }
+    const int32_t groups = (n + kZgemmRows - 1) / kZgemmRows;
+    int32_t want = (2048 + groups - 1) / groups;
+    const int32_t cap = (n + 63) / 64;
+    want = want > 32 ? 32 : want;
+    want = want > cap ? cap : want;
+    want = want < 1 ? 1 : want;
+    int32_t seg = (n + want - 1) / want;
+    seg = (seg + 7) / 8 * 8;
+    if (seg_out)
+        *seg_out = seg;
+    return (n + seg - 1) / seg;
 }
 
 hipError_t launch_zgemv(const double2* M, int32_t n, const double2* x, int64_t ld_x,
@@ -500,18 +606,18 @@ hipError_t launch_zgemv(const double2* M, int32_t n, const double2* x, int64_t l
     (void)active;
     if (n_rhs >= kZgemmMinRhs && scratch) {
         // matrix cores, 16 right-hand sides per pass over M (8 in a last pass of <= 8)
-        const int32_t n_seg = zgemm_segments(n);
-        const int32_t seg = (n + n_seg - 1) / n_seg;
+        int32_t seg = 0;
+        const int32_t n_seg = zgemm_segments(n, &seg);
         for (int32_t r0 = 0; r0 < n_rhs; r0 += 16) {
             const int32_t R = n_rhs - r0 < 16 ? n_rhs - r0 : 16;
             hipEvent_t e0 = r0 == 0 ? ev.start : nullptr;
             hipEvent_t e1 = r0 + 16 >= n_rhs ? ev.stop : nullptr;
-            dim3 grid(static_cast<unsigned>((n + 15) / 16), static_cast<unsigned>(n_seg));
+            dim3 grid(static_cast<unsigned>((n + kZgemmRows - 1) / kZgemmRows), static_cast<unsigned>(n_seg));
             if (R > 8)
-                launch_k(k_zgemm_mfma<2>, grid, dim3(64), 0, s, e0, nullptr, M, n,
+                launch_k(k_zgemm_mfma<2, kZgemmRows / 16>, grid, dim3(64), 0, s, e0, nullptr, M, n,
                          x + (size_t)r0 * ld_x, ld_x, R, seg, scratch);
             else
-                launch_k(k_zgemm_mfma<1>, grid, dim3(64), 0, s, e0, nullptr, M, n,
+                launch_k(k_zgemm_mfma<1, kZgemmRows / 16>, grid, dim3(64), 0, s, e0, nullptr, M, n,
                          x + (size_t)r0 * ld_x, ld_x, R, seg, scratch);
             launch_k(k_zgemm_reduce, dim3((n + 255) / 256, R), dim3(256), 0, s, nullptr, e1,
                      static_cast<const double2*>(scratch), n, R, n_seg, y + (size_t)r0 * ld_y, ld_y);

@@ -443,7 +443,7 @@ hipError_t launch_bem_near(const BemGeom& g, double k, double2 beta, double2* A,
 // zgemm_segments(n) * 16 * n entries), the complex products run on the FP64
 // matrix cores, one pass over M per 16; below, a GEMV pass per 4.
 constexpr int32_t kZgemmMinRhs = 8;
-int32_t zgemm_segments(int32_t n);
+int32_t zgemm_segments(int32_t n, int32_t* seg = nullptr);
 hipError_t launch_zgemv(const double2* M, int32_t n, const double2* x, int64_t ld_x,
                         int32_t n_rhs, double2* y, int64_t ld_y, const int32_t* active,
                         hipStream_t s, const ProfSlot& ev = ProfSlot(), double2* scratch = nullptr);

@@ -284,13 +284,18 @@ def test_dense_oscillating_sphere_full_size(ctx):
         del A, B, Ao, Bo
 
 
-@pytest.mark.parametrize("n_rhs", [9, 20])
-def test_dense_multi_rhs_matrix_cores(ctx, n_rhs):
+@pytest.mark.parametrize("mesh_kind,n_rhs", [("ico3", 9), ("ico3", 20), ("cube13", 16)])
+def test_dense_multi_rhs_matrix_cores(ctx, mesh_kind, n_rhs):
     """From 8 right-hand sides on, the dense products run on the FP64 matrix
-    cores (16 per pass over the matrix, a GEMV pass for a remainder below 8);
-    the solutions agree with the same right-hand sides solved one at a time
-    (GEMV path) to rounding, and the right-hand sides span several modes."""
-    v, f, u = W.icosphere(3, 0.1)
+    cores (16 per pass over the matrix, split over K segments); the solutions
+    agree with the same right-hand sides solved one at a time (GEMV path) to
+    rounding.  The 2028-triangle cube-sphere leaves a ragged last row tile and
+    a last K segment with one whole step and a partial one."""
+    if mesh_kind == "ico3":
+        v, f, u = W.icosphere(3, 0.1)
+    else:
+        u, f = W.cubesphere_unit(13)
+        v = 0.1 * u
     c = u[f].mean(axis=1)
     c /= np.linalg.norm(c, axis=1, keepdims=True)
     g = torch.from_numpy(W.sh_neumann(c, n_rhs, 77)).to(DEV)
