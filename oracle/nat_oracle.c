@@ -272,10 +272,12 @@ void orc_mc_rhs(int32_t N, const double* y, double k, double w, double eps,
  *   p(x_q) = (1/c_q) [ sum_j [|x_q - y_j| >= eps] w (dG/dn_j p_j - G g_j)
  *                      - (eps/2) g(x_q) ]
  * c_q = 1/2 for surface points (paper); c_q = 1 with eps = 0 evaluates the
- * exterior representation formula. */
+ * exterior representation formula.  c_arr, when not NULL, gives c_q per
+ * target instead (orc_free_terms). */
 void orc_mc_eval(int32_t Q, const double* x, const double* gx_in, double c_q,
-                 int32_t N, const double* y, const double* ny, const double* g_in,
-                 const double* p_in, double k, double w, double eps, double* out)
+                 const double* c_arr, int32_t N, const double* y, const double* ny,
+                 const double* g_in, const double* p_in, double k, double w, double eps,
+                 double* out)
 {
     const cplx* g = (const cplx*)g_in;
     const cplx* p = (const cplx*)p_in;
@@ -292,7 +294,77 @@ void orc_mc_eval(int32_t Q, const double* x, const double* gx_in, double c_q,
                 s += w * (orc_dGdny(k, x + 3 * q, y + 3 * j, ny + 3 * j) * p[j] - orc_G(k, r) * g[j]);
         }
         cplx disk = gx ? 0.5 * eps * gx[q] : 0.0;
-        o[q] = (s - disk) / c_q;
+        o[q] = (s - disk) / (c_arr ? c_arr[q] : c_q);
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Free term of the surface identity at a query point.  The identity      */
+/* c(x) p(x) = int (p dG/dn_y - G g) holds on the boundary with             */
+/* c(x) = 1 + int dG0/dn_y dS_y (G0 the Laplace kernel), i.e. one minus the */
+/* solid angle Omega(x) the body subtends at x over 4 pi (the Gauss         */
+/* integral); c = 1/2 where the surface is smooth, the paper's value.       */
+/* Omega(x) is the sum over the mesh triangles of their signed solid angles */
+/* at x (Van Oosterom & Strackee 1983), leaving out the triangles x lies on */
+/* (their contribution is zero: x is in their plane).  A query is on a      */
+/* vertex when two of its barycentric weights (1 - b1 - b2, b1, b2) are     */
+/* exactly zero and on an edge when one is; otherwise c = 1/2.             */
+/* jump = 0 gives c = 1/2 for every query.                                 */
+/* ---------------------------------------------------------------------- */
+static double tri_solid_angle(const double* x, const double* a, const double* b, const double* c)
+{
+    double r1[3], r2[3], r3[3], cr[3];
+    sub3(a, x, r1);
+    sub3(b, x, r2);
+    sub3(c, x, r3);
+    cr[0] = r2[1] * r3[2] - r2[2] * r3[1];
+    cr[1] = r2[2] * r3[0] - r2[0] * r3[2];
+    cr[2] = r2[0] * r3[1] - r2[1] * r3[0];
+    double num = r1[0] * cr[0] + r1[1] * cr[1] + r1[2] * cr[2];
+    double l1 = norm3(r1), l2 = norm3(r2), l3 = norm3(r3);
+    double d12 = r1[0] * r2[0] + r1[1] * r2[1] + r1[2] * r2[2];
+    double d13 = r1[0] * r3[0] + r1[1] * r3[1] + r1[2] * r3[2];
+    double d23 = r2[0] * r3[0] + r2[1] * r3[1] + r2[2] * r3[2];
+    double den = l1 * l2 * l3 + d12 * l3 + d13 * l2 + d23 * l1;
+    return 2.0 * atan2(num, den);
+}
+
+void orc_free_terms(const double* V, const int32_t* T, int32_t nT, const int32_t* q_tri,
+                    const double* q_bary, int32_t Q, int32_t jump, double* c_out)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int32_t q = 0; q < Q; ++q) {
+        c_out[q] = 0.5;
+        if (!jump)
+            continue;
+        const int32_t* tv = T + 3 * q_tri[q];
+        double b1 = q_bary[2 * q], b2 = q_bary[2 * q + 1];
+        double wt[3] = {1.0 - b1 - b2, b1, b2};
+        int zeros = (wt[0] == 0.0) + (wt[1] == 0.0) + (wt[2] == 0.0);
+        if (zeros == 0)
+            continue;
+        /* the vertices the point lies on: the corners with nonzero weight */
+        int32_t on[2];
+        int n_on = 0;
+        for (int c = 0; c < 3; ++c)
+            if (wt[c] != 0.0 && n_on < 2)
+                on[n_on++] = tv[c];
+        double x[3];
+        for (int c = 0; c < 3; ++c)
+            x[c] = wt[0] * V[3 * tv[0] + c] + wt[1] * V[3 * tv[1] + c] + wt[2] * V[3 * tv[2] + c];
+        if (zeros == 2)
+            for (int c = 0; c < 3; ++c)
+                x[c] = V[3 * on[0] + c];
+        double omega = 0.0;
+        for (int32_t t = 0; t < nT; ++t) {
+            const int32_t* u = T + 3 * t;
+            int has0 = u[0] == on[0] || u[1] == on[0] || u[2] == on[0];
+            int has1 = n_on > 1 && (u[0] == on[1] || u[1] == on[1] || u[2] == on[1]);
+            if (zeros == 2 ? has0 : (has0 && has1))
+                continue;
+            omega += tri_solid_angle(x, V + 3 * u[0], V + 3 * u[1], V + 3 * u[2]);
+        }
+        c_out[q] = 1.0 - omega / (4.0 * M_PI);
     }
 }
 
@@ -419,7 +491,7 @@ int32_t orc_mcbem(const double* V, int32_t nV, const int32_t* T, int32_t nT,
                   int32_t Q, int32_t N, uint64_t seed, double eps_scale, double tol,
                   int32_t max_iter, double* p_out /* complex [n_modes][Q] */,
                   double* p_smp_out /* complex [n_modes][N] or NULL */, int32_t* iters,
-                  double* resid, int32_t* smp_tri, double* smp_bary)
+                  double* resid, int32_t* smp_tri, double* smp_bary, int32_t jump)
 {
     (void)nV;
     double* area = (double*)malloc(sizeof(double) * (size_t)nT);
@@ -444,6 +516,8 @@ int32_t orc_mcbem(const double* V, int32_t nV, const int32_t* T, int32_t nT,
     cplx* b = (cplx*)malloc(sizeof(cplx) * (size_t)N);
     cplx* p = (cplx*)malloc(sizeof(cplx) * (size_t)N);
     cplx* M = (cplx*)malloc(sizeof(cplx) * (size_t)N * (size_t)N);
+    double* cq = (double*)malloc(sizeof(double) * (size_t)(Q > 0 ? Q : 1));
+    orc_free_terms(V, T, nT, q_tri, q_bary, Q, jump, cq);
     int32_t status = 0;
     for (int32_t m = 0; m < n_modes; ++m) {
         const double* gm = g_in + 2 * (size_t)m * (size_t)ng;
@@ -455,7 +529,7 @@ int32_t orc_mcbem(const double* V, int32_t nV, const int32_t* T, int32_t nT,
                              &resid[m]);
         if (resid[m] > tol)
             status = 3;
-        orc_mc_eval(Q, xq, (const double*)gq, 0.5, N, y, ny, (const double*)gj,
+        orc_mc_eval(Q, xq, (const double*)gq, 0.5, cq, N, y, ny, (const double*)gj,
                     (const double*)p, kv[m], w, eps, p_out + 2 * (size_t)m * (size_t)Q);
         if (p_smp_out)
             memcpy(p_smp_out + 2 * (size_t)m * (size_t)N, p, sizeof(cplx) * (size_t)N);
@@ -471,6 +545,7 @@ int32_t orc_mcbem(const double* V, int32_t nV, const int32_t* T, int32_t nT,
     free(b);
     free(p);
     free(M);
+    free(cq);
     return status;
 }
 

@@ -58,14 +58,15 @@ def lib():
         L.orc_kernels.argtypes = [C.c_double, _d, _d, _d, _d, _d]
         L.orc_mc_matrix.argtypes = [C.c_int32, _d, _d, C.c_double, C.c_double, C.c_double, _d]
         L.orc_mc_rhs.argtypes = [C.c_int32, _d, C.c_double, C.c_double, C.c_double, _d, _d]
-        L.orc_mc_eval.argtypes = [C.c_int32, _d, C.c_void_p, C.c_double, C.c_int32, _d, _d,
-                                  _d, _d, C.c_double, C.c_double, C.c_double, _d]
+        L.orc_mc_eval.argtypes = [C.c_int32, _d, C.c_void_p, C.c_double, C.c_void_p, C.c_int32,
+                                  _d, _d, _d, _d, C.c_double, C.c_double, C.c_double, _d]
+        L.orc_free_terms.argtypes = [_d, _i, C.c_int32, _i, _d, C.c_int32, C.c_int32, _d]
         L.orc_gmres.argtypes = [C.c_int32, _d, _d, _d, C.c_double, C.c_int32,
                                 C.POINTER(C.c_double)]
         L.orc_gmres.restype = C.c_int32
         L.orc_mcbem.argtypes = [_d, C.c_int32, _i, C.c_int32, _d, C.c_int32, C.c_int32, _d,
                                 _i, _d, C.c_int32, C.c_int32, C.c_uint64, C.c_double,
-                                C.c_double, C.c_int32, _d, C.c_void_p, _i, _d, _i, _d]
+                                C.c_double, C.c_int32, _d, C.c_void_p, _i, _d, _i, _d, C.c_int32]
         L.orc_mcbem.restype = C.c_int32
         L.orc_gauss_legendre01.argtypes = [C.c_int32, _d, _d]
         L.orc_self_panel.argtypes = [C.c_double, _d, _d, _d, _d]
@@ -178,16 +179,33 @@ def mc_rhs(y, k, w, eps, g):
 
 
 def mc_eval(x, gx, c_q, y, ny, g, p, k, w, eps):
-    """Stage-B sum at targets x; gx=None drops the disk term (exterior use)."""
+    """Stage-B sum at targets x; gx=None drops the disk term (exterior use).
+    c_q: one free term for every target, or an array of one per target."""
     x, y, ny = _f64(x), _f64(y), _f64(ny)
     out = np.empty(len(x), dtype=np.complex128)
     gxa = None
     if gx is not None:
         gxa = _c2d(gx)
+    carr = None
+    if np.ndim(c_q) > 0:
+        carr = _f64(c_q)
+        assert carr.shape == (len(x),)
     lib().orc_mc_eval(len(x), x.reshape(-1),
                       gxa.ctypes.data_as(C.c_void_p) if gxa is not None else None,
-                      float(c_q), len(y), y.reshape(-1), ny.reshape(-1), _c2d(g), _c2d(p),
+                      0.5 if carr is not None else float(c_q),
+                      carr.ctypes.data_as(C.c_void_p) if carr is not None else None,
+                      len(y), y.reshape(-1), ny.reshape(-1), _c2d(g), _c2d(p),
                       float(k), float(w), float(eps), out.view(np.float64))
+    return out
+
+
+def free_terms(V, T, q_tri, q_bary, jump=1):
+    """Free term c of the surface identity at each query (1/2 on smooth parts;
+    one minus the body's solid angle over 4 pi at vertices and edges)."""
+    V, T, q_tri, q_bary = _f64(V), _i32(T), _i32(q_tri), _f64(q_bary)
+    out = np.empty(len(q_tri))
+    lib().orc_free_terms(V.reshape(-1), T.reshape(-1), len(T), q_tri, q_bary.reshape(-1),
+                         len(q_tri), int(jump), out)
     return out
 
 
@@ -202,7 +220,7 @@ def gmres(A, b, tol=1e-12, max_iter=200):
 
 
 def mcbem(V, T, g, k, q_tri, q_bary, N, seed, eps_scale=1.0, tol=1e-12, max_iter=200,
-          layout=0, want_samples=False):
+          layout=0, want_samples=False, jump=0):
     """The whole MC-BEM estimate for n_modes (k_m, g_m) pairs.
 
     g: complex (n_modes, V) per-vertex (layout 0) or (n_modes, T) per triangle.
@@ -226,7 +244,7 @@ def mcbem(V, T, g, k, q_tri, q_bary, N, seed, eps_scale=1.0, tol=1e-12, max_iter
                          float(eps_scale), float(tol), int(max_iter),
                          p.view(np.float64).reshape(-1),
                          ps.ctypes.data_as(C.c_void_p) if ps is not None else None,
-                         iters, resid, tri, bary.reshape(-1))
+                         iters, resid, tri, bary.reshape(-1), int(jump))
     out = dict(p=p, iters=iters, resid=resid, tri=tri, bary=bary, status=int(st))
     if want_samples:
         out["p_samples"] = ps
