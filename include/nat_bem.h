@@ -69,9 +69,18 @@ typedef enum {
     NAT_NEUMANN_PER_TRIANGLE = 1 /* g constant on each triangle (Section 3.4 scenes)   */
 } nat_neumann_layout;
 
+/* Free term c_q of the surface identity c_q p(x_q) = integral, used when
+ * the estimate is evaluated at the queries (eq. BIE, Section 4.2). */
+typedef enum {
+    NAT_JUMP_HALF = 0,       /* c_q = 1/2 at every query (the paper's value)             */
+    NAT_JUMP_POLYHEDRAL = 1  /* c_q = 1 - Omega/(4 pi) for queries exactly on a mesh
+                              * vertex or edge, Omega the solid angle the body subtends
+                              * there (nat_mesh_free_terms); 1/2 elsewhere          */
+} nat_jump;
+
 /* Options of the Monte-Carlo estimate.  nat_mc_opts_default() fills the
  * paper's settings: linear-solver tolerance 1e-6, at most 200 iterations
- * (Section 6.1), disk radius eps = sqrt(|Gamma| / (pi N)). */
+ * (Section 6.1), disk radius eps = sqrt(|Gamma| / (pi N)), c_q = 1/2. */
 typedef struct {
     int32_t precision;      /* nat_precision                                         */
     int32_t layout;         /* nat_neumann_layout of v_n                             */
@@ -79,6 +88,8 @@ typedef struct {
     double gmres_tol;       /* relative residual |r| / |b| to stop at; > 0           */
     int32_t gmres_max_iter; /* 1 .. 1000                                             */
     int32_t flags;          /* 0 or NAT_MC_NO_GRAPH                                  */
+    int32_t jump;           /* nat_jump                                              */
+    int32_t reserved;       /* 0                                                     */
 } nat_mc_opts;
 
 /* nat_mc_opts.flags: launch every GMRES kernel directly instead of replaying
@@ -127,6 +138,15 @@ nat_status nat_mesh_validate(const double* vertices, int32_t n_vertices, const i
  * bit.  Validates the mesh first. */
 nat_status nat_mesh_geometry(const double* vertices, int32_t n_vertices, const int32_t* tris,
                              int32_t n_tris, double* area, double* normal, double* cdf);
+/* Host-only: the free terms nat_mesh_create stores for NAT_JUMP_POLYHEDRAL.
+ * c_vert[n_vertices]: 1 - Omega_v/(4 pi), Omega_v the solid angle of the body
+ * at the vertex, from its faces closed by a cap of triangles through a point
+ * inside along the vertex normal (signed solid angles, Van Oosterom and
+ * Strackee 1983).  c_edge[n_tris][3]: 1 - phi/(2 pi) for the edge opposite
+ * corner i of the triangle, phi the interior dihedral angle between the two
+ * faces of the edge.  Validates the mesh first; either output may be NULL. */
+nat_status nat_mesh_free_terms(const double* vertices, int32_t n_vertices, const int32_t* tris,
+                               int32_t n_tris, double* c_vert, double* c_edge);
 /* Total area |Gamma| and the sizes; any output pointer may be NULL. */
 nat_status nat_mesh_info(const nat_mesh* mesh, double* area, int32_t* n_vertices,
                          int32_t* n_tris);
@@ -154,8 +174,12 @@ nat_status nat_mcbem_samples(nat_mesh* mesh, int32_t n_samples, uint64_t seed, i
  *   Stage A  (1/2) p_i - sum_{j: r_ij >= eps} w dG(y_i,y_j)/dn_j p_j
  *              = - sum_{j: r_ij >= eps} w G(y_i,y_j) g_j - (eps/2) g_i
  *            solved by GMRES (x0 = 0, unrestarted, tol, max_iter);
- *   Stage B  p(x_q) = 2 [ sum_{j: |x_q-y_j| >= eps} w (dG/dn_j p_j - G g_j)
- *                         - (eps/2) g(x_q) ].
+ *   Stage B  p(x_q) = (1/c_q) [ sum_{j: |x_q-y_j| >= eps} w (dG/dn_j p_j - G g_j)
+ *                               - (eps/2) g(x_q) ],
+ *            c_q = 1/2, or per query with opts->jump = NAT_JUMP_POLYHEDRAL.
+ *            A query is on a vertex when two of its barycentric weights
+ *            (1 - b1 - b2, b1, b2), evaluated in double precision, are exactly
+ *            zero, and on an edge when one is.
  * v_n:      device complex [n_modes][n_vertices or n_tris] (opts->layout)
  * k:        host double[n_modes], each > 0
  * q_tri, q_bary: device int32[Q], double[Q][2]: query points on the mesh,

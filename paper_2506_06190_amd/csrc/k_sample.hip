@@ -231,6 +231,36 @@ hipError_t launch_checks_batch(const SurfBatch& b, int64_t max_work, hipStream_t
     return hipGetLastError();
 }
 
+// 1 / c_q for every query of every instance: a query exactly on a mesh
+// vertex (two of its barycentric weights zero) or edge (one zero) takes the
+// mesh's free term there, any other point c_q = 1/2.
+__global__ void __launch_bounds__(256)
+k_jump_batch(const SurfBatch b)
+{
+    const SurfJob& X = b.jobs[blockIdx.y];
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= X.Q)
+        return;
+    const int32_t t = X.q_tri[i];
+    const double b1 = X.q_bary[2 * i], b2 = X.q_bary[2 * i + 1];
+    const double w0 = 1.0 - b1 - b2;
+    const bool z0 = w0 == 0.0, z1 = b1 == 0.0, z2 = b2 == 0.0;
+    double c = 0.5;
+    if (z1 && z2)
+        c = X.cvert[X.T[3 * t + 0]];
+    else if (z0 && z2)
+        c = X.cvert[X.T[3 * t + 1]];
+    else if (z0 && z1)
+        c = X.cvert[X.T[3 * t + 2]];
+    else if (z0)
+        c = X.cedge[3 * t + 0];
+    else if (z1)
+        c = X.cedge[3 * t + 1];
+    else if (z2)
+        c = X.cedge[3 * t + 2];
+    b.qfac[X.oq + i] = 1.0 / c;
+}
+
 hipError_t launch_surface_batch(const SurfBatch& b, int32_t max_n, int32_t max_q, hipStream_t s)
 {
     if (b.n_jobs <= 0 || max_n <= 0)
@@ -246,6 +276,10 @@ hipError_t launch_surface_batch(const SurfBatch& b, int32_t max_n, int32_t max_q
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_neumann_batch, dim3((mx + 255) / 256, nj, max_q > 0 ? 2 : 1), dim3(256), 0, s, b);
+    e = hipGetLastError();
+    if (e != hipSuccess || !b.qfac || max_q <= 0)
+        return e;
+    hipLaunchKernelGGL(k_jump_batch, dim3((max_q + 255) / 256, nj), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

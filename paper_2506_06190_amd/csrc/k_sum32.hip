@@ -246,7 +246,8 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
 // Combine the splits of one system's targets (TwoSum in FP32) and apply the
 // epilogue of the operation in FP64:
 //   RHS   b_i = -acc_i - (eps/2) g_i
-//   EVAL  p_q = 2 (acc_q - (eps/2) g_q)
+//   EVAL  p_q = (1/c_q) (acc_q - (eps/2) g_q), 1/c_q = 2 unless the instance
+//         carries per-query factors
 template <int OP>
 __global__ void __launch_bounds__(256)
 k_reduce32(const Sum32Batch p, const double2* __restrict__ g_tgt, double2* __restrict__ out_n)
@@ -284,7 +285,9 @@ k_reduce32(const Sum32Batch p, const double2* __restrict__ g_tgt, double2* __res
         out_n[S.off_n + i] = make_double2(-accr - 0.5 * S.eps * g.x, -acci - 0.5 * S.eps * g.y);
     } else {
         const double2 g = g_tgt[S.off_q + i];
-        S.out_q[i] = make_double2(2.0 * (accr - 0.5 * S.eps * g.x), 2.0 * (acci - 0.5 * S.eps * g.y));
+        const double* qf = p.inst[S.inst].qfac;
+        const double f = qf ? qf[i] : 2.0;
+        S.out_q[i] = make_double2(f * (accr - 0.5 * S.eps * g.x), f * (acci - 0.5 * S.eps * g.y));
     }
 }
 

@@ -79,8 +79,9 @@ __global__ void __launch_bounds__(256) k_sum64(SumArgs a)
         out.y = 0.5 * x.y - si;
     } else {
         const double2 g = a.g_tgt[(size_t)m * a.ld_gt + i];
-        out.x = 2.0 * (sr - 0.5 * eps * g.x);
-        out.y = 2.0 * (si - 0.5 * eps * g.y);
+        const double f = a.qfac ? a.qfac[i] : 2.0;
+        out.x = f * (sr - 0.5 * eps * g.x);
+        out.y = f * (si - 0.5 * eps * g.y);
     }
     a.out[(size_t)m * a.ld_out + i] = out;
 }

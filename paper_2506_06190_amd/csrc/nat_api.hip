@@ -392,6 +392,8 @@ void nat_mc_opts_default(nat_mc_opts* o)
     o->gmres_tol = 1e-6;
     o->gmres_max_iter = 200;
     o->flags = 0;
+    o->jump = NAT_JUMP_HALF;
+    o->reserved = 0;
 }
 
 nat_status nat_ctx_create(int32_t device, size_t hbm_budget_bytes, nat_ctx** out)
@@ -559,6 +561,140 @@ static nat_status mesh_geometry(const double* V, int32_t n_tris, const int32_t* 
     return NAT_OK;
 }
 
+// Signed solid angle of triangle (a, b, c) seen from x (Van Oosterom and
+// Strackee 1983): positive when x is on the side the triangle's normal
+// (b - a) x (c - a) points away from.
+static double solid_angle(const double* x, const double* a, const double* b, const double* c)
+{
+    const double r1[3] = {a[0] - x[0], a[1] - x[1], a[2] - x[2]};
+    const double r2[3] = {b[0] - x[0], b[1] - x[1], b[2] - x[2]};
+    const double r3[3] = {c[0] - x[0], c[1] - x[1], c[2] - x[2]};
+    const double det = r1[0] * (r2[1] * r3[2] - r2[2] * r3[1]) - r1[1] * (r2[0] * r3[2] - r2[2] * r3[0]) +
+                       r1[2] * (r2[0] * r3[1] - r2[1] * r3[0]);
+    const double l1 = std::sqrt(r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2]);
+    const double l2 = std::sqrt(r2[0] * r2[0] + r2[1] * r2[1] + r2[2] * r2[2]);
+    const double l3 = std::sqrt(r3[0] * r3[0] + r3[1] * r3[1] + r3[2] * r3[2]);
+    const double den = l1 * l2 * l3 + (r1[0] * r2[0] + r1[1] * r2[1] + r1[2] * r2[2]) * l3 +
+                       (r1[0] * r3[0] + r1[1] * r3[1] + r1[2] * r3[2]) * l2 +
+                       (r2[0] * r3[0] + r2[1] * r3[1] + r2[2] * r3[2]) * l1;
+    return 2.0 * std::atan2(det, den);
+}
+
+// Free terms c = 1 - Omega/(4 pi) of the exterior surface identity at the
+// vertices and on the edges of a closed, outward-oriented mesh (Omega: the
+// solid angle the body subtends at the point).
+//  * Vertex v: its faces (v, a, b) form a cone; closing it with the cap
+//    triangles (c', b, a) through c' = v - L n_v (n_v the area-weighted
+//    normal, L the mean length of v's edges) gives a closed oriented surface
+//    whose solid angle at its apex v is the cone's.  The faces through v add
+//    nothing (v is in their planes), so Omega is the sum over the cap.
+//  * Edge a -> b of triangle (a, b, p) with neighbour (b, a, p'): with u, u'
+//    the unit directions from the edge to p and p' across it and e the edge
+//    direction, turning u about e in the positive sense leaves the body, so
+//    the interior dihedral angle phi is the angle from u to u' the other way
+//    round: alpha = atan2((u x u').e, u.u'), phi = -alpha (alpha <= 0) or
+//    2 pi - alpha; Omega = 2 phi.
+static void mesh_free_terms(const double* V, int32_t nV, const int32_t* T, int32_t nT,
+                            double* c_vert, double* c_edge)
+{
+    std::vector<double> nsum(3 * (size_t)nV, 0.0), lsum((size_t)nV, 0.0);
+    std::vector<int32_t> deg((size_t)nV, 0);
+    for (int32_t t = 0; t < nT; ++t) {
+        const int32_t* tv = T + 3 * (size_t)t;
+        const double* p0 = V + 3 * (size_t)tv[0];
+        const double* p1 = V + 3 * (size_t)tv[1];
+        const double* p2 = V + 3 * (size_t)tv[2];
+        const double e1[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+        const double e2[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+        const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                              e1[0] * e2[1] - e1[1] * e2[0]};
+        for (int i = 0; i < 3; ++i) {
+            const int32_t v = tv[i];
+            const double* a = V + 3 * (size_t)tv[(i + 1) % 3];
+            const double* pv = V + 3 * (size_t)v;
+            for (int d = 0; d < 3; ++d)
+                nsum[3 * (size_t)v + d] += cr[d];
+            lsum[v] += std::sqrt((a[0] - pv[0]) * (a[0] - pv[0]) + (a[1] - pv[1]) * (a[1] - pv[1]) +
+                                 (a[2] - pv[2]) * (a[2] - pv[2]));
+            deg[v] += 1;
+        }
+    }
+    if (c_vert) {
+        std::vector<double> apex(3 * (size_t)nV), omega((size_t)nV, 0.0);
+        for (int32_t v = 0; v < nV; ++v) {
+            const double* n = &nsum[3 * (size_t)v];
+            const double nl = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+            const double L = deg[v] > 0 ? lsum[v] / deg[v] : 0.0;
+            for (int d = 0; d < 3; ++d)
+                apex[3 * (size_t)v + d] = V[3 * (size_t)v + d] - (nl > 0.0 ? L * n[d] / nl : 0.0);
+        }
+        for (int32_t t = 0; t < nT; ++t) {
+            const int32_t* tv = T + 3 * (size_t)t;
+            for (int i = 0; i < 3; ++i) {
+                const int32_t v = tv[i];
+                const double* a = V + 3 * (size_t)tv[(i + 1) % 3];
+                const double* b = V + 3 * (size_t)tv[(i + 2) % 3];
+                omega[v] += solid_angle(V + 3 * (size_t)v, &apex[3 * (size_t)v], b, a);
+            }
+        }
+        for (int32_t v = 0; v < nV; ++v)
+            c_vert[v] = 1.0 - omega[v] / (4.0 * M_PI);
+    }
+    if (c_edge) {
+        std::unordered_map<uint64_t, int32_t> third;  // directed edge -> opposite vertex
+        third.reserve(3 * (size_t)nT * 2);
+        auto key = [](int32_t a, int32_t b) {
+            return (static_cast<uint64_t>(static_cast<uint32_t>(a)) << 32) | static_cast<uint32_t>(b);
+        };
+        for (int32_t t = 0; t < nT; ++t) {
+            const int32_t* tv = T + 3 * (size_t)t;
+            for (int i = 0; i < 3; ++i)
+                third[key(tv[(i + 1) % 3], tv[(i + 2) % 3])] = tv[i];
+        }
+        for (int32_t t = 0; t < nT; ++t) {
+            const int32_t* tv = T + 3 * (size_t)t;
+            for (int i = 0; i < 3; ++i) {
+                const double* a = V + 3 * (size_t)tv[(i + 1) % 3];
+                const double* b = V + 3 * (size_t)tv[(i + 2) % 3];
+                const double* p = V + 3 * (size_t)tv[i];
+                const double* q = V + 3 * (size_t)third.at(key(tv[(i + 2) % 3], tv[(i + 1) % 3]));
+                double e[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+                const double el = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+                for (int d = 0; d < 3; ++d)
+                    e[d] /= el;
+                double u[3] = {p[0] - a[0], p[1] - a[1], p[2] - a[2]};
+                double w[3] = {q[0] - a[0], q[1] - a[1], q[2] - a[2]};
+                const double ue = u[0] * e[0] + u[1] * e[1] + u[2] * e[2];
+                const double we = w[0] * e[0] + w[1] * e[1] + w[2] * e[2];
+                for (int d = 0; d < 3; ++d) {
+                    u[d] -= ue * e[d];
+                    w[d] -= we * e[d];
+                }
+                const double cx[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2],
+                                      u[0] * w[1] - u[1] * w[0]};
+                const double alpha = std::atan2(cx[0] * e[0] + cx[1] * e[1] + cx[2] * e[2],
+                                                u[0] * w[0] + u[1] * w[1] + u[2] * w[2]);
+                const double phi = alpha <= 0.0 ? -alpha : 2.0 * M_PI - alpha;
+                c_edge[3 * (size_t)t + i] = 1.0 - phi / (2.0 * M_PI);
+            }
+        }
+    }
+}
+
+nat_status nat_mesh_free_terms(const double* vertices, int32_t n_vertices, const int32_t* tris,
+                               int32_t n_tris, double* c_vert, double* c_edge)
+{
+    nat_status st = validate_topology(vertices, n_vertices, tris, n_tris);
+    if (st != NAT_OK)
+        return st;
+    std::vector<double> a(n_tris), nn(3 * (size_t)n_tris), c(n_tris);
+    st = mesh_geometry(vertices, n_tris, tris, a.data(), nn.data(), c.data());
+    if (st != NAT_OK)
+        return st;
+    mesh_free_terms(vertices, n_vertices, tris, n_tris, c_vert, c_edge);
+    return NAT_OK;
+}
+
 nat_status nat_mesh_validate(const double* vertices, int32_t n_vertices, const int32_t* tris,
                              int32_t n_tris)
 {
@@ -629,9 +765,12 @@ nat_status nat_mesh_create(nat_ctx* ctx, const double* vertices, int32_t n_verti
         delete m;
         return st;
     }
+    std::vector<double> cvert((size_t)n_vertices), cedge(3 * (size_t)n_tris);
+    mesh_free_terms(m->V.data(), n_vertices, m->T.data(), n_tris, cvert.data(), cedge.data());
     const size_t bV = sizeof(double) * 3 * (size_t)n_vertices, bT = sizeof(int32_t) * 3 * (size_t)n_tris,
-                 bN = sizeof(double) * 3 * (size_t)n_tris, bC = sizeof(double) * (size_t)n_tris;
-    m->bytes = nat::carve_size<>({bV, bT, bN, bC});
+                 bN = sizeof(double) * 3 * (size_t)n_tris, bC = sizeof(double) * (size_t)n_tris,
+                 bCV = sizeof(double) * (size_t)n_vertices, bCE = sizeof(double) * 3 * (size_t)n_tris;
+    m->bytes = nat::carve_size<>({bV, bT, bN, bC, bCV, bCE});
     void* blk = nullptr;
     st = nat::dev_alloc(ctx, m->bytes, &blk);
     if (st != NAT_OK) {
@@ -643,6 +782,8 @@ nat_status nat_mesh_create(nat_ctx* ctx, const double* vertices, int32_t n_verti
     m->d_T = cv.take<int32_t>(3 * (size_t)n_tris);
     m->d_normal = cv.take<double>(3 * (size_t)n_tris);
     m->d_cdf = cv.take<double>(n_tris);
+    m->d_cvert = cv.take<double>(n_vertices);
+    m->d_cedge = cv.take<double>(3 * (size_t)n_tris);
     hipError_t e = hipMemcpy(m->d_V, m->V.data(), bV, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(m->d_T, m->T.data(), bT, hipMemcpyHostToDevice);
@@ -650,6 +791,10 @@ nat_status nat_mesh_create(nat_ctx* ctx, const double* vertices, int32_t n_verti
         e = hipMemcpy(m->d_normal, m->normal.data(), bN, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(m->d_cdf, m->cdf.data(), bC, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(m->d_cvert, cvert.data(), bCV, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(m->d_cedge, cedge.data(), bCE, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         nat::dev_free(ctx, blk, m->bytes);
         delete m;

@@ -91,6 +91,8 @@ struct nat_mesh {
     int32_t* d_T = nullptr;
     double* d_normal = nullptr;
     double* d_cdf = nullptr;
+    double* d_cvert = nullptr;     // free term at each vertex [nV]
+    double* d_cedge = nullptr;     // free term on the edge opposite each corner [nT][3]
     size_t bytes = 0;
 };
 
@@ -208,6 +210,8 @@ struct SurfJob {
     const int32_t* q_tri;              // caller's queries
     const double* q_bary;
     const double2* v_n;                // caller's Neumann data [M][ng]
+    const double* cvert;               // mesh free terms at vertices [nV] and edges [nT][3]
+    const double* cedge;
     double area, cx, cy, cz;           // |Gamma| and the mesh centre
     uint64_t seed;
     int64_t on, oq;                    // first sample / query of the instance in the batch arrays
@@ -228,6 +232,7 @@ struct SurfBatch {
     double2* gj;                       // per system [N] at og_n + m N
     double2* gq;                       // per system [Q] at og_q + m Q
     int32_t* flags;                    // [0] query out of range, [1] non-finite Neumann data
+    double* qfac;                      // per instance [Q] at oq: 1 / c_q, or null (c_q = 1/2)
 };
 // Device-side argument checks of every instance (flags are OR-ed, not cleared).
 hipError_t launch_checks_batch(const SurfBatch& b, int64_t max_work, hipStream_t s);
@@ -265,6 +270,7 @@ struct SumArgs {
     const float* kappa32;        // [n_modes] device, k / (2 pi)
     const int32_t* active;       // [n_modes] or null: inactive modes are skipped
     double w, eps;
+    const double* qfac;          // [NT] 1 / c_q (EVAL), or null for 2
     double2* out;                // [mode * ld_out + i]
     int64_t ld_out;
 };
@@ -284,6 +290,7 @@ struct InstDev {
     const float* s32;                  // [3][n] sample positions, relative to the mesh centre
     const float* sn32;                 // [3][n] sample normals
     const float* q32;                  // [3][q] query positions
+    const double* qfac;                // [q] 1 / c_q of the queries, or null for 2
 };
 
 struct SysDev {

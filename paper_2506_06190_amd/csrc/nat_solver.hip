@@ -264,6 +264,9 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     if (!(opts->eps_scale > 0.0) || !is_finite(opts->eps_scale) || !(opts->gmres_tol > 0.0) ||
         opts->gmres_max_iter < 1 || opts->gmres_max_iter > 1000 || (opts->flags & ~NAT_MC_NO_GRAPH))
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: bad solver options");
+    if (opts->jump != NAT_JUMP_HALF && opts->jump != NAT_JUMP_POLYHEDRAL)
+        return fail(NAT_E_INVALID, "Monte-Carlo estimate: jump %d", opts->jump);
+    const bool polyhedral = opts->jump == NAT_JUMP_POLYHEDRAL;
     int64_t S64 = 0;
     for (int32_t i = 0; i < nj; ++i) {
         const McJob& J = jobs[i];
@@ -363,7 +366,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
          sizeof(double) * sum_ch, sizeof(double) * sum_ch, sizeof(double) * sum_ch,
          sizeof(double2) * S * gram_stride, sizeof(float4) * n_part, sizeof(InstDev) * nj,
          sizeof(SysDev) * S, sizeof(GroupDev) * S, sizeof(GroupDev) * S, sizeof(GroupDev) * S,
-         sizeof(int2) * sum_ch, sizeof(double) * S, sizeof(int64_t) * 8, sizeof(SurfJob) * nj});
+         sizeof(int2) * sum_ch, sizeof(double) * S, sizeof(int64_t) * 8, sizeof(SurfJob) * nj,
+         polyhedral ? sizeof(double) * inst_q : 0});
     if (bytes_only) {
         *bytes_only = bytes;
         return NAT_OK;
@@ -420,6 +424,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     double* dk = cv.take<double>(S);
     int64_t* dcnt64 = cv.take<int64_t>(8);  // items: [0] rhs, [1] eval, [2] matvec
     SurfJob* d_surf = cv.take<SurfJob>(nj);
+    double* qfac_all = polyhedral ? cv.take<double>(inst_q) : nullptr;
     T.d_nitems = dcnt + 2;
     T.d_ngroups_mv = dcnt + 3;
     T.d_iter = dcnt + 4;
@@ -436,6 +441,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
             I.s32 = x32_all + 3 * on;
             I.sn32 = n32_all + 3 * on;
             I.q32 = q32_all + 3 * oq;
+            I.qfac = qfac_all && I.q > 0 ? qfac_all + oq : nullptr;
             on += I.n;
             oq += I.q;
         }
@@ -466,6 +472,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
             X.q_tri = J.q_tri;
             X.q_bary = J.q_bary;
             X.v_n = reinterpret_cast<const double2*>(J.v_n);
+            X.cvert = m->d_cvert;
+            X.cedge = m->d_cedge;
             X.area = m->area_total;
             X.cx = m->center[0];
             X.cy = m->center[1];
@@ -505,6 +513,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         sbat.gj = gj;
         sbat.gq = gq;
         sbat.flags = dcnt;
+        sbat.qfac = qfac_all;
         NAT_HIP(hipMemsetAsync(dcnt, 0, 2 * sizeof(int32_t), s));
         NAT_HIP(launch_checks_batch(sbat, max_check, s));
         int32_t* hflags = reinterpret_cast<int32_t*>(static_cast<char*>(pin) + sizeof(SurfJob) * nj);
@@ -608,6 +617,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
             a.ld_gt = I.q;
             a.out = Y0.out_q;
             a.ld_out = I.q;
+            a.qfac = I.qfac;
         } else {
             a.NT = I.n;
             a.t64 = a.s64;

@@ -31,13 +31,16 @@ class NatError(RuntimeError):
 
 
 NAT_MC_NO_GRAPH = 1
+NAT_JUMP_HALF = 0
+NAT_JUMP_POLYHEDRAL = 1
 NAT_TUNE_FORCE = 1
 TUNE_BUCKETS = 10
 
 
 class nat_mc_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("layout", C.c_int32), ("eps_scale", C.c_double),
-                ("gmres_tol", C.c_double), ("gmres_max_iter", C.c_int32), ("flags", C.c_int32)]
+                ("gmres_tol", C.c_double), ("gmres_max_iter", C.c_int32), ("flags", C.c_int32),
+                ("jump", C.c_int32), ("reserved", C.c_int32)]
 
 
 class nat_mc_job(C.Structure):
@@ -101,6 +104,7 @@ _SIGS = {
     "nat_mesh_destroy": ([_P], None),
     "nat_mesh_validate": ([_P, C.c_int32, _P, C.c_int32], C.c_int),
     "nat_mesh_geometry": ([_P, C.c_int32, _P, C.c_int32, _P, _P, _P], C.c_int),
+    "nat_mesh_free_terms": ([_P, C.c_int32, _P, C.c_int32, _P, _P], C.c_int),
     "nat_mesh_info": ([_P, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "nat_mesh_vertex_queries": ([_P, _P, _P], C.c_int),
     "nat_mc_opts_default": ([C.POINTER(nat_mc_opts)], None),
@@ -202,6 +206,17 @@ def nat_mesh_geometry(vertices, tris):
                                    area.ctypes.data_as(_P), normal.ctypes.data_as(_P),
                                    cdf.ctypes.data_as(_P)))
     return area, normal, cdf
+
+
+def nat_mesh_free_terms(vertices, tris):
+    """(c_vert [V], c_edge [T, 3]): the free terms used by NAT_JUMP_POLYHEDRAL."""
+    v = np.ascontiguousarray(vertices, dtype=np.float64)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    cv = np.empty(len(v))
+    ce = np.empty((len(t), 3))
+    _check(lib().nat_mesh_free_terms(v.ctypes.data_as(_P), len(v), t.ctypes.data_as(_P), len(t),
+                                     cv.ctypes.data_as(_P), ce.ctypes.data_as(_P)))
+    return cv, ce
 
 
 # ---------------------------------------------------------------- handles

@@ -42,7 +42,7 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _run_gpu(ctx, wl, prec, tol, layout=0, want_samples=False, max_iter=200):
+def _run_gpu(ctx, wl, prec, tol, layout=0, want_samples=False, max_iter=200, jump=0):
     mesh = nat.Mesh(ctx, wl.vertices, wl.tris)
     g = torch.from_numpy(np.ascontiguousarray(wl.g)).to(DEV)
     qt = torch.from_numpy(np.ascontiguousarray(wl.q_tri)).to(DEV)
@@ -52,6 +52,7 @@ def _run_gpu(ctx, wl, prec, tol, layout=0, want_samples=False, max_iter=200):
     opts.gmres_tol = tol
     opts.layout = layout
     opts.gmres_max_iter = max_iter
+    opts.jump = jump
     ps = None
     if want_samples:
         ps = torch.empty((wl.n_modes, wl.n_samples), dtype=torch.complex128, device=DEV)
@@ -68,6 +69,72 @@ def _small_ellipsoid(n_modes=11, Q=700, N=600, seed=77):
     k = W.wavenumber(W.log_uniform_freqs(n_modes, seed))
     qt, qb = W.random_face_queries(len(f), Q, seed)
     return W.MCWorkload("small_ellipsoid", v, f, g, k, qt, qb, N, seed)
+
+
+def _edge_and_vertex_workload(seed, subdiv=3, n_modes=4, N=700):
+    """Noise-displaced ellipsoid with queries on every vertex, on a spread of
+    edges (one barycentric weight exactly 0) and at random face points."""
+    v, f, u = W.noisy_ellipsoid(seed, subdiv=subdiv)
+    vt, vb = W.vertex_queries(f, len(v))
+    et, eb = [], []
+    for t in range(0, len(f), 7):
+        i = t % 3
+        et.append(t)
+        eb.append([(0.37, 1.0 - 0.37), (0.0, 0.37), (0.37, 0.0)][i])
+    ft, fb = W.random_face_queries(len(f), 200, seed)
+    qt = np.concatenate([vt, np.array(et, np.int32), ft]).astype(np.int32)
+    qb = np.concatenate([vb, np.array(eb), fb])
+    g = W.sh_neumann(u, n_modes, seed)
+    k = W.wavenumber(W.log_uniform_freqs(n_modes, seed))
+    return W.MCWorkload("edge_vertex_ellipsoid", v, f, g, k, qt, qb, N, seed)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_polyhedral_free_term(ctx, prec):
+    """NAT_JUMP_POLYHEDRAL: queries on mesh vertices and edges use the free
+    term of the body's solid angle there; GPU against the oracle (its own
+    all-triangle solid-angle sum) element by element, and the default c = 1/2
+    estimate is unchanged."""
+    wl = _edge_and_vertex_workload(5)
+    _say(f"polyhedral jump {prec}: T={len(wl.tris)} Q={wl.n_queries} N={wl.n_samples}")
+    P = nat.NAT_PREC_FP64 if prec == "fp64" else nat.NAT_PREC_FP32
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    p1, rep, _ = _run_gpu(ctx, wl, P, tol, jump=nat.NAT_JUMP_POLYHEDRAL)
+    p0, _, _ = _run_gpu(ctx, wl, P, tol, jump=nat.NAT_JUMP_HALF)
+    r1 = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri, wl.q_b, wl.n_samples, wl.seed,
+                 tol=1e-12, jump=1)
+    r0 = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri, wl.q_b, wl.n_samples, wl.seed,
+                 tol=1e-12, jump=0)
+    bar = 1e-10 if prec == "fp64" else 1e-3
+    for m in range(wl.n_modes):
+        assert _rel(p1[m], r1["p"][m]) <= bar, m
+        assert _rel(p0[m], r0["p"][m]) <= bar, m
+    # the two forms differ exactly by the free-term ratio at every query
+    c = O.free_terms(wl.vertices, wl.tris, wl.q_tri, wl.q_b, 1)
+    assert np.any(c != 0.5)
+    assert np.allclose(p1, p0 * (0.5 / c)[None, :], rtol=1e-13, atol=0)
+
+
+def test_polyhedral_free_term_batch(ctx):
+    """Two instances of different sizes in one batch with per-query free
+    terms: each equals its single estimate bit for bit."""
+    wls = [_edge_and_vertex_workload(8, subdiv=2, n_modes=3, N=300),
+           _edge_and_vertex_workload(9, subdiv=3, n_modes=2, N=500)]
+    meshes = [nat.Mesh(ctx, wl.vertices, wl.tris) for wl in wls]
+    opts = nat.nat_mc_opts_default()
+    opts.jump = nat.NAT_JUMP_POLYHEDRAL
+    jobs = [nat.McJob(m, torch.from_numpy(wl.g).to(DEV), wl.k, torch.from_numpy(wl.q_tri).to(DEV),
+                      torch.from_numpy(wl.q_b).to(DEV), wl.n_samples, wl.seed)
+            for wl, m in zip(wls, meshes)]
+    nat.nat_mcbem_estimate_batch(ctx, jobs, opts)
+    torch.cuda.synchronize()
+    for wl, mesh, job in zip(wls, meshes, jobs):
+        p1, _ = nat.nat_mcbem_estimate(mesh, job.v_n, wl.k, job.q_tri, job.q_bary, wl.n_samples,
+                                       wl.seed, opts)
+        torch.cuda.synchronize()
+        assert torch.equal(job.p_out, p1)
+    for m in meshes:
+        m.close()
 
 
 def test_samples_bit_exact(ctx):
