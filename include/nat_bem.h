@@ -103,6 +103,12 @@ typedef struct {
     double rel_resid;  /* GMRES estimate of |b - A x| / |b|                         */
     double eps;        /* disk radius used (Monte-Carlo) or 0                       */
     double area;       /* |Gamma|                                                   */
+    /* device time of the stages (HIP events on the call's stream), in ms;
+     * for a batch, the whole batch's stages; a dense solve fills t_solve_ms */
+    double t_sample_ms; /* samples, points and Neumann data (Section 4.1.1)         */
+    double t_rhs_ms;    /* Stage-A right-hand side                                  */
+    double t_solve_ms;  /* Stage-A (or dense) GMRES, solution included              */
+    double t_eval_ms;   /* Stage-B evaluation at the queries                        */
 } nat_solve_report;
 
 /* ---- context ------------------------------------------------------------ */

@@ -1094,6 +1094,9 @@ nat_status nat_bem_solve(nat_bem_op* op, const double* v_n, int32_t n_rhs, int32
     } else {
         NAT_HIP(hipMemcpyAsync(gp, gin, sizeof(double2) * (size_t)M * n, hipMemcpyDeviceToDevice, s));
     }
+    StageEvents sev;
+    NAT_HIP(sev.create());
+    NAT_HIP(hipEventRecord(sev.e[0], s));
     NAT_HIP(launch_zgemv(op->d_B, n, gp, n, M, b, n, nullptr, s, ProfSlot(), zpart));
     std::function<hipError_t(int32_t)> mv = [&](int32_t j) -> hipError_t {
         return launch_zgemv(op->d_A, n, g.V + (size_t)j * n, (int64_t)mm1 * n, M, g.w, n, g.active, s,
@@ -1103,6 +1106,7 @@ nat_status nat_bem_solve(nat_bem_op* op, const double* v_n, int32_t n_rhs, int32
     if (st != NAT_OK)
         return st;
     NAT_HIP(launch_gmres_solution(g, s));
+    NAT_HIP(hipEventRecord(sev.e[1], s));
     prof_collect(ctx);
     void* pin = nullptr;
     st = pinned(ctx, (sizeof(double) + sizeof(int32_t)) * M + 64, &pin);
@@ -1113,6 +1117,8 @@ nat_status nat_bem_solve(nat_bem_op* op, const double* v_n, int32_t n_rhs, int32
     NAT_HIP(hipMemcpyAsync(hres, g.resid, sizeof(double) * M, hipMemcpyDeviceToHost, s));
     NAT_HIP(hipMemcpyAsync(hit, g.iters, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
     NAT_HIP(hipStreamSynchronize(s));
+    float t_solve = 0.0f;
+    NAT_HIP(hipEventElapsedTime(&t_solve, sev.e[0], sev.e[1]));
     bool all_conv = true;
     for (int32_t m = 0; m < M; ++m) {
         const bool conv = hres[m] <= tol;
@@ -1123,6 +1129,10 @@ nat_status nat_bem_solve(nat_bem_op* op, const double* v_n, int32_t n_rhs, int32
             report[m].rel_resid = hres[m];
             report[m].eps = 0.0;
             report[m].area = op->mesh->area_total;
+            report[m].t_sample_ms = 0.0;
+            report[m].t_rhs_ms = 0.0;
+            report[m].t_solve_ms = t_solve;
+            report[m].t_eval_ms = 0.0;
         }
     }
     if (!all_conv)

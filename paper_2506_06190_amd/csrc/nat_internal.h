@@ -158,6 +158,27 @@ inline size_t carve_size(std::initializer_list<size_t> bytes) {
     return s + 256;
 }
 
+// Events between the stages of one call (timing enabled), destroyed with it.
+struct StageEvents {
+    hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipError_t create() {
+        for (hipEvent_t& x : e) {
+            hipError_t r = hipEventCreate(&x);
+            if (r != hipSuccess)
+                return r;
+        }
+        return hipSuccess;
+    }
+    ~StageEvents() {
+        for (hipEvent_t x : e)
+            if (x)
+                (void)hipEventDestroy(x);
+    }
+    StageEvents() = default;
+    StageEvents(const StageEvents&) = delete;
+    StageEvents& operator=(const StageEvents&) = delete;
+};
+
 // ---- per-kernel timing ------------------------------------------------------
 enum ProfKind {
     PK_SUM32_RHS = 0, PK_SUM32_MATVEC = 1, PK_SUM32_EVAL = 2,

@@ -585,8 +585,14 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         NAT_HIP(hipStreamSynchronize(s));
     }
 
+    // stage timing: events on the stream between the stages
+    StageEvents sev;
+    NAT_HIP(sev.create());
+    NAT_HIP(hipEventRecord(sev.e[0], s));
+
     // ---- samples, points, Neumann data (Section 4.1.1) -----------------------
     NAT_HIP(launch_surface_batch(sbat, max_n, max_q, s));
+    NAT_HIP(hipEventRecord(sev.e[1], s));
 
     Sum32Batch sb{};
     sb.inst = T.d_inst;
@@ -654,6 +660,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         }
     }
 
+    NAT_HIP(hipEventRecord(sev.e[2], s));
+
     // ---- GMRES on (I/2 - K) p = b ---------------------------------------------
     std::function<hipError_t(int32_t)> eager = [&](int32_t j) -> hipError_t {
         for (int32_t i = 0; i < nj; ++i) {
@@ -677,6 +685,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     if (st != NAT_OK)
         return st;
     NAT_HIP(launch_gmres_solution(g, s));
+    NAT_HIP(hipEventRecord(sev.e[3], s));
 
     // ---- surface evaluation (eq. BIE at the queries, Section 4.2) --------------
     if (max_q > 0) {
@@ -705,6 +714,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
             }
         }
     }
+    NAT_HIP(hipEventRecord(sev.e[4], s));
     for (int32_t i = 0; i < nj; ++i) {
         if (!jobs[i].p_samples)
             continue;
@@ -724,6 +734,9 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     NAT_HIP(hipMemcpyAsync(hres, g.resid, sizeof(double) * S, hipMemcpyDeviceToHost, s));
     NAT_HIP(hipMemcpyAsync(hit, g.iters, sizeof(int32_t) * S, hipMemcpyDeviceToHost, s));
     NAT_HIP(hipStreamSynchronize(s));
+    float t_ms[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int c = 0; c < 4; ++c)
+        NAT_HIP(hipEventElapsedTime(&t_ms[c], sev.e[c], sev.e[c + 1]));
     bool all_conv = true;
     for (int32_t q = 0; q < S; ++q) {
         const bool conv = hres[q] <= opts->gmres_tol;
@@ -734,6 +747,10 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
             report[q].rel_resid = hres[q];
             report[q].eps = T.sys[q].eps;
             report[q].area = jobs[T.sys[q].inst].mesh->area_total;
+            report[q].t_sample_ms = t_ms[0];
+            report[q].t_rhs_ms = t_ms[1];
+            report[q].t_solve_ms = t_ms[2];
+            report[q].t_eval_ms = t_ms[3];
         }
     }
     if (!all_conv)

@@ -57,7 +57,8 @@ class nat_kernel_stat(C.Structure):
 
 class nat_solve_report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("rel_resid", C.c_double),
-                ("eps", C.c_double), ("area", C.c_double)]
+                ("eps", C.c_double), ("area", C.c_double), ("t_sample_ms", C.c_double),
+                ("t_rhs_ms", C.c_double), ("t_solve_ms", C.c_double), ("t_eval_ms", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

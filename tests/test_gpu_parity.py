@@ -190,6 +190,10 @@ def test_fp32_ragged_multimode(ctx):
     _say("  fp32 rel L2 per mode: " + " ".join(f"{e:.2e}" for e in errs))
     assert max(errs) <= 1e-3
     assert all(rr["converged"] for rr in rep)
+    # stage times of the call (device events), the same for every mode
+    for key in ("t_sample_ms", "t_rhs_ms", "t_solve_ms", "t_eval_ms"):
+        assert rep[0][key] > 0.0 and all(rr[key] == rep[0][key] for rr in rep), key
+    assert rep[0]["t_solve_ms"] > rep[0]["t_rhs_ms"]
 
 
 def test_fp32_full_precision_workload(ctx):
@@ -378,5 +382,6 @@ def test_dense_multi_rhs_matrix_cores(ctx, mesh_kind, n_rhs):
         a, b = p_all[r].cpu().numpy(), p1[0].cpu().numpy()
         assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b), r
         assert abs(rep_all[r]["iters"] - rep1[0]["iters"]) <= 1
+        assert rep_all[r]["t_solve_ms"] > 0.0 and rep_all[r]["t_rhs_ms"] == 0.0
     op.close()
     mesh.close()
