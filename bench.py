@@ -521,9 +521,13 @@ def main():
     else:
         table = nat.nat_tune_get(ctx)
         source = "defaults"
+    form = nat.nat_tune_get_form(ctx, with_rates=True)
     tune = {"cache": os.path.relpath(args.tune_cache, ROOT), "source": source,
             "seconds": round(time.perf_counter() - t0, 2), "items_a": table["items_a"],
-            "items_b": table["items_b"]}
+            "items_b": table["items_b"], "matvec_assembled": form["assembled"]}
+    if any(form["rate_matrix_free"]):
+        tune["matvec_rate_matrix_free"] = [float(f"{x:.3g}") for x in form["rate_matrix_free"]]
+        tune["matvec_rate_assembled"] = [float(f"{x:.3g}") for x in form["rate_assembled"]]
     log(f"kernel-sum tiling from {tune['source']} in {tune['seconds']} s")
     out = {"metric": METRIC, "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

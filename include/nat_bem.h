@@ -87,7 +87,7 @@ typedef struct {
     double eps_scale;       /* eps = eps_scale * sqrt(|Gamma| / (pi N)); > 0         */
     double gmres_tol;       /* relative residual |r| / |b| to stop at; > 0           */
     int32_t gmres_max_iter; /* 1 .. 1000                                             */
-    int32_t flags;          /* 0 or NAT_MC_NO_GRAPH                                  */
+    int32_t flags;          /* NAT_MC_* bits                                         */
     int32_t jump;           /* nat_jump                                              */
     int32_t reserved;       /* 0                                                     */
 } nat_mc_opts;
@@ -95,6 +95,15 @@ typedef struct {
 /* nat_mc_opts.flags: launch every GMRES kernel directly instead of replaying
  * captured runs of iterations (results are identical). */
 #define NAT_MC_NO_GRAPH 1
+/* nat_mc_opts.flags: the GMRES matvec of the FP32 form from an assembled
+ * operator for every instance (the pair terms e^{ikr}(ikr - 1)(d.n_j)/r^3 of
+ * eq. bem_linear_system stored once per mode as N^2 FP32 complex values,
+ * source-major, 0 inside the disk; each iteration multiplies them by
+ * w/(4 pi) p_j with FP64 sums), or matrix-free for every instance (the kernel sum recomputed each
+ * iteration).  Without either bit the form follows the context's tuning
+ * table by N (nat_autotune).  The plain FP64 form is always matrix-free. */
+#define NAT_MC_ASSEMBLED 2
+#define NAT_MC_MATRIX_FREE 4
 
 /* Per right-hand side report of a solve. */
 typedef struct {
@@ -288,6 +297,17 @@ nat_status nat_autotune(nat_ctx* ctx, const char* cache_path, int32_t flags, voi
 nat_status nat_tune_get(const nat_ctx* ctx, int32_t* items_a, int32_t* items_b, int32_t* tuned);
 /* Set the table (host int32[10] each, every entry 1 .. 2^20). */
 nat_status nat_tune_set(nat_ctx* ctx, const int32_t* items_a, const int32_t* items_b);
+/* The GMRES matvec form by the same buckets of N (host int32[10]: 1 =
+ * assembled operator, 0 = matrix-free).  nat_autotune times both on
+ * synthetic systems of each bucket, the assembled form charged its assembly
+ * spread over 30 iterations, and keeps the faster; buckets whose operator
+ * would exceed 2 GiB per mode stay matrix-free.  Defaults: all 0.
+ * rate_free, rate_asm (host double[10] each, may be NULL): the matvec rates
+ * the last sweep measured in (pair, mode) terms per second, 0 where not
+ * timed or when the table came from a cache or nat_tune_set_form. */
+nat_status nat_tune_get_form(const nat_ctx* ctx, int32_t* assembled, double* rate_free,
+                             double* rate_asm);
+nat_status nat_tune_set_form(nat_ctx* ctx, const int32_t* assembled);
 
 /* ---- per-kernel timing ---------------------------------------------------- */
 

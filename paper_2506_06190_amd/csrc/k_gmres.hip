@@ -215,16 +215,16 @@ __global__ void __launch_bounds__(kRows) k_orth_dots(GmresBatch g)
                 // matvec epilogue: w = v_j / 2 - (sum of the FP32 split partials)
                 float hr = 0.0f, hi = 0.0f, lr = 0.0f, li = 0.0f;
                 const float4* pp = g.partial + S.off_pa + t;
-                for (int32_t sp0 = 0; sp0 < S.nsplit_a; sp0 += 8) {
+                for (int32_t sp0 = 0; sp0 < S.nsplit_mv; sp0 += 8) {
                     // issue the group's loads together, fold in split order
                     float4 v[8];
 #pragma unroll
                     for (int c = 0; c < 8; ++c)
-                        v[c] = sp0 + c < S.nsplit_a ? pp[(int64_t)(sp0 + c) * n]
-                                                    : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                        v[c] = sp0 + c < S.nsplit_mv ? pp[(int64_t)(sp0 + c) * n]
+                                                     : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
                     for (int c = 0; c < 8; ++c) {
-                        if (sp0 + c < S.nsplit_a) {
+                        if (sp0 + c < S.nsplit_mv) {
                             fold2(hr, lr, v[c].x);
                             fold2(hi, li, v[c].y);
                             lr += v[c].z;

@@ -291,6 +291,102 @@ k_reduce32(const Sum32Batch p, const double2* __restrict__ g_tgt, double2* __res
     }
 }
 
+// Assembled form of the Stage-A operator, FP32 complex [n][n] at off_k,
+// stored source-major (entry (i, j) at j n + i) so that consecutive targets
+// are consecutive in memory: K_ij = q e^{i th} (ikr - 1) with
+// q = (d.n_j)/r^3, d = y_j - y_i, the matvec's pair term formed by the same
+// operations without the source data; 0 inside the disk (the diagonal
+// included).  One workgroup per source column, a thread per target.
+__global__ void __launch_bounds__(256)
+k_assemble32(const InstDev* __restrict__ inst, const SysDev* __restrict__ sys,
+             const int32_t* __restrict__ list, float2* __restrict__ kmat)
+{
+    const SysDev& S = sys[list[blockIdx.y]];
+    const int32_t n = S.n;
+    const InstDev& I = inst[S.inst];
+    const float* sp = I.s32;
+    const float* sn = I.sn32;
+    const float eps2 = I.eps2, kap = S.kappa32, kk = S.k32;
+    for (int32_t j = blockIdx.x; j < n; j += gridDim.x) {
+        const float sx = sp[j], sy = sp[n + j], sz = sp[2 * n + j];
+        const float nx = sn[j], ny = sn[n + j], nz = sn[2 * n + j];
+        float2* col = kmat + S.off_k + (size_t)j * n;
+        for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const float dx = sx - sp[i];
+            const float dy = sy - sp[n + i];
+            const float dz = sz - sp[2 * n + i];
+            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            float2 v = make_float2(0.0f, 0.0f);
+            if (r2 >= eps2) {
+                const float rinv = __builtin_amdgcn_rsqf(r2);
+                const float r = r2 * rinv;
+                const float dn = fmaf(dz, nz, fmaf(dy, ny, dx * nx));
+                const float q = dn * (rinv * rinv) * rinv;
+                const float ph = __builtin_amdgcn_fractf(r * kap);
+                const float sv = __builtin_amdgcn_sinf(ph);
+                const float cv = __builtin_amdgcn_cosf(ph);
+                const float kr = r * kk;
+                v = make_float2(-q * fmaf(kr, sv, cv), q * fmaf(kr, cv, -sv));
+            }
+            col[i] = v;
+        }
+    }
+}
+
+// GMRES matvec from the assembled operators: a thread per target row of a
+// (system, 256-row chunk) item walks the source columns, so every load of
+// the operator is a coalesced run along a column and the source value is
+// the same for the whole wave; products and sums in FP64, written as the
+// single (hi, lo) split partial the Arnoldi step folds.
+__global__ void __launch_bounds__(256)
+k_kmatvec32(const KmvBatch p)
+{
+    const int32_t n_items = *p.n_items;
+    for (int32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 item = p.items[it];
+        const int32_t s = item.x;
+        if (p.active && !p.active[s])
+            continue;
+        const SysDev& S = p.sys[s];
+        if (S.off_k < 0)
+            continue;
+        const int32_t n = S.n;
+        const int32_t i = item.y * 256 + static_cast<int32_t>(threadIdx.x);
+        const bool ok = i < n;
+        const float2* col = p.kmat + S.off_k + (ok ? i : 0);
+        const float2* b = p.b32 + S.off_n;
+        double ar = 0.0, ai = 0.0;
+        int32_t j = 0;
+        for (; j + 8 <= n; j += 8) {
+            float2 kv[8], bv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                kv[u] = col[(size_t)(j + u) * n];
+                bv[u] = b[j + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                ar = fma((double)kv[u].x, (double)bv[u].x, ar);
+                ar = fma(-(double)kv[u].y, (double)bv[u].y, ar);
+                ai = fma((double)kv[u].x, (double)bv[u].y, ai);
+                ai = fma((double)kv[u].y, (double)bv[u].x, ai);
+            }
+        }
+        for (; j < n; ++j) {
+            const float2 kv = col[(size_t)j * n], bv = b[j];
+            ar = fma((double)kv.x, (double)bv.x, ar);
+            ar = fma(-(double)kv.y, (double)bv.y, ar);
+            ai = fma((double)kv.x, (double)bv.y, ai);
+            ai = fma((double)kv.y, (double)bv.x, ai);
+        }
+        if (ok) {
+            const float hr = static_cast<float>(ar), hi = static_cast<float>(ai);
+            p.partial[S.off_pa + i] = make_float4(hr, hi, static_cast<float>(ar - (double)hr),
+                                                  static_cast<float>(ai - (double)hi));
+        }
+    }
+}
+
 // dst[off_n + j] = float2(sign * w/(4 pi) * src[off_n + j]) for every system.
 __global__ void __launch_bounds__(256)
 k_weight32(const SysDev* __restrict__ sys, const double2* __restrict__ src, double sign,
@@ -342,6 +438,25 @@ hipError_t launch_sum32_batch(int32_t op, const Sum32Batch& p, int32_t grid, hip
         launch_k(k_sum32<OP_EVAL>, dim3(grid), dim3(kThreads), 0, s, ev.start, ev.stop, p);
         break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_kmatvec32(const KmvBatch& p, int32_t grid, hipStream_t s, const ProfSlot& ev)
+{
+    if (grid <= 0)
+        return hipSuccess;
+    launch_k(k_kmatvec32, dim3(grid), dim3(256), 0, s, ev.start, ev.stop, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble32(const InstDev* inst, const SysDev* sys, const int32_t* list,
+                             int32_t n_list, int32_t max_n, float2* kmat, hipStream_t s)
+{
+    if (n_list <= 0 || max_n <= 0)
+        return hipSuccess;
+    const unsigned rows = static_cast<unsigned>(max_n < 2048 ? max_n : 2048);
+    hipLaunchKernelGGL(k_assemble32, dim3(rows, static_cast<unsigned>(n_list)), dim3(256), 0, s,
+                       inst, sys, list, kmat);
     return hipGetLastError();
 }
 

@@ -468,15 +468,15 @@ nat_status nat_profile_enable(nat_ctx* ctx, int32_t enable)
 
 int32_t nat_profile_read(nat_ctx* ctx, nat_kernel_stat* out, int32_t max_out)
 {
-    static const char* names[8] = {"sum32_rhs", "sum32_matvec", "sum32_eval", "sum64",
-                                   "gmres_orth", "bem_assemble", "zgemv", "other"};
+    static const char* names[9] = {"sum32_rhs", "sum32_matvec", "sum32_eval", "sum64",
+                                   "gmres_orth", "bem_assemble", "zgemv", "other", "kmatvec32"};
     if (!ctx || (max_out > 0 && !out))
         return 0;
     if (set_device(ctx) != NAT_OK)
         return 0;
     nat::prof_collect(ctx);
     int32_t n = 0;
-    for (int i = 0; i < 8 && n < max_out; ++i) {
+    for (int i = 0; i < 9 && n < max_out; ++i) {
         const NatProfStat& st = ctx->prof_stat[i];
         if (st.launches == 0)
             continue;
@@ -1102,7 +1102,7 @@ nat_status nat_bem_solve(nat_bem_op* op, const double* v_n, int32_t n_rhs, int32
         return launch_zgemv(op->d_A, n, g.V + (size_t)j * n, (int64_t)mm1 * n, M, g.w, n, g.active, s,
                             prof_slot(ctx, PK_ZGEMV, 8.0 * n * (double)n * M), zpart);
     };
-    st = gmres_drive(ctx, g, T, b, nullptr, mv, false, s);
+    st = gmres_drive(ctx, g, T, b, nullptr, nullptr, mv, false, s);
     if (st != NAT_OK)
         return st;
     NAT_HIP(launch_gmres_solution(g, s));

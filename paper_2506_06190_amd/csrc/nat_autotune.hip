@@ -6,6 +6,9 @@
 // group alone (where more splits fill the device) and many groups at once
 // (where extra splits only add partial-sum traffic), and keeps the
 // candidate with the smallest summed slowdown against each regime's best.
+// The same sweep picks, per bucket of N, the GMRES matvec form: the
+// matrix-free kernel sum or the product with an assembled operator (its
+// assembly charged over kTuneAmortize iterations).
 // Tables are cached as JSON per device architecture.
 #include <algorithm>
 #include <cmath>
@@ -30,8 +33,11 @@ int32_t tune_bucket(int32_t n)
 
 void tune_defaults(TuneTable* t)
 {
-    for (int b = 0; b < kTuneBuckets; ++b)
+    for (int b = 0; b < kTuneBuckets; ++b) {
         t->items_a[b] = t->items_b[b] = 64;
+        t->assembled[b] = 0;
+        t->rate_free[b] = t->rate_asm[b] = 0.0;
+    }
     t->tuned = 0;
 }
 
@@ -43,6 +49,8 @@ constexpr int32_t kModes = 8;                 // one full mode group
 constexpr double kBusyPairs = 2.0e10;         // pair-modes of the busy regime
 constexpr size_t kPartialCap = size_t(256) << 20;
 constexpr int32_t kEvalSources = 1024;        // sources of the query-stage sweep
+constexpr double kTuneAmortize = 30.0;        // GMRES iterations an assembly is spread over
+constexpr size_t kAsmCap = size_t(2) << 30;   // bytes of assembled operators per timing
 
 // Representative size of bucket b: the geometric middle of [2^(b+6), 2^(b+7)).
 int32_t bucket_size(int32_t b) { return (int32_t)std::lround(std::ldexp(1.41421356, b + 6)); }
@@ -214,6 +222,165 @@ double time_config(Sweep& w, int32_t op, int32_t NT, int32_t NS, int32_t groups,
     return best;
 }
 
+// The assembled form on S systems of N unknowns: per launch of the matvec
+// from the operators plus the fold of its single partial (minimum over three
+// after a warm-up), and the assembly in *t_build; milliseconds, negative on
+// failure.
+double time_assembled(Sweep& w, int32_t N, int32_t S, double* t_build)
+{
+    const int32_t nch = (N + 255) / 256;
+    std::vector<float> src(6 * (size_t)N);
+    sphere_points(N, src.data(), src.data() + 3 * (size_t)N);
+    std::vector<float2> data((size_t)S * N);
+    for (size_t j = 0; j < data.size(); ++j) {
+        const uint32_t h = static_cast<uint32_t>(j) * 2654435761u;
+        data[j] = make_float2(static_cast<float>(h & 0xffffu) * 1e-8f - 3e-4f,
+                              static_cast<float>(h >> 16) * 1e-8f - 3e-4f);
+    }
+    const size_t vec_n = (size_t)S * N;
+    const size_t bytes = carve_size<>(
+        {sizeof(float) * src.size(), sizeof(float2) * vec_n, sizeof(float4) * vec_n, sizeof(InstDev),
+         sizeof(SysDev) * S, sizeof(int2) * (size_t)S * nch, sizeof(int32_t) * 2, sizeof(int32_t) * S,
+         sizeof(float2) * vec_n * N, sizeof(double2) * vec_n, sizeof(double2) * vec_n});
+    void* ws = nullptr;
+    if (workspace(w.ctx, bytes, &ws) != NAT_OK)
+        return -1.0;
+    Carver cv(ws);
+    float* d_src = cv.take<float>(src.size());
+    float2* d_data = cv.take<float2>(vec_n);
+    float4* d_partial = cv.take<float4>(vec_n);
+    InstDev* d_inst = cv.take<InstDev>(1);
+    SysDev* d_sys = cv.take<SysDev>(S);
+    int2* d_items = cv.take<int2>((size_t)S * nch);
+    int32_t* d_count = cv.take<int32_t>(2);
+    int32_t* d_list = cv.take<int32_t>(S);
+    float2* d_k = cv.take<float2>(vec_n * N);
+    double2* d_g = cv.take<double2>(vec_n);
+    double2* d_out = cv.take<double2>(vec_n);
+
+    InstDev I{};
+    I.n = N;
+    I.n_modes = S;
+    I.nsplit_a = I.nsplit_b = 1;
+    I.per_split_a = I.per_split_b = N;
+    I.w = 4.0 * M_PI * 0.01 / N;
+    I.eps = std::sqrt(0.04 / N);
+    I.eps2 = static_cast<float>(I.eps * I.eps);
+    I.s32 = d_src;
+    I.sn32 = d_src + 3 * (size_t)N;
+    std::vector<SysDev> sys(S);
+    std::vector<int2> items((size_t)S * nch);
+    std::vector<int32_t> list(S);
+    for (int32_t q = 0; q < S; ++q) {
+        SysDev& Y = sys[q];
+        Y = SysDev{};
+        Y.n = N;
+        Y.nch = nch;
+        Y.nsplit_a = Y.nsplit_mv = 1;
+        Y.off_n = Y.off_pa = (int64_t)q * N;
+        Y.off_k = (int64_t)q * N * N;
+        Y.k = 20.0 + 15.0 * (q % kModes);
+        Y.k32 = static_cast<float>(Y.k);
+        Y.kappa32 = static_cast<float>(Y.k / (2.0 * M_PI));
+        list[q] = q;
+        for (int32_t c = 0; c < nch; ++c)
+            items[(size_t)q * nch + c] = make_int2(q, c);
+    }
+    const int32_t n_items = S * nch;
+    hipError_t e = hipMemcpyAsync(d_src, src.data(), sizeof(float) * src.size(), hipMemcpyHostToDevice, w.s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_data, data.data(), sizeof(float2) * vec_n, hipMemcpyHostToDevice, w.s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_inst, &I, sizeof(InstDev), hipMemcpyHostToDevice, w.s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_sys, sys.data(), sizeof(SysDev) * S, hipMemcpyHostToDevice, w.s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, w.s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_count, &n_items, sizeof(int32_t), hipMemcpyHostToDevice, w.s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_list, list.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, w.s);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(d_g, 0, sizeof(double2) * vec_n, w.s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(w.s);  // the host vectors go out of scope below
+    if (e != hipSuccess)
+        return -1.0;
+    float ms = 0.0f;
+    e = hipEventRecord(w.e0, w.s);
+    if (e == hipSuccess)
+        e = launch_assemble32(d_inst, d_sys, d_list, S, N, d_k, w.s);
+    if (e == hipSuccess)
+        e = hipEventRecord(w.e1, w.s);
+    if (e == hipSuccess)
+        e = hipEventSynchronize(w.e1);
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&ms, w.e0, w.e1);
+    if (e != hipSuccess)
+        return -1.0;
+    *t_build = ms;
+    KmvBatch kb{};
+    kb.sys = d_sys;
+    kb.items = d_items;
+    kb.n_items = d_count;
+    kb.kmat = d_k;
+    kb.b32 = d_data;
+    kb.partial = d_partial;
+    Sum32Batch p{};
+    p.inst = d_inst;
+    p.sys = d_sys;
+    p.partial = d_partial;
+    const int32_t grid = std::min(n_items, kGridKmv);
+    double best = 1e30;
+    for (int rep = 0; rep < 4; ++rep) {
+        e = hipEventRecord(w.e0, w.s);
+        if (e == hipSuccess)
+            e = launch_kmatvec32(kb, grid, w.s);
+        if (e == hipSuccess)
+            e = launch_reduce32_batch(OP_RHS, p, S, N, d_g, d_out, w.s);
+        if (e == hipSuccess)
+            e = hipEventRecord(w.e1, w.s);
+        if (e == hipSuccess)
+            e = hipEventSynchronize(w.e1);
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, w.e0, w.e1);
+        if (e != hipSuccess)
+            return -1.0;
+        if (rep > 0)
+            best = std::min(best, (double)ms);
+    }
+    return best;
+}
+
+// Matvec form of one bucket of N: the matrix-free kernel sum (tiling
+// `want`) against the assembled operator, per system and iteration, on as
+// many systems as the busy regime (the operators capped at kAsmCap bytes).
+nat_status tune_form(Sweep& w, int32_t N, int32_t want, TuneTable* t, int b)
+{
+    t->assembled[b] = 0;
+    const double kbytes = 8.0 * N * (double)N;
+    const int32_t groups_busy = (int32_t)std::max(1.0, std::min(256.0, kBusyPairs / (kModes * (double)N * N)));
+    int32_t groups = groups_busy;
+    while (groups > 1 && groups * kModes * kbytes > (double)kAsmCap)
+        groups /= 2;
+    const double t_free = time_config(w, OP_MATVEC, N, N, groups, want);
+    if (t_free < 0.0)
+        return fail(NAT_E_HIP, "autotune: timing launch failed");
+    const double per_free = t_free / (groups * kModes);
+    t->rate_free[b] = (double)N * N / (per_free * 1e-3);
+    const int32_t S = (int32_t)std::min<double>(groups * kModes, std::floor((double)kAsmCap / kbytes));
+    if (S < 1)
+        return NAT_OK;  // one operator would not fit: matrix-free
+    double t_build = 0.0;
+    const double t_asm = time_assembled(w, N, S, &t_build);
+    if (t_asm < 0.0)
+        return fail(NAT_E_HIP, "autotune: timing launch failed");
+    const double per_asm = (t_asm + t_build / kTuneAmortize) / S;
+    t->rate_asm[b] = (double)N * N / (per_asm * 1e-3);
+    t->assembled[b] = per_asm < per_free ? 1 : 0;
+    return NAT_OK;
+}
+
 // Best items-per-group candidate for one bucket of one stage.
 nat_status tune_bucket_op(Sweep& w, int32_t op, int32_t NT, int32_t NS, int32_t* out)
 {
@@ -302,8 +469,15 @@ bool load_cache(const char* path, const std::string& arch, TuneTable* t)
     if (text.find("\"device\": \"" + arch + "\"") == std::string::npos)
         return false;
     TuneTable tmp;
-    if (!parse_array(text, "items_a", tmp.items_a) || !parse_array(text, "items_b", tmp.items_b))
+    tune_defaults(&tmp);
+    if (!parse_array(text, "items_a", tmp.items_a) || !parse_array(text, "items_b", tmp.items_b) ||
+        !parse_array(text, "assembled_plus_one", tmp.assembled))
         return false;
+    for (int b = 0; b < kTuneBuckets; ++b) {
+        if (tmp.assembled[b] != 1 && tmp.assembled[b] != 2)
+            return false;
+        tmp.assembled[b] -= 1;
+    }
     tmp.tuned = 1;
     *t = tmp;
     return true;
@@ -315,12 +489,23 @@ bool save_cache(const char* path, const std::string& arch, const TuneTable& t)
     if (!f)
         return false;
     std::fprintf(f, "{\n  \"device\": \"%s\",\n  \"bucket_log2_min\": 6,\n", arch.c_str());
-    const int32_t* arrs[2] = {t.items_a, t.items_b};
-    const char* names[2] = {"items_a", "items_b"};
-    for (int a = 0; a < 2; ++a) {
+    int32_t asm1[kTuneBuckets];
+    for (int b = 0; b < kTuneBuckets; ++b)
+        asm1[b] = t.assembled[b] + 1;  // 1: matrix-free, 2: assembled operator
+    const int32_t* arrs[3] = {t.items_a, t.items_b, asm1};
+    const char* names[3] = {"items_a", "items_b", "assembled_plus_one"};
+    for (int a = 0; a < 3; ++a) {
         std::fprintf(f, "  \"%s\": [", names[a]);
         for (int b = 0; b < kTuneBuckets; ++b)
             std::fprintf(f, "%s%d", b ? ", " : "", arrs[a][b]);
+        std::fprintf(f, "],\n");
+    }
+    const double* rates[2] = {t.rate_free, t.rate_asm};
+    const char* rnames[2] = {"matvec_pair_modes_per_s_matrix_free", "matvec_pair_modes_per_s_assembled"};
+    for (int a = 0; a < 2; ++a) {
+        std::fprintf(f, "  \"%s\": [", rnames[a]);
+        for (int b = 0; b < kTuneBuckets; ++b)
+            std::fprintf(f, "%s%.4g", b ? ", " : "", rates[a][b]);
         std::fprintf(f, "]%s\n", a == 0 ? "," : "");
     }
     std::fprintf(f, "}\n");
@@ -357,6 +542,8 @@ nat_status nat_autotune(nat_ctx* ctx, const char* cache_path, int32_t flags, voi
         st = tune_bucket_op(w, OP_MATVEC, n, n, &t.items_a[b]);
         if (st == NAT_OK)
             st = tune_bucket_op(w, OP_EVAL, n, kEvalSources, &t.items_b[b]);
+        if (st == NAT_OK)
+            st = tune_form(w, n, t.items_a[b], &t, b);
     }
     (void)hipEventDestroy(w.e0);
     (void)hipEventDestroy(w.e1);
@@ -378,6 +565,34 @@ nat_status nat_tune_get(const nat_ctx* ctx, int32_t* items_a, int32_t* items_b, 
     std::memcpy(items_b, ctx->tune.items_b, sizeof(ctx->tune.items_b));
     if (tuned)
         *tuned = ctx->tune.tuned;
+    return NAT_OK;
+}
+
+nat_status nat_tune_get_form(const nat_ctx* ctx, int32_t* assembled, double* rate_free,
+                             double* rate_asm)
+{
+    using namespace nat;
+    if (!ctx || !assembled)
+        return fail(NAT_E_INVALID, "nat_tune_get_form: NULL argument");
+    std::memcpy(assembled, ctx->tune.assembled, sizeof(ctx->tune.assembled));
+    if (rate_free)
+        std::memcpy(rate_free, ctx->tune.rate_free, sizeof(ctx->tune.rate_free));
+    if (rate_asm)
+        std::memcpy(rate_asm, ctx->tune.rate_asm, sizeof(ctx->tune.rate_asm));
+    return NAT_OK;
+}
+
+nat_status nat_tune_set_form(nat_ctx* ctx, const int32_t* assembled)
+{
+    using namespace nat;
+    if (!ctx || !assembled)
+        return fail(NAT_E_INVALID, "nat_tune_set_form: NULL argument");
+    for (int b = 0; b < kTuneBuckets; ++b)
+        if (assembled[b] != 0 && assembled[b] != 1)
+            return fail(NAT_E_INVALID, "nat_tune_set_form: bucket %d: %d", b, assembled[b]);
+    std::memcpy(ctx->tune.assembled, assembled, sizeof(ctx->tune.assembled));
+    for (int b = 0; b < kTuneBuckets; ++b)
+        ctx->tune.rate_free[b] = ctx->tune.rate_asm[b] = 0.0;
     return NAT_OK;
 }
 

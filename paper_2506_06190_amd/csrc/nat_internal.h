@@ -54,6 +54,10 @@ constexpr int kTuneBuckets = 10;
 struct TuneTable {
     int32_t items_a[kTuneBuckets];  // sums over the samples, by the sample count N
     int32_t items_b[kTuneBuckets];  // sums at the queries, by the query count Q
+    int32_t assembled[kTuneBuckets];  // 1: GMRES matvec from the assembled operator, by N
+    // measured matvec rates of the sweep (pair-modes/s; 0 if not timed)
+    double rate_free[kTuneBuckets];
+    double rate_asm[kTuneBuckets];
     int32_t tuned = 0;              // 0: defaults, 1: swept or loaded
 };
 int32_t tune_bucket(int32_t n);
@@ -68,7 +72,7 @@ struct nat_ctx {
     bool prof = false;
     std::vector<NatProfEvent> prof_pending;
     std::vector<hipEvent_t> prof_pool;
-    NatProfStat prof_stat[8];
+    NatProfStat prof_stat[9];
     size_t budget = 0;   // 0: unlimited
     size_t in_use = 0;   // bytes charged
     NatScratch scratch;
@@ -182,7 +186,8 @@ struct StageEvents {
 // ---- per-kernel timing ------------------------------------------------------
 enum ProfKind {
     PK_SUM32_RHS = 0, PK_SUM32_MATVEC = 1, PK_SUM32_EVAL = 2,
-    PK_SUM64 = 3, PK_GMRES_ORTH = 4, PK_BEM_ASSEMBLE = 5, PK_ZGEMV = 6, PK_OTHER = 7
+    PK_SUM64 = 3, PK_GMRES_ORTH = 4, PK_BEM_ASSEMBLE = 5, PK_ZGEMV = 6, PK_OTHER = 7,
+    PK_KMATVEC = 8
 };
 // Start/stop events of one timed launch (null when profiling is off).  The
 // events ride on the dispatch packets of the first and last kernel of the
@@ -317,6 +322,8 @@ struct InstDev {
 struct SysDev {
     int32_t inst, n, q, nch;           // instance, unknowns, queries, Arnoldi row chunks
     int32_t nsplit_a, nsplit_b;
+    int32_t nsplit_mv, pad_mv;         // split partials of the GMRES matvec (1: assembled)
+    int64_t off_k;                     // assembled operator [n][n] float2, or -1 (matrix-free)
     int64_t off_n;                     // [n]-long per-system arrays
     int64_t off_q;                     // [q]-long per-system arrays
     int64_t off_v;                     // Krylov basis: (mmax+1) n
@@ -349,6 +356,26 @@ struct Sum32Batch {
     float4* partial;                   // split partials (hi.re, hi.im, lo.re, lo.im)
 };
 
+// The GMRES matvec of the systems with an assembled operator K (off_k >= 0):
+// for the listed (system, 256-row chunk) items of running systems,
+// partial[off_pa + i] = (hi, lo) of sum_j K_ij b_j accumulated in FP64.
+struct KmvBatch {
+    const SysDev* sys;
+    const int2* items;                 // the Arnoldi work list
+    const int32_t* n_items;            // device count
+    const int32_t* active;             // per system, or null
+    const float2* kmat;                // operators at off_k, source-major
+    const float2* b32;                 // weighted sources w/(4 pi) p at off_n
+    float4* partial;
+};
+hipError_t launch_kmatvec32(const KmvBatch& p, int32_t grid, hipStream_t s,
+                            const ProfSlot& ev = ProfSlot());
+// Assemble K_ij = q e^{i th}(ikr - 1) (the matvec's pair term without the
+// source data; 0 for r < eps), entry (i, j) at off_k + j n + i, for the
+// systems listed in `list` (device).
+hipError_t launch_assemble32(const InstDev* inst, const SysDev* sys, const int32_t* list,
+                             int32_t n_list, int32_t max_n, float2* kmat, hipStream_t s);
+
 // source splits of a sum with n_targets targets over n_sources sources: a
 // function of the instance's own sizes and the wanted items per mode group
 void split_rule(int32_t n_targets, int32_t n_sources, int32_t want_items, int32_t* nsplit,
@@ -360,6 +387,8 @@ constexpr int32_t kGridMatvec = 1024;
 constexpr int32_t kGridStage = 4096;
 // workgroups of the persistent Arnoldi-step kernels (5 or more resident per CU)
 constexpr int32_t kGridArnoldi = 1280;
+// workgroups of the matvec from assembled operators (8 waves per SIMD)
+constexpr int32_t kGridKmv = 2048;
 hipError_t launch_sum32_batch(int32_t op, const Sum32Batch& p, int32_t grid, hipStream_t s,
                               const ProfSlot& ev = ProfSlot());
 // RHS: out_n[off_n + i] = b_i; EVAL: sys.out_q[i] = p(x_i)
@@ -427,8 +456,10 @@ struct BatchTables {
 // matvec and runs of kLag iterations are captured once into a graph and
 // replayed (unless graphs are off or kernel timing is on); otherwise
 // eager_mv(j) launches the matvec of iteration j.
+// With `kmv` the systems that have an assembled operator take their matvec
+// from it, after the batched kernel sum of the others.
 nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double2* b,
-                       Sum32Batch* mv, const std::function<hipError_t(int32_t)>& eager_mv,
+                       Sum32Batch* mv, KmvBatch* kmv, const std::function<hipError_t(int32_t)>& eager_mv,
                        bool use_graph, hipStream_t s);
 // One Monte-Carlo job (the arguments of nat_mcbem_estimate).
 struct McJob {

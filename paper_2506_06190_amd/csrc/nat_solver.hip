@@ -33,7 +33,8 @@ struct Staging {
 struct ListStats {
     int32_t running = 0;
     int64_t mv_items = 0;
-    double mv_pairs = 0.0;  // target-source pairs of one matvec
+    double mv_pairs = 0.0;  // target-source pairs of one matrix-free matvec
+    double kmv_pairs = 0.0; // ... of one matvec from assembled operators
 };
 
 // Lists of the running systems (flag != 0) into staging, then stream-ordered
@@ -48,7 +49,10 @@ nat_status refresh_lists(const BatchTables& T, const volatile int32_t* flag, boo
         if (!flag[q])
             continue;
         ++ls.running;
-        ls.mv_pairs += (double)T.sys[q].n * (double)T.sys[q].n;
+        if (T.sys[q].off_k >= 0)
+            ls.kmv_pairs += (double)T.sys[q].n * (double)T.sys[q].n;
+        else
+            ls.mv_pairs += (double)T.sys[q].n * (double)T.sys[q].n;
         for (int32_t c = 0; c < T.sys[q].nch; ++c)
             st.items[n_items++] = make_int2(q, c);
     }
@@ -58,7 +62,7 @@ nat_status refresh_lists(const BatchTables& T, const volatile int32_t* flag, boo
             G.nm = 0;
             for (int32_t m = 0; m < I.n_modes; ++m) {
                 const int32_t q = I.sys0 + m;
-                if (!flag[q])
+                if (!flag[q] || T.sys[q].off_k >= 0)
                     continue;
                 if (G.nm == 0) {
                     G.inst = T.sys[q].inst;
@@ -105,15 +109,18 @@ void append_bytes(std::vector<unsigned char>& v, const T& x)
 
 // The run of kLag iterations as an executable graph, captured once per
 // distinct set of launch arguments and kept by the context.
-nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch& mv, int32_t grid_g,
-                        int32_t grid_mv, hipGraphExec_t* exec)
+nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch& mv,
+                        const KmvBatch* kmv, int32_t grid_g, int32_t grid_mv, int32_t grid_k,
+                        hipGraphExec_t* exec)
 {
     NatScratch& sc = scratch_of(ctx);
     std::vector<unsigned char> key;
     append_bytes(key, g);
     append_bytes(key, mv);
+    append_bytes(key, kmv ? *kmv : KmvBatch{});
     append_bytes(key, grid_g);
     append_bytes(key, grid_mv);
+    append_bytes(key, grid_k);
     if (sc.graph_exec && key == sc.graph_key) {
         *exec = sc.graph_exec;
         return NAT_OK;
@@ -130,6 +137,8 @@ nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch& mv,
     hipError_t e = hipSuccess;
     for (int32_t r = 0; r < kLag && e == hipSuccess; ++r) {
         e = launch_sum32_batch(OP_MATVEC, mv, grid_mv, cs);
+        if (e == hipSuccess && kmv)
+            e = launch_kmatvec32(*kmv, grid_k, cs);
         if (e == hipSuccess)
             e = launch_gmres_step(g, grid_g, cs);
     }
@@ -154,7 +163,7 @@ nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch& mv,
 }  // namespace
 
 nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double2* b,
-                       Sum32Batch* mv, const std::function<hipError_t(int32_t)>& eager_mv,
+                       Sum32Batch* mv, KmvBatch* kmv, const std::function<hipError_t(int32_t)>& eager_mv,
                        bool use_graph, hipStream_t s)
 {
     const int32_t S = g.n_sys;
@@ -181,6 +190,11 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
         mv->n_items = T.d_nitems_mv;
         mv->active = g.active;
     }
+    if (kmv) {
+        kmv->items = T.d_items;
+        kmv->n_items = T.d_nitems;
+        kmv->active = g.active;
+    }
 
     // two pinned staging areas for the lists, used alternately
     const size_t per = ((sizeof(GroupDev) * (size_t)S + sizeof(int2) * (size_t)T.max_items + 255) & ~size_t(255)) + 256;
@@ -204,9 +218,10 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
 
     const int32_t grid_g = static_cast<int32_t>(T.max_items < kGridArnoldi ? (T.max_items > 0 ? T.max_items : 1) : kGridArnoldi);
     const int32_t grid_mv = static_cast<int32_t>(ls.mv_items < kMaxGrid ? (ls.mv_items > 0 ? ls.mv_items : 1) : kMaxGrid);
+    const int32_t grid_k = static_cast<int32_t>(T.max_items < kGridKmv ? (T.max_items > 0 ? T.max_items : 1) : kGridKmv);
     hipGraphExec_t exec = nullptr;
     if (use_graph && mv && !ctx->prof) {
-        st = captured_run(ctx, g, *mv, grid_g, grid_mv, &exec);
+        st = captured_run(ctx, g, *mv, kmv, grid_g, grid_mv, grid_k, &exec);
         if (st != NAT_OK)
             exec = nullptr;  // fall back to direct launches
     }
@@ -223,6 +238,9 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
                                                prof_slot(ctx, PK_SUM32_MATVEC, 37.0 * ls.mv_pairs)));
                 else
                     NAT_HIP(eager_mv(launched));
+                if (kmv)
+                    NAT_HIP(launch_kmatvec32(*kmv, grid_k, s,
+                                             prof_slot(ctx, PK_KMATVEC, 8.0 * ls.kmv_pairs)));
                 NAT_HIP(launch_gmres_step(g, grid_g, s, prof_slot(ctx, PK_GMRES_ORTH, 0.0)));
                 ++launched;
             }
@@ -262,7 +280,9 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     if (opts->layout != NAT_NEUMANN_PER_VERTEX && opts->layout != NAT_NEUMANN_PER_TRIANGLE)
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: layout %d", opts->layout);
     if (!(opts->eps_scale > 0.0) || !is_finite(opts->eps_scale) || !(opts->gmres_tol > 0.0) ||
-        opts->gmres_max_iter < 1 || opts->gmres_max_iter > 1000 || (opts->flags & ~NAT_MC_NO_GRAPH))
+        opts->gmres_max_iter < 1 || opts->gmres_max_iter > 1000 ||
+        (opts->flags & ~(NAT_MC_NO_GRAPH | NAT_MC_ASSEMBLED | NAT_MC_MATRIX_FREE)) ||
+        ((opts->flags & NAT_MC_ASSEMBLED) && (opts->flags & NAT_MC_MATRIX_FREE)))
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: bad solver options");
     if (opts->jump != NAT_JUMP_HALF && opts->jump != NAT_JUMP_POLYHEDRAL)
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: jump %d", opts->jump);
@@ -303,7 +323,9 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     T.inst.resize(nj);
     T.sys.resize(S);
     size_t inst_n = 0, inst_q = 0;       // sums of n and q over instances
-    int64_t sum_n = 0, sum_q = 0, sum_v = 0, sum_ch = 0, sum_pa = 0, sum_pb = 0;
+    int64_t sum_n = 0, sum_q = 0, sum_v = 0, sum_ch = 0, sum_pa = 0, sum_pb = 0, sum_k = 0;
+    std::vector<int32_t> asm_list;  // systems whose matvec reads an assembled operator
+    int32_t max_n_asm = 0;
     int32_t max_n = 0, max_q = 0;
     for (int32_t i = 0, q = 0; i < nj; ++i) {
         const McJob& J = jobs[i];
@@ -319,6 +341,10 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         I.w = area / static_cast<double>(J.N);
         I.eps = opts->eps_scale * std::sqrt(area / (M_PI * static_cast<double>(J.N)));
         I.eps2 = static_cast<float>(I.eps * I.eps);
+        // matvec form: assembled operator or matrix-free (FP32 form only)
+        const bool asm_form = fp32 && ((opts->flags & NAT_MC_ASSEMBLED) ||
+                                       (!(opts->flags & NAT_MC_MATRIX_FREE) &&
+                                        ctx->tune.assembled[tune_bucket(J.N)]));
         inst_n += J.N;
         inst_q += J.Q;
         max_n = J.N > max_n ? J.N : max_n;
@@ -331,6 +357,13 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
             Y.nch = gmres_chunks(J.N);
             Y.nsplit_a = I.nsplit_a;
             Y.nsplit_b = J.Q > 0 ? I.nsplit_b : 0;
+            Y.nsplit_mv = asm_form ? 1 : I.nsplit_a;
+            Y.off_k = asm_form ? sum_k : -1;
+            if (asm_form) {
+                sum_k += (int64_t)J.N * J.N;
+                asm_list.push_back(q);
+                max_n_asm = J.N > max_n_asm ? J.N : max_n_asm;
+            }
             Y.off_n = sum_n;
             Y.off_q = sum_q;
             Y.off_v = sum_v;
@@ -367,7 +400,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
          sizeof(double2) * S * gram_stride, sizeof(float4) * n_part, sizeof(InstDev) * nj,
          sizeof(SysDev) * S, sizeof(GroupDev) * S, sizeof(GroupDev) * S, sizeof(GroupDev) * S,
          sizeof(int2) * sum_ch, sizeof(double) * S, sizeof(int64_t) * 8, sizeof(SurfJob) * nj,
-         polyhedral ? sizeof(double) * inst_q : 0});
+         polyhedral ? sizeof(double) * inst_q : 0, sizeof(float2) * sum_k,
+         sizeof(int32_t) * asm_list.size()});
     if (bytes_only) {
         *bytes_only = bytes;
         return NAT_OK;
@@ -425,6 +459,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     int64_t* dcnt64 = cv.take<int64_t>(8);  // items: [0] rhs, [1] eval, [2] matvec
     SurfJob* d_surf = cv.take<SurfJob>(nj);
     double* qfac_all = polyhedral ? cv.take<double>(inst_q) : nullptr;
+    float2* kmat = sum_k > 0 ? cv.take<float2>(sum_k) : nullptr;
+    int32_t* d_asm_list = asm_list.empty() ? nullptr : cv.take<int32_t>(asm_list.size());
     T.d_nitems = dcnt + 2;
     T.d_ngroups_mv = dcnt + 3;
     T.d_iter = dcnt + 4;
@@ -555,7 +591,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         const size_t bI = sizeof(InstDev) * nj, bS = sizeof(SysDev) * S;
         const size_t bG1 = sizeof(GroupDev) * grhs.size(), bG2 = sizeof(GroupDev) * geval.size();
         void* pin = nullptr;
-        st = pinned(ctx, bI + bS + bG1 + bG2 + sizeof(double) * S + 256, &pin);
+        const size_t bL = sizeof(int32_t) * asm_list.size();
+        st = pinned(ctx, bI + bS + bG1 + bG2 + sizeof(double) * S + 256 + bL, &pin);
         if (st != NAT_OK)
             return st;
         char* p = static_cast<char*>(pin);
@@ -580,6 +617,11 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         NAT_HIP(hipMemcpyAsync(dk, hk, sizeof(double) * S, hipMemcpyHostToDevice, s));
         NAT_HIP(hipMemcpyAsync(dcnt64, hc, 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
         NAT_HIP(hipMemcpyAsync(dcnt + 5, hc32, 2 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        if (bL) {
+            char* pl = p + bI + bS + bG1 + bG2 + sizeof(double) * S + 256;
+            std::memcpy(pl, asm_list.data(), bL);
+            NAT_HIP(hipMemcpyAsync(d_asm_list, pl, bL, hipMemcpyHostToDevice, s));
+        }
         // the staging above is read by the copies; the GMRES driver reuses
         // this pinned block, so wait for them
         NAT_HIP(hipStreamSynchronize(s));
@@ -663,6 +705,17 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     NAT_HIP(hipEventRecord(sev.e[2], s));
 
     // ---- GMRES on (I/2 - K) p = b ---------------------------------------------
+    // assembled operators of the systems that use them (the tuner's choice by
+    // N, or forced by the flags)
+    KmvBatch kb{};
+    if (!asm_list.empty()) {
+        NAT_HIP(launch_assemble32(T.d_inst, T.d_sys, d_asm_list, static_cast<int32_t>(asm_list.size()),
+                                  max_n_asm, kmat, s));
+        kb.sys = T.d_sys;
+        kb.kmat = kmat;
+        kb.b32 = v32;
+        kb.partial = partial;
+    }
     std::function<hipError_t(int32_t)> eager = [&](int32_t j) -> hipError_t {
         for (int32_t i = 0; i < nj; ++i) {
             const InstDev& I = T.inst[i];
@@ -680,7 +733,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         return hipSuccess;
     };
     sb.b32 = v32;
-    st = gmres_drive(ctx, g, T, bvec, fp32 ? &sb : nullptr, eager,
+    st = gmres_drive(ctx, g, T, bvec, fp32 ? &sb : nullptr, asm_list.empty() ? nullptr : &kb, eager,
                      !(opts->flags & NAT_MC_NO_GRAPH), s);
     if (st != NAT_OK)
         return st;

@@ -31,6 +31,8 @@ class NatError(RuntimeError):
 
 
 NAT_MC_NO_GRAPH = 1
+NAT_MC_ASSEMBLED = 2
+NAT_MC_MATRIX_FREE = 4
 NAT_JUMP_HALF = 0
 NAT_JUMP_POLYHEDRAL = 1
 NAT_TUNE_FORCE = 1
@@ -122,6 +124,8 @@ _SIGS = {
     "nat_autotune": ([_P, C.c_char_p, C.c_int32, _P], C.c_int),
     "nat_tune_get": ([_P, _P, _P, C.POINTER(C.c_int32)], C.c_int),
     "nat_tune_set": ([_P, _P, _P], C.c_int),
+    "nat_tune_get_form": ([_P, _P, _P, _P], C.c_int),
+    "nat_tune_set_form": ([_P, _P], C.c_int),
     "nat_server_opts_default": ([C.POINTER(nat_server_opts)], None),
     "nat_server_create": ([_P, C.POINTER(nat_server_opts), C.POINTER(_P)], C.c_int),
     "nat_server_submit": ([_P, C.POINTER(nat_request), C.POINTER(C.c_uint64)], C.c_int),
@@ -337,6 +341,26 @@ def nat_tune_set(ctx: Context, items_a, items_b):
     if a.shape != (TUNE_BUCKETS,) or b.shape != (TUNE_BUCKETS,):
         raise ValueError(f"tables must have {TUNE_BUCKETS} entries")
     _check(lib().nat_tune_set(ctx.handle, a.ctypes.data_as(_P), b.ctypes.data_as(_P)))
+
+
+def nat_tune_get_form(ctx: Context, with_rates: bool = False):
+    """Per bucket of N: 1 if the GMRES matvec uses the assembled operator;
+    with_rates adds the sweep's measured matvec rates (pair-modes/s)."""
+    a = np.zeros(TUNE_BUCKETS, dtype=np.int32)
+    rf = np.zeros(TUNE_BUCKETS)
+    ra = np.zeros(TUNE_BUCKETS)
+    _check(lib().nat_tune_get_form(ctx.handle, a.ctypes.data_as(_P), rf.ctypes.data_as(_P),
+                                   ra.ctypes.data_as(_P)))
+    if with_rates:
+        return {"assembled": a.tolist(), "rate_matrix_free": rf.tolist(), "rate_assembled": ra.tolist()}
+    return a.tolist()
+
+
+def nat_tune_set_form(ctx: Context, assembled):
+    a = np.ascontiguousarray(assembled, dtype=np.int32)
+    if a.shape != (TUNE_BUCKETS,):
+        raise ValueError(f"table must have {TUNE_BUCKETS} entries")
+    _check(lib().nat_tune_set_form(ctx.handle, a.ctypes.data_as(_P)))
 
 
 def nat_mc_opts_default() -> nat_mc_opts:

@@ -38,11 +38,82 @@ def test_sweep_and_cache(gpu, tmp_path):
     torch.cuda.synchronize()
     _say(f"tuned table: {t}")
     assert t["tuned"] and set(t["items_a"]) <= CANDIDATES and set(t["items_b"]) <= CANDIDATES
+    form = nat.nat_tune_get_form(c1)
+    _say(f"matvec form per bucket (1 = assembled): {form}")
+    assert set(form) <= {0, 1}
     assert path.exists()
     c2 = nat.Context(0)
     assert nat.nat_autotune(c2, path) == t          # loaded, not swept
+    assert nat.nat_tune_get_form(c2) == form
     c1.close()
     c2.close()
+
+
+def _job(ctx, seed, n_tri, M, Q, N):
+    v, f, u = W.cubesphere_ellipsoid(seed, n_tri)
+    g = W.sh_neumann(u, M, seed)
+    k = W.wavenumber(W.log_uniform_freqs(M, seed))
+    qt, qb = W.random_face_queries(len(f), Q, seed)
+    mesh = nat.Mesh(ctx, v, f)
+    job = nat.McJob(mesh, torch.from_numpy(g).to(DEV), k, torch.from_numpy(qt).to(DEV),
+                    torch.from_numpy(qb).to(DEV), N, seed)
+    return (v, f, g, k, qt, qb, N, seed), mesh, job
+
+
+def _estimate(mesh, job, flags):
+    opts = nat.nat_mc_opts_default()
+    opts.flags = flags
+    p, rep = nat.nat_mcbem_estimate(mesh, job.v_n, job.k, job.q_tri, job.q_bary, job.n_samples,
+                                    job.seed, opts)
+    torch.cuda.synchronize()
+    return p
+
+
+def test_assembled_operator_form(gpu):
+    """The GMRES matvec from the assembled operator: within the FP32 bar of
+    the oracle and close to the matrix-free form; graph replay equals direct
+    launches bit for bit."""
+    ctx = nat.Context(0)
+    args, mesh, job = _job(ctx, 21, 1500, 5, 600, 700)
+    p_asm = _estimate(mesh, job, nat.NAT_MC_ASSEMBLED)
+    p_asm2 = _estimate(mesh, job, nat.NAT_MC_ASSEMBLED | nat.NAT_MC_NO_GRAPH)
+    p_free = _estimate(mesh, job, nat.NAT_MC_MATRIX_FREE)
+    assert torch.equal(p_asm, p_asm2)
+    ref = O.mcbem(*args[:8])["p"]
+    a, b = p_asm.cpu().numpy(), p_free.cpu().numpy()
+    e_or = max(np.linalg.norm(a[m] - ref[m]) / np.linalg.norm(ref[m]) for m in range(len(a)))
+    e_mf = max(np.linalg.norm(a[m] - b[m]) / np.linalg.norm(b[m]) for m in range(len(a)))
+    _say(f"assembled: max rel L2 vs oracle {e_or:.2e}, vs matrix-free {e_mf:.2e}")
+    assert e_or <= 1e-3 and e_mf <= 1e-4
+    mesh.close()
+    ctx.close()
+
+
+def test_mixed_forms_in_one_batch(gpu):
+    """A batch whose instances take different matvec forms by the table (one
+    bucket assembled, the other matrix-free) equals each instance alone bit
+    for bit and stays within the oracle bar."""
+    ctx = nat.Context(0)
+    a1, m1, j1 = _job(ctx, 31, 900, 3, 300, 200)     # N = 200: bucket 1
+    a2, m2, j2 = _job(ctx, 32, 1500, 4, 500, 700)    # N = 700: bucket 3
+    form = [0] * 10
+    form[1] = 1
+    nat.nat_tune_set_form(ctx, form)
+    nat.nat_mcbem_estimate_batch(ctx, [j1, j2])
+    torch.cuda.synchronize()
+    for args, mesh, job in ((a1, m1, j1), (a2, m2, j2)):
+        p1 = _estimate(mesh, job, 0)
+        assert torch.equal(job.p_out, p1)
+        ref = O.mcbem(*args[:8])["p"]
+        got = p1.cpu().numpy()
+        e = max(np.linalg.norm(got[m] - ref[m]) / np.linalg.norm(ref[m]) for m in range(len(got)))
+        assert e <= 1e-3
+    # the assembled instance differs from its matrix-free form only by rounding
+    p_free = _estimate(m1, j1, nat.NAT_MC_MATRIX_FREE)
+    assert not torch.equal(p_free, j1.p_out)
+    m1.close()
+    m2.close()
+    ctx.close()
 
 
 @pytest.mark.parametrize("items", [16, 512])
