@@ -249,9 +249,22 @@ void orc_mc_matrix(int32_t N, const double* y, const double* ny, double k, doubl
     }
 }
 
-void orc_mc_rhs(int32_t N, const double* y, double k, double w, double eps,
-                const double* g_in, double* b_out)
+/* Integral of G over the flat disk of radius eps about the target, times
+ * the Neumann value there (Section 4.2): the paper's one-sample estimate
+ * eps/2, or (exact_disk) the closed form: in polar coordinates the area
+ * element r dr dtheta cancels the 1/r of G, leaving (1/2) int_0^eps e^{ikr} dr
+ * = (e^{ik eps} - 1)/(2ik). */
+static cplx disk_factor(double k, double eps, int32_t exact_disk)
 {
+    if (!exact_disk)
+        return 0.5 * eps;
+    return (cexp(I * k * eps) - 1.0) / (2.0 * I * k);
+}
+
+void orc_mc_rhs(int32_t N, const double* y, double k, double w, double eps,
+                const double* g_in, int32_t exact_disk, double* b_out)
+{
+    const cplx dk = disk_factor(k, eps, exact_disk);
     const cplx* g = (const cplx*)g_in;
     cplx* b = (cplx*)b_out;
 #pragma omp parallel for schedule(static)
@@ -264,7 +277,7 @@ void orc_mc_rhs(int32_t N, const double* y, double k, double w, double eps,
             if (r >= eps)
                 s += w * orc_G(k, r) * g[j];
         }
-        b[i] = -s - 0.5 * eps * g[i];
+        b[i] = -s - dk * g[i];
     }
 }
 
@@ -277,8 +290,9 @@ void orc_mc_rhs(int32_t N, const double* y, double k, double w, double eps,
 void orc_mc_eval(int32_t Q, const double* x, const double* gx_in, double c_q,
                  const double* c_arr, int32_t N, const double* y, const double* ny,
                  const double* g_in, const double* p_in, double k, double w, double eps,
-                 double* out)
+                 int32_t exact_disk, double* out)
 {
+    const cplx dk = disk_factor(k, eps, exact_disk);
     const cplx* g = (const cplx*)g_in;
     const cplx* p = (const cplx*)p_in;
     const cplx* gx = (const cplx*)gx_in;
@@ -293,7 +307,7 @@ void orc_mc_eval(int32_t Q, const double* x, const double* gx_in, double c_q,
             if (r >= eps && r > 0.0)
                 s += w * (orc_dGdny(k, x + 3 * q, y + 3 * j, ny + 3 * j) * p[j] - orc_G(k, r) * g[j]);
         }
-        cplx disk = gx ? 0.5 * eps * gx[q] : 0.0;
+        cplx disk = gx ? dk * gx[q] : 0.0;
         o[q] = (s - disk) / (c_arr ? c_arr[q] : c_q);
     }
 }
@@ -491,7 +505,8 @@ int32_t orc_mcbem(const double* V, int32_t nV, const int32_t* T, int32_t nT,
                   int32_t Q, int32_t N, uint64_t seed, double eps_scale, double tol,
                   int32_t max_iter, double* p_out /* complex [n_modes][Q] */,
                   double* p_smp_out /* complex [n_modes][N] or NULL */, int32_t* iters,
-                  double* resid, int32_t* smp_tri, double* smp_bary, int32_t jump)
+                  double* resid, int32_t* smp_tri, double* smp_bary, int32_t jump,
+                  int32_t exact_disk)
 {
     (void)nV;
     double* area = (double*)malloc(sizeof(double) * (size_t)nT);
@@ -524,13 +539,13 @@ int32_t orc_mcbem(const double* V, int32_t nV, const int32_t* T, int32_t nT,
         orc_neumann_at(T, layout, gm, N, smp_tri, smp_bary, (double*)gj);
         orc_neumann_at(T, layout, gm, Q, q_tri, q_bary, (double*)gq);
         orc_mc_matrix(N, y, ny, kv[m], w, eps, (double*)M);
-        orc_mc_rhs(N, y, kv[m], w, eps, (const double*)gj, (double*)b);
+        orc_mc_rhs(N, y, kv[m], w, eps, (const double*)gj, exact_disk, (double*)b);
         iters[m] = orc_gmres(N, (const double*)M, (const double*)b, (double*)p, tol, max_iter,
                              &resid[m]);
         if (resid[m] > tol)
             status = 3;
         orc_mc_eval(Q, xq, (const double*)gq, 0.5, cq, N, y, ny, (const double*)gj,
-                    (const double*)p, kv[m], w, eps, p_out + 2 * (size_t)m * (size_t)Q);
+                    (const double*)p, kv[m], w, eps, exact_disk, p_out + 2 * (size_t)m * (size_t)Q);
         if (p_smp_out)
             memcpy(p_smp_out + 2 * (size_t)m * (size_t)N, p, sizeof(cplx) * (size_t)N);
     }

@@ -57,16 +57,17 @@ def lib():
         L.orc_neumann_at.argtypes = [_i, C.c_int32, _d, C.c_int32, _i, _d, _d]
         L.orc_kernels.argtypes = [C.c_double, _d, _d, _d, _d, _d]
         L.orc_mc_matrix.argtypes = [C.c_int32, _d, _d, C.c_double, C.c_double, C.c_double, _d]
-        L.orc_mc_rhs.argtypes = [C.c_int32, _d, C.c_double, C.c_double, C.c_double, _d, _d]
+        L.orc_mc_rhs.argtypes = [C.c_int32, _d, C.c_double, C.c_double, C.c_double, _d, C.c_int32, _d]
         L.orc_mc_eval.argtypes = [C.c_int32, _d, C.c_void_p, C.c_double, C.c_void_p, C.c_int32,
-                                  _d, _d, _d, _d, C.c_double, C.c_double, C.c_double, _d]
+                                  _d, _d, _d, _d, C.c_double, C.c_double, C.c_double, C.c_int32, _d]
         L.orc_free_terms.argtypes = [_d, _i, C.c_int32, _i, _d, C.c_int32, C.c_int32, _d]
         L.orc_gmres.argtypes = [C.c_int32, _d, _d, _d, C.c_double, C.c_int32,
                                 C.POINTER(C.c_double)]
         L.orc_gmres.restype = C.c_int32
         L.orc_mcbem.argtypes = [_d, C.c_int32, _i, C.c_int32, _d, C.c_int32, C.c_int32, _d,
                                 _i, _d, C.c_int32, C.c_int32, C.c_uint64, C.c_double,
-                                C.c_double, C.c_int32, _d, C.c_void_p, _i, _d, _i, _d, C.c_int32]
+                                C.c_double, C.c_int32, _d, C.c_void_p, _i, _d, _i, _d, C.c_int32,
+                                C.c_int32]
         L.orc_mcbem.restype = C.c_int32
         L.orc_gauss_legendre01.argtypes = [C.c_int32, _d, _d]
         L.orc_self_panel.argtypes = [C.c_double, _d, _d, _d, _d]
@@ -169,16 +170,16 @@ def mc_matrix(y, ny, k, w, eps):
     return M
 
 
-def mc_rhs(y, k, w, eps, g):
+def mc_rhs(y, k, w, eps, g, exact_disk=False):
     y = _f64(y)
     N = len(y)
     b = np.empty(N, dtype=np.complex128)
-    lib().orc_mc_rhs(N, y.reshape(-1), float(k), float(w), float(eps), _c2d(g),
+    lib().orc_mc_rhs(N, y.reshape(-1), float(k), float(w), float(eps), _c2d(g), int(exact_disk),
                      b.view(np.float64))
     return b
 
 
-def mc_eval(x, gx, c_q, y, ny, g, p, k, w, eps):
+def mc_eval(x, gx, c_q, y, ny, g, p, k, w, eps, exact_disk=False):
     """Stage-B sum at targets x; gx=None drops the disk term (exterior use).
     c_q: one free term for every target, or an array of one per target."""
     x, y, ny = _f64(x), _f64(y), _f64(ny)
@@ -195,7 +196,7 @@ def mc_eval(x, gx, c_q, y, ny, g, p, k, w, eps):
                       0.5 if carr is not None else float(c_q),
                       carr.ctypes.data_as(C.c_void_p) if carr is not None else None,
                       len(y), y.reshape(-1), ny.reshape(-1), _c2d(g), _c2d(p),
-                      float(k), float(w), float(eps), out.view(np.float64))
+                      float(k), float(w), float(eps), int(exact_disk), out.view(np.float64))
     return out
 
 
@@ -220,7 +221,7 @@ def gmres(A, b, tol=1e-12, max_iter=200):
 
 
 def mcbem(V, T, g, k, q_tri, q_bary, N, seed, eps_scale=1.0, tol=1e-12, max_iter=200,
-          layout=0, want_samples=False, jump=0):
+          layout=0, want_samples=False, jump=0, exact_disk=False):
     """The whole MC-BEM estimate for n_modes (k_m, g_m) pairs.
 
     g: complex (n_modes, V) per-vertex (layout 0) or (n_modes, T) per triangle.
@@ -244,7 +245,7 @@ def mcbem(V, T, g, k, q_tri, q_bary, N, seed, eps_scale=1.0, tol=1e-12, max_iter
                          float(eps_scale), float(tol), int(max_iter),
                          p.view(np.float64).reshape(-1),
                          ps.ctypes.data_as(C.c_void_p) if ps is not None else None,
-                         iters, resid, tri, bary.reshape(-1), int(jump))
+                         iters, resid, tri, bary.reshape(-1), int(jump), int(exact_disk))
     out = dict(p=p, iters=iters, resid=resid, tri=tri, bary=bary, status=int(st))
     if want_samples:
         out["p_samples"] = ps

@@ -204,3 +204,26 @@ def test_convergence_slope():
         errs.append(np.mean(e))
     slope = np.polyfit(np.log(Ns), np.log(errs), 1)[0]
     assert -0.7 < slope < -0.25
+
+
+def test_exact_disk_option():
+    """The disk term of Section 4.2: the paper's one-sample estimate eps/2 by
+    default, or the flat-disk integral of G in closed form.  A single sample
+    has no other sources, so b = -(disk factor) g; the closed form is checked
+    against a polar Gauss-Legendre quadrature of the disk integral and its
+    k -> 0 limit eps/2."""
+    y = np.zeros((1, 3))
+    g = np.array([1.0 + 0.0j])
+    eps = 0.037
+    for k in (0.5, 20.0, 140.0):
+        d_paper = -O.mc_rhs(y, k, 1.0, eps, g)[0]
+        d_exact = -O.mc_rhs(y, k, 1.0, eps, g, exact_disk=True)[0]
+        assert d_paper == pytest.approx(eps / 2, rel=1e-15)
+        assert d_exact == pytest.approx(CF.flat_disk_G_integral(k, eps), rel=1e-13)
+        xr, wr = np.polynomial.legendre.leggauss(40)
+        r = 0.5 * eps * (xr + 1.0)
+        quad = 2 * np.pi * np.sum(0.5 * eps * wr * np.exp(1j * k * r) / (4 * np.pi * r) * r)
+        assert d_exact == pytest.approx(quad, rel=1e-12)
+    # small k: eps/2 + i k eps^2/4 + O(k^2)
+    d_small = -O.mc_rhs(y, 1e-6, 1.0, eps, g, exact_disk=True)[0]
+    assert d_small == pytest.approx(eps / 2 + 1j * 1e-6 * eps**2 / 4, rel=1e-9)
