@@ -104,6 +104,10 @@ typedef struct {
  * table by N (nat_autotune).  The plain FP64 form is always matrix-free. */
 #define NAT_MC_ASSEMBLED 2
 #define NAT_MC_MATRIX_FREE 4
+/* nat_mc_opts.flags: the disk term of Section 4.2 with the integral of G over
+ * the flat disk of radius eps in closed form, (e^{ik eps} - 1)/(2ik), instead
+ * of the paper's eps/2 (they differ by O(k eps^2)). */
+#define NAT_MC_EXACT_DISK 8
 
 /* Per right-hand side report of a solve. */
 typedef struct {
@@ -188,6 +192,7 @@ nat_status nat_mcbem_samples(nat_mesh* mesh, int32_t n_samples, uint64_t seed, i
  * sample set.  With N samples y_j, w = |Gamma|/N and disk radius eps:
  *   Stage A  (1/2) p_i - sum_{j: r_ij >= eps} w dG(y_i,y_j)/dn_j p_j
  *              = - sum_{j: r_ij >= eps} w G(y_i,y_j) g_j - (eps/2) g_i
+ *            (eps/2: the disk term, or its closed form, NAT_MC_EXACT_DISK)
  *            solved by GMRES (x0 = 0, unrestarted, tol, max_iter);
  *   Stage B  p(x_q) = (1/c_q) [ sum_{j: |x_q-y_j| >= eps} w (dG/dn_j p_j - G g_j)
  *                               - (eps/2) g(x_q) ],

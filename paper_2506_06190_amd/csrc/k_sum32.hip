@@ -245,8 +245,8 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
 
 // Combine the splits of one system's targets (TwoSum in FP32) and apply the
 // epilogue of the operation in FP64:
-//   RHS   b_i = -acc_i - (eps/2) g_i
-//   EVAL  p_q = (1/c_q) (acc_q - (eps/2) g_q), 1/c_q = 2 unless the instance
+//   RHS   b_i = -acc_i - d g_i    (d: the disk factor, eps/2 or its closed form)
+//   EVAL  p_q = (1/c_q) (acc_q - d g_q), 1/c_q = 2 unless the instance
 //         carries per-query factors
 template <int OP>
 __global__ void __launch_bounds__(256)
@@ -282,12 +282,14 @@ k_reduce32(const Sum32Batch p, const double2* __restrict__ g_tgt, double2* __res
     const double acci = static_cast<double>(hi) + static_cast<double>(li);
     if (OP == OP_RHS) {
         const double2 g = g_tgt[S.off_n + i];
-        out_n[S.off_n + i] = make_double2(-accr - 0.5 * S.eps * g.x, -acci - 0.5 * S.eps * g.y);
+        const double dr = S.disk.x * g.x - S.disk.y * g.y, di = S.disk.x * g.y + S.disk.y * g.x;
+        out_n[S.off_n + i] = make_double2(-accr - dr, -acci - di);
     } else {
         const double2 g = g_tgt[S.off_q + i];
         const double* qf = p.inst[S.inst].qfac;
         const double f = qf ? qf[i] : 2.0;
-        S.out_q[i] = make_double2(f * (accr - 0.5 * S.eps * g.x), f * (acci - 0.5 * S.eps * g.y));
+        const double dr = S.disk.x * g.x - S.disk.y * g.y, di = S.disk.x * g.y + S.disk.y * g.x;
+        S.out_q[i] = make_double2(f * (accr - dr), f * (acci - di));
     }
 }
 

@@ -71,8 +71,9 @@ __global__ void __launch_bounds__(256) k_sum64(SumArgs a)
     double2 out;
     if (OP == OP_RHS) {
         const double2 g = a.g_tgt[(size_t)m * a.ld_gt + i];
-        out.x = -sr - 0.5 * eps * g.x;
-        out.y = -si - 0.5 * eps * g.y;
+        const double2 d = a.disk[m];
+        out.x = -sr - (d.x * g.x - d.y * g.y);
+        out.y = -si - (d.x * g.y + d.y * g.x);
     } else if (OP == OP_MATVEC) {
         const double2 x = ps[i];
         out.x = 0.5 * x.x - sr;
@@ -80,8 +81,9 @@ __global__ void __launch_bounds__(256) k_sum64(SumArgs a)
     } else {
         const double2 g = a.g_tgt[(size_t)m * a.ld_gt + i];
         const double f = a.qfac ? a.qfac[i] : 2.0;
-        out.x = f * (sr - 0.5 * eps * g.x);
-        out.y = f * (si - 0.5 * eps * g.y);
+        const double2 d = a.disk[m];
+        out.x = f * (sr - (d.x * g.x - d.y * g.y));
+        out.y = f * (si - (d.x * g.y + d.y * g.x));
     }
     a.out[(size_t)m * a.ld_out + i] = out;
 }

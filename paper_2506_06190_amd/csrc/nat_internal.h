@@ -296,6 +296,7 @@ struct SumArgs {
     const float* kappa32;        // [n_modes] device, k / (2 pi)
     const int32_t* active;       // [n_modes] or null: inactive modes are skipped
     double w, eps;
+    const double2* disk;         // [n_modes] device: disk factor of each mode (RHS, EVAL)
     const double* qfac;          // [NT] 1 / c_q (EVAL), or null for 2
     double2* out;                // [mode * ld_out + i]
     int64_t ld_out;
@@ -331,6 +332,7 @@ struct SysDev {
     int64_t off_pa;                    // split partials over the samples: nsplit_a n
     int64_t off_pb;                    // split partials over the queries: nsplit_b q
     double k, wscale, eps;             // wavenumber, w/(4 pi), disk radius
+    double2 disk;                      // integral of G over the disk: eps/2 or the closed form
     float k32, kappa32;                // k and k/(2 pi) in FP32
     double2* out_q;                    // result at the queries (caller row) or null
     double2* out_n;                    // Stage-A solution (caller row or scratch)

@@ -281,7 +281,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: layout %d", opts->layout);
     if (!(opts->eps_scale > 0.0) || !is_finite(opts->eps_scale) || !(opts->gmres_tol > 0.0) ||
         opts->gmres_max_iter < 1 || opts->gmres_max_iter > 1000 ||
-        (opts->flags & ~(NAT_MC_NO_GRAPH | NAT_MC_ASSEMBLED | NAT_MC_MATRIX_FREE)) ||
+        (opts->flags & ~(NAT_MC_NO_GRAPH | NAT_MC_ASSEMBLED | NAT_MC_MATRIX_FREE | NAT_MC_EXACT_DISK)) ||
         ((opts->flags & NAT_MC_ASSEMBLED) && (opts->flags & NAT_MC_MATRIX_FREE)))
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: bad solver options");
     if (opts->jump != NAT_JUMP_HALF && opts->jump != NAT_JUMP_POLYHEDRAL)
@@ -375,6 +375,13 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
             Y.kappa32 = static_cast<float>(J.k[m] / kTwoPi);
             Y.wscale = I.w * kInv4Pi;
             Y.eps = I.eps;
+            if (opts->flags & NAT_MC_EXACT_DISK) {
+                // (e^{ik eps} - 1) / (2ik) = sin(x)/(2k) + i (1 - cos x)/(2k), x = k eps
+                const double x = J.k[m] * I.eps, h = std::sin(0.5 * x);
+                Y.disk = make_double2(std::sin(x) / (2.0 * J.k[m]), h * h / J.k[m]);
+            } else {
+                Y.disk = make_double2(0.5 * I.eps, 0.0);
+            }
             sum_n += J.N;
             sum_q += J.Q;
             sum_v += (int64_t)mm1 * J.N;
@@ -399,7 +406,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
          sizeof(double) * sum_ch, sizeof(double) * sum_ch, sizeof(double) * sum_ch,
          sizeof(double2) * S * gram_stride, sizeof(float4) * n_part, sizeof(InstDev) * nj,
          sizeof(SysDev) * S, sizeof(GroupDev) * S, sizeof(GroupDev) * S, sizeof(GroupDev) * S,
-         sizeof(int2) * sum_ch, sizeof(double) * S, sizeof(int64_t) * 8, sizeof(SurfJob) * nj,
+         sizeof(int2) * sum_ch, sizeof(double) * S, sizeof(double2) * S, sizeof(int64_t) * 8,
+         sizeof(SurfJob) * nj,
          polyhedral ? sizeof(double) * inst_q : 0, sizeof(float2) * sum_k,
          sizeof(int32_t) * asm_list.size()});
     if (bytes_only) {
@@ -456,6 +464,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     T.d_groups_mv = cv.take<GroupDev>(S);
     T.d_items = cv.take<int2>(sum_ch);
     double* dk = cv.take<double>(S);
+    double2* ddisk = cv.take<double2>(S);
     int64_t* dcnt64 = cv.take<int64_t>(8);  // items: [0] rhs, [1] eval, [2] matvec
     SurfJob* d_surf = cv.take<SurfJob>(nj);
     double* qfac_all = polyhedral ? cv.take<double>(inst_q) : nullptr;
@@ -592,7 +601,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         const size_t bG1 = sizeof(GroupDev) * grhs.size(), bG2 = sizeof(GroupDev) * geval.size();
         void* pin = nullptr;
         const size_t bL = sizeof(int32_t) * asm_list.size();
-        st = pinned(ctx, bI + bS + bG1 + bG2 + sizeof(double) * S + 256 + bL, &pin);
+        const size_t bD = sizeof(double2) * S;
+        st = pinned(ctx, bI + bS + bG1 + bG2 + sizeof(double) * S + 256 + bL + bD + 16, &pin);
         if (st != NAT_OK)
             return st;
         char* p = static_cast<char*>(pin);
@@ -617,11 +627,17 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         NAT_HIP(hipMemcpyAsync(dk, hk, sizeof(double) * S, hipMemcpyHostToDevice, s));
         NAT_HIP(hipMemcpyAsync(dcnt64, hc, 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
         NAT_HIP(hipMemcpyAsync(dcnt + 5, hc32, 2 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        char* pl = p + bI + bS + bG1 + bG2 + sizeof(double) * S + 256;
         if (bL) {
-            char* pl = p + bI + bS + bG1 + bG2 + sizeof(double) * S + 256;
             std::memcpy(pl, asm_list.data(), bL);
             NAT_HIP(hipMemcpyAsync(d_asm_list, pl, bL, hipMemcpyHostToDevice, s));
         }
+        // double2 is 16-byte aligned: align the staging address itself
+        double2* hd = reinterpret_cast<double2*>((reinterpret_cast<uintptr_t>(pl + bL) + 15) &
+                                                 ~uintptr_t(15));
+        for (int32_t q = 0; q < S; ++q)
+            hd[q] = T.sys[q].disk;
+        NAT_HIP(hipMemcpyAsync(ddisk, hd, bD, hipMemcpyHostToDevice, s));
         // the staging above is read by the copies; the GMRES driver reuses
         // this pinned block, so wait for them
         NAT_HIP(hipStreamSynchronize(s));
@@ -656,6 +672,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         a.s64 = x64_all + 3 * on;
         a.sn64 = n64_all + 3 * on;
         a.k = dk + I.sys0;
+        a.disk = ddisk + I.sys0;
         a.w = I.w;
         a.eps = I.eps;
         if (op == OP_EVAL) {

@@ -42,7 +42,7 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _run_gpu(ctx, wl, prec, tol, layout=0, want_samples=False, max_iter=200, jump=0):
+def _run_gpu(ctx, wl, prec, tol, layout=0, want_samples=False, max_iter=200, jump=0, flags=0):
     mesh = nat.Mesh(ctx, wl.vertices, wl.tris)
     g = torch.from_numpy(np.ascontiguousarray(wl.g)).to(DEV)
     qt = torch.from_numpy(np.ascontiguousarray(wl.q_tri)).to(DEV)
@@ -53,6 +53,7 @@ def _run_gpu(ctx, wl, prec, tol, layout=0, want_samples=False, max_iter=200, jum
     opts.layout = layout
     opts.gmres_max_iter = max_iter
     opts.jump = jump
+    opts.flags = flags
     ps = None
     if want_samples:
         ps = torch.empty((wl.n_modes, wl.n_samples), dtype=torch.complex128, device=DEV)
@@ -113,6 +114,25 @@ def test_polyhedral_free_term(ctx, prec):
     c = O.free_terms(wl.vertices, wl.tris, wl.q_tri, wl.q_b, 1)
     assert np.any(c != 0.5)
     assert np.allclose(p1, p0 * (0.5 / c)[None, :], rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_exact_disk_term(ctx, prec):
+    """NAT_MC_EXACT_DISK: the disk term in closed form in both stages, against
+    the oracle's same option; it moves the estimate by O(k eps^2)."""
+    wl = _small_ellipsoid(n_modes=5, Q=400, N=500, seed=91)
+    _say(f"exact disk {prec}: modes={wl.n_modes} N={wl.n_samples} Q={wl.n_queries}")
+    P = nat.NAT_PREC_FP64 if prec == "fp64" else nat.NAT_PREC_FP32
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    p1, _, _ = _run_gpu(ctx, wl, P, tol, flags=nat.NAT_MC_EXACT_DISK)
+    r1 = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri, wl.q_b, wl.n_samples, wl.seed,
+                 tol=1e-12, exact_disk=True)
+    r0 = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri, wl.q_b, wl.n_samples, wl.seed,
+                 tol=1e-12)
+    bar = 1e-10 if prec == "fp64" else 1e-3
+    for m in range(wl.n_modes):
+        assert _rel(p1[m], r1["p"][m]) <= bar, m
+    assert max(_rel(r1["p"][m], r0["p"][m]) for m in range(wl.n_modes)) > 10 * bar or prec == "fp32"
 
 
 def test_polyhedral_free_term_batch(ctx):
