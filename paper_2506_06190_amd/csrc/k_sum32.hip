@@ -67,25 +67,28 @@ __device__ __forceinline__ float uniform_f(float x)
 // source data).  Per (pair, mode):
 //   RHS     acc += (1/r) e^{i th} a
 //   MATVEC  acc += q e^{i th} (ikr - 1) b,           q = (d.n) / r^3
+//           with (ikr - 1) b formed as -b + i r (k b) from the staged k b
 //   EVAL    acc += e^{i th} (a/r + q (ikr - 1) b)
 // with th = 2 pi fract(kappa r) taken by the hardware sine and cosine.
 template <int OP, int MB>
 __device__ __forceinline__ void tile_pairs(const float (&s_pos)[6][kTS],
                                            const float2 (*s_a)[kMB], const float2 (*s_b)[kMB],
-                                           float tx, float ty,
+                                           const float2 (*s_kb)[kMB], float tx, float ty,
                                            float tz, float eps2, const float (&kap)[kMB],
-                                           const float (&kk)[kMB], float (&ar)[kMB], float (&ai)[kMB])
+                                           float (&ar)[kMB], float (&ai)[kMB])
 {
     constexpr bool kA = (OP == OP_RHS || OP == OP_EVAL);
     constexpr bool kB = (OP == OP_MATVEC || OP == OP_EVAL);
     for (int c = 0; c < kTS; ++c) {
-        float2 av[MB], bv[MB];
+        float2 av[MB], bv[MB], cv[MB];
 #pragma unroll
         for (int mm = 0; mm < MB; ++mm) {
             if (kA)
                 av[mm] = s_a[c][mm];
-            if (kB)
+            if (kB) {
                 bv[mm] = s_b[c][mm];
+                cv[mm] = s_kb[c][mm];
+            }
         }
         const float dx = s_pos[0][c] - tx;
         const float dy = s_pos[1][c] - ty;
@@ -109,9 +112,9 @@ __device__ __forceinline__ void tile_pairs(const float (&s_pos)[6][kTS],
                 ar[mm] = fmaf(rinv, vr, ar[mm]);
                 ai[mm] = fmaf(rinv, vi, ai[mm]);
             } else {
-                const float kr = r * kk[mm];
-                const float ur = fmaf(-kr, bv[mm].y, -bv[mm].x);
-                const float ui = fmaf(kr, bv[mm].x, -bv[mm].y);
+                // (ikr - 1) b = -b + i r (k b), k b staged with the tile
+                const float ur = fmaf(-r, cv[mm].y, -bv[mm].x);
+                const float ui = fmaf(r, cv[mm].x, -bv[mm].y);
                 if (OP == OP_MATVEC) {
                     const float vr = fmaf(cs, ur, -(sn * ui));
                     const float vi = fmaf(cs, ui, sn * ur);
@@ -136,6 +139,7 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
     __shared__ float s_pos[6][kTS];
     __shared__ float2 s_a[kA ? kTS : 1][kMB];
     __shared__ float2 s_b[kB ? kTS : 1][kMB];
+    __shared__ float2 s_kb[kB ? kTS : 1][kMB];
 
     const int32_t tid = threadIdx.x;
     const int64_t n_items = *p.n_items;
@@ -203,8 +207,11 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
                 const int64_t o = p.sys[sys[mm]].off_n + j0 + c;
                 if (kA)
                     s_a[c][mm] = ok ? p.a32[o] : make_float2(0.0f, 0.0f);
-                if (kB)
-                    s_b[c][mm] = ok ? p.b32[o] : make_float2(0.0f, 0.0f);
+                if (kB) {
+                    const float2 b = ok ? p.b32[o] : make_float2(0.0f, 0.0f);
+                    s_b[c][mm] = b;
+                    s_kb[c][mm] = make_float2(kk[mm] * b.x, kk[mm] * b.y);
+                }
             }
             __syncthreads();
 
@@ -215,13 +222,13 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
             if (!wave_live)
                 ;
             else if (nm > 4)
-                tile_pairs<OP, 8>(s_pos, s_a, s_b, tx, ty, tz, eps2, kap, kk, ar, ai);
+                tile_pairs<OP, 8>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
             else if (nm > 2)
-                tile_pairs<OP, 4>(s_pos, s_a, s_b, tx, ty, tz, eps2, kap, kk, ar, ai);
+                tile_pairs<OP, 4>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
             else if (nm > 1)
-                tile_pairs<OP, 2>(s_pos, s_a, s_b, tx, ty, tz, eps2, kap, kk, ar, ai);
+                tile_pairs<OP, 2>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
             else
-                tile_pairs<OP, 1>(s_pos, s_a, s_b, tx, ty, tz, eps2, kap, kk, ar, ai);
+                tile_pairs<OP, 1>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
 #pragma unroll
             for (int mm = 0; mm < kMB; ++mm) {
                 two_sum_fold(hr[mm], lr[mm], ar[mm]);
