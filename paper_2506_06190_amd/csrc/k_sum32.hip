@@ -16,9 +16,9 @@
 //       Z = a/r + (ikr - 1) (d.n / r^3) b,
 //    a, b = w/(4 pi)-weighted source data, so one complex multiply-add per
 //    pair and mode accumulates both the G and the dG/dn terms;
-//  * the phase is reduced in revolutions, fract(kappa r) with
-//    kappa = k/(2 pi), and fed to the hardware sine and cosine, which take
-//    revolutions;
+//  * the phase kappa r (kappa = k/(2 pi)) is fed to the hardware sine and
+//    cosine, which take revolutions; instances whose phases can exceed
+//    kPhaseRevNoFract revolutions reduce it with fract() first;
 //  * each LDS tile's FP32 sum is folded into a (hi, lo) pair with Knuth's
 //    TwoSum; the splits are combined the same way by the consumer (the
 //    reduction kernel, or the GMRES step for the matvec), in FP64 only for
@@ -69,8 +69,10 @@ __device__ __forceinline__ float uniform_f(float x)
 //   MATVEC  acc += q e^{i th} (ikr - 1) b,           q = (d.n) / r^3
 //           with (ikr - 1) b formed as -b + i r (k b) from the staged k b
 //   EVAL    acc += e^{i th} (a/r + q (ikr - 1) b)
-// with th = 2 pi fract(kappa r) taken by the hardware sine and cosine.
-template <int OP, int MB>
+// with th = 2 pi kappa r taken by the hardware sine and cosine, which take
+// revolutions (reduced by fract() first only for instances whose largest
+// kappa r exceeds kPhaseRevNoFract, RED).
+template <int OP, int MB, bool RED>
 __device__ __forceinline__ void tile_pairs(const float (&s_pos)[6][kTS],
                                            const float2 (*s_a)[kMB], const float2 (*s_b)[kMB],
                                            const float2 (*s_kb)[kMB], float tx, float ty,
@@ -103,7 +105,7 @@ __device__ __forceinline__ void tile_pairs(const float (&s_pos)[6][kTS],
         }
 #pragma unroll
         for (int mm = 0; mm < MB; ++mm) {
-            const float ph = __builtin_amdgcn_fractf(r * kap[mm]);
+            const float ph = RED ? __builtin_amdgcn_fractf(r * kap[mm]) : r * kap[mm];
             const float sn = __builtin_amdgcn_sinf(ph);
             const float cs = __builtin_amdgcn_cosf(ph);
             if (OP == OP_RHS) {
@@ -182,6 +184,7 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
             __builtin_amdgcn_readfirstlane(tile * kThreads + (tid & ~63)) < NT;
         const float tx = t32[ic], ty = t32[NT + ic], tz = t32[2 * NT + ic];
         const float eps2 = I.eps2;
+        const bool red = __builtin_amdgcn_readfirstlane(I.phase_fract) != 0;
 
         float hr[kMB], hi_[kMB], lr[kMB], li[kMB];
 #pragma unroll
@@ -221,14 +224,25 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
                 ar[mm] = ai[mm] = 0.0f;
             if (!wave_live)
                 ;
-            else if (nm > 4)
-                tile_pairs<OP, 8>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
-            else if (nm > 2)
-                tile_pairs<OP, 4>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
-            else if (nm > 1)
-                tile_pairs<OP, 2>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
-            else
-                tile_pairs<OP, 1>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
+            else if (red) {
+                if (nm > 4)
+                    tile_pairs<OP, 8, true>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
+                else if (nm > 2)
+                    tile_pairs<OP, 4, true>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
+                else if (nm > 1)
+                    tile_pairs<OP, 2, true>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
+                else
+                    tile_pairs<OP, 1, true>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
+            } else {
+                if (nm > 4)
+                    tile_pairs<OP, 8, false>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
+                else if (nm > 2)
+                    tile_pairs<OP, 4, false>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
+                else if (nm > 1)
+                    tile_pairs<OP, 2, false>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
+                else
+                    tile_pairs<OP, 1, false>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
+            }
 #pragma unroll
             for (int mm = 0; mm < kMB; ++mm) {
                 two_sum_fold(hr[mm], lr[mm], ar[mm]);

@@ -759,6 +759,8 @@ nat_status nat_mesh_create(nat_ctx* ctx, const double* vertices, int32_t n_verti
         }
     for (int d = 0; d < 3; ++d)
         m->center[d] = 0.5 * (lo[d] + hi[d]);
+    m->diameter = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                            (hi[2] - lo[2]) * (hi[2] - lo[2]));
 
     nat_status st = set_device(ctx);
     if (st != NAT_OK) {

@@ -90,6 +90,7 @@ struct nat_mesh {
     std::vector<double> cdf;     // nT, running sum of areas
     double area_total = 0.0;
     double center[3] = {0, 0, 0};  // bounding-box centre; origin of the FP32 streams
+    double diameter = 0.0;         // bounding-box diagonal: the largest pair distance
     // device copies
     double* d_V = nullptr;
     int32_t* d_T = nullptr;
@@ -312,7 +313,7 @@ struct InstDev {
     int32_t nsplit_a, per_split_a;     // source splits of the sums over the samples
     int32_t nsplit_b, per_split_b;     // ... over the queries
     float eps2;
-    int32_t pad;
+    int32_t phase_fract;               // 1: reduce k r / (2 pi) to [0, 1) before sin/cos
     double eps, w;
     const float* s32;                  // [3][n] sample positions, relative to the mesh centre
     const float* sn32;                 // [3][n] sample normals
@@ -383,6 +384,11 @@ hipError_t launch_assemble32(const InstDev* inst, const SysDev* sys, const int32
 void split_rule(int32_t n_targets, int32_t n_sources, int32_t want_items, int32_t* nsplit,
                 int32_t* per_split);
 int32_t target_tiles(int32_t n_targets);
+// The hardware sine and cosine take revolutions and reduce them themselves:
+// a development probe found them as accurate without a prior fract() for
+// arguments up to this many revolutions (the FP32 kernel sums skip it when
+// every pair of an instance stays below).
+constexpr double kPhaseRevNoFract = 64.0;
 // workgroups of the persistent kernel-sum launches: the GMRES matvec, and
 // the right-hand side and query stages
 constexpr int32_t kGridMatvec = 1024;

@@ -341,6 +341,10 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         I.w = area / static_cast<double>(J.N);
         I.eps = opts->eps_scale * std::sqrt(area / (M_PI * static_cast<double>(J.N)));
         I.eps2 = static_cast<float>(I.eps * I.eps);
+        double k_max = 0.0;
+        for (int32_t m = 0; m < J.M; ++m)
+            k_max = J.k[m] > k_max ? J.k[m] : k_max;
+        I.phase_fract = k_max / kTwoPi * J.mesh->diameter > kPhaseRevNoFract ? 1 : 0;
         // matvec form: assembled operator or matrix-free (FP32 form only)
         const bool asm_form = fp32 && ((opts->flags & NAT_MC_ASSEMBLED) ||
                                        (!(opts->flags & NAT_MC_MATRIX_FREE) &&

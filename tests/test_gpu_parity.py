@@ -216,6 +216,26 @@ def test_fp32_ragged_multimode(ctx):
     assert rep[0]["t_solve_ms"] > rep[0]["t_rhs_ms"]
 
 
+def test_fp32_long_phases(ctx):
+    """Wavenumbers high enough that k r / (2 pi) exceeds 64 revolutions on the
+    mesh (about 100), so the FP32 sums reduce the phase before the hardware
+    sine and cosine; N = 150 samples, so unrestarted GMRES with 200
+    iterations converges; within the FP32 bar of the oracle."""
+    v, f, u = W.noisy_ellipsoid(13, subdiv=3)
+    k = np.array([2200.0, 2500.0])
+    g = W.sh_neumann(u, 2, 13)
+    qt, qb = W.random_face_queries(len(f), 200, 13)
+    wl = W.MCWorkload("long_phases", v, f, g, k, qt, qb, 150, 13)
+    diam = np.linalg.norm(v.max(axis=0) - v.min(axis=0))
+    assert k.max() / (2 * np.pi) * diam > 64
+    _say(f"fp32 long phases: k={k.tolist()} diam={diam:.3f} N={wl.n_samples}")
+    p, rep, _ = _run_gpu(ctx, wl, nat.NAT_PREC_FP32, 1e-9)
+    r = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri, wl.q_b, wl.n_samples, wl.seed, tol=1e-12)
+    errs = [_rel(p[m], r["p"][m]) for m in range(2)]
+    _say("  rel L2 per mode: " + " ".join(f"{e:.2e}" for e in errs))
+    assert max(errs) <= 1e-3
+
+
 def test_fp32_full_precision_workload(ctx):
     """Noise-displaced ellipsoid, 20480 triangles, 32 modes, 4096 queries x 1024
     samples, the launch configuration the benchmark times."""
