@@ -94,6 +94,9 @@ def run_batched(nat, torch, ctx, args, dev):
     roof = roofline_from(prof)
     roof["timing_pass"] = "second pass over the same steps, eager dispatch, events on each dispatch"
     roof["traffic"] = traffic_from_profile()
+    valu = valu_from_profile()
+    roof["executed_fp32_tflops_counters"] = valu[0] if valu else None
+    roof["valu_issue_busy_counters"] = valu[1] if valu else None
     roof["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)"
     out = {
         "value": alg * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
@@ -128,15 +131,39 @@ def run_batched(nat, torch, ctx, args, dev):
             got = jobs[i].p_out.cpu().numpy()
             errs += [float(np.linalg.norm(got[q] - r["p"][q]) / np.linalg.norm(r["p"][q]))
                      for q in range(m)]
+        cores = O.num_threads()
+        # one thread, on the first instance of the sample
+        wl = wls[0]
+        m = min(n_modes, wl.n_modes)
+        O.set_threads(1)
+        t0 = time.perf_counter()
+        O.mcbem(wl.vertices, wl.tris, wl.g[:m], wl.k[:m], wl.q_tri, wl.q_b, wl.n_samples, wl.seed,
+                tol=1e-6)
+        t_one = time.perf_counter() - t0
+        O.set_threads(cores)
+        pairs_one = m * (wl.n_samples * (wl.n_samples - 1) + wl.n_queries * wl.n_samples)
         out["cpu_baseline"] = {"value": sample_pairs / t_cpu, "unit": "pair-evals/s",
-                               "cores": O.num_threads(), "kind": "oracle",
+                               "cores": cores, "kind": "oracle",
                                "sample": f"first {n_inst} instances x first {n_modes} modes of the "
                                          "headline workload, FP64, tol 1e-6",
-                               "seconds": round(t_cpu, 3)}
+                               "seconds": round(t_cpu, 3), "cpu_model": cpu_model(),
+                               "single_thread_value": pairs_one / t_one,
+                               "single_thread_sample": f"first instance x first {m} modes"}
         out["max_rel_l2_vs_oracle"] = max(errs)
     for mesh in meshes:
         mesh.close()
     return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _percentiles(x):
@@ -363,6 +390,72 @@ def pmc_summarize(d_fetch, d_write):
     print("\n".join(lines))
 
 
+VALU_FILE = os.path.join(ROOT, "profiles", "k_sum32_matvec_valu_counters.txt")
+VALU_COUNTERS = ("SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_ADD_F32",
+                 "SQ_INSTS_VALU_TRANS_F32", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVES",
+                 "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE")
+
+
+def pmc_valu_summarize(d):
+    """Executed FP32 operations and VALU issue of the matvec from one counter
+    pass (wave-level instruction counts; an FMA counts 2, a multiply, add or
+    transcendental 1, times 64 lanes)."""
+    tot = {c: 0.0 for c in VALU_COUNTERS}
+    spans = {}
+    for r in _counter_rows(d):
+        k = r["Kernel_Name"]
+        if not ("k_sum32<1>" in k or "k_sum32ILi1E" in k):
+            continue
+        if r["Counter_Name"] in tot:
+            tot[r["Counter_Name"]] += float(r["Counter_Value"])
+        spans[r.get("Dispatch_Id")] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    if not spans:
+        raise SystemExit("matvec kernel not found")
+    secs = sum(spans.values()) * 1e-9
+    flops = 64.0 * (2 * tot["SQ_INSTS_VALU_FMA_F32"] + tot["SQ_INSTS_VALU_MUL_F32"] +
+                    tot["SQ_INSTS_VALU_ADD_F32"] + tot["SQ_INSTS_VALU_TRANS_F32"])
+    # GRBM_GUI_ACTIVE is summed over the 8 XCDs; SQ_ACTIVE_INST_VALU over the
+    # 1024 SIMDs, in units of 4 cycles
+    xcd_cycles = tot["GRBM_GUI_ACTIVE"] / 8.0
+    busy = 4.0 * tot["SQ_ACTIVE_INST_VALU"] / (1024.0 * xcd_cycles)
+    lines = [
+        "# VALU counters of k_sum32<OP_MATVEC> (batched headline step, direct launches)",
+        "# command (run from the repository root, TMPDIR=/tmp):",
+        "#   rocprofv3 --pmc " + " ".join(VALU_COUNTERS) + " \\",
+        "#       --output-format csv -d gpurun_out/pmc_valu -o run -- python3 bench.py --pmc-pass",
+        "#   python3 bench.py --pmc-valu-summarize gpurun_out/pmc_valu",
+        "# executed FP32 flops = 64 lanes x (2 FMA + MUL + ADD + TRANS) wave instructions;",
+        "# VALU issue = 4 x SQ_ACTIVE_INST_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs).",
+        f"kernel_source_sha256_16: {kernel_hash()}",
+        f"matvec_dispatches: {len(spans)}",
+        f"traced_seconds: {secs:.6f}",
+    ] + [f"{c}: {tot[c]:.6g}" for c in VALU_COUNTERS] + [
+        f"executed_fp32_flops: {flops:.6g}",
+        f"executed_fp32_tflops: {flops / secs * 1e-12:.3f}",
+        f"trans_share_of_valu: {tot['SQ_INSTS_VALU_TRANS_F32'] / tot['SQ_INSTS_VALU']:.4f}",
+        f"valu_issue_busy: {busy:.4f}",
+    ]
+    with open(VALU_FILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def valu_from_profile():
+    """(executed FP32 TFLOP/s, VALU issue fraction) of the matvec, or None when
+    absent or stale."""
+    if not os.path.exists(VALU_FILE):
+        return None
+    kv = {}
+    with open(VALU_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    return float(kv["executed_fp32_tflops"]), float(kv["valu_issue_busy"])
+
+
 def traffic_from_profile():
     """Scaled HBM bytes per matvec launch, or None when absent or stale."""
     if not os.path.exists(TRAFFIC_FILE):
@@ -483,6 +576,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--pmc-pass", action="store_true")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--pmc-valu-summarize", metavar="DIR")
     ap.add_argument("--tune", choices=["cache", "default"], default="cache",
                     help="kernel-sum tiling: the autotuner's table (cache, else a sweep) or the defaults")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2506_06190_amd", "tune",
@@ -496,6 +590,9 @@ def main():
     args = ap.parse_args()
     if args.pmc_summarize:
         pmc_summarize(*args.pmc_summarize)
+        return
+    if args.pmc_valu_summarize:
+        pmc_valu_summarize(args.pmc_valu_summarize)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is "

@@ -34,6 +34,12 @@ typedef double complex cplx;
 
 #define FOUR_PI (4.0 * M_PI)
 
+/* thread count of the parallel loops that follow (timing only) */
+void orc_set_threads(int32_t n)
+{
+    omp_set_num_threads(n > 0 ? n : 1);
+}
+
 /* threads OpenMP will use for the parallel loops */
 int32_t orc_num_threads(void)
 {

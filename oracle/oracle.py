@@ -45,6 +45,7 @@ def lib():
         build(force=False)
         L = C.CDLL(str(LIB))
         L.orc_num_threads.restype = C.c_int32
+        L.orc_set_threads.argtypes = [C.c_int32]
         L.orc_geometry.argtypes = [_d, _i, C.c_int32, _d, _d, _d]
         L.orc_splitmix64.argtypes = [C.c_uint64]
         L.orc_splitmix64.restype = C.c_uint64
@@ -97,6 +98,11 @@ def _c2d(a):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the OpenMP loops that follow (the timing leg's single-thread run)."""
+    lib().orc_set_threads(int(n))
 
 
 # ---------------------------------------------------------------- geometry
