@@ -425,3 +425,32 @@ def test_dense_multi_rhs_matrix_cores(ctx, mesh_kind, n_rhs):
         assert rep_all[r]["t_solve_ms"] > 0.0 and rep_all[r]["t_rhs_ms"] == 0.0
     op.close()
     mesh.close()
+
+
+def test_options_together_in_a_batch(ctx):
+    """The polyhedral free term, the exact disk term and the assembled-operator
+    matvec at once, in a two-instance batch: each instance equals its single
+    estimate bit for bit and the oracle with the same options within the
+    FP32 bar."""
+    wls = [_edge_and_vertex_workload(41, subdiv=2, n_modes=3, N=300),
+           _edge_and_vertex_workload(42, subdiv=3, n_modes=2, N=450)]
+    meshes = [nat.Mesh(ctx, wl.vertices, wl.tris) for wl in wls]
+    opts = nat.nat_mc_opts_default()
+    opts.jump = nat.NAT_JUMP_POLYHEDRAL
+    opts.flags = nat.NAT_MC_EXACT_DISK | nat.NAT_MC_ASSEMBLED
+    jobs = [nat.McJob(m, torch.from_numpy(wl.g).to(DEV), wl.k, torch.from_numpy(wl.q_tri).to(DEV),
+                      torch.from_numpy(wl.q_b).to(DEV), wl.n_samples, wl.seed)
+            for wl, m in zip(wls, meshes)]
+    nat.nat_mcbem_estimate_batch(ctx, jobs, opts)
+    torch.cuda.synchronize()
+    for wl, mesh, job in zip(wls, meshes, jobs):
+        p1, _ = nat.nat_mcbem_estimate(mesh, job.v_n, wl.k, job.q_tri, job.q_bary, wl.n_samples,
+                                       wl.seed, opts)
+        torch.cuda.synchronize()
+        assert torch.equal(job.p_out, p1)
+        r = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri, wl.q_b, wl.n_samples, wl.seed,
+                    tol=1e-12, jump=1, exact_disk=True)
+        got = p1.cpu().numpy()
+        assert max(_rel(got[m], r["p"][m]) for m in range(wl.n_modes)) <= 1e-3
+    for m in meshes:
+        m.close()
