@@ -366,11 +366,11 @@ def pmc_summarize(d_fetch, d_write):
     lines = [
         "# HBM traffic of k_sum32<OP_MATVEC> (batched headline step, direct launches)",
         "# commands (run from the repository root, TMPDIR=/tmp):",
-        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o run -- \\",
+        f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d_fetch} -o run -- \\",
         "#       python3 bench.py --pmc-pass",
-        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o run -- \\",
+        f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d_write} -o run -- \\",
         "#       python3 bench.py --pmc-pass",
-        "#   python3 bench.py --pmc-summarize gpurun_out/pmc_fetch gpurun_out/pmc_write",
+        f"#   python3 bench.py --pmc-summarize {d_fetch} {d_write}",
         "# The copy kernel (a 1 GiB device-to-device copy, 1 GiB read + 1 GiB written) gives",
         "# the scale of each counter; per-launch figures are averages over the matvec dispatches.",
         f"kernel_source_sha256_16: {kernel_hash()}",
@@ -422,8 +422,8 @@ def pmc_valu_summarize(d):
         "# VALU counters of k_sum32<OP_MATVEC> (batched headline step, direct launches)",
         "# command (run from the repository root, TMPDIR=/tmp):",
         "#   rocprofv3 --pmc " + " ".join(VALU_COUNTERS) + " \\",
-        "#       --output-format csv -d gpurun_out/pmc_valu -o run -- python3 bench.py --pmc-pass",
-        "#   python3 bench.py --pmc-valu-summarize gpurun_out/pmc_valu",
+        f"#       --output-format csv -d {d} -o run -- python3 bench.py --pmc-pass",
+        f"#   python3 bench.py --pmc-valu-summarize {d}",
         "# executed FP32 flops = 64 lanes x (2 FMA + MUL + ADD + TRANS) wave instructions;",
         "# VALU issue = 4 x SQ_ACTIVE_INST_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs).",
         f"kernel_source_sha256_16: {kernel_hash()}",
