@@ -341,6 +341,13 @@ def test_error_paths(ctx):
     with pytest.raises(nat.NatError) as ei:
         nat.nat_mcbem_estimate(mesh, g, [1.0], qt, qb, 64, 1, opts)
     assert ei.value.status == nat.NAT_E_NOCONV
+    for field, value in (("jump", 2), ("flags", nat.NAT_MC_ASSEMBLED | nat.NAT_MC_MATRIX_FREE),
+                         ("flags", 64), ("eps_scale", 0.0)):
+        o = nat.nat_mc_opts_default()
+        setattr(o, field, value)
+        with pytest.raises(nat.NatError) as ei:        # invalid options
+            nat.nat_mcbem_estimate(mesh, g, [1.0], qt, qb, 64, 1, o)
+        assert ei.value.status == nat.NAT_E_INVALID, (field, value)
     mesh.close()
     small = nat.Context(0, hbm_budget_bytes=1 << 16)
     m2 = nat.Mesh(small, v, f)
