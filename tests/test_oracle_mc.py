@@ -227,3 +227,59 @@ def test_exact_disk_option():
     # small k: eps/2 + i k eps^2/4 + O(k^2)
     d_small = -O.mc_rhs(y, 1e-6, 1.0, eps, g, exact_disk=True)[0]
     assert d_small == pytest.approx(eps / 2 + 1j * 1e-6 * eps**2 / 4, rel=1e-9)
+
+
+def _subdivide_flat(V, T):
+    """4-way midpoint subdivision that keeps the polyhedral surface (no
+    projection); returns the parent of each child and the middle child of
+    each parent, whose centroid is the parent's."""
+    V = [tuple(v) for v in V]
+    idx = {}
+
+    def mid(a, b):
+        key = (min(a, b), max(a, b))
+        if key not in idx:
+            idx[key] = len(V)
+            V.append(tuple((np.array(V[a]) + np.array(V[b])) / 2))
+        return idx[key]
+
+    T2, parent, middle = [], [], []
+    for t, (a, b, c) in enumerate(T):
+        ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+        for tri in ((a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca)):
+            T2.append(tri)
+            parent.append(t)
+        middle.append(len(T2) - 1)
+    return np.array(V), np.array(T2, dtype=np.int32), np.array(parent), np.array(middle)
+
+
+def test_mc_converges_to_dense_on_tiny_mesh():
+    """Brute-force agreement of the two solvers on a tiny polyhedron (the
+    regular icosahedron of radius 0.1 m, ka = 1, face-constant cos(theta)
+    data): the dense Burton-Miller solution on flat refinements of the same
+    surface converges at the face centroids, and the Monte-Carlo estimate
+    there (averaged over 4 seeds) approaches it as N grows."""
+    u, f = W.icosphere_unit(0)
+    V, T, k = 0.1 * u, f.astype(np.int32), 10.0
+    c = V[T].mean(axis=1)
+    c /= np.linalg.norm(c, axis=1, keepdims=True)
+    g_face = c[:, 2].astype(np.complex128)
+    Vd, Td, gd, mids, dense = V, T, g_face.copy(), np.arange(len(T)), []
+    for level in range(3):
+        A, B = O.bem_assemble(Vd, Td, k, True)
+        p, _, _ = O.bem_solve(A, B, gd, tol=1e-12)
+        dense.append(p[mids])
+        Vd, Td, par, mid = _subdivide_flat(Vd, Td)
+        gd, mids = gd[par], mid[mids]
+    ref = dense[2]
+    d0 = np.linalg.norm(dense[0] - ref) / np.linalg.norm(ref)
+    d1 = np.linalg.norm(dense[1] - ref) / np.linalg.norm(ref)
+    assert d1 < 0.5 * d0 and d1 < 0.1
+    qt = np.arange(len(T), dtype=np.int32)
+    qb = np.full((len(T), 2), 1.0 / 3.0)
+    errs = []
+    for N in (256, 1024, 4096):
+        e = [np.linalg.norm(O.mcbem(V, T, g_face[None, :], [k], qt, qb, N, 1000 + s,
+                                    layout=1)["p"][0] - ref) / np.linalg.norm(ref) for s in range(4)]
+        errs.append(np.mean(e))
+    assert errs[2] < errs[1] < errs[0] and errs[2] < 0.1, errs
