@@ -50,11 +50,12 @@ def make_jobs(nat, torch, ctx, wls, dev):
 
 
 def roofline_from(prof, peak=FP32_VECTOR_PEAK_TFLOPS):
-    sums = {k: v for k, v in prof.items() if k.startswith("sum32")}
+    sums = {k: v for k, v in prof.items() if k.startswith(("sum32", "sym32"))}
     dom_name = max(sums, key=lambda k: sums[k]["total_ms"])
     dom = sums[dom_name]
     achieved = dom["flops"] / (dom["total_ms"] * 1e-3) / 1e12
-    return {"bound": "alu", "kernel": f"k_sum32 ({dom_name})", "achieved": round(achieved, 3),
+    kern = "k_sym32" if dom_name.startswith("sym32") else "k_sum32"
+    return {"bound": "alu", "kernel": f"{kern} ({dom_name})", "achieved": round(achieved, 3),
             "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
             "avg_launch_ms": round(dom["avg_ms"], 5), "launches": dom["launches"],
             "flops_per_launch": dom["flops"] / dom["launches"]}
@@ -93,8 +94,9 @@ def run_batched(nat, torch, ctx, args, dev):
     nat.nat_profile_enable(ctx, False)
     roof = roofline_from(prof)
     roof["timing_pass"] = "second pass over the same steps, eager dispatch, events on each dispatch"
-    roof["traffic"] = traffic_from_profile()
-    valu = valu_from_profile()
+    kern = roof["kernel"].split()[0]
+    roof["traffic"] = traffic_from_profile(kern) if kern in MATVEC else None
+    valu = valu_from_profile(kern) if kern in MATVEC else None
     roof["executed_fp32_tflops_counters"] = valu[0] if valu else None
     roof["valu_issue_busy_counters"] = valu[1] if valu else None
     roof["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)"
@@ -298,18 +300,32 @@ def run_served(nat, torch, ctx, args, dev):
 #   rocprofv3 --pmc WRITE_SIZE --output-format csv -d D2 -o run -- python3 bench.py --pmc-pass
 #   python3 bench.py --pmc-summarize D1 D2
 # --pmc-pass copies a 1 GiB buffer (the calibration kernel of known traffic)
-# and then runs one headline step with direct launches; --pmc-summarize
-# scales the matvec kernel's per-dispatch counters by the copy's measured /
-# true bytes and writes TRAFFIC_FILE, stamped with a hash of the kernel
-# source so the bench reports the figure only while the kernel is unchanged.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sum32_matvec_batched_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2506_06190_amd", "csrc", "k_sum32.hip")
+# and then runs one headline step with direct launches (--ordered: with the
+# ordered matvec form); --pmc-summarize scales the matvec kernel's
+# per-dispatch counters by the copy's measured / true bytes and writes the
+# kernel's traffic file, stamped with a hash of the kernel source so the
+# bench reports the figure only while the kernel is unchanged.
+CSRC = os.path.join(ROOT, "paper_2506_06190_amd", "csrc")
+MATVEC = {
+    # symmetric form (default): k_sym32
+    "k_sym32": {"src": os.path.join(CSRC, "k_sym32.hip"),
+                "match": lambda k: "k_sym32" in k,
+                "title": "k_sym32 (symmetric GMRES matvec)",
+                "traffic": os.path.join(ROOT, "profiles", "k_sym32_matvec_batched_traffic.txt"),
+                "valu": os.path.join(ROOT, "profiles", "k_sym32_matvec_valu_counters.txt")},
+    # ordered form (NAT_MC_ORDERED_SUM): k_sum32<OP_MATVEC>
+    "k_sum32": {"src": os.path.join(CSRC, "k_sum32.hip"),
+                "match": lambda k: "k_sum32<1>" in k or "k_sum32ILi1E" in k,
+                "title": "k_sum32<OP_MATVEC> (ordered GMRES matvec)",
+                "traffic": os.path.join(ROOT, "profiles", "k_sum32_matvec_batched_traffic.txt"),
+                "valu": os.path.join(ROOT, "profiles", "k_sum32_matvec_valu_counters.txt")},
+}
 COPY_BYTES = 1 << 30
 
 
-def kernel_hash():
+def kernel_hash(kern):
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
+    with open(MATVEC[kern]["src"], "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
@@ -324,7 +340,7 @@ def run_pmc_pass(nat, torch, ctx, args, dev):
     wls = W.config_batched()
     meshes, jobs = make_jobs(nat, torch, ctx, wls, dev)
     opts = nat.nat_mc_opts_default()
-    opts.flags = nat.NAT_MC_NO_GRAPH
+    opts.flags = nat.NAT_MC_NO_GRAPH | (nat.NAT_MC_ORDERED_SUM if args.ordered else 0)
     nat.nat_mcbem_estimate_batch(ctx, jobs, opts, allow_noconv=True)
     torch.cuda.synchronize()
     for m in meshes:
@@ -344,7 +360,16 @@ def _counter_rows(d):
     return rows
 
 
+def _matvec_in(rows):
+    for kern, spec in MATVEC.items():
+        if any(spec["match"](r["Kernel_Name"]) for r in rows):
+            return kern
+    raise SystemExit("no matvec kernel in the counter rows")
+
+
 def pmc_summarize(d_fetch, d_write):
+    kern = _matvec_in(_counter_rows(d_fetch))
+    match = MATVEC[kern]["match"]
     out = {}
     for name, d in (("FETCH_SIZE", d_fetch), ("WRITE_SIZE", d_write)):
         per = {}
@@ -354,7 +379,7 @@ def pmc_summarize(d_fetch, d_write):
             key = (r["Kernel_Name"], r.get("Dispatch_Id", r.get("Correlation_Id")))
             per[key] = per.get(key, 0.0) + float(r["Counter_Value"]) * 1024.0  # KiB per dispatch
         copy = [v for (k, _), v in per.items() if "copy" in k.lower() or "elementwise" in k.lower()]
-        mv = [v for (k, _), v in per.items() if "k_sum32<1>" in k or "k_sum32ILi1E" in k]
+        mv = [v for (k, _), v in per.items() if match(k)]
         if not copy or not mv:
             raise SystemExit(f"{name}: copy kernel or matvec kernel not found")
         big = max(copy)
@@ -364,16 +389,16 @@ def pmc_summarize(d_fetch, d_write):
     fetch = f["per_launch_raw"] * f["scale"]
     write = w["per_launch_raw"] * w["scale"]
     lines = [
-        "# HBM traffic of k_sum32<OP_MATVEC> (batched headline step, direct launches)",
+        f"# HBM traffic of {MATVEC[kern]['title']} (batched headline step, direct launches)",
         "# commands (run from the repository root, TMPDIR=/tmp):",
         f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d_fetch} -o run -- \\",
-        "#       python3 bench.py --pmc-pass",
+        f"#       python3 bench.py --pmc-pass{' --ordered' if kern == 'k_sum32' else ''}",
         f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d_write} -o run -- \\",
-        "#       python3 bench.py --pmc-pass",
+        f"#       python3 bench.py --pmc-pass{' --ordered' if kern == 'k_sum32' else ''}",
         f"#   python3 bench.py --pmc-summarize {d_fetch} {d_write}",
         "# The copy kernel (a 1 GiB device-to-device copy, 1 GiB read + 1 GiB written) gives",
         "# the scale of each counter; per-launch figures are averages over the matvec dispatches.",
-        f"kernel_source_sha256_16: {kernel_hash()}",
+        f"kernel_source_sha256_16: {kernel_hash(kern)}",
         f"matvec_dispatches: {f['dispatches']}",
         f"copy_bytes_true: {COPY_BYTES}",
         f"copy_fetch_measured_bytes: {f['copy_measured']:.0f}",
@@ -384,13 +409,13 @@ def pmc_summarize(d_fetch, d_write):
         f"write_bytes_per_launch_scaled: {write:.0f}",
         f"traffic_bytes_per_launch: {fetch + write:.0f}",
     ]
-    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
-    with open(TRAFFIC_FILE, "w") as fh:
+    path = MATVEC[kern]["traffic"]
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 
-VALU_FILE = os.path.join(ROOT, "profiles", "k_sum32_matvec_valu_counters.txt")
 VALU_COUNTERS = ("SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_ADD_F32",
                  "SQ_INSTS_VALU_TRANS_F32", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVES",
                  "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE")
@@ -402,9 +427,11 @@ def pmc_valu_summarize(d):
     transcendental 1, times 64 lanes)."""
     tot = {c: 0.0 for c in VALU_COUNTERS}
     spans = {}
-    for r in _counter_rows(d):
+    rows = _counter_rows(d)
+    kern = _matvec_in(rows)
+    for r in rows:
         k = r["Kernel_Name"]
-        if not ("k_sum32<1>" in k or "k_sum32ILi1E" in k):
+        if not MATVEC[kern]["match"](k):
             continue
         if r["Counter_Name"] in tot:
             tot[r["Counter_Name"]] += float(r["Counter_Value"])
@@ -419,14 +446,15 @@ def pmc_valu_summarize(d):
     xcd_cycles = tot["GRBM_GUI_ACTIVE"] / 8.0
     busy = 4.0 * tot["SQ_ACTIVE_INST_VALU"] / (1024.0 * xcd_cycles)
     lines = [
-        "# VALU counters of k_sum32<OP_MATVEC> (batched headline step, direct launches)",
+        f"# VALU counters of {MATVEC[kern]['title']} (batched headline step, direct launches)",
         "# command (run from the repository root, TMPDIR=/tmp):",
         "#   rocprofv3 --pmc " + " ".join(VALU_COUNTERS) + " \\",
-        f"#       --output-format csv -d {d} -o run -- python3 bench.py --pmc-pass",
+        f"#       --output-format csv -d {d} -o run -- python3 bench.py --pmc-pass"
+        f"{' --ordered' if kern == 'k_sum32' else ''}",
         f"#   python3 bench.py --pmc-valu-summarize {d}",
         "# executed FP32 flops = 64 lanes x (2 FMA + MUL + ADD + TRANS) wave instructions;",
         "# VALU issue = 4 x SQ_ACTIVE_INST_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs).",
-        f"kernel_source_sha256_16: {kernel_hash()}",
+        f"kernel_source_sha256_16: {kernel_hash(kern)}",
         f"matvec_dispatches: {len(spans)}",
         f"traced_seconds: {secs:.6f}",
     ] + [f"{c}: {tot[c]:.6g}" for c in VALU_COUNTERS] + [
@@ -435,38 +463,40 @@ def pmc_valu_summarize(d):
         f"trans_share_of_valu: {tot['SQ_INSTS_VALU_TRANS_F32'] / tot['SQ_INSTS_VALU']:.4f}",
         f"valu_issue_busy: {busy:.4f}",
     ]
-    with open(VALU_FILE, "w") as fh:
+    with open(MATVEC[kern]["valu"], "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 
-def valu_from_profile():
+def valu_from_profile(kern):
     """(executed FP32 TFLOP/s, VALU issue fraction) of the matvec, or None when
     absent or stale."""
-    if not os.path.exists(VALU_FILE):
+    path = MATVEC[kern]["valu"]
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(VALU_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256_16") != kernel_hash():
+    if kv.get("kernel_source_sha256_16") != kernel_hash(kern):
         return None
     return float(kv["executed_fp32_tflops"]), float(kv["valu_issue_busy"])
 
 
-def traffic_from_profile():
+def traffic_from_profile(kern):
     """Scaled HBM bytes per matvec launch, or None when absent or stale."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = MATVEC[kern]["traffic"]
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256_16") != kernel_hash():
+    if kv.get("kernel_source_sha256_16") != kernel_hash(kern):
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -575,6 +605,8 @@ def main():
     ap.add_argument("--workload", choices=["batched", "precision", "served", "dense"], default="batched")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--pmc-pass", action="store_true")
+    ap.add_argument("--ordered", action="store_true",
+                    help="with --pmc-pass: the ordered matvec form (NAT_MC_ORDERED_SUM)")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--pmc-valu-summarize", metavar="DIR")
     ap.add_argument("--tune", choices=["cache", "default"], default="cache",

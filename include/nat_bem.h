@@ -108,6 +108,12 @@ typedef struct {
  * the flat disk of radius eps in closed form, (e^{ik eps} - 1)/(2ik), instead
  * of the paper's eps/2 (they differ by O(k eps^2)). */
 #define NAT_MC_EXACT_DISK 8
+/* nat_mc_opts.flags: the matrix-free FP32 matvec in the ordered form (each
+ * target's thread evaluates all its pairs) instead of the symmetric form
+ * (each unordered sample pair evaluated once, feeding both of its targets,
+ * since r and e^{ikr} are the same both ways).  The two round differently;
+ * both stay within the FP32 form's tolerance. */
+#define NAT_MC_ORDERED_SUM 16
 
 /* Per right-hand side report of a solve. */
 typedef struct {

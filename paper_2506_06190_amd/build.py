@@ -28,7 +28,7 @@ PER_FILE = {"nat_api.hip": ["-ffp-contract=off"],
             "k_bem.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 SOURCES = ["nat_api.hip", "nat_solver.hip", "nat_server.hip", "nat_autotune.hip", "serve_core.cpp",
            "k_sample.hip",
-           "k_sum64.hip", "k_sum32.hip", "k_gmres.hip", "k_bem.hip"]
+           "k_sum64.hip", "k_sum32.hip", "k_sym32.hip", "k_gmres.hip", "k_bem.hip"]
 
 
 def _compile(name: str) -> Path:

@@ -217,7 +217,24 @@ __global__ void __launch_bounds__(kRows) k_orth_dots(GmresBatch g)
                 // matvec epilogue: w = v_j / 2 - (sum of the FP32 split partials)
                 float hr = 0.0f, hi = 0.0f, lr = 0.0f, li = 0.0f;
                 const float4* pp = g.partial + S.off_pa + t;
-                for (int32_t sp0 = 0; sp0 < S.nsplit_mv; sp0 += 8) {
+                const float2* pp2 = reinterpret_cast<const float2*>(g.partial) + 2 * S.off_pa + t;
+                if (S.mv_pair) {
+                    for (int32_t sp0 = 0; sp0 < S.nsplit_mv; sp0 += 8) {
+                        float2 v[8];
+#pragma unroll
+                        for (int c = 0; c < 8; ++c)
+                            v[c] = sp0 + c < S.nsplit_mv ? pp2[(int64_t)(sp0 + c) * n]
+                                                         : make_float2(0.0f, 0.0f);
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) {
+                            if (sp0 + c < S.nsplit_mv) {
+                                fold2(hr, lr, v[c].x);
+                                fold2(hi, li, v[c].y);
+                            }
+                        }
+                    }
+                }
+                for (int32_t sp0 = 0; sp0 < (S.mv_pair ? 0 : S.nsplit_mv); sp0 += 8) {
                     // issue the group's loads together, fold in split order
                     float4 v[8];
 #pragma unroll

@@ -468,15 +468,16 @@ nat_status nat_profile_enable(nat_ctx* ctx, int32_t enable)
 
 int32_t nat_profile_read(nat_ctx* ctx, nat_kernel_stat* out, int32_t max_out)
 {
-    static const char* names[9] = {"sum32_rhs", "sum32_matvec", "sum32_eval", "sum64",
-                                   "gmres_orth", "bem_assemble", "zgemv", "other", "kmatvec32"};
+    static const char* names[10] = {"sum32_rhs", "sum32_matvec", "sum32_eval", "sum64",
+                                    "gmres_orth", "bem_assemble", "zgemv", "other", "kmatvec32",
+                                    "sym32_matvec"};
     if (!ctx || (max_out > 0 && !out))
         return 0;
     if (set_device(ctx) != NAT_OK)
         return 0;
     nat::prof_collect(ctx);
     int32_t n = 0;
-    for (int i = 0; i < 9 && n < max_out; ++i) {
+    for (int i = 0; i < 10 && n < max_out; ++i) {
         const NatProfStat& st = ctx->prof_stat[i];
         if (st.launches == 0)
             continue;

@@ -36,6 +36,7 @@ void tune_defaults(TuneTable* t)
     for (int b = 0; b < kTuneBuckets; ++b) {
         t->items_a[b] = t->items_b[b] = 64;
         t->assembled[b] = 0;
+        t->symmetric[b] = 1;
         t->rate_free[b] = t->rate_asm[b] = 0.0;
     }
     t->tuned = 0;

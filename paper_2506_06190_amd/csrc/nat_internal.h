@@ -55,6 +55,7 @@ struct TuneTable {
     int32_t items_a[kTuneBuckets];  // sums over the samples, by the sample count N
     int32_t items_b[kTuneBuckets];  // sums at the queries, by the query count Q
     int32_t assembled[kTuneBuckets];  // 1: GMRES matvec from the assembled operator, by N
+    int32_t symmetric[kTuneBuckets];  // 1: matrix-free matvec in the symmetric form, by N
     // measured matvec rates of the sweep (pair-modes/s; 0 if not timed)
     double rate_free[kTuneBuckets];
     double rate_asm[kTuneBuckets];
@@ -72,7 +73,7 @@ struct nat_ctx {
     bool prof = false;
     std::vector<NatProfEvent> prof_pending;
     std::vector<hipEvent_t> prof_pool;
-    NatProfStat prof_stat[9];
+    NatProfStat prof_stat[10];
     size_t budget = 0;   // 0: unlimited
     size_t in_use = 0;   // bytes charged
     NatScratch scratch;
@@ -188,7 +189,7 @@ struct StageEvents {
 enum ProfKind {
     PK_SUM32_RHS = 0, PK_SUM32_MATVEC = 1, PK_SUM32_EVAL = 2,
     PK_SUM64 = 3, PK_GMRES_ORTH = 4, PK_BEM_ASSEMBLE = 5, PK_ZGEMV = 6, PK_OTHER = 7,
-    PK_KMATVEC = 8
+    PK_KMATVEC = 8, PK_SYM32_MATVEC = 9
 };
 // Start/stop events of one timed launch (null when profiling is off).  The
 // events ride on the dispatch packets of the first and last kernel of the
@@ -324,7 +325,9 @@ struct InstDev {
 struct SysDev {
     int32_t inst, n, q, nch;           // instance, unknowns, queries, Arnoldi row chunks
     int32_t nsplit_a, nsplit_b;
-    int32_t nsplit_mv, pad_mv;         // split partials of the GMRES matvec (1: assembled)
+    int32_t nsplit_mv;                 // split partials of the GMRES matvec (1: assembled)
+    int32_t mv_pair;                   // 1: they are plain FP32 sums, float2 at 2 off_pa
+                                       //    (symmetric form); 0: (hi, lo) float4 at off_pa
     int64_t off_k;                     // assembled operator [n][n] float2, or -1 (matrix-free)
     int64_t off_n;                     // [n]-long per-system arrays
     int64_t off_q;                     // [q]-long per-system arrays
@@ -358,6 +361,32 @@ struct Sum32Batch {
     const int32_t* active;             // per system, or null
     float4* partial;                   // split partials (hi.re, hi.im, lo.re, lo.im)
 };
+
+// Symmetric form of the matvec sum: each unordered pair of 64-sample
+// sub-tiles (P <= Q) of an instance is one wave's work item for up to 8
+// systems; items of the diagonal pairs (T of them for T sub-tiles) come
+// first, then the T (T - 1) / 2 others.  Every target receives one partial
+// per sub-tile of its instance (slot = that sub-tile).
+struct SymGroupDev {
+    int32_t inst, nm;
+    int64_t d0, o0;                    // first diagonal / off-diagonal item
+    int32_t sys[8];
+};
+struct SymBatch {
+    const InstDev* inst;
+    const SysDev* sys;
+    const SymGroupDev* groups;
+    const int32_t* n_groups;           // device counts
+    const int64_t* n_items;            // [2]: diagonal, off-diagonal items
+    const float2* b32;
+    const int32_t* active;
+    float4* partial;
+};
+// workgroups (of 4 independent waves) of the symmetric matvec launch
+constexpr int32_t kGridSym = 2048;
+// wave items below which the symmetric form narrows its mode groups
+constexpr int64_t kSymFillItems = 4096;
+hipError_t launch_sym32(const SymBatch& p, int32_t grid, hipStream_t s, const ProfSlot& ev = ProfSlot());
 
 // The GMRES matvec of the systems with an assembled operator K (off_k >= 0):
 // for the listed (system, 256-row chunk) items of running systems,
@@ -455,6 +484,12 @@ struct BatchTables {
     GroupDev* d_groups_mv = nullptr;
     int32_t* d_ngroups_mv = nullptr;
     int64_t* d_nitems_mv = nullptr;
+    // ... and of the instances whose matvec takes the symmetric form
+    std::vector<uint8_t> sym;        // per instance
+    bool any_sym = false, any_ordered = false;
+    SymGroupDev* d_groups_sym = nullptr;
+    int32_t* d_ngroups_sym = nullptr;
+    int64_t* d_nitems_sym = nullptr;  // [2]
     int2* d_items = nullptr;
     int32_t* d_nitems = nullptr;
     int32_t* d_iter = nullptr;

@@ -25,15 +25,18 @@ inline void cpu_relax() { __builtin_ia32_pause(); }
 
 struct Staging {
     GroupDev* groups;
+    SymGroupDev* sgroups;
     int2* items;
-    int32_t* c32;  // [0] Arnoldi items, [1] matvec groups
-    int64_t* c64;  // [0] matvec work items
+    int32_t* c32;  // [0] Arnoldi items, [1] matvec groups, [2] symmetric groups
+    int64_t* c64;  // [0] matvec work items, [1, 2] symmetric diagonal / other items
 };
 
 struct ListStats {
     int32_t running = 0;
     int64_t mv_items = 0;
-    double mv_pairs = 0.0;  // target-source pairs of one matrix-free matvec
+    int64_t sym_items = 0;
+    double mv_pairs = 0.0;  // target-source pairs of one ordered matvec
+    double sym_pairs = 0.0; // ... of one symmetric matvec (ordered pairs)
     double kmv_pairs = 0.0; // ... of one matvec from assembled operators
 };
 
@@ -43,57 +46,110 @@ nat_status refresh_lists(const BatchTables& T, const volatile int32_t* flag, boo
                          const Staging& st, hipStream_t s, ListStats* out)
 {
     ListStats ls;
-    int32_t n_items = 0, n_groups = 0;
+    int32_t n_items = 0, n_groups = 0, n_sgroups = 0;
+    int64_t sym_diag = 0, sym_off = 0;
     const int32_t S = static_cast<int32_t>(T.sys.size());
     for (int32_t q = 0; q < S; ++q) {
         if (!flag[q])
             continue;
         ++ls.running;
+        const double pairs = (double)T.sys[q].n * (double)T.sys[q].n;
         if (T.sys[q].off_k >= 0)
-            ls.kmv_pairs += (double)T.sys[q].n * (double)T.sys[q].n;
+            ls.kmv_pairs += pairs;
+        else if ((size_t)T.sys[q].inst < T.sym.size() && T.sym[T.sys[q].inst])
+            ls.sym_pairs += pairs;
         else
-            ls.mv_pairs += (double)T.sys[q].n * (double)T.sys[q].n;
+            ls.mv_pairs += pairs;
         for (int32_t c = 0; c < T.sys[q].nch; ++c)
             st.items[n_items++] = make_int2(q, c);
     }
+    // Mode-group width of the symmetric form: 8, unless the batch then has
+    // too few wave items to fill the chip; narrower groups multiply the items
+    // (each system's arithmetic does not depend on the grouping).
+    int32_t sym_width = 8;
+    if (with_mv && T.any_sym) {
+        std::vector<int32_t> running(T.inst.size(), 0);
+        for (int32_t q = 0; q < S; ++q)
+            if (flag[q] && T.sys[q].off_k < 0)
+                ++running[T.sys[q].inst];
+        while (sym_width > 1) {
+            int64_t items = 0;
+            for (size_t ii = 0; ii < T.inst.size(); ++ii) {
+                if (!T.sym[ii] || running[ii] == 0)
+                    continue;
+                const int64_t t64 = (T.inst[ii].n + 63) / 64;
+                items += (int64_t)((running[ii] + sym_width - 1) / sym_width) * (t64 * (t64 + 1) / 2);
+            }
+            if (items >= kSymFillItems)
+                break;
+            sym_width >>= 1;
+        }
+    }
     if (with_mv) {
-        for (const InstDev& I : T.inst) {
+        for (size_t ii = 0; ii < T.inst.size(); ++ii) {
+            const InstDev& I = T.inst[ii];
+            const bool sym = T.sym[ii] != 0;
+            const int32_t width = sym ? sym_width : 8;
+            const int32_t t64 = (I.n + 63) / 64;
+            const int64_t n_diag = t64, n_off = (int64_t)t64 * (t64 - 1) / 2;
             GroupDev G{};
-            G.nm = 0;
+            SymGroupDev Y{};
+            int32_t nm = 0;
+            auto flush = [&]() {
+                if (nm == 0)
+                    return;
+                if (sym) {
+                    Y.nm = nm;
+                    st.sgroups[n_sgroups++] = Y;
+                    sym_diag += n_diag;
+                    sym_off += n_off;
+                } else {
+                    G.nm = nm;
+                    st.groups[n_groups++] = G;
+                    ls.mv_items += (int64_t)G.tiles * G.nsplit;
+                }
+                nm = 0;
+            };
             for (int32_t m = 0; m < I.n_modes; ++m) {
                 const int32_t q = I.sys0 + m;
                 if (!flag[q] || T.sys[q].off_k >= 0)
                     continue;
-                if (G.nm == 0) {
-                    G.inst = T.sys[q].inst;
+                if (nm == 0) {
+                    G.inst = Y.inst = static_cast<int32_t>(ii);
                     G.tiles = target_tiles(I.n);
                     G.nsplit = I.nsplit_a;
                     G.item0 = ls.mv_items;
+                    Y.d0 = sym_diag;
+                    Y.o0 = sym_off;
                 }
-                G.sys[G.nm++] = q;
-                if (G.nm == 8) {
-                    st.groups[n_groups++] = G;
-                    ls.mv_items += (int64_t)G.tiles * G.nsplit;
-                    G.nm = 0;
-                }
+                G.sys[nm] = Y.sys[nm] = q;
+                if (++nm == width)
+                    flush();
             }
-            if (G.nm > 0) {
-                st.groups[n_groups++] = G;
-                ls.mv_items += (int64_t)G.tiles * G.nsplit;
-            }
+            flush();
         }
     }
+    ls.sym_items = sym_diag + sym_off;
     st.c32[0] = n_items;
     st.c32[1] = n_groups;
+    st.c32[2] = n_sgroups;
     st.c64[0] = ls.mv_items;
+    st.c64[1] = sym_diag;
+    st.c64[2] = sym_off;
     if (ls.running > 0) {
         NAT_HIP(hipMemcpyAsync(T.d_items, st.items, sizeof(int2) * n_items, hipMemcpyHostToDevice, s));
         NAT_HIP(hipMemcpyAsync(T.d_nitems, st.c32, sizeof(int32_t), hipMemcpyHostToDevice, s));
-        if (with_mv) {
+        if (with_mv && T.any_ordered) {
             NAT_HIP(hipMemcpyAsync(T.d_groups_mv, st.groups, sizeof(GroupDev) * n_groups,
                                    hipMemcpyHostToDevice, s));
             NAT_HIP(hipMemcpyAsync(T.d_ngroups_mv, st.c32 + 1, sizeof(int32_t), hipMemcpyHostToDevice, s));
             NAT_HIP(hipMemcpyAsync(T.d_nitems_mv, st.c64, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        }
+        if (with_mv && T.any_sym) {
+            NAT_HIP(hipMemcpyAsync(T.d_groups_sym, st.sgroups, sizeof(SymGroupDev) * n_sgroups,
+                                   hipMemcpyHostToDevice, s));
+            NAT_HIP(hipMemcpyAsync(T.d_ngroups_sym, st.c32 + 2, sizeof(int32_t), hipMemcpyHostToDevice, s));
+            NAT_HIP(hipMemcpyAsync(T.d_nitems_sym, st.c64 + 1, 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
         }
     }
     *out = ls;
@@ -109,17 +165,19 @@ void append_bytes(std::vector<unsigned char>& v, const T& x)
 
 // The run of kLag iterations as an executable graph, captured once per
 // distinct set of launch arguments and kept by the context.
-nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch& mv,
-                        const KmvBatch* kmv, int32_t grid_g, int32_t grid_mv, int32_t grid_k,
-                        hipGraphExec_t* exec)
+nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch* mv, const SymBatch* sym,
+                        const KmvBatch* kmv, int32_t grid_g, int32_t grid_mv, int32_t grid_sym,
+                        int32_t grid_k, hipGraphExec_t* exec)
 {
     NatScratch& sc = scratch_of(ctx);
     std::vector<unsigned char> key;
     append_bytes(key, g);
-    append_bytes(key, mv);
+    append_bytes(key, mv ? *mv : Sum32Batch{});
+    append_bytes(key, sym ? *sym : SymBatch{});
     append_bytes(key, kmv ? *kmv : KmvBatch{});
     append_bytes(key, grid_g);
     append_bytes(key, grid_mv);
+    append_bytes(key, grid_sym);
     append_bytes(key, grid_k);
     if (sc.graph_exec && key == sc.graph_key) {
         *exec = sc.graph_exec;
@@ -136,7 +194,10 @@ nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch& mv,
     NAT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int32_t r = 0; r < kLag && e == hipSuccess; ++r) {
-        e = launch_sum32_batch(OP_MATVEC, mv, grid_mv, cs);
+        if (mv)
+            e = launch_sum32_batch(OP_MATVEC, *mv, grid_mv, cs);
+        if (e == hipSuccess && sym)
+            e = launch_sym32(*sym, grid_sym, cs);
         if (e == hipSuccess && kmv)
             e = launch_kmatvec32(*kmv, grid_k, cs);
         if (e == hipSuccess)
@@ -184,12 +245,23 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
     g.items = T.d_items;
     g.n_items = T.d_nitems;
     g.iter = T.d_iter;
+    SymBatch sym{};
     if (mv) {
         mv->groups = T.d_groups_mv;
         mv->n_groups = T.d_ngroups_mv;
         mv->n_items = T.d_nitems_mv;
         mv->active = g.active;
+        sym.inst = mv->inst;
+        sym.sys = mv->sys;
+        sym.groups = T.d_groups_sym;
+        sym.n_groups = T.d_ngroups_sym;
+        sym.n_items = T.d_nitems_sym;
+        sym.b32 = mv->b32;
+        sym.active = g.active;
+        sym.partial = mv->partial;
     }
+    const Sum32Batch* mv_ord = mv && T.any_ordered ? mv : nullptr;
+    const SymBatch* mv_sym = mv && T.any_sym ? &sym : nullptr;
     if (kmv) {
         kmv->items = T.d_items;
         kmv->n_items = T.d_nitems;
@@ -197,7 +269,8 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
     }
 
     // two pinned staging areas for the lists, used alternately
-    const size_t per = ((sizeof(GroupDev) * (size_t)S + sizeof(int2) * (size_t)T.max_items + 255) & ~size_t(255)) + 256;
+    const size_t per = ((sizeof(GroupDev) * (size_t)S + sizeof(SymGroupDev) * (size_t)S +
+                         sizeof(int2) * (size_t)T.max_items + 255) & ~size_t(255)) + 256;
     void* pin = nullptr;
     st = pinned(ctx, 2 * per, &pin);
     if (st != NAT_OK)
@@ -208,7 +281,8 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
         stg[k].c32 = reinterpret_cast<int32_t*>(base);
         stg[k].c64 = reinterpret_cast<int64_t*>(base + 64);
         stg[k].groups = reinterpret_cast<GroupDev*>(base + 128);
-        stg[k].items = reinterpret_cast<int2*>(base + 128 + sizeof(GroupDev) * (size_t)S);
+        stg[k].sgroups = reinterpret_cast<SymGroupDev*>(base + 128 + sizeof(GroupDev) * (size_t)S);
+        stg[k].items = reinterpret_cast<int2*>(base + 128 + (sizeof(GroupDev) + sizeof(SymGroupDev)) * (size_t)S);
     }
     ListStats ls;
     st = refresh_lists(T, hflag, mv != nullptr, stg[0], s, &ls);
@@ -219,9 +293,19 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
     const int32_t grid_g = static_cast<int32_t>(T.max_items < kGridArnoldi ? (T.max_items > 0 ? T.max_items : 1) : kGridArnoldi);
     const int32_t grid_mv = static_cast<int32_t>(ls.mv_items < kMaxGrid ? (ls.mv_items > 0 ? ls.mv_items : 1) : kMaxGrid);
     const int32_t grid_k = static_cast<int32_t>(T.max_items < kGridKmv ? (T.max_items > 0 ? T.max_items : 1) : kGridKmv);
+    // persistent grid of the symmetric form sized for its finest grouping
+    int64_t sym_max_items = 0;
+    for (size_t ii = 0; ii < T.inst.size(); ++ii) {
+        if (T.sym.size() > ii && T.sym[ii]) {
+            const int64_t t64 = (T.inst[ii].n + 63) / 64;
+            sym_max_items += (int64_t)T.inst[ii].n_modes * (t64 * (t64 + 1) / 2);
+        }
+    }
+    const int64_t sym_blocks = (sym_max_items + 3) / 4;
+    const int32_t grid_sym = static_cast<int32_t>(sym_blocks < kGridSym ? (sym_blocks > 0 ? sym_blocks : 1) : kGridSym);
     hipGraphExec_t exec = nullptr;
     if (use_graph && mv && !ctx->prof) {
-        st = captured_run(ctx, g, *mv, kmv, grid_g, grid_mv, grid_k, &exec);
+        st = captured_run(ctx, g, mv_ord, mv_sym, kmv, grid_g, grid_mv, grid_sym, grid_k, &exec);
         if (st != NAT_OK)
             exec = nullptr;  // fall back to direct launches
     }
@@ -233,10 +317,13 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
             launched += kLag;
         } else {
             for (int32_t r = 0; r < kLag && launched < g.mmax; ++r) {
-                if (mv)
-                    NAT_HIP(launch_sum32_batch(OP_MATVEC, *mv, grid_mv, s,
+                if (mv_ord)
+                    NAT_HIP(launch_sum32_batch(OP_MATVEC, *mv_ord, grid_mv, s,
                                                prof_slot(ctx, PK_SUM32_MATVEC, 37.0 * ls.mv_pairs)));
-                else
+                if (mv_sym)
+                    NAT_HIP(launch_sym32(*mv_sym, grid_sym, s,
+                                         prof_slot(ctx, PK_SYM32_MATVEC, 37.0 * ls.sym_pairs)));
+                if (!mv)
                     NAT_HIP(eager_mv(launched));
                 if (kmv)
                     NAT_HIP(launch_kmatvec32(*kmv, grid_k, s,
@@ -281,7 +368,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: layout %d", opts->layout);
     if (!(opts->eps_scale > 0.0) || !is_finite(opts->eps_scale) || !(opts->gmres_tol > 0.0) ||
         opts->gmres_max_iter < 1 || opts->gmres_max_iter > 1000 ||
-        (opts->flags & ~(NAT_MC_NO_GRAPH | NAT_MC_ASSEMBLED | NAT_MC_MATRIX_FREE | NAT_MC_EXACT_DISK)) ||
+        (opts->flags & ~(NAT_MC_NO_GRAPH | NAT_MC_ASSEMBLED | NAT_MC_MATRIX_FREE | NAT_MC_EXACT_DISK |
+                         NAT_MC_ORDERED_SUM)) ||
         ((opts->flags & NAT_MC_ASSEMBLED) && (opts->flags & NAT_MC_MATRIX_FREE)))
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: bad solver options");
     if (opts->jump != NAT_JUMP_HALF && opts->jump != NAT_JUMP_POLYHEDRAL)
@@ -322,6 +410,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     BatchTables T;
     T.inst.resize(nj);
     T.sys.resize(S);
+    T.sym.assign(nj, 0);
     size_t inst_n = 0, inst_q = 0;       // sums of n and q over instances
     int64_t sum_n = 0, sum_q = 0, sum_v = 0, sum_ch = 0, sum_pa = 0, sum_pb = 0, sum_k = 0;
     std::vector<int32_t> asm_list;  // systems whose matvec reads an assembled operator
@@ -349,6 +438,15 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         const bool asm_form = fp32 && ((opts->flags & NAT_MC_ASSEMBLED) ||
                                        (!(opts->flags & NAT_MC_MATRIX_FREE) &&
                                         ctx->tune.assembled[tune_bucket(J.N)]));
+        // matrix-free matvec: symmetric (one partial per 64-sample sub-tile)
+        // or ordered (the instance's source splits)
+        const bool sym_form = fp32 && !asm_form && !(opts->flags & NAT_MC_ORDERED_SUM) &&
+                              ctx->tune.symmetric[tune_bucket(J.N)];
+        T.sym[i] = sym_form ? 1 : 0;
+        if (fp32 && !asm_form) {
+            T.any_sym = T.any_sym || sym_form;
+            T.any_ordered = T.any_ordered || !sym_form;
+        }
         inst_n += J.N;
         inst_q += J.Q;
         max_n = J.N > max_n ? J.N : max_n;
@@ -361,7 +459,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
             Y.nch = gmres_chunks(J.N);
             Y.nsplit_a = I.nsplit_a;
             Y.nsplit_b = J.Q > 0 ? I.nsplit_b : 0;
-            Y.nsplit_mv = asm_form ? 1 : I.nsplit_a;
+            Y.nsplit_mv = asm_form ? 1 : (sym_form ? (J.N + 63) / 64 : I.nsplit_a);
+            Y.mv_pair = sym_form ? 1 : 0;
             Y.off_k = asm_form ? sum_k : -1;
             if (asm_form) {
                 sum_k += (int64_t)J.N * J.N;
@@ -390,7 +489,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
             sum_q += J.Q;
             sum_v += (int64_t)mm1 * J.N;
             sum_ch += Y.nch;
-            sum_pa += (int64_t)Y.nsplit_a * J.N;
+            sum_pa += (int64_t)(Y.nsplit_a > Y.nsplit_mv ? Y.nsplit_a : Y.nsplit_mv) * J.N;
             sum_pb += (int64_t)Y.nsplit_b * J.Q;
         }
     }
@@ -410,6 +509,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
          sizeof(double) * sum_ch, sizeof(double) * sum_ch, sizeof(double) * sum_ch,
          sizeof(double2) * S * gram_stride, sizeof(float4) * n_part, sizeof(InstDev) * nj,
          sizeof(SysDev) * S, sizeof(GroupDev) * S, sizeof(GroupDev) * S, sizeof(GroupDev) * S,
+         sizeof(SymGroupDev) * S,
          sizeof(int2) * sum_ch, sizeof(double) * S, sizeof(double2) * S, sizeof(int64_t) * 8,
          sizeof(SurfJob) * nj,
          polyhedral ? sizeof(double) * inst_q : 0, sizeof(float2) * sum_k,
@@ -423,7 +523,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     if (st != NAT_OK)
         return st;
     Carver cv(ws);
-    int32_t* dcnt = cv.take<int32_t>(8);  // flags [0,1], n_items, n_groups_mv, iter, n_groups rhs/eval
+    int32_t* dcnt = cv.take<int32_t>(8);  // flags [0,1], n_items, n_groups_mv, iter, n_groups rhs/eval/sym
     int32_t* tri_all = cv.take<int32_t>(inst_n);
     double* bary_all = cv.take<double>(2 * inst_n);
     double* x64_all = cv.take<double>(3 * inst_n);
@@ -466,10 +566,11 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     GroupDev* d_groups_rhs = cv.take<GroupDev>(S);
     GroupDev* d_groups_eval = cv.take<GroupDev>(S);
     T.d_groups_mv = cv.take<GroupDev>(S);
+    T.d_groups_sym = cv.take<SymGroupDev>(S);
     T.d_items = cv.take<int2>(sum_ch);
     double* dk = cv.take<double>(S);
     double2* ddisk = cv.take<double2>(S);
-    int64_t* dcnt64 = cv.take<int64_t>(8);  // items: [0] rhs, [1] eval, [2] matvec
+    int64_t* dcnt64 = cv.take<int64_t>(8);  // items: [0] rhs, [1] eval, [2] matvec, [4,5] sym
     SurfJob* d_surf = cv.take<SurfJob>(nj);
     double* qfac_all = polyhedral ? cv.take<double>(inst_q) : nullptr;
     float2* kmat = sum_k > 0 ? cv.take<float2>(sum_k) : nullptr;
@@ -478,6 +579,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     T.d_ngroups_mv = dcnt + 3;
     T.d_iter = dcnt + 4;
     T.d_nitems_mv = dcnt64 + 2;
+    T.d_ngroups_sym = dcnt + 7;
+    T.d_nitems_sym = dcnt64 + 4;
     g.sys = T.d_sys;
     g.v32 = fp32 ? v32 : nullptr;
     g.partial = fp32 ? partial : nullptr;

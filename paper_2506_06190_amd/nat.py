@@ -34,6 +34,7 @@ NAT_MC_NO_GRAPH = 1
 NAT_MC_ASSEMBLED = 2
 NAT_MC_MATRIX_FREE = 4
 NAT_MC_EXACT_DISK = 8
+NAT_MC_ORDERED_SUM = 16
 NAT_JUMP_HALF = 0
 NAT_JUMP_POLYHEDRAL = 1
 NAT_TUNE_FORCE = 1
