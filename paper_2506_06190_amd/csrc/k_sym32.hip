@@ -170,6 +170,26 @@ __device__ __forceinline__ void sym_item(const SymBatch& p, const InstDev& I, co
     }
 }
 
+// One item with the group width as a compile-time constant, so no padded
+// mode costs work.
+template <bool RED>
+__device__ __forceinline__ void dispatch_item(const SymBatch& p, const InstDev& I, const int32_t (&sys)[kMB],
+                                              int32_t nm, const float (&kap)[kMB], const float (&kk)[kMB],
+                                              int32_t P, int32_t Q, const float (&sp)[6][64],
+                                              const float2 (&sd)[kMB][64])
+{
+    switch (nm) {
+    case 8: sym_item<8, RED>(p, I, sys, nm, kap, kk, P, Q, sp, sd); break;
+    case 7: sym_item<7, RED>(p, I, sys, nm, kap, kk, P, Q, sp, sd); break;
+    case 6: sym_item<6, RED>(p, I, sys, nm, kap, kk, P, Q, sp, sd); break;
+    case 5: sym_item<5, RED>(p, I, sys, nm, kap, kk, P, Q, sp, sd); break;
+    case 4: sym_item<4, RED>(p, I, sys, nm, kap, kk, P, Q, sp, sd); break;
+    case 3: sym_item<3, RED>(p, I, sys, nm, kap, kk, P, Q, sp, sd); break;
+    case 2: sym_item<2, RED>(p, I, sys, nm, kap, kk, P, Q, sp, sd); break;
+    default: sym_item<1, RED>(p, I, sys, nm, kap, kk, P, Q, sp, sd); break;
+    }
+}
+
 // 5 waves per SIMD (at most 102 VGPRs): measured faster than 4 or 6 on the
 // batched workload, with no extra instructions in the step loop
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 5))) k_sym32(const SymBatch p)
@@ -248,25 +268,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 5))
         __builtin_amdgcn_wave_barrier();
         {
             const bool red = __builtin_amdgcn_readfirstlane(I.phase_fract) != 0;
-            if (red) {
-                if (nm > 4)
-                    sym_item<8, true>(p, I, sys, nm, kap, kk, P, Q, s_pos[wave], s_dat[wave]);
-                else if (nm > 2)
-                    sym_item<4, true>(p, I, sys, nm, kap, kk, P, Q, s_pos[wave], s_dat[wave]);
-                else if (nm > 1)
-                    sym_item<2, true>(p, I, sys, nm, kap, kk, P, Q, s_pos[wave], s_dat[wave]);
-                else
-                    sym_item<1, true>(p, I, sys, nm, kap, kk, P, Q, s_pos[wave], s_dat[wave]);
-            } else {
-                if (nm > 4)
-                    sym_item<8, false>(p, I, sys, nm, kap, kk, P, Q, s_pos[wave], s_dat[wave]);
-                else if (nm > 2)
-                    sym_item<4, false>(p, I, sys, nm, kap, kk, P, Q, s_pos[wave], s_dat[wave]);
-                else if (nm > 1)
-                    sym_item<2, false>(p, I, sys, nm, kap, kk, P, Q, s_pos[wave], s_dat[wave]);
-                else
-                    sym_item<1, false>(p, I, sys, nm, kap, kk, P, Q, s_pos[wave], s_dat[wave]);
-            }
+            if (red)
+                dispatch_item<true>(p, I, sys, nm, kap, kk, P, Q, s_pos[wave], s_dat[wave]);
+            else
+                dispatch_item<false>(p, I, sys, nm, kap, kk, P, Q, s_pos[wave], s_dat[wave]);
         }
     }
 }

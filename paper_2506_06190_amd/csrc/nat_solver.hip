@@ -122,7 +122,10 @@ nat_status refresh_lists(const BatchTables& T, const volatile int32_t* flag, boo
                     Y.d0 = sym_diag;
                     Y.o0 = sym_off;
                 }
-                G.sys[nm] = Y.sys[nm] = q;
+                if (sym)
+                    Y.sys[nm] = q;
+                else
+                    G.sys[nm] = q;
                 if (++nm == width)
                     flush();
             }
