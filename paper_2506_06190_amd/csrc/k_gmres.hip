@@ -23,7 +23,8 @@
 //   dots      w formed from the FP32 matvec partials when there are any, then
 //             partial <v_i, w> and <v_i, v_j> over the chunk's rows, and the
 //             partial |w|^2
-//   coef      (first chunk) the Gram column of v_j and h = s - (G - I) s
+//   coef      the Gram column of v_j and h = s - (G - I) s, one 64-row
+//             block of h per item, the sum over k split between 4 waves
 //   update    w -= V h on the chunk's rows, partial |w|^2
 //   dots2     (only after strong cancellation) partial <v_i, w>
 //   update2   (same) w -= V h2, h += h2, partial |w|^2
@@ -271,21 +272,27 @@ __global__ void __launch_bounds__(kRows) k_orth_dots(GmresBatch g)
     }
 }
 
-// First chunk of each system: s = V^H w and the new Gram column V^H v_j from
-// the chunk partials, then h = s - (G - I) s into the Hessenberg column.
+// s = V^H w and the new Gram column V^H v_j from the chunk partials, then
+// h = s - (G - I) s into the Hessenberg column: item (system, chunk c)
+// takes the 64-row blocks b = c, c + nch, ... of h; in a block lane l owns
+// row 64 b + l and wave q sums the columns k = q, q + 4, ... of G; the four
+// partial sums are added in wave order.
 __global__ void __launch_bounds__(kRows) k_orth_coef(GmresBatch g)
 {
     extern __shared__ double2 s_sv[];  // [mmax + 1] s | [mmax + 1] Gram column j
+    __shared__ double2 s_part[kRowWaves][64];
     const int32_t j = *g.iter;
     const int32_t n_items = *g.n_items;
     if (j >= g.mmax)
         return;
     const int mm1 = g.mmax + 1;
+    const int32_t n_blk = (j + 64) / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double2* s_gj = s_sv + mm1;
     for (int32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 item = g.items[it];
         const int32_t s = item.x, chunk = item.y;
-        if (chunk != 0 || !g.active[s])
+        if (chunk >= n_blk || !g.active[s])
             continue;
         const SysDev& S = g.sys[s];
         // the full Hermitian G, column-major with leading dimension mmax + 1:
@@ -294,45 +301,58 @@ __global__ void __launch_bounds__(kRows) k_orth_coef(GmresBatch g)
         __syncthreads();
         for (int i = threadIdx.x; i <= j; i += kRows) {
             s_sv[i] = chunk_sum(g.dp1 + S.off_ch * mm1, S.nch, mm1, i);
-            const double2 gij = chunk_sum(g.dp2 + S.off_ch * mm1, S.nch, mm1, i);
-            s_gj[i] = gij;
-            G[(size_t)j * mm1 + i] = gij;
-            if (i < j)
-                G[(size_t)i * mm1 + j] = make_double2(gij.x, -gij.y);
+            s_gj[i] = chunk_sum(g.dp2 + S.off_ch * mm1, S.nch, mm1, i);
         }
         __syncthreads();
         double2* ht = g.htot + (size_t)s * mm1;
-        for (int i = threadIdx.x; i <= j; i += kRows) {
-            // (G - I) s, row i, in k order: entry (i, k) is column k's row i
-            // (loads coalesced across the rows), column j from LDS.  Groups
-            // of 8 entries are loaded together.
+        for (int32_t blk = chunk; blk < n_blk; blk += S.nch) {
+            const int i = 64 * blk + lane;
+            // (G - I) s, row i: entry (i, k) is column k's row i (loads
+            // coalesced across the lanes), column j and row j from LDS
             double er = 0.0, ei = 0.0;
-            for (int k0 = 0; k0 <= j; k0 += 8) {
-                double2 gk[8];
+            if (i <= j) {
+                for (int k0 = wave; k0 <= j; k0 += 8 * kRowWaves) {
+                    double2 gk[8];
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    const int k = k0 + c;
-                    if (k >= j)
-                        gk[c] = k == j ? s_gj[i] : make_double2(0.0, 0.0);
-                    else if (i == j)
-                        gk[c] = make_double2(s_gj[k].x, -s_gj[k].y);
-                    else
-                        gk[c] = G[(size_t)k * mm1 + i];
-                }
+                    for (int c = 0; c < 8; ++c) {
+                        const int k = k0 + kRowWaves * c;
+                        if (k >= j)
+                            gk[c] = k == j ? s_gj[i] : make_double2(0.0, 0.0);
+                        else if (i == j)
+                            gk[c] = make_double2(s_gj[k].x, -s_gj[k].y);
+                        else
+                            gk[c] = G[(size_t)k * mm1 + i];
+                    }
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    const int k = k0 + c;
-                    if (k <= j) {
-                        double2 gik = gk[c];
-                        if (k == i)
-                            gik.x -= 1.0;
-                        const double2 d = cmul(gik, s_sv[k]);
-                        er += d.x;
-                        ei += d.y;
+                    for (int c = 0; c < 8; ++c) {
+                        const int k = k0 + kRowWaves * c;
+                        if (k <= j) {
+                            double2 gik = gk[c];
+                            if (k == i)
+                                gik.x -= 1.0;
+                            const double2 d = cmul(gik, s_sv[k]);
+                            er += d.x;
+                            ei += d.y;
+                        }
                     }
                 }
             }
-            ht[i] = make_double2(s_sv[i].x - er, s_sv[i].y - ei);
+            s_part[wave][lane] = make_double2(er, ei);
+            __syncthreads();
+            if (wave == 0 && i <= j) {
+                double tr = 0.0, ti = 0.0;
+#pragma unroll
+                for (int q = 0; q < kRowWaves; ++q) {
+                    tr += s_part[q][lane].x;
+                    ti += s_part[q][lane].y;
+                }
+                ht[i] = make_double2(s_sv[i].x - tr, s_sv[i].y - ti);
+                const double2 gij = s_gj[i];
+                G[(size_t)j * mm1 + i] = gij;
+                if (i < j)
+                    G[(size_t)i * mm1 + j] = make_double2(gij.x, -gij.y);
+            }
+            __syncthreads();
         }
     }
 }
