@@ -61,6 +61,13 @@ def roofline_from(prof, peak=FP32_VECTOR_PEAK_TFLOPS):
             "flops_per_launch": dom["flops"] / dom["launches"]}
 
 
+def auto_parts(wls):
+    """The part count nat_mcbem_estimate_batch picks for n_streams = 0: one part
+    per 2e10 pair terms (M N (31 N + Q) per job), at most 4, at most one per job."""
+    work = sum(w.n_modes * w.n_samples * (31.0 * w.n_samples + w.n_queries) for w in wls)
+    return int(min(4, len(wls), max(1, work // 2e10)))
+
+
 def run_batched(nat, torch, ctx, args, dev):
     import numpy as np
     import workloads as W
@@ -85,15 +92,19 @@ def run_batched(nat, torch, ctx, args, dev):
     n_s = np.array([w.n_samples for w in wls for _ in range(w.n_modes)], dtype=np.float64)
     executed = float(np.sum(n_s * n_s) + sum(w.n_modes * w.n_queries * w.n_samples for w in wls)
                      + np.sum(iters * n_s * n_s))
-    # roofline pass: the same steps with events on the kernel dispatches
+    # roofline pass: the same steps with events on the kernel dispatches, on
+    # one stream (so no other part's kernels share the GPU with the one timed)
+    opts1 = nat.nat_mc_opts_default()
+    opts1.n_streams = 1
     nat.nat_profile_enable(ctx, True)
     for _ in range(args.steps):
-        nat.nat_mcbem_estimate_batch(ctx, jobs, opts, allow_noconv=True)
+        nat.nat_mcbem_estimate_batch(ctx, jobs, opts1, allow_noconv=True)
     torch.cuda.synchronize()
     prof = nat.nat_profile_read(ctx)
     nat.nat_profile_enable(ctx, False)
     roof = roofline_from(prof)
-    roof["timing_pass"] = "second pass over the same steps, eager dispatch, events on each dispatch"
+    roof["timing_pass"] = ("second pass over the same steps, one stream (n_streams = 1), eager "
+                           "dispatch, events on each dispatch")
     kern = roof["kernel"].split()[0]
     roof["traffic"] = traffic_from_profile(kern) if kern in MATVEC else None
     valu = valu_from_profile(kern) if kern in MATVEC else None
@@ -107,6 +118,7 @@ def run_batched(nat, torch, ctx, args, dev):
                    "instances": len(wls), "systems": int(len(iters)),
                    "triangles_total": int(sum(len(w.tris) for w in wls)),
                    "algorithmic_pair_evals_per_step": alg, "form": "FP32 compensated, graph-replayed GMRES",
+                   "n_streams": f"automatic: {auto_parts(wls)} concurrent parts",
                    "gmres_tol": 1e-6, "gmres_max_iter": 200},
         "executed_pair_evals_per_s": executed * args.steps / elapsed,
         "gmres_iters": {"mean": float(iters.mean()), "p50": float(np.median(iters)),
@@ -341,6 +353,7 @@ def run_pmc_pass(nat, torch, ctx, args, dev):
     meshes, jobs = make_jobs(nat, torch, ctx, wls, dev)
     opts = nat.nat_mc_opts_default()
     opts.flags = nat.NAT_MC_NO_GRAPH | (nat.NAT_MC_ORDERED_SUM if args.ordered else 0)
+    opts.n_streams = 1
     nat.nat_mcbem_estimate_batch(ctx, jobs, opts, allow_noconv=True)
     torch.cuda.synchronize()
     for m in meshes:

@@ -89,8 +89,21 @@ typedef struct {
     int32_t gmres_max_iter; /* 1 .. 1000                                             */
     int32_t flags;          /* NAT_MC_* bits                                         */
     int32_t jump;           /* nat_jump                                              */
-    int32_t reserved;       /* 0                                                     */
+    int32_t n_streams;      /* nat_mcbem_estimate_batch: parts run concurrently, see
+                             * below; 0 automatic, 1 the caller's stream only, <= 8 */
 } nat_mc_opts;
+
+/* nat_mc_opts.n_streams: nat_mcbem_estimate_batch splits the jobs into up to
+ * this many parts (job i to part i mod the count) and runs each part on a
+ * stream and a host thread of its own, after all work the caller queued on
+ * its stream, which then waits for every part.  One part's GMRES
+ * orthogonalisation, bound by HBM bandwidth, then overlaps another part's
+ * kernel sums, bound by the vector ALUs.  0 picks the count from the batch's
+ * size: one part per 2e10 pair terms (n_modes N (31 N + Q) per job), at most
+ * 4; 1 runs the batch on the caller's stream alone.  The parts' scratch
+ * memory is held by the context until it is destroyed.  Every result is
+ * bitwise the same for any count (a system's arithmetic depends only on its
+ * own sizes). */
 
 /* nat_mc_opts.flags: launch every GMRES kernel directly instead of replaying
  * captured runs of iterations (results are identical). */

@@ -75,6 +75,8 @@ NatScratch& scratch_of(nat_ctx* ctx) { return t_scratch ? *t_scratch : ctx->scra
 
 void bind_scratch(NatScratch* s) { t_scratch = s; }
 
+NatScratch* bound_scratch() { return t_scratch; }
+
 void release_scratch(nat_ctx* ctx, NatScratch& sc)
 {
     if (sc.ws)
@@ -393,7 +395,7 @@ void nat_mc_opts_default(nat_mc_opts* o)
     o->gmres_max_iter = 200;
     o->flags = 0;
     o->jump = NAT_JUMP_HALF;
-    o->reserved = 0;
+    o->n_streams = 0;
 }
 
 nat_status nat_ctx_create(int32_t device, size_t hbm_budget_bytes, nat_ctx** out)
@@ -442,6 +444,15 @@ void nat_ctx_destroy(nat_ctx* ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     nat::release_scratch(ctx, ctx->scratch);
+    for (int l = 0; l < nat_ctx::kMaxLanes; ++l) {
+        nat::release_scratch(ctx, ctx->lane_scratch[l]);
+        if (ctx->lane_stream[l])
+            (void)hipStreamDestroy(ctx->lane_stream[l]);
+        if (ctx->lane_event[l])
+            (void)hipEventDestroy(ctx->lane_event[l]);
+    }
+    if (ctx->lane_fork)
+        (void)hipEventDestroy(ctx->lane_fork);
     if (ctx->d_rules)
         nat::dev_free(ctx, ctx->d_rules, sizeof(double) * 38);
     nat::prof_collect(ctx);

@@ -69,6 +69,7 @@ struct nat_ctx {
     int32_t device = 0;
     nat::TuneTable tune;
     std::mutex mu;       // guards the ledger and the timing lists
+    std::mutex capture_mu;  // one graph capture at a time across a context's threads
     // per-kernel timing (off unless enabled)
     bool prof = false;
     std::vector<NatProfEvent> prof_pending;
@@ -77,6 +78,13 @@ struct nat_ctx {
     size_t budget = 0;   // 0: unlimited
     size_t in_use = 0;   // bytes charged
     NatScratch scratch;
+    // concurrent parts of a batch (nat_mc_opts.n_streams): scratch, stream
+    // and completion event of each part, created on first use
+    static constexpr int kMaxLanes = 8;
+    NatScratch lane_scratch[kMaxLanes];
+    hipStream_t lane_stream[kMaxLanes] = {};
+    hipEvent_t lane_event[kMaxLanes] = {};
+    hipEvent_t lane_fork = nullptr;
     // Gauss-Legendre rules on [0,1] for the dense assembly (device copies)
     double* d_rules = nullptr;
 };
@@ -131,6 +139,7 @@ void dev_free(nat_ctx* ctx, void* ptr, size_t bytes);
 // context's own.
 NatScratch& scratch_of(nat_ctx* ctx);
 void bind_scratch(NatScratch* s);
+NatScratch* bound_scratch();
 void release_scratch(nat_ctx* ctx, NatScratch& s);
 // grow-only scratch; contents undefined on return
 nat_status workspace(nat_ctx* ctx, size_t bytes, void** ptr);

@@ -8,6 +8,8 @@
 // systems, GMRES for all systems in lockstep, and the surface evaluation.
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <thread>
 
 #include "nat_internal.h"
 
@@ -194,6 +196,9 @@ nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch* mv,
     if (!sc.capture_stream)
         NAT_HIP(hipStreamCreateWithFlags(&sc.capture_stream, hipStreamNonBlocking));
     hipStream_t cs = sc.capture_stream;
+    // concurrent parts of a batch capture one at a time (overlapping captures
+    // from several threads have failed on this runtime)
+    std::lock_guard<std::mutex> lk(ctx->capture_mu);
     NAT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int32_t r = 0; r < kLag && e == hipSuccess; ++r) {
@@ -211,6 +216,7 @@ nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch* mv,
     if (e != hipSuccess || e2 != hipSuccess) {
         if (graph)
             (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();  // the caller falls back to direct launches
         return hip_fail(e != hipSuccess ? e : e2, "graph capture of the GMRES iterations");
     }
     hipGraphExec_t ex = nullptr;
@@ -377,6 +383,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: bad solver options");
     if (opts->jump != NAT_JUMP_HALF && opts->jump != NAT_JUMP_POLYHEDRAL)
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: jump %d", opts->jump);
+    if (opts->n_streams < 0 || opts->n_streams > nat_ctx::kMaxLanes)
+        return fail(NAT_E_INVALID, "Monte-Carlo estimate: n_streams %d", opts->n_streams);
     const bool polyhedral = opts->jump == NAT_JUMP_POLYHEDRAL;
     int64_t S64 = 0;
     for (int32_t i = 0; i < nj; ++i) {
@@ -938,6 +946,121 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     return NAT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// A batch as concurrent parts on streams of their own
+// ---------------------------------------------------------------------------
+namespace {
+
+// pair terms of a job: the right-hand side, about 30 GMRES matvecs and the
+// evaluation (sets the automatic part count)
+double job_work(const McJob& J) { return (double)J.M * J.N * (31.0 * J.N + J.Q); }
+// automatic part count: one part per this much work, at most kAutoLanes
+constexpr double kLaneWork = 2e10;
+constexpr int32_t kAutoLanes = 4;
+
+}  // namespace
+
+nat_status run_mc_parts(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts* opts,
+                        nat_solve_report* report, hipStream_t s)
+{
+    size_t bytes = 0;
+    nat_status st = run_mc(ctx, jobs, nj, opts, nullptr, s, &bytes);  // validates every job
+    if (st != NAT_OK)
+        return st;
+    double total = 0.0;
+    for (int32_t i = 0; i < nj; ++i)
+        total += job_work(jobs[i]);
+    int32_t L = opts->n_streams;
+    if (L == 0) {
+        const double want = total / kLaneWork;
+        L = want >= kAutoLanes ? kAutoLanes : (want >= 1.0 ? static_cast<int32_t>(want) : 1);
+    }
+    L = L < nj ? L : nj;
+    if (L <= 1)
+        return run_mc(ctx, jobs, nj, opts, report, s, nullptr);
+
+    // job i goes to part i mod L: every part gets a sample of the batch's
+    // mix (a work estimate without the iteration counts balanced worse)
+    std::vector<std::vector<int32_t>> idx(L);
+    for (int32_t i = 0; i < nj; ++i)
+        idx[i % L].push_back(i);
+    std::vector<int64_t> sys0(nj + 1, 0);  // first report slot of each job
+    for (int32_t i = 0; i < nj; ++i)
+        sys0[i + 1] = sys0[i] + jobs[i].M;
+    st = set_device(ctx);
+    if (st != NAT_OK)
+        return st;
+    if (!ctx->lane_fork)
+        NAT_HIP(hipEventCreateWithFlags(&ctx->lane_fork, hipEventDisableTiming));
+    for (int32_t l = 0; l < L; ++l) {
+        if (!ctx->lane_stream[l])
+            NAT_HIP(hipStreamCreateWithFlags(&ctx->lane_stream[l], hipStreamNonBlocking));
+        if (!ctx->lane_event[l])
+            NAT_HIP(hipEventCreateWithFlags(&ctx->lane_event[l], hipEventDisableTiming));
+    }
+    NAT_HIP(hipEventRecord(ctx->lane_fork, s));
+    std::vector<nat_status> sts(L, NAT_OK);
+    std::vector<std::string> msgs(L);
+    auto part = [&](int32_t l) {
+        NatScratch* prev = bound_scratch();
+        nat_status r = set_device(ctx);
+        if (r == NAT_OK) {
+            bind_scratch(&ctx->lane_scratch[l]);
+            hipStream_t ls = ctx->lane_stream[l];
+            if (hipStreamWaitEvent(ls, ctx->lane_fork, 0) != hipSuccess) {
+                r = fail(NAT_E_HIP, "hipStreamWaitEvent");
+            } else {
+                std::vector<McJob> pj;
+                int64_t ns = 0;
+                for (int32_t i : idx[l]) {
+                    pj.push_back(jobs[i]);
+                    ns += jobs[i].M;
+                }
+                std::vector<nat_solve_report> pr(report ? ns : 0);
+                r = run_mc(ctx, pj.data(), static_cast<int32_t>(pj.size()), opts,
+                           report ? pr.data() : nullptr, ls, nullptr);
+                if (report) {
+                    int64_t q = 0;
+                    for (int32_t i : idx[l])
+                        for (int32_t m = 0; m < jobs[i].M; ++m)
+                            report[sys0[i] + m] = pr[q++];
+                }
+            }
+            if (hipEventRecord(ctx->lane_event[l], ls) != hipSuccess && r == NAT_OK)
+                r = fail(NAT_E_HIP, "hipEventRecord");
+        }
+        if (r != NAT_OK) {
+            char buf[512];
+            nat_last_error(buf, sizeof(buf));
+            msgs[l] = buf;
+        }
+        sts[l] = r;
+        bind_scratch(prev);
+    };
+    std::vector<std::thread> th;
+    th.reserve(L - 1);
+    for (int32_t l = 1; l < L; ++l)
+        th.emplace_back(part, l);
+    part(0);
+    for (std::thread& t : th)
+        t.join();
+    for (int32_t l = 0; l < L; ++l)
+        NAT_HIP(hipStreamWaitEvent(s, ctx->lane_event[l], 0));
+    // a hard error first, else non-convergence, else success
+    int32_t worst = -1;
+    for (int32_t l = 0; l < L; ++l) {
+        if (sts[l] != NAT_OK && sts[l] != NAT_E_NOCONV) {
+            worst = l;
+            break;
+        }
+        if (sts[l] == NAT_E_NOCONV && worst < 0)
+            worst = l;
+    }
+    if (worst < 0)
+        return NAT_OK;
+    return fail(sts[worst], "%s", msgs[worst].c_str());
+}
+
 }  // namespace nat
 
 extern "C" {
@@ -964,7 +1087,9 @@ nat_status nat_mcbem_estimate_batch(nat_ctx* ctx, const nat_mc_job* jobs, int32_
         J[i] = nat::McJob{jobs[i].mesh, jobs[i].v_n, jobs[i].n_modes, jobs[i].n_queries,
                           jobs[i].n_samples, jobs[i].k, jobs[i].q_tri, jobs[i].q_bary,
                           jobs[i].seed, jobs[i].p_out, jobs[i].p_samples};
-    return nat::run_mc(ctx, J.data(), n_jobs, opts, reports, static_cast<hipStream_t>(stream), nullptr);
+    if (!opts)
+        return nat::fail(NAT_E_INVALID, "nat_mcbem_estimate_batch: opts is NULL");
+    return nat::run_mc_parts(ctx, J.data(), n_jobs, opts, reports, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

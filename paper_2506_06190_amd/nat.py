@@ -44,7 +44,7 @@ TUNE_BUCKETS = 10
 class nat_mc_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("layout", C.c_int32), ("eps_scale", C.c_double),
                 ("gmres_tol", C.c_double), ("gmres_max_iter", C.c_int32), ("flags", C.c_int32),
-                ("jump", C.c_int32), ("reserved", C.c_int32)]
+                ("jump", C.c_int32), ("n_streams", C.c_int32)]
 
 
 class nat_mc_job(C.Structure):

@@ -108,6 +108,50 @@ def test_graph_replay_equals_direct_launches(ctx):
         m.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_concurrent_parts_equal_one_stream(ctx, prec):
+    """nat_mc_opts.n_streams: the batch split into 2, 3 or 5 parts on streams
+    of their own gives the same bits (outputs, samples, iteration counts) as
+    the whole batch on the caller's stream."""
+    wls = _mixed_workloads(5, seed=11)
+    meshes = [nat.Mesh(ctx, wl.vertices, wl.tris) for wl in wls]
+    results = []
+    for n_streams in (1, 2, 3, 5, 0):
+        opts = nat.nat_mc_opts_default()
+        opts.precision = nat.NAT_PREC_FP32 if prec == "fp32" else nat.NAT_PREC_FP64
+        opts.n_streams = n_streams
+        jobs = _jobs(ctx, wls, meshes)
+        _say(f"{prec} n_streams={n_streams}")
+        reps = nat.nat_mcbem_estimate_batch(ctx, jobs, opts, allow_noconv=True)
+        torch.cuda.synchronize()
+        results.append(([(j.p_out.cpu(), j.p_samples.cpu()) for j in jobs],
+                        [[r["iters"] for r in rr] for rr in reps]))
+    for outs, iters in results[1:]:
+        assert iters == results[0][1]
+        for (a, b), (c, d) in zip(results[0][0], outs):
+            assert torch.equal(a, c) and torch.equal(b, d)
+    for m in meshes:
+        m.close()
+
+
+def test_concurrent_parts_errors(ctx):
+    """A bad job anywhere in a split batch is refused before any part runs,
+    and n_streams outside 0..8 is refused."""
+    wls = _mixed_workloads(4, seed=13)
+    meshes = [nat.Mesh(ctx, wl.vertices, wl.tris) for wl in wls]
+    jobs = _jobs(ctx, wls, meshes)
+    opts = nat.nat_mc_opts_default()
+    opts.n_streams = 9
+    with pytest.raises(nat.NatError):
+        nat.nat_mcbem_estimate_batch(ctx, jobs, opts)
+    opts.n_streams = 4
+    jobs[2].k = np.array([-1.0] * wls[2].n_modes)
+    with pytest.raises(nat.NatError, match="k\\[0\\]"):
+        nat.nat_mcbem_estimate_batch(ctx, jobs, opts)
+    for m in meshes:
+        m.close()
+
+
 def test_batch_fp64_plain_matches_oracle(ctx):
     wls = _mixed_workloads(3, seed=3)
     meshes = [nat.Mesh(ctx, wl.vertices, wl.tris) for wl in wls]
