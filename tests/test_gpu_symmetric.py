@@ -2,7 +2,7 @@
 sample pair evaluated once for both of its targets) against the ordered
 form and the FP64 oracle: within the FP32 bar of the oracle, within 1e-4 of
 the ordered form, the same bits with and without graph replay, and the same
-bits alone and inside a batch, for groups of 1, 2, 3 and 8 modes and sample
+bits alone and inside a batch, for groups of 1 to 8 modes and sample
 counts that fill a 64-sample sub-tile exactly, leave a ragged one, or stay
 below one."""
 import sys
@@ -78,14 +78,18 @@ def test_symmetric_against_ordered_and_oracle(ctx):
     mesh.close()
 
 
-@pytest.mark.parametrize("case", ["small_groups", "tiny"])
+@pytest.mark.parametrize("case", ["small_groups", "tiny", "widths_4_to_7"])
 def test_symmetric_batch_equals_alone(ctx, case):
     if case == "small_groups":
-        # modes 1, 2, 3 (groups of width 1, 2, 4); N = 64, 65, 130
+        # groups of 1, 2 and 3 modes; N = 64, 65, 130
         specs = [(51, 600, 1, 200, 64), (52, 700, 2, 250, 65), (53, 900, 3, 300, 130)]
-    else:
+    elif case == "tiny":
         # fewer samples than one sub-tile, and exactly two
         specs = [(54, 500, 2, 100, 2), (55, 500, 9, 150, 40), (56, 600, 1, 120, 128)]
+    else:
+        # groups of 4, 5, 6 and 7 modes; N = 191, 256, 300
+        specs = [(57, 600, 4, 120, 191), (58, 700, 5, 150, 256), (59, 800, 6, 100, 300),
+                 (60, 600, 7, 90, 191)]
     made = [_job(ctx, *s) for s in specs]
     _say(f"symmetric batch {case}: " + ", ".join(f"M={s[2]} N={s[4]}" for s in specs))
     nat.nat_mcbem_estimate_batch(ctx, [j for _, _, j in made])
