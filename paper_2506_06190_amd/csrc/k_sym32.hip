@@ -56,8 +56,7 @@ __device__ __forceinline__ int32_t find_sym_group(const SymGroupDev* __restrict_
     return lo;
 }
 
-// Value of lane l + 1 (mod 64) in lane l (DPP wave_rol:1; the compiler
-// folds it into the add that consumes it).
+// Value of lane l + 1 (mod 64) in lane l (one DPP wave_rol:1 move).
 __device__ __forceinline__ float rot_from_next(float x)
 {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x134, 0xf, 0xf, true));
