@@ -79,6 +79,7 @@ NatScratch* bound_scratch() { return t_scratch; }
 
 void release_scratch(nat_ctx* ctx, NatScratch& sc)
 {
+    std::lock_guard<std::mutex> lk(ctx->capture_mu);  // frees: as in workspace()
     if (sc.ws)
         dev_free(ctx, sc.ws, sc.ws_bytes);
     sc.ws = nullptr;
@@ -114,7 +115,9 @@ nat_status workspace(nat_ctx* ctx, size_t bytes, void** ptr)
         *ptr = sc.ws;
         return NAT_OK;
     }
-    // grow: release the old block first (the device must be idle for it)
+    // grow: release the old block first (the device must be idle for it; no
+    // other thread of this context may be capturing a graph meanwhile)
+    std::lock_guard<std::mutex> lk(ctx->capture_mu);
     if (sc.ws) {
         NAT_HIP(hipDeviceSynchronize());
         dev_free(ctx, sc.ws, sc.ws_bytes);
@@ -139,6 +142,7 @@ nat_status pinned(nat_ctx* ctx, size_t bytes, void** ptr)
 {
     NatScratch& sc = scratch_of(ctx);
     if (bytes > sc.pinned_bytes) {
+        std::lock_guard<std::mutex> lk(ctx->capture_mu);  // as in workspace()
         if (sc.pinned) {
             NAT_HIP(hipDeviceSynchronize());
             (void)hipHostFree(sc.pinned);
@@ -211,6 +215,7 @@ nat_status mapped_words(nat_ctx* ctx, size_t n, int32_t** host, int32_t** dev)
 {
     NatScratch& sc = scratch_of(ctx);
     if (n > sc.mapped_ints) {
+        std::lock_guard<std::mutex> lk(ctx->capture_mu);  // as in workspace()
         if (sc.mapped) {
             NAT_HIP(hipDeviceSynchronize());
             (void)hipHostFree(sc.mapped);

@@ -69,7 +69,9 @@ struct nat_ctx {
     int32_t device = 0;
     nat::TuneTable tune;
     std::mutex mu;       // guards the ledger and the timing lists
-    std::mutex capture_mu;  // one graph capture at a time across a context's threads
+    // one graph capture at a time across a context's threads, never during
+    // another thread's scratch growth (which synchronises the device)
+    std::mutex capture_mu;
     // per-kernel timing (off unless enabled)
     bool prof = false;
     std::vector<NatProfEvent> prof_pending;

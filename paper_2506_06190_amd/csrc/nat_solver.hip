@@ -188,6 +188,10 @@ nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch* mv,
         *exec = sc.graph_exec;
         return NAT_OK;
     }
+    // one capture at a time across the context's threads, and none while
+    // another thread grows its scratch (a device-wide synchronisation or free
+    // is refused while any stream captures)
+    std::lock_guard<std::mutex> lk(ctx->capture_mu);
     if (sc.graph_exec) {
         (void)hipGraphExecDestroy(sc.graph_exec);
         sc.graph_exec = nullptr;
@@ -196,9 +200,6 @@ nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch* mv,
     if (!sc.capture_stream)
         NAT_HIP(hipStreamCreateWithFlags(&sc.capture_stream, hipStreamNonBlocking));
     hipStream_t cs = sc.capture_stream;
-    // concurrent parts of a batch capture one at a time (overlapping captures
-    // from several threads have failed on this runtime)
-    std::lock_guard<std::mutex> lk(ctx->capture_mu);
     NAT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int32_t r = 0; r < kLag && e == hipSuccess; ++r) {

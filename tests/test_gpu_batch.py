@@ -134,6 +134,31 @@ def test_concurrent_parts_equal_one_stream(ctx, prec):
         m.close()
 
 
+def test_concurrent_parts_grow_scratch():
+    """Parts whose scratch has to grow while other parts capture their GMRES
+    graphs (a fresh context: small batch first, then a larger one), against
+    the one-stream run of the larger batch."""
+    c = nat.Context(0)
+    small = _mixed_workloads(4, seed=17)
+    large = _mixed_workloads(8, seed=19)
+    for wls in (small, large):
+        meshes = [nat.Mesh(c, wl.vertices, wl.tris) for wl in wls]
+        outs = []
+        for n_streams in (4, 1):
+            opts = nat.nat_mc_opts_default()
+            opts.n_streams = n_streams
+            jobs = _jobs(c, wls, meshes)
+            _say(f"grow: {len(wls)} jobs, n_streams={n_streams}")
+            nat.nat_mcbem_estimate_batch(c, jobs, opts, allow_noconv=True)
+            torch.cuda.synchronize()
+            outs.append([j.p_out.cpu() for j in jobs])
+        for a, b in zip(*outs):
+            assert torch.equal(a, b)
+        for m in meshes:
+            m.close()
+    c.close()
+
+
 def test_concurrent_parts_errors(ctx):
     """A bad job anywhere in a split batch is refused before any part runs,
     and n_streams outside 0..8 is refused."""
