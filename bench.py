@@ -63,9 +63,9 @@ def roofline_from(prof, peak=FP32_VECTOR_PEAK_TFLOPS):
 
 def auto_parts(wls):
     """The part count nat_mcbem_estimate_batch picks for n_streams = 0: one part
-    per 2e10 pair terms (M N (31 N + Q) per job), at most 4, at most one per job."""
+    per 2e10 pair terms (M N (31 N + Q) per job), at most 3, at most one per job."""
     work = sum(w.n_modes * w.n_samples * (31.0 * w.n_samples + w.n_queries) for w in wls)
-    return int(min(4, len(wls), max(1, work // 2e10)))
+    return int(min(3, len(wls), max(1, work // 2e10)))
 
 
 def run_batched(nat, torch, ctx, args, dev):

@@ -100,7 +100,8 @@ typedef struct {
  * orthogonalisation, bound by HBM bandwidth, then overlaps another part's
  * kernel sums, bound by the vector ALUs.  0 picks the count from the batch's
  * size: one part per 2e10 pair terms (n_modes N (31 N + Q) per job), at most
- * 4; 1 runs the batch on the caller's stream alone.  The parts' scratch
+ * 3 (with the caller's stream, the 4 hardware queues a process gets by
+ * default); 1 runs the batch on the caller's stream alone.  The parts' scratch
  * memory is held by the context until it is destroyed.  Every result is
  * bitwise the same for any count (a system's arithmetic depends only on its
  * own sizes). */

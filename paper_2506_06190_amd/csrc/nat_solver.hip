@@ -19,8 +19,15 @@ namespace {
 constexpr double kInv4Pi = 0.07957747154594767;
 constexpr double kTwoPi = 6.283185307179586;
 // iterations per captured run; also how far the host may run ahead of the
-// device before it waits to refresh the running-system lists
+// device before it waits to refresh the running-system lists.  Batches whose
+// matvec has at least kLagPairs target-source pairs (an iteration of a
+// millisecond or so) refresh every kLagShort iterations, so converged systems
+// leave the lists sooner (the matvec of a mode group runs while any of its
+// systems does); smaller ones every kLag, so the host's refresh does not
+// starve a device that finishes an iteration in tens of microseconds.
 constexpr int32_t kLag = 4;
+constexpr int32_t kLagShort = 2;
+constexpr double kLagPairs = 1e9;
 constexpr int32_t kMaxGrid = kGridMatvec;
 
 inline void cpu_relax() { __builtin_ia32_pause(); }
@@ -172,7 +179,7 @@ void append_bytes(std::vector<unsigned char>& v, const T& x)
 // distinct set of launch arguments and kept by the context.
 nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch* mv, const SymBatch* sym,
                         const KmvBatch* kmv, int32_t grid_g, int32_t grid_mv, int32_t grid_sym,
-                        int32_t grid_k, hipGraphExec_t* exec)
+                        int32_t grid_k, int32_t lag, hipGraphExec_t* exec)
 {
     NatScratch& sc = scratch_of(ctx);
     std::vector<unsigned char> key;
@@ -184,6 +191,7 @@ nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch* mv,
     append_bytes(key, grid_mv);
     append_bytes(key, grid_sym);
     append_bytes(key, grid_k);
+    append_bytes(key, lag);
     if (sc.graph_exec && key == sc.graph_key) {
         *exec = sc.graph_exec;
         return NAT_OK;
@@ -202,7 +210,7 @@ nat_status captured_run(nat_ctx* ctx, const GmresBatch& g, const Sum32Batch* mv,
     hipStream_t cs = sc.capture_stream;
     NAT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int32_t r = 0; r < kLag && e == hipSuccess; ++r) {
+    for (int32_t r = 0; r < lag && e == hipSuccess; ++r) {
         if (mv)
             e = launch_sum32_batch(OP_MATVEC, *mv, grid_mv, cs);
         if (e == hipSuccess && sym)
@@ -303,6 +311,7 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
     const int32_t grid_g = static_cast<int32_t>(T.max_items < kGridArnoldi ? (T.max_items > 0 ? T.max_items : 1) : kGridArnoldi);
     const int32_t grid_mv = static_cast<int32_t>(ls.mv_items < kMaxGrid ? (ls.mv_items > 0 ? ls.mv_items : 1) : kMaxGrid);
     const int32_t grid_k = static_cast<int32_t>(T.max_items < kGridKmv ? (T.max_items > 0 ? T.max_items : 1) : kGridKmv);
+    const int32_t lag = ls.mv_pairs + ls.sym_pairs + ls.kmv_pairs >= kLagPairs ? kLagShort : kLag;
     // persistent grid of the symmetric form sized for its finest grouping
     int64_t sym_max_items = 0;
     for (size_t ii = 0; ii < T.inst.size(); ++ii) {
@@ -315,7 +324,7 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
     const int32_t grid_sym = static_cast<int32_t>(sym_blocks < kGridSym ? (sym_blocks > 0 ? sym_blocks : 1) : kGridSym);
     hipGraphExec_t exec = nullptr;
     if (use_graph && mv && !ctx->prof) {
-        st = captured_run(ctx, g, mv_ord, mv_sym, kmv, grid_g, grid_mv, grid_sym, grid_k, &exec);
+        st = captured_run(ctx, g, mv_ord, mv_sym, kmv, grid_g, grid_mv, grid_sym, grid_k, lag, &exec);
         if (st != NAT_OK)
             exec = nullptr;  // fall back to direct launches
     }
@@ -324,9 +333,9 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
     while (launched < g.mmax) {
         if (exec) {
             NAT_HIP(hipGraphLaunch(exec, s));
-            launched += kLag;
+            launched += lag;
         } else {
-            for (int32_t r = 0; r < kLag && launched < g.mmax; ++r) {
+            for (int32_t r = 0; r < lag && launched < g.mmax; ++r) {
                 if (mv_ord)
                     NAT_HIP(launch_sum32_batch(OP_MATVEC, *mv_ord, grid_mv, s,
                                                prof_slot(ctx, PK_SUM32_MATVEC, 37.0 * ls.mv_pairs)));
@@ -345,7 +354,7 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
         if (launched >= g.mmax)
             break;
         // wait until the device has finished all but the run just queued
-        const int32_t target = launched - kLag;
+        const int32_t target = launched - lag;
         int64_t spins = 0;
         while (*hprog < target) {
             if (++spins > (int64_t(1) << 26)) {
@@ -955,9 +964,12 @@ namespace {
 // pair terms of a job: the right-hand side, about 30 GMRES matvecs and the
 // evaluation (sets the automatic part count)
 double job_work(const McJob& J) { return (double)J.M * J.N * (31.0 * J.N + J.Q); }
-// automatic part count: one part per this much work, at most kAutoLanes
+// automatic part count: one part per this much work, at most kAutoLanes.
+// HIP gives a process 4 hardware queues by default; 3 parts plus the
+// caller's stream fit them (measured on the headline batch: 1, 2, 3, 4
+// parts took 300, 261, 250-256, 281-285 ms per step).
 constexpr double kLaneWork = 2e10;
-constexpr int32_t kAutoLanes = 4;
+constexpr int32_t kAutoLanes = 3;
 
 }  // namespace
 
