@@ -1050,11 +1050,21 @@ nat_status run_mc_parts(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_m
         sts[l] = r;
         bind_scratch(prev);
     };
+    // a part whose thread cannot be started runs on this thread afterwards
+    // (no exception crosses the C ABI)
     std::vector<std::thread> th;
+    std::vector<int32_t> inline_parts;
     th.reserve(L - 1);
-    for (int32_t l = 1; l < L; ++l)
-        th.emplace_back(part, l);
+    for (int32_t l = 1; l < L; ++l) {
+        try {
+            th.emplace_back(part, l);
+        } catch (...) {
+            inline_parts.push_back(l);
+        }
+    }
     part(0);
+    for (int32_t l : inline_parts)
+        part(l);
     for (std::thread& t : th)
         t.join();
     for (int32_t l = 0; l < L; ++l)
