@@ -393,8 +393,11 @@ struct SymBatch {
     const int32_t* active;
     float4* partial;
 };
-// workgroups (of 4 independent waves) of the symmetric matvec launch
-constexpr int32_t kGridSym = 2048;
+// most workgroups (of 4 independent waves) of the symmetric matvec launch:
+// enough that a headline matvec gives each wave a few items, so the
+// hardware dispatcher, not a fixed stride, balances their uneven cost
+// (one-stream batched step: 2048 -> 298 ms, 8192 -> 283, 32768 -> 281)
+constexpr int32_t kGridSym = 32768;
 // wave items below which the symmetric form narrows its mode groups
 constexpr int64_t kSymFillItems = 4096;
 hipError_t launch_sym32(const SymBatch& p, int32_t grid, hipStream_t s, const ProfSlot& ev = ProfSlot());
