@@ -109,7 +109,7 @@ def run_batched(nat, torch, ctx, args, dev):
     roof["traffic"] = traffic_from_profile(kern) if kern in MATVEC else None
     valu = valu_from_profile(kern) if kern in MATVEC else None
     roof["executed_fp32_tflops_counters"] = valu[0] if valu else None
-    roof["valu_issue_busy_counters"] = valu[1] if valu else None
+    roof["valu_active_per_simd_cycle_counters"] = valu[1] if valu else None
     roof["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)"
     out = {
         "value": alg * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
@@ -454,10 +454,13 @@ def pmc_valu_summarize(d):
     secs = sum(spans.values()) * 1e-9
     flops = 64.0 * (2 * tot["SQ_INSTS_VALU_FMA_F32"] + tot["SQ_INSTS_VALU_MUL_F32"] +
                     tot["SQ_INSTS_VALU_ADD_F32"] + tot["SQ_INSTS_VALU_TRANS_F32"])
-    # GRBM_GUI_ACTIVE is summed over the 8 XCDs; SQ_ACTIVE_INST_VALU over the
-    # 1024 SIMDs, in units of 4 cycles
+    # GRBM_GUI_ACTIVE is summed over the 8 XCDs; SQ_ACTIVE_INST_VALU counts,
+    # per wave, the quad-cycles with a VALU instruction in flight, summed over
+    # the waves: per SIMD cycle it can exceed 1 when the instructions of
+    # several waves on one SIMD overlap, so it is a ratio, not a fraction
     xcd_cycles = tot["GRBM_GUI_ACTIVE"] / 8.0
     busy = 4.0 * tot["SQ_ACTIVE_INST_VALU"] / (1024.0 * xcd_cycles)
+    ipc = tot["SQ_INSTS_VALU"] / (1024.0 * xcd_cycles)
     lines = [
         f"# VALU counters of {MATVEC[kern]['title']} (batched headline step, direct launches)",
         "# command (run from the repository root, TMPDIR=/tmp):",
@@ -466,7 +469,9 @@ def pmc_valu_summarize(d):
         f"{' --ordered' if kern == 'k_sum32' else ''}",
         f"#   python3 bench.py --pmc-valu-summarize {d}",
         "# executed FP32 flops = 64 lanes x (2 FMA + MUL + ADD + TRANS) wave instructions;",
-        "# VALU issue = 4 x SQ_ACTIVE_INST_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs).",
+        "# valu_active_per_simd_cycle = 4 x SQ_ACTIVE_INST_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs)",
+        "#   (per-wave VALU-active cycles summed over waves; can exceed 1 when waves overlap);",
+        "# valu_insts_per_simd_cycle = SQ_INSTS_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs).",
         f"kernel_source_sha256_16: {kernel_hash(kern)}",
         f"matvec_dispatches: {len(spans)}",
         f"traced_seconds: {secs:.6f}",
@@ -474,7 +479,8 @@ def pmc_valu_summarize(d):
         f"executed_fp32_flops: {flops:.6g}",
         f"executed_fp32_tflops: {flops / secs * 1e-12:.3f}",
         f"trans_share_of_valu: {tot['SQ_INSTS_VALU_TRANS_F32'] / tot['SQ_INSTS_VALU']:.4f}",
-        f"valu_issue_busy: {busy:.4f}",
+        f"valu_active_per_simd_cycle: {busy:.4f}",
+        f"valu_insts_per_simd_cycle: {ipc:.4f}",
     ]
     with open(MATVEC[kern]["valu"], "w") as fh:
         fh.write("\n".join(lines) + "\n")
@@ -482,8 +488,8 @@ def pmc_valu_summarize(d):
 
 
 def valu_from_profile(kern):
-    """(executed FP32 TFLOP/s, VALU issue fraction) of the matvec, or None when
-    absent or stale."""
+    """(executed FP32 TFLOP/s, VALU-active cycles per SIMD cycle) of the matvec,
+    or None when absent or stale."""
     path = MATVEC[kern]["valu"]
     if not os.path.exists(path):
         return None
@@ -495,7 +501,9 @@ def valu_from_profile(kern):
                 kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256_16") != kernel_hash(kern):
         return None
-    return float(kv["executed_fp32_tflops"]), float(kv["valu_issue_busy"])
+    if "valu_active_per_simd_cycle" not in kv:
+        return None
+    return float(kv["executed_fp32_tflops"]), float(kv["valu_active_per_simd_cycle"])
 
 
 def traffic_from_profile(kern):
