@@ -421,6 +421,13 @@ nat_status nat_ctx_create(int32_t device, size_t hbm_budget_bytes, nat_ctx** out
     c->device = device;
     c->budget = hbm_budget_bytes;
     nat::tune_defaults(&c->tune);
+    // the streams of a batch's automatic parts first, before any other stream
+    // of the context: HIP maps streams onto its few hardware queues in
+    // creation order, and parts whose streams came after the graph-capture
+    // streams ran 10 % slower (a failure here only defers their creation)
+    for (int l = 0; l < nat::kAutoLanes; ++l)
+        if (hipStreamCreateWithFlags(&c->lane_stream[l], hipStreamNonBlocking) != hipSuccess)
+            c->lane_stream[l] = nullptr;
     // quadrature rules of the dense assembly: far 3-point, angular 16-point
     double rules[2 * 3 + 2 * 16];
     nat::gauss_legendre01(3, rules, rules + 3);

@@ -393,6 +393,11 @@ struct SymBatch {
     const int32_t* active;
     float4* partial;
 };
+// most concurrent parts of an automatic batch split.  HIP gives a process 4
+// hardware queues by default; 3 parts plus the caller's stream fit them
+// (measured on the headline batch: 1, 2, 3, 4 parts took 300, 261, 250-256,
+// 281-285 ms per step).
+constexpr int32_t kAutoLanes = 3;
 // most workgroups (of 4 independent waves) of the symmetric matvec launch:
 // enough that a headline matvec gives each wave a few items, so the
 // hardware dispatcher, not a fixed stride, balances their uneven cost

@@ -964,12 +964,8 @@ namespace {
 // pair terms of a job: the right-hand side, about 30 GMRES matvecs and the
 // evaluation (sets the automatic part count)
 double job_work(const McJob& J) { return (double)J.M * J.N * (31.0 * J.N + J.Q); }
-// automatic part count: one part per this much work, at most kAutoLanes.
-// HIP gives a process 4 hardware queues by default; 3 parts plus the
-// caller's stream fit them (measured on the headline batch: 1, 2, 3, 4
-// parts took 300, 261, 250-256, 281-285 ms per step).
+// automatic part count: one part per this much work, at most kAutoLanes
 constexpr double kLaneWork = 2e10;
-constexpr int32_t kAutoLanes = 3;
 
 }  // namespace
 
@@ -1011,6 +1007,34 @@ nat_status run_mc_parts(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_m
         if (!ctx->lane_event[l])
             NAT_HIP(hipEventCreateWithFlags(&ctx->lane_event[l], hipEventDisableTiming));
     }
+    // the parts' jobs, and their workspaces grown here, before any part runs
+    // (so no part synchronises the device for a growth while others run)
+    std::vector<std::vector<McJob>> pjobs(L);
+    for (int32_t l = 0; l < L; ++l)
+        for (int32_t i : idx[l])
+            pjobs[l].push_back(jobs[i]);
+    {
+        std::vector<size_t> need(L, 0);
+        bool grow = false;
+        for (int32_t l = 0; l < L; ++l) {
+            st = run_mc(ctx, pjobs[l].data(), static_cast<int32_t>(pjobs[l].size()), opts, nullptr, s,
+                        &need[l]);
+            if (st != NAT_OK)
+                return st;
+            grow = grow || need[l] > ctx->lane_scratch[l].ws_bytes;
+        }
+        if (grow) {
+            NatScratch* prev = bound_scratch();
+            for (int32_t l = 0; l < L && st == NAT_OK; ++l) {
+                bind_scratch(&ctx->lane_scratch[l]);
+                void* w = nullptr;
+                st = workspace(ctx, need[l], &w);
+            }
+            bind_scratch(prev);
+            if (st != NAT_OK)
+                return st;
+        }
+    }
     NAT_HIP(hipEventRecord(ctx->lane_fork, s));
     std::vector<nat_status> sts(L, NAT_OK);
     std::vector<std::string> msgs(L);
@@ -1023,12 +1047,10 @@ nat_status run_mc_parts(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_m
             if (hipStreamWaitEvent(ls, ctx->lane_fork, 0) != hipSuccess) {
                 r = fail(NAT_E_HIP, "hipStreamWaitEvent");
             } else {
-                std::vector<McJob> pj;
+                const std::vector<McJob>& pj = pjobs[l];
                 int64_t ns = 0;
-                for (int32_t i : idx[l]) {
-                    pj.push_back(jobs[i]);
+                for (int32_t i : idx[l])
                     ns += jobs[i].M;
-                }
                 std::vector<nat_solve_report> pr(report ? ns : 0);
                 r = run_mc(ctx, pj.data(), static_cast<int32_t>(pj.size()), opts,
                            report ? pr.data() : nullptr, ls, nullptr);
