@@ -432,17 +432,24 @@ nat_status nat_ctx_create(int32_t device, size_t hbm_budget_bytes, nat_ctx** out
     double rules[2 * 3 + 2 * 16];
     nat::gauss_legendre01(3, rules, rules + 3);
     nat::gauss_legendre01(16, rules + 6, rules + 22);
+    // a failure below ends the context: its part streams go with it
+    auto discard = [c]() {
+        for (int l = 0; l < nat::kAutoLanes; ++l)
+            if (c->lane_stream[l])
+                (void)hipStreamDestroy(c->lane_stream[l]);
+        delete c;
+    };
     void* d = nullptr;
     nat_status st = nat::dev_alloc(c, sizeof(rules), &d);
     if (st != NAT_OK) {
-        delete c;
+        discard();
         return st;
     }
     c->d_rules = static_cast<double*>(d);
     e = hipMemcpy(c->d_rules, rules, sizeof(rules), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         nat::dev_free(c, d, sizeof(rules));
-        delete c;
+        discard();
         return nat::hip_fail(e, "hipMemcpy rules");
     }
     *out = c;

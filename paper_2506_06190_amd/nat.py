@@ -406,7 +406,9 @@ def nat_mcbem_estimate(mesh: Mesh, v_n, k: Sequence[float], q_tri, q_bary, n_sam
 
 
 class McJob:
-    """One problem of nat_mcbem_estimate_batch (device tensors, host k)."""
+    """One problem of nat_mcbem_estimate_batch (device tensors, host k).  The
+    Neumann layout must be the batch's (nat_mc_opts.layout): the C job record
+    carries none, and v_n is read with the batch's layout."""
 
     def __init__(self, mesh: Mesh, v_n, k, q_tri, q_bary, n_samples: int, seed: int,
                  p_out=None, p_samples=None, layout: int = NAT_NEUMANN_PER_VERTEX):
@@ -414,6 +416,7 @@ class McJob:
         self.mesh = mesh
         self.k = np.ascontiguousarray(np.atleast_1d(k), dtype=np.float64)
         self.n_modes = len(self.k)
+        self.layout = int(layout)
         ng = mesh.n_tris if layout == NAT_NEUMANN_PER_TRIANGLE else mesh.n_vertices
         self.Q = int(q_tri.shape[0])
         self.v_n, self.q_tri, self.q_bary = v_n, q_tri, q_bary
@@ -426,11 +429,14 @@ class McJob:
         self.p_out = p_out
         self.p_samples = p_samples
 
-    def record(self) -> nat_mc_job:
+    def record(self, layout: int) -> nat_mc_job:
         import torch
+        if int(layout) != self.layout:
+            raise ValueError(f"job layout {self.layout} differs from the batch layout {layout}")
+        ng = self.mesh.n_tris if layout == NAT_NEUMANN_PER_TRIANGLE else self.mesh.n_vertices
         j = nat_mc_job()
         j.mesh = self.mesh.handle.value
-        j.v_n = self.v_n.data_ptr()
+        j.v_n = _dptr(self.v_n, torch.complex128, (self.n_modes, ng), "v_n").value
         j.n_modes = self.n_modes
         j.n_queries = self.Q
         j.k = self.k.ctypes.data
@@ -449,7 +455,7 @@ def nat_mcbem_estimate_batch(ctx: Context, jobs, opts: Optional[nat_mc_opts] = N
     """Runs the jobs (list of McJob) in one batch; returns per-job lists of report dicts."""
     if opts is None:
         opts = nat_mc_opts_default()
-    recs = (nat_mc_job * len(jobs))(*[j.record() for j in jobs])
+    recs = (nat_mc_job * len(jobs))(*[j.record(opts.layout) for j in jobs])
     n_sys = sum(j.n_modes for j in jobs)
     reps = (nat_solve_report * n_sys)()
     st = lib().nat_mcbem_estimate_batch(ctx.handle, C.cast(recs, _P), len(jobs), C.byref(opts),

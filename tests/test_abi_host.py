@@ -79,3 +79,16 @@ def test_mesh_validation_rejects_bad_meshes():
     vz[t0[2]] = vz[t0[1]]
     st, msg = nat.nat_mesh_validate(vz, f)
     assert st == nat.NAT_E_INVALID and "zero area" in msg
+
+
+def test_batch_job_layout_must_match_the_batch():
+    """A job whose Neumann data was shaped for one layout cannot enter a batch
+    run with the other (the C job record has no layout of its own, so the
+    library would read v_n with the batch's layout)."""
+    job = nat.McJob.__new__(nat.McJob)
+    job.layout = nat.NAT_NEUMANN_PER_VERTEX
+    with pytest.raises(ValueError, match="layout"):
+        job.record(nat.NAT_NEUMANN_PER_TRIANGLE)
+    job.layout = nat.NAT_NEUMANN_PER_TRIANGLE
+    with pytest.raises(ValueError, match="layout"):
+        job.record(nat.NAT_NEUMANN_PER_VERTEX)

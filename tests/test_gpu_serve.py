@@ -3,25 +3,22 @@ a mixed stream equals the same request run alone (bit for bit: the batch
 tiling of a request depends only on its own sizes, and a dense request runs
 the same assembly and solve), the arena budget bounds the device memory,
 a request larger than the arena is refused at submission, and a request
-whose data fails the device checks fails alone inside its batch."""
-import sys
-
-import numpy as np
+whose data fails the device checks fails alone inside its batch; every
+served result of a mixed stream matches the FP64 oracle (Monte-Carlo
+requests within 1e-3, dense requests within 1e-9, per mode and element by
+element)."""
 import pytest
 
 import workloads as W
+from oracle import oracle as O
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_2506_06190_amd import nat  # noqa: E402
+from _parity import check_modes, say as _say  # noqa: E402
 
 DEV = "cuda:0"
-
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
 
 
 @pytest.fixture(scope="module")
@@ -130,6 +127,48 @@ def test_served_equal_solo_bitwise(ctx, stream_setup):
         assert [x["iters"] for x in reps] == [x["iters"] for x in rep_solo]
     _say(f"  {n_batched} of {len(reqs)} requests ran in shared batches; all equal their solo runs")
     assert n_batched > 0
+
+
+def test_served_results_match_oracle(ctx, stream_setup):
+    """Every request of the mixed stream, served with continuous batching over
+    three worker streams, against the FP64 oracle on the same inputs:
+    Monte-Carlo requests at the same seed, GMRES tolerance 1e-6 and cap 200
+    (bar 1e-3); dense requests solved to 1e-12 against the oracle's
+    collocation assembly and solve (bar 1e-9)."""
+    meshes, reqs, res = stream_setup
+    sopts = nat.nat_server_opts_default()
+    sopts.n_slots = 3
+    sopts.max_batch = 8
+    sopts.hbm_budget = 2 << 30
+    sopts.dense_tol = 1e-12
+    srv = nat.Server(ctx, sopts)
+    torch.cuda.synchronize()
+    built = [_request(rq, res[rq.mesh]) for rq in reqs]
+    tickets = [nat.nat_server_submit(srv, b) for b in built]
+    results = [nat.nat_server_wait(srv, t) for t in tickets]
+    srv.close()
+    n_mc = n_dense = 0
+    for j, (rq, b, (st, r, reps)) in enumerate(zip(reqs, built, results)):
+        assert st in (nat.NAT_OK, nat.NAT_E_NOCONV)
+        m = meshes[rq.mesh]
+        got = b.p_out.cpu().numpy()
+        M = rq.n_modes
+        if rq.kind == "mc":
+            ref = O.mcbem(m.vertices, m.tris, m.g_vertex[rq.m0:rq.m0 + M], rq.k,
+                          m.q_tri[:rq.n_queries], m.q_b[:rq.n_queries], rq.n_samples, rq.seed,
+                          tol=1e-6, max_iter=200)["p"]
+            check_modes(got, ref, 1e-3, f"request {j} mc M={M} Q={rq.n_queries} "
+                        f"N={rq.n_samples} (batch {r['batch_size']})")
+            n_mc += 1
+        else:
+            ref = []
+            for a in range(M):
+                A, B = O.bem_assemble(m.vertices, m.tris, rq.k[a], True)
+                ref.append(O.bem_solve(A, B, m.g_tri[rq.m0 + a], tol=1e-12)[0])
+            check_modes(got, ref, 1e-9, f"request {j} dense M={M} n={len(m.tris)}")
+            n_dense += 1
+    _say(f"  {n_mc} Monte-Carlo and {n_dense} dense served results match the oracle")
+    assert n_mc > 0 and n_dense > 0
 
 
 def test_budget_bounds_admission(ctx, stream_setup):

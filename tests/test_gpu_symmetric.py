@@ -5,9 +5,6 @@ the ordered form, the same bits with and without graph replay, and the same
 bits alone and inside a batch, for groups of 1 to 8 modes and sample
 counts that fill a 64-sample sub-tile exactly, leave a ragged one, or stay
 below one."""
-import sys
-
-import numpy as np
 import pytest
 
 import workloads as W
@@ -17,13 +14,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_2506_06190_amd import nat  # noqa: E402
+from _parity import check_modes, say as _say  # noqa: E402
 
 DEV = "cuda:0"
-
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
 
 
 @pytest.fixture(scope="module")
@@ -56,10 +49,6 @@ def _estimate(mesh, job, flags):
     return p, rep
 
 
-def _max_rel(a, b):
-    return max(float(np.linalg.norm(a[m] - b[m]) / np.linalg.norm(b[m])) for m in range(len(a)))
-
-
 def test_symmetric_against_ordered_and_oracle(ctx):
     # N = 600: nine full sub-tiles and a ragged one; 11 modes: groups of 8 and 3
     args, mesh, job = _job(ctx, 41, 1500, 11, 600, 600)
@@ -71,9 +60,9 @@ def test_symmetric_against_ordered_and_oracle(ctx):
     assert not torch.equal(p_sym, p_ord)
     ref = O.mcbem(*args[:8])["p"]
     a, b = p_sym.cpu().numpy(), p_ord.cpu().numpy()
-    e_sym, e_ord, e_ab = _max_rel(a, ref), _max_rel(b, ref), _max_rel(a, b)
-    _say(f"  max rel L2: symmetric {e_sym:.2e}, ordered {e_ord:.2e}, between {e_ab:.2e}")
-    assert e_sym <= 1e-3 and e_ord <= 1e-3 and e_ab <= 1e-4
+    check_modes(a, ref, 1e-3, "symmetric vs oracle")
+    check_modes(b, ref, 1e-3, "ordered vs oracle")
+    check_modes(a, b, 1e-4, "symmetric vs ordered")
     assert all(r["converged"] for r in rep)
     mesh.close()
 
@@ -98,8 +87,6 @@ def test_symmetric_batch_equals_alone(ctx, case):
         p1, _ = _estimate(mesh, job, 0)
         assert torch.equal(job.p_out, p1)
         ref = O.mcbem(*args[:8])["p"]
-        e = _max_rel(p1.cpu().numpy(), ref)
-        _say(f"  M={args[3].shape[0]} N={args[6]}: max rel L2 vs oracle {e:.2e}")
-        assert e <= 1e-3
+        check_modes(p1.cpu().numpy(), ref, 1e-3, f"M={args[3].shape[0]} N={args[6]} vs oracle")
     for _, mesh, _ in made:
         mesh.close()
