@@ -31,6 +31,14 @@ def pulsating_sphere(k, a, g=1.0):
     return g * a / (1j * k * a - 1.0)
 
 
+def pulsating_sphere_field(k, a, r, g=1.0):
+    """Exterior field of the pulsating sphere (dp/dr = g on r = a): the
+    monopole p(r) = g a^2 e^{ik(r-a)} / ((ika - 1) r), equal to
+    pulsating_sphere(k, a, g) at r = a."""
+    r = np.asarray(r, dtype=np.float64)
+    return g * a * a * np.exp(1j * k * (r - a)) / ((1j * k * a - 1.0) * r)
+
+
 def oscillating_sphere_factor(k, a):
     """dp/dr = cos(theta) on r = a:  p(a, theta) = F cos(theta) with
     F = a (z + i) / (i z^2 - 2 z - 2 i),  z = k a."""

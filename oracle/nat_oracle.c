@@ -319,6 +319,48 @@ void orc_mc_eval(int32_t Q, const double* x, const double* gx_in, double c_q,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Field points around a scene (Section 3.4, training data; Section 3.1,  */
+/* FFAT maps).  R is the bounding-box radius (half the box diagonal) and  */
+/* c the box centre.                                                      */
+/*  kind 0 (shell): n_a points; point i draws u0, u1, u2 from counters    */
+/*    3i, 3i+1, 3i+2 of stream 5 and takes r = R (r_lo + (r_hi - r_lo) u0),*/
+/*    cos(theta) = 1 - 2 u1, phi = 2 pi u2 (a direction uniform on the    */
+/*    sphere, a radius uniform in the shell).                             */
+/*  kind 1 (FFAT grid): n_a x n_b points on the sphere of radius R r_lo,  */
+/*    theta_a = (a + 1/2) pi / n_a, phi_b = (b + 1/2) 2 pi / n_b, point    */
+/*    a n_b + b (an image with theta down the rows, phi along them).      */
+/* x = c + r (sin theta cos phi, sin theta sin phi, cos theta); coords    */
+/* holds (r, theta, phi) per point.                                       */
+/* ---------------------------------------------------------------------- */
+void orc_field_points(const double* center, double R, int32_t kind, int32_t n_a, int32_t n_b,
+                      double r_lo, double r_hi, uint64_t seed, double* xyz, double* coords)
+{
+    int32_t n = kind == 0 ? n_a : n_a * n_b;
+    for (int32_t i = 0; i < n; ++i) {
+        double r, th, ph;
+        if (kind == 0) {
+            double u0 = orc_u01(orc_rng_word(seed, 5, 3ULL * (uint64_t)i + 0));
+            double u1 = orc_u01(orc_rng_word(seed, 5, 3ULL * (uint64_t)i + 1));
+            double u2 = orc_u01(orc_rng_word(seed, 5, 3ULL * (uint64_t)i + 2));
+            r = R * (r_lo + (r_hi - r_lo) * u0);
+            th = acos(1.0 - 2.0 * u1);
+            ph = 2.0 * M_PI * u2;
+        } else {
+            int32_t a = i / n_b, b = i % n_b;
+            r = R * r_lo;
+            th = (a + 0.5) * M_PI / n_a;
+            ph = (b + 0.5) * 2.0 * M_PI / n_b;
+        }
+        xyz[3 * i + 0] = center[0] + r * (sin(th) * cos(ph));
+        xyz[3 * i + 1] = center[1] + r * (sin(th) * sin(ph));
+        xyz[3 * i + 2] = center[2] + r * cos(th);
+        coords[3 * i + 0] = r;
+        coords[3 * i + 1] = th;
+        coords[3 * i + 2] = ph;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
 /* Free term of the surface identity at a query point.  The identity      */
 /* c(x) p(x) = int (p dG/dn_y - G g) holds on the boundary with             */
 /* c(x) = 1 + int dG0/dn_y dS_y (G0 the Laplace kernel), i.e. one minus the */

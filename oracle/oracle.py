@@ -62,6 +62,8 @@ def lib():
         L.orc_mc_eval.argtypes = [C.c_int32, _d, C.c_void_p, C.c_double, C.c_void_p, C.c_int32,
                                   _d, _d, _d, _d, C.c_double, C.c_double, C.c_double, C.c_int32, _d]
         L.orc_free_terms.argtypes = [_d, _i, C.c_int32, _i, _d, C.c_int32, C.c_int32, _d]
+        L.orc_field_points.argtypes = [_d, C.c_double, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                       C.c_double, C.c_uint64, _d, _d]
         L.orc_gmres.argtypes = [C.c_int32, _d, _d, _d, C.c_double, C.c_int32,
                                 C.POINTER(C.c_double)]
         L.orc_gmres.restype = C.c_int32
@@ -203,6 +205,48 @@ def mc_eval(x, gx, c_q, y, ny, g, p, k, w, eps, exact_disk=False):
                       carr.ctypes.data_as(C.c_void_p) if carr is not None else None,
                       len(y), y.reshape(-1), ny.reshape(-1), _c2d(g), _c2d(p),
                       float(k), float(w), float(eps), int(exact_disk), out.view(np.float64))
+    return out
+
+
+def bounding_sphere(V):
+    """(centre, radius) of the axis-aligned bounding box: its centre and half its diagonal."""
+    V = _f64(V)
+    lo, hi = V.min(axis=0), V.max(axis=0)
+    return 0.5 * (lo + hi), 0.5 * float(np.linalg.norm(hi - lo))
+
+
+def field_points(V, kind, n_a, n_b=1, r_lo=1.5, r_hi=3.0, seed=0):
+    """Field points around the mesh (Section 3.4 shell, kind 0; FFAT grid of
+    n_a x n_b directions at radius r_lo R, kind 1).  Returns (xyz, coords)
+    with coords = (r, theta, phi) per point."""
+    c, R = bounding_sphere(V)
+    n = n_a if kind == 0 else n_a * n_b
+    xyz = np.empty((n, 3))
+    coords = np.empty((n, 3))
+    lib().orc_field_points(_f64(c), float(R), int(kind), int(n_a), int(n_b), float(r_lo),
+                           float(r_hi), seed, xyz.reshape(-1), coords.reshape(-1))
+    return xyz, coords
+
+
+def mcbem_field(V, T, g, k, N, seed, points, p_samples, eps_scale=1.0, layout=0):
+    """Pressure at exterior points from the sample values of an estimate
+    (Section 3.4: the field from the Neumann and Dirichlet data): the
+    representation formula p(x) = sum_j w (dG/dn_j p_j - G g_j) over the same
+    samples, with c = 1 and no disk term.  p_samples: (n_modes, N), e.g. the
+    p_samples of mcbem() with the same N and seed."""
+    V, T = _f64(V), _i32(T)
+    g = np.ascontiguousarray(np.atleast_2d(g), dtype=np.complex128)
+    k = np.atleast_1d(np.asarray(k, dtype=np.float64))
+    p_samples = np.ascontiguousarray(np.atleast_2d(p_samples), dtype=np.complex128)
+    area, nrm, cdf = geometry(V, T)
+    tri, bary = samples(V, T, N, seed)
+    y = surface_points(V, T, tri, bary)
+    ny = np.ascontiguousarray(nrm[tri])
+    w, eps = mc_constants(cdf[-1], N, eps_scale)
+    out = np.empty((len(k), len(points)), dtype=np.complex128)
+    for m in range(len(k)):
+        gj = neumann_at(T, g[m], tri, bary, layout)
+        out[m] = mc_eval(points, None, 1.0, y, ny, gj, p_samples[m], k[m], w, eps)
     return out
 
 
