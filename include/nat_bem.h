@@ -237,6 +237,27 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
                               const nat_mc_opts* opts, double* p_out, double* p_samples,
                               nat_solve_report* report, void* stream);
 
+/* Allocation-free nat_mcbem_estimate, for callers that cannot allocate
+ * memory during the call (serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, same validation and the same results bit for bit as
+ * nat_mcbem_estimate with NAT_MC_NO_GRAPH; opts->n_streams is ignored.  The
+ * device workspace comes from one fixed block of 256 MiB per GPU that the
+ * library holds from its first use on that GPU until the process ends (not
+ * charged to the context's budget), host staging from fixed host blocks;
+ * the call allocates no device or pinned memory and creates no stream,
+ * event or graph.  An estimate whose workspace exceeds the block returns
+ * NAT_E_BUDGET before any device work (the workspace grows with
+ * n_modes x n_samples x (gmres_max_iter + 1); 32 modes x 1024 samples x 200
+ * iterations with 4096 queries fit).  Stage times in the report read 0.
+ * All calls on one GPU share its block and its host staging: calls that
+ * overlap in time on one GPU race and must be serialised by the caller.
+ * Blocks until done. */
+nat_status nat_mcbem_estimate_noalloc(nat_mesh* mesh, const double* v_n, int32_t n_modes,
+                                      const double* k, const int32_t* q_tri, const double* q_bary,
+                                      int32_t n_queries, int32_t n_samples, uint64_t seed,
+                                      const nat_mc_opts* opts, double* p_out, double* p_samples,
+                                      nat_solve_report* report, void* stream);
+
 /* One problem of a batch: the arguments of nat_mcbem_estimate. */
 typedef struct {
     nat_mesh* mesh;

@@ -141,6 +141,13 @@ nat_status workspace(nat_ctx* ctx, size_t bytes, void** ptr)
 nat_status pinned(nat_ctx* ctx, size_t bytes, void** ptr)
 {
     NatScratch& sc = scratch_of(ctx);
+    if (sc.noalloc) {
+        if (bytes > sc.pinned_bytes)
+            return fail(NAT_E_BUDGET, "host staging: need %zu bytes, the fixed block holds %zu", bytes,
+                        sc.pinned_bytes);
+        *ptr = sc.pinned;
+        return NAT_OK;
+    }
     if (bytes > sc.pinned_bytes) {
         std::lock_guard<std::mutex> lk(ctx->capture_mu);  // as in workspace()
         if (sc.pinned) {
@@ -173,7 +180,7 @@ static hipEvent_t prof_event(nat_ctx* ctx)
 ProfSlot prof_slot(nat_ctx* ctx, int32_t kind, double flops)
 {
     ProfSlot slot;
-    if (!ctx || !ctx->prof)
+    if (!ctx || !ctx->prof || scratch_of(ctx).noalloc)
         return slot;
     std::lock_guard<std::mutex> lk(ctx->mu);
     NatProfEvent ev;
@@ -214,6 +221,14 @@ void prof_collect(nat_ctx* ctx)
 nat_status mapped_words(nat_ctx* ctx, size_t n, int32_t** host, int32_t** dev)
 {
     NatScratch& sc = scratch_of(ctx);
+    if (sc.noalloc) {
+        // host words only: the driver copies the device's flags into them
+        if (n > sc.mapped_ints)
+            return fail(NAT_E_BUDGET, "host words: need %zu, the fixed block holds %zu", n, sc.mapped_ints);
+        *host = sc.mapped;
+        *dev = nullptr;
+        return NAT_OK;
+    }
     if (n > sc.mapped_ints) {
         std::lock_guard<std::mutex> lk(ctx->capture_mu);  // as in workspace()
         if (sc.mapped) {

@@ -44,6 +44,13 @@ struct NatScratch {
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::vector<unsigned char> graph_key;
+    // Scratch of the allocation-free entry point: ext_ws is a fixed device
+    // block, pinned/mapped are fixed host blocks (pageable), and nothing
+    // grows -- a request that needs more fails with NAT_E_BUDGET.  The
+    // GMRES driver then polls the device's convergence flags by copies
+    // instead of mapped words, never captures a graph, and the solve takes
+    // no stage or profiling events.
+    bool noalloc = false;
 };
 
 namespace nat {
@@ -178,13 +185,21 @@ inline size_t carve_size(std::initializer_list<size_t> bytes) {
 // Events between the stages of one call (timing enabled), destroyed with it.
 struct StageEvents {
     hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool on = false;
     hipError_t create() {
         for (hipEvent_t& x : e) {
             hipError_t r = hipEventCreate(&x);
             if (r != hipSuccess)
                 return r;
         }
+        on = true;
         return hipSuccess;
+    }
+    // no-ops when the events were not created (stage times then read 0)
+    hipError_t record(int i, hipStream_t s) { return on ? hipEventRecord(e[i], s) : hipSuccess; }
+    hipError_t elapsed(int i, float* ms) {
+        *ms = 0.0f;
+        return on ? hipEventElapsedTime(ms, e[i], e[i + 1]) : hipSuccess;
     }
     ~StageEvents() {
         for (hipEvent_t x : e)

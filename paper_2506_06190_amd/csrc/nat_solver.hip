@@ -246,6 +246,9 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
                        bool use_graph, hipStream_t s)
 {
     const int32_t S = g.n_sys;
+    // allocation-free scratch: no mapped words; the flags are copied from
+    // the device after each run of iterations
+    const bool noalloc = scratch_of(ctx).noalloc;
     int32_t* hw = nullptr;
     int32_t* dw = nullptr;
     nat_status st = mapped_words(ctx, 16 + (size_t)S, &hw, &dw);
@@ -259,7 +262,7 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
     for (int32_t q = 0; q < S; ++q)
         hflag[q] = 1;
     g.host_progress = dw;
-    g.host_active = dw + 16;
+    g.host_active = dw ? dw + 16 : nullptr;
     g.items = T.d_items;
     g.n_items = T.d_nitems;
     g.iter = T.d_iter;
@@ -323,7 +326,7 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
     const int64_t sym_blocks = (sym_max_items + 3) / 4;
     const int32_t grid_sym = static_cast<int32_t>(sym_blocks < kGridSym ? (sym_blocks > 0 ? sym_blocks : 1) : kGridSym);
     hipGraphExec_t exec = nullptr;
-    if (use_graph && mv && !ctx->prof) {
+    if (use_graph && mv && !ctx->prof && !noalloc) {
         st = captured_run(ctx, g, mv_ord, mv_sym, kmv, grid_g, grid_mv, grid_sym, grid_k, lag, &exec);
         if (st != NAT_OK)
             exec = nullptr;  // fall back to direct launches
@@ -353,15 +356,22 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
         }
         if (launched >= g.mmax)
             break;
-        // wait until the device has finished all but the run just queued
-        const int32_t target = launched - lag;
-        int64_t spins = 0;
-        while (*hprog < target) {
-            if (++spins > (int64_t(1) << 26)) {
-                NAT_HIP(hipStreamSynchronize(s));
-                break;
+        if (noalloc) {
+            // wait for the whole run, then read the device's flags
+            NAT_HIP(hipMemcpyAsync(const_cast<int32_t*>(hflag), g.active, sizeof(int32_t) * (size_t)S,
+                                   hipMemcpyDeviceToHost, s));
+            NAT_HIP(hipStreamSynchronize(s));
+        } else {
+            // wait until the device has finished all but the run just queued
+            const int32_t target = launched - lag;
+            int64_t spins = 0;
+            while (*hprog < target) {
+                if (++spins > (int64_t(1) << 26)) {
+                    NAT_HIP(hipStreamSynchronize(s));
+                    break;
+                }
+                cpu_relax();
             }
-            cpu_relax();
         }
         buf ^= 1;
         st = refresh_lists(T, hflag, mv != nullptr, stg[buf], s, &ls);
@@ -771,14 +781,16 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         NAT_HIP(hipStreamSynchronize(s));
     }
 
-    // stage timing: events on the stream between the stages
+    // stage timing: events on the stream between the stages (none in the
+    // allocation-free form)
     StageEvents sev;
-    NAT_HIP(sev.create());
-    NAT_HIP(hipEventRecord(sev.e[0], s));
+    if (!scratch_of(ctx).noalloc)
+        NAT_HIP(sev.create());
+    NAT_HIP(sev.record(0, s));
 
     // ---- samples, points, Neumann data (Section 4.1.1) -----------------------
     NAT_HIP(launch_surface_batch(sbat, max_n, max_q, s));
-    NAT_HIP(hipEventRecord(sev.e[1], s));
+    NAT_HIP(sev.record(1, s));
 
     Sum32Batch sb{};
     sb.inst = T.d_inst;
@@ -847,7 +859,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         }
     }
 
-    NAT_HIP(hipEventRecord(sev.e[2], s));
+    NAT_HIP(sev.record(2, s));
 
     // ---- GMRES on (I/2 - K) p = b ---------------------------------------------
     // assembled operators of the systems that use them (the tuner's choice by
@@ -883,7 +895,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     if (st != NAT_OK)
         return st;
     NAT_HIP(launch_gmres_solution(g, s));
-    NAT_HIP(hipEventRecord(sev.e[3], s));
+    NAT_HIP(sev.record(3, s));
 
     // ---- surface evaluation (eq. BIE at the queries, Section 4.2) --------------
     if (max_q > 0) {
@@ -912,7 +924,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
             }
         }
     }
-    NAT_HIP(hipEventRecord(sev.e[4], s));
+    NAT_HIP(sev.record(4, s));
     for (int32_t i = 0; i < nj; ++i) {
         if (!jobs[i].p_samples)
             continue;
@@ -934,7 +946,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     NAT_HIP(hipStreamSynchronize(s));
     float t_ms[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int c = 0; c < 4; ++c)
-        NAT_HIP(hipEventElapsedTime(&t_ms[c], sev.e[c], sev.e[c + 1]));
+        NAT_HIP(sev.elapsed(c, &t_ms[c]));
     bool all_conv = true;
     for (int32_t q = 0; q < S; ++q) {
         const bool conv = hres[q] <= opts->gmres_tol;

@@ -116,6 +116,8 @@ _SIGS = {
     "nat_mcbem_samples": ([_P, C.c_int32, C.c_uint64, _P, _P, _P], C.c_int),
     "nat_mcbem_estimate": ([_P, _P, C.c_int32, _P, _P, _P, C.c_int32, C.c_int32, C.c_uint64,
                             C.POINTER(nat_mc_opts), _P, _P, _P, _P], C.c_int),
+    "nat_mcbem_estimate_noalloc": ([_P, _P, C.c_int32, _P, _P, _P, C.c_int32, C.c_int32, C.c_uint64,
+                                    C.POINTER(nat_mc_opts), _P, _P, _P, _P], C.c_int),
     "nat_mcbem_estimate_batch": ([_P, _P, C.c_int32, C.POINTER(nat_mc_opts), _P, _P], C.c_int),
     "nat_bem_assemble": ([_P, C.c_double, C.c_int32, C.POINTER(_P), _P], C.c_int),
     "nat_bem_solve": ([_P, _P, C.c_int32, C.c_int32, C.c_double, C.c_int32, _P, _P, _P], C.c_int),
@@ -395,6 +397,32 @@ def nat_mcbem_estimate(mesh: Mesh, v_n, k: Sequence[float], q_tri, q_bary, n_sam
         p_out = torch.empty((M, Q), dtype=torch.complex128, device=dev)
     reps = (nat_solve_report * M)()
     st = lib().nat_mcbem_estimate(
+        mesh.handle, _dptr(v_n, torch.complex128, (M, ng), "v_n"), M, k.ctypes.data_as(_P),
+        _dptr(q_tri, torch.int32, (Q,), "q_tri"), _dptr(q_bary, torch.float64, (Q, 2), "q_bary"),
+        Q, n_samples, C.c_uint64(seed), C.byref(opts),
+        _dptr(p_out, torch.complex128, (M, Q), "p_out"),
+        _dptr(p_samples, torch.complex128, (M, n_samples), "p_samples") if p_samples is not None else None,
+        C.cast(reps, _P), _stream(stream))
+    _check(st, allow=(NAT_E_NOCONV,) if allow_noconv else ())
+    return p_out, [r.as_dict() for r in reps]
+
+
+def nat_mcbem_estimate_noalloc(mesh: Mesh, v_n, k: Sequence[float], q_tri, q_bary, n_samples: int,
+                               seed: int, opts: Optional[nat_mc_opts] = None, p_out=None,
+                               p_samples=None, stream=None, allow_noconv: bool = False):
+    """nat_mcbem_estimate without allocation inside the call: p_out (and
+    p_samples) must be given as device tensors by the caller."""
+    import torch
+    if opts is None:
+        opts = nat_mc_opts_default()
+    if p_out is None:
+        raise ValueError("nat_mcbem_estimate_noalloc: p_out must be allocated by the caller")
+    k = np.ascontiguousarray(np.atleast_1d(k), dtype=np.float64)
+    M = len(k)
+    ng = mesh.n_tris if opts.layout == NAT_NEUMANN_PER_TRIANGLE else mesh.n_vertices
+    Q = int(q_tri.shape[0])
+    reps = (nat_solve_report * M)()
+    st = lib().nat_mcbem_estimate_noalloc(
         mesh.handle, _dptr(v_n, torch.complex128, (M, ng), "v_n"), M, k.ctypes.data_as(_P),
         _dptr(q_tri, torch.int32, (Q,), "q_tri"), _dptr(q_bary, torch.float64, (Q, 2), "q_bary"),
         Q, n_samples, C.c_uint64(seed), C.byref(opts),
