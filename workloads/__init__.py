@@ -189,6 +189,83 @@ def cubesphere_ellipsoid(seed: int, n_tri_target: int, base_radius: float = 0.1)
     return v, f, u
 
 
+def torus(major: float, minor: float, nu: int, nv: int):
+    """Closed torus about the y axis (tube centre circle of radius `major` in
+    the xz plane, tube radius `minor`), nu x nv quads split in two,
+    counter-clockwise seen from outside: (V, T)."""
+    u = 2.0 * np.pi * np.arange(nu) / nu
+    w = 2.0 * np.pi * np.arange(nv) / nv
+    U, Wv = np.meshgrid(u, w, indexing="ij")
+    rad = major + minor * np.cos(Wv)
+    v = np.stack([rad * np.cos(U), minor * np.sin(Wv), rad * np.sin(U)], -1).reshape(-1, 3)
+    I, J = np.meshgrid(np.arange(nu), np.arange(nv), indexing="ij")
+    a = I * nv + J
+    b = ((I + 1) % nu) * nv + J
+    c = ((I + 1) % nu) * nv + (J + 1) % nv
+    d = I * nv + (J + 1) % nv
+    f = np.concatenate([np.stack([a, b, c], -1).reshape(-1, 3),
+                        np.stack([a, c, d], -1).reshape(-1, 3)]).astype(np.int32)
+    # outward: away from the tube's centre circle
+    cen = v[f].mean(axis=1)
+    ang = np.arctan2(cen[:, 2], cen[:, 0])
+    ring = np.stack([major * np.cos(ang), np.zeros_like(ang), major * np.sin(ang)], -1)
+    nrm = np.cross(v[f[:, 1]] - v[f[:, 0]], v[f[:, 2]] - v[f[:, 0]])
+    bad = np.einsum("ij,ij->i", nrm, cen - ring) < 0
+    f[bad] = f[bad][:, [0, 2, 1]]
+    return v, f
+
+
+@dataclass
+class Scene:
+    """Several closed bodies in one mesh (Section 4.1.1's smooth-Neumann
+    scenes): vertices and triangles of every body concatenated, the body of
+    each triangle, and per-triangle Neumann data g (1 on the speaker's
+    vibrating patch, 0 on every other triangle)."""
+    vertices: np.ndarray
+    tris: np.ndarray
+    body: np.ndarray                 # (T,) int32: 0 speaker, 1.. passive bodies
+    g_tri: np.ndarray                # (T,) complex128
+
+
+def scene_speaker_torus(speaker_y: float, speaker_n: int = 12, torus_nu: int = 96,
+                        torus_nv: int = 40, major: float = 0.06, minor: float = 0.025,
+                        speaker_axes=(0.012, 0.02, 0.012), patch: float = 0.8) -> Scene:
+    """A small speaker (cube-sphere ellipsoid, long axis along y) at height
+    `speaker_y` on the axis of a passive torus (radius 0.06 m, tube 0.025 m,
+    its hole 0.035 m wide): the speaker moves along y through the hole as the
+    paper's phone moves along y past the cup (Section 6).  Only the
+    speaker's lower end vibrates: g = 1 on its triangles whose unit-sphere
+    direction has y < -patch, 0 elsewhere (per triangle)."""
+    us, fs = cubesphere_unit(speaker_n)
+    vs = us * np.asarray(speaker_axes)[None, :] + np.array([0.0, speaker_y, 0.0])[None, :]
+    vt, ft = torus(major, minor, torus_nu, torus_nv)
+    v = np.concatenate([vs, vt])
+    f = np.concatenate([fs, ft + len(vs)]).astype(np.int32)
+    body = np.concatenate([np.zeros(len(fs), np.int32), np.ones(len(ft), np.int32)])
+    c = us[fs].mean(axis=1)
+    c /= np.linalg.norm(c, axis=1, keepdims=True)
+    g = np.zeros(len(f), dtype=np.complex128)
+    g[:len(fs)][c[:, 1] < -patch] = 1.0
+    return Scene(v, f, body, g)
+
+
+def config_scenes(n_positions: int = 16, n_modes: int = 8, n_samples: int = 2048,
+                  n_queries: int = 4096, seed: int = BASE_SEED + 5, y_range=(-0.15, 0.15)):
+    """Speaker-torus scenes at evenly spaced speaker heights (the condition
+    variable v of Section 3.4), each with n_modes frequencies log-uniform
+    200 Hz - 8 kHz and per-triangle Neumann data (the same patch for every
+    frequency), random surface queries on all bodies."""
+    out = []
+    for i, y in enumerate(np.linspace(y_range[0], y_range[1], n_positions)):
+        sc = scene_speaker_torus(float(y))
+        k = wavenumber(log_uniform_freqs(n_modes, seed * 100 + i))
+        g = np.ascontiguousarray(np.repeat(sc.g_tri[None, :], n_modes, axis=0))
+        qt, qb = random_face_queries(len(sc.tris), n_queries, seed * 100 + i)
+        out.append(MCWorkload(f"scene{i}_y{y:+.3f}", sc.vertices, sc.tris, g, k, qt, qb, n_samples,
+                              seed * 100 + i, {"body": sc.body, "speaker_y": float(y)}))
+    return out
+
+
 # --------------------------------------------------------------------------
 # Neumann data, frequencies, queries
 # --------------------------------------------------------------------------
