@@ -240,6 +240,17 @@ def _percentiles(x):
 
 
 def run_served(nat, torch, ctx, args, dev):
+    """The request server on a Poisson stream over 64 resident meshes, in
+    three runs: (1) capacity, the whole stream submitted at once; (2) the
+    stream at 70 % of the served capacity (latency at the served form's own
+    operating point); (3) equal load: the first requests of the stream at
+    70 % of the plain per-solve form's capacity, run by both forms, so both
+    latencies are measured at one offered load below both capacities.  The
+    plain per-solve form runs the same requests one at a time on one stream
+    (FP32 compensated like the served form, direct launches, no batching, no
+    graph); its service times give its capacity.  Results of the served run
+    are compared with the plain ones bit for bit, and a sample of requests
+    with the FP64 oracle."""
     import numpy as np
     import workloads as W
     t0 = time.perf_counter()
@@ -281,6 +292,50 @@ def run_served(nat, torch, ctx, args, dev):
                               allow_noconv=True)
             op.close()
 
+    def served_run(sub, rate):
+        """Submit `sub` at Poisson times of the given rate (None: all at once);
+        returns (latencies, queue times, batch sizes, max iterations, span)."""
+        built = [build(rq) for rq in sub]
+        torch.cuda.synchronize()
+        arrive = np.cumsum([rq.gap for rq in sub]) / rate if rate else np.zeros(len(sub))
+        lat, qms, bsz, itm = [], [], [], []
+        t0 = time.perf_counter()
+        tickets = []
+        for i, b in enumerate(built):
+            d = arrive[i] - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            tickets.append(nat.nat_server_submit(srv, b))
+        for t in tickets:
+            st, r, _ = nat.nat_server_wait(srv, t)
+            if st not in (nat.NAT_OK, nat.NAT_E_NOCONV):
+                raise RuntimeError(f"served request failed: {nat.status_str(st)}")
+            lat.append(r["latency_ms"])
+            qms.append(r["queue_ms"])
+            bsz.append(r["batch_size"])
+            itm.append(r["max_iters"])
+        return built, lat, qms, bsz, itm, time.perf_counter() - t0
+
+    def plain_run(sub, rate, outs):
+        """The plain form on the same arrivals (None: back to back); returns
+        (latencies, service times, span)."""
+        arrive = np.cumsum([rq.gap for rq in sub]) / rate if rate else None
+        lat, svc = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, rq in enumerate(sub):
+            if arrive is not None:
+                d = arrive[i] - (time.perf_counter() - t0)
+                if d > 0:
+                    time.sleep(d)
+            ts = time.perf_counter()
+            plain(rq, outs[i])
+            torch.cuda.synchronize()
+            te = time.perf_counter()
+            svc.append(1e3 * (te - ts))
+            lat.append(1e3 * (te - t0 - (arrive[i] if arrive is not None else (ts - t0))))
+        return lat, svc, time.perf_counter() - t0
+
     srv = nat.Server(ctx, sopts)
     # warm-up: the first 16 requests
     warm = [build(rq) for rq in reqs[:16]]
@@ -288,74 +343,75 @@ def run_served(nat, torch, ctx, args, dev):
     for t in [nat.nat_server_submit(srv, b) for b in warm]:
         nat.nat_server_wait(srv, t)
     del warm
-    # capacity: the whole stream submitted at once
-    built = [build(rq) for rq in reqs]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    tickets = [nat.nat_server_submit(srv, b) for b in built]
-    for t in tickets:
-        nat.nat_server_wait(srv, t)
-    cap_s = time.perf_counter() - t0
+    # (1) served capacity
+    _, _, _, _, _, cap_s = served_run(reqs, None)
     capacity = len(reqs) / cap_s
     log(f"served capacity: {len(reqs)} requests in {cap_s:.2f} s")
-    # Poisson arrivals at 70 % of that capacity
+    # (2) the stream at 70 % of the served capacity
     rate = 0.7 * capacity
-    arrive = np.cumsum([rq.gap for rq in reqs]) / rate
-    built = [build(rq) for rq in reqs]
-    torch.cuda.synchronize()
-    lat, qms, bsz, iters_max = [], [], [], []
-    t0 = time.perf_counter()
-    tickets = []
-    for i, b in enumerate(built):
-        d = arrive[i] - (time.perf_counter() - t0)
-        if d > 0:
-            time.sleep(d)
-        tickets.append(nat.nat_server_submit(srv, b))
-    for t in tickets:
-        st, r, _ = nat.nat_server_wait(srv, t)
-        if st not in (nat.NAT_OK, nat.NAT_E_NOCONV):
-            raise RuntimeError(f"served request failed: {nat.status_str(st)}")
-        lat.append(r["latency_ms"])
-        qms.append(r["queue_ms"])
-        bsz.append(r["batch_size"])
-        iters_max.append(r["max_iters"])
-    span = time.perf_counter() - t0
+    built, lat, qms, bsz, itm, span = served_run(reqs, rate)
     stats = nat.nat_server_stats_read(srv)
-    srv.close()
     log(f"served Poisson run: {span:.2f} s")
-    # plain per-solve form on the same arrivals
+    # the plain per-solve form back to back: service times and capacity, and
+    # the served results against its outputs bit for bit
     outs = [torch.empty_like(b.p_out) for b in built]
-    torch.cuda.synchronize()
-    plat = []
-    t0 = time.perf_counter()
-    for i, rq in enumerate(reqs):
-        d = arrive[i] - (time.perf_counter() - t0)
-        if d > 0:
-            time.sleep(d)
-        plain(rq, outs[i])
-        torch.cuda.synchronize()
-        plat.append(1e3 * (time.perf_counter() - t0 - arrive[i]))
-    pspan = time.perf_counter() - t0
-    log(f"plain per-solve run: {pspan:.2f} s")
+    _, svc, pspan = plain_run(reqs, None, outs)
+    plain_capacity = len(reqs) / pspan
     equal = all(torch.equal(b.p_out, o) for b, o in zip(built, outs))
-    alg = sum(rq.pair_evals() for rq in reqs)
-    for r in R:
-        r["mesh"].close()
-    return {
+    log(f"plain per-solve back to back: {pspan:.2f} s")
+    # (3) equal load, below both capacities
+    n_eq = min(len(reqs), args.serve_equal_load_requests)
+    sub = reqs[:n_eq]
+    rate_eq = 0.7 * plain_capacity
+    _, lat_s, _, bsz_eq, _, _ = served_run(sub, rate_eq)
+    lat_p, _, _ = plain_run(sub, rate_eq, [torch.empty_like(b.p_out) for b in built[:n_eq]])
+    log(f"equal-load runs: {n_eq} requests at {rate_eq:.1f} req/s")
+    srv.close()
+    out = {
         "workload": f"{len(meshes)} resident cube-spheres T {min(len(m.tris) for m in meshes)}-"
                     f"{max(len(m.tris) for m in meshes)}, {len(reqs)} requests "
-                    f"({sum(rq.kind == 'dense' for rq in reqs)} dense), modes 1-64, Q 1-16k, N 512-2048",
+                    f"({sum(rq.kind == 'dense' for rq in reqs)} dense: meshes <= 8000 triangles, 1-4 "
+                    f"modes), modes 1-64, Q 1-16k, N 512-2048",
         "server": {"slots": sopts.n_slots, "max_batch": sopts.max_batch, "budget_gib": args.serve_budget_gib},
-        "capacity_req_per_s": round(capacity, 2), "arrival_rate_req_per_s": round(rate, 2),
-        "latency": _percentiles(lat), "queue": _percentiles(qms),
-        "solves_per_s": round(len(reqs) / span, 2),
-        "mc_pair_evals_per_s_at_capacity": alg / cap_s,
-        "batch_size_mean": round(float(np.mean(bsz)), 2), "gmres_iters_max": int(max(iters_max)),
+        "forms": {"served": "FP32 compensated, continuous batching over worker streams, graph-replayed GMRES",
+                  "plain_per_solve": "FP32 compensated, one request at a time on one stream, direct "
+                                     "launches, no batching, no graph"},
+        "capacity_req_per_s": round(capacity, 2),
+        "plain_capacity_req_per_s": round(plain_capacity, 2),
+        "at_served_operating_point": {
+            "arrival_rate_req_per_s": round(rate, 2), "latency": _percentiles(lat),
+            "queue": _percentiles(qms), "solves_per_s": round(len(reqs) / span, 2),
+            "batch_size_mean": round(float(np.mean(bsz)), 2), "gmres_iters_max": int(max(itm))},
+        "equal_load": {
+            "requests": n_eq, "arrival_rate_req_per_s": round(rate_eq, 2),
+            "note": "70 % of the plain form's capacity, below both forms' capacities",
+            "served_latency": _percentiles(lat_s), "plain_latency": _percentiles(lat_p),
+            "served_batch_size_mean": round(float(np.mean(bsz_eq)), 2)},
+        "plain_service_time": _percentiles(svc),
+        "mc_pair_evals_per_s_at_capacity": sum(rq.pair_evals() for rq in reqs) / cap_s,
         "stats": stats,
-        "plain_per_solve": {"latency": _percentiles(plat), "solves_per_s": round(len(reqs) / pspan, 2),
-                            "form": "one request at a time, direct launches, no batching"},
         "results_bitwise_equal_to_plain": bool(equal),
     }
+    if not args.no_cpu_baseline:
+        # the first few Monte-Carlo requests of at most 3e8 pair evaluations
+        # against the FP64 oracle (same seed, GMRES tol 1e-6, at most 200
+        # iterations)
+        from oracle import oracle as O
+        errs = []
+        for rq, b in zip(reqs, built):
+            if rq.kind != "mc" or rq.pair_evals() > 3e8 or len(errs) >= args.serve_oracle_requests:
+                continue
+            m = meshes[rq.mesh]
+            M = rq.n_modes
+            ref = O.mcbem(m.vertices, m.tris, m.g_vertex[rq.m0:rq.m0 + M], rq.k, m.q_tri[:rq.n_queries],
+                          m.q_b[:rq.n_queries], rq.n_samples, rq.seed, tol=1e-6)["p"]
+            got = b.p_out.cpu().numpy()
+            errs.append(max(max(rel_l2(got[q], ref[q]), rel_max(got[q], ref[q])) for q in range(M)))
+        out["vs_oracle"] = {"requests": len(errs), "max_error_per_request": [float(f"{e:.3g}") for e in errs],
+                            "bar": 1e-3, "error": "max over modes of rel L2 and element-wise"}
+    for r in R:
+        r["mesh"].close()
+    return out
 
 
 # ---------------------------------------------------------------- HBM traffic
@@ -625,6 +681,91 @@ def run_dense(nat, torch, ctx, args, dev):
             "iters_16rhs_max": max(r["iters"] for r in rep16)}
 
 
+def run_field(nat, torch, ctx, args, dev):
+    """Exterior field of the precision workload (20480-triangle ellipsoid, 32
+    modes, N = 1024): from the FP32 estimate's sample values, the pressure
+    and |p| at 10,000 random shell points per mode (1.5-3 R, the training
+    tuples) and on the 32 x 64 FFAT grid at 2 R.  Reports the field step's
+    time and pair-evals/s, the evaluation kernel's roofline, and the error of
+    each mode against the oracle on the first 500 shell points and the whole
+    FFAT grid."""
+    import numpy as np
+    import workloads as W
+    wl = W.config_precision()
+    mesh = nat.Mesh(ctx, wl.vertices, wl.tris)
+    g = torch.from_numpy(wl.g).to(dev)
+    ps = torch.empty((wl.n_modes, wl.n_samples), dtype=torch.complex128, device=dev)
+    nat.nat_mcbem_estimate(mesh, g, wl.k, torch.from_numpy(wl.q_tri).to(dev),
+                           torch.from_numpy(wl.q_b).to(dev), wl.n_samples, wl.seed, p_samples=ps)
+    P = 10000
+    pts, co = nat.nat_field_points(mesh, nat.NAT_FIELD_SHELL, P, 1, 1.5, 3.0, 11)
+    gpts, gco = nat.nat_field_points(mesh, nat.NAT_FIELD_FFAT_GRID, 32, 64, 2.0, 2.0, 0)
+    p = torch.empty((wl.n_modes, P), dtype=torch.complex128, device=dev)
+    a = torch.empty((wl.n_modes, P), dtype=torch.float64, device=dev)
+
+    def step():
+        nat.nat_field_points(mesh, nat.NAT_FIELD_SHELL, P, 1, 1.5, 3.0, 11, points=pts, coords=co)
+        nat.nat_mcbem_field(mesh, g, wl.k, ps, wl.n_samples, wl.seed, pts, p_out=p, abs_out=a)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    steps = max(args.steps, 10)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    pairs = wl.n_modes * P * wl.n_samples
+    nat.nat_profile_enable(ctx, True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    prof = nat.nat_profile_read(ctx)
+    nat.nat_profile_enable(ctx, False)
+    ev = prof.get("sum32_eval")
+    out = {"workload": "exterior field of the precision workload: 32 modes, N 1024, 10,000 shell "
+                       "points per mode at 1.5-3 R, and a 32 x 64 FFAT grid at 2 R",
+           "ms_per_step": round(1e3 * t, 4), "pair_evals_per_s": pairs / t,
+           "points_per_s": wl.n_modes * P / t}
+    if ev:
+        # one evaluation launch per step over all 32 modes
+        flops_per_launch = 47.0 * pairs * steps / ev["launches"]
+        achieved = flops_per_launch / (ev["avg_ms"] * 1e-3) / 1e12
+        out["roofline"] = {"bound": "alu", "kernel": "k_sum32<OP_EVAL> + k_reduce32 (sum32_eval)",
+                           "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                           "avg_launch_ms": round(ev["avg_ms"], 5), "launches": ev["launches"],
+                           "flops_per_launch": flops_per_launch,
+                           "credit": "47 flops per (point, sample, mode)"}
+    pg, ag = nat.nat_mcbem_field(mesh, g, wl.k, ps, wl.n_samples, wl.seed, gpts, want_abs=True)
+    torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        ref = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri[:0], wl.q_b[:0], wl.n_samples,
+                      wl.seed, tol=1e-12, want_samples=True)
+        xs = pts[:500].cpu().numpy()
+        xo, _ = O.field_points(wl.vertices, 0, 500, seed=11)
+        pts_ok = float(np.abs(xs - xo).max())
+        po = O.mcbem_field(wl.vertices, wl.tris, wl.g, wl.k, wl.n_samples, wl.seed, xo,
+                           ref["p_samples"])
+        got = p[:, :500].cpu().numpy()
+        xg, cg = O.field_points(wl.vertices, 1, 32, 64, r_lo=2.0)
+        pgo = O.mcbem_field(wl.vertices, wl.tris, wl.g, wl.k, wl.n_samples, wl.seed, xg,
+                            ref["p_samples"])
+        ffat = ag.cpu().numpy() * cg[None, :, 0]
+        ffat_o = np.abs(pgo) * cg[None, :, 0]
+        out["vs_oracle"] = {
+            "shell_points_max_coord_err": pts_ok,
+            "shell_rel_l2_per_mode": [float(f"{rel_l2(got[m], po[m]):.3g}") for m in range(wl.n_modes)],
+            "shell_elementwise_per_mode": [float(f"{rel_max(got[m], po[m]):.3g}")
+                                           for m in range(wl.n_modes)],
+            "ffat_map_rel_l2_per_mode": [float(f"{rel_l2(ffat[m], ffat_o[m]):.3g}")
+                                         for m in range(wl.n_modes)]}
+    mesh.close()
+    return out
+
+
 def run_precision(nat, torch, ctx, args, dev, with_plain=True):
     import numpy as np
     import workloads as W
@@ -636,9 +777,10 @@ def run_precision(nat, torch, ctx, args, dev, with_plain=True):
     p = torch.empty((wl.n_modes, wl.n_queries), dtype=torch.complex128, device=dev)
     alg = wl.pair_evals()
 
-    def step(prec):
+    def step(prec, flags=0):
         o = nat.nat_mc_opts_default()
         o.precision = prec
+        o.flags = flags
         return nat.nat_mcbem_estimate(mesh, g, wl.k, qt, qb, wl.n_samples, wl.seed, o, p_out=p)
 
     for _ in range(max(1, args.warmup)):
@@ -653,6 +795,17 @@ def run_precision(nat, torch, ctx, args, dev, with_plain=True):
     p32 = p.cpu().numpy()
     out = {"workload": wl.name, "fp32": {"value": alg / t32, "ms_per_step": 1e3 * t32},
            "gmres_iters": [r["iters"] for r in reps]}
+    # the same with the phase formed from FP64 positions and reduced in FP64
+    step(nat.NAT_PREC_FP32, nat.NAT_MC_FP64_PHASE)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, reps_ph = step(nat.NAT_PREC_FP32, nat.NAT_MC_FP64_PHASE)
+    torch.cuda.synchronize()
+    tph = (time.perf_counter() - t0) / steps
+    pph = p.cpu().numpy()
+    out["fp32_fp64_phase"] = {"value": alg / tph, "ms_per_step": 1e3 * tph,
+                              "gmres_iters": [r["iters"] for r in reps_ph]}
     if with_plain:
         step(nat.NAT_PREC_FP64)
         torch.cuda.synchronize()
@@ -677,6 +830,9 @@ def run_precision(nat, torch, ctx, args, dev, with_plain=True):
         out["fp32_vs_oracle_per_mode"] = {
             "rel_l2": [float(f"{rel_l2(p32[m], ref[m]):.3g}") for m in range(wl.n_modes)],
             "elementwise": [float(f"{rel_max(p32[m], ref[m]):.3g}") for m in range(wl.n_modes)]}
+        out["fp32_fp64_phase_vs_oracle_per_mode"] = {
+            "rel_l2": [float(f"{rel_l2(pph[m], ref[m]):.3g}") for m in range(wl.n_modes)],
+            "elementwise": [float(f"{rel_max(pph[m], ref[m]):.3g}") for m in range(wl.n_modes)]}
         if with_plain:
             out["plain_fp64_vs_oracle_per_mode"] = {
                 "rel_l2": [float(f"{rel_l2(p64[m], ref[m]):.3g}") for m in range(wl.n_modes)],
@@ -689,7 +845,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["batched", "precision", "served", "dense"], default="batched")
+    ap.add_argument("--workload", choices=["batched", "precision", "served", "dense", "field"],
+                    default="batched")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--pmc-pass", action="store_true")
     ap.add_argument("--ordered", action="store_true",
@@ -700,7 +857,9 @@ def main():
                     help="kernel-sum tiling: the autotuner's table (cache, else a sweep) or the defaults")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2506_06190_amd", "tune",
                                                          "kernel_sum_tiles.json"))
-    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-equal-load-requests", type=int, default=400)
+    ap.add_argument("--serve-oracle-requests", type=int, default=8)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-max-batch", type=int, default=64)
     ap.add_argument("--serve-budget-gib", type=int, default=64)
@@ -756,13 +915,14 @@ def main():
         out.update(res)
         out["precision"] = run_precision(nat, torch, ctx, args, dev, with_plain=not args.no_plain)
         out["dense"] = run_dense(nat, torch, ctx, args, dev)
+        out["field"] = run_field(nat, torch, ctx, args, dev)
         if not args.no_serve:
             out["served"] = run_served(nat, torch, ctx, args, dev)
     elif args.workload == "served":
         res = run_served(nat, torch, ctx, args, dev)
         out["metric"] = "served solves/s with p50/p99 latency"
         out["unit"] = "solves/s"
-        out["value"] = res["solves_per_s"]
+        out["value"] = res["at_served_operating_point"]["solves_per_s"]
         out["ms_per_step"] = None
         out["config"] = {"workload": res["workload"]}
         out["served"] = res
@@ -775,6 +935,13 @@ def main():
         out["dtype"] = "f64"
         out["config"] = {"workload": res["workload"]}
         out["dense"] = res
+    elif args.workload == "field":
+        res = run_field(nat, torch, ctx, args, dev)
+        out["metric"] = "exterior field pair-evals/s"
+        out["value"] = res["pair_evals_per_s"]
+        out["ms_per_step"] = res["ms_per_step"]
+        out["config"] = {"workload": res["workload"]}
+        out["field"] = res
     else:
         res = run_precision(nat, torch, ctx, args, dev, with_plain=not args.no_plain)
         out["value"] = res["fp32"]["value"]

@@ -128,6 +128,15 @@ typedef struct {
  * since r and e^{ikr} are the same both ways).  The two round differently;
  * both stay within the FP32 form's tolerance. */
 #define NAT_MC_ORDERED_SUM 16
+/* nat_mc_opts.flags: the phase k r of every FP32 kernel sum reduced in FP64:
+ * r refined from the FP64 sample and query positions (one Newton step on
+ * the FP32 distance), kr / (2 pi) formed and reduced to [0, 1) revolutions
+ * in FP64, only the reduced phase rounded to FP32 for the sine and cosine.
+ * Without it the phase is formed from FP32 positions relative to the mesh
+ * centre, whose rounding (about 6e-8 of the object size) bounds its
+ * accuracy at k times that.  Forces the matrix-free matvec; the plain FP64
+ * form ignores it. */
+#define NAT_MC_FP64_PHASE 32
 
 /* Per right-hand side report of a solve. */
 typedef struct {
@@ -159,7 +168,9 @@ size_t nat_ctx_bytes_in_use(const nat_ctx* ctx);
  * tris: host int32[n_tris][3], counter-clockwise seen from outside.  The
  * mesh must be closed and consistently oriented (every edge shared by
  * exactly two triangles with opposite directions), with no zero-area
- * triangle and positive enclosed volume.  Triangle areas, unit normals and
+ * triangle; it may hold several closed bodies (a scene: triangles that
+ * share a vertex belong to one body), each of which must enclose a
+ * positive volume (be oriented outward).  Triangle areas, unit normals and
  * the cumulative area table (sampling density 1/|Gamma|, Section 4.1.1) are
  * built in FP64 on the host and copied to the device with the geometry. */
 nat_status nat_mesh_create(nat_ctx* ctx, const double* vertices, int32_t n_vertices,
@@ -257,6 +268,48 @@ nat_status nat_mcbem_estimate_noalloc(nat_mesh* mesh, const double* v_n, int32_t
                                       int32_t n_queries, int32_t n_samples, uint64_t seed,
                                       const nat_mc_opts* opts, double* p_out, double* p_samples,
                                       nat_solve_report* report, void* stream);
+
+/* ---- exterior field (Section 3.4 training data, Section 3.1 FFAT maps) -- */
+
+/* Pressure at points outside the body from the Neumann data and the surface
+ * values of a Monte-Carlo estimate: the representation formula (eq. BIE
+ * with the free term c = 1 off the surface and no disk term)
+ *   p(x) = sum_j [|x - y_j| >= eps] w (dG/dn_j(x, y_j) p_j - G(x, y_j) g_j)
+ * over the estimate's own samples y_j (the same n_samples and seed give the
+ * same samples), w = |Gamma|/N.  p_samples: device complex
+ * [n_modes][n_samples], the p_samples output of nat_mcbem_estimate with the
+ * same v_n, k, n_samples, seed and opts.  points: device double
+ * [n_points][3] in the mesh's coordinates, meant to lie outside the body
+ * (as from nat_field_points).  p_out: device complex [n_modes][n_points];
+ * abs_out: device double [n_modes][n_points] with |p| (the training value),
+ * or NULL.  opts->precision picks the FP32 compensated or the plain FP64
+ * sums; the GMRES settings are unused.  A non-finite point returns
+ * NAT_E_INVALID.  Blocks until done. */
+nat_status nat_mcbem_field(nat_mesh* mesh, const double* v_n, int32_t n_modes, const double* k,
+                           const double* p_samples, int32_t n_samples, uint64_t seed,
+                           const double* points, int32_t n_points, const nat_mc_opts* opts,
+                           double* p_out, double* abs_out, void* stream);
+
+typedef enum {
+    NAT_FIELD_SHELL = 0,     /* random points in a shell (training data)                 */
+    NAT_FIELD_FFAT_GRID = 1  /* a grid of directions on one sphere (an FFAT map image)   */
+} nat_field_kind;
+
+/* Field points about the centre c of the mesh's bounding box, R = half its
+ * diagonal (the scene's bounding radius).
+ *  NAT_FIELD_SHELL: n_a points (n_b unused), point i with radius
+ *    r = R (r_lo + (r_hi - r_lo) u0), cos(theta) = 1 - 2 u1, phi = 2 pi u2,
+ *    u0..u2 from counters 3i..3i+2 of stream 5 of the counter generator of
+ *    the samples (a direction uniform on the sphere, a radius uniform in
+ *    [r_lo R, r_hi R]; Section 3.4 uses 1.5 and 3).
+ *  NAT_FIELD_FFAT_GRID: n_a x n_b points at radius r_lo R (r_hi unused),
+ *    point a n_b + b at theta = (a + 1/2) pi / n_a, phi = (b + 1/2) 2 pi / n_b
+ *    (an image with theta down the rows; Section 6 uses 64 x 32 maps).
+ * points: device double [n][3], x = c + r (sin th cos ph, sin th sin ph,
+ * cos th); coords: device double [n][3] with (r, theta, phi), or NULL.
+ * Stream-ordered. */
+nat_status nat_field_points(const nat_mesh* mesh, int32_t kind, int32_t n_a, int32_t n_b, double r_lo,
+                            double r_hi, uint64_t seed, double* points, double* coords, void* stream);
 
 /* One problem of a batch: the arguments of nat_mcbem_estimate. */
 typedef struct {

@@ -148,15 +148,25 @@ __global__ void __launch_bounds__(256) k_points_batch(const SurfBatch b)
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
+    const double ctr[3] = {J.cx, J.cy, J.cz};
+    double* x64 = q ? b.q64 + 3 * J.oq : b.x64 + 3 * J.on;
+    float* x32 = q ? b.q32 + 3 * J.oq : b.x32 + 3 * J.on;
+    if (q && J.fpts) {
+        // free field points, world coordinates
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double x = J.fpts[3 * i + d];
+            x64[(size_t)d * n + i] = x;
+            x32[(size_t)d * n + i] = static_cast<float>(x - ctr[d]);
+        }
+        return;
+    }
     const int32_t t = q ? J.q_tri[i] : b.tri[J.on + i];
     const double* bb = q ? J.q_bary + 2 * i : b.bary + 2 * (J.on + i);
     const double b1 = bb[0], b2 = bb[1];
     const double* v0 = J.V + 3 * J.T[3 * t + 0];
     const double* v1 = J.V + 3 * J.T[3 * t + 1];
     const double* v2 = J.V + 3 * J.T[3 * t + 2];
-    const double ctr[3] = {J.cx, J.cy, J.cz};
-    double* x64 = q ? b.q64 + 3 * J.oq : b.x64 + 3 * J.on;
-    float* x32 = q ? b.q32 + 3 * J.oq : b.x32 + 3 * J.on;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const double x = v0[d] + b1 * (v1[d] - v0[d]) + b2 * (v2[d] - v0[d]);
@@ -179,9 +189,15 @@ __global__ void __launch_bounds__(256) k_neumann_batch(const SurfBatch b)
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
+    double2* out = q ? b.gq + J.og_q : b.gj + J.og_n;
+    if (q && J.fpts) {
+        // no Neumann data off the surface (the disk term is zero there)
+        for (int32_t m = 0; m < J.M; ++m)
+            out[(size_t)m * n + i] = make_double2(0.0, 0.0);
+        return;
+    }
     const int32_t t = q ? J.q_tri[i] : b.tri[J.on + i];
     const double* bb = q ? J.q_bary + 2 * i : b.bary + 2 * (J.on + i);
-    double2* out = q ? b.gq + J.og_q : b.gj + J.og_n;
     if (b.layout == NAT_NEUMANN_PER_TRIANGLE) {
         for (int32_t m = 0; m < J.M; ++m)
             out[(size_t)m * n + i] = J.v_n[(size_t)m * J.ng + t];
@@ -208,7 +224,10 @@ __global__ void __launch_bounds__(256) k_checks_batch(const SurfBatch b)
     const double* vals = reinterpret_cast<const double*>(J.v_n);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_vals || i < J.Q; i += stride) {
-        if (i < J.Q) {
+        if (i < J.Q && J.fpts) {
+            if (!isfinite(J.fpts[3 * i]) || !isfinite(J.fpts[3 * i + 1]) || !isfinite(J.fpts[3 * i + 2]))
+                atomicOr(b.flags, 1);
+        } else if (i < J.Q) {
             const int32_t t = J.q_tri[i];
             const double b1 = J.q_bary[2 * i], b2 = J.q_bary[2 * i + 1];
             if (!(t >= 0 && t < J.nT && b1 >= 0.0 && b2 >= 0.0 && b1 + b2 <= 1.0 + 1e-12))
@@ -219,7 +238,81 @@ __global__ void __launch_bounds__(256) k_checks_batch(const SurfBatch b)
     }
 }
 
+// Field points around a scene (Section 3.4: random points in a shell of
+// radius r_lo R .. r_hi R about the bounding-box centre; Section 3.1: an
+// n_a x n_b grid of directions at radius r_lo R for FFAT maps).  Shell
+// point i draws u0, u1, u2 from counters 3i .. 3i+2 of stream 5:
+// r = R (r_lo + (r_hi - r_lo) u0), cos(theta) = 1 - 2 u1, phi = 2 pi u2.
+// Grid point a n_b + b: theta = (a + 1/2) pi / n_a, phi = (b + 1/2) 2 pi / n_b.
+__global__ void __launch_bounds__(256)
+k_field_points(double cx, double cy, double cz, double R, int32_t kind, int32_t n_a, int32_t n_b,
+               double r_lo, double r_hi, uint64_t seed, double* __restrict__ xyz,
+               double* __restrict__ coords)
+{
+    const int64_t n = kind == 0 ? (int64_t)n_a : (int64_t)n_a * n_b;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    constexpr double kPi = 3.141592653589793;
+    double r, th, ph;
+    if (kind == 0) {
+        const uint64_t c = 3ull * static_cast<uint64_t>(i);
+        const double u0 = unit_draw(seed, 5, c);
+        const double u1 = unit_draw(seed, 5, c + 1);
+        const double u2 = unit_draw(seed, 5, c + 2);
+        r = R * (r_lo + (r_hi - r_lo) * u0);
+        th = acos(1.0 - 2.0 * u1);
+        ph = 2.0 * kPi * u2;
+    } else {
+        const int32_t a = static_cast<int32_t>(i / n_b), b = static_cast<int32_t>(i % n_b);
+        r = R * r_lo;
+        th = (a + 0.5) * kPi / n_a;
+        ph = (b + 0.5) * 2.0 * kPi / n_b;
+    }
+    double st, ct, sp, cp;
+    sincos(th, &st, &ct);
+    sincos(ph, &sp, &cp);
+    xyz[3 * i + 0] = cx + r * (st * cp);
+    xyz[3 * i + 1] = cy + r * (st * sp);
+    xyz[3 * i + 2] = cz + r * ct;
+    if (coords) {
+        coords[3 * i + 0] = r;
+        coords[3 * i + 1] = th;
+        coords[3 * i + 2] = ph;
+    }
+}
+
+// out[i] = |z[i]|
+__global__ void __launch_bounds__(256) k_abs(const double2* __restrict__ z, int64_t n,
+                                             double* __restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) {
+        const double2 v = z[i];
+        out[i] = __builtin_sqrt(v.x * v.x + v.y * v.y);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_field_points(const nat_mesh* m, int32_t kind, int32_t n_a, int32_t n_b, double r_lo,
+                               double r_hi, uint64_t seed, double* xyz, double* coords, hipStream_t s)
+{
+    const int64_t n = kind == 0 ? (int64_t)n_a : (int64_t)n_a * n_b;
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_field_points, grid1(n), dim3(256), 0, s, m->center[0], m->center[1],
+                       m->center[2], 0.5 * m->diameter, kind, n_a, n_b, r_lo, r_hi, seed, xyz, coords);
+    return hipGetLastError();
+}
+
+hipError_t launch_abs(const double2* z, int64_t n, double* out, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_abs, grid1(n), dim3(256), 0, s, z, n, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_checks_batch(const SurfBatch& b, int64_t max_work, hipStream_t s)
 {
@@ -233,7 +326,8 @@ hipError_t launch_checks_batch(const SurfBatch& b, int64_t max_work, hipStream_t
 
 // 1 / c_q for every query of every instance: a query exactly on a mesh
 // vertex (two of its barycentric weights zero) or edge (one zero) takes the
-// mesh's free term there, any other point c_q = 1/2.
+// mesh's free term there, any other point c_q = 1/2; a free field point
+// c_q = 1.
 __global__ void __launch_bounds__(256)
 k_jump_batch(const SurfBatch b)
 {
@@ -241,6 +335,11 @@ k_jump_batch(const SurfBatch b)
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= X.Q)
         return;
+    if (X.fpts) {
+        // exterior point: the representation formula has c = 1
+        b.qfac[X.oq + i] = 1.0;
+        return;
+    }
     const int32_t t = X.q_tri[i];
     const double b1 = X.q_bary[2 * i], b2 = X.q_bary[2 * i + 1];
     const double w0 = 1.0 - b1 - b2;

@@ -33,6 +33,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kTS = 64;  // sources per LDS tile
 constexpr int kMB = 8;   // systems per mode group
+constexpr double kInv2Pi = 0.15915494309189535;  // 1 / (2 pi)
 
 __device__ __forceinline__ void two_sum_fold(float& hi, float& lo, float t)
 {
@@ -71,12 +72,17 @@ __device__ __forceinline__ float uniform_f(float x)
 //   EVAL    acc += e^{i th} (a/r + q (ikr - 1) b)
 // with th = 2 pi kappa r taken by the hardware sine and cosine, which take
 // revolutions (reduced by fract() first only for instances whose largest
-// kappa r exceeds kPhaseRevNoFract, RED).
-template <int OP, int MB, bool RED>
+// kappa r exceeds kPhaseRevNoFract, RED).  PH64: the FP64 phase -- r refined
+// from the FP64 positions (s_p64, t64) by one Newton step on the FP32
+// distance, r + (r64^2 - r^2) / (2 r), and kappa r reduced to [0, 1)
+// revolutions in FP64 before the FP32 sine and cosine.
+template <int OP, int MB, bool RED, bool PH64>
 __device__ __forceinline__ void tile_pairs(const float (&s_pos)[6][kTS],
                                            const float2 (*s_a)[kMB], const float2 (*s_b)[kMB],
                                            const float2 (*s_kb)[kMB], float tx, float ty,
                                            float tz, float eps2, const float (&kap)[kMB],
+                                           const double (*s_p64)[kTS], const double (&t64)[3],
+                                           const double (&kap64)[kMB],
                                            float (&ar)[kMB], float (&ai)[kMB])
 {
     constexpr bool kA = (OP == OP_RHS || OP == OP_EVAL);
@@ -103,9 +109,18 @@ __device__ __forceinline__ void tile_pairs(const float (&s_pos)[6][kTS],
             const float dn = fmaf(dz, s_pos[5][c], fmaf(dy, s_pos[4][c], dx * s_pos[3][c]));
             q = dn * (rinv * rinv) * rinv;
         }
+        double rd = 0.0;
+        if (PH64) {
+            const double ex = s_p64[0][c] - t64[0];
+            const double ey = s_p64[1][c] - t64[1];
+            const double ez = s_p64[2][c] - t64[2];
+            const double rr = static_cast<double>(r);
+            rd = fma(fma(ez, ez, fma(ey, ey, ex * ex)) - rr * rr, static_cast<double>(0.5f * rinv), rr);
+        }
 #pragma unroll
         for (int mm = 0; mm < MB; ++mm) {
-            const float ph = RED ? __builtin_amdgcn_fractf(r * kap[mm]) : r * kap[mm];
+            const float ph = PH64 ? static_cast<float>(__builtin_amdgcn_fract(kap64[mm] * rd))
+                                  : (RED ? __builtin_amdgcn_fractf(r * kap[mm]) : r * kap[mm]);
             const float sn = __builtin_amdgcn_sinf(ph);
             const float cs = __builtin_amdgcn_cosf(ph);
             if (OP == OP_RHS) {
@@ -133,12 +148,32 @@ __device__ __forceinline__ void tile_pairs(const float (&s_pos)[6][kTS],
     }
 }
 
-template <int OP>
+// The tile's pairs for the group width rounded up to 1, 2, 4 or 8 modes.
+template <int OP, bool RED, bool PH64>
+__device__ __forceinline__ void tile_width(int32_t nm, const float (&s_pos)[6][kTS],
+                                           const float2 (*s_a)[kMB], const float2 (*s_b)[kMB],
+                                           const float2 (*s_kb)[kMB], float tx, float ty, float tz,
+                                           float eps2, const float (&kap)[kMB],
+                                           const double (*s_p64)[kTS], const double (&t64)[3],
+                                           const double (&kap64)[kMB], float (&ar)[kMB], float (&ai)[kMB])
+{
+    if (nm > 4)
+        tile_pairs<OP, 8, RED, PH64>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, s_p64, t64, kap64, ar, ai);
+    else if (nm > 2)
+        tile_pairs<OP, 4, RED, PH64>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, s_p64, t64, kap64, ar, ai);
+    else if (nm > 1)
+        tile_pairs<OP, 2, RED, PH64>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, s_p64, t64, kap64, ar, ai);
+    else
+        tile_pairs<OP, 1, RED, PH64>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, s_p64, t64, kap64, ar, ai);
+}
+
+template <int OP, bool PH64>
 __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
 {
     constexpr bool kA = (OP == OP_RHS || OP == OP_EVAL);
     constexpr bool kB = (OP == OP_MATVEC || OP == OP_EVAL);
     __shared__ float s_pos[6][kTS];
+    __shared__ double s_pos64[PH64 ? 3 : 1][kTS];
     __shared__ float2 s_a[kA ? kTS : 1][kMB];
     __shared__ float2 s_b[kB ? kTS : 1][kMB];
     __shared__ float2 s_kb[kB ? kTS : 1][kMB];
@@ -163,6 +198,7 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
 
         int32_t sys[kMB];
         float kap[kMB], kk[kMB];
+        double kap64[kMB];
         bool any = false;
 #pragma unroll
         for (int mm = 0; mm < kMB; ++mm) {
@@ -172,6 +208,7 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
             any |= mm < nm && (!p.active || p.active[sys[mm]]);
             kap[mm] = uniform_f(S.kappa32);
             kk[mm] = uniform_f(S.k32);
+            kap64[mm] = PH64 ? S.k * kInv2Pi : 0.0;
         }
         if (!any)
             continue;  // uniform across the workgroup
@@ -183,6 +220,13 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
         const bool wave_live =
             __builtin_amdgcn_readfirstlane(tile * kThreads + (tid & ~63)) < NT;
         const float tx = t32[ic], ty = t32[NT + ic], tz = t32[2 * NT + ic];
+        double t64[3] = {0.0, 0.0, 0.0};
+        if (PH64) {
+            const double* tp = (OP == OP_EVAL) ? I.q64 : I.s64;
+            t64[0] = tp[ic];
+            t64[1] = tp[NT + ic];
+            t64[2] = tp[2 * NT + ic];
+        }
         const float eps2 = I.eps2;
         const bool red = __builtin_amdgcn_readfirstlane(I.phase_fract) != 0;
 
@@ -204,6 +248,12 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
                                 : I.sn32[(size_t)(row - 3) * NS + j0 + c];
                 s_pos[row][c] = v;
             }
+            if (PH64) {
+                for (int e = tid; e < 3 * kTS; e += kThreads) {
+                    const int row = e / kTS, c = e % kTS;
+                    s_pos64[row][c] = c < cnt ? I.s64[(size_t)row * NS + j0 + c] : 0.0;
+                }
+            }
             for (int e = tid; e < kMB * kTS; e += kThreads) {
                 const int mm = e / kTS, c = e % kTS;
                 const bool ok = c < cnt && mm < nm;
@@ -224,25 +274,15 @@ __global__ void __launch_bounds__(kThreads) k_sum32(const Sum32Batch p)
                 ar[mm] = ai[mm] = 0.0f;
             if (!wave_live)
                 ;
-            else if (red) {
-                if (nm > 4)
-                    tile_pairs<OP, 8, true>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
-                else if (nm > 2)
-                    tile_pairs<OP, 4, true>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
-                else if (nm > 1)
-                    tile_pairs<OP, 2, true>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
-                else
-                    tile_pairs<OP, 1, true>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
-            } else {
-                if (nm > 4)
-                    tile_pairs<OP, 8, false>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
-                else if (nm > 2)
-                    tile_pairs<OP, 4, false>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
-                else if (nm > 1)
-                    tile_pairs<OP, 2, false>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
-                else
-                    tile_pairs<OP, 1, false>(s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, ar, ai);
-            }
+            else if (PH64)
+                tile_width<OP, false, true>(nm, s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, s_pos64,
+                                            t64, kap64, ar, ai);
+            else if (red)
+                tile_width<OP, true, false>(nm, s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, s_pos64,
+                                            t64, kap64, ar, ai);
+            else
+                tile_width<OP, false, false>(nm, s_pos, s_a, s_b, s_kb, tx, ty, tz, eps2, kap, s_pos64,
+                                             t64, kap64, ar, ai);
 #pragma unroll
             for (int mm = 0; mm < kMB; ++mm) {
                 two_sum_fold(hr[mm], lr[mm], ar[mm]);
@@ -450,15 +490,25 @@ hipError_t launch_sum32_batch(int32_t op, const Sum32Batch& p, int32_t grid, hip
 {
     if (grid <= 0)
         return hipSuccess;
+    const bool ph64 = p.phase64 != 0;
     switch (op) {
     case OP_RHS:
-        launch_k(k_sum32<OP_RHS>, dim3(grid), dim3(kThreads), 0, s, ev.start, ev.stop, p);
+        if (ph64)
+            launch_k(k_sum32<OP_RHS, true>, dim3(grid), dim3(kThreads), 0, s, ev.start, ev.stop, p);
+        else
+            launch_k(k_sum32<OP_RHS, false>, dim3(grid), dim3(kThreads), 0, s, ev.start, ev.stop, p);
         break;
     case OP_MATVEC:
-        launch_k(k_sum32<OP_MATVEC>, dim3(grid), dim3(kThreads), 0, s, ev.start, ev.stop, p);
+        if (ph64)
+            launch_k(k_sum32<OP_MATVEC, true>, dim3(grid), dim3(kThreads), 0, s, ev.start, ev.stop, p);
+        else
+            launch_k(k_sum32<OP_MATVEC, false>, dim3(grid), dim3(kThreads), 0, s, ev.start, ev.stop, p);
         break;
     default:
-        launch_k(k_sum32<OP_EVAL>, dim3(grid), dim3(kThreads), 0, s, ev.start, ev.stop, p);
+        if (ph64)
+            launch_k(k_sum32<OP_EVAL, true>, dim3(grid), dim3(kThreads), 0, s, ev.start, ev.stop, p);
+        else
+            launch_k(k_sum32<OP_EVAL, false>, dim3(grid), dim3(kThreads), 0, s, ev.start, ev.stop, p);
         break;
     }
     return hipGetLastError();

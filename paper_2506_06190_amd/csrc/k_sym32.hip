@@ -33,6 +33,7 @@ namespace {
 
 constexpr int kMB = 8;  // systems per mode group
 constexpr int kWaves = 4;
+constexpr double kInv2Pi = 0.15915494309189535;  // 1 / (2 pi)
 
 __device__ __forceinline__ float uniform_f(float x)
 {
@@ -62,19 +63,30 @@ __device__ __forceinline__ float rot_from_next(float x)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x134, 0xf, 0xf, true));
 }
 
+// FP64 positions of the item's targets and staged sources, for the FP64
+// phase (PH64): r refined from them by one Newton step on the FP32
+// distance, r + (r64^2 - r^2) / (2 r), and k r / (2 pi) reduced to [0, 1)
+// revolutions in FP64 before the FP32 sine and cosine.
+struct Pos64 {
+    const double (*src)[64];   // LDS [3][64], the staged sub-tile
+    double tx, ty, tz;         // the lane's target
+};
+
 // The steps c0 <= c < c1 of one item for the first MB modes of the group.
 // BOTH: the step feeds the column sums too; RED: reduce the phase with
-// fract() first.  Both directions share f = e^{ikr} (ikr - 1):
+// fract() first; PH64: form and reduce the phase in FP64 (then RED is
+// moot).  Both directions share f = e^{ikr} (ikr - 1):
 //   row:    acc_i += q_ij f b_j        column: col_j += q_ji f b_i
 // The column sum of the source a lane meets travels with that source: at
 // step c lane l meets source (l + c) mod 64, so the sums move one lane down
 // before each step's term is added; after the last step lane l holds the
 // sum of source (l + c1 - 1) mod 64.
-template <int MB, bool RED>
+template <int MB, bool RED, bool PH64>
 __device__ __forceinline__ void sym_steps(int c0, int c1, bool both, const float (&sp)[6][64],
                                           const float2 (&sd)[kMB][64], float tx, float ty, float tz,
                                           float tnx, float tny, float tnz, const float2 (&bi)[MB],
                                           float eps2, const float (&kap)[kMB], const float (&kk)[kMB],
+                                          const Pos64& p64, const double (&kap64)[kMB],
                                           float (&ar)[MB], float (&ai)[MB], float (&cr)[MB], float (&ci)[MB])
 {
     const int lane = threadIdx.x & 63;
@@ -89,10 +101,19 @@ __device__ __forceinline__ void sym_steps(int c0, int c1, bool both, const float
         const float r3 = (rinv * rinv) * rinv;
         const float qij = fmaf(dz, sp[5][jl], fmaf(dy, sp[4][jl], dx * sp[3][jl])) * r3;
         const float qji = -(fmaf(dz, tnz, fmaf(dy, tny, dx * tnx)) * r3);
+        double rd = 0.0;
+        if (PH64) {
+            const double ex = p64.src[0][jl] - p64.tx;
+            const double ey = p64.src[1][jl] - p64.ty;
+            const double ez = p64.src[2][jl] - p64.tz;
+            const double rr = static_cast<double>(r);
+            rd = fma(fma(ez, ez, fma(ey, ey, ex * ex)) - rr * rr, static_cast<double>(0.5f * rinv), rr);
+        }
 #pragma unroll
         for (int mm = 0; mm < MB; ++mm) {
             const float2 bj = sd[mm][jl];
-            const float ph = RED ? __builtin_amdgcn_fractf(r * kap[mm]) : r * kap[mm];
+            const float ph = PH64 ? static_cast<float>(__builtin_amdgcn_fract(kap64[mm] * rd))
+                                  : (RED ? __builtin_amdgcn_fractf(r * kap[mm]) : r * kap[mm]);
             const float sn = __builtin_amdgcn_sinf(ph);
             const float cs = __builtin_amdgcn_cosf(ph);
             const float rk = r * kk[mm];
@@ -113,11 +134,12 @@ __device__ __forceinline__ void sym_steps(int c0, int c1, bool both, const float
     }
 }
 
-template <int MB, bool RED>
+template <int MB, bool RED, bool PH64>
 __device__ __forceinline__ void sym_item(const SymBatch& p, const InstDev& I, const int32_t (&sys)[kMB],
                                          int32_t nm, const float (&kap)[kMB], const float (&kk)[kMB],
-                                         int32_t P, int32_t Q, const float (&sp)[6][64],
-                                         const float2 (&sd)[kMB][64])
+                                         const double (&kap64)[kMB], int32_t P, int32_t Q,
+                                         const float (&sp)[6][64], const float2 (&sd)[kMB][64],
+                                         const double (*sp64)[64])
 {
     const int lane = threadIdx.x & 63;
     const int32_t n = I.n;
@@ -130,6 +152,12 @@ __device__ __forceinline__ void sym_item(const SymBatch& p, const InstDev& I, co
     const float tnx = oki ? I.sn32[ic] : 0.0f;
     const float tny = oki ? I.sn32[n + ic] : 0.0f;
     const float tnz = oki ? I.sn32[2 * n + ic] : 0.0f;
+    Pos64 p64{sp64, 0.0, 0.0, 0.0};
+    if (PH64) {
+        p64.tx = I.s64[ic];
+        p64.ty = I.s64[n + ic];
+        p64.tz = I.s64[2 * n + ic];
+    }
     float2 bi[MB];
     float ar[MB], ai[MB], cr[MB], ci[MB];
 #pragma unroll
@@ -142,10 +170,13 @@ __device__ __forceinline__ void sym_item(const SymBatch& p, const InstDev& I, co
     // and at step 32 each lane of a pair adds its own row term
     const int32_t c_last = (P == Q) ? 31 : 63;
     if (P == Q) {
-        sym_steps<MB, RED>(1, 32, true, sp, sd, tx, ty, tz, tnx, tny, tnz, bi, eps2, kap, kk, ar, ai, cr, ci);
-        sym_steps<MB, RED>(32, 33, false, sp, sd, tx, ty, tz, tnx, tny, tnz, bi, eps2, kap, kk, ar, ai, cr, ci);
+        sym_steps<MB, RED, PH64>(1, 32, true, sp, sd, tx, ty, tz, tnx, tny, tnz, bi, eps2, kap, kk, p64,
+                                 kap64, ar, ai, cr, ci);
+        sym_steps<MB, RED, PH64>(32, 33, false, sp, sd, tx, ty, tz, tnx, tny, tnz, bi, eps2, kap, kk, p64,
+                                 kap64, ar, ai, cr, ci);
     } else {
-        sym_steps<MB, RED>(0, 64, true, sp, sd, tx, ty, tz, tnx, tny, tnz, bi, eps2, kap, kk, ar, ai, cr, ci);
+        sym_steps<MB, RED, PH64>(0, 64, true, sp, sd, tx, ty, tz, tnx, tny, tnz, bi, eps2, kap, kk, p64,
+                                 kap64, ar, ai, cr, ci);
     }
     // the column sum of source l sits in lane l - c_last
     const int src_lane = (lane - c_last) & 63;
@@ -171,30 +202,35 @@ __device__ __forceinline__ void sym_item(const SymBatch& p, const InstDev& I, co
 
 // One item with the group width as a compile-time constant, so no padded
 // mode costs work.
-template <bool RED>
+template <bool RED, bool PH64>
 __device__ __forceinline__ void dispatch_item(const SymBatch& p, const InstDev& I, const int32_t (&sys)[kMB],
                                               int32_t nm, const float (&kap)[kMB], const float (&kk)[kMB],
-                                              int32_t P, int32_t Q, const float (&sp)[6][64],
-                                              const float2 (&sd)[kMB][64])
+                                              const double (&kap64)[kMB], int32_t P, int32_t Q,
+                                              const float (&sp)[6][64], const float2 (&sd)[kMB][64],
+                                              const double (*sp64)[64])
 {
     switch (nm) {
-    case 8: sym_item<8, RED>(p, I, sys, nm, kap, kk, P, Q, sp, sd); break;
-    case 7: sym_item<7, RED>(p, I, sys, nm, kap, kk, P, Q, sp, sd); break;
-    case 6: sym_item<6, RED>(p, I, sys, nm, kap, kk, P, Q, sp, sd); break;
-    case 5: sym_item<5, RED>(p, I, sys, nm, kap, kk, P, Q, sp, sd); break;
-    case 4: sym_item<4, RED>(p, I, sys, nm, kap, kk, P, Q, sp, sd); break;
-    case 3: sym_item<3, RED>(p, I, sys, nm, kap, kk, P, Q, sp, sd); break;
-    case 2: sym_item<2, RED>(p, I, sys, nm, kap, kk, P, Q, sp, sd); break;
-    default: sym_item<1, RED>(p, I, sys, nm, kap, kk, P, Q, sp, sd); break;
+    case 8: sym_item<8, RED, PH64>(p, I, sys, nm, kap, kk, kap64, P, Q, sp, sd, sp64); break;
+    case 7: sym_item<7, RED, PH64>(p, I, sys, nm, kap, kk, kap64, P, Q, sp, sd, sp64); break;
+    case 6: sym_item<6, RED, PH64>(p, I, sys, nm, kap, kk, kap64, P, Q, sp, sd, sp64); break;
+    case 5: sym_item<5, RED, PH64>(p, I, sys, nm, kap, kk, kap64, P, Q, sp, sd, sp64); break;
+    case 4: sym_item<4, RED, PH64>(p, I, sys, nm, kap, kk, kap64, P, Q, sp, sd, sp64); break;
+    case 3: sym_item<3, RED, PH64>(p, I, sys, nm, kap, kk, kap64, P, Q, sp, sd, sp64); break;
+    case 2: sym_item<2, RED, PH64>(p, I, sys, nm, kap, kk, kap64, P, Q, sp, sd, sp64); break;
+    default: sym_item<1, RED, PH64>(p, I, sys, nm, kap, kk, kap64, P, Q, sp, sd, sp64); break;
     }
 }
 
 // 5 waves per SIMD (at most 102 VGPRs): measured faster than 4 or 6 on the
-// batched workload, with no extra instructions in the step loop
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 5))) k_sym32(const SymBatch p)
+// batched workload, with no extra instructions in the step loop.  PH64:
+// the FP64-phase form, which also stages the sources' FP64 positions.
+template <bool PH64>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PH64 ? 4 : 5, 5)))
+k_sym32(const SymBatch p)
 {
     __shared__ float s_pos[kWaves][6][64];
     __shared__ float2 s_dat[kWaves][kMB][64];
+    __shared__ double s_pos64[PH64 ? kWaves : 1][3][64];
     const int32_t tid = threadIdx.x, lane = tid & 63;
     const int32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t n_diag = p.n_items[0];
@@ -230,6 +266,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 5))
         const InstDev& I = p.inst[__builtin_amdgcn_readfirstlane(G.inst)];
         int32_t sys[kMB];
         float kap[kMB], kk[kMB];
+        double kap64[kMB];
         bool any = false;
 #pragma unroll
         for (int mm = 0; mm < kMB; ++mm) {
@@ -239,6 +276,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 5))
             any |= mm < nm && (!p.active || p.active[sys[mm]]);
             kap[mm] = uniform_f(S.kappa32);
             kk[mm] = uniform_f(S.k32);
+            kap64[mm] = PH64 ? S.k * kInv2Pi : 0.0;
         }
         if (!any)
             continue;  // uniform across the wave
@@ -257,6 +295,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 5))
             s_pos[wave][3][lane] = ok ? I.sn32[j] : 0.0f;
             s_pos[wave][4][lane] = ok ? I.sn32[n + j] : 0.0f;
             s_pos[wave][5][lane] = ok ? I.sn32[2 * n + j] : 0.0f;
+            if (PH64) {
+                s_pos64[wave][0][lane] = ok ? I.s64[j] : 0.0;
+                s_pos64[wave][1][lane] = ok ? I.s64[n + j] : 0.0;
+                s_pos64[wave][2][lane] = ok ? I.s64[2 * n + j] : 0.0;
+            }
 #pragma unroll
             for (int mm = 0; mm < kMB; ++mm) {
                 const float2 b = (ok && mm < nm) ? p.b32[p.sys[sys[mm]].off_n + j] : make_float2(0.0f, 0.0f);
@@ -267,10 +310,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 5))
         __builtin_amdgcn_wave_barrier();
         {
             const bool red = __builtin_amdgcn_readfirstlane(I.phase_fract) != 0;
-            if (red)
-                dispatch_item<true>(p, I, sys, nm, kap, kk, P, Q, s_pos[wave], s_dat[wave]);
+            const double (*sp64)[64] = s_pos64[PH64 ? wave : 0];
+            if (PH64)
+                dispatch_item<false, true>(p, I, sys, nm, kap, kk, kap64, P, Q, s_pos[wave], s_dat[wave],
+                                           sp64);
+            else if (red)
+                dispatch_item<true, false>(p, I, sys, nm, kap, kk, kap64, P, Q, s_pos[wave], s_dat[wave],
+                                           sp64);
             else
-                dispatch_item<false>(p, I, sys, nm, kap, kk, P, Q, s_pos[wave], s_dat[wave]);
+                dispatch_item<false, false>(p, I, sys, nm, kap, kk, kap64, P, Q, s_pos[wave], s_dat[wave],
+                                            sp64);
         }
     }
 }
@@ -281,7 +330,10 @@ hipError_t launch_sym32(const SymBatch& p, int32_t grid, hipStream_t s, const Pr
 {
     if (grid <= 0)
         return hipSuccess;
-    launch_k(k_sym32, dim3(grid), dim3(256), 0, s, ev.start, ev.stop, p);
+    if (p.phase64)
+        launch_k(k_sym32<true>, dim3(grid), dim3(256), 0, s, ev.start, ev.stop, p);
+    else
+        launch_k(k_sym32<false>, dim3(grid), dim3(256), 0, s, ev.start, ev.stop, p);
     return hipGetLastError();
 }
 

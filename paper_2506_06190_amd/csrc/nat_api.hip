@@ -575,13 +575,49 @@ static nat_status validate_topology(const double* vertices, int32_t n_vertices, 
     return NAT_OK;
 }
 
-// Areas, unit normals and the running area sum in the written operation order
-// (no contraction in this file).  Rejects zero-area triangles and a
-// non-positive enclosed volume.
-static nat_status mesh_geometry(const double* V, int32_t n_tris, const int32_t* tris, double* area,
-                                double* normal, double* cdf)
+// Connected bodies of a mesh: component label per triangle (triangles that
+// share a vertex are in one body), by union-find over the vertices.
+static int32_t mesh_bodies(int32_t n_vertices, int32_t n_tris, const int32_t* tris,
+                           std::vector<int32_t>& body)
 {
-    double run = 0.0, vol6 = 0.0;
+    std::vector<int32_t> up(n_vertices);
+    for (int32_t v = 0; v < n_vertices; ++v)
+        up[v] = v;
+    auto root = [&](int32_t v) {
+        while (up[v] != v) {
+            up[v] = up[up[v]];
+            v = up[v];
+        }
+        return v;
+    };
+    for (int32_t t = 0; t < n_tris; ++t)
+        for (int c = 1; c < 3; ++c) {
+            const int32_t a = root(tris[3 * t]), b = root(tris[3 * t + c]);
+            if (a != b)
+                up[a < b ? b : a] = a < b ? a : b;
+        }
+    std::vector<int32_t> label(n_vertices, -1);
+    int32_t n = 0;
+    body.resize(n_tris);
+    for (int32_t t = 0; t < n_tris; ++t) {
+        const int32_t r = root(tris[3 * t]);
+        if (label[r] < 0)
+            label[r] = n++;
+        body[t] = label[r];
+    }
+    return n;
+}
+
+// Areas, unit normals and the running area sum in the written operation order
+// (no contraction in this file).  Rejects zero-area triangles and a body
+// (connected component) whose enclosed volume is not positive.
+static nat_status mesh_geometry(const double* V, int32_t n_vertices, int32_t n_tris, const int32_t* tris,
+                                double* area, double* normal, double* cdf)
+{
+    std::vector<int32_t> body;
+    const int32_t n_bodies = mesh_bodies(n_vertices, n_tris, tris, body);
+    std::vector<double> vol6(n_bodies, 0.0);
+    double run = 0.0;
     for (int32_t t = 0; t < n_tris; ++t) {
         const double* v0 = V + 3 * (size_t)tris[3 * t + 0];
         const double* v1 = V + 3 * (size_t)tris[3 * t + 1];
@@ -599,11 +635,13 @@ static nat_status mesh_geometry(const double* V, int32_t n_tris, const int32_t* 
         normal[3 * t + 2] = c[2] / len;
         run = run + area[t];
         cdf[t] = run;
-        vol6 += v0[0] * (v1[1] * v2[2] - v1[2] * v2[1]) - v0[1] * (v1[0] * v2[2] - v1[2] * v2[0]) +
-                v0[2] * (v1[0] * v2[1] - v1[1] * v2[0]);
+        vol6[body[t]] += v0[0] * (v1[1] * v2[2] - v1[2] * v2[1]) - v0[1] * (v1[0] * v2[2] - v1[2] * v2[0]) +
+                         v0[2] * (v1[0] * v2[1] - v1[1] * v2[0]);
     }
-    if (!(vol6 > 0.0))
-        return fail(NAT_E_INVALID, "mesh: enclosed volume is not positive (inward orientation?)");
+    for (int32_t b = 0; b < n_bodies; ++b)
+        if (!(vol6[b] > 0.0))
+            return fail(NAT_E_INVALID, "mesh: body %d of %d encloses no positive volume (inward orientation?)",
+                        b, n_bodies);
     return NAT_OK;
 }
 
@@ -734,7 +772,7 @@ nat_status nat_mesh_free_terms(const double* vertices, int32_t n_vertices, const
     if (st != NAT_OK)
         return st;
     std::vector<double> a(n_tris), nn(3 * (size_t)n_tris), c(n_tris);
-    st = mesh_geometry(vertices, n_tris, tris, a.data(), nn.data(), c.data());
+    st = mesh_geometry(vertices, n_vertices, n_tris, tris, a.data(), nn.data(), c.data());
     if (st != NAT_OK)
         return st;
     mesh_free_terms(vertices, n_vertices, tris, n_tris, c_vert, c_edge);
@@ -748,7 +786,7 @@ nat_status nat_mesh_validate(const double* vertices, int32_t n_vertices, const i
     if (st != NAT_OK)
         return st;
     std::vector<double> a(n_tris), nn(3 * (size_t)n_tris), c(n_tris);
-    return mesh_geometry(vertices, n_tris, tris, a.data(), nn.data(), c.data());
+    return mesh_geometry(vertices, n_vertices, n_tris, tris, a.data(), nn.data(), c.data());
 }
 
 nat_status nat_mesh_geometry(const double* vertices, int32_t n_vertices, const int32_t* tris,
@@ -759,7 +797,7 @@ nat_status nat_mesh_geometry(const double* vertices, int32_t n_vertices, const i
     nat_status st = validate_topology(vertices, n_vertices, tris, n_tris);
     if (st != NAT_OK)
         return st;
-    return mesh_geometry(vertices, n_tris, tris, area, normal, cdf);
+    return mesh_geometry(vertices, n_vertices, n_tris, tris, area, normal, cdf);
 }
 
 nat_status nat_mesh_create(nat_ctx* ctx, const double* vertices, int32_t n_vertices,
@@ -787,7 +825,7 @@ nat_status nat_mesh_create(nat_ctx* ctx, const double* vertices, int32_t n_verti
     m->normal.resize(3 * (size_t)n_tris);
     m->cdf.resize(n_tris);
     {
-        nat_status gst = mesh_geometry(m->V.data(), n_tris, tris, m->area.data(), m->normal.data(),
+        nat_status gst = mesh_geometry(m->V.data(), n_vertices, n_tris, tris, m->area.data(), m->normal.data(),
                                        m->cdf.data());
         if (gst != NAT_OK) {
             delete m;
@@ -907,6 +945,29 @@ nat_status nat_mcbem_samples(nat_mesh* m, int32_t N, uint64_t seed, int32_t* tri
     if (st != NAT_OK)
         return st;
     NAT_HIP(nat::launch_samples(m, N, seed, tri, bary, static_cast<hipStream_t>(stream)));
+    return NAT_OK;
+}
+
+nat_status nat_field_points(const nat_mesh* m, int32_t kind, int32_t n_a, int32_t n_b, double r_lo,
+                            double r_hi, uint64_t seed, double* points, double* coords, void* stream)
+{
+    if (!m)
+        return fail(NAT_E_INVALID, "nat_field_points: mesh is NULL");
+    if (kind != NAT_FIELD_SHELL && kind != NAT_FIELD_FFAT_GRID)
+        return fail(NAT_E_INVALID, "nat_field_points: kind %d", kind);
+    const int64_t n = kind == NAT_FIELD_SHELL ? (int64_t)n_a : (int64_t)n_a * n_b;
+    if (n_a < 0 || (kind == NAT_FIELD_FFAT_GRID && n_b < 1) || n > (int64_t(1) << 30))
+        return fail(NAT_E_INVALID, "nat_field_points: %d x %d points", n_a, n_b);
+    if (!(r_lo > 0.0) || !std::isfinite(r_lo) ||
+        (kind == NAT_FIELD_SHELL && (!(r_hi >= r_lo) || !std::isfinite(r_hi))))
+        return fail(NAT_E_INVALID, "nat_field_points: radii %g, %g", r_lo, r_hi);
+    if (n > 0 && !points)
+        return fail(NAT_E_INVALID, "nat_field_points: points is NULL");
+    nat_status st = set_device(m->ctx);
+    if (st != NAT_OK)
+        return st;
+    NAT_HIP(nat::launch_field_points(m, kind, n_a, n_b, r_lo, r_hi, seed, points, coords,
+                                     static_cast<hipStream_t>(stream)));
     return NAT_OK;
 }
 

@@ -263,6 +263,7 @@ struct SurfJob {
     const double* cdf;                 // running area sum [nT]
     const int32_t* q_tri;              // caller's queries
     const double* q_bary;
+    const double* fpts;                // or free field points [Q][3] (world), c = 1, no disk
     const double2* v_n;                // caller's Neumann data [M][ng]
     const double* cvert;               // mesh free terms at vertices [nV] and edges [nT][3]
     const double* cedge;
@@ -288,8 +289,13 @@ struct SurfBatch {
     int32_t* flags;                    // [0] query out of range, [1] non-finite Neumann data
     double* qfac;                      // per instance [Q] at oq: 1 / c_q, or null (c_q = 1/2)
 };
-// Device-side argument checks of every instance (flags are OR-ed, not cleared).
+// Device-side argument checks of every instance (flags are OR-ed, not cleared):
+// flags[0] for a query record out of range or a non-finite field point.
 hipError_t launch_checks_batch(const SurfBatch& b, int64_t max_work, hipStream_t s);
+// Field points around the mesh (kind 0: random shell, 1: FFAT direction grid)
+hipError_t launch_field_points(const nat_mesh* m, int32_t kind, int32_t n_a, int32_t n_b, double r_lo,
+                               double r_hi, uint64_t seed, double* xyz, double* coords, hipStream_t s);
+hipError_t launch_abs(const double2* z, int64_t n, double* out, hipStream_t s);
 // Samples, points and Neumann data of every instance.
 hipError_t launch_surface_batch(const SurfBatch& b, int32_t max_n, int32_t max_q, hipStream_t s);
 
@@ -345,6 +351,8 @@ struct InstDev {
     const float* s32;                  // [3][n] sample positions, relative to the mesh centre
     const float* sn32;                 // [3][n] sample normals
     const float* q32;                  // [3][q] query positions
+    const double* s64;                 // [3][n] sample positions (FP64, world)
+    const double* q64;                 // [3][q] query positions (FP64, world)
     const double* qfac;                // [q] 1 / c_q of the queries, or null for 2
 };
 
@@ -386,6 +394,7 @@ struct Sum32Batch {
     const float2* b32;                 //                                  w/(4 pi) p
     const int32_t* active;             // per system, or null
     float4* partial;                   // split partials (hi.re, hi.im, lo.re, lo.im)
+    int32_t phase64;                   // 1: phase from FP64 positions, reduced in FP64
 };
 
 // Symmetric form of the matvec sum: each unordered pair of 64-sample
@@ -407,6 +416,7 @@ struct SymBatch {
     const float2* b32;
     const int32_t* active;
     float4* partial;
+    int32_t phase64;                   // as in Sum32Batch
 };
 // most concurrent parts of an automatic batch split.  HIP gives a process 4
 // hardware queues by default; 3 parts plus the caller's stream fit them
@@ -549,6 +559,11 @@ struct McJob {
     uint64_t seed;
     double* p_out;
     double* p_samples;
+    // exterior field form: the queries are free points fpts [Q][3] (world
+    // coordinates; c = 1, no disk term) and the sample values are given
+    // (p_given [M][N], a previous estimate's p_samples): no Stage A
+    const double* fpts = nullptr;
+    const double* p_given = nullptr;
 };
 // Run the jobs as one batch; with bytes_only set, only validate the host
 // arguments and report the workspace the batch needs.

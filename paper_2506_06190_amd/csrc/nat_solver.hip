@@ -280,6 +280,7 @@ nat_status gmres_drive(nat_ctx* ctx, GmresBatch& g, BatchTables& T, const double
         sym.b32 = mv->b32;
         sym.active = g.active;
         sym.partial = mv->partial;
+        sym.phase64 = mv->phase64;
     }
     const Sum32Batch* mv_ord = mv && T.any_ordered ? mv : nullptr;
     const SymBatch* mv_sym = mv && T.any_sym ? &sym : nullptr;
@@ -398,26 +399,32 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     if (!(opts->eps_scale > 0.0) || !is_finite(opts->eps_scale) || !(opts->gmres_tol > 0.0) ||
         opts->gmres_max_iter < 1 || opts->gmres_max_iter > 1000 ||
         (opts->flags & ~(NAT_MC_NO_GRAPH | NAT_MC_ASSEMBLED | NAT_MC_MATRIX_FREE | NAT_MC_EXACT_DISK |
-                         NAT_MC_ORDERED_SUM)) ||
-        ((opts->flags & NAT_MC_ASSEMBLED) && (opts->flags & NAT_MC_MATRIX_FREE)))
+                         NAT_MC_ORDERED_SUM | NAT_MC_FP64_PHASE)) ||
+        ((opts->flags & NAT_MC_ASSEMBLED) && (opts->flags & (NAT_MC_MATRIX_FREE | NAT_MC_FP64_PHASE))))
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: bad solver options");
     if (opts->jump != NAT_JUMP_HALF && opts->jump != NAT_JUMP_POLYHEDRAL)
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: jump %d", opts->jump);
     if (opts->n_streams < 0 || opts->n_streams > nat_ctx::kMaxLanes)
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: n_streams %d", opts->n_streams);
+    // exterior field form (given sample values, free field points): every
+    // job of the batch or none
+    const bool field = nj > 0 && jobs[0].p_given != nullptr;
     const bool polyhedral = opts->jump == NAT_JUMP_POLYHEDRAL;
     int64_t S64 = 0;
     for (int32_t i = 0; i < nj; ++i) {
         const McJob& J = jobs[i];
         if (!J.mesh || !J.v_n || !J.k)
             return fail(NAT_E_INVALID, "job %d: NULL argument", i);
+        if ((J.p_given != nullptr) != field || (!field && J.fpts))
+            return fail(NAT_E_INVALID, "job %d: field and surface jobs mixed", i);
         if (J.mesh->ctx != ctx)
             return fail(NAT_E_INVALID, "job %d: mesh belongs to another context", i);
         if (J.M < 1 || J.M > 4096)
             return fail(NAT_E_INVALID, "job %d: n_modes = %d", i, J.M);
         if (J.N < 2 || J.N > (1 << 24))
             return fail(NAT_E_INVALID, "job %d: n_samples = %d", i, J.N);
-        if (J.Q < 0 || J.Q > (1 << 26) || (J.Q > 0 && (!J.q_tri || !J.q_bary || !J.p_out)))
+        if (J.Q < 0 || J.Q > (1 << 26) ||
+            (J.Q > 0 && (field ? (!J.fpts || !J.p_out) : (!J.q_tri || !J.q_bary || !J.p_out))))
             return fail(NAT_E_INVALID, "job %d: bad queries (Q = %d)", i, J.Q);
         for (int32_t m = 0; m < J.M; ++m)
             if (!(J.k[m] > 0.0) || !is_finite(J.k[m]))
@@ -434,7 +441,10 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     }
     const int32_t S = static_cast<int32_t>(S64);
     const bool fp32 = opts->precision == NAT_PREC_FP32;
-    const int32_t mmax = opts->gmres_max_iter;
+    // the field form runs no GMRES: its basis and Hessenberg arrays shrink
+    const int32_t mmax = field ? 1 : opts->gmres_max_iter;
+    // per-query factors 1/c_q: polyhedral free terms, or c = 1 at field points
+    const bool with_qfac = polyhedral || field;
     const size_t mm1 = (size_t)mmax + 1;
 
     // ---- layout ----------------------------------------------------------
@@ -466,7 +476,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
             k_max = J.k[m] > k_max ? J.k[m] : k_max;
         I.phase_fract = k_max / kTwoPi * J.mesh->diameter > kPhaseRevNoFract ? 1 : 0;
         // matvec form: assembled operator or matrix-free (FP32 form only)
-        const bool asm_form = fp32 && ((opts->flags & NAT_MC_ASSEMBLED) ||
+        const bool asm_form = !field && fp32 && !(opts->flags & NAT_MC_FP64_PHASE) &&
+                              ((opts->flags & NAT_MC_ASSEMBLED) ||
                                        (!(opts->flags & NAT_MC_MATRIX_FREE) &&
                                         ctx->tune.assembled[tune_bucket(J.N)]));
         // matrix-free matvec: symmetric (one partial per 64-sample sub-tile)
@@ -509,7 +520,9 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
             Y.kappa32 = static_cast<float>(J.k[m] / kTwoPi);
             Y.wscale = I.w * kInv4Pi;
             Y.eps = I.eps;
-            if (opts->flags & NAT_MC_EXACT_DISK) {
+            if (field) {
+                Y.disk = make_double2(0.0, 0.0);  // no disk term off the surface
+            } else if (opts->flags & NAT_MC_EXACT_DISK) {
                 // (e^{ik eps} - 1) / (2ik) = sin(x)/(2k) + i (1 - cos x)/(2k), x = k eps
                 const double x = J.k[m] * I.eps, h = std::sin(0.5 * x);
                 Y.disk = make_double2(std::sin(x) / (2.0 * J.k[m]), h * h / J.k[m]);
@@ -543,7 +556,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
          sizeof(SymGroupDev) * S,
          sizeof(int2) * sum_ch, sizeof(double) * S, sizeof(double2) * S, sizeof(int64_t) * 8,
          sizeof(SurfJob) * nj,
-         polyhedral ? sizeof(double) * inst_q : 0, sizeof(float2) * sum_k,
+         with_qfac ? sizeof(double) * inst_q : 0, sizeof(float2) * sum_k,
          sizeof(int32_t) * asm_list.size()});
     if (bytes_only) {
         *bytes_only = bytes;
@@ -603,7 +616,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     double2* ddisk = cv.take<double2>(S);
     int64_t* dcnt64 = cv.take<int64_t>(8);  // items: [0] rhs, [1] eval, [2] matvec, [4,5] sym
     SurfJob* d_surf = cv.take<SurfJob>(nj);
-    double* qfac_all = polyhedral ? cv.take<double>(inst_q) : nullptr;
+    double* qfac_all = with_qfac ? cv.take<double>(inst_q) : nullptr;
     float2* kmat = sum_k > 0 ? cv.take<float2>(sum_k) : nullptr;
     int32_t* d_asm_list = asm_list.empty() ? nullptr : cv.take<int32_t>(asm_list.size());
     T.d_nitems = dcnt + 2;
@@ -624,6 +637,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
             I.s32 = x32_all + 3 * on;
             I.sn32 = n32_all + 3 * on;
             I.q32 = q32_all + 3 * oq;
+            I.s64 = x64_all + 3 * on;
+            I.q64 = q64_all + 3 * oq;
             I.qfac = qfac_all && I.q > 0 ? qfac_all + oq : nullptr;
             on += I.n;
             oq += I.q;
@@ -654,6 +669,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
             X.cdf = m->d_cdf;
             X.q_tri = J.q_tri;
             X.q_bary = J.q_bary;
+            X.fpts = J.fpts;
             X.v_n = reinterpret_cast<const double2*>(J.v_n);
             X.cvert = m->d_cvert;
             X.cedge = m->d_cedge;
@@ -703,7 +719,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         NAT_HIP(hipMemcpyAsync(hflags, dcnt, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         NAT_HIP(hipStreamSynchronize(s));
         if (hflags[0])
-            return fail(NAT_E_INVALID, "Monte-Carlo estimate: query record out of range");
+            return fail(NAT_E_INVALID, field ? "Monte-Carlo field: a field point is not finite"
+                                             : "Monte-Carlo estimate: query record out of range");
         if (hflags[1])
             return fail(NAT_E_INVALID, "Monte-Carlo estimate: non-finite Neumann data");
     }
@@ -796,6 +813,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     sb.inst = T.d_inst;
     sb.sys = T.d_sys;
     sb.partial = partial;
+    sb.phase64 = (opts->flags & NAT_MC_FP64_PHASE) ? 1 : 0;
     // per-instance arguments of the plain FP64 sums
     auto plain_args = [&](int32_t i, int32_t op) {
         const InstDev& I = T.inst[i];
@@ -840,7 +858,9 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         pairs_rhs += (double)Y.n * Y.n;
         pairs_eval += (double)Y.q * Y.n;
     }
-    if (fp32) {
+    if (field) {
+        // the field form starts from the given sample values
+    } else if (fp32) {
         NAT_HIP(launch_weight32_batch(T.d_sys, S, max_n, gj, 1.0, a32, s));
         sb.groups = d_groups_rhs;
         sb.n_groups = dcnt + 5;
@@ -865,7 +885,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     // assembled operators of the systems that use them (the tuner's choice by
     // N, or forced by the flags)
     KmvBatch kb{};
-    if (!asm_list.empty()) {
+    if (!field && !asm_list.empty()) {
         NAT_HIP(launch_assemble32(T.d_inst, T.d_sys, d_asm_list, static_cast<int32_t>(asm_list.size()),
                                   max_n_asm, kmat, s));
         kb.sys = T.d_sys;
@@ -890,11 +910,18 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         return hipSuccess;
     };
     sb.b32 = v32;
-    st = gmres_drive(ctx, g, T, bvec, fp32 ? &sb : nullptr, asm_list.empty() ? nullptr : &kb, eager,
-                     !(opts->flags & NAT_MC_NO_GRAPH), s);
-    if (st != NAT_OK)
-        return st;
-    NAT_HIP(launch_gmres_solution(g, s));
+    if (field) {
+        for (int32_t i = 0; i < nj; ++i)
+            NAT_HIP(hipMemcpyAsync(xsol + T.sys[T.inst[i].sys0].off_n, jobs[i].p_given,
+                                   sizeof(double2) * (size_t)jobs[i].M * jobs[i].N,
+                                   hipMemcpyDeviceToDevice, s));
+    } else {
+        st = gmres_drive(ctx, g, T, bvec, fp32 ? &sb : nullptr, asm_list.empty() ? nullptr : &kb, eager,
+                         !(opts->flags & NAT_MC_NO_GRAPH), s);
+        if (st != NAT_OK)
+            return st;
+        NAT_HIP(launch_gmres_solution(g, s));
+    }
     NAT_HIP(sev.record(3, s));
 
     // ---- surface evaluation (eq. BIE at the queries, Section 4.2) --------------
@@ -941,8 +968,15 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
         return st;
     double* hres = static_cast<double*>(pin);
     int32_t* hit = reinterpret_cast<int32_t*>(hres + S);
-    NAT_HIP(hipMemcpyAsync(hres, g.resid, sizeof(double) * S, hipMemcpyDeviceToHost, s));
-    NAT_HIP(hipMemcpyAsync(hit, g.iters, sizeof(int32_t) * S, hipMemcpyDeviceToHost, s));
+    if (field) {
+        for (int32_t q = 0; q < S; ++q) {
+            hres[q] = 0.0;
+            hit[q] = 0;
+        }
+    } else {
+        NAT_HIP(hipMemcpyAsync(hres, g.resid, sizeof(double) * S, hipMemcpyDeviceToHost, s));
+        NAT_HIP(hipMemcpyAsync(hit, g.iters, sizeof(int32_t) * S, hipMemcpyDeviceToHost, s));
+    }
     NAT_HIP(hipStreamSynchronize(s));
     float t_ms[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int c = 0; c < 4; ++c)
@@ -1131,6 +1165,26 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
         return nat::fail(NAT_E_INVALID, "nat_mcbem_estimate: mesh is NULL");
     nat::McJob J{mesh, v_n, n_modes, Q, N, k, q_tri, q_bary, seed, p_out, p_samples};
     return nat::run_mc(mesh->ctx, &J, 1, opts, report, static_cast<hipStream_t>(stream), nullptr);
+}
+
+nat_status nat_mcbem_field(nat_mesh* mesh, const double* v_n, int32_t n_modes, const double* k,
+                           const double* p_samples, int32_t n_samples, uint64_t seed,
+                           const double* points, int32_t n_points, const nat_mc_opts* opts,
+                           double* p_out, double* abs_out, void* stream)
+{
+    if (!mesh)
+        return nat::fail(NAT_E_INVALID, "nat_mcbem_field: mesh is NULL");
+    if (!p_samples)
+        return nat::fail(NAT_E_INVALID, "nat_mcbem_field: p_samples is NULL");
+    nat::McJob J{mesh, v_n, n_modes, n_points, n_samples, k, nullptr, nullptr, seed, p_out, nullptr};
+    J.fpts = points;
+    J.p_given = p_samples;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    nat_status st = nat::run_mc(mesh->ctx, &J, 1, opts, nullptr, s, nullptr);
+    if (st == NAT_OK && abs_out && n_points > 0)
+        NAT_HIP(nat::launch_abs(reinterpret_cast<const double2*>(p_out), (int64_t)n_modes * n_points,
+                                abs_out, s));
+    return st;
 }
 
 nat_status nat_mcbem_estimate_batch(nat_ctx* ctx, const nat_mc_job* jobs, int32_t n_jobs,

@@ -35,8 +35,11 @@ NAT_MC_ASSEMBLED = 2
 NAT_MC_MATRIX_FREE = 4
 NAT_MC_EXACT_DISK = 8
 NAT_MC_ORDERED_SUM = 16
+NAT_MC_FP64_PHASE = 32
 NAT_JUMP_HALF = 0
 NAT_JUMP_POLYHEDRAL = 1
+NAT_FIELD_SHELL = 0
+NAT_FIELD_FFAT_GRID = 1
 NAT_TUNE_FORCE = 1
 TUNE_BUCKETS = 10
 
@@ -119,6 +122,10 @@ _SIGS = {
     "nat_mcbem_estimate_noalloc": ([_P, _P, C.c_int32, _P, _P, _P, C.c_int32, C.c_int32, C.c_uint64,
                                     C.POINTER(nat_mc_opts), _P, _P, _P, _P], C.c_int),
     "nat_mcbem_estimate_batch": ([_P, _P, C.c_int32, C.POINTER(nat_mc_opts), _P, _P], C.c_int),
+    "nat_mcbem_field": ([_P, _P, C.c_int32, _P, _P, C.c_int32, C.c_uint64, _P, C.c_int32,
+                         C.POINTER(nat_mc_opts), _P, _P, _P], C.c_int),
+    "nat_field_points": ([_P, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_uint64,
+                          _P, _P, _P], C.c_int),
     "nat_bem_assemble": ([_P, C.c_double, C.c_int32, C.POINTER(_P), _P], C.c_int),
     "nat_bem_solve": ([_P, _P, C.c_int32, C.c_int32, C.c_double, C.c_int32, _P, _P, _P], C.c_int),
     "nat_bem_op_matrices": ([_P, _P, _P, _P], C.c_int),
@@ -431,6 +438,52 @@ def nat_mcbem_estimate_noalloc(mesh: Mesh, v_n, k: Sequence[float], q_tri, q_bar
         C.cast(reps, _P), _stream(stream))
     _check(st, allow=(NAT_E_NOCONV,) if allow_noconv else ())
     return p_out, [r.as_dict() for r in reps]
+
+
+def nat_mcbem_field(mesh: Mesh, v_n, k: Sequence[float], p_samples, n_samples: int, seed: int,
+                    points, opts: Optional[nat_mc_opts] = None, p_out=None, abs_out=None,
+                    want_abs: bool = False, stream=None):
+    """Exterior field at points [P, 3] (device float64) from an estimate's
+    p_samples [n_modes, n_samples].  Returns (p_out [n_modes, P] complex128,
+    abs_out [n_modes, P] float64 or None)."""
+    import torch
+    if opts is None:
+        opts = nat_mc_opts_default()
+    k = np.ascontiguousarray(np.atleast_1d(k), dtype=np.float64)
+    M = len(k)
+    ng = mesh.n_tris if opts.layout == NAT_NEUMANN_PER_TRIANGLE else mesh.n_vertices
+    P = int(points.shape[0])
+    dev = v_n.device
+    if p_out is None:
+        p_out = torch.empty((M, P), dtype=torch.complex128, device=dev)
+    if abs_out is None and want_abs:
+        abs_out = torch.empty((M, P), dtype=torch.float64, device=dev)
+    st = lib().nat_mcbem_field(
+        mesh.handle, _dptr(v_n, torch.complex128, (M, ng), "v_n"), M, k.ctypes.data_as(_P),
+        _dptr(p_samples, torch.complex128, (M, n_samples), "p_samples"), n_samples, C.c_uint64(seed),
+        _dptr(points, torch.float64, (P, 3), "points"), P, C.byref(opts),
+        _dptr(p_out, torch.complex128, (M, P), "p_out"),
+        _dptr(abs_out, torch.float64, (M, P), "abs_out") if abs_out is not None else None,
+        _stream(stream))
+    _check(st)
+    return p_out, abs_out
+
+
+def nat_field_points(mesh: Mesh, kind: int, n_a: int, n_b: int = 1, r_lo: float = 1.5,
+                     r_hi: float = 3.0, seed: int = 0, points=None, coords=None, stream=None,
+                     device="cuda"):
+    """Shell (NAT_FIELD_SHELL, n_a points) or FFAT grid (NAT_FIELD_FFAT_GRID,
+    n_a x n_b) field points: returns (points [n, 3], coords [n, 3] = (r, theta, phi))."""
+    import torch
+    n = n_a if kind == NAT_FIELD_SHELL else n_a * n_b
+    if points is None:
+        points = torch.empty((n, 3), dtype=torch.float64, device=device)
+    if coords is None:
+        coords = torch.empty((n, 3), dtype=torch.float64, device=device)
+    _check(lib().nat_field_points(mesh.handle, int(kind), int(n_a), int(n_b), float(r_lo), float(r_hi),
+                                  C.c_uint64(seed), _dptr(points, torch.float64, (n, 3), "points"),
+                                  _dptr(coords, torch.float64, (n, 3), "coords"), _stream(stream)))
+    return points, coords
 
 
 class McJob:

@@ -92,3 +92,20 @@ def test_batch_job_layout_must_match_the_batch():
     job.layout = nat.NAT_NEUMANN_PER_TRIANGLE
     with pytest.raises(ValueError, match="layout"):
         job.record(nat.NAT_NEUMANN_PER_VERTEX)
+
+
+def test_scene_of_several_bodies_validated_per_body():
+    """A mesh of several closed bodies is accepted when every body is
+    oriented outward; turning any one body inside out is refused, naming it
+    (the total volume of the scene would still be positive)."""
+    sc = W.scene_speaker_torus(0.03)
+    assert nat.nat_mesh_validate(sc.vertices, sc.tris) == (nat.NAT_OK, "")
+    for b in (0, 1):
+        f = sc.tris.copy()
+        f[sc.body == b] = f[sc.body == b][:, [0, 2, 1]]
+        st, msg = nat.nat_mesh_validate(sc.vertices, f)
+        assert st == nat.NAT_E_INVALID and f"body {b} of 2" in msg
+    # the geometry of a scene equals the oracle's bit for bit, as for one body
+    area, nrm, cdf = nat.nat_mesh_geometry(sc.vertices, sc.tris)
+    ao, no, co = O.geometry(sc.vertices, sc.tris)
+    assert np.array_equal(area, ao) and np.array_equal(nrm, no) and np.array_equal(cdf, co)

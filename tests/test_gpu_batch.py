@@ -204,18 +204,29 @@ def full_batch(ctx):
         m.close()
 
 
-def _check_systems(full_batch, picks, label):
+_ORACLE_CACHE = {}
+
+
+def _oracle_systems(wl, i, modes):
+    key = (i, tuple(modes))
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = O.mcbem(wl.vertices, wl.tris, wl.g[modes], wl.k[modes], wl.q_tri, wl.q_b,
+                                     wl.n_samples, wl.seed, tol=1e-6, max_iter=200)
+    return _ORACLE_CACHE[key]
+
+
+def _check_systems(full_batch, picks, label, outs=None):
     """picks: {instance: [modes]}; each system against the FP64 oracle at the
     same GMRES settings (tol 1e-6, at most 200 iterations), per system both
-    bars at 1e-3; every system's error is printed."""
+    bars at 1e-3; every system's error is printed.  outs: per-instance
+    outputs to check instead of the batch's own."""
     wls, jobs, reps = full_batch
     worst = 0.0
     for i in sorted(picks):
         wl = wls[i]
         modes = sorted(set(picks[i]))
-        ref = O.mcbem(wl.vertices, wl.tris, wl.g[modes], wl.k[modes], wl.q_tri, wl.q_b,
-                      wl.n_samples, wl.seed, tol=1e-6, max_iter=200)
-        got = jobs[i].p_out[modes].cpu().numpy()
+        ref = _oracle_systems(wl, i, modes)
+        got = (outs[i] if outs is not None else jobs[i].p_out)[modes].cpu().numpy()
         diam = float(np.linalg.norm(wl.vertices.max(axis=0) - wl.vertices.min(axis=0)))
         for a, (m, (e2, ei)) in enumerate(zip(modes, mode_errors(got, ref["p"]))):
             r = reps[i][m]
@@ -226,6 +237,7 @@ def _check_systems(full_batch, picks, label):
             worst = max(worst, e2, ei)
             assert e2 <= 1e-3 and ei <= 1e-3, (i, m, e2, ei)
     _say(f"  {label}: worst {worst:.2e} over {sum(len(set(v)) for v in picks.values())} systems")
+    return worst
 
 
 def test_full_batched_workload_finite(full_batch):
@@ -259,3 +271,25 @@ def test_full_batched_capped_systems(full_batch):
                 picks.setdefault(i, []).append(m)
     assert picks
     _check_systems(full_batch, picks, "capped:")
+
+
+def test_full_batched_capped_systems_fp64_phase(full_batch, ctx):
+    """The headline batch again with NAT_MC_FP64_PHASE (phase from FP64
+    positions, reduced in FP64): the systems that stop at the iteration cap
+    against the same oracle references; both forms' errors are printed."""
+    wls, jobs, reps = full_batch
+    picks = {}
+    for i, rr in enumerate(reps):
+        for m, r in enumerate(rr):
+            if not r["converged"]:
+                picks.setdefault(i, []).append(m)
+    opts = nat.nat_mc_opts_default()
+    opts.flags = nat.NAT_MC_FP64_PHASE
+    outs = [torch.empty_like(j.p_out) for j in jobs]
+    jobs2 = [nat.McJob(j.mesh, j.v_n, j.k, j.q_tri, j.q_bary, j.n_samples, j.seed, p_out=o)
+             for j, o in zip(jobs, outs)]
+    nat.nat_mcbem_estimate_batch(ctx, jobs2, opts, allow_noconv=True)
+    torch.cuda.synchronize()
+    w32 = _check_systems(full_batch, picks, "capped, fp32 phase:")
+    w64 = _check_systems(full_batch, picks, "capped, fp64 phase:", outs=outs)
+    _say(f"  capped systems worst error: fp32 phase {w32:.2e}, fp64 phase {w64:.2e}")

@@ -1,0 +1,129 @@
+"""GPU tests of the exterior field (Section 3.4 training data, Section 3.1
+FFAT maps) through the C ABI: field points against the oracle's point sets,
+and the field itself against the oracle's representation-formula sum, per
+mode and element by element -- from the oracle's own sample values (the
+field kernel alone: FP64 within 1e-10, FP32 within 1e-3) and end to end
+from the GPU estimate (FP32 within 1e-3), at 10,000 shell points and on a
+32 x 64 FFAT grid of the 20480-triangle precision workload."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2506_06190_amd import nat  # noqa: E402
+from _parity import check_modes, say as _say  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = nat.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.mark.parametrize("kind,n_a,n_b,seed", [(0, 10000, 1, 7), (0, 333, 1, 2**63 + 5),
+                                               (1, 32, 64, 0), (1, 7, 5, 0)])
+def test_field_points_match_oracle(ctx, kind, n_a, n_b, seed):
+    v, f, _ = W.noisy_ellipsoid(3, subdiv=3)
+    mesh = nat.Mesh(ctx, v, f)
+    x, co = nat.nat_field_points(mesh, kind, n_a, n_b, 1.5 if kind == 0 else 2.0, 3.0, seed)
+    torch.cuda.synchronize()
+    xo, coo = O.field_points(v, kind, n_a, n_b, r_lo=1.5 if kind == 0 else 2.0, r_hi=3.0, seed=seed)
+    _, R = O.bounding_sphere(v)
+    assert np.abs(x.cpu().numpy() - xo).max() <= 1e-13 * R
+    assert np.abs(co.cpu().numpy() - coo).max() <= 1e-13 * max(R, 2 * np.pi)
+    mesh.close()
+
+
+def _small(seed=23, M=5, N=600):
+    v, f, u = W.noisy_ellipsoid(seed, subdiv=3)
+    g = W.sh_neumann(u, M, seed)
+    k = W.wavenumber(W.log_uniform_freqs(M, seed))
+    return v, f, g, k, N, seed
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_field_from_oracle_samples(ctx, prec):
+    """The field kernel alone: the oracle's sample values in, the oracle's sum
+    at the same 2000 shell points and 8 x 16 grid points as the bar."""
+    v, f, g, k, N, seed = _small()
+    ref = O.mcbem(v, f, g, k, np.zeros(0, np.int32), np.zeros((0, 2)), N, seed, tol=1e-12,
+                  want_samples=True)
+    xs, _ = O.field_points(v, 0, 2000, seed=4)
+    xg, _ = O.field_points(v, 1, 8, 16, r_lo=1.7)
+    pts = np.concatenate([xs, xg])
+    po = O.mcbem_field(v, f, g, k, N, seed, pts, ref["p_samples"])
+    mesh = nat.Mesh(ctx, v, f)
+    opts = nat.nat_mc_opts_default()
+    opts.precision = nat.NAT_PREC_FP64 if prec == "fp64" else nat.NAT_PREC_FP32
+    p, a = nat.nat_mcbem_field(mesh, _dev(g), k, _dev(ref["p_samples"]), N, seed, _dev(pts), opts,
+                               want_abs=True)
+    torch.cuda.synchronize()
+    bar = 1e-10 if prec == "fp64" else 1e-3
+    check_modes(p.cpu().numpy(), po, bar, f"field {prec} from oracle samples")
+    check_modes(a.cpu().numpy(), np.abs(po), bar, f"|p| {prec}")
+    mesh.close()
+
+
+def test_field_end_to_end_precision_workload(ctx):
+    """The 20480-triangle, 32-mode workload: GPU estimate (FP32) and then the
+    GPU field at 10,000 shell points (1.5-3 R) and on the 32 x 64 FFAT grid
+    at 2 R, against the oracle's estimate and field on the same points."""
+    wl = W.config_precision()
+    ref = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri, wl.q_b, wl.n_samples, wl.seed,
+                  tol=1e-12, want_samples=True)
+    xs, cs = O.field_points(wl.vertices, 0, 10000, seed=11)
+    xg, cg = O.field_points(wl.vertices, 1, 32, 64, r_lo=2.0)
+    mesh = nat.Mesh(ctx, wl.vertices, wl.tris)
+    g = _dev(wl.g)
+    ps = torch.empty((wl.n_modes, wl.n_samples), dtype=torch.complex128, device=DEV)
+    nat.nat_mcbem_estimate(mesh, g, wl.k, _dev(wl.q_tri), _dev(wl.q_b), wl.n_samples, wl.seed,
+                           p_samples=ps)
+    for name, pts, co in (("shell 10000", xs, cs), ("FFAT 32x64", xg, cg)):
+        p, a = nat.nat_mcbem_field(mesh, g, wl.k, ps, wl.n_samples, wl.seed, _dev(pts), want_abs=True)
+        torch.cuda.synchronize()
+        po = O.mcbem_field(wl.vertices, wl.tris, wl.g, wl.k, wl.n_samples, wl.seed, pts,
+                           ref["p_samples"])
+        check_modes(p.cpu().numpy(), po, 1e-3, f"{name} end to end")
+        if name.startswith("FFAT"):
+            # the map: r |p| on the grid, image [theta][phi]
+            ffat = (a.cpu().numpy() * co[None, :, 0]).reshape(wl.n_modes, 32, 64)
+            ffat_o = (np.abs(po) * co[None, :, 0]).reshape(wl.n_modes, 32, 64)
+            check_modes(ffat.reshape(wl.n_modes, -1), ffat_o.reshape(wl.n_modes, -1), 1e-3,
+                        "FFAT map r|p|")
+    mesh.close()
+
+
+def test_field_errors(ctx):
+    v, f, g, k, N, seed = _small(M=2, N=100)
+    mesh = nat.Mesh(ctx, v, f)
+    ps = torch.zeros((2, N), dtype=torch.complex128, device=DEV)
+    pts = torch.zeros((4, 3), dtype=torch.float64, device=DEV)
+    pts[:, 0] = 1.0
+    pts[2, 1] = float("inf")
+    with pytest.raises(nat.NatError) as ei:
+        nat.nat_mcbem_field(mesh, _dev(g), k, ps, N, seed, pts)
+    assert ei.value.status == nat.NAT_E_INVALID and "not finite" in str(ei.value)
+    with pytest.raises(nat.NatError) as ei:
+        nat.nat_field_points(mesh, 2, 10)
+    assert ei.value.status == nat.NAT_E_INVALID
+    with pytest.raises(nat.NatError) as ei:
+        nat.nat_field_points(mesh, nat.NAT_FIELD_SHELL, 10, r_lo=2.0, r_hi=1.0)
+    assert ei.value.status == nat.NAT_E_INVALID
+    # no points: nothing to do
+    p, _ = nat.nat_mcbem_field(mesh, _dev(g), k, ps, N, seed, pts[:0])
+    assert p.shape == (2, 0)
+    mesh.close()

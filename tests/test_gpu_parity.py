@@ -219,6 +219,53 @@ def test_fp32_long_phases(ctx):
     check_modes(p, r["p"], 1e-3, "long phases")
 
 
+def test_fp64_phase_long_phases(ctx):
+    """NAT_MC_FP64_PHASE at phases of about 100 revolutions: the phase formed
+    from FP64 positions and reduced in FP64, in both matvec forms, against
+    the oracle; the FP64 phase is at least as close to the oracle as the
+    FP32 phase."""
+    v, f, u = W.noisy_ellipsoid(13, subdiv=3)
+    k = np.array([2200.0, 2500.0])
+    g = W.sh_neumann(u, 2, 13)
+    qt, qb = W.random_face_queries(len(f), 200, 13)
+    wl = W.MCWorkload("long_phases", v, f, g, k, qt, qb, 150, 13)
+    r = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri, wl.q_b, wl.n_samples, wl.seed, tol=1e-12)
+    worst = {}
+    for name, flags in (("fp32 phase", 0), ("fp64 phase", nat.NAT_MC_FP64_PHASE),
+                        ("fp64 phase, ordered", nat.NAT_MC_FP64_PHASE | nat.NAT_MC_ORDERED_SUM)):
+        p, rep, ps = _run_gpu(ctx, wl, nat.NAT_PREC_FP32, 1e-9, flags=flags, want_samples=True)
+        errs = check_modes(p, r["p"], 1e-3, name)
+        worst[name] = max(max(e) for e in errs)
+    _say(f"  worst error: {worst}")
+    assert worst["fp64 phase"] <= worst["fp32 phase"]
+    assert worst["fp64 phase, ordered"] <= worst["fp32 phase"]
+
+
+def test_fp64_phase_batch_equals_alone(ctx):
+    """The FP64-phase form in a batch of uneven instances: each equals its
+    single estimate bit for bit and the oracle within the FP32 bar."""
+    wls = [_small_ellipsoid(n_modes=3, Q=300, N=400, seed=61), _small_ellipsoid(n_modes=9, Q=200, N=257,
+                                                                              seed=62)]
+    meshes = [nat.Mesh(ctx, wl.vertices, wl.tris) for wl in wls]
+    opts = nat.nat_mc_opts_default()
+    opts.flags = nat.NAT_MC_FP64_PHASE
+    jobs = [nat.McJob(m, torch.from_numpy(wl.g).to(DEV), wl.k, torch.from_numpy(wl.q_tri).to(DEV),
+                      torch.from_numpy(wl.q_b).to(DEV), wl.n_samples, wl.seed)
+            for wl, m in zip(wls, meshes)]
+    nat.nat_mcbem_estimate_batch(ctx, jobs, opts)
+    torch.cuda.synchronize()
+    for wl, mesh, job in zip(wls, meshes, jobs):
+        p1, _ = nat.nat_mcbem_estimate(mesh, job.v_n, wl.k, job.q_tri, job.q_bary, wl.n_samples,
+                                       wl.seed, opts)
+        torch.cuda.synchronize()
+        assert torch.equal(job.p_out, p1)
+        r = O.mcbem(wl.vertices, wl.tris, wl.g, wl.k, wl.q_tri, wl.q_b, wl.n_samples, wl.seed,
+                    tol=1e-12)
+        check_modes(p1.cpu().numpy(), r["p"], 1e-3, "fp64 phase in a batch")
+    for m in meshes:
+        m.close()
+
+
 def test_fp32_full_precision_workload(ctx):
     """Noise-displaced ellipsoid, 20480 triangles, 32 modes, 4096 queries x 1024
     samples, the launch configuration the benchmark times."""
@@ -322,6 +369,7 @@ def test_error_paths(ctx):
         nat.nat_mcbem_estimate(mesh, g, [1.0], qt, qb, 64, 1, opts)
     assert ei.value.status == nat.NAT_E_NOCONV
     for field, value in (("jump", 2), ("flags", nat.NAT_MC_ASSEMBLED | nat.NAT_MC_MATRIX_FREE),
+                         ("flags", nat.NAT_MC_ASSEMBLED | nat.NAT_MC_FP64_PHASE),
                          ("flags", 64), ("eps_scale", 0.0)):
         o = nat.nat_mc_opts_default()
         setattr(o, field, value)
