@@ -157,6 +157,207 @@ void orc_samples(const double* cdf, int32_t nT, int32_t N, uint64_t seed,
     }
 }
 
+/* ---------------------------------------------------------------------- */
+/* Poisson-disk sample set (Section 4.2: parallel Poisson-disk sampling   */
+/* after Bowers, Wang, Wei & Maletz 2010).                                */
+/* Candidates: M = cand_factor N area-uniform points; candidate i draws   */
+/* u0, u1, u2 from counters 3i..3i+2 of stream 6, takes the triangle of   */
+/* u0 A as the samples do and the point (b1, b2) = (u1, u2), folded to    */
+/* (1 - u1, 1 - u2) when u1 + u2 > 1 (a uniform point of the triangle      */
+/* with exact arithmetic).  Radius r = rscale sqrt(A / N).                 */
+/* Grid: cells of side h = r / sqrt(3) (a cell holds at most one accepted  */
+/* point) over the mesh's bounding box, cell (cx, cy, cz) =                */
+/* floor((x - lo) sqrt(3)/r) per axis, key (cx NY + cy) NZ + cz; a cell's  */
+/* candidates in index order.  Phase of a cell (cx mod 3, cy mod 3,        */
+/* cz mod 3) as 9 a + 3 b + c: cells of one phase are more than r apart,   */
+/* so they can be decided independently (in parallel).                    */
+/* Passes p = 0, 1, ...; in each, phases 0..26 in order; in each phase the */
+/* cells in key order without an accepted point try their p-th candidate, */
+/* which is accepted unless an accepted point of the 5 x 5 x 5 cells      */
+/* around lies closer than r (squared distances in FP64, no fused          */
+/* multiply-add).  The samples are the first N accepted points in         */
+/* acceptance order (n_out_max > N returns more of them, for tests).      */
+/* Returns the number accepted (the estimator needs >= N).                 */
+/* ---------------------------------------------------------------------- */
+/* radius scale and candidate count of the estimator's Poisson-disk set */
+#define ORC_POISSON_RSCALE 0.72
+#define ORC_POISSON_CANDIDATES 16
+
+typedef struct {
+    int64_t key;
+    int32_t idx;
+} orc_keyidx;
+
+void orc_surface_points(const double* V, const int32_t* T, int32_t n, const int32_t* tri,
+                        const double* bary, double* xyz);
+
+static int orc_cmp_keyidx(const void* a, const void* b)
+{
+    const orc_keyidx* x = (const orc_keyidx*)a;
+    const orc_keyidx* y = (const orc_keyidx*)b;
+    if (x->key != y->key)
+        return x->key < y->key ? -1 : 1;
+    return x->idx < y->idx ? -1 : (x->idx > y->idx);
+}
+
+void orc_poisson_candidates(const double* V, const int32_t* T, const double* cdf, int32_t nT,
+                            int32_t M, uint64_t seed, int32_t* tri, double* bary, double* xyz)
+{
+    double A = cdf[nT - 1];
+    for (int32_t i = 0; i < M; ++i) {
+        double u0 = orc_u01(orc_rng_word(seed, 6, 3ULL * (uint64_t)i + 0));
+        double u1 = orc_u01(orc_rng_word(seed, 6, 3ULL * (uint64_t)i + 1));
+        double u2 = orc_u01(orc_rng_word(seed, 6, 3ULL * (uint64_t)i + 2));
+        tri[i] = orc_cdf_search(cdf, nT, u0 * A);
+        double b1 = u1, b2 = u2;
+        if (u1 + u2 > 1.0) {
+            b1 = 1.0 - u1;
+            b2 = 1.0 - u2;
+        }
+        bary[2 * i + 0] = b1;
+        bary[2 * i + 1] = b2;
+    }
+    orc_surface_points(V, T, M, tri, bary, xyz);
+}
+
+static int32_t find_cell(const int64_t* keys, int32_t n, int64_t key)
+{
+    int32_t lo = 0, hi = n - 1;
+    while (lo <= hi) {
+        int32_t mid = lo + (hi - lo) / 2;
+        if (keys[mid] == key)
+            return mid;
+        if (keys[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid - 1;
+    }
+    return -1;
+}
+
+int32_t orc_poisson_samples(const double* V, int32_t nV, const int32_t* T, int32_t nT, int32_t N,
+                            uint64_t seed, double rscale, int32_t cand_factor, int32_t n_out_max,
+                            int32_t* tri_out, double* bary_out)
+{
+    double* area = (double*)malloc(sizeof(double) * (size_t)nT);
+    double* nrm = (double*)malloc(sizeof(double) * 3 * (size_t)nT);
+    double* cdf = (double*)malloc(sizeof(double) * (size_t)nT);
+    orc_geometry(V, T, nT, area, nrm, cdf);
+    double A = cdf[nT - 1];
+    double r = rscale * sqrt(A / (double)N);
+    double r2 = r * r;
+    double inv_h = sqrt(3.0) / r;
+    double lo[3], hi[3];
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = V[c];
+        hi[c] = V[c];
+    }
+    for (int32_t v = 1; v < nV; ++v)
+        for (int c = 0; c < 3; ++c) {
+            if (V[3 * v + c] < lo[c])
+                lo[c] = V[3 * v + c];
+            if (V[3 * v + c] > hi[c])
+                hi[c] = V[3 * v + c];
+        }
+    int64_t dim[3];
+    for (int c = 0; c < 3; ++c)
+        dim[c] = (int64_t)floor((hi[c] - lo[c]) * inv_h) + 1;
+    int32_t M = cand_factor * N;
+    int32_t* ctri = (int32_t*)malloc(sizeof(int32_t) * (size_t)M);
+    double* cbary = (double*)malloc(sizeof(double) * 2 * (size_t)M);
+    double* cx = (double*)malloc(sizeof(double) * 3 * (size_t)M);
+    orc_poisson_candidates(V, T, cdf, nT, M, seed, ctri, cbary, cx);
+    orc_keyidx* ki = (orc_keyidx*)malloc(sizeof(orc_keyidx) * (size_t)M);
+    for (int32_t i = 0; i < M; ++i) {
+        int64_t cc[3];
+        for (int c = 0; c < 3; ++c) {
+            int64_t q = (int64_t)floor((cx[3 * i + c] - lo[c]) * inv_h);
+            cc[c] = q < 0 ? 0 : (q >= dim[c] ? dim[c] - 1 : q);
+        }
+        ki[i].key = (cc[0] * dim[1] + cc[1]) * dim[2] + cc[2];
+        ki[i].idx = i;
+    }
+    qsort(ki, (size_t)M, sizeof(orc_keyidx), orc_cmp_keyidx);
+    /* cells: runs of equal keys */
+    int64_t* ckey = (int64_t*)malloc(sizeof(int64_t) * (size_t)M);
+    int32_t* cstart = (int32_t*)malloc(sizeof(int32_t) * (size_t)M);
+    int32_t* ccount = (int32_t*)malloc(sizeof(int32_t) * (size_t)M);
+    int32_t* cacc = (int32_t*)malloc(sizeof(int32_t) * (size_t)M);
+    int32_t* cphase = (int32_t*)malloc(sizeof(int32_t) * (size_t)M);
+    int32_t ncell = 0, maxc = 0;
+    for (int32_t i = 0; i < M; ++i) {
+        if (ncell == 0 || ckey[ncell - 1] != ki[i].key) {
+            ckey[ncell] = ki[i].key;
+            cstart[ncell] = i;
+            ccount[ncell] = 0;
+            ++ncell;
+        }
+        ++ccount[ncell - 1];
+        if (ccount[ncell - 1] > maxc)
+            maxc = ccount[ncell - 1];
+    }
+    for (int32_t c = 0; c < ncell; ++c) {
+        int64_t k = ckey[c];
+        int64_t z = k % dim[2], y = (k / dim[2]) % dim[1], x = k / (dim[1] * dim[2]);
+        cphase[c] = (int32_t)((x % 3) * 9 + (y % 3) * 3 + (z % 3));
+        cacc[c] = -1;
+    }
+    int32_t* accepted = (int32_t*)malloc(sizeof(int32_t) * (size_t)ncell);
+    int32_t nacc = 0;
+    for (int32_t p = 0; p < maxc; ++p) {
+        for (int32_t ph = 0; ph < 27; ++ph) {
+            for (int32_t c = 0; c < ncell; ++c) {
+                if (cphase[c] != ph || cacc[c] >= 0 || ccount[c] <= p)
+                    continue;
+                int32_t cand = ki[cstart[c] + p].idx;
+                const double* xc = cx + 3 * (size_t)cand;
+                int64_t k = ckey[c];
+                int64_t z = k % dim[2], y = (k / dim[2]) % dim[1], x = k / (dim[1] * dim[2]);
+                int ok = 1;
+                for (int dx = -2; dx <= 2 && ok; ++dx)
+                    for (int dy = -2; dy <= 2 && ok; ++dy)
+                        for (int dz = -2; dz <= 2 && ok; ++dz) {
+                            int64_t nx = x + dx, ny = y + dy, nz = z + dz;
+                            if (nx < 0 || ny < 0 || nz < 0 || nx >= dim[0] || ny >= dim[1] || nz >= dim[2])
+                                continue;
+                            int32_t nc = find_cell(ckey, ncell, (nx * dim[1] + ny) * dim[2] + nz);
+                            if (nc < 0 || cacc[nc] < 0)
+                                continue;
+                            const double* xa = cx + 3 * (size_t)cacc[nc];
+                            double ex = xc[0] - xa[0], ey = xc[1] - xa[1], ez = xc[2] - xa[2];
+                            double d2 = ex * ex + ey * ey + ez * ez;
+                            if (d2 < r2)
+                                ok = 0;
+                        }
+                if (ok) {
+                    cacc[c] = cand;
+                    accepted[nacc++] = cand;
+                }
+            }
+        }
+    }
+    int32_t n_out = nacc < n_out_max ? nacc : n_out_max;
+    for (int32_t j = 0; j < n_out; ++j) {
+        tri_out[j] = ctri[accepted[j]];
+        bary_out[2 * j + 0] = cbary[2 * (size_t)accepted[j] + 0];
+        bary_out[2 * j + 1] = cbary[2 * (size_t)accepted[j] + 1];
+    }
+    free(area);
+    free(nrm);
+    free(cdf);
+    free(ctri);
+    free(cbary);
+    free(cx);
+    free(ki);
+    free(ckey);
+    free(cstart);
+    free(ccount);
+    free(cacc);
+    free(cphase);
+    free(accepted);
+    return nacc;
+}
+
 /* x = v0 + b1 (v1 - v0) + b2 (v2 - v0) */
 void orc_surface_points(const double* V, const int32_t* T, int32_t n,
                         const int32_t* tri, const double* bary, double* xyz)
@@ -554,15 +755,25 @@ int32_t orc_mcbem(const double* V, int32_t nV, const int32_t* T, int32_t nT,
                   int32_t max_iter, double* p_out /* complex [n_modes][Q] */,
                   double* p_smp_out /* complex [n_modes][N] or NULL */, int32_t* iters,
                   double* resid, int32_t* smp_tri, double* smp_bary, int32_t jump,
-                  int32_t exact_disk)
+                  int32_t exact_disk, int32_t poisson)
 {
-    (void)nV;
     double* area = (double*)malloc(sizeof(double) * (size_t)nT);
     double* nrm = (double*)malloc(sizeof(double) * 3 * (size_t)nT);
     double* cdf = (double*)malloc(sizeof(double) * (size_t)nT);
     orc_geometry(V, T, nT, area, nrm, cdf);
     double A = cdf[nT - 1];
-    orc_samples(cdf, nT, N, seed, smp_tri, smp_bary);
+    if (poisson) {
+        /* Section 4.2: Poisson-disk samples instead of independent ones */
+        if (orc_poisson_samples(V, nV, T, nT, N, seed, ORC_POISSON_RSCALE, ORC_POISSON_CANDIDATES, N,
+                                smp_tri, smp_bary) < N) {
+            free(area);
+            free(nrm);
+            free(cdf);
+            return 5;
+        }
+    } else {
+        orc_samples(cdf, nT, N, seed, smp_tri, smp_bary);
+    }
     double* y = (double*)malloc(sizeof(double) * 3 * (size_t)N);
     double* ny = (double*)malloc(sizeof(double) * 3 * (size_t)N);
     double* xq = (double*)malloc(sizeof(double) * 3 * (size_t)Q);

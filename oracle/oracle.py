@@ -55,6 +55,10 @@ def lib():
         L.orc_cdf_search.restype = C.c_int32
         L.orc_samples.argtypes = [_d, C.c_int32, C.c_int32, C.c_uint64, _i, _d]
         L.orc_surface_points.argtypes = [_d, _i, C.c_int32, _i, _d, _d]
+        L.orc_poisson_candidates.argtypes = [_d, _i, _d, C.c_int32, C.c_int32, C.c_uint64, _i, _d, _d]
+        L.orc_poisson_samples.argtypes = [_d, C.c_int32, _i, C.c_int32, C.c_int32, C.c_uint64,
+                                          C.c_double, C.c_int32, C.c_int32, _i, _d]
+        L.orc_poisson_samples.restype = C.c_int32
         L.orc_neumann_at.argtypes = [_i, C.c_int32, _d, C.c_int32, _i, _d, _d]
         L.orc_kernels.argtypes = [C.c_double, _d, _d, _d, _d, _d]
         L.orc_mc_matrix.argtypes = [C.c_int32, _d, _d, C.c_double, C.c_double, C.c_double, _d]
@@ -70,7 +74,7 @@ def lib():
         L.orc_mcbem.argtypes = [_d, C.c_int32, _i, C.c_int32, _d, C.c_int32, C.c_int32, _d,
                                 _i, _d, C.c_int32, C.c_int32, C.c_uint64, C.c_double,
                                 C.c_double, C.c_int32, _d, C.c_void_p, _i, _d, _i, _d, C.c_int32,
-                                C.c_int32]
+                                C.c_int32, C.c_int32]
         L.orc_mcbem.restype = C.c_int32
         L.orc_gauss_legendre01.argtypes = [C.c_int32, _d, _d]
         L.orc_self_panel.argtypes = [C.c_double, _d, _d, _d, _d]
@@ -138,6 +142,36 @@ def samples(V, T, N, seed):
     bary = np.empty((N, 2))
     lib().orc_samples(cdf, len(cdf), N, seed, tri, bary.reshape(-1))
     return tri, bary
+
+
+POISSON_RSCALE = 0.72      # r = POISSON_RSCALE sqrt(|Gamma| / N)
+POISSON_CANDIDATES = 16    # candidates per requested sample
+
+
+def poisson_candidates(V, T, M, seed):
+    """The candidate pool of the Poisson-disk sampler: (tri, bary, xyz)."""
+    V, T = _f64(V), _i32(T)
+    _, _, cdf = geometry(V, T)
+    tri = np.empty(M, dtype=np.int32)
+    bary = np.empty((M, 2))
+    xyz = np.empty((M, 3))
+    lib().orc_poisson_candidates(V.reshape(-1), T.reshape(-1), cdf, len(T), int(M), seed, tri,
+                                 bary.reshape(-1), xyz.reshape(-1))
+    return tri, bary, xyz
+
+
+def poisson_samples(V, T, N, seed, rscale=POISSON_RSCALE, cand_factor=POISSON_CANDIDATES,
+                    all_accepted=False):
+    """Poisson-disk samples (Section 4.2): the first N accepted points (every
+    accepted point with all_accepted).  Returns (tri, bary, n_accepted)."""
+    V, T = _f64(V), _i32(T)
+    cap = cand_factor * N if all_accepted else N
+    tri = np.empty(cap, dtype=np.int32)
+    bary = np.empty((cap, 2))
+    n = int(lib().orc_poisson_samples(V.reshape(-1), len(V), T.reshape(-1), len(T), int(N), seed,
+                                      float(rscale), int(cand_factor), int(cap), tri, bary.reshape(-1)))
+    m = min(cap, n)
+    return tri[:m], bary[:m], n
 
 
 def surface_points(V, T, tri, bary):
@@ -228,7 +262,7 @@ def field_points(V, kind, n_a, n_b=1, r_lo=1.5, r_hi=3.0, seed=0):
     return xyz, coords
 
 
-def mcbem_field(V, T, g, k, N, seed, points, p_samples, eps_scale=1.0, layout=0):
+def mcbem_field(V, T, g, k, N, seed, points, p_samples, eps_scale=1.0, layout=0, poisson=False):
     """Pressure at exterior points from the sample values of an estimate
     (Section 3.4: the field from the Neumann and Dirichlet data): the
     representation formula p(x) = sum_j w (dG/dn_j p_j - G g_j) over the same
@@ -239,7 +273,10 @@ def mcbem_field(V, T, g, k, N, seed, points, p_samples, eps_scale=1.0, layout=0)
     k = np.atleast_1d(np.asarray(k, dtype=np.float64))
     p_samples = np.ascontiguousarray(np.atleast_2d(p_samples), dtype=np.complex128)
     area, nrm, cdf = geometry(V, T)
-    tri, bary = samples(V, T, N, seed)
+    if poisson:
+        tri, bary, _ = poisson_samples(V, T, N, seed)
+    else:
+        tri, bary = samples(V, T, N, seed)
     y = surface_points(V, T, tri, bary)
     ny = np.ascontiguousarray(nrm[tri])
     w, eps = mc_constants(cdf[-1], N, eps_scale)
@@ -271,7 +308,7 @@ def gmres(A, b, tol=1e-12, max_iter=200):
 
 
 def mcbem(V, T, g, k, q_tri, q_bary, N, seed, eps_scale=1.0, tol=1e-12, max_iter=200,
-          layout=0, want_samples=False, jump=0, exact_disk=False):
+          layout=0, want_samples=False, jump=0, exact_disk=False, poisson=False):
     """The whole MC-BEM estimate for n_modes (k_m, g_m) pairs.
 
     g: complex (n_modes, V) per-vertex (layout 0) or (n_modes, T) per triangle.
@@ -295,7 +332,10 @@ def mcbem(V, T, g, k, q_tri, q_bary, N, seed, eps_scale=1.0, tol=1e-12, max_iter
                          float(eps_scale), float(tol), int(max_iter),
                          p.view(np.float64).reshape(-1),
                          ps.ctypes.data_as(C.c_void_p) if ps is not None else None,
-                         iters, resid, tri, bary.reshape(-1), int(jump), int(exact_disk))
+                         iters, resid, tri, bary.reshape(-1), int(jump), int(exact_disk),
+                         int(bool(poisson)))
+    if st == 5:
+        raise ValueError(f"Poisson-disk sampling accepted fewer than N = {N} points")
     out = dict(p=p, iters=iters, resid=resid, tri=tri, bary=bary, status=int(st))
     if want_samples:
         out["p_samples"] = ps
