@@ -766,6 +766,82 @@ def run_field(nat, torch, ctx, args, dev):
     return out
 
 
+def run_scenes(nat, torch, ctx, args, dev):
+    """Training-data generation for a family of scenes (Section 3.4): 16
+    speaker-torus scenes (a speaker patch with g = 1 moving along the axis of
+    a passive torus, per-triangle data, ~9.4k triangles each) x 8
+    frequencies, N = 2048 samples and 4096 surface queries each, solved as
+    one batch (FP32); then the field at 10,000 shell points per (scene,
+    frequency) from each scene's sample values: the (theta, phi, r, |p|)
+    tuples the neural field trains on."""
+    import numpy as np
+    import workloads as W
+    wls = W.config_scenes()
+    meshes, jobs, ps = [], [], []
+    opts = nat.nat_mc_opts_default()
+    opts.layout = nat.NAT_NEUMANN_PER_TRIANGLE
+    for wl in wls:
+        mesh = nat.Mesh(ctx, wl.vertices, wl.tris)
+        meshes.append(mesh)
+        p_s = torch.empty((wl.n_modes, wl.n_samples), dtype=torch.complex128, device=dev)
+        ps.append(p_s)
+        jobs.append(nat.McJob(mesh, torch.from_numpy(wl.g).to(dev), wl.k, torch.from_numpy(wl.q_tri).to(dev),
+                              torch.from_numpy(wl.q_b).to(dev), wl.n_samples, wl.seed, p_samples=p_s,
+                              layout=nat.NAT_NEUMANN_PER_TRIANGLE))
+    P = 10000
+    pts = [nat.nat_field_points(m, nat.NAT_FIELD_SHELL, P, 1, 1.5, 3.0, 100 + i)[0]
+           for i, m in enumerate(meshes)]
+    fout = [torch.empty((wl.n_modes, P), dtype=torch.complex128, device=dev) for wl in wls]
+    fabs = [torch.empty((wl.n_modes, P), dtype=torch.float64, device=dev) for wl in wls]
+
+    def step():
+        reps = nat.nat_mcbem_estimate_batch(ctx, jobs, opts, allow_noconv=True)
+        for i, (wl, m) in enumerate(zip(wls, meshes)):
+            nat.nat_field_points(m, nat.NAT_FIELD_SHELL, P, 1, 1.5, 3.0, 100 + i, points=pts[i])
+            nat.nat_mcbem_field(m, jobs[i].v_n, wl.k, ps[i], wl.n_samples, wl.seed, pts[i], opts,
+                                p_out=fout[i], abs_out=fabs[i])
+        return reps
+
+    step()
+    torch.cuda.synchronize()
+    steps = max(args.steps, 3)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        reps = step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    alg = sum(w.pair_evals() for w in wls) + sum(w.n_modes * P * w.n_samples for w in wls)
+    iters = [r["iters"] for rr in reps for r in rr]
+    out = {"workload": f"{len(wls)} speaker-torus scenes ({len(wls[0].tris)} triangles), "
+                       f"{wls[0].n_modes} frequencies each, N {wls[0].n_samples}, Q {wls[0].n_queries}, "
+                       f"{P} field points per (scene, frequency)",
+           "ms_per_step": round(1e3 * t, 3), "pair_evals_per_s": alg / t,
+           "training_tuples_per_s": sum(w.n_modes for w in wls) * P / t,
+           "gmres_iters": {"mean": float(np.mean(iters)), "max": int(max(iters))}}
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        errs = []
+        for i in (0, len(wls) // 2):
+            wl = wls[i]
+            modes = [0, wl.n_modes - 1]
+            ref = O.mcbem(wl.vertices, wl.tris, wl.g[modes], wl.k[modes], wl.q_tri, wl.q_b, wl.n_samples,
+                          wl.seed, tol=1e-6, layout=1, want_samples=True)
+            got = jobs[i].p_out[modes].cpu().numpy()
+            xs = pts[i][:300].cpu().numpy()
+            fo = O.mcbem_field(wl.vertices, wl.tris, wl.g[modes], wl.k[modes], wl.n_samples, wl.seed, xs,
+                               ref["p_samples"], layout=1)
+            fg = fout[i][modes][:, :300].cpu().numpy()
+            for a, m in enumerate(modes):
+                errs.append({"scene": i, "mode": m,
+                             "surface_rel_l2": float(f"{rel_l2(got[a], ref['p'][a]):.3g}"),
+                             "surface_elementwise": float(f"{rel_max(got[a], ref['p'][a]):.3g}"),
+                             "field_elementwise": float(f"{rel_max(fg[a], fo[a]):.3g}")})
+        out["vs_oracle"] = errs
+    for m in meshes:
+        m.close()
+    return out
+
+
 def run_precision(nat, torch, ctx, args, dev, with_plain=True):
     import numpy as np
     import workloads as W
@@ -845,7 +921,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["batched", "precision", "served", "dense", "field"],
+    ap.add_argument("--workload", choices=["batched", "precision", "served", "dense", "field", "scenes"],
                     default="batched")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--pmc-pass", action="store_true")
@@ -916,6 +992,7 @@ def main():
         out["precision"] = run_precision(nat, torch, ctx, args, dev, with_plain=not args.no_plain)
         out["dense"] = run_dense(nat, torch, ctx, args, dev)
         out["field"] = run_field(nat, torch, ctx, args, dev)
+        out["scenes"] = run_scenes(nat, torch, ctx, args, dev)
         if not args.no_serve:
             out["served"] = run_served(nat, torch, ctx, args, dev)
     elif args.workload == "served":
@@ -935,6 +1012,12 @@ def main():
         out["dtype"] = "f64"
         out["config"] = {"workload": res["workload"]}
         out["dense"] = res
+    elif args.workload == "scenes":
+        res = run_scenes(nat, torch, ctx, args, dev)
+        out["value"] = res["pair_evals_per_s"]
+        out["ms_per_step"] = res["ms_per_step"]
+        out["config"] = {"workload": res["workload"]}
+        out["scenes"] = res
     elif args.workload == "field":
         res = run_field(nat, torch, ctx, args, dev)
         out["metric"] = "exterior field pair-evals/s"
