@@ -27,8 +27,9 @@ Definition (the paper's Sections 3.2-3.4; readings in the design notes):
     after each third of the steps (Section 3.4).
 Everything is float64.  With bf16=True the values the GPU form stores in
 bfloat16 (the MLP's inputs, weights and hidden activations, and the
-back-propagated gradients it multiplies) are rounded to bfloat16 (round to
-nearest even) at the same points, with all sums in float64.
+back-propagated gradients it multiplies and sums for the weights and the
+biases) are rounded to bfloat16 (round to nearest even) at the same
+points, with all sums in float64.
 """
 from __future__ import annotations
 
@@ -177,7 +178,7 @@ def loss_and_grad(theta, phi, r, v, f, target, params, r_lo, r_hi, bf=False):
     gW, gb = [None] * n, [None] * n
     for i in range(n - 1, -1, -1):
         gW[i] = q(dz).T @ acts[i]
-        gb[i] = dz.sum(axis=0)
+        gb[i] = q(dz).sum(axis=0)
         dh = q(dz) @ q(params["W"][i])
         if i > 0:
             dz = dh * (pre[i - 1] > 0.0)
