@@ -137,6 +137,12 @@ typedef struct {
  * accuracy at k times that.  Forces the matrix-free matvec; the plain FP64
  * form ignores it. */
 #define NAT_MC_FP64_PHASE 32
+/* nat_mc_opts.flags: Poisson-disk samples (Section 4.2) instead of
+ * independent ones: the first N points accepted by the parallel Poisson-disk
+ * sampler of nat_mcbem_poisson_samples with the same N and seed.  The
+ * weights stay |Gamma|/N and eps = eps_scale sqrt(|Gamma|/(pi N)).  Fails
+ * with NAT_E_INVALID when fewer than N points are accepted. */
+#define NAT_MC_POISSON 64
 
 /* Per right-hand side report of a solve. */
 typedef struct {
@@ -217,6 +223,25 @@ void nat_mc_opts_default(nat_mc_opts* opts);
  * (double).  Stream-ordered. */
 nat_status nat_mcbem_samples(nat_mesh* mesh, int32_t n_samples, uint64_t seed, int32_t* tri,
                              double* bary, void* stream);
+
+/* Poisson-disk samples (Section 4.2: parallel Poisson-disk sampling, after
+ * Bowers et al. 2010).  Candidates: 16 N area-uniform points; candidate i
+ * takes counters 3i..3i+2 of stream 6 (u0, u1, u2 as for the samples), the
+ * triangle of u0 |Gamma| and (b1, b2) = (u1, u2), or (1 - u1, 1 - u2) when
+ * u1 + u2 > 1.  Radius r = 0.72 sqrt(|Gamma| / N).  Cells of side r/sqrt(3)
+ * over the mesh's bounding box (corner lo = the smallest vertex
+ * coordinates), cell = floor((x - lo) sqrt(3)/r) per axis; a cell's
+ * candidates in index order.  Passes p = 0, 1, ...: phases
+ * (cx mod 3, cy mod 3, cz mod 3) as 9a + 3b + c in order; every cell of the
+ * phase without an accepted point tries its p-th candidate, accepted unless
+ * an accepted point of the 5 x 5 x 5 cells around is closer than r
+ * (positions and squared distances in FP64 as written, no fused
+ * multiply-add).  Outputs (device): tri[N], bary[N][2] = the first N
+ * accepted points in acceptance order (pass, phase, cell key); *n_accepted
+ * (host, may be NULL) = the number accepted.  NAT_E_INVALID if fewer than N
+ * are accepted (outputs then undefined).  Blocks until done. */
+nat_status nat_mcbem_poisson_samples(nat_mesh* mesh, int32_t n_samples, uint64_t seed, int32_t* tri,
+                                     double* bary, int32_t* n_accepted, void* stream);
 
 /* The whole Monte-Carlo estimate of the surface pressure at Q query
  * points for n_modes independent problems (k_m, g_m) on one mesh sharing one

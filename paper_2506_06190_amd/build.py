@@ -24,11 +24,13 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-I", str(ROOT / "include"), "-I", str(SRC), "-Wall", "-Wno-unused-function",
           "-Wno-unused-command-line-argument"]
 PER_FILE = {"nat_api.hip": ["-ffp-contract=off"],
+            # Poisson-disk decisions must round exactly as written (no fused multiply-add)
+            "k_poisson.hip": ["-ffp-contract=off"],
             # keep MFMA accumulators in VGPRs (no AGPR copies around the K loop)
             "k_bem.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 SOURCES = ["nat_api.hip", "nat_solver.hip", "nat_noalloc.hip", "nat_server.hip", "nat_autotune.hip",
            "serve_core.cpp",
-           "k_sample.hip",
+           "k_sample.hip", "k_poisson.hip",
            "k_sum64.hip", "k_sum32.hip", "k_sym32.hip", "k_gmres.hip", "k_bem.hip"]
 
 

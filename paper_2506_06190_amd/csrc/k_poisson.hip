@@ -1,0 +1,453 @@
+// Poisson-disk sample sets (Section 4.2: parallel Poisson-disk sampling,
+// after Bowers, Wang, Wei & Maletz 2010) for every instance of a batch at
+// once.
+//
+// Definition (shared with no other code; the same steps as the CPU oracle):
+//  * candidates: M = 16 N area-uniform points per instance; candidate i
+//    draws u0, u1, u2 from counters 3i..3i+2 of stream 6 of the counter
+//    generator, takes the triangle of u0 |Gamma| as the samples do and the
+//    point (b1, b2) = (u1, u2), folded to (1 - u1, 1 - u2) when u1 + u2 > 1
+//    (exact arithmetic, so every machine gets the same point bits);
+//  * radius r = 0.72 sqrt(|Gamma| / N); cells of side r / sqrt(3) over the
+//    mesh's bounding box (a cell holds at most one accepted point); a cell's
+//    candidates in index order;
+//  * phase of a cell (cx mod 3, cy mod 3, cz mod 3): cells of one phase are
+//    more than r apart, so each phase is decided in parallel;
+//  * passes p = 0, 1, ...: phases 0..26 in order, each cell of the phase
+//    without an accepted point tries its p-th candidate, accepted unless an
+//    accepted point of the 5 x 5 x 5 cells around lies closer than r;
+//  * the instance's samples are its first N accepted points in acceptance
+//    order (pass, phase, cell).
+// Positions and squared distances are formed in FP64 in the written order
+// with no contraction (this file is built with -ffp-contract=off), so the
+// decisions, and the sample records, are bit-for-bit those of any IEEE
+// implementation of the same steps.
+#include "nat_internal.h"
+
+#include <hipcub/hipcub.hpp>
+
+namespace nat {
+namespace {
+
+constexpr int kPhases = 27;
+constexpr int64_t kTagNone = 0x7fff;  // sorts after every real tag
+
+__device__ __forceinline__ uint64_t pd_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double pd_unit(uint64_t seed, uint32_t stream, uint64_t counter)
+{
+    const uint64_t start = seed ^ (static_cast<uint64_t>(stream) << 56);
+    return static_cast<double>(pd_mix64(start + (counter + 1ull) * 0x9E3779B97F4A7C15ull) >> 11) *
+           0x1.0p-53;
+}
+
+__device__ __forceinline__ int32_t pd_search(const double* __restrict__ cdf, int32_t nT, double tau)
+{
+    int32_t lo = 0, hi = nT - 1;
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (cdf[mid] > tau)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// Candidates of every instance: blockIdx.y is the instance.
+__global__ void __launch_bounds__(256) k_pd_candidates(const PdInst* __restrict__ inst,
+                                                       int32_t* __restrict__ ctri,
+                                                       double* __restrict__ cbary,
+                                                       double* __restrict__ cxyz,
+                                                       uint64_t* __restrict__ key,
+                                                       int32_t* __restrict__ idx)
+{
+    const PdInst& I = inst[blockIdx.y];
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= I.M)
+        return;
+    const uint64_t c = 3ull * static_cast<uint64_t>(i);
+    const double u0 = pd_unit(I.seed, 6, c);
+    const double u1 = pd_unit(I.seed, 6, c + 1);
+    const double u2 = pd_unit(I.seed, 6, c + 2);
+    const int32_t t = pd_search(I.cdf, I.nT, u0 * I.area);
+    double b1 = u1, b2 = u2;
+    if (u1 + u2 > 1.0) {
+        b1 = 1.0 - u1;
+        b2 = 1.0 - u2;
+    }
+    const int64_t g = I.coff + i;
+    ctri[g] = t;
+    cbary[2 * g + 0] = b1;
+    cbary[2 * g + 1] = b2;
+    const double* v0 = I.V + 3 * I.T[3 * t + 0];
+    const double* v1 = I.V + 3 * I.T[3 * t + 1];
+    const double* v2 = I.V + 3 * I.T[3 * t + 2];
+    int64_t cell[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double x = v0[d] + b1 * (v1[d] - v0[d]) + b2 * (v2[d] - v0[d]);
+        cxyz[3 * g + d] = x;
+        int64_t q = static_cast<int64_t>(floor((x - I.lo[d]) * I.inv_h));
+        cell[d] = q < 0 ? 0 : (q >= I.dim[d] ? I.dim[d] - 1 : q);
+    }
+    key[g] = (static_cast<uint64_t>(blockIdx.y) << kPdInstShift) |
+             static_cast<uint64_t>((cell[0] * I.dim[1] + cell[1]) * I.dim[2] + cell[2]);
+    idx[g] = static_cast<int32_t>(g);
+}
+
+__device__ __forceinline__ void cell_coords(uint64_t key, const PdInst& I, int64_t* c)
+{
+    const int64_t k = static_cast<int64_t>(key & kPdLocalMask);
+    c[2] = k % I.dim[2];
+    c[1] = (k / I.dim[2]) % I.dim[1];
+    c[0] = k / (I.dim[1] * I.dim[2]);
+}
+
+// Phase of every cell, counts of cells per (instance-independent) phase and
+// the largest candidate count of a cell.
+__global__ void __launch_bounds__(256) k_pd_cells(const PdInst* __restrict__ inst,
+                                                  const uint64_t* __restrict__ ukey,
+                                                  const int32_t* __restrict__ n_cells,
+                                                  const int32_t* __restrict__ count,
+                                                  uint32_t* __restrict__ phase,
+                                                  int32_t* __restrict__ cell_id,
+                                                  int32_t* __restrict__ acc,
+                                                  int32_t* __restrict__ tag,
+                                                  int32_t* __restrict__ stats)
+{
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= *n_cells)
+        return;
+    const uint64_t k = ukey[c];
+    const PdInst& I = inst[k >> kPdInstShift];
+    int64_t cc[3];
+    cell_coords(k, I, cc);
+    const uint32_t ph = static_cast<uint32_t>((cc[0] % 3) * 9 + (cc[1] % 3) * 3 + (cc[2] % 3));
+    phase[c] = ph;
+    cell_id[c] = c;
+    acc[c] = -1;
+    tag[c] = static_cast<int32_t>(kTagNone);
+    atomicAdd(&stats[ph], 1);
+    atomicMax(&stats[kPhases], count[c]);
+}
+
+__device__ __forceinline__ int32_t pd_find(const uint64_t* __restrict__ ukey, int32_t n, uint64_t key)
+{
+    int32_t lo = 0, hi = n - 1;
+    while (lo <= hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        const uint64_t v = ukey[mid];
+        if (v == key)
+            return mid;
+        if (v < key)
+            lo = mid + 1;
+        else
+            hi = mid - 1;
+    }
+    return -1;
+}
+
+// Pass p of phase ph: every cell of the phase without an accepted point
+// tries its p-th candidate.  Cells of one phase are more than r apart, so
+// none reads what another writes in the same launch.
+__global__ void __launch_bounds__(256) k_pd_try(const PdInst* __restrict__ inst,
+                                                const uint64_t* __restrict__ ukey,
+                                                const int32_t* __restrict__ n_cells,
+                                                const int32_t* __restrict__ start,
+                                                const int32_t* __restrict__ count,
+                                                const int32_t* __restrict__ sorted_idx,
+                                                const int32_t* __restrict__ phase_cells,
+                                                int32_t first, int32_t n_phase, int32_t p, int32_t ph,
+                                                const double* __restrict__ cxyz,
+                                                int32_t* __restrict__ acc, int32_t* __restrict__ tag)
+{
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_phase)
+        return;
+    const int32_t c = phase_cells[first + t];
+    if (acc[c] >= 0 || count[c] <= p)
+        return;
+    const int32_t cand = sorted_idx[start[c] + p];
+    const uint64_t k = ukey[c];
+    const uint64_t ibits = k & ~kPdLocalMask;
+    const PdInst& I = inst[k >> kPdInstShift];
+    int64_t cc[3];
+    cell_coords(k, I, cc);
+    const double x0 = cxyz[3 * (int64_t)cand], x1 = cxyz[3 * (int64_t)cand + 1],
+                 x2 = cxyz[3 * (int64_t)cand + 2];
+    const int32_t nc = *n_cells;
+    for (int dx = -2; dx <= 2; ++dx) {
+        const int64_t nx = cc[0] + dx;
+        if (nx < 0 || nx >= I.dim[0])
+            continue;
+        for (int dy = -2; dy <= 2; ++dy) {
+            const int64_t ny = cc[1] + dy;
+            if (ny < 0 || ny >= I.dim[1])
+                continue;
+            for (int dz = -2; dz <= 2; ++dz) {
+                const int64_t nz = cc[2] + dz;
+                if (nz < 0 || nz >= I.dim[2])
+                    continue;
+                const int32_t n = pd_find(ukey, nc, ibits | static_cast<uint64_t>((nx * I.dim[1] + ny) * I.dim[2] + nz));
+                if (n < 0)
+                    continue;
+                const int32_t a = acc[n];
+                if (a < 0)
+                    continue;
+                const double ex = x0 - cxyz[3 * (int64_t)a];
+                const double ey = x1 - cxyz[3 * (int64_t)a + 1];
+                const double ez = x2 - cxyz[3 * (int64_t)a + 2];
+                const double d2 = ex * ex + ey * ey + ez * ez;
+                if (d2 < I.r2)
+                    return;
+            }
+        }
+    }
+    acc[c] = cand;
+    tag[c] = p * kPhases + ph;
+}
+
+// Acceptance-order keys: (instance, tag, cell); the accepted count of each
+// instance.
+__global__ void __launch_bounds__(256) k_pd_order(const uint64_t* __restrict__ ukey,
+                                                  const int32_t* __restrict__ n_cells,
+                                                  const int32_t* __restrict__ acc,
+                                                  const int32_t* __restrict__ tag,
+                                                  uint64_t* __restrict__ okey,
+                                                  int32_t* __restrict__ oval,
+                                                  int32_t* __restrict__ n_acc)
+{
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= *n_cells)
+        return;
+    const uint64_t inst = ukey[c] >> kPdInstShift;
+    okey[c] = (inst << 47) | (static_cast<uint64_t>(tag[c]) << 32) | static_cast<uint64_t>(c);
+    oval[c] = acc[c];
+    if (acc[c] >= 0)
+        atomicAdd(&n_acc[inst], 1);
+}
+
+// First cell (in key order) of every instance.
+__global__ void __launch_bounds__(256) k_pd_inst_first(const uint64_t* __restrict__ ukey,
+                                                       const int32_t* __restrict__ n_cells,
+                                                       int32_t n_inst, int32_t* __restrict__ first)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_inst)
+        return;
+    const uint64_t lo_key = static_cast<uint64_t>(i) << kPdInstShift;
+    int32_t lo = 0, hi = *n_cells;
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (ukey[mid] < lo_key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    first[i] = lo;
+}
+
+// The first N accepted points of every instance, as sample records.
+__global__ void __launch_bounds__(256) k_pd_gather(const PdInst* __restrict__ inst,
+                                                   const int32_t* __restrict__ first,
+                                                   const int32_t* __restrict__ oval_sorted,
+                                                   const int32_t* __restrict__ ctri,
+                                                   const double* __restrict__ cbary,
+                                                   int32_t* __restrict__ tri, double* __restrict__ bary)
+{
+    const PdInst& I = inst[blockIdx.y];
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= I.N)
+        return;
+    const int32_t cand = oval_sorted[first[blockIdx.y] + j];
+    tri[I.on + j] = ctri[cand];
+    bary[2 * (I.on + j) + 0] = cbary[2 * (int64_t)cand + 0];
+    bary[2 * (I.on + j) + 1] = cbary[2 * (int64_t)cand + 1];
+}
+
+inline dim3 pd_grid(int64_t n) { return dim3(static_cast<unsigned>((n + 255) / 256)); }
+
+// scratch of the library primitives for up to M items
+size_t pd_temp_bytes(int64_t M)
+{
+    size_t sort64 = 0, sort32 = 0, rle = 0, scan = 0;
+    hipcub::DeviceRadixSort::SortPairs(nullptr, sort64, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                       (int32_t*)nullptr, (int32_t*)nullptr, (int)M, 0, 64);
+    hipcub::DeviceRadixSort::SortPairs(nullptr, sort32, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                                       (int32_t*)nullptr, (int32_t*)nullptr, (int)M, 0, 5);
+    hipcub::DeviceRunLengthEncode::Encode(nullptr, rle, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                          (int32_t*)nullptr, (int32_t*)nullptr, (int)M);
+    hipcub::DeviceScan::ExclusiveSum(nullptr, scan, (int32_t*)nullptr, (int32_t*)nullptr, (int)M);
+    size_t temp = sort64;
+    temp = temp > sort32 ? temp : sort32;
+    temp = temp > rle ? temp : rle;
+    temp = temp > scan ? temp : scan;
+    return temp;
+}
+
+}  // namespace
+
+size_t pd_workspace_bytes(int64_t total_candidates, int32_t n_inst)
+{
+    const int64_t M = total_candidates > 0 ? total_candidates : 1;
+    const size_t temp = pd_temp_bytes(M);
+    return carve_size<>({sizeof(int32_t) * M, sizeof(double) * 2 * M, sizeof(double) * 3 * M,
+                         sizeof(uint64_t) * M, sizeof(uint64_t) * M, sizeof(int32_t) * M,
+                         sizeof(int32_t) * M, sizeof(uint64_t) * M, sizeof(int32_t) * M,
+                         sizeof(int32_t) * M, sizeof(uint32_t) * M, sizeof(uint32_t) * M,
+                         sizeof(int32_t) * M, sizeof(int32_t) * M, sizeof(int32_t) * M,
+                         sizeof(int32_t) * M, sizeof(int32_t) * (kPhases + 1) * 2,
+                         sizeof(int32_t) * n_inst, sizeof(int32_t) * n_inst, sizeof(int32_t) * 2, temp});
+}
+
+// The record of one instance: radius r = 0.72 sqrt(A / N), the grid of
+// cells of side r / sqrt(3) over the mesh's bounding box, 16 N candidates.
+nat_status pd_instance(const nat_mesh* m, int32_t N, uint64_t seed, int64_t coff, int64_t on, PdInst* out)
+{
+    PdInst I{};
+    I.V = m->d_V;
+    I.T = m->d_T;
+    I.cdf = m->d_cdf;
+    I.nT = m->nT;
+    I.area = m->area_total;
+    I.seed = seed;
+    I.N = N;
+    I.M = kPdCandidates * N;
+    I.coff = coff;
+    I.on = on;
+    const double r = kPdRadiusScale * std::sqrt(I.area / (double)N);
+    I.r2 = r * r;
+    I.inv_h = std::sqrt(3.0) / r;
+    double lo[3] = {m->V[0], m->V[1], m->V[2]}, hi[3] = {m->V[0], m->V[1], m->V[2]};
+    for (int32_t v = 1; v < m->nV; ++v)
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = m->V[3 * (size_t)v + c] < lo[c] ? m->V[3 * (size_t)v + c] : lo[c];
+            hi[c] = m->V[3 * (size_t)v + c] > hi[c] ? m->V[3 * (size_t)v + c] : hi[c];
+        }
+    double cells = 1.0;
+    for (int c = 0; c < 3; ++c) {
+        I.lo[c] = lo[c];
+        I.dim[c] = (int64_t)std::floor((hi[c] - lo[c]) * I.inv_h) + 1;
+        cells *= (double)I.dim[c];
+    }
+    if (!(cells < (double)kPdLocalMask))
+        return fail(NAT_E_INVALID, "Poisson-disk sampling: %g grid cells over the mesh's box", cells);
+    *out = I;
+    return NAT_OK;
+}
+
+nat_status run_poisson(nat_ctx* ctx, const PdInst* d_inst, const std::vector<PdInst>& h_inst,
+                       void* ws, size_t ws_bytes, int32_t* tri, double* bary, hipStream_t s,
+                       std::vector<int32_t>* accepted)
+{
+    const int32_t nj = static_cast<int32_t>(h_inst.size());
+    int64_t M = 0;
+    int32_t max_m = 0, max_n = 0;
+    for (const PdInst& I : h_inst) {
+        M += I.M;
+        max_m = I.M > max_m ? I.M : max_m;
+        max_n = I.N > max_n ? I.N : max_n;
+    }
+    if (M > (int64_t(1) << 30))
+        return fail(NAT_E_INVALID, "Poisson-disk sampling: %lld candidates", (long long)M);
+    const size_t need = pd_workspace_bytes(M, nj);
+    if (need > ws_bytes)
+        return fail(NAT_E_INTERNAL, "Poisson-disk sampling: workspace %zu < %zu", ws_bytes, need);
+    Carver cv(ws);
+    int32_t* ctri = cv.take<int32_t>(M);
+    double* cbary = cv.take<double>(2 * M);
+    double* cxyz = cv.take<double>(3 * M);
+    uint64_t* key = cv.take<uint64_t>(M);
+    uint64_t* key_s = cv.take<uint64_t>(M);
+    int32_t* idx = cv.take<int32_t>(M);
+    int32_t* idx_s = cv.take<int32_t>(M);
+    uint64_t* ukey = cv.take<uint64_t>(M);
+    int32_t* count = cv.take<int32_t>(M);
+    int32_t* start = cv.take<int32_t>(M);
+    uint32_t* phase = cv.take<uint32_t>(M);
+    uint32_t* phase_s = cv.take<uint32_t>(M);
+    int32_t* cell_id = cv.take<int32_t>(M);
+    int32_t* phase_cells = cv.take<int32_t>(M);
+    int32_t* acc = cv.take<int32_t>(M);
+    int32_t* tag = cv.take<int32_t>(M);
+    int32_t* stats = cv.take<int32_t>((kPhases + 1) * 2);   // per-phase counts, max count
+    int32_t* first = cv.take<int32_t>(nj);
+    int32_t* n_acc = cv.take<int32_t>(nj);
+    int32_t* n_cells = cv.take<int32_t>(2);
+    // the library primitives' scratch
+    const size_t temp_bytes = pd_temp_bytes(M);
+    void* temp = cv.take<char>(temp_bytes);
+    // the acceptance-order keys reuse the candidate key arrays
+    uint64_t* okey = key;
+    uint64_t* okey_s = key_s;
+    int32_t* oval = idx;
+    int32_t* oval_s = count;  // the counts are not needed once the passes are done
+
+    hipLaunchKernelGGL(k_pd_candidates, dim3((max_m + 255) / 256, nj), dim3(256), 0, s, d_inst, ctri, cbary,
+                       cxyz, key, idx);
+    NAT_HIP(hipGetLastError());
+    size_t tb = temp_bytes;
+    NAT_HIP(hipcub::DeviceRadixSort::SortPairs(temp, tb, key, key_s, idx, idx_s, (int)M, 0, 64, s));
+    tb = temp_bytes;
+    NAT_HIP(hipcub::DeviceRunLengthEncode::Encode(temp, tb, key_s, ukey, count, n_cells, (int)M, s));
+    tb = temp_bytes;
+    NAT_HIP(hipcub::DeviceScan::ExclusiveSum(temp, tb, count, start, (int)M, s));
+    NAT_HIP(hipMemsetAsync(stats, 0, sizeof(int32_t) * (kPhases + 1), s));
+    NAT_HIP(hipMemsetAsync(n_acc, 0, sizeof(int32_t) * nj, s));
+    hipLaunchKernelGGL(k_pd_cells, pd_grid(M), dim3(256), 0, s, d_inst, ukey, n_cells, count, phase, cell_id,
+                       acc, tag, stats);
+    NAT_HIP(hipGetLastError());
+    int32_t h_nc = 0;
+    int32_t h_stats[kPhases + 1];
+    NAT_HIP(hipMemcpyAsync(&h_nc, n_cells, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    NAT_HIP(hipMemcpyAsync(h_stats, stats, sizeof(h_stats), hipMemcpyDeviceToHost, s));
+    NAT_HIP(hipStreamSynchronize(s));
+    // cells grouped by phase, key order within a phase (the sort is stable)
+    tb = temp_bytes;
+    NAT_HIP(hipcub::DeviceRadixSort::SortPairs(temp, tb, phase, phase_s, cell_id, phase_cells, h_nc, 0, 5, s));
+    int32_t off[kPhases + 1];
+    off[0] = 0;
+    for (int ph = 0; ph < kPhases; ++ph)
+        off[ph + 1] = off[ph] + h_stats[ph];
+    const int32_t maxc = h_stats[kPhases];
+    if ((int64_t)maxc * kPhases >= kTagNone)
+        return fail(NAT_E_INVALID, "Poisson-disk sampling: %d candidates in one cell", maxc);
+    for (int32_t p = 0; p < maxc; ++p)
+        for (int ph = 0; ph < kPhases; ++ph) {
+            const int32_t n_ph = off[ph + 1] - off[ph];
+            if (n_ph == 0)
+                continue;
+            hipLaunchKernelGGL(k_pd_try, pd_grid(n_ph), dim3(256), 0, s, d_inst, ukey, n_cells, start, count,
+                               idx_s, phase_cells, off[ph], n_ph, p, ph, cxyz, acc, tag);
+            NAT_HIP(hipGetLastError());
+        }
+    hipLaunchKernelGGL(k_pd_order, pd_grid(h_nc), dim3(256), 0, s, ukey, n_cells, acc, tag, okey, oval, n_acc);
+    NAT_HIP(hipGetLastError());
+    tb = temp_bytes;
+    NAT_HIP(hipcub::DeviceRadixSort::SortPairs(temp, tb, okey, okey_s, oval, oval_s, h_nc, 0, 64, s));
+    hipLaunchKernelGGL(k_pd_inst_first, pd_grid(nj), dim3(256), 0, s, ukey, n_cells, nj, first);
+    NAT_HIP(hipGetLastError());
+    std::vector<int32_t> h_acc(nj);
+    NAT_HIP(hipMemcpyAsync(h_acc.data(), n_acc, sizeof(int32_t) * nj, hipMemcpyDeviceToHost, s));
+    NAT_HIP(hipStreamSynchronize(s));
+    if (accepted)
+        *accepted = h_acc;
+    for (int32_t i = 0; i < nj; ++i)
+        if (h_acc[i] < h_inst[i].N)
+            return fail(NAT_E_INVALID,
+                        "Poisson-disk sampling of job %d accepted %d points, fewer than N = %d", i,
+                        h_acc[i], h_inst[i].N);
+    hipLaunchKernelGGL(k_pd_gather, dim3((max_n + 255) / 256, nj), dim3(256), 0, s, d_inst, first, oval_s, ctri,
+                       cbary, tri, bary);
+    NAT_HIP(hipGetLastError());
+    (void)ctx;
+    return NAT_OK;
+}
+
+}  // namespace nat

@@ -366,10 +366,13 @@ hipError_t launch_surface_batch(const SurfBatch& b, int32_t max_n, int32_t max_q
         return hipSuccess;
     const int32_t mx = max_n > max_q ? max_n : max_q;
     const unsigned nj = static_cast<unsigned>(b.n_jobs);
-    hipLaunchKernelGGL(k_samples_batch, dim3((max_n + 255) / 256, nj), dim3(256), 0, s, b);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
+    hipError_t e = hipSuccess;
+    if (!b.samples_given) {
+        hipLaunchKernelGGL(k_samples_batch, dim3((max_n + 255) / 256, nj), dim3(256), 0, s, b);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
     hipLaunchKernelGGL(k_points_batch, dim3((mx + 255) / 256, nj, max_q > 0 ? 2 : 1), dim3(256), 0, s, b);
     e = hipGetLastError();
     if (e != hipSuccess)

@@ -288,6 +288,7 @@ struct SurfBatch {
     double2* gq;                       // per system [Q] at og_q + m Q
     int32_t* flags;                    // [0] query out of range, [1] non-finite Neumann data
     double* qfac;                      // per instance [Q] at oq: 1 / c_q, or null (c_q = 1/2)
+    int32_t samples_given;             // 1: tri/bary already hold the samples (Poisson-disk sets)
 };
 // Device-side argument checks of every instance (flags are OR-ed, not cleared):
 // flags[0] for a query record out of range or a non-finite field point.
@@ -298,6 +299,30 @@ hipError_t launch_field_points(const nat_mesh* m, int32_t kind, int32_t n_a, int
 hipError_t launch_abs(const double2* z, int64_t n, double* out, hipStream_t s);
 // Samples, points and Neumann data of every instance.
 hipError_t launch_surface_batch(const SurfBatch& b, int32_t max_n, int32_t max_q, hipStream_t s);
+
+// ---- Poisson-disk sample sets (k_poisson.hip) --------------------------------
+constexpr int32_t kPdCandidates = 16;       // candidates per requested sample
+constexpr double kPdRadiusScale = 0.72;     // r = kPdRadiusScale sqrt(|Gamma| / N)
+constexpr int kPdInstShift = 40;            // cell key: instance << 40 | cell in the instance's grid
+constexpr uint64_t kPdLocalMask = (uint64_t(1) << kPdInstShift) - 1;
+struct PdInst {
+    const double* V;                   // mesh vertices, triangles, running area sum (device)
+    const int32_t* T;
+    const double* cdf;
+    int32_t nT, N, M, pad;             // triangles, samples wanted, candidates
+    double area, r2, inv_h;            // |Gamma|, r^2, sqrt(3) / r
+    double lo[3];                      // bounding-box corner
+    int64_t dim[3];                    // cells per axis
+    int64_t coff, on;                  // first candidate / sample of the instance in the batch
+    uint64_t seed;
+};
+nat_status pd_instance(const nat_mesh* m, int32_t N, uint64_t seed, int64_t coff, int64_t on, PdInst* out);
+size_t pd_workspace_bytes(int64_t total_candidates, int32_t n_inst);
+// Samples of every instance into tri[on + j], bary[on + j] (device arrays);
+// accepted (optional) receives each instance's accepted count.  Blocks.
+nat_status run_poisson(nat_ctx* ctx, const PdInst* d_inst, const std::vector<PdInst>& h_inst, void* ws,
+                       size_t ws_bytes, int32_t* tri, double* bary, hipStream_t s,
+                       std::vector<int32_t>* accepted);
 
 // ---- kernel sums ----------------------------------------------------------
 // Operation of a kernel sum over sources j for target i (w = |Gamma|/N):

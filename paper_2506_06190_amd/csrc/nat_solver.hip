@@ -399,7 +399,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     if (!(opts->eps_scale > 0.0) || !is_finite(opts->eps_scale) || !(opts->gmres_tol > 0.0) ||
         opts->gmres_max_iter < 1 || opts->gmres_max_iter > 1000 ||
         (opts->flags & ~(NAT_MC_NO_GRAPH | NAT_MC_ASSEMBLED | NAT_MC_MATRIX_FREE | NAT_MC_EXACT_DISK |
-                         NAT_MC_ORDERED_SUM | NAT_MC_FP64_PHASE)) ||
+                         NAT_MC_ORDERED_SUM | NAT_MC_FP64_PHASE | NAT_MC_POISSON)) ||
         ((opts->flags & NAT_MC_ASSEMBLED) && (opts->flags & (NAT_MC_MATRIX_FREE | NAT_MC_FP64_PHASE))))
         return fail(NAT_E_INVALID, "Monte-Carlo estimate: bad solver options");
     if (opts->jump != NAT_JUMP_HALF && opts->jump != NAT_JUMP_POLYHEDRAL)
@@ -540,6 +540,9 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     T.max_items = sum_ch;
     const int64_t n_part = sum_pa > sum_pb ? sum_pa : sum_pb;
     const int64_t gram_stride = (int64_t)mm1 * mm1;
+    // Poisson-disk samples (Section 4.2): candidate pools of every instance
+    const bool poisson = (opts->flags & NAT_MC_POISSON) != 0;
+    const size_t pd_bytes = poisson ? pd_workspace_bytes((int64_t)kPdCandidates * (int64_t)inst_n, nj) : 0;
     const size_t bytes = carve_size<>(
         {sizeof(int32_t) * 8, sizeof(int32_t) * inst_n, sizeof(double) * 2 * inst_n,
          sizeof(double) * 3 * inst_n, sizeof(double) * 3 * inst_n, sizeof(float) * 3 * inst_n,
@@ -557,7 +560,7 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
          sizeof(int2) * sum_ch, sizeof(double) * S, sizeof(double2) * S, sizeof(int64_t) * 8,
          sizeof(SurfJob) * nj,
          with_qfac ? sizeof(double) * inst_q : 0, sizeof(float2) * sum_k,
-         sizeof(int32_t) * asm_list.size()});
+         sizeof(int32_t) * asm_list.size(), sizeof(PdInst) * (poisson ? nj : 0), pd_bytes});
     if (bytes_only) {
         *bytes_only = bytes;
         return NAT_OK;
@@ -619,6 +622,8 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     double* qfac_all = with_qfac ? cv.take<double>(inst_q) : nullptr;
     float2* kmat = sum_k > 0 ? cv.take<float2>(sum_k) : nullptr;
     int32_t* d_asm_list = asm_list.empty() ? nullptr : cv.take<int32_t>(asm_list.size());
+    PdInst* d_pd = poisson ? cv.take<PdInst>(nj) : nullptr;
+    void* pd_ws = poisson ? cv.take<char>(pd_bytes) : nullptr;
     T.d_nitems = dcnt + 2;
     T.d_ngroups_mv = dcnt + 3;
     T.d_iter = dcnt + 4;
@@ -806,6 +811,28 @@ nat_status run_mc(nat_ctx* ctx, const McJob* jobs, int32_t nj, const nat_mc_opts
     NAT_HIP(sev.record(0, s));
 
     // ---- samples, points, Neumann data (Section 4.1.1) -----------------------
+    if (poisson) {
+        // Poisson-disk sets instead of independent samples (Section 4.2)
+        std::vector<PdInst> pd(nj);
+        int64_t coff = 0, on = 0;
+        for (int32_t i = 0; i < nj; ++i) {
+            st = pd_instance(jobs[i].mesh, jobs[i].N, jobs[i].seed, coff, on, &pd[i]);
+            if (st != NAT_OK)
+                return st;
+            coff += pd[i].M;
+            on += jobs[i].N;
+        }
+        void* pin = nullptr;
+        st = pinned(ctx, sizeof(PdInst) * nj + 64, &pin);
+        if (st != NAT_OK)
+            return st;
+        std::memcpy(pin, pd.data(), sizeof(PdInst) * nj);
+        NAT_HIP(hipMemcpyAsync(d_pd, pin, sizeof(PdInst) * nj, hipMemcpyHostToDevice, s));
+        st = run_poisson(ctx, d_pd, pd, pd_ws, pd_bytes, tri_all, bary_all, s, nullptr);
+        if (st != NAT_OK)
+            return st;
+        sbat.samples_given = 1;
+    }
     NAT_HIP(launch_surface_batch(sbat, max_n, max_q, s));
     NAT_HIP(sev.record(1, s));
 
@@ -1165,6 +1192,46 @@ nat_status nat_mcbem_estimate(nat_mesh* mesh, const double* v_n, int32_t n_modes
         return nat::fail(NAT_E_INVALID, "nat_mcbem_estimate: mesh is NULL");
     nat::McJob J{mesh, v_n, n_modes, Q, N, k, q_tri, q_bary, seed, p_out, p_samples};
     return nat::run_mc(mesh->ctx, &J, 1, opts, report, static_cast<hipStream_t>(stream), nullptr);
+}
+
+nat_status nat_mcbem_poisson_samples(nat_mesh* mesh, int32_t N, uint64_t seed, int32_t* tri,
+                                     double* bary, int32_t* n_accepted, void* stream)
+{
+    using namespace nat;
+    if (n_accepted)
+        *n_accepted = 0;
+    if (!mesh || !tri || !bary)
+        return fail(NAT_E_INVALID, "nat_mcbem_poisson_samples: NULL argument");
+    if (N < 2 || N > (1 << 24))
+        return fail(NAT_E_INVALID, "nat_mcbem_poisson_samples: N = %d", N);
+    nat_ctx* ctx = mesh->ctx;
+    nat_status st = set_device(ctx);
+    if (st != NAT_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<PdInst> pd(1);
+    st = pd_instance(mesh, N, seed, 0, 0, &pd[0]);
+    if (st != NAT_OK)
+        return st;
+    const size_t pdb = pd_workspace_bytes(pd[0].M, 1);
+    void* ws = nullptr;
+    st = workspace(ctx, carve_size<>({sizeof(PdInst), pdb}), &ws);
+    if (st != NAT_OK)
+        return st;
+    Carver cv(ws);
+    PdInst* d_pd = cv.take<PdInst>(1);
+    void* pws = cv.take<char>(pdb);
+    void* pin = nullptr;
+    st = pinned(ctx, sizeof(PdInst) + 64, &pin);
+    if (st != NAT_OK)
+        return st;
+    std::memcpy(pin, pd.data(), sizeof(PdInst));
+    NAT_HIP(hipMemcpyAsync(d_pd, pin, sizeof(PdInst), hipMemcpyHostToDevice, s));
+    std::vector<int32_t> acc;
+    st = run_poisson(ctx, d_pd, pd, pws, pdb, tri, bary, s, &acc);
+    if (n_accepted && !acc.empty())
+        *n_accepted = acc[0];
+    return st;
 }
 
 nat_status nat_mcbem_field(nat_mesh* mesh, const double* v_n, int32_t n_modes, const double* k,

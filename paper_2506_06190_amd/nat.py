@@ -36,6 +36,7 @@ NAT_MC_MATRIX_FREE = 4
 NAT_MC_EXACT_DISK = 8
 NAT_MC_ORDERED_SUM = 16
 NAT_MC_FP64_PHASE = 32
+NAT_MC_POISSON = 64
 NAT_JUMP_HALF = 0
 NAT_JUMP_POLYHEDRAL = 1
 NAT_FIELD_SHELL = 0
@@ -117,6 +118,7 @@ _SIGS = {
     "nat_mesh_vertex_queries": ([_P, _P, _P], C.c_int),
     "nat_mc_opts_default": ([C.POINTER(nat_mc_opts)], None),
     "nat_mcbem_samples": ([_P, C.c_int32, C.c_uint64, _P, _P, _P], C.c_int),
+    "nat_mcbem_poisson_samples": ([_P, C.c_int32, C.c_uint64, _P, _P, C.POINTER(C.c_int32), _P], C.c_int),
     "nat_mcbem_estimate": ([_P, _P, C.c_int32, _P, _P, _P, C.c_int32, C.c_int32, C.c_uint64,
                             C.POINTER(nat_mc_opts), _P, _P, _P, _P], C.c_int),
     "nat_mcbem_estimate_noalloc": ([_P, _P, C.c_int32, _P, _P, _P, C.c_int32, C.c_int32, C.c_uint64,
@@ -386,6 +388,22 @@ def nat_mcbem_samples(mesh: Mesh, n_samples: int, seed: int, tri, bary, stream=N
                                    _dptr(tri, torch.int32, (n_samples,), "tri"),
                                    _dptr(bary, torch.float64, (n_samples, 2), "bary"),
                                    _stream(stream)))
+
+
+def nat_mcbem_poisson_samples(mesh: Mesh, n_samples: int, seed: int, tri=None, bary=None, stream=None,
+                              device="cuda"):
+    """Poisson-disk sample records: (tri [N] int32, bary [N, 2] float64, accepted count)."""
+    import torch
+    if tri is None:
+        tri = torch.empty(n_samples, dtype=torch.int32, device=device)
+    if bary is None:
+        bary = torch.empty((n_samples, 2), dtype=torch.float64, device=device)
+    n = C.c_int32(0)
+    _check(lib().nat_mcbem_poisson_samples(mesh.handle, int(n_samples), C.c_uint64(seed),
+                                           _dptr(tri, torch.int32, (n_samples,), "tri"),
+                                           _dptr(bary, torch.float64, (n_samples, 2), "bary"),
+                                           C.byref(n), _stream(stream)))
+    return tri, bary, int(n.value)
 
 
 def nat_mcbem_estimate(mesh: Mesh, v_n, k: Sequence[float], q_tri, q_bary, n_samples: int,
