@@ -112,6 +112,8 @@ def pe(c):
     """Positional encoding of scalars c (B, m) -> (B, 12 m): per scalar
     sin(2^k pi c), cos(2^k pi c), k = 0..5."""
     c = np.atleast_2d(np.asarray(c, dtype=np.float64))
+    if c.shape[1] == 0:
+        return np.zeros((c.shape[0], 0))
     cols = []
     for s in range(c.shape[1]):
         for k in range(PE_FREQS):

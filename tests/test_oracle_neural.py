@@ -127,3 +127,21 @@ def test_training_fits_a_smooth_field(bf):
         first = loss if first is None else first
         NF.adam_step(p, g, st, s, 200)
     assert loss < 0.1 * first, (first, loss)
+
+
+def test_frequency_only_input_layout():
+    """With no condition variables the input is [G (16) | P(f) (12) | 0 (4)]:
+    width 32, P(f) the closed-form sines and cosines of 2^k pi f, the pad
+    zero."""
+    B = 5
+    th, ph, r, v, f = _batch(B, 0, 11)
+    p = NF.init_params(0, 1, 2)
+    x = NF.encode(th, ph, r, v, f, p["grid"], 1.5, 3.0)
+    assert NF.input_dim(0) == 32 and x.shape == (B, 32)
+    for k in range(6):
+        a = (2.0 ** k) * np.pi * f
+        assert np.allclose(x[:, 16 + 2 * k], np.sin(a), atol=1e-15)
+        assert np.allclose(x[:, 17 + 2 * k], np.cos(a), atol=1e-15)
+    assert np.all(x[:, 28:] == 0.0)
+    y, _ = NF.forward(x, p)
+    assert y.shape == (B, 1)
