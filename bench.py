@@ -842,6 +842,92 @@ def run_scenes(nat, torch, ctx, args, dev):
     return out
 
 
+def run_neural(nat, torch, ctx, args, dev):
+    """Neural-field training and inference (Sections 3.2-3.4): one condition
+    variable and the frequency, |p| as the one output, synthetic training
+    rows of the paper's shell (directions uniform, 1.5-3 R) with a smooth
+    target.  Training steps of 2^18 rows (loss, gradient of every parameter,
+    Adam) and inference over 2^20 rows.  The credited work is the MLP's
+    products (2 flops per multiply-add: forward, input gradient, weight
+    gradient) against the bfloat16 matrix-core peak, and the step's
+    algorithmic HBM bytes (each activation written and read in both
+    layouts) against 8 TB/s."""
+    import numpy as np
+    import workloads as W
+    n_v, n_out, B, B_inf = 1, 1, 1 << 18, 1 << 20
+
+    def rows_of(n, seed):
+        th, ph, r, v, f = W.nf_rows(n, n_v, seed)
+        tgt = W.nf_smooth_target(th, ph, r, v, f, n_out)
+        rows = np.concatenate([th[:, None], ph[:, None], r[:, None], v, f[:, None]], axis=1)
+        return (torch.from_numpy(rows.astype(np.float32)).to(dev),
+                torch.from_numpy(tgt.astype(np.float32)).to(dev), (th, ph, r, v, f, tgt))
+
+    x, t, host = rows_of(B, 21)
+    xi, _, _ = rows_of(B_inf, 22)
+    nf = nat.NeuralField(ctx, n_v, n_out, 1.5, 3.0, seed=5)
+    D = nf.input_dim
+    steps = max(args.steps, 20)
+    warm = max(args.warmup, 2)
+    total = warm + steps + 1
+    first = nf.train_step(x, t, 0, total)
+    for s in range(1, warm):
+        nf.train_step(x, t, s, total, want_loss=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        nf.train_step(x, t, warm + s, total, want_loss=False)
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / steps
+    last = nf.train_step(x, t, total - 1, total)
+    y = nf.infer(xi)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        nf.infer(xi, out=y)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t0) / reps
+    H = 128
+    fwd = 2 * (D * H + 3 * H * H + H * n_out)
+    bwd_in = 2 * (3 * H * H + H * 32 + H * n_out)
+    wgrad = 2 * (D * H + 3 * H * H + H * n_out)
+    flops_step = B * (fwd + bwd_in + wgrad)
+    # HBM bytes per row of the step as built (bfloat16 = 2 B): the input
+    # row written in both layouts and read twice (forward, weight gradient);
+    # each hidden activation written in both layouts and read three times
+    # (next product, ReLU mask, weight gradient); each dZ_0..3 written in
+    # both layouts and read twice; dH_0 (16 FP32) written and read; the input
+    # row (5 FP32) read twice and the target once.  The grid tables (1.6 MB)
+    # stay in L2.
+    per_row = 2 * (2 * D + 2 * D) + 4 * 2 * (2 * H + 3 * H) + 4 * 2 * (2 * H + 2 * H) + 2 * 64 + 44
+    bytes_step = B * per_row
+    tf = flops_step / t_step / 1e12
+    bw = bytes_step / t_step / 1e9
+    out = {"workload": f"neural field (grid 4 levels x 4 features, PE 6 freqs, MLP 4x128), n_v {n_v}, "
+                       f"D {D}, training batch {B} rows, inference {B_inf} rows",
+           "train_ms_per_step": round(1e3 * t_step, 4), "train_rows_per_s": B / t_step,
+           "infer_ms": round(1e3 * t_inf, 4), "infer_rows_per_s": B_inf / t_inf,
+           "loss_first": first, "loss_after": last, "steps_trained": total,
+           "mfma": {"achieved": round(tf, 3), "peak": 2500.0, "unit": "TFLOP/s",
+                    "frac": round(tf / 2500.0, 5), "flops_per_step": flops_step},
+           "hbm": {"achieved": round(bw, 1), "peak": 8000.0, "unit": "GB/s", "frac": round(bw / 8000.0, 4),
+                   "bytes_per_step": bytes_step}}
+    if not args.no_cpu_baseline:
+        from oracle import neural as NF
+        th, ph, r, v, f, tgt = host
+        n = 16384
+        p = NF.init_params(n_v, n_out, 5)
+        t0 = time.perf_counter()
+        loss, g = NF.loss_and_grad(th[:n], ph[:n], r[:n], v[:n], f[:n], tgt[:n], p, 1.5, 3.0, bf=True)
+        NF.adam_step(p, g, {}, 0, 10)
+        t_cpu = time.perf_counter() - t0
+        out["cpu_oracle"] = {"rows_per_s": n / t_cpu, "sample": f"one training step of {n} rows",
+                             "kind": "oracle"}
+    nf.close()
+    return out
+
+
 def run_precision(nat, torch, ctx, args, dev, with_plain=True):
     import numpy as np
     import workloads as W
@@ -921,7 +1007,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["batched", "precision", "served", "dense", "field", "scenes"],
+    ap.add_argument("--workload", choices=["batched", "precision", "served", "dense", "field", "scenes", "neural"],
                     default="batched")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--pmc-pass", action="store_true")
@@ -993,6 +1079,7 @@ def main():
         out["dense"] = run_dense(nat, torch, ctx, args, dev)
         out["field"] = run_field(nat, torch, ctx, args, dev)
         out["scenes"] = run_scenes(nat, torch, ctx, args, dev)
+        out["neural"] = run_neural(nat, torch, ctx, args, dev)
         if not args.no_serve:
             out["served"] = run_served(nat, torch, ctx, args, dev)
     elif args.workload == "served":
@@ -1018,6 +1105,15 @@ def main():
         out["ms_per_step"] = res["ms_per_step"]
         out["config"] = {"workload": res["workload"]}
         out["scenes"] = res
+    elif args.workload == "neural":
+        res = run_neural(nat, torch, ctx, args, dev)
+        out["metric"] = "neural-field training rows/s"
+        out["unit"] = "rows/s"
+        out["value"] = res["train_rows_per_s"]
+        out["ms_per_step"] = res["train_ms_per_step"]
+        out["dtype"] = "bf16"
+        out["config"] = {"workload": res["workload"]}
+        out["neural"] = res
     elif args.workload == "field":
         res = run_field(nat, torch, ctx, args, dev)
         out["metric"] = "exterior field pair-evals/s"

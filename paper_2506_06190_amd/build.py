@@ -31,7 +31,8 @@ PER_FILE = {"nat_api.hip": ["-ffp-contract=off"],
 SOURCES = ["nat_api.hip", "nat_solver.hip", "nat_noalloc.hip", "nat_server.hip", "nat_autotune.hip",
            "serve_core.cpp",
            "k_sample.hip", "k_poisson.hip",
-           "k_sum64.hip", "k_sum32.hip", "k_sym32.hip", "k_gmres.hip", "k_bem.hip"]
+           "k_sum64.hip", "k_sum32.hip", "k_sym32.hip", "k_gmres.hip", "k_bem.hip",
+           "k_neural.hip"]
 
 
 def _compile(name: str) -> Path:

@@ -277,13 +277,15 @@ inline dim3 pd_grid(int64_t n) { return dim3(static_cast<unsigned>((n + 255) / 2
 size_t pd_temp_bytes(int64_t M)
 {
     size_t sort64 = 0, sort32 = 0, rle = 0, scan = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, sort64, (uint64_t*)nullptr, (uint64_t*)nullptr,
+    // size queries only (no launch); a failed query leaves 0 and the call
+    // that uses the scratch then reports the error
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort64, (uint64_t*)nullptr, (uint64_t*)nullptr,
                                        (int32_t*)nullptr, (int32_t*)nullptr, (int)M, 0, 64);
-    hipcub::DeviceRadixSort::SortPairs(nullptr, sort32, (uint32_t*)nullptr, (uint32_t*)nullptr,
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort32, (uint32_t*)nullptr, (uint32_t*)nullptr,
                                        (int32_t*)nullptr, (int32_t*)nullptr, (int)M, 0, 5);
-    hipcub::DeviceRunLengthEncode::Encode(nullptr, rle, (uint64_t*)nullptr, (uint64_t*)nullptr,
+    (void)hipcub::DeviceRunLengthEncode::Encode(nullptr, rle, (uint64_t*)nullptr, (uint64_t*)nullptr,
                                           (int32_t*)nullptr, (int32_t*)nullptr, (int)M);
-    hipcub::DeviceScan::ExclusiveSum(nullptr, scan, (int32_t*)nullptr, (int32_t*)nullptr, (int)M);
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan, (int32_t*)nullptr, (int32_t*)nullptr, (int)M);
     size_t temp = sort64;
     temp = temp > sort32 ? temp : sort32;
     temp = temp > rle ? temp : rle;

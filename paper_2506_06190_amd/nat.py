@@ -148,6 +148,15 @@ _SIGS = {
     "nat_server_destroy": ([_P], None),
     "nat_status_str": ([C.c_int], C.c_char_p),
     "nat_last_error": ([C.c_char_p, C.c_size_t], C.c_size_t),
+    "nat_nf_create": ([_P, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_uint64, C.POINTER(_P)], C.c_int),
+    "nat_nf_destroy": ([_P], None),
+    "nat_nf_info": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int),
+    "nat_nf_set_params": ([_P, _P, C.c_int64], C.c_int),
+    "nat_nf_get_params": ([_P, _P, C.c_int64], C.c_int),
+    "nat_nf_get_grads": ([_P, _P, C.c_int64], C.c_int),
+    "nat_nf_loss_grad": ([_P, _P, _P, C.c_int32, C.POINTER(C.c_double), _P], C.c_int),
+    "nat_nf_train_step": ([_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double), _P], C.c_int),
+    "nat_nf_infer": ([_P, _P, C.c_int32, _P, _P], C.c_int),
 }
 
 _lib = None
@@ -714,3 +723,79 @@ def nat_server_stats_read(srv: Server) -> dict:
 
 def nat_server_destroy(srv: Server):
     srv.close()
+
+
+# ------------------------------------------------------------ neural field
+class NeuralField:
+    """The neural acoustic transfer field of include/nat_neural.h: inputs are
+    float32 device rows (theta, phi, r, v_0 .. v_{n_v-1}, f), targets float32
+    device rows [B, n_out]."""
+
+    def __init__(self, ctx: Context, n_v: int, n_out: int, r_lo: float, r_hi: float, seed: int = 0):
+        self.ctx = ctx
+        self.n_v, self.n_out = int(n_v), int(n_out)
+        h = _P()
+        _check(lib().nat_nf_create(ctx.handle, self.n_v, self.n_out, float(r_lo), float(r_hi),
+                                   C.c_uint64(seed), C.byref(h)))
+        self.handle = h
+        d = C.c_int32()
+        n = C.c_int64()
+        _check(lib().nat_nf_info(h, C.byref(d), C.byref(n)))
+        self.input_dim, self.n_params = d.value, n.value
+
+    def _host(self, fn, what):
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(fn(self.handle, out.ctypes.data_as(_P), self.n_params))
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(lib().nat_nf_set_params(self.handle, p.ctypes.data_as(_P), int(p.size)))
+
+    def get_params(self):
+        return self._host(lib().nat_nf_get_params, "params")
+
+    def get_grads(self):
+        return self._host(lib().nat_nf_get_grads, "grads")
+
+    def _rows(self, inputs, targets=None):
+        import torch
+        B = int(inputs.shape[0]) if inputs.dim() == 2 else -1
+        pi = _dptr(inputs, torch.float32, (B, 3 + self.n_v + 1), "inputs")
+        pt = None
+        if targets is not None:
+            pt = _dptr(targets, torch.float32, (B, self.n_out), "targets")
+        return B, pi, pt
+
+    def loss_grad(self, inputs, targets, stream=None) -> float:
+        B, pi, pt = self._rows(inputs, targets)
+        loss = C.c_double()
+        _check(lib().nat_nf_loss_grad(self.handle, pi, pt, B, C.byref(loss), _stream(stream)))
+        return loss.value
+
+    def train_step(self, inputs, targets, step: int, total_steps: int, want_loss: bool = True, stream=None):
+        B, pi, pt = self._rows(inputs, targets)
+        loss = C.c_double()
+        _check(lib().nat_nf_train_step(self.handle, pi, pt, B, int(step), int(total_steps),
+                                       C.byref(loss) if want_loss else None, _stream(stream)))
+        return loss.value if want_loss else None
+
+    def infer(self, inputs, out=None, stream=None):
+        import torch
+        B, pi, _ = self._rows(inputs)
+        if out is None:
+            out = torch.empty((B, self.n_out), dtype=torch.float32, device=inputs.device)
+        _check(lib().nat_nf_infer(self.handle, pi, B, _dptr(out, torch.float32, (B, self.n_out), "out"),
+                                  _stream(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().nat_nf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -25,11 +25,27 @@ def declared_functions():
 def test_library_exports_every_declared_symbol():
     L = nat.lib()
     names = declared_functions()
-    assert len(HEADERS) == 2 and len(names) >= 25
+    assert len(HEADERS) == 3 and len(names) >= 34
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
     # the binding wraps each of them under the same name
     assert set(names) <= set(nat._SIGS)
+
+
+def test_neural_field_calls_validate_before_device_work():
+    """The neural-field calls refuse missing handles and bad sizes on the
+    host (no device is touched)."""
+    import ctypes as C
+    L = nat.lib()
+    h = C.c_void_p()
+    assert L.nat_nf_create(None, 0, 1, 1.5, 3.0, 0, C.byref(h)) == nat.NAT_E_INVALID
+    assert "context is NULL" in nat.last_error()
+    assert L.nat_nf_create(None, 0, 1, 1.5, 3.0, 0, None) == nat.NAT_E_INVALID
+    assert L.nat_nf_info(None, None, None) == nat.NAT_E_INVALID
+    assert L.nat_nf_infer(None, None, 4, None, None) == nat.NAT_E_INVALID
+    assert L.nat_nf_train_step(None, None, None, 4, 0, 1, None, None) == nat.NAT_E_INVALID
+    assert L.nat_nf_get_params(None, None, 0) == nat.NAT_E_INVALID
+    L.nat_nf_destroy(None)
 
 
 def test_status_strings_and_defaults():

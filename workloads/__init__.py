@@ -483,3 +483,26 @@ def config_served(seed: int = BASE_SEED + 4, n_meshes: int = 64, n_requests: int
         reqs.append(ServedRequest("dense" if dense else "mc", mi, m0, k, q, max(n, 2),
                                   seed * 100000 + r, float(rng.exponential(1.0))))
     return meshes, reqs
+
+
+# ------------------------------------------------- neural-field training rows
+def nf_rows(B: int, n_v: int, seed: int, r_lo: float = 1.5, r_hi: float = 3.0):
+    """Seeded listener rows of the neural field's training shell (Section
+    3.4): directions uniform on the sphere (theta = arccos(1 - 2 u)), radius
+    uniform in [r_lo, r_hi], condition variables and normalised frequency
+    uniform in [0, 1].  Returns float64 arrays theta, phi, r, v [B, n_v], f."""
+    rng = np.random.default_rng([seed, 31])
+    th = np.arccos(1.0 - 2.0 * rng.uniform(0.0, 1.0, B))
+    ph = rng.uniform(0.0, 2.0 * np.pi, B)
+    r = rng.uniform(r_lo, r_hi, B)
+    v = rng.uniform(0.0, 1.0, (B, n_v))
+    f = rng.uniform(0.0, 1.0, B)
+    return th, ph, r, v, f
+
+
+def nf_smooth_target(th, ph, r, v, f, n_out: int = 1):
+    """A smooth positive stand-in for |p| over the shell (synthetic training
+    values; output o adds a phase o to the azimuthal term)."""
+    vs = v.sum(axis=1) if v.shape[1] else np.zeros_like(th)
+    cols = [(1.0 + 0.5 * np.cos(th) * np.sin(ph + 2.0 * vs + o) + 0.3 * f) / r for o in range(n_out)]
+    return np.stack(cols, 1)
