@@ -34,12 +34,11 @@ constexpr int kPeFreqs = 6;
 constexpr int kHidden = 128;
 constexpr int kLayers = 5;  // 4 hidden + output
 constexpr int kRowTile = 128;   // rows per product tile (4 waves x 32)
+constexpr int kGemmGrid = 512;  // workgroups of a product launch (persistent)
 constexpr int kMaxNv = 16;
 constexpr int kMaxOut = 32;
 constexpr uint32_t kPrime1 = 2654435761u;
 constexpr uint32_t kPrime2 = 805459861u;
-// LDS lattices of the gradient scatter: levels 0 and 1 (9^3 and 17^3 vertices)
-constexpr int kLdsLevels = 2;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -48,7 +47,15 @@ __host__ __device__ constexpr int level_res(int l) { return kBaseRes << l; }
 __host__ __device__ constexpr int level_n1cube(int l) { return (level_res(l) + 1) * (level_res(l) + 1) * (level_res(l) + 1); }
 __host__ __device__ constexpr bool level_hashed(int l) { return level_n1cube(l) > kTable; }
 __host__ __device__ constexpr int level_size(int l) { return level_hashed(l) ? kTable : level_n1cube(l); }
-constexpr int kLdsFloats = (level_size(0) + level_size(1)) * kFeat;
+__host__ __device__ constexpr int level_base(int l) { return l == 0 ? 0 : level_base(l - 1) + level_size(l - 1) * kFeat; }
+// The grid-feature gradient is accumulated in 64-bit fixed point in LDS
+// partitions of the four lattices' tables laid end to end (kGridFloats
+// values, every partition a whole number of vertices).
+constexpr int kGridFloats = level_base(kLevels);
+constexpr int kGridPart = 4608 * kFeat;  // 144 KB of 64-bit accumulators
+constexpr int kGridParts = (kGridFloats + kGridPart - 1) / kGridPart;
+constexpr int kGridGroupsMax = 21;       // row groups per partition
+static_assert(kGridPart % kFeat == 0, "partitions hold whole vertices");
 
 __device__ __forceinline__ uint16_t to_bf16(float x)
 {
@@ -186,8 +193,9 @@ __global__ void __launch_bounds__(256) k_nf_encode(NfDev f, const float* __restr
 
 // C = A B^T with A [M][K] (lda), B [N][K] (ldb), bfloat16, both contiguous
 // along K; M a multiple of 128, K of 16, N <= 32 NBLK.  Epilogue: + bias,
-// relu, * [mask > 0], then bfloat16 stores row-major (C) and transposed
-// (CT), and FP32 stores of the first nf columns (Cf).
+// relu, * [mask > 0] (mask given transposed, [N][ldm]), then bfloat16 stores
+// row-major (C) and transposed (CT), and FP32 stores of the first nf
+// columns (Cf).
 struct NfGemm {
     const uint16_t* A;
     int32_t lda;
@@ -204,15 +212,21 @@ struct NfGemm {
     int32_t ldct;
     float* Cf;
     int32_t ldcf, nf;
+    float* gmax;     // grid epilogue: max |Cf| of each workgroup [gridDim.x]
 };
 
+// Epilogue of a product: forward (+ bias, relu), input gradient (* [mask >
+// 0]) or the grid-feature columns (FP32).
+enum { kEpiFwd = 0, kEpiBwd = 1, kEpiGrid = 2 };
+
 // Each workgroup stages B in LDS once (rows padded by 16 bytes) and walks
-// row tiles of 128; wave w computes rows 32 w .. 32 w + 31 of the tile
-// against all N columns.  MFMA 32x32x16 operand layout: lane l holds row
-// (or column) l mod 32 and K entries 8 (l / 32) .. 8 (l / 32) + 7 of the
-// step; accumulator entry i of lane l is row 8 (i / 4) + 4 (l / 32) + i mod 4,
-// column l mod 32.
-template <int NBLK>
+// row tiles of 128 (persistent); wave w computes rows 32 w .. 32 w + 31 of
+// the tile against all N columns, with the loads of up to 8 K steps of its
+// A rows issued before their products.  MFMA 32x32x16 operand layout: lane
+// l holds row (or column) l mod 32 and K entries 8 (l / 32) .. 8 (l / 32) + 7
+// of the step; accumulator entry i of lane l is row 8 (i / 4) + 4 (l / 32) +
+// i mod 4, column l mod 32.
+template <int NBLK, int EPI>
 __global__ void __launch_bounds__(256) k_nf_gemm(NfGemm g)
 {
     extern __shared__ uint4 s_raw[];
@@ -230,6 +244,7 @@ __global__ void __launch_bounds__(256) k_nf_gemm(NfGemm g)
     __syncthreads();
     const int half = lane >> 5, l32 = lane & 31;
     const int n_tiles = g.M / kRowTile;
+    float wmax = 0.0f;
     for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int row0 = tile * kRowTile + wave * 32;
         f32x16 acc[NBLK];
@@ -238,12 +253,23 @@ __global__ void __launch_bounds__(256) k_nf_gemm(NfGemm g)
             acc[nb] = f32x16{};
         const uint16_t* ap = g.A + (size_t)(row0 + l32) * g.lda + half * 8;
         const uint16_t* bp = sB + l32 * ldsb + half * 8;
-        for (int kk = 0; kk < K; kk += 16) {
-            const bf16x8 a = load8(ap + kk);
+        float vmax = 0.0f;
+        for (int kc = 0; kc < K; kc += 128) {
+            const int ns = min(8, (K - kc) >> 4);
+            bf16x8 a[8];
 #pragma unroll
-            for (int nb = 0; nb < NBLK; ++nb) {
-                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(bp + nb * 32 * ldsb + kk);
-                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[nb], 0, 0, 0);
+            for (int j = 0; j < 8; ++j)
+                if (j < ns)
+                    a[j] = load8(ap + kc + 16 * j);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (j < ns) {
+#pragma unroll
+                    for (int nb = 0; nb < NBLK; ++nb) {
+                        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(bp + nb * 32 * ldsb + kc + 16 * j);
+                        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[j], bv, acc[nb], 0, 0, 0);
+                    }
+                }
             }
         }
 #pragma unroll
@@ -251,32 +277,57 @@ __global__ void __launch_bounds__(256) k_nf_gemm(NfGemm g)
             const int col = nb * 32 + l32;
             if (col >= g.N)
                 continue;
-            const float bias = g.bias ? g.bias[col] : 0.0f;
+            const float bias = EPI == kEpiFwd ? g.bias[col] : 0.0f;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int rbase = row0 + 8 * q + 4 * half;
                 uint16_t h[4];
+                uint2 m4 = make_uint2(0, 0);
+                if (EPI == kEpiBwd)  // mask rows rbase .. rbase + 3 of column col (transposed copy)
+                    m4 = *reinterpret_cast<const uint2*>(g.mask + (size_t)col * g.ldm + rbase);
+                const uint16_t mk[4] = {static_cast<uint16_t>(m4.x), static_cast<uint16_t>(m4.x >> 16),
+                                        static_cast<uint16_t>(m4.y), static_cast<uint16_t>(m4.y >> 16)};
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = rbase + r;
-                    float v = acc[nb][4 * q + r] + bias;
-                    if (g.relu)
-                        v = fmaxf(v, 0.0f);
-                    if (g.mask && !bf16_positive(g.mask[(size_t)row * g.ldm + col]))
+                    float v = acc[nb][4 * q + r];
+                    if (EPI == kEpiFwd)
+                        v = fmaxf(v + bias, 0.0f);
+                    if (EPI == kEpiBwd && !bf16_positive(mk[r]))
                         v = 0.0f;
-                    h[r] = to_bf16(v);
-                    if (g.C)
+                    if (EPI == kEpiGrid) {
+                        if (col < g.nf)
+                            g.Cf[(size_t)row * g.ldcf + col] = v;
+                    } else {
+                        h[r] = to_bf16(v);
                         g.C[(size_t)row * g.ldc + col] = h[r];
-                    if (g.Cf && col < g.nf)
-                        g.Cf[(size_t)row * g.ldcf + col] = v;
+                    }
                 }
-                if (g.CT) {
+                if (EPI == kEpiGrid) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (col < g.nf)
+                            vmax = fmaxf(vmax, fabsf(acc[nb][4 * q + r]));
+                }
+                if (EPI != kEpiGrid && g.CT) {
                     const uint2 pk = make_uint2(h[0] | (static_cast<uint32_t>(h[1]) << 16),
                                                 h[2] | (static_cast<uint32_t>(h[3]) << 16));
                     *reinterpret_cast<uint2*>(g.CT + (size_t)col * g.ldct + rbase) = pk;
                 }
             }
         }
+        if (EPI == kEpiGrid)
+            wmax = fmaxf(wmax, vmax);
+    }
+    if (EPI == kEpiGrid) {
+        __shared__ float s_max[4];
+        for (int o = 32; o > 0; o >>= 1)
+            wmax = fmaxf(wmax, __shfl_xor(wmax, o, 64));
+        if (lane == 0)
+            s_max[wave] = wmax;
+        __syncthreads();
+        if (tid == 0)
+            g.gmax[blockIdx.x] = fmaxf(fmaxf(s_max[0], s_max[1]), fmaxf(s_max[2], s_max[3]));
     }
 }
 
@@ -469,7 +520,8 @@ __global__ void __launch_bounds__(256) k_nf_sum(const double* __restrict__ parts
         *out = s[0];
 }
 
-// Chunk partials folded in chunk order into the gradient array.
+// Chunk partials folded in chunk order into the gradient array (one
+// segment per blockIdx.y; the loads of 8 chunks are issued together).
 struct NfSeg {
     const float* part;
     float* out;
@@ -477,7 +529,6 @@ struct NfSeg {
 };
 struct NfReduce {
     NfSeg seg[2 * kLayers];
-    int32_t n_seg;
 };
 
 __global__ void __launch_bounds__(256) k_nf_reduce(NfReduce r)
@@ -485,64 +536,108 @@ __global__ void __launch_bounds__(256) k_nf_reduce(NfReduce r)
     const NfSeg& s = r.seg[blockIdx.y];
     for (int32_t e = blockIdx.x * 256 + threadIdx.x; e < s.n; e += gridDim.x * 256) {
         double a = 0.0;
-        for (int c = 0; c < s.nch; ++c)
-            a += s.part[(size_t)c * s.n + e];
+        for (int c0 = 0; c0 < s.nch; c0 += 8) {
+            float v[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                v[c] = c0 + c < s.nch ? s.part[(size_t)(c0 + c) * s.n + e] : 0.0f;
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                a += v[c];
+        }
         s.out[e] = static_cast<float>(a);
     }
 }
 
-// Grid-feature gradient: each row's dH_0 over its 8 corners per lattice,
-// with the trilinear weights.  The two coarse lattices accumulate in LDS
-// first (their vertices are shared by many rows), the others go straight
-// to memory.
-__global__ void __launch_bounds__(256) k_nf_grid_back(NfDev f, const float* __restrict__ in, int32_t B,
-                                                      const float* __restrict__ dh0, float* const* ggrid)
+// Grid-feature gradient: each row's dH_0 goes to the 8 corners of its cell
+// on every lattice with the trilinear weights.  The terms are added as
+// 64-bit integers in units of 1/S, S a power of two with B * 8 * max|dH_0|
+// * S below 2^62: each term w g S is formed exactly in FP64 and rounded once,
+// and integer sums do not depend on their order, so the gradient is the
+// same on every run.  Workgroup (p, g) adds the terms of row group g that
+// fall in partition p in LDS and writes the partition out as group g's
+// partial; the fold adds the partials and scales back.  (Floating-point
+// atomic additions, in LDS or in memory, measured 3-8 times slower here.)
+__device__ __forceinline__ double grid_scale(float gmax, int32_t B)
 {
-    __shared__ float s_acc[kLdsFloats];
-    for (int e = threadIdx.x; e < kLdsFloats; e += 256)
-        s_acc[e] = 0.0f;
+    // the largest power of two S with B * 8 * gmax * S <= 2^62
+    const double bound = static_cast<double>(B) * 8.0 * static_cast<double>(gmax);
+    if (!(bound > 0.0) || !isfinite(bound))
+        return 1.0;
+    return exp2(floor(62.0 - log2(bound)));
+}
+
+// The largest of the n per-workgroup maxima (every thread of the block).
+__device__ float block_max(const float* __restrict__ m, int32_t n)
+{
+    __shared__ float s[256];
+    float a = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 256)
+        a = fmaxf(a, m[i]);
+    s[threadIdx.x] = a;
     __syncthreads();
-    float* gg[kLevels];
-    for (int l = 0; l < kLevels; ++l)
-        gg[l] = ggrid[l];
-    for (int32_t b = blockIdx.x * 256 + threadIdx.x; b < B; b += gridDim.x * 256) {
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            s[threadIdx.x] = fmaxf(s[threadIdx.x], s[threadIdx.x + h]);
+        __syncthreads();
+    }
+    const float r = s[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(256) k_nf_grid_part(NfDev f, const float* __restrict__ in, int32_t B,
+                                                      const float* __restrict__ dh0, const float* gmax,
+                                                      int32_t n_gmax, long long* __restrict__ part, int32_t G)
+{
+    __shared__ unsigned long long s_acc[kGridPart];
+    const int p = blockIdx.x % kGridParts, g = blockIdx.x / kGridParts;
+    const int lo = p * kGridPart;
+    const int n = min(kGridPart, kGridFloats - lo);
+    const double S = grid_scale(block_max(gmax, n_gmax), B);
+    for (int e = threadIdx.x; e < n; e += 256)
+        s_acc[e] = 0ull;
+    __syncthreads();
+    for (int32_t b = g * 256 + threadIdx.x; b < B; b += G * 256) {
         const float* row = in + (size_t)b * f.ld_in;
         float u[3];
         unit_coords(f, row, u);
         const float4* dg = reinterpret_cast<const float4*>(dh0 + (size_t)b * (kLevels * kFeat));
 #pragma unroll
         for (int l = 0; l < kLevels; ++l) {
+            if (level_base(l + 1) <= lo || level_base(l) >= lo + n)
+                continue;  // the lattice lies outside this partition
             Corners c;
             cell_corners(u, l, c);
-            const float4 g = dg[l];
+            const float4 gv = dg[l];
+            const double gs[4] = {gv.x * S, gv.y * S, gv.z * S, gv.w * S};
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const float w = c.w[e];
-                if (l < kLdsLevels) {
-                    float* t = s_acc + (l == 0 ? 0 : level_size(0) * kFeat) + (size_t)c.idx[e] * kFeat;
-                    atomicAdd(t + 0, w * g.x);
-                    atomicAdd(t + 1, w * g.y);
-                    atomicAdd(t + 2, w * g.z);
-                    atomicAdd(t + 3, w * g.w);
-                } else {
-                    float* t = gg[l] + (size_t)c.idx[e] * kFeat;
-                    unsafeAtomicAdd(t + 0, w * g.x);
-                    unsafeAtomicAdd(t + 1, w * g.y);
-                    unsafeAtomicAdd(t + 2, w * g.z);
-                    unsafeAtomicAdd(t + 3, w * g.w);
+                const int at = level_base(l) + static_cast<int>(c.idx[e]) * kFeat - lo;
+                if (at >= 0 && at < n) {
+                    const double w = c.w[e];
+#pragma unroll
+                    for (int q = 0; q < kFeat; ++q)
+                        atomicAdd(s_acc + at + q, static_cast<unsigned long long>(__double2ll_rn(w * gs[q])));
                 }
             }
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kLdsFloats; e += 256) {
-        const float v = s_acc[e];
-        if (v != 0.0f) {
-            if (e < level_size(0) * kFeat)
-                unsafeAtomicAdd(gg[0] + e, v);
-            else
-                unsafeAtomicAdd(gg[1] + (e - level_size(0) * kFeat), v);
-        }
+    long long* dst = part + (size_t)g * kGridFloats + lo;
+    for (int e = threadIdx.x; e < n; e += 256)
+        dst[e] = static_cast<long long>(s_acc[e]);
+}
+
+__global__ void __launch_bounds__(256) k_nf_grid_fold(const long long* __restrict__ part, int32_t G, int32_t B,
+                                                      const float* gmax, int32_t n_gmax, float* __restrict__ out)
+{
+    const double inv = 1.0 / grid_scale(block_max(gmax, n_gmax), B);
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < kGridFloats; e += gridDim.x * 256) {
+        long long a = 0;
+        for (int g = 0; g < G; ++g)
+            a += part[(size_t)g * kGridFloats + e];
+        out[e] = static_cast<float>(static_cast<double>(a) * inv);
     }
 }
 
@@ -611,7 +706,6 @@ struct nat_nf {
     float* d_v = nullptr;
     uint16_t* d_wb = nullptr;   // bfloat16 weights, row-major, then transposed
     uint16_t* d_wbt = nullptr;
-    float** d_ggrid = nullptr;  // device array of the 4 grid-gradient pointers
     size_t fixed_bytes = 0;
     void* d_fixed = nullptr;
     // batch workspace, grown on demand
@@ -632,10 +726,19 @@ struct NfWs {
     float* dh0;               // [Bp][16]
     double* loss_part;
     double* loss;
-    float* P;                 // weight-gradient chunk partials
-    float* Q;                 // bias-gradient chunk partials
-    int32_t chunk, nch;
+    float* P;                 // weight-gradient chunk partials, every layer
+    float* Q;                 // bias-gradient chunk partials, every layer
+    long long* gpart;         // grid-gradient partials [grid_groups][kGridFloats]
+    float* gmax;              // max |dH_0| of each workgroup of its product
+    int32_t n_gmax;
+    int64_t offP[kLayers], offQ[kLayers];
+    int32_t chunk, nch, grid_groups;
 };
+
+int32_t nf_grid_groups(int32_t Bp)
+{
+    return static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(kGridGroupsMax, (Bp + 4095) / 4096)));
+}
 
 void nf_chunks(int32_t Bp, int32_t* chunk, int32_t* nch)
 {
@@ -650,9 +753,12 @@ size_t nf_ws_layout(const nat_nf* nf, int32_t Bp, NfWs* w, void* base)
     int32_t chunk, nch;
     nf_chunks(Bp, &chunk, &nch);
     const size_t bp = static_cast<size_t>(Bp);
-    size_t max_pq = 0;
-    for (int i = 0; i < kLayers; ++i)
-        max_pq = std::max(max_pq, static_cast<size_t>(nf->out_dim[i]) * nf->in_dim[i]);
+    size_t sum_pq = 0, sum_q = 0;
+    for (int i = 0; i < kLayers; ++i) {
+        sum_pq += static_cast<size_t>(nf->out_dim[i]) * nf->in_dim[i];
+        sum_q += static_cast<size_t>(nf->out_dim[i]);
+    }
+    const int32_t G = nf_grid_groups(Bp);
     std::vector<size_t> sz;
     sz.push_back(2 * bp * nf->D);
     sz.push_back(2 * bp * nf->D);
@@ -662,8 +768,10 @@ size_t nf_ws_layout(const nat_nf* nf, int32_t Bp, NfWs* w, void* base)
     sz.push_back(4 * bp * kLevels * kFeat);
     sz.push_back(8 * (bp / 256 + 1));
     sz.push_back(8);
-    sz.push_back(4 * max_pq * nch);
-    sz.push_back(4 * static_cast<size_t>(kHidden) * nch);
+    sz.push_back(4 * sum_pq * nch);
+    sz.push_back(4 * sum_q * nch);
+    sz.push_back(8 * static_cast<size_t>(kGridFloats) * G);
+    sz.push_back(4 * static_cast<size_t>(kGemmGrid));
     size_t total = 0;
     for (size_t s : sz)
         total = ((total + 255) & ~size_t(255)) + s;
@@ -684,10 +792,21 @@ size_t nf_ws_layout(const nat_nf* nf, int32_t Bp, NfWs* w, void* base)
         w->dh0 = cv.take<float>(bp * kLevels * kFeat);
         w->loss_part = cv.take<double>(bp / 256 + 1);
         w->loss = cv.take<double>(1);
-        w->P = cv.take<float>(max_pq * nch);
-        w->Q = cv.take<float>(static_cast<size_t>(kHidden) * nch);
+        w->P = cv.take<float>(sum_pq * nch);
+        w->Q = cv.take<float>(sum_q * nch);
+        w->gpart = cv.take<long long>(static_cast<size_t>(kGridFloats) * G);
+        w->gmax = cv.take<float>(kGemmGrid);
+        w->n_gmax = std::min(Bp / kRowTile, kGemmGrid);
+        int64_t op = 0, oq = 0;
+        for (int i = 0; i < kLayers; ++i) {
+            w->offP[i] = op;
+            w->offQ[i] = oq;
+            op += (int64_t)nf->out_dim[i] * nf->in_dim[i] * nch;
+            oq += (int64_t)nf->out_dim[i] * nch;
+        }
         w->chunk = chunk;
         w->nch = nch;
+        w->grid_groups = G;
     }
     return total;
 }
@@ -727,19 +846,30 @@ NfDev nf_dev(const nat_nf* nf)
     return f;
 }
 
-hipError_t launch_gemm(const NfGemm& g, hipStream_t s)
+template <int EPI>
+hipError_t launch_gemm_epi(const NfGemm& g, hipStream_t s)
 {
     const int nblk = (g.N + 31) / 32;
     const size_t lds = static_cast<size_t>(nblk) * 32 * (g.K + 8) * sizeof(uint16_t);
-    const int grid = std::min(g.M / kRowTile, 2048);
+    // persistent: B is staged once per workgroup
+    const int grid = std::min(g.M / kRowTile, kGemmGrid);
     switch (nblk) {
-    case 1: hipLaunchKernelGGL(k_nf_gemm<1>, dim3(grid), dim3(256), lds, s, g); break;
-    case 2: hipLaunchKernelGGL(k_nf_gemm<2>, dim3(grid), dim3(256), lds, s, g); break;
-    case 3: hipLaunchKernelGGL(k_nf_gemm<3>, dim3(grid), dim3(256), lds, s, g); break;
-    case 4: hipLaunchKernelGGL(k_nf_gemm<4>, dim3(grid), dim3(256), lds, s, g); break;
+    case 1: hipLaunchKernelGGL((k_nf_gemm<1, EPI>), dim3(grid), dim3(256), lds, s, g); break;
+    case 2: hipLaunchKernelGGL((k_nf_gemm<2, EPI>), dim3(grid), dim3(256), lds, s, g); break;
+    case 3: hipLaunchKernelGGL((k_nf_gemm<3, EPI>), dim3(grid), dim3(256), lds, s, g); break;
+    case 4: hipLaunchKernelGGL((k_nf_gemm<4, EPI>), dim3(grid), dim3(256), lds, s, g); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_gemm(const NfGemm& g, hipStream_t s)
+{
+    if (g.Cf)
+        return launch_gemm_epi<kEpiGrid>(g, s);
+    if (g.mask)
+        return launch_gemm_epi<kEpiBwd>(g, s);
+    return launch_gemm_epi<kEpiFwd>(g, s);
 }
 
 hipError_t launch_wgrad(const NfWgrad& w, int nch, hipStream_t s)
@@ -824,8 +954,8 @@ hipError_t nf_backward(nat_nf* nf, const NfWs& w, const float* in, int32_t B, in
         g.K = kHidden;
         if (i > 0) {
             g.N = kHidden;
-            g.mask = w.H[i - 1];
-            g.ldm = kHidden;
+            g.mask = w.HT[i - 1];  // A_i transposed: [128][Bp]
+            g.ldm = Bp;
             g.C = w.dz[i - 1];
             g.ldc = kHidden;
             g.CT = w.dzT[i - 1];
@@ -835,10 +965,14 @@ hipError_t nf_backward(nat_nf* nf, const NfWs& w, const float* in, int32_t B, in
             g.Cf = w.dh0;
             g.ldcf = kLevels * kFeat;
             g.nf = kLevels * kFeat;
+            g.gmax = w.gmax;
         }
         e = launch_gemm(g, s);
     }
-    // weight and bias gradients, chunk partials then the ordered fold
+    // weight and bias gradients: chunk partials of every layer, then one
+    // launch folds them in chunk order
+    NfReduce red{};
+    int32_t max_n = 0;
     for (int i = 0; i < kLayers && e == hipSuccess; ++i) {
         NfWgrad g{};
         g.A = i == 4 ? w.dzoT : w.dzT[i];
@@ -848,29 +982,27 @@ hipError_t nf_backward(nat_nf* nf, const NfWs& w, const float* in, int32_t B, in
         g.Ni = nf->in_dim[i];
         g.chunk = w.chunk;
         g.n_rows = Bp;
-        g.P = w.P;
-        g.Q = w.Q;
-        // one layer at a time through the shared partial buffers
+        g.P = w.P + w.offP[i];
+        g.Q = w.Q + w.offQ[i];
         e = launch_wgrad(g, w.nch, s);
-        if (e != hipSuccess)
-            break;
-        NfReduce r1{};
-        r1.n_seg = 2;
-        r1.seg[0] = NfSeg{w.P, nf->d_grads + nf->offW[i], nf->out_dim[i] * nf->in_dim[i], w.nch};
-        r1.seg[1] = NfSeg{w.Q, nf->d_grads + nf->offb[i], nf->out_dim[i], w.nch};
-        hipLaunchKernelGGL(k_nf_reduce, dim3(grid_for(r1.seg[0].n, 256, 64), 2), dim3(256), 0, s, r1);
-        e = hipGetLastError();
+        red.seg[2 * i] = NfSeg{g.P, nf->d_grads + nf->offW[i], nf->out_dim[i] * nf->in_dim[i], w.nch};
+        red.seg[2 * i + 1] = NfSeg{g.Q, nf->d_grads + nf->offb[i], nf->out_dim[i], w.nch};
+        max_n = std::max(max_n, nf->out_dim[i] * nf->in_dim[i]);
     }
     if (e != hipSuccess)
         return e;
-    // grid-feature gradient
-    const int64_t g0 = nf->offG[0];
-    e = hipMemsetAsync(nf->d_grads + g0, 0, sizeof(float) * (nf->n_params - g0), s);
-    if (e != hipSuccess)
+    hipLaunchKernelGGL(k_nf_reduce, dim3(grid_for(max_n, 256, 64), 2 * kLayers), dim3(256), 0, s, red);
+    if ((e = hipGetLastError()) != hipSuccess)
         return e;
+    // grid-feature gradient: LDS partitions, then the ordered fold
     const NfDev f = nf_dev(nf);
-    hipLaunchKernelGGL(k_nf_grid_back, dim3(grid_for(B, 256, 512)), dim3(256), 0, s, f, in, B, w.dh0,
-                       nf->d_ggrid);
+    const int32_t G = w.grid_groups;
+    hipLaunchKernelGGL(k_nf_grid_part, dim3(kGridParts * G), dim3(256), 0, s, f, in, B, w.dh0, w.gmax, w.n_gmax,
+                       w.gpart, G);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_nf_grid_fold, dim3(grid_for(kGridFloats, 256, 512)), dim3(256), 0, s, w.gpart, G, B,
+                       w.gmax, w.n_gmax, nf->d_grads + nf->offG[0]);
     return hipGetLastError();
 }
 
@@ -993,8 +1125,7 @@ nat_status nat_nf_create(nat_ctx* ctx, int32_t n_v, int32_t n_out, double r_lo, 
     }
     nf->n_params = off;
     const size_t np = static_cast<size_t>(off);
-    const size_t bytes = carve_size<>({4 * np, 4 * np, 4 * np, 4 * np, 2 * (size_t)offb, 2 * (size_t)offb,
-                                       sizeof(float*) * kLevels});
+    const size_t bytes = carve_size<>({4 * np, 4 * np, 4 * np, 4 * np, 2 * (size_t)offb, 2 * (size_t)offb});
     st = dev_alloc(ctx, bytes, &nf->d_fixed);
     if (st != NAT_OK) {
         delete nf;
@@ -1008,7 +1139,6 @@ nat_status nat_nf_create(nat_ctx* ctx, int32_t n_v, int32_t n_out, double r_lo, 
     nf->d_v = cv.take<float>(np);
     nf->d_wb = cv.take<uint16_t>(offb);
     nf->d_wbt = cv.take<uint16_t>(offb);
-    nf->d_ggrid = cv.take<float*>(kLevels);
     // initial parameters (Glorot-uniform weights, zero biases, small grid)
     std::vector<float> h(np, 0.0f);
     for (int i = 0; i < kLayers; ++i) {
@@ -1020,9 +1150,6 @@ nat_status nat_nf_create(nat_ctx* ctx, int32_t n_v, int32_t n_out, double r_lo, 
     for (int l = 0; l < kLevels; ++l)
         for (int64_t e = 0; e < (int64_t)level_size(l) * kFeat; ++e)
             h[nf->offG[l] + e] = static_cast<float>(1e-4 * uniform_pm1(seed, 8 + l, e));
-    float* gptr[kLevels];
-    for (int l = 0; l < kLevels; ++l)
-        gptr[l] = nf->d_grads + nf->offG[l];
     hipError_t e = hipMemcpy(nf->d_params, h.data(), 4 * np, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemset(nf->d_grads, 0, 4 * np);
@@ -1030,8 +1157,6 @@ nat_status nat_nf_create(nat_ctx* ctx, int32_t n_v, int32_t n_out, double r_lo, 
         e = hipMemset(nf->d_m, 0, 4 * np);
     if (e == hipSuccess)
         e = hipMemset(nf->d_v, 0, 4 * np);
-    if (e == hipSuccess)
-        e = hipMemcpy(nf->d_ggrid, gptr, sizeof(gptr), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = nf_cast(nf, nullptr);
     if (e == hipSuccess)
