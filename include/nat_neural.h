@@ -30,9 +30,11 @@
  * back-propagated gradients are stored in bfloat16 (round to nearest even)
  * and multiplied on the matrix cores with FP32 accumulation; the grid
  * features, biases, the output, the loss and every parameter with its Adam
- * moments are FP32.  The grid-feature gradient is summed with FP32 atomic
- * additions (its rounding depends on their order); every other sum runs in
- * a fixed order that depends only on the batch size.
+ * moments are FP32.  The grid-feature gradient is summed in 64-bit fixed
+ * point (units of 2^-e, e chosen from the batch size and the largest
+ * back-propagated grid feature so that no sum can overflow); every other
+ * sum runs in a fixed order that depends only on the batch size, so a
+ * gradient is the same on every run.
  *
  * Parameters (host arrays of nat_nf_set_params and friends) are one FP32
  * array in this order: for layer i = 0..4 the weights W_i [out_i][in_i]

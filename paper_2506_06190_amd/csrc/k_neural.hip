@@ -16,8 +16,8 @@
 //   weights   dW_i = dZ_i^T A_i, split over the batch in chunks whose
 //             partial products are added in chunk order
 // The output layer (width n_out) and the loss run on the vector units, fused
-// with the step back to dZ_3.  The grid-feature gradient is scattered with
-// FP32 atomic additions (through LDS for the two coarse lattices).
+// with the step back to dZ_3.  The grid-feature gradient is accumulated in
+// 64-bit fixed point in LDS partitions of the lattice tables.
 #include "nat_internal.h"
 #include "nat_neural.h"
 

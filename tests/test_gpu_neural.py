@@ -127,6 +127,23 @@ def test_loss_and_gradients_match_oracle(env, n_v, n_out, B):
     nf.close()
 
 
+def test_gradient_is_reproducible(env):
+    """Every sum of the gradient runs in a fixed order or in integers: two
+    evaluations at the same parameters agree bit for bit."""
+    nat, ctx, torch = env
+    n_v, n_out, B = 1, 2, 5000
+    p = oracle_params(n_v, n_out, 21)
+    _, tgt, rows = make_rows(B, n_v, n_out, 22)
+    nf = field(env, n_v, n_out, p)
+    x, t = dev(torch, rows), dev(torch, tgt)
+    l1 = nf.loss_grad(x, t)
+    g1 = nf.get_grads()
+    l2 = nf.loss_grad(x, t)
+    g2 = nf.get_grads()
+    assert l1 == l2 and np.array_equal(g1, g2)
+    nf.close()
+
+
 def test_train_step_matches_oracle(env):
     """One Adam step from the same parameters: where the gradient is clearly
     nonzero the move is lr g / (|g| + eps) on both sides and must agree to
