@@ -164,6 +164,8 @@ typedef struct {
 /* Create a context on HIP device `device` whose library-owned device
  * allocations may total at most `hbm_budget_bytes` (0 = no limit). */
 nat_status nat_ctx_create(int32_t device, size_t hbm_budget_bytes, nat_ctx** out);
+/* Every mesh, operator, server and neural field made from the context must
+ * be destroyed before it. */
 void nat_ctx_destroy(nat_ctx* ctx);
 /* Bytes of device memory currently charged to the context. */
 size_t nat_ctx_bytes_in_use(const nat_ctx* ctx);

@@ -10,6 +10,7 @@ loudly when the library has not been built.
 from __future__ import annotations
 
 import ctypes as C
+import weakref
 from pathlib import Path
 from typing import Optional, Sequence
 
@@ -248,17 +249,33 @@ def nat_mesh_free_terms(vertices, tris):
 
 # ---------------------------------------------------------------- handles
 class Context:
+    """Handle of nat_ctx_create.  Closing it first closes every mesh,
+    operator, server and neural field made from it that is still open (the
+    C library requires them destroyed before their context)."""
+
     def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
         h = C.c_void_p()
         _check(lib().nat_ctx_create(device, hbm_budget_bytes, C.byref(h)))
         self.handle = h
         self.device = device
+        self._children = []  # weak references, in creation order
+
+    def _adopt(self, obj):
+        self._children.append(weakref.ref(obj))
 
     def bytes_in_use(self) -> int:
         return int(lib().nat_ctx_bytes_in_use(self.handle))
 
     def close(self):
         if self.handle:
+            live = [c for c in (r() for r in self._children) if c is not None]
+            # dependents (servers, operators, fields) before the meshes they use
+            for c in sorted(live, key=lambda c: isinstance(c, Mesh)):
+                try:
+                    c.close()
+                except Exception:
+                    pass
+            self._children.clear()
             lib().nat_ctx_destroy(self.handle)
             self.handle = None
 
@@ -280,6 +297,7 @@ class Mesh:
         self.handle = h
         self.n_vertices = len(v)
         self.n_tris = len(t)
+        ctx._adopt(self)
 
     def info(self):
         a, nv, nt = C.c_double(), C.c_int32(), C.c_int32()
@@ -311,6 +329,7 @@ class BemOp:
         self.mesh = mesh
         self.k = k
         self.n = mesh.n_tris
+        mesh.ctx._adopt(self)
 
     def close(self):
         if self.handle:
@@ -669,6 +688,7 @@ class Server:
         _check(lib().nat_server_create(ctx.handle, C.byref(opts), C.byref(h)))
         self.ctx, self.handle, self.opts = ctx, h, opts
         self._live = {}
+        ctx._adopt(self)
 
     def close(self):
         if self.handle:
@@ -738,6 +758,7 @@ class NeuralField:
         _check(lib().nat_nf_create(ctx.handle, self.n_v, self.n_out, float(r_lo), float(r_hi),
                                    C.c_uint64(seed), C.byref(h)))
         self.handle = h
+        ctx._adopt(self)
         d = C.c_int32()
         n = C.c_int64()
         _check(lib().nat_nf_info(h, C.byref(d), C.byref(n)))

@@ -341,6 +341,22 @@ def test_deterministic_and_rigid_motion(ctx):
         assert _rel(c[m], a[m]) <= 1e-4
 
 
+def test_context_closes_what_it_made():
+    """Closing a context first closes the meshes, servers and fields made
+    from it, so a later close (or garbage collection) of those is a no-op."""
+    c = nat.Context(0)
+    v, f = W.icosphere(2, 1.0)[:2]
+    m = nat.Mesh(c, v, f)
+    so = nat.nat_server_opts_default()
+    so.hbm_budget = 1 << 28
+    srv = nat.Server(c, so)
+    nf = nat.NeuralField(c, 0, 1, 1.5, 3.0)
+    c.close()
+    assert m.handle is None and srv.handle is None and nf.handle is None and c.handle is None
+    m.close()
+    nf.close()
+
+
 def test_error_paths(ctx):
     v, f, u = W.icosphere(2, 1.0)
     mesh = nat.Mesh(ctx, v, f)
@@ -370,7 +386,7 @@ def test_error_paths(ctx):
     assert ei.value.status == nat.NAT_E_NOCONV
     for field, value in (("jump", 2), ("flags", nat.NAT_MC_ASSEMBLED | nat.NAT_MC_MATRIX_FREE),
                          ("flags", nat.NAT_MC_ASSEMBLED | nat.NAT_MC_FP64_PHASE),
-                         ("flags", 64), ("eps_scale", 0.0)):
+                         ("flags", 128), ("eps_scale", 0.0)):
         o = nat.nat_mc_opts_default()
         setattr(o, field, value)
         with pytest.raises(nat.NatError) as ei:        # invalid options
