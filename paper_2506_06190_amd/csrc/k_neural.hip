@@ -4,17 +4,17 @@
 // 128 (Section 3.4), its mean-squared-error gradient and the Adam update.
 //
 // One batch is a set of rows; the batch is padded to a multiple of 128 rows
-// with zero inputs and zero loss weight.  Layout of the activations in HBM:
-// each layer's input is kept twice in bfloat16, row-major [rows][width]
-// (the operand of the forward and the input-gradient products, contiguous
-// along the contraction) and transposed [width][rows] (the operand of the
-// weight-gradient products, contiguous along the batch).  The products run
-// on the matrix cores (32x32x16 bfloat16 MFMA, FP32 accumulation):
+// with zero inputs and zero loss weight.  Activations and back-propagated
+// gradients live in HBM in bfloat16, row-major [rows][width].  The products
+// run on the matrix cores (32x32x16 bfloat16 MFMA, FP32 accumulation):
 //   forward   Z_i  = A_i W_i^T + b_i, A_{i+1} = relu(Z_i)       (i = 0..3)
-//   input     dH_i = dZ_i W_i, dZ_{i-1} = dH_i * [A_i > 0]     (i = 3..1),
-//             dH_0 = dZ_0 W_0 for the grid features
-//   weights   dW_i = dZ_i^T A_i, split over the batch in chunks whose
-//             partial products are added in chunk order
+//   backward  one fused pass per layer i = 3..0 over 128-row tiles:
+//             dH_i = dZ_i W_i, dZ_{i-1} = dH_i * [A_i > 0] (or the 16 grid
+//             columns of dH_0), and dW_i += dZ_i^T A_i, db_i += sums of dZ_i
+//             from the same tile transposed in LDS; each workgroup's dW_i is
+//             a partial, added in workgroup order
+//   output    dW_4 = dZ_4^T A_4 split over the batch in chunks (A_4 is also
+//             kept transposed), added in chunk order
 // The output layer (width n_out) and the loss run on the vector units, fused
 // with the step back to dZ_3.  The grid-feature gradient is accumulated in
 // 64-bit fixed point in LDS partitions of the lattice tables.
@@ -35,6 +35,7 @@ constexpr int kHidden = 128;
 constexpr int kLayers = 5;  // 4 hidden + output
 constexpr int kRowTile = 128;   // rows per product tile (4 waves x 32)
 constexpr int kGemmGrid = 512;  // workgroups of a product launch (persistent)
+constexpr int kTilePitch = kRowTile + 8;  // LDS pitch (bfloat16) of a 128-wide tile row
 constexpr int kMaxNv = 16;
 constexpr int kMaxOut = 32;
 constexpr uint32_t kPrime1 = 2654435761u;
@@ -141,10 +142,10 @@ struct RowWriter {
     }
 };
 
-// MLP input of each row: [G | P(v) | P(f) | 0], row-major and (when XT is
-// given) transposed.  Padding rows are zero.
+// MLP input of each row: [G | P(v) | P(f) | 0], row-major.  Padding rows
+// are zero.
 __global__ void __launch_bounds__(256) k_nf_encode(NfDev f, const float* __restrict__ in, int32_t B, int32_t Bp,
-                                                   uint16_t* __restrict__ X, uint16_t* __restrict__ XT)
+                                                   uint16_t* __restrict__ X)
 {
     const int32_t b = blockIdx.x * 256 + threadIdx.x;
     if (b >= Bp)
@@ -154,8 +155,6 @@ __global__ void __launch_bounds__(256) k_nf_encode(NfDev f, const float* __restr
     auto emit = [&](float v) {
         const uint16_t h = to_bf16(v);
         wr.put(h);
-        if (XT)
-            XT[(size_t)col * Bp + b] = h;
         ++col;
     };
     if (b < B) {
@@ -191,11 +190,9 @@ __global__ void __launch_bounds__(256) k_nf_encode(NfDev f, const float* __restr
         emit(0.0f);
 }
 
-// C = A B^T with A [M][K] (lda), B [N][K] (ldb), bfloat16, both contiguous
-// along K; M a multiple of 128, K of 16, N <= 32 NBLK.  Epilogue: + bias,
-// relu, * [mask > 0] (mask given transposed, [N][ldm]), then bfloat16 stores
-// row-major (C) and transposed (CT), and FP32 stores of the first nf
-// columns (Cf).
+// Forward product of a hidden layer: C = relu(A B^T + bias) with A [M][K]
+// (lda), B [N][K] (ldb), bfloat16, both contiguous along K; M a multiple of
+// 128, K of 16, N <= 32 NBLK; C stored in bfloat16, row-major.
 struct NfGemm {
     const uint16_t* A;
     int32_t lda;
@@ -203,21 +200,9 @@ struct NfGemm {
     int32_t ldb;
     int32_t M, N, K;
     const float* bias;
-    int32_t relu;
-    const uint16_t* mask;
-    int32_t ldm;
     uint16_t* C;
     int32_t ldc;
-    uint16_t* CT;
-    int32_t ldct;
-    float* Cf;
-    int32_t ldcf, nf;
-    float* gmax;     // grid epilogue: max |Cf| of each workgroup [gridDim.x]
 };
-
-// Epilogue of a product: forward (+ bias, relu), input gradient (* [mask >
-// 0]) or the grid-feature columns (FP32).
-enum { kEpiFwd = 0, kEpiBwd = 1, kEpiGrid = 2 };
 
 // Each workgroup stages B in LDS once (rows padded by 16 bytes) and walks
 // row tiles of 128 (persistent); wave w computes rows 32 w .. 32 w + 31 of
@@ -226,7 +211,7 @@ enum { kEpiFwd = 0, kEpiBwd = 1, kEpiGrid = 2 };
 // l holds row (or column) l mod 32 and K entries 8 (l / 32) .. 8 (l / 32) + 7
 // of the step; accumulator entry i of lane l is row 8 (i / 4) + 4 (l / 32) +
 // i mod 4, column l mod 32.
-template <int NBLK, int EPI>
+template <int NBLK>
 __global__ void __launch_bounds__(256) k_nf_gemm(NfGemm g)
 {
     extern __shared__ uint4 s_raw[];
@@ -244,7 +229,6 @@ __global__ void __launch_bounds__(256) k_nf_gemm(NfGemm g)
     __syncthreads();
     const int half = lane >> 5, l32 = lane & 31;
     const int n_tiles = g.M / kRowTile;
-    float wmax = 0.0f;
     for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int row0 = tile * kRowTile + wave * 32;
         f32x16 acc[NBLK];
@@ -253,7 +237,6 @@ __global__ void __launch_bounds__(256) k_nf_gemm(NfGemm g)
             acc[nb] = f32x16{};
         const uint16_t* ap = g.A + (size_t)(row0 + l32) * g.lda + half * 8;
         const uint16_t* bp = sB + l32 * ldsb + half * 8;
-        float vmax = 0.0f;
         for (int kc = 0; kc < K; kc += 128) {
             const int ns = min(8, (K - kc) >> 4);
             bf16x8 a[8];
@@ -277,224 +260,312 @@ __global__ void __launch_bounds__(256) k_nf_gemm(NfGemm g)
             const int col = nb * 32 + l32;
             if (col >= g.N)
                 continue;
-            const float bias = EPI == kEpiFwd ? g.bias[col] : 0.0f;
+            const float bias = g.bias[col];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int rbase = row0 + 8 * q + 4 * half;
-                uint16_t h[4];
-                uint2 m4 = make_uint2(0, 0);
-                if (EPI == kEpiBwd)  // mask rows rbase .. rbase + 3 of column col (transposed copy)
-                    m4 = *reinterpret_cast<const uint2*>(g.mask + (size_t)col * g.ldm + rbase);
-                const uint16_t mk[4] = {static_cast<uint16_t>(m4.x), static_cast<uint16_t>(m4.x >> 16),
-                                        static_cast<uint16_t>(m4.y), static_cast<uint16_t>(m4.y >> 16)};
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = rbase + r;
-                    float v = acc[nb][4 * q + r];
-                    if (EPI == kEpiFwd)
-                        v = fmaxf(v + bias, 0.0f);
-                    if (EPI == kEpiBwd && !bf16_positive(mk[r]))
-                        v = 0.0f;
-                    if (EPI == kEpiGrid) {
-                        if (col < g.nf)
-                            g.Cf[(size_t)row * g.ldcf + col] = v;
-                    } else {
-                        h[r] = to_bf16(v);
-                        g.C[(size_t)row * g.ldc + col] = h[r];
-                    }
-                }
-                if (EPI == kEpiGrid) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (col < g.nf)
-                            vmax = fmaxf(vmax, fabsf(acc[nb][4 * q + r]));
-                }
-                if (EPI != kEpiGrid && g.CT) {
-                    const uint2 pk = make_uint2(h[0] | (static_cast<uint32_t>(h[1]) << 16),
-                                                h[2] | (static_cast<uint32_t>(h[3]) << 16));
-                    *reinterpret_cast<uint2*>(g.CT + (size_t)col * g.ldct + rbase) = pk;
-                }
+            for (int i = 0; i < 16; ++i) {
+                const int row = row0 + 8 * (i / 4) + 4 * half + (i % 4);
+                g.C[(size_t)row * g.ldc + col] = to_bf16(fmaxf(acc[nb][i] + bias, 0.0f));
             }
         }
-        if (EPI == kEpiGrid)
-            wmax = fmaxf(wmax, vmax);
-    }
-    if (EPI == kEpiGrid) {
-        __shared__ float s_max[4];
-        for (int o = 32; o > 0; o >>= 1)
-            wmax = fmaxf(wmax, __shfl_xor(wmax, o, 64));
-        if (lane == 0)
-            s_max[wave] = wmax;
-        __syncthreads();
-        if (tid == 0)
-            g.gmax[blockIdx.x] = fmaxf(fmaxf(s_max[0], s_max[1]), fmaxf(s_max[2], s_max[3]));
     }
 }
 
-// Weight gradient partials: P[c] = A[:, chunk c] B[:, chunk c]^T with
-// A = dZ^T [Mo][ld] and B = act^T [Ni][ld] (bfloat16, contiguous along
-// the batch), Mo <= 128, Ni <= 32 NBLK; and the bias-gradient partials
-// Q[c][m] = sum of A[m][chunk c].  The contraction order inside a chunk is
-// a fixed permutation shared by both operands: at step s of 64 rows, lane l
-// covers rows 32 (l / 32) + 8 j .. + 7 in MFMA j = 0..3, so each lane reads
-// 64 contiguous bytes of its operand rows.
-struct NfWgrad {
-    const uint16_t* A;
-    const uint16_t* Bm;
-    int64_t ld;
-    int32_t Mo, Ni, chunk, n_rows;
-    float* P;
-    float* Q;
+// Fused backward pass of layer i (input width IN <= 32 NB) over 128-row
+// tiles (persistent):
+//   dH_i^T = W_i^T dZ_i^T: wave w computes rows k = 32 w .. 32 w + 31, its
+//            W_i^T fragments held in registers, dZ_i read row-major;
+//   dZ_{i-1} = dH_i [A_i > 0] stored row-major (GRID: the 16 grid columns of
+//            dH_0 in FP32 instead, and the workgroup's max |dH_0|);
+//   dW_i  += dZ_i^T A_i and db_i += column sums of dZ_i, wave w computing
+//            rows m = 32 w .. 32 w + 31, from the tile's dZ_i and A_i
+//            transposed into LDS (both operands contiguous along the rows).
+// Each workgroup writes its dW_i, db_i as one partial.
+struct NfBwd {
+    const uint16_t* dz;    // dZ_i [Bp][128]
+    const uint16_t* act;   // A_i [Bp][in_dim]
+    const uint16_t* wt;    // W_i^T [in_dim][128]
+    int32_t in_dim, Bp;
+    uint16_t* dz_prev;     // dZ_{i-1} [Bp][128]
+    float* dh0;            // [Bp][16]
+    float* gmax;           // [gridDim.x]
+    float* Pw;             // [gridDim.x][128][in_dim]
+    float* Pb;             // [gridDim.x][128]
 };
 
-template <int NBLK>
-__global__ void __launch_bounds__(256) k_nf_wgrad(NfWgrad w)
+
+template <int NB, bool GRID>
+__global__ void __launch_bounds__(256) k_nf_bwd(NfBwd p)
 {
+    __shared__ uint16_t sDZ[kHidden * kTilePitch];  // dZ tile transposed [m][row]
+    __shared__ uint16_t sA[NB * 32 * kTilePitch];   // A tile transposed [k][row]
+    __shared__ float s_max[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int half = lane >> 5, l32 = lane & 31;
-    const int c = blockIdx.x;
-    const int m0 = wave * 32;
-    if (m0 >= w.Mo)
-        return;
-    const int k0 = c * w.chunk;
-    const int k1 = min(k0 + w.chunk, w.n_rows);
-    const int am = m0 + l32;
-    const bool a_ok = am < w.Mo;
-    const uint16_t* ap = w.A + (size_t)(a_ok ? am : 0) * w.ld + half * 32;
-    const uint16_t* bp[NBLK];
-    bool b_ok[NBLK];
-#pragma unroll
-    for (int nb = 0; nb < NBLK; ++nb) {
-        const int bn = nb * 32 + l32;
-        b_ok[nb] = bn < w.Ni;
-        bp[nb] = w.Bm + (size_t)(b_ok[nb] ? bn : 0) * w.ld + half * 32;
-    }
-    f32x16 acc[NBLK];
-#pragma unroll
-    for (int nb = 0; nb < NBLK; ++nb)
-        acc[nb] = f32x16{};
-    float gsum = 0.0f;
+    const int IN = p.in_dim;
     const bf16x8 zero = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
-    for (int k = k0; k < k1; k += 64) {
-        bf16x8 a[4];
+    const bool dh_wave = GRID ? wave == 0 : wave * 32 < IN;
+    bf16x8 wfr[kHidden / 16];
+    {
+        const int k = wave * 32 + l32;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            a[j] = a_ok ? load8(ap + k + 8 * j) : zero;
+        for (int kk = 0; kk < kHidden / 16; ++kk)
+            wfr[kk] = (dh_wave && k < IN) ? load8(p.wt + (size_t)k * kHidden + kk * 16 + half * 8) : zero;
+    }
+    f32x16 accW[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+        accW[nb] = f32x16{};
+    float gb = 0.0f, vmax = 0.0f;
+    const int n_tiles = p.Bp / kRowTile;
+    const int in8 = IN / 8;
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int b0 = tile * kRowTile;
+        __syncthreads();
+        // stage both tiles transposed: a task is a pair of rows and 8 columns,
+        // written as 8 packed pairs (consecutive lanes take consecutive pairs)
+        for (int task = tid; task < 64 * (kHidden / 8); task += 256) {
+            const int rp = task & 63, cj = task >> 6;
+            const uint4 r0 = *reinterpret_cast<const uint4*>(p.dz + (size_t)(b0 + 2 * rp) * kHidden + cj * 8);
+            const uint4 r1 = *reinterpret_cast<const uint4*>(p.dz + (size_t)(b0 + 2 * rp + 1) * kHidden + cj * 8);
+            const uint32_t x0[4] = {r0.x, r0.y, r0.z, r0.w}, x1[4] = {r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t lo = (x0[e >> 1] >> ((e & 1) * 16)) & 0xffffu;
+                const uint32_t hi = (x1[e >> 1] >> ((e & 1) * 16)) & 0xffffu;
+                *reinterpret_cast<uint32_t*>(sDZ + (cj * 8 + e) * kTilePitch + 2 * rp) = lo | (hi << 16);
+            }
+        }
+        for (int task = tid; task < 64 * in8; task += 256) {
+            const int rp = task & 63, cj = task >> 6;
+            const uint4 r0 = *reinterpret_cast<const uint4*>(p.act + (size_t)(b0 + 2 * rp) * IN + cj * 8);
+            const uint4 r1 = *reinterpret_cast<const uint4*>(p.act + (size_t)(b0 + 2 * rp + 1) * IN + cj * 8);
+            const uint32_t x0[4] = {r0.x, r0.y, r0.z, r0.w}, x1[4] = {r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t lo = (x0[e >> 1] >> ((e & 1) * 16)) & 0xffffu;
+                const uint32_t hi = (x1[e >> 1] >> ((e & 1) * 16)) & 0xffffu;
+                *reinterpret_cast<uint32_t*>(sA + (cj * 8 + e) * kTilePitch + 2 * rp) = lo | (hi << 16);
+            }
+        }
+        __syncthreads();
+        if (dh_wave) {
+            f32x16 acc[kRowTile / 32];
+#pragma unroll
+            for (int bb = 0; bb < kRowTile / 32; ++bb)
+                acc[bb] = f32x16{};
+#pragma unroll
+            for (int bb = 0; bb < kRowTile / 32; ++bb) {
+                const uint16_t* dr = p.dz + (size_t)(b0 + bb * 32 + l32) * kHidden + half * 8;
+                bf16x8 bv[kHidden / 16];
+#pragma unroll
+                for (int kk = 0; kk < kHidden / 16; ++kk)
+                    bv[kk] = load8(dr + kk * 16);
+#pragma unroll
+                for (int kk = 0; kk < kHidden / 16; ++kk)
+                    acc[bb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfr[kk], bv[kk], acc[bb], 0, 0, 0);
+            }
+#pragma unroll
+            for (int bb = 0; bb < kRowTile / 32; ++bb) {
+                const int b = bb * 32 + l32;  // tile row
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int k0 = wave * 32 + 8 * q + 4 * half;
+                    if (GRID) {
+                        if (k0 < kLevels * kFeat) {
+                            const float4 v = make_float4(acc[bb][4 * q], acc[bb][4 * q + 1], acc[bb][4 * q + 2],
+                                                         acc[bb][4 * q + 3]);
+                            *reinterpret_cast<float4*>(p.dh0 + (size_t)(b0 + b) * (kLevels * kFeat) + k0) = v;
+                            vmax = fmaxf(vmax, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+                        }
+                    } else {
+                        uint16_t h[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const float v = bf16_positive(sA[(k0 + r) * kTilePitch + b]) ? acc[bb][4 * q + r] : 0.0f;
+                            h[r] = to_bf16(v);
+                        }
+                        const uint2 pk = make_uint2(h[0] | (static_cast<uint32_t>(h[1]) << 16),
+                                                    h[2] | (static_cast<uint32_t>(h[3]) << 16));
+                        *reinterpret_cast<uint2*>(p.dz_prev + (size_t)(b0 + b) * kHidden + k0) = pk;
+                    }
+                }
+            }
+        }
+        // dW += dZ^T A and db over the tile's rows
+        const uint16_t* ar = sDZ + (wave * 32 + l32) * kTilePitch + half * 8;
+#pragma unroll
+        for (int kk = 0; kk < kRowTile / 16; ++kk) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8*>(ar + kk * 16);
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                gsum += static_cast<float>(a[j][e]);
-        }
+                gb += static_cast<float>(av[e]);
 #pragma unroll
-        for (int nb = 0; nb < NBLK; ++nb) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const bf16x8 bv = b_ok[nb] ? load8(bp[nb] + k + 8 * j) : zero;
-                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[j], bv, acc[nb], 0, 0, 0);
+            for (int nb = 0; nb < NB; ++nb) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sA + (nb * 32 + l32) * kTilePitch + kk * 16 + half * 8);
+                accW[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, accW[nb], 0, 0, 0);
             }
         }
     }
-    float* P = w.P + (size_t)c * w.Mo * w.Ni;
+    float* Pw = p.Pw + (size_t)blockIdx.x * kHidden * IN;
 #pragma unroll
-    for (int nb = 0; nb < NBLK; ++nb) {
-        const int col = nb * 32 + l32;
-        if (col >= w.Ni)
+    for (int nb = 0; nb < NB; ++nb) {
+        const int k = nb * 32 + l32;
+        if (k >= IN)
             continue;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int m = m0 + 8 * (i / 4) + 4 * half + (i % 4);
-            if (m < w.Mo)
-                P[(size_t)m * w.Ni + col] = acc[nb][i];
-        }
+        for (int i = 0; i < 16; ++i)
+            Pw[(size_t)(wave * 32 + 8 * (i / 4) + 4 * half + (i % 4)) * IN + k] = accW[nb][i];
     }
-    gsum += __shfl_xor(gsum, 32, 64);
-    if (half == 0 && a_ok)
-        w.Q[(size_t)c * w.Mo + am] = gsum;
+    gb += __shfl_xor(gb, 32, 64);
+    if (half == 0)
+        p.Pb[(size_t)blockIdx.x * kHidden + wave * 32 + l32] = gb;
+    if (GRID) {
+        for (int o = 32; o > 0; o >>= 1)
+            vmax = fmaxf(vmax, __shfl_xor(vmax, o, 64));
+        if (lane == 0)
+            s_max[wave] = vmax;
+        __syncthreads();
+        if (tid == 0)
+            p.gmax[blockIdx.x] = fmaxf(fmaxf(s_max[0], s_max[1]), fmaxf(s_max[2], s_max[3]));
+    }
 }
 
-// Output layer, loss and the step back to dZ_3, one thread per row.
+// Output layer over 128-row tiles (persistent): y = A_4 W_4^T + b_4, the
+// loss, dZ_4 = 2 (y - t) / (B n_out) rounded to bfloat16, and in training
+// dZ_3 = (dZ_4 W_4) [A_4 > 0] row-major plus the workgroup's partials of
+// dW_4 = dZ_4^T A_4 and db_4 = sums of dZ_4.  Row r's output is the sum of
+// two half-rows of 64 products.
 struct NfOut {
     const uint16_t* H;   // A_4 [Bp][128]
     const uint16_t* W;   // W_4 [n_out][128] bfloat16
     const float* b;      // b_4
     const float* target; // [B][n_out] (training) or null
-    float* y;            // [B][n_out] (inference) or null
+    float* y;            // [B][n_out] or null
     int32_t B, Bp, n_out;
     float scale;         // 2 / (B n_out)
-    uint16_t* dzoT;      // dZ_4^T [n_out][Bp]
-    uint16_t* dz3;       // [Bp][128]
-    uint16_t* dz3T;      // [128][Bp]
-    double* loss_part;   // per workgroup
+    uint16_t* dz3;       // [Bp][128] (training) or null
+    float* Pw4;          // [gridDim.x][n_out][128]
+    float* Pb4;          // [gridDim.x][n_out]
+    double* loss_part;   // [gridDim.x]
 };
+
+constexpr int kOutPitch = kHidden + 2;  // bfloat16 per LDS row: an odd number of dwords
+constexpr int kOutTasks = kMaxOut * kHidden / 256;
 
 __global__ void __launch_bounds__(256) k_nf_out(NfOut o)
 {
-    __shared__ float s_dz[kMaxOut][256];
+    __shared__ uint16_t sH[kRowTile * kOutPitch];
+    __shared__ float sW[kMaxOut * kHidden];
+    __shared__ float s_dz[kMaxOut][kRowTile];
     __shared__ double s_red[256];
     const int tid = threadIdx.x;
-    const int32_t b = blockIdx.x * 256 + tid;
-    const bool live = b < o.B;
+    const bool train = o.dz3 != nullptr;
+    const int nO = o.n_out;
+    for (int e = tid; e < nO * kHidden; e += 256)
+        sW[e] = from_bf16(o.W[e]);
+    float accw[kOutTasks];
+#pragma unroll
+    for (int j = 0; j < kOutTasks; ++j)
+        accw[j] = 0.0f;
+    float accb = 0.0f;
     double lsum = 0.0;
-    uint4 hrow[kHidden / 8];
-    if (b < o.Bp) {
-#pragma unroll
-        for (int q = 0; q < kHidden / 8; ++q)
-            hrow[q] = reinterpret_cast<const uint4*>(o.H + (size_t)b * kHidden)[q];
-    }
-    if (b < o.Bp) {
-        for (int oi = 0; oi < o.n_out; ++oi) {
-            const uint16_t* wr = o.W + (size_t)oi * kHidden;
-            float acc = 0.0f;
-#pragma unroll
-            for (int q = 0; q < kHidden / 8; ++q) {
-                const uint32_t hw[4] = {hrow[q].x, hrow[q].y, hrow[q].z, hrow[q].w};
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const uint16_t hv = static_cast<uint16_t>(hw[e >> 1] >> ((e & 1) * 16));
-                    acc = fmaf(from_bf16(hv), from_bf16(wr[q * 8 + e]), acc);
+    const int r = tid >> 1, hf = tid & 1;
+    const int n_tiles = o.Bp / kRowTile;
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int b0 = tile * kRowTile;
+        __syncthreads();
+        for (int task = tid; task < kRowTile * (kHidden / 8); task += 256) {
+            const int rr = task >> 4, c = task & 15;
+            const uint4 v = *reinterpret_cast<const uint4*>(o.H + (size_t)(b0 + rr) * kHidden + c * 8);
+            uint32_t* d = reinterpret_cast<uint32_t*>(sH + rr * kOutPitch + c * 8);
+            d[0] = v.x;
+            d[1] = v.y;
+            d[2] = v.z;
+            d[3] = v.w;
+        }
+        __syncthreads();
+        const int row = b0 + r;
+        const bool live = row < o.B;
+        for (int oi = 0; oi < nO; ++oi) {
+            float part = 0.0f;
+            const uint16_t* hr = sH + r * kOutPitch + hf * 64;
+            const float* wr = sW + oi * kHidden + hf * 64;
+#pragma unroll 8
+            for (int k = 0; k < 64; ++k)
+                part = fmaf(from_bf16(hr[k]), wr[k], part);
+            part += __shfl_xor(part, 1, 64);
+            if (hf == 0) {
+                const float yv = part + o.b[oi];
+                float dz = 0.0f;
+                if (live) {
+                    if (o.y)
+                        o.y[(size_t)row * nO + oi] = yv;
+                    if (o.target) {
+                        const float diff = yv - o.target[(size_t)row * nO + oi];
+                        lsum += static_cast<double>(diff) * diff;
+                        dz = o.scale * diff;
+                    }
                 }
-            }
-            const float yv = acc + o.b[oi];
-            float dz = 0.0f;
-            if (live) {
-                if (o.y)
-                    o.y[(size_t)b * o.n_out + oi] = yv;
-                if (o.target) {
-                    const float diff = yv - o.target[(size_t)b * o.n_out + oi];
-                    lsum += static_cast<double>(diff) * diff;
-                    dz = o.scale * diff;
-                }
-            }
-            if (o.dzoT) {
-                const uint16_t h = to_bf16(dz);
-                o.dzoT[(size_t)oi * o.Bp + b] = h;
-                s_dz[oi][tid] = from_bf16(h);
+                s_dz[oi][r] = from_bf16(to_bf16(dz));
             }
         }
-        if (o.dz3) {
-            RowWriter wr{o.dz3 + (size_t)b * kHidden};
+        if (!train)
+            continue;
+        __syncthreads();
+        // dZ_3, one 8-column piece of a row per task
+        for (int task = tid; task < kRowTile * (kHidden / 8); task += 256) {
+            const int rr = task >> 4, c = task & 15;
+            uint32_t pk[4];
 #pragma unroll
-            for (int q = 0; q < kHidden / 8; ++q) {
-                const uint32_t hw[4] = {hrow[q].x, hrow[q].y, hrow[q].z, hrow[q].w};
+            for (int e = 0; e < 8; e += 2) {
+                uint32_t two = 0;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int k = q * 8 + e;
-                    const uint16_t hv = static_cast<uint16_t>(hw[e >> 1] >> ((e & 1) * 16));
+                for (int u = 0; u < 2; ++u) {
+                    const int k = c * 8 + e + u;
                     float dh = 0.0f;
-                    for (int oi = 0; oi < o.n_out; ++oi)
-                        dh = fmaf(s_dz[oi][tid], from_bf16(o.W[(size_t)oi * kHidden + k]), dh);
-                    const uint16_t h = to_bf16(bf16_positive(hv) ? dh : 0.0f);
-                    wr.put(h);
-                    o.dz3T[(size_t)k * o.Bp + b] = h;
+                    for (int oi = 0; oi < nO; ++oi)
+                        dh = fmaf(s_dz[oi][rr], sW[oi * kHidden + k], dh);
+                    const uint16_t h = to_bf16(bf16_positive(sH[rr * kOutPitch + k]) ? dh : 0.0f);
+                    two |= static_cast<uint32_t>(h) << (16 * u);
                 }
+                pk[e >> 1] = two;
+            }
+            *reinterpret_cast<uint4*>(o.dz3 + (size_t)(b0 + rr) * kHidden + c * 8) =
+                make_uint4(pk[0], pk[1], pk[2], pk[3]);
+        }
+        // dW_4 and db_4 over the tile's rows
+#pragma unroll
+        for (int j = 0; j < kOutTasks; ++j) {
+            const int e = tid + 256 * j;
+            if (e < nO * kHidden) {
+                const int oi = e / kHidden, k = e - oi * kHidden;
+                float a = accw[j];
+                for (int rr = 0; rr < kRowTile; ++rr)
+                    a = fmaf(s_dz[oi][rr], from_bf16(sH[rr * kOutPitch + k]), a);
+                accw[j] = a;
             }
         }
+        if (tid < nO)
+            for (int rr = 0; rr < kRowTile; ++rr)
+                accb += s_dz[tid][rr];
+    }
+    if (train) {
+#pragma unroll
+        for (int j = 0; j < kOutTasks; ++j) {
+            const int e = tid + 256 * j;
+            if (e < nO * kHidden)
+                o.Pw4[(size_t)blockIdx.x * nO * kHidden + e] = accw[j];
+        }
+        if (tid < nO)
+            o.Pb4[(size_t)blockIdx.x * nO + tid] = accb;
     }
     if (o.loss_part) {
+        __syncthreads();
         s_red[tid] = lsum;
         __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (tid < s)
-                s_red[tid] += s_red[tid + s];
+        for (int h = 128; h > 0; h >>= 1) {
+            if (tid < h)
+                s_red[tid] += s_red[tid + h];
             __syncthreads();
         }
         if (tid == 0)
@@ -533,19 +604,32 @@ struct NfReduce {
 
 __global__ void __launch_bounds__(256) k_nf_reduce(NfReduce r)
 {
+    // 64 outputs per workgroup; wave g sums the g-th quarter of the partials
+    // in order, then the four quarter sums are added in order
+    __shared__ double s_q[4][64];
     const NfSeg& s = r.seg[blockIdx.y];
-    for (int32_t e = blockIdx.x * 256 + threadIdx.x; e < s.n; e += gridDim.x * 256) {
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int32_t per = (s.nch + 3) / 4;
+    const int32_t c_lo = g * per, c_hi = min(s.nch, c_lo + per);
+    for (int32_t e0 = blockIdx.x * 64; e0 < s.n; e0 += gridDim.x * 64) {
+        const int32_t e = e0 + lane;
         double a = 0.0;
-        for (int c0 = 0; c0 < s.nch; c0 += 8) {
-            float v[8];
+        if (e < s.n) {
+            for (int32_t c0 = c_lo; c0 < c_hi; c0 += 8) {
+                float v[8];
 #pragma unroll
-            for (int c = 0; c < 8; ++c)
-                v[c] = c0 + c < s.nch ? s.part[(size_t)(c0 + c) * s.n + e] : 0.0f;
+                for (int c = 0; c < 8; ++c)
+                    v[c] = c0 + c < c_hi ? s.part[(size_t)(c0 + c) * s.n + e] : 0.0f;
 #pragma unroll
-            for (int c = 0; c < 8; ++c)
-                a += v[c];
+                for (int c = 0; c < 8; ++c)
+                    a += v[c];
+            }
         }
-        s.out[e] = static_cast<float>(a);
+        __syncthreads();
+        s_q[g][lane] = a;
+        __syncthreads();
+        if (g == 0 && e < s.n)
+            s.out[e] = static_cast<float>(((s_q[0][lane] + s_q[1][lane]) + s_q[2][lane]) + s_q[3][lane]);
     }
 }
 
@@ -719,59 +803,47 @@ namespace {
 
 // Workspace of a batch of Bp rows.
 struct NfWs {
-    uint16_t *X, *XT;
-    uint16_t *H[4], *HT[4];   // A_1 .. A_4
-    uint16_t *dz[4], *dzT[4]; // dZ_0 .. dZ_3
-    uint16_t* dzoT;           // dZ_4^T
+    uint16_t* X;
+    uint16_t* H[4];           // A_1 .. A_4
+    uint16_t* dz[4];          // dZ_0 .. dZ_3
     float* dh0;               // [Bp][16]
-    double* loss_part;
+    double* loss_part;        // [bwd_grid]
     double* loss;
-    float* P;                 // weight-gradient chunk partials, every layer
-    float* Q;                 // bias-gradient chunk partials, every layer
+    float* Pw[kLayers];       // dW_0 .. dW_4 workgroup partials [bwd_grid][out_i][in_i]
+    float* Pb[kLayers];       // db_0 .. db_4 workgroup partials [bwd_grid][out_i]
     long long* gpart;         // grid-gradient partials [grid_groups][kGridFloats]
-    float* gmax;              // max |dH_0| of each workgroup of its product
+    float* gmax;              // max |dH_0| of each workgroup of the layer-0 backward
     int32_t n_gmax;
-    int64_t offP[kLayers], offQ[kLayers];
-    int32_t chunk, nch, grid_groups;
+    int32_t grid_groups, bwd_grid;
 };
+
+constexpr int kBwdGrid = 512;  // workgroups of a fused backward pass (persistent)
 
 int32_t nf_grid_groups(int32_t Bp)
 {
     return static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(kGridGroupsMax, (Bp + 4095) / 4096)));
 }
 
-void nf_chunks(int32_t Bp, int32_t* chunk, int32_t* nch)
-{
-    int64_t c = (Bp + 255) / 256;
-    c = std::max<int64_t>(kRowTile, (c + kRowTile - 1) / kRowTile * kRowTile);
-    *chunk = static_cast<int32_t>(c);
-    *nch = static_cast<int32_t>((Bp + c - 1) / c);
-}
-
 size_t nf_ws_layout(const nat_nf* nf, int32_t Bp, NfWs* w, void* base)
 {
-    int32_t chunk, nch;
-    nf_chunks(Bp, &chunk, &nch);
     const size_t bp = static_cast<size_t>(Bp);
-    size_t sum_pq = 0, sum_q = 0;
-    for (int i = 0; i < kLayers; ++i) {
-        sum_pq += static_cast<size_t>(nf->out_dim[i]) * nf->in_dim[i];
-        sum_q += static_cast<size_t>(nf->out_dim[i]);
-    }
     const int32_t G = nf_grid_groups(Bp);
+    const int32_t GB = std::min(Bp / kRowTile, kBwdGrid);
     std::vector<size_t> sz;
-    sz.push_back(2 * bp * nf->D);
-    sz.push_back(2 * bp * nf->D);
-    for (int i = 0; i < 16; ++i)
-        sz.push_back(2 * bp * kHidden);
-    sz.push_back(2 * bp * nf->n_out);
-    sz.push_back(4 * bp * kLevels * kFeat);
-    sz.push_back(8 * (bp / 256 + 1));
-    sz.push_back(8);
-    sz.push_back(4 * sum_pq * nch);
-    sz.push_back(4 * sum_q * nch);
+    sz.push_back(2 * bp * nf->D);                 // X
+    for (int i = 0; i < 4; ++i)
+        sz.push_back(2 * bp * kHidden);           // H
+    for (int i = 0; i < 4; ++i)
+        sz.push_back(2 * bp * kHidden);           // dz
+    sz.push_back(4 * bp * kLevels * kFeat);       // dh0
+    sz.push_back(8 * static_cast<size_t>(GB));    // loss_part
+    sz.push_back(8);                              // loss
+    for (int i = 0; i < kLayers; ++i)
+        sz.push_back(4 * static_cast<size_t>(GB) * nf->out_dim[i] * nf->in_dim[i]);  // Pw
+    for (int i = 0; i < kLayers; ++i)
+        sz.push_back(4 * static_cast<size_t>(GB) * nf->out_dim[i]);                  // Pb
     sz.push_back(8 * static_cast<size_t>(kGridFloats) * G);
-    sz.push_back(4 * static_cast<size_t>(kGemmGrid));
+    sz.push_back(4 * static_cast<size_t>(GB));
     size_t total = 0;
     for (size_t s : sz)
         total = ((total + 255) & ~size_t(255)) + s;
@@ -779,34 +851,22 @@ size_t nf_ws_layout(const nat_nf* nf, int32_t Bp, NfWs* w, void* base)
     if (w && base) {
         Carver cv(base);
         w->X = cv.take<uint16_t>(bp * nf->D);
-        w->XT = cv.take<uint16_t>(bp * nf->D);
         for (int i = 0; i < 4; ++i)
             w->H[i] = cv.take<uint16_t>(bp * kHidden);
         for (int i = 0; i < 4; ++i)
-            w->HT[i] = cv.take<uint16_t>(bp * kHidden);
-        for (int i = 0; i < 4; ++i)
             w->dz[i] = cv.take<uint16_t>(bp * kHidden);
-        for (int i = 0; i < 4; ++i)
-            w->dzT[i] = cv.take<uint16_t>(bp * kHidden);
-        w->dzoT = cv.take<uint16_t>(bp * nf->n_out);
         w->dh0 = cv.take<float>(bp * kLevels * kFeat);
-        w->loss_part = cv.take<double>(bp / 256 + 1);
+        w->loss_part = cv.take<double>(GB);
         w->loss = cv.take<double>(1);
-        w->P = cv.take<float>(sum_pq * nch);
-        w->Q = cv.take<float>(sum_q * nch);
+        for (int i = 0; i < kLayers; ++i)
+            w->Pw[i] = cv.take<float>(static_cast<size_t>(GB) * nf->out_dim[i] * nf->in_dim[i]);
+        for (int i = 0; i < kLayers; ++i)
+            w->Pb[i] = cv.take<float>(static_cast<size_t>(GB) * nf->out_dim[i]);
         w->gpart = cv.take<long long>(static_cast<size_t>(kGridFloats) * G);
-        w->gmax = cv.take<float>(kGemmGrid);
-        w->n_gmax = std::min(Bp / kRowTile, kGemmGrid);
-        int64_t op = 0, oq = 0;
-        for (int i = 0; i < kLayers; ++i) {
-            w->offP[i] = op;
-            w->offQ[i] = oq;
-            op += (int64_t)nf->out_dim[i] * nf->in_dim[i] * nch;
-            oq += (int64_t)nf->out_dim[i] * nch;
-        }
-        w->chunk = chunk;
-        w->nch = nch;
+        w->gmax = cv.take<float>(GB);
+        w->n_gmax = GB;
         w->grid_groups = G;
+        w->bwd_grid = GB;
     }
     return total;
 }
@@ -846,56 +906,29 @@ NfDev nf_dev(const nat_nf* nf)
     return f;
 }
 
-template <int EPI>
-hipError_t launch_gemm_epi(const NfGemm& g, hipStream_t s)
+hipError_t launch_gemm(const NfGemm& g, hipStream_t s)
 {
     const int nblk = (g.N + 31) / 32;
     const size_t lds = static_cast<size_t>(nblk) * 32 * (g.K + 8) * sizeof(uint16_t);
     // persistent: B is staged once per workgroup
     const int grid = std::min(g.M / kRowTile, kGemmGrid);
     switch (nblk) {
-    case 1: hipLaunchKernelGGL((k_nf_gemm<1, EPI>), dim3(grid), dim3(256), lds, s, g); break;
-    case 2: hipLaunchKernelGGL((k_nf_gemm<2, EPI>), dim3(grid), dim3(256), lds, s, g); break;
-    case 3: hipLaunchKernelGGL((k_nf_gemm<3, EPI>), dim3(grid), dim3(256), lds, s, g); break;
-    case 4: hipLaunchKernelGGL((k_nf_gemm<4, EPI>), dim3(grid), dim3(256), lds, s, g); break;
+    case 1: hipLaunchKernelGGL(k_nf_gemm<1>, dim3(grid), dim3(256), lds, s, g); break;
+    case 2: hipLaunchKernelGGL(k_nf_gemm<2>, dim3(grid), dim3(256), lds, s, g); break;
+    case 3: hipLaunchKernelGGL(k_nf_gemm<3>, dim3(grid), dim3(256), lds, s, g); break;
+    case 4: hipLaunchKernelGGL(k_nf_gemm<4>, dim3(grid), dim3(256), lds, s, g); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_gemm(const NfGemm& g, hipStream_t s)
-{
-    if (g.Cf)
-        return launch_gemm_epi<kEpiGrid>(g, s);
-    if (g.mask)
-        return launch_gemm_epi<kEpiBwd>(g, s);
-    return launch_gemm_epi<kEpiFwd>(g, s);
-}
-
-hipError_t launch_wgrad(const NfWgrad& w, int nch, hipStream_t s)
-{
-    const int nblk = (w.Ni + 31) / 32;
-    switch (nblk) {
-    case 1: hipLaunchKernelGGL(k_nf_wgrad<1>, dim3(nch), dim3(256), 0, s, w); break;
-    case 2: hipLaunchKernelGGL(k_nf_wgrad<2>, dim3(nch), dim3(256), 0, s, w); break;
-    case 3: hipLaunchKernelGGL(k_nf_wgrad<3>, dim3(nch), dim3(256), 0, s, w); break;
-    case 4: hipLaunchKernelGGL(k_nf_wgrad<4>, dim3(nch), dim3(256), 0, s, w); break;
-    case 5: hipLaunchKernelGGL(k_nf_wgrad<5>, dim3(nch), dim3(256), 0, s, w); break;
-    case 6: hipLaunchKernelGGL(k_nf_wgrad<6>, dim3(nch), dim3(256), 0, s, w); break;
-    case 7: hipLaunchKernelGGL(k_nf_wgrad<7>, dim3(nch), dim3(256), 0, s, w); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-// Forward pass of B rows (padded to Bp); with `train` the transposed copies
-// are written and the output kernel forms the loss and dZ_4, dZ_3.
+// Forward pass of B rows (padded to Bp); with `train` the output kernel also
+// forms the loss, dZ_3 and the partials of dW_4, db_4.
 hipError_t nf_forward(nat_nf* nf, const NfWs& w, const float* in, const float* target, int32_t B, int32_t Bp,
                       float* y, bool train, hipStream_t s)
 {
     const NfDev f = nf_dev(nf);
-    hipLaunchKernelGGL(k_nf_encode, dim3((Bp + 255) / 256), dim3(256), 0, s, f, in, B, Bp, w.X,
-                       train ? w.XT : nullptr);
+    hipLaunchKernelGGL(k_nf_encode, dim3((Bp + 255) / 256), dim3(256), 0, s, f, in, B, Bp, w.X);
     hipError_t e = hipGetLastError();
     for (int i = 0; i < 4 && e == hipSuccess; ++i) {
         NfGemm g{};
@@ -907,11 +940,8 @@ hipError_t nf_forward(nat_nf* nf, const NfWs& w, const float* in, const float* t
         g.N = kHidden;
         g.K = nf->in_dim[i];
         g.bias = nf->d_params + nf->offb[i];
-        g.relu = 1;
         g.C = w.H[i];
         g.ldc = kHidden;
-        g.CT = train ? w.HT[i] : nullptr;
-        g.ldct = Bp;
         e = launch_gemm(g, s);
     }
     if (e != hipSuccess)
@@ -926,72 +956,66 @@ hipError_t nf_forward(nat_nf* nf, const NfWs& w, const float* in, const float* t
     o.Bp = Bp;
     o.n_out = nf->n_out;
     o.scale = static_cast<float>(2.0 / (static_cast<double>(B) * nf->n_out));
-    o.dzoT = train ? w.dzoT : nullptr;
     o.dz3 = train ? w.dz[3] : nullptr;
-    o.dz3T = train ? w.dzT[3] : nullptr;
+    o.Pw4 = w.Pw[4];
+    o.Pb4 = w.Pb[4];
     o.loss_part = train ? w.loss_part : nullptr;
-    hipLaunchKernelGGL(k_nf_out, dim3((Bp + 255) / 256), dim3(256), 0, s, o);
+    hipLaunchKernelGGL(k_nf_out, dim3(w.bwd_grid), dim3(256), 0, s, o);
     e = hipGetLastError();
     if (e == hipSuccess && train) {
-        hipLaunchKernelGGL(k_nf_sum, dim3(1), dim3(256), 0, s, w.loss_part, (Bp + 255) / 256, w.loss);
+        hipLaunchKernelGGL(k_nf_sum, dim3(1), dim3(256), 0, s, w.loss_part, w.bwd_grid, w.loss);
         e = hipGetLastError();
     }
     return e;
+}
+
+template <bool GRID>
+hipError_t launch_bwd(const NfBwd& p, int grid, hipStream_t s)
+{
+    switch ((p.in_dim + 31) / 32) {
+    case 1: hipLaunchKernelGGL((k_nf_bwd<1, GRID>), dim3(grid), dim3(256), 0, s, p); break;
+    case 2: hipLaunchKernelGGL((k_nf_bwd<2, GRID>), dim3(grid), dim3(256), 0, s, p); break;
+    case 3: hipLaunchKernelGGL((k_nf_bwd<3, GRID>), dim3(grid), dim3(256), 0, s, p); break;
+    case 4: hipLaunchKernelGGL((k_nf_bwd<4, GRID>), dim3(grid), dim3(256), 0, s, p); break;
+    case 5: hipLaunchKernelGGL((k_nf_bwd<5, GRID>), dim3(grid), dim3(256), 0, s, p); break;
+    case 6: hipLaunchKernelGGL((k_nf_bwd<6, GRID>), dim3(grid), dim3(256), 0, s, p); break;
+    case 7: hipLaunchKernelGGL((k_nf_bwd<7, GRID>), dim3(grid), dim3(256), 0, s, p); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // Gradient of every parameter into d_grads (after nf_forward with train).
 hipError_t nf_backward(nat_nf* nf, const NfWs& w, const float* in, int32_t B, int32_t Bp, hipStream_t s)
 {
     hipError_t e = hipSuccess;
-    // input gradients: dZ_3 -> dZ_2 -> dZ_1 -> dZ_0 -> dH_0 (grid columns)
+    // fused passes, layer 3 down to layer 0 (the grid columns of dH_0)
     for (int i = 3; i >= 0 && e == hipSuccess; --i) {
-        NfGemm g{};
-        g.A = w.dz[i];
-        g.lda = kHidden;
-        g.Bm = nf->d_wbt + nf->offWb[i];  // W_i^T [in_i][128]
-        g.ldb = kHidden;
-        g.M = Bp;
-        g.K = kHidden;
-        if (i > 0) {
-            g.N = kHidden;
-            g.mask = w.HT[i - 1];  // A_i transposed: [128][Bp]
-            g.ldm = Bp;
-            g.C = w.dz[i - 1];
-            g.ldc = kHidden;
-            g.CT = w.dzT[i - 1];
-            g.ldct = Bp;
-        } else {
-            g.N = 32;  // the grid features are the first 16 input columns
-            g.Cf = w.dh0;
-            g.ldcf = kLevels * kFeat;
-            g.nf = kLevels * kFeat;
-            g.gmax = w.gmax;
-        }
-        e = launch_gemm(g, s);
-    }
-    // weight and bias gradients: chunk partials of every layer, then one
-    // launch folds them in chunk order
-    NfReduce red{};
-    int32_t max_n = 0;
-    for (int i = 0; i < kLayers && e == hipSuccess; ++i) {
-        NfWgrad g{};
-        g.A = i == 4 ? w.dzoT : w.dzT[i];
-        g.Bm = i == 0 ? w.XT : w.HT[i - 1];
-        g.ld = Bp;
-        g.Mo = nf->out_dim[i];
-        g.Ni = nf->in_dim[i];
-        g.chunk = w.chunk;
-        g.n_rows = Bp;
-        g.P = w.P + w.offP[i];
-        g.Q = w.Q + w.offQ[i];
-        e = launch_wgrad(g, w.nch, s);
-        red.seg[2 * i] = NfSeg{g.P, nf->d_grads + nf->offW[i], nf->out_dim[i] * nf->in_dim[i], w.nch};
-        red.seg[2 * i + 1] = NfSeg{g.Q, nf->d_grads + nf->offb[i], nf->out_dim[i], w.nch};
-        max_n = std::max(max_n, nf->out_dim[i] * nf->in_dim[i]);
+        NfBwd p{};
+        p.dz = w.dz[i];
+        p.act = i == 0 ? w.X : w.H[i - 1];
+        p.wt = nf->d_wbt + nf->offWb[i];  // W_i^T [in_i][128]
+        p.in_dim = nf->in_dim[i];
+        p.Bp = Bp;
+        p.dz_prev = i > 0 ? w.dz[i - 1] : nullptr;
+        p.dh0 = w.dh0;
+        p.gmax = w.gmax;
+        p.Pw = w.Pw[i];
+        p.Pb = w.Pb[i];
+        e = i > 0 ? launch_bwd<false>(p, w.bwd_grid, s) : launch_bwd<true>(p, w.bwd_grid, s);
     }
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_nf_reduce, dim3(grid_for(max_n, 256, 64), 2 * kLayers), dim3(256), 0, s, red);
+    // every layer's workgroup partials folded in workgroup order
+    NfReduce red{};
+    int32_t max_n = 0;
+    for (int i = 0; i < kLayers; ++i) {
+        const int32_t n = nf->out_dim[i] * nf->in_dim[i];
+        red.seg[2 * i] = NfSeg{w.Pw[i], nf->d_grads + nf->offW[i], n, w.bwd_grid};
+        red.seg[2 * i + 1] = NfSeg{w.Pb[i], nf->d_grads + nf->offb[i], nf->out_dim[i], w.bwd_grid};
+        max_n = std::max(max_n, n);
+    }
+    hipLaunchKernelGGL(k_nf_reduce, dim3(grid_for(max_n, 64, 1024), 2 * kLayers), dim3(256), 0, s, red);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     // grid-feature gradient: LDS partitions, then the ordered fold
