@@ -76,6 +76,32 @@ def test_batch_equals_single_and_oracle(ctx):
         m.close()
 
 
+def test_system_alone_equals_forty_copies_in_one_batch(ctx):
+    """One system alone (8 chunks of 256 rows) and 40 copies of it in one
+    batch (320 chunks, 40 instances sharing every launch) agree bit for bit in
+    results and iteration counts, with and without graph replay."""
+    v, f, u = W.cubesphere_ellipsoid(77, 3000)
+    g = torch.from_numpy(W.sh_neumann(u, 1, 77)).to(DEV)
+    k = [float(W.wavenumber(np.array([2500.0]))[0])]
+    N = 2048
+    qt, qb = W.random_face_queries(len(f), 300, 77)
+    qt, qb = torch.from_numpy(qt).to(DEV), torch.from_numpy(qb).to(DEV)
+    mesh = nat.Mesh(ctx, v, f)
+    for flags in (0, nat.NAT_MC_NO_GRAPH):
+        opts = nat.nat_mc_opts_default()
+        opts.flags = flags
+        p_alone, rep_alone = nat.nat_mcbem_estimate(mesh, g, k, qt, qb, N, 5, opts)
+        jobs = [nat.McJob(mesh, g, k, qt, qb, N, 5) for _ in range(40)]
+        reps = nat.nat_mcbem_estimate_batch(ctx, jobs, opts)
+        torch.cuda.synchronize()
+        _say(f"  flags {flags}: {rep_alone[0]['iters']} iterations")
+        assert rep_alone[0]["iters"] >= 5
+        for job, rep in zip(jobs, reps):
+            assert rep[0]["iters"] == rep_alone[0]["iters"]
+            assert torch.equal(job.p_out, p_alone)
+    mesh.close()
+
+
 def test_graph_replay_equals_direct_launches(ctx):
     # one mode of this batch is close to an interior resonance of the
     # conventional equation and stops at 200 iterations above 1e-6 (the FP64
