@@ -893,17 +893,15 @@ def run_neural(nat, torch, ctx, args, dev):
     bwd_in = 2 * (3 * H * H + H * 32 + H * n_out)
     wgrad = 2 * (D * H + 3 * H * H + H * n_out)
     flops_step = B * (fwd + bwd_in + wgrad)
-    # HBM bytes per row of the step as built (bfloat16 = 2 B): the encoding
-    # writes the input row (2 D) and reads the 5 FP32 inputs; the forward
-    # products read their inputs (2 D + 3 x 256) and write the 4 hidden
-    # activations (4 x 256); the output step reads A_4 (256) and the target
-    # and writes dZ_3 (256); each fused backward pass reads dZ_i and A_i and
-    # writes dZ_{i-1} (3 x 768), the first-layer pass reads dZ_0 and the input
-    # (256 + 2 D) and writes the 16 FP32 grid columns (64); the grid gradient
-    # reads the inputs and those columns (84).  The grid tables (1.6 MB) stay
-    # in L2.
-    per_row = 2 * D + 20 + (2 * D + 3 * 2 * H) + 4 * 2 * H + (2 * H + 4 + 2 * H) + 3 * 3 * 2 * H + \
-        (2 * H + 2 * D + 64) + 84
+    # HBM bytes per row of the step as built (bfloat16 = 2 B): the fused
+    # forward pass reads the 5 FP32 inputs and writes the input row (2 D) and
+    # the 4 hidden activations (4 x 256); the output step reads A_4 (256) and
+    # the target and writes dZ_3 (256); each fused backward pass reads dZ_i
+    # and A_i and writes dZ_{i-1} (3 x 768), the first-layer pass reads dZ_0
+    # and the input (256 + 2 D) and writes the 16 FP32 grid columns (64); the
+    # grid gradient reads the inputs and those columns (84).  The grid
+    # tables (1.6 MB) stay in L2.
+    per_row = 20 + 2 * D + 4 * 2 * H + (2 * H + 4 + 2 * H) + 3 * 3 * 2 * H + (2 * H + 2 * D + 64) + 84
     bytes_step = B * per_row
     tf = flops_step / t_step / 1e12
     bw = bytes_step / t_step / 1e9

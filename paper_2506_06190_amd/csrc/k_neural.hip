@@ -7,7 +7,10 @@
 // with zero inputs and zero loss weight.  Activations and back-propagated
 // gradients live in HBM in bfloat16, row-major [rows][width].  The products
 // run on the matrix cores (32x32x16 bfloat16 MFMA, FP32 accumulation):
-//   forward   Z_i  = A_i W_i^T + b_i, A_{i+1} = relu(Z_i)       (i = 0..3)
+//   forward   one fused pass over 128-row tiles: the encoding into LDS, then
+//             Z_i = A_i W_i^T + b_i, A_{i+1} = relu(Z_i) (i = 0..3) with the
+//             tile's activations kept in LDS, then y (inference) or the
+//             activations written out (training)
 //   backward  one fused pass per layer i = 3..0 over 128-row tiles:
 //             dH_i = dZ_i W_i, dZ_{i-1} = dH_i * [A_i > 0] (or the 16 grid
 //             columns of dH_0), and dW_i += dZ_i^T A_i, db_i += sums of dZ_i
@@ -34,7 +37,7 @@ constexpr int kPeFreqs = 6;
 constexpr int kHidden = 128;
 constexpr int kLayers = 5;  // 4 hidden + output
 constexpr int kRowTile = 128;   // rows per product tile (4 waves x 32)
-constexpr int kGemmGrid = 512;  // workgroups of a product launch (persistent)
+constexpr int kGemmGrid = 512;  // workgroups of a forward pass (persistent)
 constexpr int kTilePitch = kRowTile + 8;  // LDS pitch (bfloat16) of a 128-wide tile row
 constexpr int kMaxNv = 16;
 constexpr int kMaxOut = 32;
@@ -127,144 +130,187 @@ __device__ __forceinline__ void unit_coords(const NfDev& f, const float* row, fl
     u[2] = (row[2] - f.r_lo) * f.inv_span;
 }
 
-// Packs bfloat16 values of one row into 16-byte stores.
-struct RowWriter {
-    uint16_t* dst;
-    uint32_t buf[4] = {0, 0, 0, 0};
-    int n = 0;
-    __device__ void put(uint16_t h)
-    {
-        const int w = (n >> 1) & 3;
-        buf[w] = (n & 1) ? (buf[w] | (static_cast<uint32_t>(h) << 16)) : static_cast<uint32_t>(h);
-        if ((++n & 7) == 0) {
-            *reinterpret_cast<uint4*>(dst + n - 8) = make_uint4(buf[0], buf[1], buf[2], buf[3]);
-        }
-    }
+// Forward pass fused over 128-row tiles (persistent): the rows are encoded
+// into LDS, the four hidden layers run on the matrix cores with the tile's
+// activations kept in LDS (each wave rewrites its own 32 rows in place once
+// its operands are in registers; a layer's weights are staged once per
+// tile), and then either the output layer is applied (inference: y, two
+// half-row sums per output as in the training output step) or the input and
+// the four activations are written to HBM for the backward passes.  The
+// products are those of the unfused layers, so the values are the same.
+struct NfFwd {
+    NfDev f;
+    const float* in;
+    int32_t B, Bp;
+    const uint16_t* wb;          // bfloat16 weights, row-major, layer i at offWb[i]
+    int64_t offWb[kLayers];
+    const float* bias[kLayers];
+    uint16_t* X;                 // [Bp][D] (training) or null
+    uint16_t* H[4];              // [Bp][128] (training) or null
+    float* y;                    // [B][n_out] (inference) or null
 };
 
-// MLP input of each row: [G | P(v) | P(f) | 0], row-major.  Padding rows
-// are zero.
-__global__ void __launch_bounds__(256) k_nf_encode(NfDev f, const float* __restrict__ in, int32_t B, int32_t Bp,
-                                                   uint16_t* __restrict__ X)
-{
-    const int32_t b = blockIdx.x * 256 + threadIdx.x;
-    if (b >= Bp)
-        return;
-    RowWriter wr{X + (size_t)b * f.D};
-    int col = 0;
-    auto emit = [&](float v) {
-        const uint16_t h = to_bf16(v);
-        wr.put(h);
-        ++col;
-    };
-    if (b < B) {
-        const float* row = in + (size_t)b * f.ld_in;
-        float u[3];
-        unit_coords(f, row, u);
-        for (int l = 0; l < kLevels; ++l) {
-            Corners c;
-            cell_corners(u, l, c);
-            float acc[kFeat] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float4 g = *reinterpret_cast<const float4*>(f.grid[l] + (size_t)c.idx[e] * kFeat);
-                acc[0] = fmaf(c.w[e], g.x, acc[0]);
-                acc[1] = fmaf(c.w[e], g.y, acc[1]);
-                acc[2] = fmaf(c.w[e], g.z, acc[2]);
-                acc[3] = fmaf(c.w[e], g.w, acc[3]);
-            }
-            for (int q = 0; q < kFeat; ++q)
-                emit(acc[q]);
-        }
-        for (int s = 0; s <= f.n_v; ++s) {
-            const float x = row[3 + s];  // v_0 .. v_{n_v-1}, then f
-            for (int m = 0; m < kPeFreqs; ++m) {
-                float sn, cs;
-                sincospif(ldexpf(x, m), &sn, &cs);
-                emit(sn);
-                emit(cs);
-            }
-        }
-    }
-    while (col < f.D)
-        emit(0.0f);
-}
+__device__ __forceinline__ int fwd_pitch(int D) { return (D > kHidden ? D : kHidden) + 8; }
 
-// Forward product of a hidden layer: C = relu(A B^T + bias) with A [M][K]
-// (lda), B [N][K] (ldb), bfloat16, both contiguous along K; M a multiple of
-// 128, K of 16, N <= 32 NBLK; C stored in bfloat16, row-major.
-struct NfGemm {
-    const uint16_t* A;
-    int32_t lda;
-    const uint16_t* Bm;
-    int32_t ldb;
-    int32_t M, N, K;
-    const float* bias;
-    uint16_t* C;
-    int32_t ldc;
-};
-
-// Each workgroup stages B in LDS once (rows padded by 16 bytes) and walks
-// row tiles of 128 (persistent); wave w computes rows 32 w .. 32 w + 31 of
-// the tile against all N columns, with the loads of up to 8 K steps of its
-// A rows issued before their products.  MFMA 32x32x16 operand layout: lane
-// l holds row (or column) l mod 32 and K entries 8 (l / 32) .. 8 (l / 32) + 7
-// of the step; accumulator entry i of lane l is row 8 (i / 4) + 4 (l / 32) +
-// i mod 4, column l mod 32.
-template <int NBLK>
-__global__ void __launch_bounds__(256) k_nf_gemm(NfGemm g)
+template <int KS>  // K steps of 16 held in registers: max(D, 128) / 16
+__global__ void __launch_bounds__(256) k_nf_fwd(NfFwd p)
 {
     extern __shared__ uint4 s_raw[];
-    uint16_t* sB = reinterpret_cast<uint16_t*>(s_raw);
+    const NfDev& f = p.f;
+    const int D = f.D;
+    const int pitch = fwd_pitch(D);
+    uint16_t* sAct = reinterpret_cast<uint16_t*>(s_raw);  // [128][pitch]
+    uint16_t* sW = sAct + kRowTile * pitch;               // [128][pitch]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int K = g.K, ldsb = K + 8;
-    const int k8 = K / 8;
-    for (int e = tid; e < NBLK * 32 * k8; e += 256) {
-        const int r = e / k8, c = e - r * k8;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (r < g.N)
-            v = *reinterpret_cast<const uint4*>(g.Bm + (size_t)r * g.ldb + c * 8);
-        *reinterpret_cast<uint4*>(sB + r * ldsb + c * 8) = v;
-    }
-    __syncthreads();
     const int half = lane >> 5, l32 = lane & 31;
-    const int n_tiles = g.M / kRowTile;
+    const int n_tiles = p.Bp / kRowTile;
     for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int row0 = tile * kRowTile + wave * 32;
-        f32x16 acc[NBLK];
+        const int b0 = tile * kRowTile;
+        __syncthreads();
+        // encode: threads 0..127 the grid features of row tid, threads
+        // 128..255 the positional encodings and the padding of row tid - 128
+        {
+            const int r = tid & (kRowTile - 1);
+            const int b = b0 + r;
+            uint16_t* dst = sAct + r * pitch;
+            const bool live = b < p.B;
+            const float* row = p.in + (size_t)(live ? b : 0) * f.ld_in;
+            if (tid < kRowTile) {
+                float u[3];
+                unit_coords(f, row, u);
+                for (int l = 0; l < kLevels; ++l) {
+                    float acc[kFeat] = {0.0f, 0.0f, 0.0f, 0.0f};
+                    if (live) {
+                        Corners c;
+                        cell_corners(u, l, c);
 #pragma unroll
-        for (int nb = 0; nb < NBLK; ++nb)
-            acc[nb] = f32x16{};
-        const uint16_t* ap = g.A + (size_t)(row0 + l32) * g.lda + half * 8;
-        const uint16_t* bp = sB + l32 * ldsb + half * 8;
-        for (int kc = 0; kc < K; kc += 128) {
-            const int ns = min(8, (K - kc) >> 4);
-            bf16x8 a[8];
+                        for (int e = 0; e < 8; ++e) {
+                            const float4 gq = *reinterpret_cast<const float4*>(f.grid[l] + (size_t)c.idx[e] * kFeat);
+                            acc[0] = fmaf(c.w[e], gq.x, acc[0]);
+                            acc[1] = fmaf(c.w[e], gq.y, acc[1]);
+                            acc[2] = fmaf(c.w[e], gq.z, acc[2]);
+                            acc[3] = fmaf(c.w[e], gq.w, acc[3]);
+                        }
+                    }
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (j < ns)
-                    a[j] = load8(ap + kc + 16 * j);
+                    for (int q = 0; q < kFeat; ++q)
+                        dst[l * kFeat + q] = to_bf16(acc[q]);
+                }
+            } else {
+                int col = kLevels * kFeat;
+                for (int sv = 0; sv <= f.n_v; ++sv) {
+                    const float x = live ? row[3 + sv] : 0.0f;  // v_0 .. v_{n_v-1}, then f
+                    for (int m = 0; m < kPeFreqs; ++m) {
+                        float sn, cs;
+                        sincospif(ldexpf(x, m), &sn, &cs);
+                        dst[col++] = to_bf16(live ? sn : 0.0f);
+                        dst[col++] = to_bf16(live ? cs : 0.0f);
+                    }
+                }
+                for (; col < D; ++col)
+                    dst[col] = 0;
+            }
+        }
+        __syncthreads();
+        if (p.X) {
+            const int d8 = D / 8;
+            for (int task = tid; task < kRowTile * d8; task += 256) {
+                const int r = task / d8, c = task - r * d8;
+                const uint16_t* src = sAct + r * pitch + c * 8;
+                uint4 v;
+                v.x = src[0] | (static_cast<uint32_t>(src[1]) << 16);
+                v.y = src[2] | (static_cast<uint32_t>(src[3]) << 16);
+                v.z = src[4] | (static_cast<uint32_t>(src[5]) << 16);
+                v.w = src[6] | (static_cast<uint32_t>(src[7]) << 16);
+                *reinterpret_cast<uint4*>(p.X + (size_t)(b0 + r) * D + c * 8) = v;
+            }
+        }
+        for (int i = 0; i < 4; ++i) {
+            const int K = i == 0 ? D : kHidden;
+            const int k8 = K / 8;
+            __syncthreads();  // the previous layer's weights are no longer read
+            const uint16_t* W = p.wb + p.offWb[i];
+            for (int e = tid; e < kHidden * k8; e += 256) {
+                const int r = e / k8, c = e - r * k8;
+                const uint4 v = *reinterpret_cast<const uint4*>(W + (size_t)r * K + c * 8);
+                uint32_t* d = reinterpret_cast<uint32_t*>(sW + r * pitch + c * 8);
+                d[0] = v.x;
+                d[1] = v.y;
+                d[2] = v.z;
+                d[3] = v.w;
+            }
+            __syncthreads();
+            // the wave's A rows for every K step, then the products
+            bf16x8 a[KS];
+            const uint16_t* ar = sAct + (wave * 32 + l32) * pitch + half * 8;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (j < ns) {
+            for (int ks = 0; ks < KS; ++ks)
+                if (ks * 16 < K)
+                    a[ks] = *reinterpret_cast<const bf16x8*>(ar + ks * 16);
+            f32x16 acc[kHidden / 32];
 #pragma unroll
-                    for (int nb = 0; nb < NBLK; ++nb) {
-                        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(bp + nb * 32 * ldsb + kc + 16 * j);
-                        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[j], bv, acc[nb], 0, 0, 0);
+            for (int nb = 0; nb < kHidden / 32; ++nb)
+                acc[nb] = f32x16{};
+            const uint16_t* bp = sW + l32 * pitch + half * 8;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                if (ks * 16 < K) {
+#pragma unroll
+                    for (int nb = 0; nb < kHidden / 32; ++nb) {
+                        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(bp + nb * 32 * pitch + ks * 16);
+                        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], bv, acc[nb], 0, 0, 0);
                     }
                 }
             }
+            // relu(Z + b) into the wave's own rows (its loads are complete:
+            // the stores depend on every product)
+            const float* bias = p.bias[i];
+#pragma unroll
+            for (int nb = 0; nb < kHidden / 32; ++nb) {
+                const int col = nb * 32 + l32;
+                const float bc = bias[col];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int r = wave * 32 + 8 * (q / 4) + 4 * half + (q % 4);
+                    sAct[r * pitch + col] = to_bf16(fmaxf(acc[nb][q] + bc, 0.0f));
+                }
+            }
+            if (p.H[i]) {
+                __syncthreads();
+                for (int task = tid; task < kRowTile * (kHidden / 8); task += 256) {
+                    const int r = task >> 4, c = task & 15;
+                    const uint16_t* src = sAct + r * pitch + c * 8;
+                    uint4 v;
+                    v.x = src[0] | (static_cast<uint32_t>(src[1]) << 16);
+                    v.y = src[2] | (static_cast<uint32_t>(src[3]) << 16);
+                    v.z = src[4] | (static_cast<uint32_t>(src[5]) << 16);
+                    v.w = src[6] | (static_cast<uint32_t>(src[7]) << 16);
+                    *reinterpret_cast<uint4*>(p.H[i] + (size_t)(b0 + r) * kHidden + c * 8) = v;
+                }
+            }
         }
-#pragma unroll
-        for (int nb = 0; nb < NBLK; ++nb) {
-            const int col = nb * 32 + l32;
-            if (col >= g.N)
-                continue;
-            const float bias = g.bias[col];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int row = row0 + 8 * (i / 4) + 4 * half + (i % 4);
-                g.C[(size_t)row * g.ldc + col] = to_bf16(fmaxf(acc[nb][i] + bias, 0.0f));
+        if (p.y) {
+            // output layer: W_4 as floats into the weight area, two half-row
+            // sums per (row, output)
+            const int nO = f.n_out;
+            float* sW4 = reinterpret_cast<float*>(sW);
+            __syncthreads();
+            const uint16_t* W4 = p.wb + p.offWb[4];
+            for (int e = tid; e < nO * kHidden; e += 256)
+                sW4[e] = from_bf16(W4[e]);
+            __syncthreads();
+            const int r = tid >> 1, hf = tid & 1;
+            const int row = b0 + r;
+            for (int oi = 0; oi < nO; ++oi) {
+                float part = 0.0f;
+                const uint16_t* hr = sAct + r * pitch + hf * 64;
+                const float* wr = sW4 + oi * kHidden + hf * 64;
+#pragma unroll 8
+                for (int k = 0; k < 64; ++k)
+                    part = fmaf(from_bf16(hr[k]), wr[k], part);
+                part += __shfl_xor(part, 1, 64);
+                if (hf == 0 && row < p.B)
+                    p.y[(size_t)row * nO + oi] = part + p.bias[4][oi];
             }
         }
     }
@@ -906,63 +952,58 @@ NfDev nf_dev(const nat_nf* nf)
     return f;
 }
 
-hipError_t launch_gemm(const NfGemm& g, hipStream_t s)
-{
-    const int nblk = (g.N + 31) / 32;
-    const size_t lds = static_cast<size_t>(nblk) * 32 * (g.K + 8) * sizeof(uint16_t);
-    // persistent: B is staged once per workgroup
-    const int grid = std::min(g.M / kRowTile, kGemmGrid);
-    switch (nblk) {
-    case 1: hipLaunchKernelGGL(k_nf_gemm<1>, dim3(grid), dim3(256), lds, s, g); break;
-    case 2: hipLaunchKernelGGL(k_nf_gemm<2>, dim3(grid), dim3(256), lds, s, g); break;
-    case 3: hipLaunchKernelGGL(k_nf_gemm<3>, dim3(grid), dim3(256), lds, s, g); break;
-    case 4: hipLaunchKernelGGL(k_nf_gemm<4>, dim3(grid), dim3(256), lds, s, g); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
 // Forward pass of B rows (padded to Bp); with `train` the output kernel also
 // forms the loss, dZ_3 and the partials of dW_4, db_4.
 hipError_t nf_forward(nat_nf* nf, const NfWs& w, const float* in, const float* target, int32_t B, int32_t Bp,
                       float* y, bool train, hipStream_t s)
 {
-    const NfDev f = nf_dev(nf);
-    hipLaunchKernelGGL(k_nf_encode, dim3((Bp + 255) / 256), dim3(256), 0, s, f, in, B, Bp, w.X);
-    hipError_t e = hipGetLastError();
-    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
-        NfGemm g{};
-        g.A = i == 0 ? w.X : w.H[i - 1];
-        g.lda = i == 0 ? nf->D : kHidden;
-        g.Bm = nf->d_wb + nf->offWb[i];
-        g.ldb = nf->in_dim[i];
-        g.M = Bp;
-        g.N = kHidden;
-        g.K = nf->in_dim[i];
-        g.bias = nf->d_params + nf->offb[i];
-        g.C = w.H[i];
-        g.ldc = kHidden;
-        e = launch_gemm(g, s);
+    NfFwd p{};
+    p.f = nf_dev(nf);
+    p.in = in;
+    p.B = B;
+    p.Bp = Bp;
+    p.wb = nf->d_wb;
+    for (int i = 0; i < kLayers; ++i) {
+        p.offWb[i] = nf->offWb[i];
+        p.bias[i] = nf->d_params + nf->offb[i];
     }
-    if (e != hipSuccess)
+    p.X = train ? w.X : nullptr;
+    for (int i = 0; i < 4; ++i)
+        p.H[i] = train ? w.H[i] : nullptr;
+    p.y = train ? nullptr : y;
+    const int kmax = std::max(nf->D, kHidden);
+    const size_t lds = sizeof(uint16_t) * 2 * kRowTile * (size_t)(kmax + 8);
+    const int grid = std::min(Bp / kRowTile, kGemmGrid);
+    switch (kmax / 16) {
+    case 8: hipLaunchKernelGGL(k_nf_fwd<8>, dim3(grid), dim3(256), lds, s, p); break;
+    case 9: hipLaunchKernelGGL(k_nf_fwd<9>, dim3(grid), dim3(256), lds, s, p); break;
+    case 10: hipLaunchKernelGGL(k_nf_fwd<10>, dim3(grid), dim3(256), lds, s, p); break;
+    case 11: hipLaunchKernelGGL(k_nf_fwd<11>, dim3(grid), dim3(256), lds, s, p); break;
+    case 12: hipLaunchKernelGGL(k_nf_fwd<12>, dim3(grid), dim3(256), lds, s, p); break;
+    case 13: hipLaunchKernelGGL(k_nf_fwd<13>, dim3(grid), dim3(256), lds, s, p); break;
+    case 14: hipLaunchKernelGGL(k_nf_fwd<14>, dim3(grid), dim3(256), lds, s, p); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !train)
         return e;
     NfOut o{};
     o.H = w.H[3];
     o.W = nf->d_wb + nf->offWb[4];
     o.b = nf->d_params + nf->offb[4];
-    o.target = train ? target : nullptr;
-    o.y = y;
+    o.target = target;
+    o.y = nullptr;
     o.B = B;
     o.Bp = Bp;
     o.n_out = nf->n_out;
     o.scale = static_cast<float>(2.0 / (static_cast<double>(B) * nf->n_out));
-    o.dz3 = train ? w.dz[3] : nullptr;
+    o.dz3 = w.dz[3];
     o.Pw4 = w.Pw[4];
     o.Pb4 = w.Pb[4];
-    o.loss_part = train ? w.loss_part : nullptr;
+    o.loss_part = w.loss_part;
     hipLaunchKernelGGL(k_nf_out, dim3(w.bwd_grid), dim3(256), 0, s, o);
     e = hipGetLastError();
-    if (e == hipSuccess && train) {
+    if (e == hipSuccess) {
         hipLaunchKernelGGL(k_nf_sum, dim3(1), dim3(256), 0, s, w.loss_part, w.bwd_grid, w.loss);
         e = hipGetLastError();
     }
