@@ -90,7 +90,8 @@ def dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-@pytest.mark.parametrize("n_v,n_out,B", [(0, 1, 1), (0, 1, 300), (2, 3, 1000), (1, 1, 4096)])
+@pytest.mark.parametrize("n_v,n_out,B", [(0, 1, 1), (0, 1, 300), (2, 3, 1000), (1, 1, 4096), (9, 2, 700),
+                                         (16, 1, 513)])
 def test_infer_matches_oracle(env, n_v, n_out, B):
     nat, ctx, torch = env
     p = oracle_params(n_v, n_out, 10 + B)
@@ -104,8 +105,9 @@ def test_infer_matches_oracle(env, n_v, n_out, B):
     nf.close()
 
 
-@pytest.mark.parametrize("n_v,n_out,B", [(0, 1, 300), (2, 3, 1000), (1, 1, 2048)])
+@pytest.mark.parametrize("n_v,n_out,B", [(0, 1, 300), (2, 3, 1000), (1, 1, 2048), (9, 2, 700), (16, 1, 513)])
 def test_loss_and_gradients_match_oracle(env, n_v, n_out, B):
+    # input widths 32, 64, 48, 144 and 224: every block count of the products
     nat, ctx, torch = env
     p = oracle_params(n_v, n_out, 30 + B)
     (th, ph, r, v, f), tgt, rows = make_rows(B, n_v, n_out, 40 + B)
