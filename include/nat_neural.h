@@ -95,7 +95,8 @@ nat_status nat_nf_loss_grad(nat_nf* nf, const float* inputs, const float* target
 nat_status nat_nf_train_step(nat_nf* nf, const float* inputs, const float* targets, int32_t B,
                              int32_t step, int32_t total_steps, double* loss, void* stream);
 
-/* Field values out [B][n_out] (device, FP32) at B input rows. */
+/* Field values out [B][n_out] (device, FP32) at B input rows.  Allocates
+ * nothing: the whole forward pass runs in on-chip memory. */
 nat_status nat_nf_infer(nat_nf* nf, const float* inputs, int32_t B, float* out, void* stream);
 
 #ifdef __cplusplus

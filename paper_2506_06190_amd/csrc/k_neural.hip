@@ -1351,10 +1351,9 @@ nat_status nat_nf_infer(nat_nf* nf, const float* inputs, int32_t B, float* out, 
         return st;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const int32_t Bp = (B + nat::kRowTile - 1) / nat::kRowTile * nat::kRowTile;
-    nat::NfWs w{};
-    if ((st = nat::nf_workspace(nf, Bp, &w)) != NAT_OK)
-        return st;
-    NAT_HIP(nat::nf_forward(nf, w, inputs, nullptr, B, Bp, out, false, s));
+    // the fused forward pass keeps everything in LDS: no workspace
+    const nat::NfWs none{};
+    NAT_HIP(nat::nf_forward(nf, none, inputs, nullptr, B, Bp, out, false, s));
     return NAT_OK;
 }
 

@@ -238,6 +238,21 @@ def test_full_batch_sampled_rows(env):
     nf.close()
 
 
+def test_inference_allocates_nothing(env):
+    """Inference runs entirely in on-chip memory: the context's charged
+    bytes do not move, however large the batch."""
+    nat, ctx, torch = env
+    nf = nat.NeuralField(ctx, 1, 1, R_LO, R_HI, seed=2)
+    _, _, rows = make_rows(100000, 1, 1, 3)
+    x = dev(torch, rows)
+    out = torch.empty((100000, 1), dtype=torch.float32, device="cuda")
+    before = ctx.bytes_in_use()
+    nf.infer(x, out=out)
+    torch.cuda.synchronize()
+    assert ctx.bytes_in_use() == before and torch.isfinite(out).all()
+    nf.close()
+
+
 def test_neural_field_errors(env):
     nat, ctx, torch = env
     with pytest.raises(nat.NatError):
