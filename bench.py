@@ -900,6 +900,8 @@ def train_on_scene_tuples(nat, torch, ctx, dev, wls, coords, fabs, steps=3000, b
             "loss_first": first, "loss_last": last, "held_out_rel_rms_error_abs_p": round(err, 4),
             "target_rms": scale}
 
+
+def run_neural(nat, torch, ctx, args, dev):
     """Neural-field training and inference (Sections 3.2-3.4): one condition
     variable and the frequency, |p| as the one output, synthetic training
     rows of the paper's shell (directions uniform, 1.5-3 R) with a smooth
