@@ -59,6 +59,10 @@ constexpr int kGridFloats = level_base(kLevels);
 constexpr int kGridPart = 4608 * kFeat;  // 144 KB of 64-bit accumulators
 constexpr int kGridParts = (kGridFloats + kGridPart - 1) / kGridPart;
 constexpr int kGridGroupsMax = 21;       // row groups per partition
+// Threads of a partition workgroup: the accumulators fill the LDS, so one
+// workgroup runs per CU, and 16 waves keep its loads and atomics in flight
+// (286 us with 4 waves, 207 us with 16, for 2^18 rows).
+constexpr int kGridThreads = 1024;
 static_assert(kGridPart % kFeat == 0, "partitions hold whole vertices");
 
 __device__ __forceinline__ uint16_t to_bf16(float x)
@@ -700,23 +704,24 @@ __device__ __forceinline__ double grid_scale(float gmax, int32_t B)
 // The largest of the n per-workgroup maxima (every thread of the block).
 __device__ float block_max(const float* __restrict__ m, int32_t n)
 {
-    __shared__ float s[256];
+    __shared__ float s[16];
     float a = 0.0f;
-    for (int i = threadIdx.x; i < n; i += 256)
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
         a = fmaxf(a, m[i]);
-    s[threadIdx.x] = a;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        a = fmaxf(a, __shfl_xor(a, off, 64));
+    if ((threadIdx.x & 63) == 0)
+        s[threadIdx.x >> 6] = a;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h)
-            s[threadIdx.x] = fmaxf(s[threadIdx.x], s[threadIdx.x + h]);
-        __syncthreads();
-    }
-    const float r = s[0];
+    float r = 0.0f;
+    for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w)
+        r = fmaxf(r, s[w]);
     __syncthreads();
     return r;
 }
 
-__global__ void __launch_bounds__(256) k_nf_grid_part(NfDev f, const float* __restrict__ in, int32_t B,
+__global__ void __launch_bounds__(kGridThreads) k_nf_grid_part(NfDev f, const float* __restrict__ in, int32_t B,
                                                       const float* __restrict__ dh0, const float* gmax,
                                                       int32_t n_gmax, long long* __restrict__ part, int32_t G)
 {
@@ -725,10 +730,10 @@ __global__ void __launch_bounds__(256) k_nf_grid_part(NfDev f, const float* __re
     const int lo = p * kGridPart;
     const int n = min(kGridPart, kGridFloats - lo);
     const double S = grid_scale(block_max(gmax, n_gmax), B);
-    for (int e = threadIdx.x; e < n; e += 256)
+    for (int e = threadIdx.x; e < n; e += kGridThreads)
         s_acc[e] = 0ull;
     __syncthreads();
-    for (int32_t b = g * 256 + threadIdx.x; b < B; b += G * 256) {
+    for (int32_t b = g * kGridThreads + threadIdx.x; b < B; b += G * kGridThreads) {
         const float* row = in + (size_t)b * f.ld_in;
         float u[3];
         unit_coords(f, row, u);
@@ -755,7 +760,7 @@ __global__ void __launch_bounds__(256) k_nf_grid_part(NfDev f, const float* __re
     }
     __syncthreads();
     long long* dst = part + (size_t)g * kGridFloats + lo;
-    for (int e = threadIdx.x; e < n; e += 256)
+    for (int e = threadIdx.x; e < n; e += kGridThreads)
         dst[e] = static_cast<long long>(s_acc[e]);
 }
 
@@ -1062,8 +1067,8 @@ hipError_t nf_backward(nat_nf* nf, const NfWs& w, const float* in, int32_t B, in
     // grid-feature gradient: LDS partitions, then the ordered fold
     const NfDev f = nf_dev(nf);
     const int32_t G = w.grid_groups;
-    hipLaunchKernelGGL(k_nf_grid_part, dim3(kGridParts * G), dim3(256), 0, s, f, in, B, w.dh0, w.gmax, w.n_gmax,
-                       w.gpart, G);
+    hipLaunchKernelGGL(k_nf_grid_part, dim3(kGridParts * G), dim3(kGridThreads), 0, s, f, in, B, w.dh0, w.gmax,
+                       w.n_gmax, w.gpart, G);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_nf_grid_fold, dim3(grid_for(kGridFloats, 256, 512)), dim3(256), 0, s, w.gpart, G, B,
