@@ -766,6 +766,97 @@ def run_field(nat, torch, ctx, args, dev):
     return out
 
 
+def run_poisson(nat, torch, ctx, args, dev):
+    """Poisson-disk sample sets (Section 4.2, parallel Poisson-disk sampling;
+    Section 6.1: Poisson-disk samples beat independent ones at the same N):
+    the sampler's time per set on the precision workload's 20480-triangle
+    ellipsoid and on a 40k-triangle cube-sphere at N = 1024-10240 (the
+    paper's 1K-10K), the precision-form estimate with Poisson-disk samples
+    against independent ones, and (with the oracle) the sets checked bit for
+    bit, the oracle's time for the same sets and the estimate's error
+    against the closed-form spheres both ways."""
+    import numpy as np
+    import workloads as W
+    wl = W.config_precision()
+    cube = W.cubesphere_ellipsoid(9, 40000)
+    meshes = [("ellipsoid 20480 tri", wl.vertices, wl.tris), (f"cube-sphere {len(cube[1])} tri", cube[0], cube[1])]
+    reps = max(args.steps, 10)
+    sets = []
+    handles = []
+    for name, v, f in meshes:
+        mesh = nat.Mesh(ctx, v, f)
+        handles.append(mesh)
+        for N in (1024, 4096, 10240):
+            tri = torch.empty(N, dtype=torch.int32, device=dev)
+            bary = torch.empty((N, 2), dtype=torch.float64, device=dev)
+            nat.nat_mcbem_poisson_samples(mesh, N, wl.seed, tri, bary)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for r in range(reps):
+                _, _, n_acc = nat.nat_mcbem_poisson_samples(mesh, N, wl.seed + r, tri, bary)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+            sets.append({"mesh": name, "N": N, "ms_per_set": round(1e3 * t, 4), "samples_per_s": N / t,
+                         "accepted": n_acc, "candidates": 16 * N})
+    out = {"workload": "Poisson-disk sample sets: 20480-triangle ellipsoid and 40k-triangle cube-sphere, "
+                       "N 1024 / 4096 / 10240, candidate pool 16 N",
+           "sets": sets}
+    # the precision-form estimate with independent and with Poisson-disk samples
+    g = torch.from_numpy(wl.g).to(dev)
+    qt, qb = torch.from_numpy(wl.q_tri).to(dev), torch.from_numpy(wl.q_b).to(dev)
+    est = {}
+    for label, flags in (("independent", 0), ("poisson", nat.NAT_MC_POISSON)):
+        opts = nat.nat_mc_opts_default()
+        opts.flags = flags
+        nat.nat_mcbem_estimate(handles[0], g, wl.k, qt, qb, wl.n_samples, wl.seed, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            nat.nat_mcbem_estimate(handles[0], g, wl.k, qt, qb, wl.n_samples, wl.seed, opts)
+        torch.cuda.synchronize()
+        est[label] = round(1e3 * (time.perf_counter() - t0) / reps, 4)
+    out["precision_form_estimate_ms"] = est
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        from oracle import closed_forms as CF
+        N = 1024
+        tri, bary, n_acc = nat.nat_mcbem_poisson_samples(handles[0], N, wl.seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_o, b_o, n_o = O.poisson_samples(wl.vertices, wl.tris, N, wl.seed)
+        t_cpu = time.perf_counter() - t0
+        out["vs_oracle"] = {"set": "ellipsoid, N 1024", "bit_exact": bool(
+            n_acc == n_o and np.array_equal(tri.cpu().numpy(), t_o) and np.array_equal(bary.cpu().numpy(), b_o))}
+        out["cpu_oracle"] = {"ms_per_set": round(1e3 * t_cpu, 3), "cores": 1, "kind": "oracle",
+                             "sample": "ellipsoid 20480 tri, N 1024"}
+        # error against the closed forms, FP32 GPU estimates, independent vs Poisson-disk samples
+        acc = {}
+        cases = [("pulsating sphere, ico3, k a = 2", W.config_pulsating_sphere(),
+                  lambda w: np.full(w.n_queries, CF.pulsating_sphere(2.0, 1.0)), 4),
+                 ("oscillating sphere, ico4, k a = 5", W.config_oscillating_sphere(ka=(5.0,)),
+                  lambda w: CF.oscillating_sphere_factor(w.k[0], 0.1) * w.extra["u"][:, 2], 4)]
+        for name, w, exact_of, n_seeds in cases:
+            m = nat.Mesh(ctx, w.vertices, w.tris)
+            ex = exact_of(w)
+            gw = torch.from_numpy(w.g).to(dev)
+            qtw, qbw = torch.from_numpy(w.q_tri).to(dev), torch.from_numpy(w.q_b).to(dev)
+            row = {}
+            for label, flags in (("independent", 0), ("poisson", nat.NAT_MC_POISSON)):
+                opts = nat.nat_mc_opts_default()
+                opts.flags = flags
+                errs = []
+                for sd in range(n_seeds):
+                    p, _ = nat.nat_mcbem_estimate(m, gw, w.k, qtw, qbw, 1024, 300 + sd, opts)
+                    errs.append(float(np.linalg.norm(p[0].cpu().numpy() - ex) / np.linalg.norm(ex)))
+                row[label] = round(float(np.mean(errs)), 4)
+            acc[name] = row
+            m.close()
+        out["rel_error_vs_closed_form_N1024_mean_of_4_seeds"] = acc
+    for m in handles:
+        m.close()
+    return out
+
+
 def run_scenes(nat, torch, ctx, args, dev):
     """Training-data generation for a family of scenes (Section 3.4): 16
     speaker-torus scenes (a speaker patch with g = 1 moving along the axis of
@@ -1067,7 +1158,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["batched", "precision", "served", "dense", "field", "scenes", "neural"],
+    ap.add_argument("--workload", choices=["batched", "precision", "served", "dense", "field", "scenes", "neural",
+                                           "poisson"],
                     default="batched")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--pmc-pass", action="store_true")
@@ -1140,6 +1232,7 @@ def main():
         out["field"] = run_field(nat, torch, ctx, args, dev)
         out["scenes"] = run_scenes(nat, torch, ctx, args, dev)
         out["neural"] = run_neural(nat, torch, ctx, args, dev)
+        out["poisson"] = run_poisson(nat, torch, ctx, args, dev)
         if not args.no_serve:
             out["served"] = run_served(nat, torch, ctx, args, dev)
     elif args.workload == "served":
@@ -1174,6 +1267,16 @@ def main():
         out["dtype"] = "bf16"
         out["config"] = {"workload": res["workload"]}
         out["neural"] = res
+    elif args.workload == "poisson":
+        res = run_poisson(nat, torch, ctx, args, dev)
+        out["metric"] = "Poisson-disk samples/s"
+        out["unit"] = "samples/s"
+        big = res["sets"][2]
+        out["value"] = big["samples_per_s"]
+        out["ms_per_step"] = big["ms_per_set"]
+        out["dtype"] = "f64"
+        out["config"] = {"workload": res["workload"]}
+        out["poisson"] = res
     elif args.workload == "field":
         res = run_field(nat, torch, ctx, args, dev)
         out["metric"] = "exterior field pair-evals/s"

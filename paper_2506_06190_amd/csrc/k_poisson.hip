@@ -31,6 +31,7 @@ namespace {
 
 constexpr int kPhases = 27;
 constexpr int64_t kTagNone = 0x7fff;  // sorts after every real tag
+constexpr int32_t kPdMaxPasses = static_cast<int32_t>((kTagNone - 1) / kPhases);  // tags stay below kTagNone
 
 __device__ __forceinline__ uint64_t pd_mix64(uint64_t z)
 {
@@ -137,37 +138,80 @@ __global__ void __launch_bounds__(256) k_pd_cells(const PdInst* __restrict__ ins
     atomicMax(&stats[kPhases], count[c]);
 }
 
-__device__ __forceinline__ int32_t pd_find(const uint64_t* __restrict__ ukey, int32_t n, uint64_t key)
+// Cell lookup: an open-addressing table (linear probing, load factor at most
+// one half) from a cell key to the cell's index among the occupied cells.
+// Which slot a key lands in depends on the insertion order, but every lookup
+// returns the same index, so the decisions do not.
+constexpr uint64_t kPdEmpty = ~uint64_t(0);
+
+__device__ __forceinline__ uint32_t pd_slot(uint64_t key, uint32_t mask)
 {
-    int32_t lo = 0, hi = n - 1;
-    while (lo <= hi) {
-        const int32_t mid = lo + ((hi - lo) >> 1);
-        const uint64_t v = ukey[mid];
-        if (v == key)
-            return mid;
-        if (v < key)
-            lo = mid + 1;
-        else
-            hi = mid - 1;
+    return static_cast<uint32_t>(pd_mix64(key)) & mask;
+}
+
+__global__ void __launch_bounds__(256) k_pd_table_clear(uint64_t* __restrict__ tkey, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        tkey[i] = kPdEmpty;
+}
+
+__global__ void __launch_bounds__(256) k_pd_table_fill(const uint64_t* __restrict__ ukey,
+                                                       const int32_t* __restrict__ n_cells,
+                                                       uint64_t* __restrict__ tkey, int32_t* __restrict__ tval,
+                                                       uint32_t mask)
+{
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= *n_cells)
+        return;
+    const uint64_t k = ukey[c];
+    uint32_t h = pd_slot(k, mask);
+    // the table has at least twice as many slots as keys, so a free slot exists
+    while (true) {
+        const unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long*>(tkey + h),
+                                                  static_cast<unsigned long long>(kPdEmpty),
+                                                  static_cast<unsigned long long>(k));
+        if (prev == static_cast<unsigned long long>(kPdEmpty)) {
+            tval[h] = c;
+            return;
+        }
+        h = (h + 1) & mask;
     }
-    return -1;
+}
+
+__device__ __forceinline__ int32_t pd_lookup(const uint64_t* __restrict__ tkey, const int32_t* __restrict__ tval,
+                                             uint32_t mask, uint64_t key)
+{
+    uint32_t h = pd_slot(key, mask);
+    while (true) {
+        const uint64_t v = tkey[h];
+        if (v == key)
+            return tval[h];
+        if (v == kPdEmpty)
+            return -1;
+        h = (h + 1) & mask;
+    }
 }
 
 // Pass p of phase ph: every cell of the phase without an accepted point
-// tries its p-th candidate.  Cells of one phase are more than r apart, so
-// none reads what another writes in the same launch.
+// tries its p-th candidate; one wave per cell, each lane checking two of
+// the 125 cells around it.  Cells of one phase are more than r apart, so
+// none reads what another writes in the same launch.  A rejected candidate
+// of a cell with candidates left sets more[p].
 __global__ void __launch_bounds__(256) k_pd_try(const PdInst* __restrict__ inst,
                                                 const uint64_t* __restrict__ ukey,
-                                                const int32_t* __restrict__ n_cells,
                                                 const int32_t* __restrict__ start,
                                                 const int32_t* __restrict__ count,
                                                 const int32_t* __restrict__ sorted_idx,
                                                 const int32_t* __restrict__ phase_cells,
                                                 int32_t first, int32_t n_phase, int32_t p, int32_t ph,
                                                 const double* __restrict__ cxyz,
-                                                int32_t* __restrict__ acc, int32_t* __restrict__ tag)
+                                                const uint64_t* __restrict__ tkey,
+                                                const int32_t* __restrict__ tval, uint32_t mask,
+                                                int32_t* __restrict__ acc, int32_t* __restrict__ tag,
+                                                int32_t* __restrict__ more)
 {
-    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t t = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (t >= n_phase)
         return;
     const int32_t c = phase_cells[first + t];
@@ -181,36 +225,36 @@ __global__ void __launch_bounds__(256) k_pd_try(const PdInst* __restrict__ inst,
     cell_coords(k, I, cc);
     const double x0 = cxyz[3 * (int64_t)cand], x1 = cxyz[3 * (int64_t)cand + 1],
                  x2 = cxyz[3 * (int64_t)cand + 2];
-    const int32_t nc = *n_cells;
-    for (int dx = -2; dx <= 2; ++dx) {
-        const int64_t nx = cc[0] + dx;
-        if (nx < 0 || nx >= I.dim[0])
+    bool close = false;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = lane + 64 * h;  // neighbour (dx, dy, dz) = (q / 25, q / 5 % 5, q % 5) - 2
+        if (q >= 125)
             continue;
-        for (int dy = -2; dy <= 2; ++dy) {
-            const int64_t ny = cc[1] + dy;
-            if (ny < 0 || ny >= I.dim[1])
-                continue;
-            for (int dz = -2; dz <= 2; ++dz) {
-                const int64_t nz = cc[2] + dz;
-                if (nz < 0 || nz >= I.dim[2])
-                    continue;
-                const int32_t n = pd_find(ukey, nc, ibits | static_cast<uint64_t>((nx * I.dim[1] + ny) * I.dim[2] + nz));
-                if (n < 0)
-                    continue;
-                const int32_t a = acc[n];
-                if (a < 0)
-                    continue;
-                const double ex = x0 - cxyz[3 * (int64_t)a];
-                const double ey = x1 - cxyz[3 * (int64_t)a + 1];
-                const double ez = x2 - cxyz[3 * (int64_t)a + 2];
-                const double d2 = ex * ex + ey * ey + ez * ez;
-                if (d2 < I.r2)
-                    return;
-            }
-        }
+        const int64_t nx = cc[0] + q / 25 - 2, ny = cc[1] + (q / 5) % 5 - 2, nz = cc[2] + q % 5 - 2;
+        if (nx < 0 || nx >= I.dim[0] || ny < 0 || ny >= I.dim[1] || nz < 0 || nz >= I.dim[2])
+            continue;
+        const int32_t n = pd_lookup(tkey, tval, mask, ibits | static_cast<uint64_t>((nx * I.dim[1] + ny) * I.dim[2] + nz));
+        if (n < 0)
+            continue;
+        const int32_t a = acc[n];
+        if (a < 0)
+            continue;
+        const double ex = x0 - cxyz[3 * (int64_t)a];
+        const double ey = x1 - cxyz[3 * (int64_t)a + 1];
+        const double ez = x2 - cxyz[3 * (int64_t)a + 2];
+        const double d2 = ex * ex + ey * ey + ez * ez;
+        close = close || d2 < I.r2;
     }
-    acc[c] = cand;
-    tag[c] = p * kPhases + ph;
+    const bool rejected = __ballot(close) != 0;
+    if (lane != 0)
+        return;
+    if (!rejected) {
+        acc[c] = cand;
+        tag[c] = p * kPhases + ph;
+    } else if (count[c] > p + 1) {
+        more[p] = 1;
+    }
 }
 
 // Acceptance-order keys: (instance, tag, cell); the accepted count of each
@@ -295,17 +339,28 @@ size_t pd_temp_bytes(int64_t M)
 
 }  // namespace
 
+// Slots of the cell table: a power of two at least twice the candidate count.
+int64_t pd_table_slots(int64_t M)
+{
+    int64_t h = 2;
+    while (h < 2 * M)
+        h *= 2;
+    return h;
+}
+
 size_t pd_workspace_bytes(int64_t total_candidates, int32_t n_inst)
 {
     const int64_t M = total_candidates > 0 ? total_candidates : 1;
     const size_t temp = pd_temp_bytes(M);
+    const int64_t H = pd_table_slots(M);
     return carve_size<>({sizeof(int32_t) * M, sizeof(double) * 2 * M, sizeof(double) * 3 * M,
                          sizeof(uint64_t) * M, sizeof(uint64_t) * M, sizeof(int32_t) * M,
                          sizeof(int32_t) * M, sizeof(uint64_t) * M, sizeof(int32_t) * M,
                          sizeof(int32_t) * M, sizeof(uint32_t) * M, sizeof(uint32_t) * M,
                          sizeof(int32_t) * M, sizeof(int32_t) * M, sizeof(int32_t) * M,
                          sizeof(int32_t) * M, sizeof(int32_t) * (kPhases + 1) * 2,
-                         sizeof(int32_t) * n_inst, sizeof(int32_t) * n_inst, sizeof(int32_t) * 2, temp});
+                         sizeof(int32_t) * n_inst, sizeof(int32_t) * n_inst, sizeof(int32_t) * 2,
+                         sizeof(uint64_t) * H, sizeof(int32_t) * H, sizeof(int32_t) * kPdMaxPasses, temp});
 }
 
 // The record of one instance: radius r = 0.72 sqrt(A / N), the grid of
@@ -382,6 +437,11 @@ nat_status run_poisson(nat_ctx* ctx, const PdInst* d_inst, const std::vector<PdI
     int32_t* first = cv.take<int32_t>(nj);
     int32_t* n_acc = cv.take<int32_t>(nj);
     int32_t* n_cells = cv.take<int32_t>(2);
+    const int64_t H = pd_table_slots(M);
+    uint64_t* tkey = cv.take<uint64_t>(H);
+    int32_t* tval = cv.take<int32_t>(H);
+    int32_t* more = cv.take<int32_t>(kPdMaxPasses);
+    const uint32_t mask = static_cast<uint32_t>(H - 1);
     // the library primitives' scratch
     const size_t temp_bytes = pd_temp_bytes(M);
     void* temp = cv.take<char>(temp_bytes);
@@ -402,6 +462,11 @@ nat_status run_poisson(nat_ctx* ctx, const PdInst* d_inst, const std::vector<PdI
     NAT_HIP(hipcub::DeviceScan::ExclusiveSum(temp, tb, count, start, (int)M, s));
     NAT_HIP(hipMemsetAsync(stats, 0, sizeof(int32_t) * (kPhases + 1), s));
     NAT_HIP(hipMemsetAsync(n_acc, 0, sizeof(int32_t) * nj, s));
+    NAT_HIP(hipMemsetAsync(more, 0, sizeof(int32_t) * kPdMaxPasses, s));
+    hipLaunchKernelGGL(k_pd_table_clear, pd_grid(std::min<int64_t>(H, 256 * 2048)), dim3(256), 0, s, tkey, H);
+    NAT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_pd_table_fill, pd_grid(M), dim3(256), 0, s, ukey, n_cells, tkey, tval, mask);
+    NAT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_pd_cells, pd_grid(M), dim3(256), 0, s, d_inst, ukey, n_cells, count, phase, cell_id,
                        acc, tag, stats);
     NAT_HIP(hipGetLastError());
@@ -418,17 +483,27 @@ nat_status run_poisson(nat_ctx* ctx, const PdInst* d_inst, const std::vector<PdI
     for (int ph = 0; ph < kPhases; ++ph)
         off[ph + 1] = off[ph] + h_stats[ph];
     const int32_t maxc = h_stats[kPhases];
-    if ((int64_t)maxc * kPhases >= kTagNone)
+    if (maxc > kPdMaxPasses)
         return fail(NAT_E_INVALID, "Poisson-disk sampling: %d candidates in one cell", maxc);
-    for (int32_t p = 0; p < maxc; ++p)
+    // passes until no cell has a candidate left to try: after each pass the
+    // host reads whether a rejected cell still had candidates (a pass with
+    // no tries changes nothing, so stopping there gives the same set)
+    for (int32_t p = 0; p < maxc; ++p) {
         for (int ph = 0; ph < kPhases; ++ph) {
             const int32_t n_ph = off[ph + 1] - off[ph];
             if (n_ph == 0)
                 continue;
-            hipLaunchKernelGGL(k_pd_try, pd_grid(n_ph), dim3(256), 0, s, d_inst, ukey, n_cells, start, count,
-                               idx_s, phase_cells, off[ph], n_ph, p, ph, cxyz, acc, tag);
+            hipLaunchKernelGGL(k_pd_try, dim3(static_cast<unsigned>((n_ph + 3) / 4)), dim3(256), 0, s, d_inst,
+                               ukey, start, count, idx_s, phase_cells, off[ph], n_ph, p, ph, cxyz, tkey, tval,
+                               mask, acc, tag, more);
             NAT_HIP(hipGetLastError());
         }
+        int32_t h_more = 0;
+        NAT_HIP(hipMemcpyAsync(&h_more, more + p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        NAT_HIP(hipStreamSynchronize(s));
+        if (h_more == 0)
+            break;
+    }
     hipLaunchKernelGGL(k_pd_order, pd_grid(h_nc), dim3(256), 0, s, ukey, n_cells, acc, tag, okey, oval, n_acc);
     NAT_HIP(hipGetLastError());
     tb = temp_bytes;
