@@ -122,25 +122,36 @@ __global__ void __launch_bounds__(256) k_pd_cells(const PdInst* __restrict__ ins
                                                   int32_t* __restrict__ tag,
                                                   int32_t* __restrict__ stats)
 {
+    // the workgroup's counts in LDS first, then one global update per phase
+    __shared__ int32_t s_cnt[kPhases + 1];
+    if (threadIdx.x <= kPhases)
+        s_cnt[threadIdx.x] = 0;
+    __syncthreads();
     const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= *n_cells)
-        return;
-    const uint64_t k = ukey[c];
-    const PdInst& I = inst[k >> kPdInstShift];
-    int64_t cc[3];
-    cell_coords(k, I, cc);
-    const uint32_t ph = static_cast<uint32_t>((cc[0] % 3) * 9 + (cc[1] % 3) * 3 + (cc[2] % 3));
-    phase[c] = ph;
-    cell_id[c] = c;
-    acc[c] = -1;
-    tag[c] = static_cast<int32_t>(kTagNone);
-    atomicAdd(&stats[ph], 1);
-    atomicMax(&stats[kPhases], count[c]);
+    if (c < *n_cells) {
+        const uint64_t k = ukey[c];
+        const PdInst& I = inst[k >> kPdInstShift];
+        int64_t cc[3];
+        cell_coords(k, I, cc);
+        const uint32_t ph = static_cast<uint32_t>((cc[0] % 3) * 9 + (cc[1] % 3) * 3 + (cc[2] % 3));
+        phase[c] = ph;
+        cell_id[c] = c;
+        acc[c] = -1;
+        tag[c] = static_cast<int32_t>(kTagNone);
+        atomicAdd(&s_cnt[ph], 1);
+        atomicMax(&s_cnt[kPhases], count[c]);
+    }
+    __syncthreads();
+    if (threadIdx.x < kPhases && s_cnt[threadIdx.x] > 0)
+        atomicAdd(&stats[threadIdx.x], s_cnt[threadIdx.x]);
+    else if (threadIdx.x == kPhases)
+        atomicMax(&stats[kPhases], s_cnt[kPhases]);
 }
 
 // Cell lookup: an open-addressing table (linear probing, load factor at most
-// one half) from a cell key to the cell's index among the occupied cells.
-// Which slot a key lands in depends on the insertion order, but every lookup
+// one half) from a cell key to the cell's index among the occupied cells,
+// one 16-byte slot (key, index) per entry so a probe is one load.  Which
+// slot a key lands in depends on the insertion order, but every lookup
 // returns the same index, so the decisions do not.
 constexpr uint64_t kPdEmpty = ~uint64_t(0);
 
@@ -149,44 +160,52 @@ __device__ __forceinline__ uint32_t pd_slot(uint64_t key, uint32_t mask)
     return static_cast<uint32_t>(pd_mix64(key)) & mask;
 }
 
-__global__ void __launch_bounds__(256) k_pd_table_clear(uint64_t* __restrict__ tkey, int64_t n)
+__global__ void __launch_bounds__(256) k_pd_table_clear(ulonglong2* __restrict__ tab, int64_t n)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        tkey[i] = kPdEmpty;
+        tab[i] = make_ulonglong2(kPdEmpty, 0ull);
 }
 
+// The table, and every candidate's position in cell order.
 __global__ void __launch_bounds__(256) k_pd_table_fill(const uint64_t* __restrict__ ukey,
                                                        const int32_t* __restrict__ n_cells,
-                                                       uint64_t* __restrict__ tkey, int32_t* __restrict__ tval,
-                                                       uint32_t mask)
+                                                       ulonglong2* __restrict__ tab, uint32_t mask,
+                                                       const int32_t* __restrict__ sorted_idx, int64_t M,
+                                                       const double* __restrict__ cxyz,
+                                                       double* __restrict__ cxyz_s)
 {
     const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < M) {
+        const int64_t g = sorted_idx[c];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            cxyz_s[3 * (int64_t)c + d] = cxyz[3 * g + d];
+    }
     if (c >= *n_cells)
         return;
     const uint64_t k = ukey[c];
     uint32_t h = pd_slot(k, mask);
     // the table has at least twice as many slots as keys, so a free slot exists
     while (true) {
-        const unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long*>(tkey + h),
+        const unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[h].x),
                                                   static_cast<unsigned long long>(kPdEmpty),
                                                   static_cast<unsigned long long>(k));
         if (prev == static_cast<unsigned long long>(kPdEmpty)) {
-            tval[h] = c;
+            tab[h].y = static_cast<unsigned long long>(c);
             return;
         }
         h = (h + 1) & mask;
     }
 }
 
-__device__ __forceinline__ int32_t pd_lookup(const uint64_t* __restrict__ tkey, const int32_t* __restrict__ tval,
-                                             uint32_t mask, uint64_t key)
+__device__ __forceinline__ int32_t pd_lookup(const ulonglong2* __restrict__ tab, uint32_t mask, uint64_t key)
 {
     uint32_t h = pd_slot(key, mask);
     while (true) {
-        const uint64_t v = tkey[h];
-        if (v == key)
-            return tval[h];
-        if (v == kPdEmpty)
+        const ulonglong2 e = tab[h];
+        if (e.x == key)
+            return static_cast<int32_t>(e.y);
+        if (e.x == kPdEmpty)
             return -1;
         h = (h + 1) & mask;
     }
@@ -195,8 +214,10 @@ __device__ __forceinline__ int32_t pd_lookup(const uint64_t* __restrict__ tkey, 
 // Pass p of phase ph: every cell of the phase without an accepted point
 // tries its p-th candidate; one wave per cell, each lane checking two of
 // the 125 cells around it.  Cells of one phase are more than r apart, so
-// none reads what another writes in the same launch.  A rejected candidate
-// of a cell with candidates left sets more[p].
+// none reads what another writes in the same launch.  An accepted point's
+// position is copied to its cell (apos).  A rejected candidate of a cell
+// with candidates left sets more[p][ph]: the cells that try in pass p + 1
+// are exactly those.
 __global__ void __launch_bounds__(256) k_pd_try(const PdInst* __restrict__ inst,
                                                 const uint64_t* __restrict__ ukey,
                                                 const int32_t* __restrict__ start,
@@ -204,27 +225,25 @@ __global__ void __launch_bounds__(256) k_pd_try(const PdInst* __restrict__ inst,
                                                 const int32_t* __restrict__ sorted_idx,
                                                 const int32_t* __restrict__ phase_cells,
                                                 int32_t first, int32_t n_phase, int32_t p, int32_t ph,
-                                                const double* __restrict__ cxyz,
-                                                const uint64_t* __restrict__ tkey,
-                                                const int32_t* __restrict__ tval, uint32_t mask,
+                                                const double* __restrict__ cxyz_s,
+                                                const ulonglong2* __restrict__ tab, uint32_t mask,
                                                 int32_t* __restrict__ acc, int32_t* __restrict__ tag,
-                                                int32_t* __restrict__ more)
+                                                double* __restrict__ apos, int32_t* __restrict__ more)
 {
     const int32_t t = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (t >= n_phase)
         return;
     const int32_t c = phase_cells[first + t];
-    if (acc[c] >= 0 || count[c] <= p)
-        return;
-    const int32_t cand = sorted_idx[start[c] + p];
+    const int32_t a0 = acc[c], cnt = count[c], j = start[c] + p;
     const uint64_t k = ukey[c];
+    if (a0 >= 0 || cnt <= p)
+        return;
     const uint64_t ibits = k & ~kPdLocalMask;
     const PdInst& I = inst[k >> kPdInstShift];
     int64_t cc[3];
     cell_coords(k, I, cc);
-    const double x0 = cxyz[3 * (int64_t)cand], x1 = cxyz[3 * (int64_t)cand + 1],
-                 x2 = cxyz[3 * (int64_t)cand + 2];
+    const double x0 = cxyz_s[3 * (int64_t)j], x1 = cxyz_s[3 * (int64_t)j + 1], x2 = cxyz_s[3 * (int64_t)j + 2];
     bool close = false;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -234,15 +253,16 @@ __global__ void __launch_bounds__(256) k_pd_try(const PdInst* __restrict__ inst,
         const int64_t nx = cc[0] + q / 25 - 2, ny = cc[1] + (q / 5) % 5 - 2, nz = cc[2] + q % 5 - 2;
         if (nx < 0 || nx >= I.dim[0] || ny < 0 || ny >= I.dim[1] || nz < 0 || nz >= I.dim[2])
             continue;
-        const int32_t n = pd_lookup(tkey, tval, mask, ibits | static_cast<uint64_t>((nx * I.dim[1] + ny) * I.dim[2] + nz));
+        const int32_t n = pd_lookup(tab, mask, ibits | static_cast<uint64_t>((nx * I.dim[1] + ny) * I.dim[2] + nz));
         if (n < 0)
             continue;
         const int32_t a = acc[n];
+        const double y0 = apos[3 * (int64_t)n], y1 = apos[3 * (int64_t)n + 1], y2 = apos[3 * (int64_t)n + 2];
         if (a < 0)
             continue;
-        const double ex = x0 - cxyz[3 * (int64_t)a];
-        const double ey = x1 - cxyz[3 * (int64_t)a + 1];
-        const double ez = x2 - cxyz[3 * (int64_t)a + 2];
+        const double ex = x0 - y0;
+        const double ey = x1 - y1;
+        const double ez = x2 - y2;
         const double d2 = ex * ex + ey * ey + ez * ez;
         close = close || d2 < I.r2;
     }
@@ -250,10 +270,13 @@ __global__ void __launch_bounds__(256) k_pd_try(const PdInst* __restrict__ inst,
     if (lane != 0)
         return;
     if (!rejected) {
-        acc[c] = cand;
+        acc[c] = sorted_idx[j];
         tag[c] = p * kPhases + ph;
-    } else if (count[c] > p + 1) {
-        more[p] = 1;
+        apos[3 * (int64_t)c] = x0;
+        apos[3 * (int64_t)c + 1] = x1;
+        apos[3 * (int64_t)c + 2] = x2;
+    } else if (cnt > p + 1) {
+        more[p * kPhases + ph] = 1;
     }
 }
 
@@ -268,13 +291,28 @@ __global__ void __launch_bounds__(256) k_pd_order(const uint64_t* __restrict__ u
                                                   int32_t* __restrict__ n_acc)
 {
     const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= *n_cells)
-        return;
-    const uint64_t inst = ukey[c] >> kPdInstShift;
-    okey[c] = (inst << 47) | (static_cast<uint64_t>(tag[c]) << 32) | static_cast<uint64_t>(c);
-    oval[c] = acc[c];
-    if (acc[c] >= 0)
-        atomicAdd(&n_acc[inst], 1);
+    const int lane = threadIdx.x & 63;
+    bool ok = false;
+    int32_t inst = 0;
+    if (c < *n_cells) {
+        inst = static_cast<int32_t>(ukey[c] >> kPdInstShift);
+        const int32_t a = acc[c];
+        okey[c] = (static_cast<uint64_t>(inst) << 47) | (static_cast<uint64_t>(tag[c]) << 32) |
+                  static_cast<uint64_t>(c);
+        oval[c] = a;
+        ok = a >= 0;
+    }
+    // one atomic per instance present in the wave (cells are in key order,
+    // so a wave rarely spans more than one instance)
+    unsigned long long todo = __ballot(ok);
+    while (todo) {
+        const int leader = __ffsll(todo) - 1;
+        const int32_t li = __shfl(inst, leader, 64);
+        const unsigned long long m = __ballot(ok && inst == li);
+        if (lane == leader)
+            atomicAdd(&n_acc[li], __popcll(m));
+        todo &= ~m;
+    }
 }
 
 // First cell (in key order) of every instance.
@@ -360,7 +398,8 @@ size_t pd_workspace_bytes(int64_t total_candidates, int32_t n_inst)
                          sizeof(int32_t) * M, sizeof(int32_t) * M, sizeof(int32_t) * M,
                          sizeof(int32_t) * M, sizeof(int32_t) * (kPhases + 1) * 2,
                          sizeof(int32_t) * n_inst, sizeof(int32_t) * n_inst, sizeof(int32_t) * 2,
-                         sizeof(uint64_t) * H, sizeof(int32_t) * H, sizeof(int32_t) * kPdMaxPasses, temp});
+                         sizeof(ulonglong2) * H, sizeof(double) * 3 * M, sizeof(double) * 3 * M,
+                         sizeof(int32_t) * kPdMaxPasses * kPhases, temp});
 }
 
 // The record of one instance: radius r = 0.72 sqrt(A / N), the grid of
@@ -438,9 +477,10 @@ nat_status run_poisson(nat_ctx* ctx, const PdInst* d_inst, const std::vector<PdI
     int32_t* n_acc = cv.take<int32_t>(nj);
     int32_t* n_cells = cv.take<int32_t>(2);
     const int64_t H = pd_table_slots(M);
-    uint64_t* tkey = cv.take<uint64_t>(H);
-    int32_t* tval = cv.take<int32_t>(H);
-    int32_t* more = cv.take<int32_t>(kPdMaxPasses);
+    ulonglong2* tab = cv.take<ulonglong2>(H);
+    double* cxyz_s = cv.take<double>(3 * M);  // candidate positions in cell order
+    double* apos = cv.take<double>(3 * M);    // accepted position of each cell
+    int32_t* more = cv.take<int32_t>(kPdMaxPasses * kPhases);
     const uint32_t mask = static_cast<uint32_t>(H - 1);
     // the library primitives' scratch
     const size_t temp_bytes = pd_temp_bytes(M);
@@ -462,10 +502,11 @@ nat_status run_poisson(nat_ctx* ctx, const PdInst* d_inst, const std::vector<PdI
     NAT_HIP(hipcub::DeviceScan::ExclusiveSum(temp, tb, count, start, (int)M, s));
     NAT_HIP(hipMemsetAsync(stats, 0, sizeof(int32_t) * (kPhases + 1), s));
     NAT_HIP(hipMemsetAsync(n_acc, 0, sizeof(int32_t) * nj, s));
-    NAT_HIP(hipMemsetAsync(more, 0, sizeof(int32_t) * kPdMaxPasses, s));
-    hipLaunchKernelGGL(k_pd_table_clear, pd_grid(std::min<int64_t>(H, 256 * 2048)), dim3(256), 0, s, tkey, H);
+    NAT_HIP(hipMemsetAsync(more, 0, sizeof(int32_t) * kPdMaxPasses * kPhases, s));
+    hipLaunchKernelGGL(k_pd_table_clear, pd_grid(std::min<int64_t>(H, 256 * 2048)), dim3(256), 0, s, tab, H);
     NAT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_pd_table_fill, pd_grid(M), dim3(256), 0, s, ukey, n_cells, tkey, tval, mask);
+    hipLaunchKernelGGL(k_pd_table_fill, pd_grid(M), dim3(256), 0, s, ukey, n_cells, tab, mask, idx_s, M, cxyz,
+                       cxyz_s);
     NAT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_pd_cells, pd_grid(M), dim3(256), 0, s, d_inst, ukey, n_cells, count, phase, cell_id,
                        acc, tag, stats);
@@ -486,22 +527,28 @@ nat_status run_poisson(nat_ctx* ctx, const PdInst* d_inst, const std::vector<PdI
     if (maxc > kPdMaxPasses)
         return fail(NAT_E_INVALID, "Poisson-disk sampling: %d candidates in one cell", maxc);
     // passes until no cell has a candidate left to try: after each pass the
-    // host reads whether a rejected cell still had candidates (a pass with
-    // no tries changes nothing, so stopping there gives the same set)
+    // host reads which phases had a rejected cell with candidates left, and
+    // the next pass launches only those (a phase with no tries changes
+    // nothing, so skipping it gives the same set)
+    int32_t live[kPhases];
+    for (int ph = 0; ph < kPhases; ++ph)
+        live[ph] = 1;
     for (int32_t p = 0; p < maxc; ++p) {
         for (int ph = 0; ph < kPhases; ++ph) {
             const int32_t n_ph = off[ph + 1] - off[ph];
-            if (n_ph == 0)
+            if (n_ph == 0 || !live[ph])
                 continue;
             hipLaunchKernelGGL(k_pd_try, dim3(static_cast<unsigned>((n_ph + 3) / 4)), dim3(256), 0, s, d_inst,
-                               ukey, start, count, idx_s, phase_cells, off[ph], n_ph, p, ph, cxyz, tkey, tval,
-                               mask, acc, tag, more);
+                               ukey, start, count, idx_s, phase_cells, off[ph], n_ph, p, ph, cxyz_s, tab, mask,
+                               acc, tag, apos, more);
             NAT_HIP(hipGetLastError());
         }
-        int32_t h_more = 0;
-        NAT_HIP(hipMemcpyAsync(&h_more, more + p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        NAT_HIP(hipMemcpyAsync(live, more + (size_t)p * kPhases, sizeof(live), hipMemcpyDeviceToHost, s));
         NAT_HIP(hipStreamSynchronize(s));
-        if (h_more == 0)
+        bool any = false;
+        for (int ph = 0; ph < kPhases; ++ph)
+            any = any || live[ph] != 0;
+        if (!any)
             break;
     }
     hipLaunchKernelGGL(k_pd_order, pd_grid(h_nc), dim3(256), 0, s, ukey, n_cells, acc, tag, okey, oval, n_acc);
