@@ -694,11 +694,22 @@ __global__ void __launch_bounds__(256) k_nf_reduce(NfReduce r)
 // atomic additions, in LDS or in memory, measured 3-8 times slower here.)
 __device__ __forceinline__ double grid_scale(float gmax, int32_t B)
 {
-    // the largest power of two S with B * 8 * gmax * S <= 2^62
-    const double bound = static_cast<double>(B) * 8.0 * static_cast<double>(gmax);
+    // the largest power of two S with B * 8 * gmax * S <= 2^62 and
+    // gmax * S <= 2^50 (so every term converts as below)
+    const double g = static_cast<double>(gmax);
+    const double bound = static_cast<double>(B) * 8.0 * g;
     if (!(bound > 0.0) || !isfinite(bound))
         return 1.0;
-    return exp2(floor(62.0 - log2(bound)));
+    return exp2(floor(fmin(62.0 - log2(bound), 50.0 - log2(g))));
+}
+
+// round(x) to a 64-bit integer, ties to even, for |x| < 2^51: adding
+// 1.5 * 2^52 leaves the rounded value in the low mantissa bits (three
+// instructions instead of the general conversion's seven)
+__device__ __forceinline__ long long fixed_rn(double x)
+{
+    constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
+    return __double_as_longlong(x + kMagic) - __double_as_longlong(kMagic);
 }
 
 // The largest of the n per-workgroup maxima (every thread of the block).
@@ -753,7 +764,7 @@ __global__ void __launch_bounds__(kGridThreads) k_nf_grid_part(NfDev f, const fl
                     const double w = c.w[e];
 #pragma unroll
                     for (int q = 0; q < kFeat; ++q)
-                        atomicAdd(s_acc + at + q, static_cast<unsigned long long>(__double2ll_rn(w * gs[q])));
+                        atomicAdd(s_acc + at + q, static_cast<unsigned long long>(fixed_rn(w * gs[q])));
                 }
             }
         }
