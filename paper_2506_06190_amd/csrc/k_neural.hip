@@ -652,34 +652,75 @@ struct NfReduce {
     NfSeg seg[2 * kLayers];
 };
 
-__global__ void __launch_bounds__(256) k_nf_reduce(NfReduce r)
+constexpr int kReduceWaves = 16;
+
+__global__ void __launch_bounds__(64 * kReduceWaves) k_nf_reduce(NfReduce r)
 {
-    // 64 outputs per workgroup; wave g sums the g-th quarter of the partials
-    // in order, then the four quarter sums are added in order
-    __shared__ double s_q[4][64];
+    // 256 outputs per workgroup, four per lane (one 16-byte load per lane
+    // and partial); wave g sums the g-th eighth of the partials in order,
+    // then the eight sums are added in order.  Segments whose length is not
+    // a multiple of 4 (the biases of a narrow output layer) take one output
+    // per lane.
+    __shared__ double s_q[kReduceWaves][256];
     const NfSeg& s = r.seg[blockIdx.y];
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int32_t per = (s.nch + 3) / 4;
+    const int32_t per = (s.nch + kReduceWaves - 1) / kReduceWaves;
     const int32_t c_lo = g * per, c_hi = min(s.nch, c_lo + per);
-    for (int32_t e0 = blockIdx.x * 64; e0 < s.n; e0 += gridDim.x * 64) {
-        const int32_t e = e0 + lane;
-        double a = 0.0;
-        if (e < s.n) {
-            for (int32_t c0 = c_lo; c0 < c_hi; c0 += 8) {
-                float v[8];
+    const bool vec = (s.n & 3) == 0;
+    const int32_t span = vec ? 256 : 64;
+    for (int32_t e0 = blockIdx.x * span; e0 < s.n; e0 += gridDim.x * span) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        if (vec) {
+            const int32_t e = e0 + 4 * lane;
+            if (e < s.n) {
+                for (int32_t c0 = c_lo; c0 < c_hi; c0 += 8) {
+                    float4 v[8];
 #pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    v[c] = c0 + c < c_hi ? s.part[(size_t)(c0 + c) * s.n + e] : 0.0f;
+                    for (int c = 0; c < 8; ++c)
+                        v[c] = c0 + c < c_hi ? *reinterpret_cast<const float4*>(s.part + (size_t)(c0 + c) * s.n + e)
+                                             : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    a += v[c];
+                    for (int c = 0; c < 8; ++c) {
+                        a[0] += v[c].x;
+                        a[1] += v[c].y;
+                        a[2] += v[c].z;
+                        a[3] += v[c].w;
+                    }
+                }
+            }
+        } else {
+            const int32_t e = e0 + lane;
+            if (e < s.n) {
+                for (int32_t c0 = c_lo; c0 < c_hi; c0 += 8) {
+                    float v[8];
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        v[c] = c0 + c < c_hi ? s.part[(size_t)(c0 + c) * s.n + e] : 0.0f;
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        a[0] += v[c];
+                }
             }
         }
         __syncthreads();
-        s_q[g][lane] = a;
+        if (vec) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                s_q[g][4 * lane + k] = a[k];
+        } else {
+            s_q[g][lane] = a[0];
+        }
         __syncthreads();
-        if (g == 0 && e < s.n)
-            s.out[e] = static_cast<float>(((s_q[0][lane] + s_q[1][lane]) + s_q[2][lane]) + s_q[3][lane]);
+        for (int t = threadIdx.x; t < span; t += 64 * kReduceWaves) {
+            const int32_t e = e0 + t;
+            if (e < s.n) {
+                double acc = s_q[0][t];
+#pragma unroll
+                for (int q = 1; q < kReduceWaves; ++q)
+                    acc += s_q[q][t];
+                s.out[e] = static_cast<float>(acc);
+            }
+        }
     }
 }
 
@@ -1072,7 +1113,8 @@ hipError_t nf_backward(nat_nf* nf, const NfWs& w, const float* in, int32_t B, in
         red.seg[2 * i + 1] = NfSeg{w.Pb[i], nf->d_grads + nf->offb[i], nf->out_dim[i], w.bwd_grid};
         max_n = std::max(max_n, n);
     }
-    hipLaunchKernelGGL(k_nf_reduce, dim3(grid_for(max_n, 64, 1024), 2 * kLayers), dim3(256), 0, s, red);
+    hipLaunchKernelGGL(k_nf_reduce, dim3(grid_for(max_n, 256, 1024), 2 * kLayers), dim3(64 * kReduceWaves), 0, s,
+                       red);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     // grid-feature gradient: LDS partitions, then the ordered fold
