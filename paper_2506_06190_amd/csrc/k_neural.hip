@@ -819,12 +819,25 @@ __global__ void __launch_bounds__(kGridThreads) k_nf_grid_part(NfDev f, const fl
 __global__ void __launch_bounds__(256) k_nf_grid_fold(const long long* __restrict__ part, int32_t G, int32_t B,
                                                       const float* gmax, int32_t n_gmax, float* __restrict__ out)
 {
+    static_assert(kGridFloats % 2 == 0, "pairs of values");
     const double inv = 1.0 / grid_scale(block_max(gmax, n_gmax), B);
-    for (int e = blockIdx.x * 256 + threadIdx.x; e < kGridFloats; e += gridDim.x * 256) {
-        long long a = 0;
-        for (int g = 0; g < G; ++g)
-            a += part[(size_t)g * kGridFloats + e];
-        out[e] = static_cast<float>(static_cast<double>(a) * inv);
+    // two values per thread (16-byte loads), eight row groups' loads in flight
+    for (int e = 2 * (blockIdx.x * 256 + threadIdx.x); e < kGridFloats; e += 2 * gridDim.x * 256) {
+        long long a0 = 0, a1 = 0;
+        for (int g0 = 0; g0 < G; g0 += 8) {
+            longlong2 v[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                v[c] = g0 + c < G ? *reinterpret_cast<const longlong2*>(part + (size_t)(g0 + c) * kGridFloats + e)
+                                  : make_longlong2(0, 0);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                a0 += v[c].x;
+                a1 += v[c].y;
+            }
+        }
+        out[e] = static_cast<float>(static_cast<double>(a0) * inv);
+        out[e + 1] = static_cast<float>(static_cast<double>(a1) * inv);
     }
 }
 
@@ -1124,7 +1137,7 @@ hipError_t nf_backward(nat_nf* nf, const NfWs& w, const float* in, int32_t B, in
                        w.n_gmax, w.gpart, G);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_nf_grid_fold, dim3(grid_for(kGridFloats, 256, 512)), dim3(256), 0, s, w.gpart, G, B,
+    hipLaunchKernelGGL(k_nf_grid_fold, dim3(grid_for(kGridFloats / 2, 256, 1024)), dim3(256), 0, s, w.gpart, G, B,
                        w.gmax, w.n_gmax, nf->d_grads + nf->offG[0]);
     return hipGetLastError();
 }
