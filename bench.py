@@ -929,7 +929,21 @@ def run_scenes(nat, torch, ctx, args, dev):
                              "surface_elementwise": float(f"{rel_max(got[a], ref['p'][a]):.3g}"),
                              "field_elementwise": float(f"{rel_max(fg[a], fo[a]):.3g}")})
         out["vs_oracle"] = errs
-    out["neural_field_trained_on_these_tuples"] = train_on_scene_tuples(nat, torch, ctx, dev, wls, coords, fabs)
+    # the same tuples from an independent sample set (seed + 1000): how much
+    # of the field's held-out error is the targets' own Monte-Carlo noise
+    jobs2, ps2 = [], []
+    for i, (wl, m) in enumerate(zip(wls, meshes)):
+        p_s = torch.empty((wl.n_modes, wl.n_samples), dtype=torch.complex128, device=dev)
+        ps2.append(p_s)
+        jobs2.append(nat.McJob(m, jobs[i].v_n, wl.k, jobs[i].q_tri, jobs[i].q_bary, wl.n_samples, wl.seed + 1000,
+                               p_samples=p_s, layout=nat.NAT_NEUMANN_PER_TRIANGLE))
+    nat.nat_mcbem_estimate_batch(ctx, jobs2, opts, allow_noconv=True)
+    fabs2 = [torch.empty((wl.n_modes, P), dtype=torch.float64, device=dev) for wl in wls]
+    for i, (wl, m) in enumerate(zip(wls, meshes)):
+        nat.nat_mcbem_field(m, jobs[i].v_n, wl.k, ps2[i], wl.n_samples, wl.seed + 1000, pts[i], opts,
+                            abs_out=fabs2[i])
+    out["neural_field_trained_on_these_tuples"] = train_on_scene_tuples(nat, torch, ctx, dev, wls, coords, fabs,
+                                                                        fabs2=fabs2)
     for m in meshes:
         m.close()
     return out
@@ -956,12 +970,15 @@ def scene_training_rows(torch, wls, coords, fabs):
     return torch.cat(rows).float().contiguous(), torch.cat(tgt).float()[:, None].contiguous()
 
 
-def train_on_scene_tuples(nat, torch, ctx, dev, wls, coords, fabs, steps=3000, batch=1 << 16):
+def train_on_scene_tuples(nat, torch, ctx, dev, wls, coords, fabs, steps=3000, batch=1 << 16, fabs2=None):
     """The neural field (one condition variable: the speaker height) trained
     on the scenes' (theta, phi, r, v, f, |p|) tuples with Adam (Section 3.4),
     minibatches drawn uniformly from 90 % of the tuples; reports the loss and
     the relative RMS error of |p| on the held-out 10 % (every tenth tuple).
-    Targets are divided by their RMS so the loss is relative."""
+    Targets are divided by their RMS so the loss is relative.  With fabs2
+    (the same tuples from an independent sample set) it also reports the
+    targets' own noise, sqrt(1/2) |Y - Y2| / |Y|, and the held-out error
+    against Y2 and against the mean of the two."""
     X, Y = scene_training_rows(torch, wls, coords, fabs)
     scale = float(Y.pow(2).mean().sqrt())
     Y = Y / scale
@@ -986,10 +1003,18 @@ def train_on_scene_tuples(nat, torch, ctx, dev, wls, coords, fabs, steps=3000, b
     pred = nf.infer(Xte)
     err = float((pred - Yte).norm() / Yte.norm())
     nf.close()
-    return {"tuples": int(X.shape[0]), "held_out": int(Xte.shape[0]), "steps": steps, "batch": batch,
-            "seconds": round(t, 3), "train_rows_per_s_incl_sampling": steps * batch / t,
-            "loss_first": first, "loss_last": last, "held_out_rel_rms_error_abs_p": round(err, 4),
-            "target_rms": scale}
+    out = {"tuples": int(X.shape[0]), "held_out": int(Xte.shape[0]), "steps": steps, "batch": batch,
+           "seconds": round(t, 3), "train_rows_per_s_incl_sampling": steps * batch / t,
+           "loss_first": first, "loss_last": last, "held_out_rel_rms_error_abs_p": round(err, 4),
+           "target_rms": scale}
+    if fabs2 is not None:
+        _, Y2 = scene_training_rows(torch, wls, coords, fabs2)
+        Y2te = (Y2 / scale)[held].contiguous()
+        mean = 0.5 * (Yte + Y2te)
+        out["held_out_target_noise_rel_rms"] = round(float((Yte - Y2te).norm() / Yte.norm()) / 2 ** 0.5, 4)
+        out["held_out_rel_rms_error_vs_independent_targets"] = round(float((pred - Y2te).norm() / Y2te.norm()), 4)
+        out["held_out_rel_rms_error_vs_mean_of_two"] = round(float((pred - mean).norm() / mean.norm()), 4)
+    return out
 
 
 def run_neural(nat, torch, ctx, args, dev):
