@@ -929,21 +929,38 @@ def run_scenes(nat, torch, ctx, args, dev):
                              "surface_elementwise": float(f"{rel_max(got[a], ref['p'][a]):.3g}"),
                              "field_elementwise": float(f"{rel_max(fg[a], fo[a]):.3g}")})
         out["vs_oracle"] = errs
-    # the same tuples from an independent sample set (seed + 1000): how much
-    # of the field's held-out error is the targets' own Monte-Carlo noise
-    jobs2, ps2 = [], []
-    for i, (wl, m) in enumerate(zip(wls, meshes)):
-        p_s = torch.empty((wl.n_modes, wl.n_samples), dtype=torch.complex128, device=dev)
-        ps2.append(p_s)
-        jobs2.append(nat.McJob(m, jobs[i].v_n, wl.k, jobs[i].q_tri, jobs[i].q_bary, wl.n_samples, wl.seed + 1000,
-                               p_samples=p_s, layout=nat.NAT_NEUMANN_PER_TRIANGLE))
-    nat.nat_mcbem_estimate_batch(ctx, jobs2, opts, allow_noconv=True)
-    fabs2 = [torch.empty((wl.n_modes, P), dtype=torch.float64, device=dev) for wl in wls]
-    for i, (wl, m) in enumerate(zip(wls, meshes)):
-        nat.nat_mcbem_field(m, jobs[i].v_n, wl.k, ps2[i], wl.n_samples, wl.seed + 1000, pts[i], opts,
-                            abs_out=fabs2[i])
+    # the same tuples from independent sample sets (seed + 1000), and both
+    # again with Poisson-disk samples (Section 4.2): how much of the field's
+    # held-out error is the targets' own Monte-Carlo noise, and how much the
+    # Poisson-disk sets lower it
+    def tuples(seed_off, flags):
+        o = nat.nat_mc_opts_default()
+        o.layout = nat.NAT_NEUMANN_PER_TRIANGLE
+        o.flags = flags
+        jj, pp = [], []
+        for i, (wl, m) in enumerate(zip(wls, meshes)):
+            p_s = torch.empty((wl.n_modes, wl.n_samples), dtype=torch.complex128, device=dev)
+            pp.append(p_s)
+            jj.append(nat.McJob(m, jobs[i].v_n, wl.k, jobs[i].q_tri, jobs[i].q_bary, wl.n_samples,
+                                wl.seed + seed_off, p_samples=p_s, layout=nat.NAT_NEUMANN_PER_TRIANGLE))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nat.nat_mcbem_estimate_batch(ctx, jj, o, allow_noconv=True)
+        fa = [torch.empty((wl.n_modes, P), dtype=torch.float64, device=dev) for wl in wls]
+        for i, (wl, m) in enumerate(zip(wls, meshes)):
+            nat.nat_mcbem_field(m, jobs[i].v_n, wl.k, pp[i], wl.n_samples, wl.seed + seed_off, pts[i], o,
+                                abs_out=fa[i])
+        torch.cuda.synchronize()
+        return fa, time.perf_counter() - t0
+
+    fabs2, _ = tuples(1000, 0)
+    fabs_p, _ = tuples(0, nat.NAT_MC_POISSON)
+    fabs_p2, t_p = tuples(1000, nat.NAT_MC_POISSON)  # the second call: workspace already grown
+    out["poisson_disk_step_ms"] = round(1e3 * t_p, 3)
     out["neural_field_trained_on_these_tuples"] = train_on_scene_tuples(nat, torch, ctx, dev, wls, coords, fabs,
                                                                         fabs2=fabs2)
+    out["neural_field_trained_on_poisson_disk_tuples"] = train_on_scene_tuples(
+        nat, torch, ctx, dev, wls, coords, fabs_p, fabs2=fabs_p2)
     for m in meshes:
         m.close()
     return out
