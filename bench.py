@@ -886,12 +886,14 @@ def run_scenes(nat, torch, ctx, args, dev):
     fout = [torch.empty((wl.n_modes, P), dtype=torch.complex128, device=dev) for wl in wls]
     fabs = [torch.empty((wl.n_modes, P), dtype=torch.float64, device=dev) for wl in wls]
 
+    fjobs = [nat.FieldJob(m, jobs[i].v_n, wl.k, ps[i], wl.n_samples, wl.seed, pts[i], p_out=fout[i],
+                          abs_out=fabs[i]) for i, (wl, m) in enumerate(zip(wls, meshes))]
+
     def step():
         reps = nat.nat_mcbem_estimate_batch(ctx, jobs, opts, allow_noconv=True)
-        for i, (wl, m) in enumerate(zip(wls, meshes)):
+        for i, m in enumerate(meshes):
             nat.nat_field_points(m, nat.NAT_FIELD_SHELL, P, 1, 1.5, 3.0, 100 + i, points=pts[i])
-            nat.nat_mcbem_field(m, jobs[i].v_n, wl.k, ps[i], wl.n_samples, wl.seed, pts[i], opts,
-                                p_out=fout[i], abs_out=fabs[i])
+        nat.nat_mcbem_field_batch(ctx, fjobs, opts)
         return reps
 
     step()
@@ -946,10 +948,10 @@ def run_scenes(nat, torch, ctx, args, dev):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         nat.nat_mcbem_estimate_batch(ctx, jj, o, allow_noconv=True)
-        fa = [torch.empty((wl.n_modes, P), dtype=torch.float64, device=dev) for wl in wls]
-        for i, (wl, m) in enumerate(zip(wls, meshes)):
-            nat.nat_mcbem_field(m, jobs[i].v_n, wl.k, pp[i], wl.n_samples, wl.seed + seed_off, pts[i], o,
-                                abs_out=fa[i])
+        fj = [nat.FieldJob(m, jobs[i].v_n, wl.k, pp[i], wl.n_samples, wl.seed + seed_off, pts[i], want_abs=True)
+              for i, (wl, m) in enumerate(zip(wls, meshes))]
+        nat.nat_mcbem_field_batch(ctx, fj, o)
+        fa = [j.abs_out for j in fj]
         torch.cuda.synchronize()
         return fa, time.perf_counter() - t0
 

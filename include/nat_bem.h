@@ -367,6 +367,33 @@ nat_status nat_mcbem_estimate_batch(nat_ctx* ctx, const nat_mc_job* jobs, int32_
                                     const nat_mc_opts* opts, nat_solve_report* reports,
                                     void* stream);
 
+/* One exterior field of a batch: the arguments of nat_mcbem_field. */
+typedef struct {
+    nat_mesh* mesh;
+    const double* v_n;       /* device complex [n_modes][n_vertices or n_tris]      */
+    int32_t n_modes;
+    int32_t n_points;
+    const double* k;         /* host double[n_modes]                                */
+    const double* p_samples; /* device complex [n_modes][n_samples]: an estimate's  */
+    int32_t n_samples;
+    int32_t reserved;        /* ignored                                             */
+    uint64_t seed;
+    const double* points;    /* device double[n_points][3]                          */
+    double* p_out;           /* device complex [n_modes][n_points]                   */
+    double* abs_out;         /* device double[n_modes][n_points] or NULL             */
+} nat_field_job;
+
+/* Many exterior fields at once (Section 3.4: the training tuples of a
+ * family of scenes), each job as nat_mcbem_field with the same options:
+ * the samples of every job are drawn in one launch (one Poisson-disk
+ * sampler call for all jobs with NAT_MC_POISSON) and the field sums of all
+ * (job, mode) pairs run as one launch.  Each job's result is bit-for-bit
+ * that of nat_mcbem_field on the same job.  Meshes must belong to ctx.
+ * Blocks until the sums are done; abs_out is written stream-ordered after
+ * them. */
+nat_status nat_mcbem_field_batch(nat_ctx* ctx, const nat_field_job* jobs, int32_t n_jobs,
+                                 const nat_mc_opts* opts, void* stream);
+
 /* ---- dense collocation Burton-Miller BEM (Section 4, Section 4.1) -------- */
 
 /* Assemble A and B of A p = B g for piecewise-constant p and g with

@@ -1254,6 +1254,37 @@ nat_status nat_mcbem_field(nat_mesh* mesh, const double* v_n, int32_t n_modes, c
     return st;
 }
 
+nat_status nat_mcbem_field_batch(nat_ctx* ctx, const nat_field_job* jobs, int32_t n_jobs,
+                                 const nat_mc_opts* opts, void* stream)
+{
+    if (!ctx || !jobs || n_jobs < 1)
+        return nat::fail(NAT_E_INVALID, "nat_mcbem_field_batch: bad arguments");
+    std::vector<nat::McJob> J(n_jobs);
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        const nat_field_job& F = jobs[i];
+        if (!F.mesh || F.mesh->ctx != ctx)
+            return nat::fail(NAT_E_INVALID, "nat_mcbem_field_batch: job %d: mesh is NULL or of another context",
+                             i);
+        if (!F.p_samples)
+            return nat::fail(NAT_E_INVALID, "nat_mcbem_field_batch: job %d: p_samples is NULL", i);
+        J[i] = nat::McJob{F.mesh, F.v_n, F.n_modes, F.n_points, F.n_samples, F.k, nullptr, nullptr, F.seed,
+                          F.p_out, nullptr};
+        J[i].fpts = F.points;
+        J[i].p_given = F.p_samples;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    nat_status st = nat::run_mc(ctx, J.data(), n_jobs, opts, nullptr, s, nullptr);
+    if (st != NAT_OK)
+        return st;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        const nat_field_job& F = jobs[i];
+        if (F.abs_out && F.n_points > 0)
+            NAT_HIP(nat::launch_abs(reinterpret_cast<const double2*>(F.p_out), (int64_t)F.n_modes * F.n_points,
+                                    F.abs_out, s));
+    }
+    return NAT_OK;
+}
+
 nat_status nat_mcbem_estimate_batch(nat_ctx* ctx, const nat_mc_job* jobs, int32_t n_jobs,
                                     const nat_mc_opts* opts, nat_solve_report* reports,
                                     void* stream)

@@ -59,6 +59,13 @@ class nat_mc_job(C.Structure):
                 ("seed", C.c_uint64), ("p_out", C.c_void_p), ("p_samples", C.c_void_p)]
 
 
+class nat_field_job(C.Structure):
+    _fields_ = [("mesh", C.c_void_p), ("v_n", C.c_void_p), ("n_modes", C.c_int32),
+                ("n_points", C.c_int32), ("k", C.c_void_p), ("p_samples", C.c_void_p),
+                ("n_samples", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64),
+                ("points", C.c_void_p), ("p_out", C.c_void_p), ("abs_out", C.c_void_p)]
+
+
 class nat_kernel_stat(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double),
                 ("flops", C.c_double)]
@@ -127,6 +134,7 @@ _SIGS = {
     "nat_mcbem_estimate_batch": ([_P, _P, C.c_int32, C.POINTER(nat_mc_opts), _P, _P], C.c_int),
     "nat_mcbem_field": ([_P, _P, C.c_int32, _P, _P, C.c_int32, C.c_uint64, _P, C.c_int32,
                          C.POINTER(nat_mc_opts), _P, _P, _P], C.c_int),
+    "nat_mcbem_field_batch": ([_P, _P, C.c_int32, C.POINTER(nat_mc_opts), _P], C.c_int),
     "nat_field_points": ([_P, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_uint64,
                           _P, _P, _P], C.c_int),
     "nat_bem_assemble": ([_P, C.c_double, C.c_int32, C.POINTER(_P), _P], C.c_int),
@@ -513,6 +521,53 @@ def nat_mcbem_field(mesh: Mesh, v_n, k: Sequence[float], p_samples, n_samples: i
         _stream(stream))
     _check(st)
     return p_out, abs_out
+
+
+class FieldJob:
+    """One field of nat_mcbem_field_batch (device tensors, host k); the
+    Neumann layout is the batch's (nat_mc_opts.layout)."""
+
+    def __init__(self, mesh: Mesh, v_n, k, p_samples, n_samples: int, seed: int, points, p_out=None,
+                 abs_out=None, want_abs: bool = False):
+        import torch
+        self.mesh = mesh
+        self.k = np.ascontiguousarray(np.atleast_1d(k), dtype=np.float64)
+        self.n_modes = len(self.k)
+        self.v_n, self.p_samples, self.points = v_n, p_samples, points
+        self.n_samples, self.seed = int(n_samples), int(seed)
+        self.P = int(points.shape[0])
+        if p_out is None:
+            p_out = torch.empty((self.n_modes, self.P), dtype=torch.complex128, device=v_n.device)
+        if abs_out is None and want_abs:
+            abs_out = torch.empty((self.n_modes, self.P), dtype=torch.float64, device=v_n.device)
+        self.p_out, self.abs_out = p_out, abs_out
+
+    def record(self, layout: int) -> nat_field_job:
+        import torch
+        ng = self.mesh.n_tris if layout == NAT_NEUMANN_PER_TRIANGLE else self.mesh.n_vertices
+        j = nat_field_job()
+        j.mesh = self.mesh.handle.value
+        j.v_n = _dptr(self.v_n, torch.complex128, (self.n_modes, ng), "v_n").value
+        j.n_modes = self.n_modes
+        j.n_points = self.P
+        j.k = self.k.ctypes.data
+        j.p_samples = _dptr(self.p_samples, torch.complex128, (self.n_modes, self.n_samples), "p_samples").value
+        j.n_samples = self.n_samples
+        j.seed = self.seed
+        j.points = _dptr(self.points, torch.float64, (self.P, 3), "points").value
+        j.p_out = _dptr(self.p_out, torch.complex128, (self.n_modes, self.P), "p_out").value
+        j.abs_out = (_dptr(self.abs_out, torch.float64, (self.n_modes, self.P), "abs_out").value
+                     if self.abs_out is not None else None)
+        return j
+
+
+def nat_mcbem_field_batch(ctx: Context, jobs, opts: Optional[nat_mc_opts] = None, stream=None):
+    """Runs the field jobs (list of FieldJob) in one batch."""
+    if opts is None:
+        opts = nat_mc_opts_default()
+    recs = (nat_field_job * len(jobs))(*[j.record(opts.layout) for j in jobs])
+    _check(lib().nat_mcbem_field_batch(ctx.handle, C.cast(recs, _P), len(jobs), C.byref(opts), _stream(stream)))
+    return jobs
 
 
 def nat_field_points(mesh: Mesh, kind: int, n_a: int, n_b: int = 1, r_lo: float = 1.5,

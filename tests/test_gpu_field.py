@@ -127,3 +127,38 @@ def test_field_errors(ctx):
     p, _ = nat.nat_mcbem_field(mesh, _dev(g), k, ps, N, seed, pts[:0])
     assert p.shape == (2, 0)
     mesh.close()
+
+
+@pytest.mark.parametrize("flags", [0, nat.NAT_MC_POISSON])
+def test_field_batch_equals_single_fields(ctx, flags):
+    """nat_mcbem_field_batch on three fields of uneven size (different meshes,
+    modes, sample counts and point counts; independent or Poisson-disk
+    samples) gives each job bit for bit what nat_mcbem_field gives it alone,
+    and the first job matches the oracle's field from the oracle's sample
+    values within the FP32 bar, element by element."""
+    specs = [(23, 5, 600, 700), (24, 3, 900, 257), (25, 1, 512, 1000)]
+    meshes, jobs, singles = [], [], []
+    opts = nat.nat_mc_opts_default()
+    opts.flags = flags
+    refs = []
+    for seed, M, N, P in specs:
+        v, f, g, k, _, _ = _small(seed=seed, M=M, N=N)
+        ref = O.mcbem(v, f, g, k, np.zeros(0, np.int32), np.zeros((0, 2)), N, seed, tol=1e-12,
+                      want_samples=True, poisson=bool(flags))
+        xs, _ = O.field_points(v, 0, P, seed=seed)
+        refs.append((v, f, g, k, N, seed, xs, ref))
+        mesh = nat.Mesh(ctx, v, f)
+        meshes.append(mesh)
+        ps, pts = _dev(ref["p_samples"]), _dev(xs)
+        jobs.append(nat.FieldJob(mesh, _dev(g), k, ps, N, seed, pts, want_abs=True))
+        singles.append(nat.nat_mcbem_field(mesh, _dev(g), k, ps, N, seed, pts, opts, want_abs=True))
+    _say(f"field batch of {len(jobs)} jobs, flags {flags}")
+    nat.nat_mcbem_field_batch(ctx, jobs, opts)
+    torch.cuda.synchronize()
+    for j, (p1, a1) in zip(jobs, singles):
+        assert torch.equal(j.p_out, p1) and torch.equal(j.abs_out, a1)
+    v, f, g, k, N, seed, xs, ref = refs[0]
+    po = O.mcbem_field(v, f, g, k, N, seed, xs, ref["p_samples"], poisson=bool(flags))
+    check_modes(jobs[0].p_out.cpu().numpy(), po, 1e-3, "field batch job 0 vs oracle")
+    for m in meshes:
+        m.close()
