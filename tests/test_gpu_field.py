@@ -162,3 +162,22 @@ def test_field_batch_equals_single_fields(ctx, flags):
     check_modes(jobs[0].p_out.cpu().numpy(), po, 1e-3, "field batch job 0 vs oracle")
     for m in meshes:
         m.close()
+
+
+def test_field_batch_errors(ctx):
+    """An empty batch and a job whose mesh belongs to another context are
+    refused before any device work."""
+    with pytest.raises(nat.NatError) as ei:
+        nat.nat_mcbem_field_batch(ctx, [])
+    assert ei.value.status == nat.NAT_E_INVALID
+    v, f, g, k, N, seed = _small(M=2, N=100)
+    other = nat.Context(0)
+    mesh = nat.Mesh(other, v, f)
+    ps = torch.zeros((2, N), dtype=torch.complex128, device=DEV)
+    pts = torch.ones((4, 3), dtype=torch.float64, device=DEV)
+    job = nat.FieldJob(mesh, _dev(g), k, ps, N, seed, pts)
+    with pytest.raises(nat.NatError) as ei:
+        nat.nat_mcbem_field_batch(ctx, [job])
+    assert ei.value.status == nat.NAT_E_INVALID and "another context" in str(ei.value)
+    mesh.close()
+    other.close()
