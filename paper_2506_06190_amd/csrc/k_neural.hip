@@ -778,7 +778,15 @@ __global__ void __launch_bounds__(kGridThreads) k_nf_grid_part(NfDev f, const fl
                                                       int32_t n_gmax, long long* __restrict__ part, int32_t G)
 {
     __shared__ unsigned long long s_acc[kGridPart];
-    const int p = blockIdx.x % kGridParts, g = blockIdx.x / kGridParts;
+    // Workgroups go to the 8 XCDs in turn (block b to XCD b mod 8); taking
+    // (group, partition) pairs in order within each XCD's share keeps a row
+    // group's partitions on one or two XCDs, so its rows are fetched into
+    // one or two L2s instead of all eight (a bijection: kGridParts is a
+    // multiple of 8)
+    static_assert(kGridParts % 8 == 0, "partitions per row group a multiple of the XCD count");
+    const int per_xcd = static_cast<int>(gridDim.x) / 8;
+    const int L = static_cast<int>(blockIdx.x % 8) * per_xcd + static_cast<int>(blockIdx.x / 8);
+    const int p = L % kGridParts, g = L / kGridParts;
     const int lo = p * kGridPart;
     const int n = min(kGridPart, kGridFloats - lo);
     const double S = grid_scale(block_max(gmax, n_gmax), B);
