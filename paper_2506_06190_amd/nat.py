@@ -809,6 +809,7 @@ class NeuralField:
     def __init__(self, ctx: Context, n_v: int, n_out: int, r_lo: float, r_hi: float, seed: int = 0):
         self.ctx = ctx
         self.n_v, self.n_out = int(n_v), int(n_out)
+        self.r_lo, self.r_hi = float(r_lo), float(r_hi)
         h = _P()
         _check(lib().nat_nf_create(ctx.handle, self.n_v, self.n_out, float(r_lo), float(r_hi),
                                    C.c_uint64(seed), C.byref(h)))
@@ -864,6 +865,23 @@ class NeuralField:
         _check(lib().nat_nf_infer(self.handle, pi, B, _dptr(out, torch.float32, (B, self.n_out), "out"),
                                   _stream(stream)))
         return out
+
+    def save(self, path):
+        """Writes the field's sizes, training shell and parameters to a .npz
+        file (the Adam moments are not saved: a field loaded from it starts
+        them at zero, as after set_params)."""
+        np.savez(path, format=np.int64(1), n_v=np.int64(self.n_v), n_out=np.int64(self.n_out),
+                 r_lo=np.float64(self.r_lo), r_hi=np.float64(self.r_hi), params=self.get_params())
+
+    @classmethod
+    def load(cls, ctx: Context, path):
+        """A field made from a file written by save()."""
+        with np.load(path, allow_pickle=False) as z:
+            if int(z["format"]) != 1:
+                raise ValueError(f"{path}: unknown neural-field file format {int(z['format'])}")
+            nf = cls(ctx, int(z["n_v"]), int(z["n_out"]), float(z["r_lo"]), float(z["r_hi"]))
+            nf.set_params(z["params"])
+        return nf
 
     def close(self):
         if getattr(self, "handle", None):

@@ -238,6 +238,26 @@ def test_full_batch_sampled_rows(env):
     nf.close()
 
 
+def test_save_and_load_round_trip(env, tmp_path):
+    """A trained field written with save() and read back with load() gives
+    the same inference bit for bit, on a field with two condition variables
+    and three outputs over a shell other than the default."""
+    nat, ctx, torch = env
+    _, tgt, rows = make_rows(2048, 2, 3, 21)
+    nf = nat.NeuralField(ctx, 2, 3, 1.2, 2.5, seed=4)
+    x, t = dev(torch, rows), dev(torch, tgt)
+    for s_ in range(5):
+        nf.train_step(x, t, s_, 5, want_loss=False)
+    path = tmp_path / "field.npz"
+    nf.save(path)
+    nf2 = nat.NeuralField.load(ctx, path)
+    assert (nf2.n_v, nf2.n_out, nf2.r_lo, nf2.r_hi) == (2, 3, 1.2, 2.5)
+    assert np.array_equal(nf2.get_params(), nf.get_params())
+    assert torch.equal(nf2.infer(x), nf.infer(x))
+    nf.close()
+    nf2.close()
+
+
 def test_inference_allocates_nothing(env):
     """Inference runs entirely in on-chip memory: the context's charged
     bytes do not move, however large the batch."""
