@@ -502,15 +502,26 @@ struct NfOut {
 constexpr int kOutPitch = kHidden + 2;  // bfloat16 per LDS row: an odd number of dwords
 constexpr int kOutTasks = kMaxOut * kHidden / 256;
 
+// LDS bytes of the output step for n_out outputs: the tile, W_4 and dZ_4 as
+// floats, the loss reduction.
+__host__ __device__ constexpr size_t nf_out_lds(int n_out)
+{
+    return sizeof(uint16_t) * kRowTile * kOutPitch + 2 * sizeof(float) * kHidden * (size_t)n_out +
+           sizeof(double) * 256;
+}
+
 __global__ void __launch_bounds__(256) k_nf_out(NfOut o)
 {
-    __shared__ uint16_t sH[kRowTile * kOutPitch];
-    __shared__ float sW[kMaxOut * kHidden];
-    __shared__ float s_dz[kMaxOut][kRowTile];
-    __shared__ double s_red[256];
+    // sized by n_out (dynamic), so that narrow output layers leave room for
+    // more workgroups per CU
+    extern __shared__ uint4 s_out_raw[];
+    const int nO = o.n_out;
+    uint16_t* sH = reinterpret_cast<uint16_t*>(s_out_raw);  // [kRowTile][kOutPitch]
+    float* sW = reinterpret_cast<float*>(sH + kRowTile * kOutPitch);  // [n_out][128]
+    float* s_dz = sW + nO * kHidden;                                  // [n_out][kRowTile]
+    double* s_red = reinterpret_cast<double*>(s_dz + nO * kRowTile);  // [256]
     const int tid = threadIdx.x;
     const bool train = o.dz3 != nullptr;
-    const int nO = o.n_out;
     for (int e = tid; e < nO * kHidden; e += 256)
         sW[e] = from_bf16(o.W[e]);
     float accw[kOutTasks];
@@ -556,7 +567,7 @@ __global__ void __launch_bounds__(256) k_nf_out(NfOut o)
                         dz = o.scale * diff;
                     }
                 }
-                s_dz[oi][r] = from_bf16(to_bf16(dz));
+                s_dz[oi * kRowTile + r] = from_bf16(to_bf16(dz));
             }
         }
         if (!train)
@@ -574,7 +585,7 @@ __global__ void __launch_bounds__(256) k_nf_out(NfOut o)
                     const int k = c * 8 + e + u;
                     float dh = 0.0f;
                     for (int oi = 0; oi < nO; ++oi)
-                        dh = fmaf(s_dz[oi][rr], sW[oi * kHidden + k], dh);
+                        dh = fmaf(s_dz[oi * kRowTile + rr], sW[oi * kHidden + k], dh);
                     const uint16_t h = to_bf16(bf16_positive(sH[rr * kOutPitch + k]) ? dh : 0.0f);
                     two |= static_cast<uint32_t>(h) << (16 * u);
                 }
@@ -591,13 +602,13 @@ __global__ void __launch_bounds__(256) k_nf_out(NfOut o)
                 const int oi = e / kHidden, k = e - oi * kHidden;
                 float a = accw[j];
                 for (int rr = 0; rr < kRowTile; ++rr)
-                    a = fmaf(s_dz[oi][rr], from_bf16(sH[rr * kOutPitch + k]), a);
+                    a = fmaf(s_dz[oi * kRowTile + rr], from_bf16(sH[rr * kOutPitch + k]), a);
                 accw[j] = a;
             }
         }
         if (tid < nO)
             for (int rr = 0; rr < kRowTile; ++rr)
-                accb += s_dz[tid][rr];
+                accb += s_dz[tid * kRowTile + rr];
     }
     if (train) {
 #pragma unroll
@@ -931,17 +942,18 @@ struct NfWs {
     uint16_t* H[4];           // A_1 .. A_4
     uint16_t* dz[4];          // dZ_0 .. dZ_3
     float* dh0;               // [Bp][16]
-    double* loss_part;        // [bwd_grid]
+    double* loss_part;        // [out_grid]
     double* loss;
-    float* Pw[kLayers];       // dW_0 .. dW_4 workgroup partials [bwd_grid][out_i][in_i]
-    float* Pb[kLayers];       // db_0 .. db_4 workgroup partials [bwd_grid][out_i]
+    float* Pw[kLayers];       // dW_0 .. dW_4 workgroup partials [bwd_grid, or out_grid for dW_4][out_i][in_i]
+    float* Pb[kLayers];       // db_0 .. db_4 workgroup partials [bwd_grid, or out_grid for db_4][out_i]
     long long* gpart;         // grid-gradient partials [grid_groups][kGridFloats]
     float* gmax;              // max |dH_0| of each workgroup of the layer-0 backward
     int32_t n_gmax;
-    int32_t grid_groups, bwd_grid;
+    int32_t grid_groups, bwd_grid, out_grid;
 };
 
 constexpr int kBwdGrid = 512;  // workgroups of a fused backward pass (persistent)
+constexpr int kOutGrid = 1024; // workgroups of the output step (more tiles in flight than the backward grid)
 
 int32_t nf_grid_groups(int32_t Bp)
 {
@@ -953,6 +965,10 @@ size_t nf_ws_layout(const nat_nf* nf, int32_t Bp, NfWs* w, void* base)
     const size_t bp = static_cast<size_t>(Bp);
     const int32_t G = nf_grid_groups(Bp);
     const int32_t GB = std::min(Bp / kRowTile, kBwdGrid);
+    const int32_t OG = std::min(Bp / kRowTile, kOutGrid);
+    // the output layer's partials come from the output step, the others
+    // from the backward passes
+    auto parts = [&](int i) { return static_cast<size_t>(i == kLayers - 1 ? OG : GB); };
     std::vector<size_t> sz;
     sz.push_back(2 * bp * nf->D);                 // X
     for (int i = 0; i < 4; ++i)
@@ -960,12 +976,12 @@ size_t nf_ws_layout(const nat_nf* nf, int32_t Bp, NfWs* w, void* base)
     for (int i = 0; i < 4; ++i)
         sz.push_back(2 * bp * kHidden);           // dz
     sz.push_back(4 * bp * kLevels * kFeat);       // dh0
-    sz.push_back(8 * static_cast<size_t>(GB));    // loss_part
+    sz.push_back(8 * static_cast<size_t>(OG));    // loss_part
     sz.push_back(8);                              // loss
     for (int i = 0; i < kLayers; ++i)
-        sz.push_back(4 * static_cast<size_t>(GB) * nf->out_dim[i] * nf->in_dim[i]);  // Pw
+        sz.push_back(4 * parts(i) * nf->out_dim[i] * nf->in_dim[i]);  // Pw
     for (int i = 0; i < kLayers; ++i)
-        sz.push_back(4 * static_cast<size_t>(GB) * nf->out_dim[i]);                  // Pb
+        sz.push_back(4 * parts(i) * nf->out_dim[i]);                  // Pb
     sz.push_back(8 * static_cast<size_t>(kGridFloats) * G);
     sz.push_back(4 * static_cast<size_t>(GB));
     size_t total = 0;
@@ -980,17 +996,18 @@ size_t nf_ws_layout(const nat_nf* nf, int32_t Bp, NfWs* w, void* base)
         for (int i = 0; i < 4; ++i)
             w->dz[i] = cv.take<uint16_t>(bp * kHidden);
         w->dh0 = cv.take<float>(bp * kLevels * kFeat);
-        w->loss_part = cv.take<double>(GB);
+        w->loss_part = cv.take<double>(OG);
         w->loss = cv.take<double>(1);
         for (int i = 0; i < kLayers; ++i)
-            w->Pw[i] = cv.take<float>(static_cast<size_t>(GB) * nf->out_dim[i] * nf->in_dim[i]);
+            w->Pw[i] = cv.take<float>(parts(i) * nf->out_dim[i] * nf->in_dim[i]);
         for (int i = 0; i < kLayers; ++i)
-            w->Pb[i] = cv.take<float>(static_cast<size_t>(GB) * nf->out_dim[i]);
+            w->Pb[i] = cv.take<float>(parts(i) * nf->out_dim[i]);
         w->gpart = cv.take<long long>(static_cast<size_t>(kGridFloats) * G);
         w->gmax = cv.take<float>(GB);
         w->n_gmax = GB;
         w->grid_groups = G;
         w->bwd_grid = GB;
+        w->out_grid = OG;
     }
     return total;
 }
@@ -1079,10 +1096,10 @@ hipError_t nf_forward(nat_nf* nf, const NfWs& w, const float* in, const float* t
     o.Pw4 = w.Pw[4];
     o.Pb4 = w.Pb[4];
     o.loss_part = w.loss_part;
-    hipLaunchKernelGGL(k_nf_out, dim3(w.bwd_grid), dim3(256), 0, s, o);
+    hipLaunchKernelGGL(k_nf_out, dim3(w.out_grid), dim3(256), nf_out_lds(nf->n_out), s, o);
     e = hipGetLastError();
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_nf_sum, dim3(1), dim3(256), 0, s, w.loss_part, w.bwd_grid, w.loss);
+        hipLaunchKernelGGL(k_nf_sum, dim3(1), dim3(256), 0, s, w.loss_part, w.out_grid, w.loss);
         e = hipGetLastError();
     }
     return e;
@@ -1130,8 +1147,9 @@ hipError_t nf_backward(nat_nf* nf, const NfWs& w, const float* in, int32_t B, in
     int32_t max_n = 0;
     for (int i = 0; i < kLayers; ++i) {
         const int32_t n = nf->out_dim[i] * nf->in_dim[i];
-        red.seg[2 * i] = NfSeg{w.Pw[i], nf->d_grads + nf->offW[i], n, w.bwd_grid};
-        red.seg[2 * i + 1] = NfSeg{w.Pb[i], nf->d_grads + nf->offb[i], nf->out_dim[i], w.bwd_grid};
+        const int32_t nch = i == kLayers - 1 ? w.out_grid : w.bwd_grid;
+        red.seg[2 * i] = NfSeg{w.Pw[i], nf->d_grads + nf->offW[i], n, nch};
+        red.seg[2 * i + 1] = NfSeg{w.Pb[i], nf->d_grads + nf->offb[i], nf->out_dim[i], nch};
         max_n = std::max(max_n, n);
     }
     hipLaunchKernelGGL(k_nf_reduce, dim3(grid_for(max_n, 256, 1024), 2 * kLayers), dim3(64 * kReduceWaves), 0, s,
