@@ -532,21 +532,43 @@ __global__ void __launch_bounds__(256) k_nf_out(NfOut o)
     double lsum = 0.0;
     const int r = tid >> 1, hf = tid & 1;
     const int n_tiles = o.Bp / kRowTile;
+    // the next tile's A_4 is loaded into registers while this tile is
+    // worked on (eight 16-byte pieces per thread)
+    constexpr int kPre = kRowTile * (kHidden / 8) / 256;
+    uint4 pre[kPre];
+    auto fetch = [&](int t) {
+        const int bt = t * kRowTile;
+#pragma unroll
+        for (int j = 0; j < kPre; ++j) {
+            const int task = tid + 256 * j;
+            const int rr = task >> 4, c = task & 15;
+            pre[j] = *reinterpret_cast<const uint4*>(o.H + (size_t)(bt + rr) * kHidden + c * 8);
+        }
+    };
+    if (static_cast<int>(blockIdx.x) < n_tiles)
+        fetch(blockIdx.x);
     for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int b0 = tile * kRowTile;
         __syncthreads();
-        for (int task = tid; task < kRowTile * (kHidden / 8); task += 256) {
+#pragma unroll
+        for (int j = 0; j < kPre; ++j) {
+            const int task = tid + 256 * j;
             const int rr = task >> 4, c = task & 15;
-            const uint4 v = *reinterpret_cast<const uint4*>(o.H + (size_t)(b0 + rr) * kHidden + c * 8);
             uint32_t* d = reinterpret_cast<uint32_t*>(sH + rr * kOutPitch + c * 8);
-            d[0] = v.x;
-            d[1] = v.y;
-            d[2] = v.z;
-            d[3] = v.w;
+            d[0] = pre[j].x;
+            d[1] = pre[j].y;
+            d[2] = pre[j].z;
+            d[3] = pre[j].w;
         }
         __syncthreads();
         const int row = b0 + r;
         const bool live = row < o.B;
+        // this tile's first target before the next tile's loads are issued
+        // (loads complete in order, so a later target load would wait for
+        // them)
+        const float tgt0 = (o.target && live && hf == 0) ? o.target[(size_t)row * nO] : 0.0f;
+        if (tile + static_cast<int>(gridDim.x) < n_tiles)
+            fetch(tile + gridDim.x);
         for (int oi = 0; oi < nO; ++oi) {
             float part = 0.0f;
             const uint16_t* hr = sH + r * kOutPitch + hf * 64;
@@ -562,7 +584,7 @@ __global__ void __launch_bounds__(256) k_nf_out(NfOut o)
                     if (o.y)
                         o.y[(size_t)row * nO + oi] = yv;
                     if (o.target) {
-                        const float diff = yv - o.target[(size_t)row * nO + oi];
+                        const float diff = yv - (oi == 0 ? tgt0 : o.target[(size_t)row * nO + oi]);
                         lsum += static_cast<double>(diff) * diff;
                         dz = o.scale * diff;
                     }
@@ -953,7 +975,7 @@ struct NfWs {
 };
 
 constexpr int kBwdGrid = 512;  // workgroups of a fused backward pass (persistent)
-constexpr int kOutGrid = 1024; // workgroups of the output step (more tiles in flight than the backward grid)
+constexpr int kOutGrid = 512;  // workgroups of the output step
 
 int32_t nf_grid_groups(int32_t Bp)
 {
