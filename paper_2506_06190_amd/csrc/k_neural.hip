@@ -83,6 +83,18 @@ __device__ __forceinline__ bf16x8 load8(const uint16_t* p)
     return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
 }
 
+// Eight bfloat16 values of one LDS column (stride kTilePitch), packed as one
+// MFMA operand fragment.
+__device__ __forceinline__ bf16x8 lds_col8(const uint16_t* p)
+{
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        w[i] = static_cast<uint32_t>(p[(2 * i) * kTilePitch]) |
+               (static_cast<uint32_t>(p[(2 * i + 1) * kTilePitch]) << 16);
+    return __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+}
+
 struct NfDev {
     int32_t n_v, n_out, D, ld_in;
     float r_lo, inv_span;
@@ -408,11 +420,13 @@ __global__ void __launch_bounds__(256) k_nf_bwd(NfBwd p)
                 acc[bb] = f32x16{};
 #pragma unroll
             for (int bb = 0; bb < kRowTile / 32; ++bb) {
-                const uint16_t* dr = p.dz + (size_t)(b0 + bb * 32 + l32) * kHidden + half * 8;
+                // dZ row b0 + bb * 32 + l32, columns kk * 16 + half * 8 + 0..7,
+                // gathered from the transposed tile in LDS
+                const uint16_t* dr = sDZ + (half * 8) * kTilePitch + bb * 32 + l32;
                 bf16x8 bv[kHidden / 16];
 #pragma unroll
                 for (int kk = 0; kk < kHidden / 16; ++kk)
-                    bv[kk] = load8(dr + kk * 16);
+                    bv[kk] = lds_col8(dr + kk * 16 * kTilePitch);
 #pragma unroll
                 for (int kk = 0; kk < kHidden / 16; ++kk)
                     acc[bb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfr[kk], bv[kk], acc[bb], 0, 0, 0);
