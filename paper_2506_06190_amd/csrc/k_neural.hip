@@ -235,12 +235,8 @@ __global__ void __launch_bounds__(256) k_nf_fwd(NfFwd p)
             const int d8 = D / 8;
             for (int task = tid; task < kRowTile * d8; task += 256) {
                 const int r = task / d8, c = task - r * d8;
-                const uint16_t* src = sAct + r * pitch + c * 8;
-                uint4 v;
-                v.x = src[0] | (static_cast<uint32_t>(src[1]) << 16);
-                v.y = src[2] | (static_cast<uint32_t>(src[3]) << 16);
-                v.z = src[4] | (static_cast<uint32_t>(src[5]) << 16);
-                v.w = src[6] | (static_cast<uint32_t>(src[7]) << 16);
+                // 16-byte aligned: the pitch is a multiple of 8 values
+                const uint4 v = *reinterpret_cast<const uint4*>(sAct + r * pitch + c * 8);
                 *reinterpret_cast<uint4*>(p.X + (size_t)(b0 + r) * D + c * 8) = v;
             }
         }
@@ -298,12 +294,7 @@ __global__ void __launch_bounds__(256) k_nf_fwd(NfFwd p)
                 __syncthreads();
                 for (int task = tid; task < kRowTile * (kHidden / 8); task += 256) {
                     const int r = task >> 4, c = task & 15;
-                    const uint16_t* src = sAct + r * pitch + c * 8;
-                    uint4 v;
-                    v.x = src[0] | (static_cast<uint32_t>(src[1]) << 16);
-                    v.y = src[2] | (static_cast<uint32_t>(src[3]) << 16);
-                    v.z = src[4] | (static_cast<uint32_t>(src[5]) << 16);
-                    v.w = src[6] | (static_cast<uint32_t>(src[7]) << 16);
+                    const uint4 v = *reinterpret_cast<const uint4*>(sAct + r * pitch + c * 8);
                     *reinterpret_cast<uint4*>(p.H[i] + (size_t)(b0 + r) * kHidden + c * 8) = v;
                 }
             }
