@@ -197,18 +197,24 @@ __global__ void __launch_bounds__(256) k_nf_fwd(NfFwd p)
             if (tid < kRowTile) {
                 float u[3];
                 unit_coords(f, row, u);
+#pragma unroll
                 for (int l = 0; l < kLevels; ++l) {
                     float acc[kFeat] = {0.0f, 0.0f, 0.0f, 0.0f};
                     if (live) {
                         Corners c;
                         cell_corners(u, l, c);
+                        // the 8 gathers in flight together, then the sums in
+                        // corner order
+                        float4 gq[8];
+#pragma unroll
+                        for (int e = 0; e < 8; ++e)
+                            gq[e] = *reinterpret_cast<const float4*>(f.grid[l] + (size_t)c.idx[e] * kFeat);
 #pragma unroll
                         for (int e = 0; e < 8; ++e) {
-                            const float4 gq = *reinterpret_cast<const float4*>(f.grid[l] + (size_t)c.idx[e] * kFeat);
-                            acc[0] = fmaf(c.w[e], gq.x, acc[0]);
-                            acc[1] = fmaf(c.w[e], gq.y, acc[1]);
-                            acc[2] = fmaf(c.w[e], gq.z, acc[2]);
-                            acc[3] = fmaf(c.w[e], gq.w, acc[3]);
+                            acc[0] = fmaf(c.w[e], gq[e].x, acc[0]);
+                            acc[1] = fmaf(c.w[e], gq[e].y, acc[1]);
+                            acc[2] = fmaf(c.w[e], gq[e].z, acc[2]);
+                            acc[3] = fmaf(c.w[e], gq[e].w, acc[3]);
                         }
                     }
 #pragma unroll
@@ -244,15 +250,23 @@ __global__ void __launch_bounds__(256) k_nf_fwd(NfFwd p)
             const int K = i == 0 ? D : kHidden;
             const int k8 = K / 8;
             __syncthreads();  // the previous layer's weights are no longer read
+            // row tid / 2 of W_i, its 16-byte runs c = tid % 2 + 2 j (k8 is
+            // even): every load in flight before the first LDS write
             const uint16_t* W = p.wb + p.offWb[i];
-            for (int e = tid; e < kHidden * k8; e += 256) {
-                const int r = e / k8, c = e - r * k8;
-                const uint4 v = *reinterpret_cast<const uint4*>(W + (size_t)r * K + c * 8);
-                uint32_t* d = reinterpret_cast<uint32_t*>(sW + r * pitch + c * 8);
-                d[0] = v.x;
-                d[1] = v.y;
-                d[2] = v.z;
-                d[3] = v.w;
+            const int wr = tid >> 1, wc = tid & 1;
+            const uint16_t* wsrc = W + (size_t)wr * K + wc * 8;
+            uint16_t* wdst = sW + wr * pitch + wc * 8;
+            static_assert(KS <= 16, "at most 16 runs of 8 per thread");
+            {
+                uint4 wq[KS];
+#pragma unroll
+                for (int t = 0; t < KS; ++t)  // runs past the row re-read run 0
+                    wq[t] = *reinterpret_cast<const uint4*>(wsrc + (2 * t < k8 ? 16 * t : 0));
+                // (a run past the row lands in the padding columns K .. 16 KS - 1,
+                // which no product reads)
+#pragma unroll
+                for (int t = 0; t < KS; ++t)
+                    *reinterpret_cast<uint4*>(wdst + 16 * t) = wq[t];
             }
             __syncthreads();
             // the wave's A rows for every K step, then the products
