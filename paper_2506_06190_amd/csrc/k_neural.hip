@@ -729,11 +729,16 @@ __global__ void __launch_bounds__(64 * kReduceWaves) k_nf_reduce(NfReduce r)
             const int32_t e = e0 + 4 * lane;
             if (e < s.n) {
                 for (int32_t c0 = c_lo; c0 < c_hi; c0 += 8) {
+                    // eight loads in flight (past the end: the last partial
+                    // again, replaced by zeros)
                     float4 v[8];
 #pragma unroll
                     for (int c = 0; c < 8; ++c)
-                        v[c] = c0 + c < c_hi ? *reinterpret_cast<const float4*>(s.part + (size_t)(c0 + c) * s.n + e)
-                                             : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                        v[c] = *reinterpret_cast<const float4*>(s.part + (size_t)min(c0 + c, c_hi - 1) * s.n + e);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        if (c0 + c >= c_hi)
+                            v[c] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
                     for (int c = 0; c < 8; ++c) {
                         a[0] += v[c].x;
@@ -750,7 +755,11 @@ __global__ void __launch_bounds__(64 * kReduceWaves) k_nf_reduce(NfReduce r)
                     float v[8];
 #pragma unroll
                     for (int c = 0; c < 8; ++c)
-                        v[c] = c0 + c < c_hi ? s.part[(size_t)(c0 + c) * s.n + e] : 0.0f;
+                        v[c] = s.part[(size_t)min(c0 + c, c_hi - 1) * s.n + e];
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        if (c0 + c >= c_hi)
+                            v[c] = 0.0f;
 #pragma unroll
                     for (int c = 0; c < 8; ++c)
                         a[0] += v[c];
@@ -892,8 +901,11 @@ __global__ void __launch_bounds__(256) k_nf_grid_fold(const long long* __restric
             longlong2 v[8];
 #pragma unroll
             for (int c = 0; c < 8; ++c)
-                v[c] = g0 + c < G ? *reinterpret_cast<const longlong2*>(part + (size_t)(g0 + c) * kGridFloats + e)
-                                  : make_longlong2(0, 0);
+                v[c] = *reinterpret_cast<const longlong2*>(part + (size_t)min(g0 + c, G - 1) * kGridFloats + e);
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (g0 + c >= G)
+                    v[c] = make_longlong2(0, 0);
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 a0 += v[c].x;
