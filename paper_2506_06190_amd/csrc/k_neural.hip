@@ -59,8 +59,9 @@ constexpr int kGridFloats = level_base(kLevels);
 constexpr int kGridPart = 5112 * kFeat;  // 159.75 KB of 64-bit accumulators (the LDS of a CU)
 constexpr int kGridParts = (kGridFloats + kGridPart - 1) / kGridPart;
 // Row groups per partition: for 2^18 rows, 21 partitions x 36 groups = 756
-// workgroups, about three rounds of one per CU, measured best (training step
-// 0.662 ms; 0.667 with 24 groups, 0.749 with 12, 0.849 with 8).
+// workgroups, about three rounds of one per CU, measured best over 8-64
+// groups (a training step 0.662 ms against 0.667 with 24 groups, 0.749 with
+// 12 and 0.849 with 8, the other kernels as they were at the time).
 constexpr int kGridGroupsMax = 36;
 // Threads of a partition workgroup: the accumulators fill the LDS, so one
 // workgroup runs per CU, and 16 waves keep its loads and atomics in flight
