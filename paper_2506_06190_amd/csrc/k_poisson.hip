@@ -526,14 +526,44 @@ nat_status run_poisson(nat_ctx* ctx, const PdInst* d_inst, const std::vector<PdI
     const int32_t maxc = h_stats[kPhases];
     if (maxc > kPdMaxPasses)
         return fail(NAT_E_INVALID, "Poisson-disk sampling: %d candidates in one cell", maxc);
-    // passes until no cell has a candidate left to try: after each pass the
-    // host reads which phases had a rejected cell with candidates left, and
-    // the next pass launches only those (a phase with no tries changes
-    // nothing, so skipping it gives the same set)
+    // Passes until no cell has a candidate left to try.  A phase with no cell
+    // left to try stays so, and a launch in which no cell tries changes
+    // nothing, so pass p may launch the phases still live after pass p - 2
+    // (a superset of those live after pass p - 1): the flags of each pass are
+    // read back while the next pass runs, and the host waits only for that
+    // copy, not for the stream.
+    struct FlagEvents {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~FlagEvents()
+        {
+            for (hipEvent_t x : e)
+                if (x)
+                    (void)hipEventDestroy(x);
+        }
+    } fe;
+    for (hipEvent_t& x : fe.e)
+        NAT_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+    // two slots of flags in pinned memory, past the callers' instance staging
+    const size_t stage = (sizeof(PdInst) * static_cast<size_t>(nj) + 63) / 64 * 64;
+    void* pin = nullptr;
+    nat_status pst = pinned(ctx, stage + 2 * sizeof(int32_t) * kPhases, &pin);
+    if (pst != NAT_OK)
+        return pst;
+    int32_t* hflag = reinterpret_cast<int32_t*>(static_cast<char*>(pin) + stage);
     int32_t live[kPhases];
     for (int ph = 0; ph < kPhases; ++ph)
         live[ph] = 1;
     for (int32_t p = 0; p < maxc; ++p) {
+        if (p >= 2) {
+            NAT_HIP(hipEventSynchronize(fe.e[p & 1]));  // the flags of pass p - 2
+            bool any = false;
+            for (int ph = 0; ph < kPhases; ++ph) {
+                live[ph] = hflag[(p & 1) * kPhases + ph];
+                any = any || live[ph] != 0;
+            }
+            if (!any)
+                break;
+        }
         for (int ph = 0; ph < kPhases; ++ph) {
             const int32_t n_ph = off[ph + 1] - off[ph];
             if (n_ph == 0 || !live[ph])
@@ -543,13 +573,9 @@ nat_status run_poisson(nat_ctx* ctx, const PdInst* d_inst, const std::vector<PdI
                                acc, tag, apos, more);
             NAT_HIP(hipGetLastError());
         }
-        NAT_HIP(hipMemcpyAsync(live, more + (size_t)p * kPhases, sizeof(live), hipMemcpyDeviceToHost, s));
-        NAT_HIP(hipStreamSynchronize(s));
-        bool any = false;
-        for (int ph = 0; ph < kPhases; ++ph)
-            any = any || live[ph] != 0;
-        if (!any)
-            break;
+        NAT_HIP(hipMemcpyAsync(hflag + (p & 1) * kPhases, more + (size_t)p * kPhases, sizeof(int32_t) * kPhases,
+                               hipMemcpyDeviceToHost, s));
+        NAT_HIP(hipEventRecord(fe.e[p & 1], s));
     }
     hipLaunchKernelGGL(k_pd_order, pd_grid(h_nc), dim3(256), 0, s, ukey, n_cells, acc, tag, okey, oval, n_acc);
     NAT_HIP(hipGetLastError());
